@@ -1,0 +1,252 @@
+/*
+ * calclens_mi.h -- C ABI of the MI355X lens-plane solver.
+ *
+ * The library implements the hot path of Becker (2013), "CALCLENS: weak
+ * lensing simulations for large-area sky surveys" (arXiv:1210.3069):
+ *   - the plane Poisson equation on the sphere (Sec. 2.1, eq. lenspoisson),
+ *     solved by a spherical-harmonic transform on a coarse HEALPix grid and
+ *     refined by multigrid on rotated patches around ray bundles (Sec. 3.2);
+ *   - the deflection and shear from 4th-order finite differences, with the
+ *     Christoffel terms of App. A, at arbitrary points (Sec. 3.2);
+ *   - the multiple-plane propagation of ray directions, positions and
+ *     lensing Jacobians (Sec. 2.2, eqs. betaprop, posprop, Atraj, with the
+ *     parallel transport of App. B) and the radial interpolation of the
+ *     Jacobian to galaxies (App. D, eq. gatraj).
+ *
+ * Conventions used by every call:
+ *   - Pointers named *_dev are device pointers (HIP device memory on the
+ *     plan's device); pointers named *_host are host pointers.  The caller
+ *     allocates and owns every input and output buffer; the plan owns its
+ *     workspace, allocated once in clm_plan_create and freed in
+ *     clm_plan_destroy.
+ *   - Calls are asynchronous on the given stream (0 = the null stream) and
+ *     never synchronise, except clm_plan_sync_status and clm_plan_timing.
+ *   - kappa is the standard convergence; the solve uses lap psi = 2 kappa
+ *     (the paper's kappa^(m) is twice the standard one, Sec. 2.1), so
+ *     psi_lm = -2 kappa_lm / (l (l+1)) with psi_00 = 0 (Sec. 3.2).
+ *   - Maps are HEALPix RING order unless stated; a_lm are complex128
+ *     (re, im interleaved) in HEALPix order index = m (2 lmax + 1 - m)/2 + l.
+ *   - Vectors and tensors on the sphere are given in the orthonormal
+ *     (theta-hat, phi-hat) basis at the point: axis 1 = theta-hat (south),
+ *     axis 2 = phi-hat (east), as in App. A.
+ *   - Argument and shape errors return a status synchronously and launch
+ *     nothing.  Conditions found on the device (a ray that left its patch,
+ *     a non-finite value) are latched in the plan and reported by
+ *     clm_plan_sync_status.  No C++ exception crosses this interface.
+ *   - A plan is not thread-safe; use one plan per stream.
+ */
+#ifndef CALCLENS_MI_H
+#define CALCLENS_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct clm_plan_s* clm_plan;
+
+typedef enum {
+  CLM_OK = 0,
+  CLM_EINVAL = 1,           /* bad argument, size or pointer                 */
+  CLM_ENOMEM = 2,           /* workspace allocation failed                   */
+  CLM_EHIP = 3,             /* a HIP runtime call or kernel launch failed    */
+  CLM_ENOTCONV = 4,         /* reserved: multigrid tolerance not reached     */
+  CLM_ERAY_LEFT_PATCH = 5,  /* a point fell outside its bundle's patch       */
+  CLM_ENONFINITE = 6,       /* a non-finite value was produced               */
+  CLM_EUNSUPPORTED = 7      /* valid request this build does not implement   */
+} clm_status;
+
+typedef enum { CLM_FP64 = 0, CLM_FP32 = 1 } clm_precision;
+typedef enum { CLM_SOLVER_SHT = 0, CLM_SOLVER_SHT_MG = 1 } clm_solver;
+typedef enum { CLM_ORDER_RING = 0, CLM_ORDER_NESTED = 1 } clm_order;
+
+/*
+ * Plan description.  Sizes follow Sec. 3.1-3.2: rays on a HEALPix grid of
+ * resolution nside_fine, bundles of resolution nside_bundle (a ray's bundle
+ * is its NESTED index shifted right by 2 log2(nside_fine/nside_bundle)), an
+ * SHT on a HEALPix grid of resolution nside_sht up to lmax, and multigrid
+ * patches whose side is patch_factor bundle sizes with patch_cells finest
+ * cells per side (Delta theta' = Delta phi').
+ */
+typedef struct {
+  int32_t nside_fine;    /* power of two >= 1: ray / output grid               */
+  int32_t nside_sht;     /* power of two, <= nside_fine (SHT solver: == fine)  */
+  int32_t lmax;          /* >= 1; default 2 * nside_sht                        */
+  int32_t nside_bundle;  /* power of two, <= nside_fine                        */
+  int32_t patch_factor;  /* patch side / bundle side (Sec. 3.2: 4)             */
+  int32_t patch_cells;   /* finest cells per side: power of two, 8..4096       */
+  int32_t mg_vcycles;    /* fixed number of V-cycles per solve, >= 1           */
+  int32_t nu_pre;        /* red-black sweeps before restriction, 1..4          */
+  int32_t nu_post;       /* red-black sweeps after prolongation, 1..4          */
+  int32_t solver;        /* clm_solver                                         */
+  int32_t mg_prec;       /* clm_precision of the multigrid correction          */
+  int32_t max_planes;    /* solution slots held by the plan, >= 1              */
+} clm_plan_desc;
+
+/* Fill *d with the defaults for a fine grid: nside_sht = nside_fine / 8
+ * (>= 1), lmax = 2 nside_sht, nside_bundle = max(1, nside_fine / 64),
+ * patch_factor 4, patch_cells = max(256, 4 nside_fine / nside_bundle),
+ * 4 V-cycles of (2, 2) sweeps, SHT+MG solver, FP32 multigrid, 1 slot. */
+clm_status clm_plan_desc_default(clm_plan_desc* d, int32_t nside_fine);
+
+/* Create a plan on HIP device `device`: validates *desc, allocates all
+ * workspace and builds the geometry tables (ring tables, Legendre starting
+ * values, NESTED/RING maps, patch rotations, multigrid coefficients).
+ * Synchronises the device once.  *out is NULL on failure. */
+clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out);
+clm_status clm_plan_destroy(clm_plan plan);
+const char* clm_status_string(clm_status s);
+/* Copy the last error text of the plan (NUL-terminated, truncated to len). */
+clm_status clm_plan_last_error(clm_plan plan, char* buf_host, size_t len);
+/* Synchronise `stream`, return and clear the status latched by kernels. */
+clm_status clm_plan_sync_status(clm_plan plan, hipStream_t stream);
+/* Bytes of device workspace held by the plan. */
+size_t clm_plan_workspace_bytes(clm_plan plan);
+/* Copy the resolved description (defaults applied) to *out_host. */
+clm_status clm_plan_get_desc(clm_plan plan, clm_plan_desc* out_host);
+
+/*
+ * Synthesis of a real field from a_lm (Sec. 3.2, the SHT synthesis):
+ *   f(r, j) = sum_l a_l0 lambda_l0(theta_r)
+ *             + 2 Re sum_{m>=1} [sum_l a_lm lambda_lm(theta_r)] e^{i m phi_rj}
+ * alm_dev: [nalm(lmax)] complex128; map_dev: [12 nside^2] float64 (RING).
+ * Independent of any plan; allocates and frees its own temporary workspace
+ * (not for use under stream capture).
+ */
+clm_status clm_alm2map(const double* alm_dev, int32_t lmax, int32_t nside,
+                       double* map_dev, hipStream_t stream);
+
+/*
+ * The plane Poisson solve (Sec. 3.2).  kappa_dev: [nplanes][12 nside_fine^2]
+ * standard convergence, RING order, float64 (kappa_is_fp64 = 1) or float32.
+ * Plane p of the batch goes to solution slot first_slot + p
+ * (first_slot + nplanes <= max_planes).  Steps per plane:
+ *   1. kappa' = kappa - mean(kappa); degrade to nside_sht by the mean of the
+ *      NESTED children (mass conserving, Sec. 3.2);
+ *   2. analysis a_lm = (4 pi / N_pix) sum_r lambda_lm(theta_r) F_m(r), with
+ *      F_m(r) the DFT of ring r at order m (HEALPix aliasing kept);
+ *   3. psi_lm = -2 a_lm / (l (l+1)), psi_00 = 0;
+ *   4. synthesis of psi on the nside_sht grid;
+ *   SHT+MG solver only:
+ *   5. per bundle b: rotated patch, u0 = psi_SHT interpolated (HEALPix
+ *      linear interpolation) at the cell centres, Dirichlet data psi_SHT on
+ *      the patch faces, f = 2 (kappa' interpolated at the cell centres),
+ *      f' = f - L u0 in float64;
+ *   6. mg_vcycles FAS V-cycles on du = u - u0 (zero on the faces) with
+ *      red-black Gauss-Seidel, area-weighted restriction and bilinear
+ *      prolongation with injection on the outermost ring, levels down to
+ *      4 x 4 solved exactly.
+ * Results stay in the slot: psi_lm, the psi_SHT map and (SHT+MG) the patch
+ * potential u0 + du.
+ */
+clm_status clm_poisson_solve(clm_plan plan, const void* kappa_dev, int32_t kappa_is_fp64,
+                             int32_t first_slot, int32_t nplanes, hipStream_t stream);
+
+/* Copies out of a solution slot (device destinations):
+ *   psi_alm: [nalm(lmax)] complex128; psi_map: [12 nside_sht^2] float64;
+ *   patch potential: [npatch][patch_cells][patch_cells] float64 = u0 + du
+ *   of patches (bundles, NESTED index) first_patch .. first_patch+npatch-1. */
+clm_status clm_get_psi_alm(clm_plan plan, int32_t slot, double* out_dev, hipStream_t stream);
+clm_status clm_get_psi_map(clm_plan plan, int32_t slot, double* out_dev, hipStream_t stream);
+clm_status clm_get_patch_potential(clm_plan plan, int32_t slot, int64_t first_patch,
+                                   int64_t npatch, double* out_dev, hipStream_t stream);
+
+/*
+ * Gradient and covariant Hessian of psi (Sec. 3.2 last paragraphs, App. A):
+ *   grad = (d_theta psi, d_phi psi / sin theta)
+ *   hess = (U_tt, U_pp, U_tp) with U_tt = psi_tt,
+ *          U_pp = psi_pp / sin^2 + cot psi_t, U_tp = psi_tp / sin - cos psi_p / sin^2.
+ * shear = ((U_tt - U_pp)/2, U_tp), convergence = (U_tt + U_pp)/2.
+ * SHT+MG: 4th-order finite differences of u0 + du at the cells (one-sided
+ * stencils within one cell of the patch edge), bilinear interpolation of
+ * the raw partials to the point, metric terms at the point, rotation to the
+ * global basis.  A point is evaluated in the patch of the bundle that
+ * contains it.
+ *
+ * clm_shear_from_potential: points theta_dev/phi_dev [npts] float64 (SHT+MG
+ * solver only).  clm_shear_at_pixels: all 12 nside_fine^2 pixel centres in
+ * `order` (both solvers; the SHT solver synthesises the derivatives
+ * directly from psi_lm).  grad_dev: [2][npts], hess_dev: [3][npts], float64
+ * if out_fp64 else float32.  Points whose interpolation footprint leaves
+ * their patch get NaN and latch CLM_ERAY_LEFT_PATCH.
+ */
+clm_status clm_shear_from_potential(clm_plan plan, int32_t slot, const double* theta_dev,
+                                    const double* phi_dev, int64_t npts, int32_t out_fp64,
+                                    void* grad_dev, void* hess_dev, hipStream_t stream);
+clm_status clm_shear_at_pixels(clm_plan plan, int32_t slot, int32_t order, int32_t out_fp64,
+                               void* grad_dev, void* hess_dev, hipStream_t stream);
+
+/*
+ * Ray state (Sec. 2.2), one ray per HEALPix pixel of nside_fine in NESTED
+ * order (Sec. 3.1), caller-owned device arrays of n = 12 nside_fine^2:
+ *   theta, phi: angular position on the current plane (float64);
+ *   beta: [3][n] propagation direction (float64, Cartesian);
+ *   A, A_prev: [4][n] lensing Jacobian on the current and previous plane,
+ *   row-major 2 x 2 (A11, A12, A21, A22), float32, in the basis at the
+ *   ray's current position.
+ */
+typedef struct {
+  double* theta;
+  double* phi;
+  double* beta;
+  float* A;
+  float* A_prev;
+  int64_t n;
+} clm_rays;
+
+/* Galaxies for the radial interpolation of App. D: sky position, comoving
+ * distance chi (same units as the plane distances), output A [4][n]
+ * float32 written when the galaxy's shell is passed. */
+typedef struct {
+  const double* theta;
+  const double* phi;
+  const double* chi;
+  float* A;
+  int64_t n;
+} clm_galaxies;
+
+/* Rays at the pixel centres, beta = n, A = A_prev = I (eqs. betaprop,
+ * posprop, Atraj initial conditions). */
+clm_status clm_rays_init(clm_plan plan, const clm_rays* rays, hipStream_t stream);
+
+/*
+ * Propagate rays through lens planes first_plane .. first_plane+nplanes-1
+ * (SHT+MG solver).  kappa_dev: [nplanes][12 nside_fine^2] (RING) of those
+ * planes.  chi_host: [nchi] comoving distances of all planes of the run,
+ * chi_0 .. chi_{N-1}, followed by the final target chi_N (nchi = N + 1);
+ * curvature_K in the inverse square of the same unit.  For each plane m the
+ * call solves the plane (slot 0), then for every ray:
+ *   g, U at n^(m) from the ray's bundle patch; d = -(g_t theta-hat + g_p phi-hat);
+ *   beta <- R(n x d/|d|, |d|) beta (eq. betaprop, read so that rays bend
+ *   toward mass, as eq. disclighttraj requires);
+ *   x <- x + lambda beta with |x + lambda beta| = chi_{m+1} (eq. posprop);
+ *   A^(m+1) = (1 - c_m) A^(m-1) + c_m A^(m) - d_m U A^(m) (eq. Atraj,
+ *   chi_{-1} = 0); A^(m+1) and A^(m) parallel transported to n^(m+1) (App. B).
+ * Galaxies (may be NULL) whose shell k (chi between the midpoints around
+ * chi_k) satisfies first_plane < k <= first_plane + nplanes get
+ * A_g = (1 - w) A^(k-1) + w A^(k), w = D_k D_{k-1,g} / (D_g D_{k-1,k}) (eq.
+ * gatraj), with the ray Jacobians taken by HEALPix linear interpolation on
+ * the image-plane grid; shell-0 galaxies get A_g = I when first_plane = 0.
+ */
+clm_status clm_raytrace_planes(clm_plan plan, const void* kappa_dev, int32_t kappa_is_fp64,
+                               const double* chi_host, int32_t nchi, int32_t first_plane,
+                               int32_t nplanes, double curvature_K, const clm_rays* rays,
+                               const clm_galaxies* galaxies, hipStream_t stream);
+
+/*
+ * One ray update through an already solved slot (the per-plane step of
+ * clm_raytrace_planes without the solve and without galaxies): plane index
+ * m, distances chi_host as above.
+ */
+clm_status clm_ray_update(clm_plan plan, int32_t slot, const double* chi_host, int32_t nchi,
+                          int32_t m, double curvature_K, const clm_rays* rays,
+                          hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CALCLENS_MI_H */

@@ -1,0 +1,268 @@
+"""Python binding of libcalclens_mi.so (ctypes).  Argument marshalling only:
+tensors are passed by device pointer together with the current HIP stream;
+every step of the computation runs in the library's kernels.  Raises when
+the library is missing or a call fails; there is no fallback path."""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcalclens_mi.so")
+
+CLM_OK, CLM_EINVAL, CLM_ENOMEM, CLM_EHIP = 0, 1, 2, 3
+CLM_ENOTCONV, CLM_ERAY_LEFT_PATCH, CLM_ENONFINITE, CLM_EUNSUPPORTED = 4, 5, 6, 7
+FP64, FP32 = 0, 1
+SOLVER_SHT, SOLVER_SHT_MG = 0, 1
+ORDER_RING, ORDER_NESTED = 0, 1
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in (
+        "nside_fine", "nside_sht", "lmax", "nside_bundle", "patch_factor", "patch_cells",
+        "mg_vcycles", "nu_pre", "nu_post", "solver", "mg_prec", "max_planes")]
+
+
+class Rays(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("beta", ctypes.c_void_p),
+                ("A", ctypes.c_void_p), ("A_prev", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class Galaxies(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("chi", ctypes.c_void_p),
+                ("A", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class ClmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (status %d)" % (msg, status))
+        self.status = status
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "clm_plan_desc_default": (ctypes.POINTER(PlanDesc), _I32),
+    "clm_plan_create": (ctypes.POINTER(PlanDesc), ctypes.c_int, ctypes.POINTER(_P)),
+    "clm_plan_destroy": (_P,),
+    "clm_status_string": (_I32,),
+    "clm_plan_last_error": (_P, ctypes.c_char_p, ctypes.c_size_t),
+    "clm_plan_sync_status": (_P, _P),
+    "clm_plan_workspace_bytes": (_P,),
+    "clm_plan_get_desc": (_P, ctypes.POINTER(PlanDesc)),
+    "clm_alm2map": (_P, _I32, _I32, _P, _P),
+    "clm_poisson_solve": (_P, _P, _I32, _I32, _I32, _P),
+    "clm_get_psi_alm": (_P, _I32, _P, _P),
+    "clm_get_psi_map": (_P, _I32, _P, _P),
+    "clm_get_patch_potential": (_P, _I32, _I64, _I64, _P, _P),
+    "clm_shear_from_potential": (_P, _I32, _P, _P, _I64, _I32, _P, _P, _P),
+    "clm_shear_at_pixels": (_P, _I32, _I32, _I32, _P, _P, _P),
+    "clm_rays_init": (_P, ctypes.POINTER(Rays), _P),
+    "clm_raytrace_planes": (_P, _P, _I32, ctypes.POINTER(_D), _I32, _I32, _I32, _D,
+                            ctypes.POINTER(Rays), ctypes.POINTER(Galaxies), _P),
+    "clm_ray_update": (_P, _I32, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays), _P),
+}
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcalclens_mi.so is not built: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = list(args)
+            f.restype = ctypes.c_int32
+        L.clm_status_string.restype = ctypes.c_char_p
+        L.clm_plan_workspace_bytes.restype = ctypes.c_size_t
+        _lib = L
+    return _lib
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError("expected a contiguous %s tensor on the GPU" % dtype)
+    return t
+
+
+def nalm(lmax):
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def alm2map(alm, lmax, nside):
+    """Real map (RING, float64) of complex a_lm (HEALPix order) on the GPU."""
+    a = torch.view_as_real(_dev(alm, torch.complex128)).contiguous()
+    out = torch.empty(12 * nside * nside, dtype=torch.float64, device=alm.device)
+    st = lib().clm_alm2map(_ptr(a), lmax, nside, _ptr(out), _stream())
+    if st != CLM_OK:
+        raise ClmError(st, "clm_alm2map failed: %s" % lib().clm_status_string(st).decode())
+    return out
+
+
+class Plan:
+    """A solver plan (workspace on the current device)."""
+
+    def __init__(self, nside_fine, device=None, **kw):
+        L = lib()
+        d = PlanDesc()
+        self._check(L.clm_plan_desc_default(ctypes.byref(d), nside_fine), "desc_default", None)
+        for k, v in kw.items():
+            if k == "solver" and isinstance(v, str):
+                v = {"sht": SOLVER_SHT, "sht_mg": SOLVER_SHT_MG}[v]
+            if k == "mg_prec" and isinstance(v, str):
+                v = {"fp64": FP64, "fp32": FP32}[v]
+            setattr(d, k, int(v))
+        dev = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        st = L.clm_plan_create(ctypes.byref(d), dev, ctypes.byref(h))
+        if st != CLM_OK:
+            raise ClmError(st, "clm_plan_create failed: %s" % L.clm_status_string(st).decode())
+        self.h = h
+        self.device = torch.device("cuda", dev)
+        out = PlanDesc()
+        L.clm_plan_get_desc(self.h, ctypes.byref(out))
+        self.desc = {f: getattr(out, f) for f, _ in PlanDesc._fields_}
+        nf = self.desc["nside_fine"]
+        self.npix_fine = 12 * nf * nf
+        self.npix_sht = 12 * self.desc["nside_sht"] ** 2
+        self.lmax = self.desc["lmax"]
+
+    def _check(self, st, what, h="self"):
+        if st == CLM_OK:
+            return
+        L = lib()
+        msg = "%s: %s" % (what, L.clm_status_string(st).decode())
+        if h == "self" and getattr(self, "h", None):
+            buf = ctypes.create_string_buffer(512)
+            L.clm_plan_last_error(self.h, buf, 512)
+            if buf.value:
+                msg += " (" + buf.value.decode() + ")"
+        raise ClmError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().clm_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self):
+        return lib().clm_plan_workspace_bytes(self.h)
+
+    def sync_status(self):
+        """Synchronise and raise if a kernel latched an error."""
+        self._check(lib().clm_plan_sync_status(self.h, _stream()), "device status")
+
+    # ---------------------------------------------------------------- solve
+    def poisson_solve(self, kappa, first_slot=0):
+        k = kappa if kappa.dim() == 2 else kappa.reshape(1, -1)
+        if k.dtype not in (torch.float64, torch.float32):
+            raise ValueError("kappa must be float64 or float32")
+        _dev(k, k.dtype)
+        if k.shape[1] != self.npix_fine:
+            raise ValueError("kappa has %d pixels, plan expects %d" % (k.shape[1], self.npix_fine))
+        self._check(lib().clm_poisson_solve(self.h, _ptr(k), int(k.dtype == torch.float64),
+                                            first_slot, k.shape[0], _stream()), "poisson_solve")
+
+    def psi_alm(self, slot=0):
+        out = torch.empty(nalm(self.lmax), 2, dtype=torch.float64, device=self.device)
+        self._check(lib().clm_get_psi_alm(self.h, slot, _ptr(out), _stream()), "get_psi_alm")
+        return torch.view_as_complex(out)
+
+    def psi_map(self, slot=0):
+        out = torch.empty(self.npix_sht, dtype=torch.float64, device=self.device)
+        self._check(lib().clm_get_psi_map(self.h, slot, _ptr(out), _stream()), "get_psi_map")
+        return out
+
+    def patch_potential(self, first, npatch, slot=0):
+        n = self.desc["patch_cells"]
+        out = torch.empty(npatch, n, n, dtype=torch.float64, device=self.device)
+        self._check(lib().clm_get_patch_potential(self.h, slot, first, npatch, _ptr(out),
+                                                  _stream()), "get_patch_potential")
+        return out
+
+    def shear_from_potential(self, theta, phi, slot=0, fp64=True):
+        _dev(theta, torch.float64)
+        _dev(phi, torch.float64)
+        n = theta.numel()
+        dt = torch.float64 if fp64 else torch.float32
+        g = torch.empty(2, n, dtype=dt, device=self.device)
+        h = torch.empty(3, n, dtype=dt, device=self.device)
+        self._check(lib().clm_shear_from_potential(self.h, slot, _ptr(theta), _ptr(phi), n,
+                                                   int(fp64), _ptr(g), _ptr(h), _stream()),
+                    "shear_from_potential")
+        return g, h
+
+    def shear_at_pixels(self, slot=0, order="ring", fp64=True, out=None):
+        o = ORDER_RING if order == "ring" else ORDER_NESTED
+        dt = torch.float64 if fp64 else torch.float32
+        if out is None:
+            g = torch.empty(2, self.npix_fine, dtype=dt, device=self.device)
+            h = torch.empty(3, self.npix_fine, dtype=dt, device=self.device)
+        else:
+            g, h = out
+        self._check(lib().clm_shear_at_pixels(self.h, slot, o, int(fp64), _ptr(g), _ptr(h),
+                                              _stream()), "shear_at_pixels")
+        return g, h
+
+    # ---------------------------------------------------------------- rays
+    def new_rays(self):
+        n = self.npix_fine
+        f64 = dict(dtype=torch.float64, device=self.device)
+        f32 = dict(dtype=torch.float32, device=self.device)
+        r = dict(theta=torch.empty(n, **f64), phi=torch.empty(n, **f64),
+                 beta=torch.empty(3, n, **f64), A=torch.empty(4, n, **f32),
+                 A_prev=torch.empty(4, n, **f32))
+        self.rays_init(r)
+        return r
+
+    @staticmethod
+    def _rays_struct(r):
+        return Rays(r["theta"].data_ptr(), r["phi"].data_ptr(), r["beta"].data_ptr(),
+                    r["A"].data_ptr(), r["A_prev"].data_ptr(), r["theta"].numel())
+
+    def rays_init(self, r):
+        s = self._rays_struct(r)
+        self._check(lib().clm_rays_init(self.h, ctypes.byref(s), _stream()), "rays_init")
+
+    def raytrace_planes(self, kappa, chi, first_plane, rays, K=0.0, galaxies=None):
+        k = kappa if kappa.dim() == 2 else kappa.reshape(1, -1)
+        _dev(k, k.dtype)
+        chi = np.ascontiguousarray(chi, dtype=np.float64)
+        s = self._rays_struct(rays)
+        gp = None
+        if galaxies is not None:
+            g = Galaxies(galaxies["theta"].data_ptr(), galaxies["phi"].data_ptr(),
+                         galaxies["chi"].data_ptr(), galaxies["A"].data_ptr(),
+                         galaxies["theta"].numel())
+            gp = ctypes.byref(g)
+        self._check(lib().clm_raytrace_planes(
+            self.h, _ptr(k), int(k.dtype == torch.float64),
+            chi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), chi.size, first_plane,
+            k.shape[0], K, ctypes.byref(s), gp, _stream()), "raytrace_planes")
+
+    def ray_update(self, chi, m, rays, slot=0, K=0.0):
+        chi = np.ascontiguousarray(chi, dtype=np.float64)
+        s = self._rays_struct(rays)
+        self._check(lib().clm_ray_update(self.h, slot,
+                                         chi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         chi.size, m, K, ctypes.byref(s), _stream()),
+                    "ray_update")

@@ -1,0 +1,131 @@
+// Internal definitions shared by the library's translation units: the plan
+// object, error plumbing and the launchers each stage exports.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "calclens_mi.h"
+
+namespace clm {
+
+// Device-side latched conditions (bit flags in plan->status_dev).
+enum : int { ST_LEFT_PATCH = 1, ST_NONFINITE = 2 };
+
+// Largest multigrid level handled entirely inside one workgroup's LDS.
+constexpr int kLdsLevelMax = 64;
+// Interior side of the multigrid tiles streamed through LDS on larger levels.
+constexpr int kTile = 64;
+
+struct LevelGeom {
+  int n;         // cells per side
+  size_t crow;   // offset of this level's row coefficients (4 doubles per row)
+};
+
+struct Slot {
+  double* alm = nullptr;     // [nalm] complex (2 doubles each)
+  double* psi_s = nullptr;   // [npix_s]
+  double* u0 = nullptr;      // [npatch][(n+2)^2], SHT+MG only
+  void* du = nullptr;        // [npatch][n^2] of T, SHT+MG only
+};
+
+struct Plan {
+  clm_plan_desc d{};
+  int device = 0;
+  bool mg = false;
+  bool fp64mg = false;
+  int64_t npix_f = 0, npix_s = 0, nalm = 0, nbundle = 0;
+  int nring_s = 0, nring_f = 0, H = 0;  // rings; north rings incl. equator
+  int n = 0, nlev = 0, ktile = 0;       // patch cells, levels, first LDS level
+  int bundle_shift = 0;                 // ray NESTED index >> shift = bundle
+  double side_b = 0, L = 0, delta = 0;
+  std::vector<LevelGeom> lev;
+  size_t bytes = 0;
+  std::string err;
+
+  // tables
+  double* ring_s = nullptr;     // [nring_s][4]: z, sin theta, theta, phi0
+  int* ringi_s = nullptr;       // [nring_s][2]: n, first
+  double* ring_f = nullptr;     // same for the fine grid
+  int* ringi_f = nullptr;
+  double* lam_mant = nullptr;   // [lmax+1][H] lambda_mm mantissa
+  int* lam_scale = nullptr;     // [lmax+1][H] scale exponent (units of 2^800)
+  int* r2n_s = nullptr;         // RING -> NESTED at nside_sht
+  int* r2n_f = nullptr;         // RING -> NESTED at nside_fine
+  double* rot = nullptr;        // [nbundle][9] patch rotations R_b
+  double* coef = nullptr;       // level row coefficients
+  double* cinv = nullptr;       // [16*16] inverse of the coarsest operator
+
+  // scratch
+  double* kap_s = nullptr;      // [npix_s] degraded, demeaned kappa
+  double* F = nullptr;          // [nring_s][lmax+1] complex
+  double* G = nullptr;          // [5][nring_s][lmax+1] complex (synthesis)
+  double* red = nullptr;        // [1024] reduction partials; red[1023] = mean
+  double* deriv = nullptr;      // [5][npix_s] pure-SHT raw derivative maps
+  void* fprime = nullptr;       // [npatch][n^2] T
+  void* dutmp = nullptr;        // [npatch][n^2] T (ping-pong partner of du)
+  // per coarser tile level k (1 .. ktile), and the LDS level ktile:
+  std::vector<void*> ubar, rbar, flev, ulev, ulev2;
+  int* status_dev = nullptr;
+
+  std::vector<Slot> slots;
+
+  ~Plan();
+};
+
+#define CLM_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      p->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+      return CLM_EHIP;                                                       \
+    }                                                                        \
+  } while (0)
+
+#define CLM_LAUNCH_CHECK()                                                   \
+  do {                                                                       \
+    hipError_t e_ = hipGetLastError();                                       \
+    if (e_ != hipSuccess) {                                                  \
+      p->err = std::string("kernel launch: ") + hipGetErrorString(e_);       \
+      return CLM_EHIP;                                                       \
+    }                                                                        \
+  } while (0)
+
+inline clm_status fail(Plan* p, clm_status s, const std::string& msg) {
+  if (p) p->err = msg;
+  return s;
+}
+
+// ---- stage launchers (each returns CLM_OK or an error recorded in p->err)
+clm_status build_tables(Plan* p);                       // plan.hip
+clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot,
+                     hipStream_t s);                    // sht.hip
+clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64,
+                            void* grad, void* hess, hipStream_t s);  // sht.hip
+clm_status mg_solve(Plan* p, const void* kappa, int kappa_fp64, int slot,
+                    hipStream_t s);                     // mg.hip
+clm_status mg_patch_potential(Plan* p, int slot, int64_t first, int64_t np,
+                              double* out, hipStream_t s);  // mg.hip
+clm_status eval_points(Plan* p, int slot, const double* th, const double* ph,
+                       int64_t npts, int order, int out_fp64, void* grad,
+                       void* hess, hipStream_t s);      // eval.hip
+clm_status rays_init(Plan* p, const clm_rays* r, hipStream_t s);  // rays.hip
+clm_status ray_update(Plan* p, int slot, const double* chi, int nchi, int m,
+                      double K, const clm_rays* r, hipStream_t s);   // rays.hip
+clm_status galaxies_shell(Plan* p, const double* chi, int nchi, int k, double K,
+                          const clm_rays* r, const clm_galaxies* g,
+                          hipStream_t s);               // rays.hip
+
+inline int ilog2(int64_t v) {
+  int k = 0;
+  while ((int64_t(1) << (k + 1)) <= v) ++k;
+  return k;
+}
+
+}  // namespace clm
+
+struct clm_plan_s : clm::Plan {};

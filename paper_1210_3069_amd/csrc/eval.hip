@@ -1,0 +1,103 @@
+// Deflection and shear at points or at every pixel centre from the solved
+// patch potentials (Sec. 3.2): one thread per point, gather of the 6 x 6
+// cell window around the point from u0 (float64) and du.
+#include <cmath>
+
+#include "clm_internal.h"
+#include "eval_dev.h"
+#include "healpix_dev.h"
+
+namespace clm {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct EvalArgs {
+  PatchField P;
+  const double* th;    // nullptr: all pixel centres of the fine grid
+  const double* ph;
+  int64_t npts;
+  int order;           // pixel mode: CLM_ORDER_RING or CLM_ORDER_NESTED
+  const int* r2n_f;
+  int64_t Nf, Nb;
+  int shift;
+  void* grad;
+  void* hess;
+  int* status;
+};
+
+template <typename T, typename TO>
+__global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.npts) return;
+  double vx, vy, vz;
+  int64_t b;
+  if (a.th) {
+    double st, ct, sp, cp;
+    sincos(a.th[i], &st, &ct);
+    sincos(a.ph[i], &sp, &cp);
+    vx = st * cp; vy = st * sp; vz = ct;
+    b = hpx::ang2nest(a.Nb, ct, a.ph[i]);
+  } else {
+    int64_t pring, pnest;
+    if (a.order == CLM_ORDER_NESTED) {
+      pnest = i;
+      pring = hpx::nest2ring(a.Nf, i);
+    } else {
+      pring = i;
+      pnest = a.r2n_f[i];
+    }
+    double z, st, phi;
+    hpx::pix2ang_ring(a.Nf, pring, z, st, phi);
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    vx = st * cp; vy = st * sp; vz = z;
+    b = pnest >> a.shift;
+  }
+  double g[2], U[3];
+  TO* gr = static_cast<TO*>(a.grad);
+  TO* hs = static_cast<TO*>(a.hess);
+  if (!eval_patch<T>(a.P, b, vx, vy, vz, g, U)) {
+    atomicOr(a.status, ST_LEFT_PATCH);
+    const TO nan = TO(NAN);
+    gr[i] = nan; gr[a.npts + i] = nan;
+    hs[i] = nan; hs[a.npts + i] = nan; hs[2 * a.npts + i] = nan;
+    return;
+  }
+  gr[i] = TO(g[0]);
+  gr[a.npts + i] = TO(g[1]);
+  hs[i] = TO(U[0]);
+  hs[a.npts + i] = TO(U[1]);
+  hs[2 * a.npts + i] = TO(U[2]);
+}
+
+}  // namespace
+
+clm_status eval_points(Plan* p, int slot, const double* th, const double* ph, int64_t npts,
+                       int order, int out_fp64, void* grad, void* hess, hipStream_t s) {
+  EvalArgs a;
+  a.P = PatchField{p->rot, p->slots[slot].u0, p->slots[slot].du, p->n, p->L, p->delta};
+  a.th = th;
+  a.ph = ph;
+  a.npts = npts;
+  a.order = order;
+  a.r2n_f = p->r2n_f;
+  a.Nf = p->d.nside_fine;
+  a.Nb = p->d.nside_bundle;
+  a.shift = p->bundle_shift;
+  a.grad = grad;
+  a.hess = hess;
+  a.status = p->status_dev;
+  const dim3 g((npts + kBlock - 1) / kBlock);
+  if (p->fp64mg) {
+    if (out_fp64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eval<double, double>), g, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eval<double, float>), g, dim3(kBlock), 0, s, a);
+  } else {
+    if (out_fp64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eval<float, double>), g, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eval<float, float>), g, dim3(kBlock), 0, s, a);
+  }
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+}  // namespace clm

@@ -1,0 +1,204 @@
+// Gradient and covariant Hessian of the patch potential u0 + du at a point
+// (Sec. 3.2 last paragraphs, App. A): 4th-order finite differences of the
+// raw partials psi_t', psi_p', psi_t't', psi_p'p', psi_t'p' at the four
+// cells around the point, bilinear interpolation to the point, metric terms
+// at the point's own theta', rotation to the global (theta-hat, phi-hat)
+// basis.  Shared by the shear evaluation and the ray update.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace clm {
+
+struct PatchField {
+  const double* rot;   // [nbundle][9]
+  const double* u0;    // [nbundle][(n+2)^2] with ghosts
+  const void* du;      // [nbundle][n^2] of T
+  int n;
+  double L, delta;
+};
+
+// u = u0 + du at cell (i, j), i, j in [-1, n]; du across the patch face is
+// the negative of the interior cell it faces (zero face value).
+template <typename T>
+__device__ __forceinline__ double patch_u(const double* u0, const T* du, int n, int i, int j) {
+  const double a = u0[(i + 1) * (n + 2) + (j + 1)];
+  int ii = i, jj = j;
+  double sg = 1.0;
+  if (ii < 0) { ii = 0; sg = -1.0; }
+  if (ii > n - 1) { ii = n - 1; sg = -1.0; }
+  if (jj < 0) { jj = 0; sg = -1.0; }
+  if (jj > n - 1) { jj = n - 1; sg = -1.0; }
+  return a + sg * double(du[ii * n + jj]);
+}
+
+// 4th-order first- and second-derivative stencils at cell c of n along one
+// axis: offsets o[k] = first + k and weights in units of 1/12.
+struct Stencil {
+  int first, len;
+  double w[6];
+};
+
+__device__ __forceinline__ Stencil d1_stencil(int c, int n) {
+  Stencil s;
+  if (c >= 1 && c <= n - 2) {
+    s.first = -2; s.len = 5;
+    s.w[0] = 1; s.w[1] = -8; s.w[2] = 0; s.w[3] = 8; s.w[4] = -1;
+  } else if (c == 0) {  // nodes -1 .. 3
+    s.first = -1; s.len = 5;
+    s.w[0] = -3; s.w[1] = -10; s.w[2] = 18; s.w[3] = -6; s.w[4] = 1;
+  } else {              // nodes -3 .. 1
+    s.first = -3; s.len = 5;
+    s.w[0] = -1; s.w[1] = 6; s.w[2] = -18; s.w[3] = 10; s.w[4] = 3;
+  }
+  s.w[5] = 0;
+  return s;
+}
+
+__device__ __forceinline__ Stencil d2_stencil(int c, int n) {
+  Stencil s;
+  if (c >= 1 && c <= n - 2) {
+    s.first = -2; s.len = 5;
+    s.w[0] = -1; s.w[1] = 16; s.w[2] = -30; s.w[3] = 16; s.w[4] = -1; s.w[5] = 0;
+  } else if (c == 0) {  // nodes -1 .. 4
+    s.first = -1; s.len = 6;
+    s.w[0] = 10; s.w[1] = -15; s.w[2] = -4; s.w[3] = 14; s.w[4] = -6; s.w[5] = 1;
+  } else {              // nodes -4 .. 1
+    s.first = -4; s.len = 6;
+    s.w[0] = 1; s.w[1] = -6; s.w[2] = 14; s.w[3] = -4; s.w[4] = -15; s.w[5] = 10;
+  }
+  return s;
+}
+
+// Raw partials at cell (i, j) with the general (edge-aware) stencils.
+template <typename T>
+__device__ void partials_general(const double* u0, const T* du, int n, int i, int j, double h,
+                                 double out[5]) {
+  const Stencil a1 = d1_stencil(i, n), b1 = d1_stencil(j, n);
+  const Stencil a2 = d2_stencil(i, n), b2 = d2_stencil(j, n);
+  double pt = 0, pp = 0, ptt = 0, ppp = 0, ptp = 0;
+  for (int k = 0; k < a1.len; ++k) pt += a1.w[k] * patch_u(u0, du, n, i + a1.first + k, j);
+  for (int k = 0; k < b1.len; ++k) pp += b1.w[k] * patch_u(u0, du, n, i, j + b1.first + k);
+  for (int k = 0; k < a2.len; ++k) ptt += a2.w[k] * patch_u(u0, du, n, i + a2.first + k, j);
+  for (int k = 0; k < b2.len; ++k) ppp += b2.w[k] * patch_u(u0, du, n, i, j + b2.first + k);
+  for (int k = 0; k < a1.len; ++k) {
+    if (a1.w[k] == 0) continue;
+    double row = 0;
+    for (int q = 0; q < b1.len; ++q)
+      row += b1.w[q] * patch_u(u0, du, n, i + a1.first + k, j + b1.first + q);
+    ptp += a1.w[k] * row;
+  }
+  out[0] = pt / (12 * h);
+  out[1] = pp / (12 * h);
+  out[2] = ptt / (12 * h * h);
+  out[3] = ppp / (12 * h * h);
+  out[4] = ptp / (144 * h * h);
+}
+
+// g = (g_t, g_p), U = (U_tt, U_pp, U_tp) of psi at unit vector v in patch b,
+// global basis.  Returns false when the bilinear footprint leaves the patch.
+template <typename T>
+__device__ bool eval_patch(const PatchField& P, int64_t b, double vx, double vy, double vz,
+                           double g[2], double U[3]) {
+  const double pi = 3.14159265358979323846;
+  const double* R = P.rot + 9 * b;
+  const double px = R[0] * vx + R[1] * vy + R[2] * vz;
+  const double py = R[3] * vx + R[4] * vy + R[5] * vz;
+  const double pz = R[6] * vx + R[7] * vy + R[8] * vz;
+  const double sp_ = sqrt(px * px + py * py);  // sin theta'
+  const double thp = atan2(sp_, pz);
+  const double php = atan2(py, px);
+  const int n = P.n;
+  const double h = P.delta;
+  const double fi = (thp - (pi / 2 - P.L / 2)) / h - 0.5;
+  const double fj = (php + P.L / 2) / h - 0.5;
+  const double ffi = floor(fi), ffj = floor(fj);
+  if (!(ffi >= 0 && ffi <= n - 2 && ffj >= 0 && ffj <= n - 2)) return false;
+  const int i0 = int(ffi), j0 = int(ffj);
+  const double t = fi - ffi, s = fj - ffj;
+  const double* u0 = P.u0 + size_t(b) * (n + 2) * (n + 2);
+  const T* du = static_cast<const T*>(P.du) + size_t(b) * n * n;
+  double Pc[4][5];
+  if (i0 >= 2 && i0 + 3 <= n - 1 && j0 >= 2 && j0 + 3 <= n - 1) {
+    // centred stencils only: a 6 x 6 window of u around the four cells
+    double w[6][6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const double* ur = u0 + (i0 - 2 + r + 1) * (n + 2) + (j0 - 2 + 1);
+      const T* dr = du + (i0 - 2 + r) * n + (j0 - 2);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) w[r][c] = ur[c] + double(dr[c]);
+    }
+    const double c1[4] = {1, -8, 8, -1};
+    const int o1[4] = {-2, -1, 1, 2};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = 2 + (k >> 1), c = 2 + (k & 1);
+      const double pt = w[r - 2][c] - 8 * w[r - 1][c] + 8 * w[r + 1][c] - w[r + 2][c];
+      const double pp = w[r][c - 2] - 8 * w[r][c - 1] + 8 * w[r][c + 1] - w[r][c + 2];
+      const double ptt = -w[r - 2][c] + 16 * w[r - 1][c] - 30 * w[r][c] + 16 * w[r + 1][c] -
+                         w[r + 2][c];
+      const double ppp = -w[r][c - 2] + 16 * w[r][c - 1] - 30 * w[r][c] + 16 * w[r][c + 1] -
+                         w[r][c + 2];
+      double ptp = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        double row = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) row += c1[q] * w[r + o1[a]][c + o1[q]];
+        ptp += c1[a] * row;
+      }
+      Pc[k][0] = pt / (12 * h);
+      Pc[k][1] = pp / (12 * h);
+      Pc[k][2] = ptt / (12 * h * h);
+      Pc[k][3] = ppp / (12 * h * h);
+      Pc[k][4] = ptp / (144 * h * h);
+    }
+  } else {
+    for (int k = 0; k < 4; ++k)
+      partials_general<T>(u0, du, n, i0 + (k >> 1), j0 + (k & 1), h, Pc[k]);
+  }
+  double Pv[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q)
+    Pv[q] = (1 - t) * (1 - s) * Pc[0][q] + (1 - t) * s * Pc[1][q] + t * (1 - s) * Pc[2][q] +
+            t * s * Pc[3][q];
+  // covariant components in the patch frame at the point (App. A)
+  const double st = sp_, ct = pz;
+  const double gpt = Pv[0], gpp = Pv[1] / st;
+  const double Utt = Pv[2];
+  const double Upp = Pv[3] / (st * st) + (ct / st) * Pv[0];
+  const double Utp = Pv[4] / st - ct * Pv[1] / (st * st);
+  // patch basis at the point, in global coordinates: R^T (theta'-hat, phi'-hat)
+  const double cpp = px / st, spp = py / st;
+  const double et_p[3] = {ct * cpp, ct * spp, -st};
+  const double ep_p[3] = {-spp, cpp, 0.0};
+  double etp[3], epp[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    etp[k] = R[k] * et_p[0] + R[3 + k] * et_p[1] + R[6 + k] * et_p[2];
+    epp[k] = R[k] * ep_p[0] + R[3 + k] * ep_p[1] + R[6 + k] * ep_p[2];
+  }
+  // global basis at the point
+  const double sg = sqrt(vx * vx + vy * vy);
+  const double cph = vx / sg, sph = vy / sg;
+  const double et[3] = {vz * cph, vz * sph, -sg};
+  const double ep[3] = {-sph, cph, 0.0};
+  const double q00 = et[0] * etp[0] + et[1] * etp[1] + et[2] * etp[2];
+  const double q01 = et[0] * epp[0] + et[1] * epp[1] + et[2] * epp[2];
+  const double q10 = ep[0] * etp[0] + ep[1] * etp[1] + ep[2] * etp[2];
+  const double q11 = ep[0] * epp[0] + ep[1] * epp[1] + ep[2] * epp[2];
+  g[0] = q00 * gpt + q01 * gpp;
+  g[1] = q10 * gpt + q11 * gpp;
+  // U = Q U' Q^T
+  const double a00 = q00 * Utt + q01 * Utp, a01 = q00 * Utp + q01 * Upp;
+  const double a10 = q10 * Utt + q11 * Utp, a11 = q10 * Utp + q11 * Upp;
+  U[0] = a00 * q00 + a01 * q01;
+  U[1] = a10 * q10 + a11 * q11;
+  U[2] = a00 * q10 + a01 * q11;
+  return true;
+}
+
+}  // namespace clm

@@ -1,0 +1,548 @@
+// Plan creation, workspace, geometry tables and the small C-ABI entry points
+// (status, getters, dispatch to the stage launchers).
+#include <cmath>
+#include <cstring>
+
+#include "clm_internal.h"
+#include "healpix_dev.h"
+
+namespace clm {
+
+Plan::~Plan() {
+  auto f = [](void* q) { if (q) (void)hipFree(q); };
+  f(ring_s); f(ringi_s); f(ring_f); f(ringi_f); f(lam_mant); f(lam_scale);
+  f(r2n_s); f(r2n_f); f(rot); f(coef); f(cinv); f(kap_s); f(F); f(G); f(red);
+  f(deriv); f(fprime); f(dutmp); f(status_dev);
+  for (auto* q : ubar) f(q);
+  for (auto* q : rbar) f(q);
+  for (auto* q : flev) f(q);
+  for (auto* q : ulev) f(q);
+  for (auto* q : ulev2) f(q);
+  for (auto& s : slots) { f(s.alm); f(s.psi_s); f(s.u0); f(s.du); }
+}
+
+namespace {
+
+bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Host ring tables of a HEALPix grid (rings 1..4N-1 stored 0-based).
+void host_rings(int N, std::vector<double>& rt, std::vector<int>& ri) {
+  const int nr = 4 * N - 1;
+  rt.assign(4 * nr, 0.0);
+  ri.assign(2 * nr, 0);
+  const double pi = 3.14159265358979323846;
+  for (int q = 0; q < nr; ++q) {
+    const int64_t i = q + 1;
+    double z, st;
+    int64_t n, first;
+    bool shifted = true;
+    if (i < N) {
+      const double omz = double(i) * double(i) / (3.0 * N * N);
+      z = 1.0 - omz;
+      st = std::sqrt(omz * (1.0 + z));
+      n = 4 * i;
+      first = 2 * i * (i - 1);
+    } else if (i <= 3 * N) {
+      z = (4.0 * N - 2.0 * i) / (3.0 * N);
+      st = std::sqrt((1.0 - z) * (1.0 + z));
+      n = 4 * N;
+      first = 2 * int64_t(N) * (N - 1) + 4 * int64_t(N) * (i - N);
+      shifted = ((i - N) % 2) == 0;
+    } else {
+      const int64_t ip = 4 * N - i;
+      const double opz = double(ip) * double(ip) / (3.0 * N * N);
+      z = opz - 1.0;
+      st = std::sqrt(opz * (2.0 - opz));
+      n = 4 * ip;
+      first = 12 * int64_t(N) * N - 2 * ip * (ip + 1);
+    }
+    rt[4 * q + 0] = z;
+    rt[4 * q + 1] = st;
+    rt[4 * q + 2] = std::atan2(st, z);
+    rt[4 * q + 3] = shifted ? pi / double(n) : 0.0;
+    ri[2 * q + 0] = int(n);
+    ri[2 * q + 1] = int(first);
+  }
+}
+
+// lambda_mm(theta_q) for the north rings, by the product recursion
+// lambda_00 = 1/sqrt(4 pi), lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1},
+// with a scale exponent in units of 2^800 keeping the mantissa above 2^-400.
+__global__ void k_lambda_mm(const double* rt, int H, int lmax, double* mant, int* scale) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= H) return;
+  const double st = rt[4 * q + 1];
+  double v = 0.28209479177387814347403972578039;  // 1/sqrt(4 pi)
+  int s = 0;
+  mant[q] = v;
+  scale[q] = 0;
+  const double tiny = 0x1p-400, big = 0x1p800;
+  for (int m = 1; m <= lmax; ++m) {
+    v *= -sqrt((2.0 * m + 1.0) / (2.0 * m)) * st;
+    if (fabs(v) < tiny) {
+      v *= big;
+      s -= 1;
+    }
+    mant[size_t(m) * H + q] = v;
+    scale[size_t(m) * H + q] = s;
+  }
+}
+
+__global__ void k_ring2nest(int64_t N, int* table) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= 12 * N * N) return;
+  table[hpx::nest2ring(N, p)] = int(p);
+}
+
+// R_b rows (c, phi-hat_c, -theta-hat_c) for every bundle (NESTED index).
+__global__ void k_rotations(int64_t Nb, int64_t nb, double* rot) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  double z, st, phi;
+  hpx::pix2ang_ring(Nb, hpx::nest2ring(Nb, b), z, st, phi);
+  const double cp = cos(phi), sp = sin(phi);
+  double* R = rot + 9 * b;
+  R[0] = st * cp; R[1] = st * sp; R[2] = z;        // c
+  R[3] = -sp;     R[4] = cp;      R[5] = 0.0;      // phi-hat
+  R[6] = -z * cp; R[7] = -z * sp; R[8] = st;       // -theta-hat
+}
+
+template <typename T>
+clm_status alloc(Plan* p, T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) return CLM_OK;
+  hipError_t e = hipMalloc((void**)ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    p->err = "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed";
+    return CLM_ENOMEM;
+  }
+  p->bytes += count * sizeof(T);
+  return CLM_OK;
+}
+
+#define CLM_TRY(x)                   \
+  do {                               \
+    clm_status s_ = (x);             \
+    if (s_ != CLM_OK) return s_;     \
+  } while (0)
+
+// Dense inverse (Gauss-Jordan, partial pivoting) of an n x n matrix.
+bool invert(std::vector<double>& a, int n) {
+  std::vector<double> inv(n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[r * n + c]) > std::fabs(a[piv * n + c])) piv = r;
+    if (a[piv * n + c] == 0.0) return false;
+    for (int k = 0; k < n; ++k) {
+      std::swap(a[c * n + k], a[piv * n + k]);
+      std::swap(inv[c * n + k], inv[piv * n + k]);
+    }
+    const double d = a[c * n + c];
+    for (int k = 0; k < n; ++k) { a[c * n + k] /= d; inv[c * n + k] /= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        a[r * n + k] -= f * a[c * n + k];
+        inv[r * n + k] -= f * inv[c * n + k];
+      }
+    }
+  }
+  a = inv;
+  return true;
+}
+
+}  // namespace
+
+clm_status build_tables(Plan* p) {
+  const clm_plan_desc& d = p->d;
+  std::vector<double> rt;
+  std::vector<int> ri;
+  host_rings(d.nside_sht, rt, ri);
+  CLM_TRY(alloc(p, &p->ring_s, rt.size()));
+  CLM_TRY(alloc(p, &p->ringi_s, ri.size()));
+  CLM_HIP(hipMemcpy(p->ring_s, rt.data(), rt.size() * 8, hipMemcpyHostToDevice));
+  CLM_HIP(hipMemcpy(p->ringi_s, ri.data(), ri.size() * 4, hipMemcpyHostToDevice));
+  host_rings(d.nside_fine, rt, ri);
+  CLM_TRY(alloc(p, &p->ring_f, rt.size()));
+  CLM_TRY(alloc(p, &p->ringi_f, ri.size()));
+  CLM_HIP(hipMemcpy(p->ring_f, rt.data(), rt.size() * 8, hipMemcpyHostToDevice));
+  CLM_HIP(hipMemcpy(p->ringi_f, ri.data(), ri.size() * 4, hipMemcpyHostToDevice));
+
+  // Legendre starting values on the north rings of the SHT grid
+  CLM_TRY(alloc(p, &p->lam_mant, size_t(d.lmax + 1) * p->H));
+  CLM_TRY(alloc(p, &p->lam_scale, size_t(d.lmax + 1) * p->H));
+  hipLaunchKernelGGL(k_lambda_mm, dim3((p->H + 127) / 128), dim3(128), 0, 0, p->ring_s, p->H,
+                     d.lmax, p->lam_mant, p->lam_scale);
+  CLM_LAUNCH_CHECK();
+
+  CLM_TRY(alloc(p, &p->r2n_s, size_t(p->npix_s)));
+  hipLaunchKernelGGL(k_ring2nest, dim3((p->npix_s + 255) / 256), dim3(256), 0, 0,
+                     int64_t(d.nside_sht), p->r2n_s);
+  CLM_LAUNCH_CHECK();
+  CLM_TRY(alloc(p, &p->r2n_f, size_t(p->npix_f)));
+  hipLaunchKernelGGL(k_ring2nest, dim3((p->npix_f + 255) / 256), dim3(256), 0, 0,
+                     int64_t(d.nside_fine), p->r2n_f);
+  CLM_LAUNCH_CHECK();
+
+  if (!p->mg) return CLM_OK;
+
+  CLM_TRY(alloc(p, &p->rot, size_t(p->nbundle) * 9));
+  hipLaunchKernelGGL(k_rotations, dim3((p->nbundle + 127) / 128), dim3(128), 0, 0,
+                     int64_t(d.nside_bundle), p->nbundle, p->rot);
+  CLM_LAUNCH_CHECK();
+
+  // finite-volume Laplacian row coefficients per level:
+  // s_m = sin theta'_{i-1/2}, s_p = sin theta'_{i+1/2}, s_c = sin theta'_i,
+  // area = 2 Delta_k sin theta'_i sin(Delta_k / 2)
+  const double pi = 3.14159265358979323846;
+  std::vector<double> cf;
+  for (int l = 0; l < p->nlev; ++l) {
+    const int nk = p->n >> l;
+    p->lev.push_back({nk, cf.size()});
+    const double dk = p->L / nk;
+    for (int i = 0; i < nk; ++i) {
+      const double e0 = pi / 2 - p->L / 2 + i * dk;
+      const double e1 = pi / 2 - p->L / 2 + (i + 1) * dk;
+      const double tc = 0.5 * (e0 + e1);
+      cf.push_back(std::sin(e0));
+      cf.push_back(std::sin(e1));
+      cf.push_back(std::sin(tc));
+      cf.push_back(2.0 * dk * std::sin(tc) * std::sin(0.5 * dk));
+    }
+  }
+  CLM_TRY(alloc(p, &p->coef, cf.size()));
+  CLM_HIP(hipMemcpy(p->coef, cf.data(), cf.size() * 8, hipMemcpyHostToDevice));
+
+  // coarsest level (4 x 4): dense operator with zero face values, inverted
+  {
+    const int nc = 4;
+    const double* c = cf.data() + p->lev.back().crow;
+    std::vector<double> M(16 * 16, 0.0);
+    for (int i = 0; i < nc; ++i)
+      for (int j = 0; j < nc; ++j) {
+        const double sm = c[4 * i], sp = c[4 * i + 1], sc = c[4 * i + 2], A = c[4 * i + 3];
+        const int row = i * nc + j;
+        double diag = sm + sp + 2.0 / sc;
+        if (i > 0) M[row * 16 + (i - 1) * nc + j] += sm / A; else diag += sm;
+        if (i < nc - 1) M[row * 16 + (i + 1) * nc + j] += sp / A; else diag += sp;
+        if (j > 0) M[row * 16 + i * nc + j - 1] += 1.0 / (sc * A); else diag += 1.0 / sc;
+        if (j < nc - 1) M[row * 16 + i * nc + j + 1] += 1.0 / (sc * A); else diag += 1.0 / sc;
+        M[row * 16 + row] -= diag / A;
+      }
+    if (!invert(M, 16)) return fail(p, CLM_EINVAL, "singular coarsest operator");
+    CLM_TRY(alloc(p, &p->cinv, 256));
+    CLM_HIP(hipMemcpy(p->cinv, M.data(), 256 * 8, hipMemcpyHostToDevice));
+  }
+  return CLM_OK;
+}
+
+}  // namespace clm
+
+using namespace clm;
+
+extern "C" {
+
+const char* clm_status_string(clm_status s) {
+  switch (s) {
+    case CLM_OK: return "ok";
+    case CLM_EINVAL: return "invalid argument";
+    case CLM_ENOMEM: return "out of device memory";
+    case CLM_EHIP: return "HIP runtime error";
+    case CLM_ENOTCONV: return "multigrid did not converge";
+    case CLM_ERAY_LEFT_PATCH: return "a point left its bundle's patch";
+    case CLM_ENONFINITE: return "non-finite value";
+    case CLM_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+clm_status clm_plan_desc_default(clm_plan_desc* d, int32_t nside_fine) {
+  if (!d || nside_fine < 1) return CLM_EINVAL;
+  std::memset(d, 0, sizeof(*d));
+  d->nside_fine = nside_fine;
+  d->nside_sht = nside_fine >= 8 ? nside_fine / 8 : 1;
+  d->lmax = 2 * d->nside_sht;
+  d->nside_bundle = nside_fine >= 64 ? nside_fine / 64 : 1;
+  d->patch_factor = 4;
+  const int64_t c = int64_t(4) * nside_fine / d->nside_bundle;
+  d->patch_cells = int32_t(c > 256 ? c : 256);
+  d->mg_vcycles = 4;
+  d->nu_pre = 2;
+  d->nu_post = 2;
+  d->solver = CLM_SOLVER_SHT_MG;
+  d->mg_prec = CLM_FP32;
+  d->max_planes = 1;
+  return CLM_OK;
+}
+
+clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out) {
+  if (!out) return CLM_EINVAL;
+  *out = nullptr;
+  if (!desc) return CLM_EINVAL;
+  const clm_plan_desc& d = *desc;
+  if (!pow2(d.nside_fine) || !pow2(d.nside_sht) || d.nside_sht > d.nside_fine ||
+      d.nside_fine > 8192 || d.lmax < 1 || d.max_planes < 1 ||
+      (d.solver != CLM_SOLVER_SHT && d.solver != CLM_SOLVER_SHT_MG))
+    return CLM_EINVAL;
+  if (d.solver == CLM_SOLVER_SHT && d.nside_sht != d.nside_fine) return CLM_EINVAL;
+  if (d.solver == CLM_SOLVER_SHT_MG) {
+    if (!pow2(d.nside_bundle) || d.nside_bundle > d.nside_fine || d.patch_factor < 1 ||
+        !pow2(d.patch_cells) || d.patch_cells < 8 || d.patch_cells > 4096 ||
+        d.mg_vcycles < 1 || d.nu_pre < 1 || d.nu_pre > 4 || d.nu_post < 1 ||
+        d.nu_post > 4 || (d.mg_prec != CLM_FP32 && d.mg_prec != CLM_FP64))
+      return CLM_EINVAL;
+    // the patch must stay far from the poles of its rotated frame
+    const double side = std::sqrt(4.0 * 3.14159265358979323846 /
+                                  (12.0 * double(d.nside_bundle) * d.nside_bundle));
+    if (d.patch_factor * side > 2.0) return CLM_EINVAL;
+  }
+  if (hipSetDevice(device) != hipSuccess) return CLM_EINVAL;
+
+  clm_plan P = new clm_plan_s();
+  Plan* p = P;
+  p->d = d;
+  p->device = device;
+  p->mg = d.solver == CLM_SOLVER_SHT_MG;
+  p->fp64mg = d.mg_prec == CLM_FP64;
+  p->npix_f = 12 * int64_t(d.nside_fine) * d.nside_fine;
+  p->npix_s = 12 * int64_t(d.nside_sht) * d.nside_sht;
+  p->nalm = int64_t(d.lmax + 1) * (d.lmax + 2) / 2;
+  p->nring_s = 4 * d.nside_sht - 1;
+  p->nring_f = 4 * d.nside_fine - 1;
+  p->H = 2 * d.nside_sht;
+  auto bail = [&](clm_status s) {
+    delete P;
+    return s;
+  };
+  if (p->mg) {
+    p->nbundle = 12 * int64_t(d.nside_bundle) * d.nside_bundle;
+    p->bundle_shift = 2 * ilog2(d.nside_fine / d.nside_bundle);
+    p->n = d.patch_cells;
+    p->nlev = ilog2(p->n) - 1;  // n .. 4
+    p->side_b = std::sqrt(4.0 * 3.14159265358979323846 /
+                          (12.0 * double(d.nside_bundle) * d.nside_bundle));
+    p->L = d.patch_factor * p->side_b;
+    p->delta = p->L / p->n;
+    int k = 0;
+    while ((p->n >> k) > kLdsLevelMax) ++k;
+    p->ktile = k;
+  }
+
+  clm_status s;
+  if ((s = build_tables(p)) != CLM_OK) return bail(s);
+
+  const int64_t nF = int64_t(p->nring_s) * (d.lmax + 1) * 2;
+  if ((s = alloc(p, &p->kap_s, size_t(p->npix_s))) != CLM_OK) return bail(s);
+  if ((s = alloc(p, &p->F, size_t(nF))) != CLM_OK) return bail(s);
+  if ((s = alloc(p, &p->G, size_t(nF) * (p->mg ? 1 : 5))) != CLM_OK) return bail(s);
+  if ((s = alloc(p, &p->red, 1024)) != CLM_OK) return bail(s);
+  if ((s = alloc(p, &p->status_dev, 1)) != CLM_OK) return bail(s);
+  if (hipMemset(p->status_dev, 0, sizeof(int)) != hipSuccess) return bail(CLM_EHIP);
+
+  const size_t esz = p->fp64mg ? 8 : 4;
+  p->slots.resize(d.max_planes);
+  for (auto& sl : p->slots) {
+    if ((s = alloc(p, &sl.alm, size_t(p->nalm) * 2)) != CLM_OK) return bail(s);
+    if ((s = alloc(p, &sl.psi_s, size_t(p->npix_s))) != CLM_OK) return bail(s);
+    if (p->mg) {
+      const size_t cells = size_t(p->nbundle) * p->n * p->n;
+      const size_t gcells = size_t(p->nbundle) * (p->n + 2) * (p->n + 2);
+      if ((s = alloc(p, &sl.u0, gcells)) != CLM_OK) return bail(s);
+      char* du = nullptr;
+      if ((s = alloc(p, &du, cells * esz)) != CLM_OK) return bail(s);
+      sl.du = du;
+    }
+  }
+  if (p->mg) {
+    const size_t cells = size_t(p->nbundle) * p->n * p->n;
+    char* q = nullptr;
+    if ((s = alloc(p, &q, cells * esz)) != CLM_OK) return bail(s);
+    p->fprime = q;
+    if ((s = alloc(p, &q, cells * esz)) != CLM_OK) return bail(s);
+    p->dutmp = q;
+    // levels 1 .. ktile: restricted u and residual; tile levels also keep
+    // their source and two iterates
+    p->ubar.assign(p->nlev, nullptr);
+    p->rbar.assign(p->nlev, nullptr);
+    p->flev.assign(p->nlev, nullptr);
+    p->ulev.assign(p->nlev, nullptr);
+    p->ulev2.assign(p->nlev, nullptr);
+    for (int l = 1; l <= p->ktile && l < p->nlev; ++l) {
+      const size_t c = size_t(p->nbundle) * (p->n >> l) * (p->n >> l);
+      if ((s = alloc(p, &q, c * esz)) != CLM_OK) return bail(s);
+      p->ubar[l] = q;
+      if ((s = alloc(p, &q, c * esz)) != CLM_OK) return bail(s);
+      p->rbar[l] = q;
+      if ((s = alloc(p, &q, c * esz)) != CLM_OK) return bail(s);
+      p->ulev[l] = q;
+      if (l < p->ktile) {
+        if ((s = alloc(p, &q, c * esz)) != CLM_OK) return bail(s);
+        p->flev[l] = q;
+        if ((s = alloc(p, &q, c * esz)) != CLM_OK) return bail(s);
+        p->ulev2[l] = q;
+      }
+    }
+  } else {
+    if ((s = alloc(p, &p->deriv, size_t(p->npix_s) * 5)) != CLM_OK) return bail(s);
+  }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    p->err = "device synchronisation after table construction failed";
+    return bail(CLM_EHIP);
+  }
+  *out = P;
+  return CLM_OK;
+}
+
+clm_status clm_plan_destroy(clm_plan plan) {
+  if (!plan) return CLM_EINVAL;
+  (void)hipSetDevice(plan->device);
+  delete plan;
+  return CLM_OK;
+}
+
+clm_status clm_plan_last_error(clm_plan plan, char* buf, size_t len) {
+  if (!plan || !buf || len == 0) return CLM_EINVAL;
+  std::snprintf(buf, len, "%s", plan->err.c_str());
+  return CLM_OK;
+}
+
+size_t clm_plan_workspace_bytes(clm_plan plan) { return plan ? plan->bytes : 0; }
+
+clm_status clm_plan_get_desc(clm_plan plan, clm_plan_desc* out) {
+  if (!plan || !out) return CLM_EINVAL;
+  *out = plan->d;
+  return CLM_OK;
+}
+
+clm_status clm_plan_sync_status(clm_plan plan, hipStream_t stream) {
+  if (!plan) return CLM_EINVAL;
+  Plan* p = plan;
+  int st = 0;
+  CLM_HIP(hipMemcpyAsync(&st, p->status_dev, sizeof(int), hipMemcpyDeviceToHost, stream));
+  CLM_HIP(hipStreamSynchronize(stream));
+  CLM_HIP(hipMemsetAsync(p->status_dev, 0, sizeof(int), stream));
+  CLM_HIP(hipStreamSynchronize(stream));
+  if (st & ST_LEFT_PATCH) return fail(p, CLM_ERAY_LEFT_PATCH, "a point left its bundle's patch");
+  if (st & ST_NONFINITE) return fail(p, CLM_ENONFINITE, "non-finite value produced");
+  return CLM_OK;
+}
+
+clm_status clm_poisson_solve(clm_plan plan, const void* kappa, int32_t kappa_is_fp64,
+                             int32_t first_slot, int32_t nplanes, hipStream_t stream) {
+  if (!plan || !kappa || nplanes < 1 || first_slot < 0 ||
+      first_slot + nplanes > plan->d.max_planes)
+    return CLM_EINVAL;
+  Plan* p = plan;
+  CLM_HIP(hipSetDevice(p->device));
+  const size_t esz = kappa_is_fp64 ? 8 : 4;
+  for (int k = 0; k < nplanes; ++k) {
+    const char* kp = static_cast<const char*>(kappa) + size_t(k) * p->npix_f * esz;
+    clm_status s = sht_solve(p, kp, kappa_is_fp64, first_slot + k, stream);
+    if (s != CLM_OK) return s;
+    if (p->mg) {
+      s = mg_solve(p, kp, kappa_is_fp64, first_slot + k, stream);
+      if (s != CLM_OK) return s;
+    }
+  }
+  return CLM_OK;
+}
+
+clm_status clm_get_psi_alm(clm_plan plan, int32_t slot, double* out, hipStream_t stream) {
+  if (!plan || !out || slot < 0 || slot >= plan->d.max_planes) return CLM_EINVAL;
+  Plan* p = plan;
+  CLM_HIP(hipMemcpyAsync(out, p->slots[slot].alm, size_t(p->nalm) * 16,
+                         hipMemcpyDeviceToDevice, stream));
+  return CLM_OK;
+}
+
+clm_status clm_get_psi_map(clm_plan plan, int32_t slot, double* out, hipStream_t stream) {
+  if (!plan || !out || slot < 0 || slot >= plan->d.max_planes) return CLM_EINVAL;
+  Plan* p = plan;
+  CLM_HIP(hipMemcpyAsync(out, p->slots[slot].psi_s, size_t(p->npix_s) * 8,
+                         hipMemcpyDeviceToDevice, stream));
+  return CLM_OK;
+}
+
+clm_status clm_get_patch_potential(clm_plan plan, int32_t slot, int64_t first, int64_t np,
+                                   double* out, hipStream_t stream) {
+  if (!plan || !out || slot < 0 || slot >= plan->d.max_planes) return CLM_EINVAL;
+  if (!plan->mg) return CLM_EUNSUPPORTED;
+  if (first < 0 || np < 1 || first + np > plan->nbundle) return CLM_EINVAL;
+  return mg_patch_potential(plan, slot, first, np, out, stream);
+}
+
+clm_status clm_shear_from_potential(clm_plan plan, int32_t slot, const double* th,
+                                    const double* ph, int64_t npts, int32_t out_fp64,
+                                    void* grad, void* hess, hipStream_t stream) {
+  if (!plan || npts < 0 || slot < 0 || slot >= plan->d.max_planes) return CLM_EINVAL;
+  if (!plan->mg) return CLM_EUNSUPPORTED;
+  if (npts == 0) return CLM_OK;
+  if (!th || !ph || !grad || !hess) return CLM_EINVAL;
+  return eval_points(plan, slot, th, ph, npts, -1, out_fp64, grad, hess, stream);
+}
+
+clm_status clm_shear_at_pixels(clm_plan plan, int32_t slot, int32_t order, int32_t out_fp64,
+                               void* grad, void* hess, hipStream_t stream) {
+  if (!plan || !grad || !hess || slot < 0 || slot >= plan->d.max_planes ||
+      (order != CLM_ORDER_RING && order != CLM_ORDER_NESTED))
+    return CLM_EINVAL;
+  if (!plan->mg) return sht_pixel_derivs(plan, slot, order, out_fp64, grad, hess, stream);
+  return eval_points(plan, slot, nullptr, nullptr, plan->npix_f, order, out_fp64, grad, hess,
+                     stream);
+}
+
+clm_status clm_rays_init(clm_plan plan, const clm_rays* rays, hipStream_t stream) {
+  if (!plan || !rays || rays->n != plan->npix_f || !rays->theta || !rays->phi || !rays->beta ||
+      !rays->A || !rays->A_prev)
+    return CLM_EINVAL;
+  return rays_init(plan, rays, stream);
+}
+
+clm_status clm_ray_update(clm_plan plan, int32_t slot, const double* chi, int32_t nchi,
+                          int32_t m, double K, const clm_rays* rays, hipStream_t stream) {
+  if (!plan || !rays || !chi || rays->n != plan->npix_f || slot < 0 ||
+      slot >= plan->d.max_planes || m < 0 || m + 1 >= nchi)
+    return CLM_EINVAL;
+  if (!plan->mg) return CLM_EUNSUPPORTED;
+  return ray_update(plan, slot, chi, nchi, m, K, rays, stream);
+}
+
+clm_status clm_raytrace_planes(clm_plan plan, const void* kappa, int32_t kappa_is_fp64,
+                               const double* chi, int32_t nchi, int32_t first_plane,
+                               int32_t nplanes, double K, const clm_rays* rays,
+                               const clm_galaxies* gal, hipStream_t stream) {
+  if (!plan || !kappa || !chi || !rays || rays->n != plan->npix_f || first_plane < 0 ||
+      nplanes < 1 || first_plane + nplanes + 1 > nchi)
+    return CLM_EINVAL;
+  if (!plan->mg) return CLM_EUNSUPPORTED;
+  if (gal && (gal->n < 0 || (gal->n > 0 && (!gal->theta || !gal->phi || !gal->chi || !gal->A))))
+    return CLM_EINVAL;
+  for (int k = 1; k < nchi; ++k)
+    if (!(chi[k] > chi[k - 1]) || !(chi[0] > 0)) return CLM_EINVAL;
+  Plan* p = plan;
+  CLM_HIP(hipSetDevice(p->device));
+  const size_t esz = kappa_is_fp64 ? 8 : 4;
+  clm_status s;
+  if (gal && gal->n > 0 && first_plane == 0) {
+    s = galaxies_shell(p, chi, nchi, 0, K, rays, gal, stream);
+    if (s != CLM_OK) return s;
+  }
+  for (int k = 0; k < nplanes; ++k) {
+    const int m = first_plane + k;
+    const char* kp = static_cast<const char*>(kappa) + size_t(k) * p->npix_f * esz;
+    if ((s = sht_solve(p, kp, kappa_is_fp64, 0, stream)) != CLM_OK) return s;
+    if ((s = mg_solve(p, kp, kappa_is_fp64, 0, stream)) != CLM_OK) return s;
+    if ((s = ray_update(p, 0, chi, nchi, m, K, rays, stream)) != CLM_OK) return s;
+    if (gal && gal->n > 0) {
+      if ((s = galaxies_shell(p, chi, nchi, m + 1, K, rays, gal, stream)) != CLM_OK) return s;
+    }
+  }
+  return CLM_OK;
+}
+
+}  // extern "C"

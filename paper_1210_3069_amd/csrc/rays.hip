@@ -1,0 +1,293 @@
+// Multiple-plane ray propagation on the sphere (Sec. 2.2, App. B, App. D).
+//
+// Ray state is structure-of-arrays in NESTED pixel order of the fine grid,
+// so the rays of one bundle are contiguous and their patch is bundle =
+// ray >> shift (Sec. 3.1).  One thread per ray: gather g and U from the
+// bundle's patch, rotate the direction (eq. betaprop), move to the next
+// plane (eq. posprop), step the Jacobian (eq. Atraj) and parallel transport
+// both Jacobians to the new position (App. B).  Geometry in float64,
+// Jacobians stored as float32 and combined in float64.
+#include <cmath>
+
+#include "clm_internal.h"
+#include "eval_dev.h"
+#include "healpix_dev.h"
+
+namespace clm {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+__global__ void k_rays_init(int64_t Nf, int64_t n, double* th, double* ph, double* beta,
+                            float* A, float* Ap) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double z, st, phi;
+  hpx::pix2ang_ring(Nf, hpx::nest2ring(Nf, i), z, st, phi);
+  th[i] = atan2(st, z);
+  ph[i] = phi;
+  beta[i] = st * cos(phi);
+  beta[n + i] = st * sin(phi);
+  beta[2 * n + i] = z;
+  const float I4[4] = {1.f, 0.f, 0.f, 1.f};
+  for (int k = 0; k < 4; ++k) {
+    A[k * n + i] = I4[k];
+    Ap[k * n + i] = I4[k];
+  }
+}
+
+// v rotated by angle w counter-clockwise about unit axis k (Rodrigues).
+__device__ __forceinline__ void rotate(const double k[3], double w, const double v[3],
+                                       double out[3]) {
+  double s, c;
+  sincos(w, &s, &c);
+  const double kv = k[0] * v[0] + k[1] * v[1] + k[2] * v[2];
+  const double cx = k[1] * v[2] - k[2] * v[1];
+  const double cy = k[2] * v[0] - k[0] * v[2];
+  const double cz = k[0] * v[1] - k[1] * v[0];
+  out[0] = v[0] * c + cx * s + k[0] * kv * (1.0 - c);
+  out[1] = v[1] * c + cy * s + k[1] * kv * (1.0 - c);
+  out[2] = v[2] * c + cz * s + k[2] * kv * (1.0 - c);
+}
+
+// theta-hat and phi-hat at unit vector v
+__device__ __forceinline__ void basis(const double v[3], double et[3], double ep[3]) {
+  const double s = sqrt(v[0] * v[0] + v[1] * v[1]);
+  const double cp = v[0] / s, sp = v[1] / s;
+  et[0] = v[2] * cp; et[1] = v[2] * sp; et[2] = -s;
+  ep[0] = -sp; ep[1] = cp; ep[2] = 0.0;
+}
+
+struct RayArgs {
+  PatchField P;
+  int shift;
+  int64_t n;
+  double chi_m, chi_m1;  // chi_m, chi_{m+1}
+  double c, d;           // c_m, d_m of eq. Atraj
+  double* th;
+  double* ph;
+  double* beta;
+  float* A;
+  float* Ap;
+  int* status;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ray_update(RayArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t n = a.n;
+  double st, ct, sp, cp;
+  sincos(a.th[i], &st, &ct);
+  sincos(a.ph[i], &sp, &cp);
+  const double nv[3] = {st * cp, st * sp, ct};
+  double g[2], U[3];
+  if (!eval_patch<T>(a.P, i >> a.shift, nv[0], nv[1], nv[2], g, U)) {
+    atomicOr(a.status, ST_LEFT_PATCH);
+    for (int k = 0; k < 4; ++k) a.A[k * n + i] = NAN;
+    return;
+  }
+  double et[3], ep[3];
+  basis(nv, et, ep);
+  // eq. betaprop with the deflection d = -grad psi
+  double b[3] = {a.beta[i], a.beta[n + i], a.beta[2 * n + i]};
+  const double dv[3] = {-(g[0] * et[0] + g[1] * ep[0]), -(g[0] * et[1] + g[1] * ep[1]),
+                        -(g[0] * et[2] + g[1] * ep[2])};
+  const double dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  if (dn > 0) {
+    double k[3] = {nv[1] * dv[2] - nv[2] * dv[1], nv[2] * dv[0] - nv[0] * dv[2],
+                   nv[0] * dv[1] - nv[1] * dv[0]};
+    const double kn = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    k[0] /= kn; k[1] /= kn; k[2] /= kn;
+    double out[3];
+    rotate(k, dn, b, out);
+    b[0] = out[0]; b[1] = out[1]; b[2] = out[2];
+  }
+  // eq. posprop: |x + lambda beta| = chi_{m+1}, lambda > 0, cancellation-free root
+  const double x[3] = {a.chi_m * nv[0], a.chi_m * nv[1], a.chi_m * nv[2]};
+  const double bb = x[0] * b[0] + x[1] * b[1] + x[2] * b[2];
+  const double q = a.chi_m1 * a.chi_m1 - a.chi_m * a.chi_m;
+  const double lam = q / (bb + sqrt(bb * bb + q));
+  double xn[3] = {x[0] + lam * b[0], x[1] + lam * b[1], x[2] + lam * b[2]};
+  const double xl = sqrt(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2]);
+  const double nn[3] = {xn[0] / xl, xn[1] / xl, xn[2] / xl};
+  // eq. Atraj: A^(m+1) = (1 - c) A^(m-1) + c A^(m) - d U A^(m)
+  double A0[4], Ap0[4];
+  for (int k = 0; k < 4; ++k) {
+    A0[k] = double(a.A[k * n + i]);
+    Ap0[k] = double(a.Ap[k * n + i]);
+  }
+  const double Um[4] = {U[0], U[2], U[2], U[1]};
+  double An[4];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) {
+      const double UA = Um[2 * r] * A0[c] + Um[2 * r + 1] * A0[2 + c];
+      An[2 * r + c] = (1.0 - a.c) * Ap0[2 * r + c] + a.c * A0[2 * r + c] - a.d * UA;
+    }
+  // App. B: rotate the old basis along the great circle n -> n', project on
+  // the new basis, A <- M A M^T for both Jacobians
+  double et1[3], ep1[3];
+  basis(nn, et1, ep1);
+  double ax[3] = {nv[1] * nn[2] - nv[2] * nn[1], nv[2] * nn[0] - nv[0] * nn[2],
+                  nv[0] * nn[1] - nv[1] * nn[0]};
+  const double sn = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+  double rt[3], rp[3];
+  if (sn > 0) {
+    ax[0] /= sn; ax[1] /= sn; ax[2] /= sn;
+    const double w = atan2(sn, nv[0] * nn[0] + nv[1] * nn[1] + nv[2] * nn[2]);
+    rotate(ax, w, et, rt);
+    rotate(ax, w, ep, rp);
+  } else {
+    for (int k = 0; k < 3; ++k) { rt[k] = et[k]; rp[k] = ep[k]; }
+  }
+  const double M[4] = {et1[0] * rt[0] + et1[1] * rt[1] + et1[2] * rt[2],
+                       et1[0] * rp[0] + et1[1] * rp[1] + et1[2] * rp[2],
+                       ep1[0] * rt[0] + ep1[1] * rt[1] + ep1[2] * rt[2],
+                       ep1[0] * rp[0] + ep1[1] * rp[1] + ep1[2] * rp[2]};
+  auto transport = [&](const double X[4], float* dst) {
+    // M X M^T
+    const double t00 = M[0] * X[0] + M[1] * X[2], t01 = M[0] * X[1] + M[1] * X[3];
+    const double t10 = M[2] * X[0] + M[3] * X[2], t11 = M[2] * X[1] + M[3] * X[3];
+    dst[0 * n + i] = float(t00 * M[0] + t01 * M[1]);
+    dst[1 * n + i] = float(t00 * M[2] + t01 * M[3]);
+    dst[2 * n + i] = float(t10 * M[0] + t11 * M[1]);
+    dst[3 * n + i] = float(t10 * M[2] + t11 * M[3]);
+  };
+  transport(A0, a.Ap);
+  transport(An, a.A);
+  double phn = atan2(nn[1], nn[0]);
+  if (phn < 0) phn += kTwoPi;
+  a.th[i] = atan2(sqrt(nn[0] * nn[0] + nn[1] * nn[1]), nn[2]);
+  a.ph[i] = phn;
+  a.beta[i] = b[0];
+  a.beta[n + i] = b[1];
+  a.beta[2 * n + i] = b[2];
+}
+
+__device__ __forceinline__ double r_of(double x, double K) {
+  if (K > 0) return sin(sqrt(K) * x) / sqrt(K);
+  if (K < 0) return sinh(sqrt(-K) * x) / sqrt(-K);
+  return x;
+}
+
+struct GalArgs {
+  hpx::Rings rf;
+  const int* r2n_f;
+  int64_t nray;
+  const float* A;
+  const float* Ap;
+  const double* th;
+  const double* ph;
+  const double* chi;
+  float* Ag;
+  int64_t ngal;
+  double lo, hi;          // shell [lo, hi)
+  int k;                  // shell index
+  double chi_km1, chi_k;  // chi_{k-1}, chi_k
+  double K;
+};
+
+// eq. gatraj: A_g = (1 - w) A^(k-1) + w A^(k), w = D_k D_{k-1,g} / (D_g D_{k-1,k}),
+// the ray Jacobians taken by HEALPix linear interpolation on the image-plane
+// grid at the galaxy position; shell 0 gets the identity.
+__global__ void k_galaxies(GalArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.ngal) return;
+  const double cg = a.chi[i];
+  if (!(cg >= a.lo && cg < a.hi)) return;
+  const int64_t ng = a.ngal;
+  if (a.k == 0) {
+    a.Ag[i] = 1.f; a.Ag[ng + i] = 0.f; a.Ag[2 * ng + i] = 0.f; a.Ag[3 * ng + i] = 1.f;
+    return;
+  }
+  const double w = r_of(a.chi_k, a.K) * r_of(cg - a.chi_km1, a.K) /
+                   (r_of(cg, a.K) * r_of(a.chi_k - a.chi_km1, a.K));
+  int64_t pix[4];
+  double wt[4];
+  hpx::interp_weights(a.rf, a.th[i], a.ph[i], pix, wt);
+  double Ai[4] = {0, 0, 0, 0}, Api[4] = {0, 0, 0, 0};
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r = a.r2n_f[pix[q]];
+    for (int k = 0; k < 4; ++k) {
+      Ai[k] += wt[q] * double(a.A[k * a.nray + r]);
+      Api[k] += wt[q] * double(a.Ap[k * a.nray + r]);
+    }
+  }
+  for (int k = 0; k < 4; ++k) a.Ag[k * ng + i] = float((1.0 - w) * Api[k] + w * Ai[k]);
+}
+
+}  // namespace
+
+clm_status rays_init(Plan* p, const clm_rays* r, hipStream_t s) {
+  hipLaunchKernelGGL(k_rays_init, dim3((r->n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     int64_t(p->d.nside_fine), r->n, r->theta, r->phi, r->beta, r->A, r->A_prev);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+static double r_host(double x, double K) {
+  if (K > 0) return std::sin(std::sqrt(K) * x) / std::sqrt(K);
+  if (K < 0) return std::sinh(std::sqrt(-K) * x) / std::sqrt(-K);
+  return x;
+}
+
+clm_status ray_update(Plan* p, int slot, const double* chi, int nchi, int m, double K,
+                      const clm_rays* r, hipStream_t s) {
+  (void)nchi;
+  RayArgs a;
+  a.P = PatchField{p->rot, p->slots[slot].u0, p->slots[slot].du, p->n, p->L, p->delta};
+  a.shift = p->bundle_shift;
+  a.n = r->n;
+  a.chi_m = chi[m];
+  a.chi_m1 = chi[m + 1];
+  // eq. Atraj with chi_{-1} = 0: c_m = D_m/D_{m+1} * D_{m-1,m+1}/D_{m-1,m},
+  // d_m = D_{m,m+1}/D_{m+1}
+  const double cm1 = m == 0 ? 0.0 : chi[m - 1];
+  a.c = (r_host(chi[m], K) / r_host(chi[m + 1], K)) *
+        (r_host(chi[m + 1] - cm1, K) / r_host(chi[m] - cm1, K));
+  a.d = r_host(chi[m + 1] - chi[m], K) / r_host(chi[m + 1], K);
+  a.th = r->theta;
+  a.ph = r->phi;
+  a.beta = r->beta;
+  a.A = r->A;
+  a.Ap = r->A_prev;
+  a.status = p->status_dev;
+  const dim3 g((r->n + kBlock - 1) / kBlock);
+  if (p->fp64mg)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ray_update<double>), g, dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ray_update<float>), g, dim3(kBlock), 0, s, a);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+clm_status galaxies_shell(Plan* p, const double* chi, int nchi, int k, double K,
+                          const clm_rays* r, const clm_galaxies* gl, hipStream_t s) {
+  // shell edges: 0, midpoints between consecutive planes, and above the
+  // last plane everything (chi_0 .. chi_{N-1} planes, chi_N the target)
+  const int N = nchi - 1;
+  auto edge = [&](int e) { return e == 0 ? 0.0 : 0.5 * (chi[e - 1] + chi[e]); };
+  GalArgs a;
+  a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->nring_f, p->d.nside_fine};
+  a.r2n_f = p->r2n_f;
+  a.nray = r->n;
+  a.A = r->A;
+  a.Ap = r->A_prev;
+  a.th = gl->theta;
+  a.ph = gl->phi;
+  a.chi = gl->chi;
+  a.Ag = gl->A;
+  a.ngal = gl->n;
+  a.k = k;
+  a.lo = edge(k);
+  a.hi = k < N ? edge(k + 1) : INFINITY;
+  a.chi_km1 = k >= 1 ? chi[k - 1] : 0.0;
+  a.chi_k = k <= N ? chi[k] : 0.0;
+  a.K = K;
+  hipLaunchKernelGGL(k_galaxies, dim3((gl->n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+}  // namespace clm

@@ -1,0 +1,579 @@
+// Spherical-harmonic stage of the plane solve (Sec. 3.2): demean and
+// degrade, ring DFTs, Legendre analysis and synthesis, the harmonic Poisson
+// step and the pure-SHT derivative synthesis.  All float64.
+//
+// Layout: F and G are ring-major [ring][m] complex (m = 0..lmax); the
+// Legendre kernels work one order m per workgroup with the north rings
+// spread over the threads, so the three-term recurrence in l runs in
+// registers and mirror rings are folded in with the (-1)^(l+m) parity.
+#include <cmath>
+
+#include "clm_internal.h"
+#include "healpix_dev.h"
+
+namespace clm {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kHuge = 0x1p400;    // rescale threshold of the scaled recurrence
+constexpr double kSmall = 0x1p-800;  // rescale factor
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------- mean
+template <typename T>
+__global__ void k_partial_sum(const T* x, int64_t n, double* out) {
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    acc += double(x[i]);
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += sh[w];
+    out[blockIdx.x] = s;
+  }
+}
+
+__global__ void k_final_mean(double* red, int nb, double inv_n) {
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += red[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += sh[w];
+    red[1023] = s * inv_n;
+  }
+}
+
+// kappa_s(p) = mean of the NESTED children of p at nside_fine, minus the
+// mean of the fine map (mass-conserving degrade of the demeaned map).
+template <typename T>
+__global__ void k_degrade(const T* kap, int64_t Nf, int64_t npix_s, const int* r2n_s, int64_t k2,
+                          const double* red, double* out) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= npix_s) return;
+  const int64_t pn = r2n_s[r];
+  double acc = 0.0;
+  for (int64_t c = 0; c < k2; ++c) acc += double(kap[hpx::nest2ring(Nf, pn * k2 + c)]);
+  out[r] = acc / double(k2) - red[1023];
+}
+
+// ---------------------------------------------------------------- ring DFTs
+// F_m(q) = e^{-i m phi0_q} sum_j f_{q,j} e^{-2 pi i (m mod n) j / n}, m = 0..lmax.
+__global__ void k_ring_forward(const double* map, const double* rt, const int* ri, int lmax,
+                               double* F) {
+  extern __shared__ double sm[];
+  const int q = blockIdx.x;
+  const int n = ri[2 * q];
+  const int64_t first = ri[2 * q + 1];
+  double* f = sm;             // [n]
+  double* tw = sm + n;        // [n][2] cos, sin of 2 pi t / n
+  double* X = sm + 3 * n;     // [min(n, lmax+1)][2] DFT bins
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    f[j] = map[first + j];
+    double s, c;
+    sincospi(2.0 * double(j) / double(n), &s, &c);
+    tw[2 * j] = c;
+    tw[2 * j + 1] = s;
+  }
+  __syncthreads();
+  const int nb = n < lmax + 1 ? n : lmax + 1;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    int t = 0;
+    for (int j = 0; j < n; ++j) {
+      re += f[j] * tw[2 * t];
+      im -= f[j] * tw[2 * t + 1];
+      t += k;
+      if (t >= n) t -= n;
+    }
+    X[2 * k] = re;
+    X[2 * k + 1] = im;
+  }
+  __syncthreads();
+  const double phi0 = rt[4 * q + 3];
+  double* out = F + size_t(q) * (lmax + 1) * 2;
+  for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
+    const int k = m % n;
+    double s, c;
+    sincos(double(m) * phi0, &s, &c);
+    const double xr = X[2 * k], xi = X[2 * k + 1];
+    out[2 * m] = c * xr + s * xi;       // (c - i s)(xr + i xi)
+    out[2 * m + 1] = c * xi - s * xr;
+  }
+}
+
+// f_{q,j} = Re sum_{m=0}^{lmax} c_m G_m(q) e^{i m (phi0 + 2 pi j / n)}, c_0 = 1,
+// c_m = 2; nf fields [nf][ring][m] -> [nf][npix].
+__global__ void k_ring_inverse(const double* G, int nring, const double* rt, const int* ri,
+                               int lmax, int64_t npix, int nf, double* out) {
+  extern __shared__ double sm[];
+  const int q = blockIdx.x;
+  const int n = ri[2 * q];
+  const int64_t first = ri[2 * q + 1];
+  double* tw = sm;           // [n][2]
+  double* B = sm + 2 * n;    // [n][2]
+  const double phi0 = rt[4 * q + 3];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double s, c;
+    sincospi(2.0 * double(j) / double(n), &s, &c);
+    tw[2 * j] = c;
+    tw[2 * j + 1] = s;
+  }
+  for (int fld = 0; fld < nf; ++fld) {
+    const double* g = G + (size_t(fld) * nring + q) * (lmax + 1) * 2;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      double br = 0.0, bi = 0.0;
+      for (int m = k; m <= lmax; m += n) {
+        double s, c;
+        sincos(double(m) * phi0, &s, &c);
+        const double cm = m == 0 ? 1.0 : 2.0;
+        const double gr = g[2 * m], gi = g[2 * m + 1];
+        br += cm * (c * gr - s * gi);
+        bi += cm * (c * gi + s * gr);
+      }
+      B[2 * k] = br;
+      B[2 * k + 1] = bi;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      double acc = 0.0;
+      int t = 0;
+      for (int k = 0; k < n; ++k) {
+        acc += B[2 * k] * tw[2 * t] - B[2 * k + 1] * tw[2 * t + 1];
+        t += j;
+        if (t >= n) t -= n;
+      }
+      out[size_t(fld) * npix + first + j] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Legendre
+// Coefficients of lambda_l = a_l (z lambda_{l-1} - b_l lambda_{l-2}):
+// a_l = sqrt((4l^2-1)/(l^2-m^2)), b_l = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)).
+__device__ __forceinline__ void recur_coeffs(int m, int lmax, double* a, double* b) {
+  for (int l = m + 2 + threadIdx.x; l <= lmax; l += blockDim.x) {
+    const double L = l, M = m;
+    a[l - m] = sqrt((4.0 * L * L - 1.0) / (L * L - M * M));
+    b[l - m] = sqrt(((L - 1.0) * (L - 1.0) - M * M) / (4.0 * (L - 1.0) * (L - 1.0) - 1.0));
+  }
+}
+
+// Per-ring recurrence state: p1 = lambda_{l-1}, p2 = lambda_{l-2}, scale s.
+struct Recur {
+  double p1, p2;
+  int s;
+};
+
+__device__ __forceinline__ double recur_value(const Recur& r) { return r.s == 0 ? r.p1 : 0.0; }
+
+// Advance from lambda_{l-1} to lambda_l (l >= m+2) for cos theta = z.
+__device__ __forceinline__ void recur_step(Recur& r, double z, double a, double b) {
+  const double p0 = a * (z * r.p1 - b * r.p2);
+  r.p2 = r.p1;
+  r.p1 = p0;
+  if (r.s < 0 && fabs(p0) > kHuge) {
+    r.p1 *= kSmall;
+    r.p2 *= kSmall;
+    r.s += 1;
+  }
+}
+
+// a_lm = w sum_{north q} lambda_lm(theta_q) [F_m(q) + (-1)^(l+m) F_m(q')],
+// the equator counted once; one workgroup per m.
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_analysis(const double* F, const double* rt,
+                                                     const double* lam_mant,
+                                                     const int* lam_scale, int H, int nring,
+                                                     int lmax, double w, double* alm) {
+  extern __shared__ double sm[];
+  const int m = blockIdx.x;
+  const int nl = lmax - m + 1;
+  double* a = sm;                 // [nl]
+  double* b = sm + nl;            // [nl]
+  double* part = sm + 2 * nl;     // [64][kBlock/64][2]
+  recur_coeffs(m, lmax, a, b);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+  double z[RPT], fpr[RPT], fpi[RPT], fmr[RPT], fmi[RPT];
+  Recur st[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int q = threadIdx.x + k * kBlock;
+    if (q < H) {
+      z[k] = rt[4 * q];
+      const int qm = nring - 1 - q;
+      const double* fn = F + (size_t(q) * (lmax + 1) + m) * 2;
+      const double* fs = F + (size_t(qm) * (lmax + 1) + m) * 2;
+      if (qm != q) {
+        fpr[k] = fn[0] + fs[0]; fpi[k] = fn[1] + fs[1];
+        fmr[k] = fn[0] - fs[0]; fmi[k] = fn[1] - fs[1];
+      } else {
+        fpr[k] = fmr[k] = fn[0];
+        fpi[k] = fmi[k] = fn[1];
+      }
+      st[k].p1 = lam_mant[size_t(m) * H + q];
+      st[k].p2 = 0.0;
+      st[k].s = lam_scale[size_t(m) * H + q];
+    } else {
+      z[k] = 0.0; fpr[k] = fpi[k] = fmr[k] = fmi[k] = 0.0;
+      st[k].p1 = st[k].p2 = 0.0; st[k].s = -1;
+    }
+  }
+  __syncthreads();
+  for (int l0 = 0; l0 < nl; l0 += 64) {
+    const int cnt = nl - l0 < 64 ? nl - l0 : 64;
+    for (int c = 0; c < cnt; ++c) {
+      const int dl = l0 + c;  // l - m
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        if (dl == 1) {
+          // lambda_{m+1,m} = sqrt(2m+3) z lambda_mm
+          st[k].p2 = st[k].p1;
+          st[k].p1 = sqrt(2.0 * m + 3.0) * z[k] * st[k].p2;
+        } else if (dl >= 2) {
+          recur_step(st[k], z[k], a[dl], b[dl]);
+        }
+        const double v = recur_value(st[k]);
+        if (dl & 1) { sr += v * fmr[k]; si += v * fmi[k]; }
+        else        { sr += v * fpr[k]; si += v * fpi[k]; }
+      }
+      sr = wave_sum(sr);
+      si = wave_sum(si);
+      if (lane == 0) {
+        part[(c * (kBlock / 64) + wv) * 2] = sr;
+        part[(c * (kBlock / 64) + wv) * 2 + 1] = si;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+      const int c = threadIdx.x;
+      double sr = 0.0, si = 0.0;
+      for (int v = 0; v < kBlock / 64; ++v) {
+        sr += part[(c * (kBlock / 64) + v) * 2];
+        si += part[(c * (kBlock / 64) + v) * 2 + 1];
+      }
+      const size_t idx = size_t(m) * (2 * lmax + 1 - m) / 2 + (m + l0 + c);
+      alm[2 * idx] = w * sr;
+      alm[2 * idx + 1] = w * si;
+    }
+    __syncthreads();
+  }
+}
+
+// psi_lm = -2 kappa_lm / (l (l+1)), psi_00 = 0
+__global__ void k_poisson(double* alm, int lmax) {
+  const int m = blockIdx.x;
+  for (int l = m + threadIdx.x; l <= lmax; l += blockDim.x) {
+    const size_t idx = size_t(m) * (2 * lmax + 1 - m) / 2 + l;
+    const double f = l == 0 ? 0.0 : -2.0 / (double(l) * (double(l) + 1.0));
+    alm[2 * idx] *= f;
+    alm[2 * idx + 1] *= f;
+  }
+}
+
+// G_m(q) = sum_l alm_lm lambda_lm(theta_q) on north ring q and its mirror.
+// DERIV: also the theta-derivative sums needed for the pure-SHT gradient
+// and Hessian:  G_t = sum dlambda, G_tt = sum d2lambda, with
+// sin dlambda_l = l z lambda_l - sqrt((2l+1)(l^2-m^2)/(2l-1)) lambda_{l-1} and
+// d2lambda = -cot dlambda - (l(l+1) - m^2/sin^2) lambda.
+// Output fields (DERIV): 0 = G, 1 = G_t, 2 = G_tt  ([field][ring][m]).
+template <bool DERIV>
+__global__ __launch_bounds__(kBlock) void k_synthesis(const double* alm, const double* rt,
+                                                      const double* lam_mant,
+                                                      const int* lam_scale, int H, int nring,
+                                                      int lmax, double* G) {
+  extern __shared__ double sm[];
+  const int m = blockIdx.x;
+  const int nl = lmax - m + 1;
+  double* a = sm;
+  double* b = sm + nl;
+  double* c = sm + 2 * nl;  // [nl][2] alm for this m
+  recur_coeffs(m, lmax, a, b);
+  const size_t base = size_t(m) * (2 * lmax + 1 - m) / 2 + m;
+  for (int dl = threadIdx.x; dl < nl; dl += blockDim.x) {
+    c[2 * dl] = alm[2 * (base + dl)];
+    c[2 * dl + 1] = alm[2 * (base + dl) + 1];
+  }
+  __syncthreads();
+  const int q = blockIdx.y * blockDim.x + threadIdx.x;
+  if (q >= H) return;
+  const double z = rt[4 * q], st = rt[4 * q + 1];
+  Recur r;
+  r.p1 = lam_mant[size_t(m) * H + q];
+  r.p2 = 0.0;
+  r.s = lam_scale[size_t(m) * H + q];
+  double er = 0, ei = 0, orr = 0, oi = 0;     // even / odd (l+m) sums
+  double ter = 0, tei = 0, tor = 0, toi = 0;  // dlambda sums
+  double wer = 0, wei = 0, wor = 0, woi = 0;  // d2lambda sums
+  const double M = m;
+  for (int dl = 0; dl < nl; ++dl) {
+    const double lm1 = r.s == 0 ? r.p1 : 0.0;  // lambda_{l-1} (valid for dl >= 1)
+    if (dl == 1) {
+      r.p2 = r.p1;
+      r.p1 = sqrt(2.0 * m + 3.0) * z * r.p2;
+    } else if (dl >= 2) {
+      recur_step(r, z, a[dl], b[dl]);
+    }
+    const double v = recur_value(r);
+    const double cr = c[2 * dl], ci = c[2 * dl + 1];
+    if (dl & 1) { orr += v * cr; oi += v * ci; }
+    else        { er += v * cr; ei += v * ci; }
+    if (DERIV) {
+      const double L = m + dl;
+      const double prev = dl == 0 ? 0.0 : lm1;
+      const double k = sqrt((2.0 * L + 1.0) * (L * L - M * M) / fmax(2.0 * L - 1.0, 1.0));
+      const double d1 = (L * z * v - k * prev) / st;
+      const double d2 = -(z / st) * d1 - L * (L + 1.0) * v + M * M * v / (st * st);
+      if (dl & 1) { tor += d1 * cr; toi += d1 * ci; wor += d2 * cr; woi += d2 * ci; }
+      else        { ter += d1 * cr; tei += d1 * ci; wer += d2 * cr; wei += d2 * ci; }
+    }
+  }
+  const int qm = nring - 1 - q;
+  const size_t fs = size_t(nring) * (lmax + 1) * 2;  // field stride
+  double* gn = G + (size_t(q) * (lmax + 1) + m) * 2;
+  double* gs = G + (size_t(qm) * (lmax + 1) + m) * 2;
+  gn[0] = er + orr;
+  gn[1] = ei + oi;
+  if (qm != q) { gs[0] = er - orr; gs[1] = ei - oi; }
+  if (DERIV) {
+    // lambda'(pi - theta) = -(-1)^(l+m) lambda'(theta); lambda'' keeps the parity
+    gn[fs] = ter + tor;
+    gn[fs + 1] = tei + toi;
+    gn[2 * fs] = wer + wor;
+    gn[2 * fs + 1] = wei + woi;
+    if (qm != q) {
+      gs[fs] = tor - ter;
+      gs[fs + 1] = toi - tei;
+      gs[2 * fs] = wer - wor;
+      gs[2 * fs + 1] = wei - woi;
+    }
+  }
+}
+
+// From the three synthesis fields build the five pixel-space sums
+// psi_t (G_t), psi_p (i m G), psi_tt (G_tt), psi_pp (-m^2 G), psi_tp (i m G_t).
+__global__ void k_phi_fields(const double* G3, int nring, int lmax, double* G5) {
+  const size_t per = size_t(nring) * (lmax + 1);
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= per) return;
+  const double m = double(i % (lmax + 1));
+  const double gr = G3[2 * i], gi = G3[2 * i + 1];
+  const double tr = G3[2 * (per + i)], ti = G3[2 * (per + i) + 1];
+  const double wr = G3[2 * (2 * per + i)], wi = G3[2 * (2 * per + i) + 1];
+  G5[2 * i] = tr;                  G5[2 * i + 1] = ti;                  // psi_t
+  G5[2 * (per + i)] = -m * gi;     G5[2 * (per + i) + 1] = m * gr;      // psi_p
+  G5[2 * (2 * per + i)] = wr;      G5[2 * (2 * per + i) + 1] = wi;      // psi_tt
+  G5[2 * (3 * per + i)] = -m * m * gr; G5[2 * (3 * per + i) + 1] = -m * m * gi;  // psi_pp
+  G5[2 * (4 * per + i)] = -m * ti; G5[2 * (4 * per + i) + 1] = m * tr;  // psi_tp
+}
+
+// Covariant gradient and Hessian (App. A) from raw derivative maps, written
+// in RING or NESTED order.
+template <typename TO>
+__global__ void k_covariant(const double* D, int64_t npix, const double* rt, const int* ri,
+                            int nring, const int* r2n, int nested, TO* grad, TO* hess) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  int lo = 0, hi = nring - 1;  // ring of pixel p
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ri[2 * mid + 1] <= p) lo = mid; else hi = mid - 1;
+  }
+  const double z = rt[4 * lo], s = rt[4 * lo + 1];
+  const double pt = D[p], pp = D[npix + p], ptt = D[2 * npix + p], ppp = D[3 * npix + p],
+               ptp = D[4 * npix + p];
+  const int64_t o = nested ? int64_t(r2n[p]) : p;
+  grad[o] = TO(pt);
+  grad[npix + o] = TO(pp / s);
+  hess[o] = TO(ptt);
+  hess[npix + o] = TO(ppp / (s * s) + (z / s) * pt);
+  hess[2 * npix + o] = TO(ptp / s - z * pp / (s * s));
+}
+
+template <typename K>
+clm_status allow_lds(Plan* p, K kernel, size_t bytes);
+
+int rpt_for(int H) {
+  int r = (H + kBlock - 1) / kBlock;
+  int k = 1;
+  while (k < r) k <<= 1;
+  return k;
+}
+
+template <int RPT>
+void launch_analysis(Plan* p, hipStream_t s, double* alm) {
+  const int lmax = p->d.lmax;
+  const size_t shm = (2 * size_t(lmax + 1) + 64 * (kBlock / 64) * 2) * sizeof(double);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis<RPT>), dim3(lmax + 1), dim3(kBlock), shm, s,
+                     p->F, p->ring_s, p->lam_mant, p->lam_scale, p->H, p->nring_s, lmax,
+                     4.0 * kPi / double(p->npix_s), alm);
+}
+
+clm_status ring_forward(Plan* p, const double* map, hipStream_t s) {
+  const int nmax = 4 * p->d.nside_sht;
+  const int nb = nmax < p->d.lmax + 1 ? nmax : p->d.lmax + 1;
+  const size_t shm = (3 * size_t(nmax) + 2 * size_t(nb)) * sizeof(double);
+  if (allow_lds(p, k_ring_forward, shm) != CLM_OK) return CLM_EHIP;
+  hipLaunchKernelGGL(k_ring_forward, dim3(p->nring_s), dim3(kBlock), shm, s, map, p->ring_s,
+                     p->ringi_s, p->d.lmax, p->F);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+// LDS above 64 KiB needs an explicit opt-in per kernel.
+template <typename K>
+clm_status allow_lds(Plan* p, K kernel, size_t bytes) {
+  if (bytes > 65536)
+    CLM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  return CLM_OK;
+}
+
+clm_status synthesis(Plan* p, const double* alm, hipStream_t s) {
+  const int lmax = p->d.lmax;
+  const size_t shm = 4 * size_t(lmax + 1) * sizeof(double);
+  dim3 grid(lmax + 1, (p->H + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<false>), grid, dim3(kBlock), shm, s, alm,
+                     p->ring_s, p->lam_mant, p->lam_scale, p->H, p->nring_s, lmax, p->G);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+clm_status ring_inverse(Plan* p, const double* G, int nf, double* out, hipStream_t s) {
+  const int nmax = 4 * p->d.nside_sht;
+  const size_t shm = 4 * size_t(nmax) * sizeof(double);
+  if (allow_lds(p, k_ring_inverse, shm) != CLM_OK) return CLM_EHIP;
+  hipLaunchKernelGGL(k_ring_inverse, dim3(p->nring_s), dim3(kBlock), shm, s, G, p->nring_s,
+                     p->ring_s, p->ringi_s, p->d.lmax, p->npix_s, nf, out);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+}  // namespace
+
+clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
+  const clm_plan_desc& d = p->d;
+  if (4 * d.nside_sht > 4096)
+    return fail(p, CLM_EUNSUPPORTED, "ring transforms support nside_sht <= 1024");
+  const int nb = 1023;
+  // mean of the fine map
+  if (kappa_fp64)
+    hipLaunchKernelGGL(k_partial_sum<double>, dim3(nb), dim3(kBlock), 0, s,
+                       static_cast<const double*>(kappa), p->npix_f, p->red);
+  else
+    hipLaunchKernelGGL(k_partial_sum<float>, dim3(nb), dim3(kBlock), 0, s,
+                       static_cast<const float*>(kappa), p->npix_f, p->red);
+  CLM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_final_mean, dim3(1), dim3(kBlock), 0, s, p->red, nb,
+                     1.0 / double(p->npix_f));
+  CLM_LAUNCH_CHECK();
+  // degrade
+  const int64_t ratio = d.nside_fine / d.nside_sht;
+  const int64_t k2 = ratio * ratio;
+  if (kappa_fp64)
+    hipLaunchKernelGGL(k_degrade<double>, dim3((p->npix_s + kBlock - 1) / kBlock),
+                       dim3(kBlock), 0, s, static_cast<const double*>(kappa),
+                       int64_t(d.nside_fine), p->npix_s, p->r2n_s, k2, p->red, p->kap_s);
+  else
+    hipLaunchKernelGGL(k_degrade<float>, dim3((p->npix_s + kBlock - 1) / kBlock),
+                       dim3(kBlock), 0, s, static_cast<const float*>(kappa),
+                       int64_t(d.nside_fine), p->npix_s, p->r2n_s, k2, p->red, p->kap_s);
+  CLM_LAUNCH_CHECK();
+  clm_status st = ring_forward(p, p->kap_s, s);
+  if (st != CLM_OK) return st;
+  double* alm = p->slots[slot].alm;
+  const int rpt = rpt_for(p->H);
+  switch (rpt) {
+    case 1: launch_analysis<1>(p, s, alm); break;
+    case 2: launch_analysis<2>(p, s, alm); break;
+    case 4: launch_analysis<4>(p, s, alm); break;
+    case 8: launch_analysis<8>(p, s, alm); break;
+    default: return fail(p, CLM_EUNSUPPORTED, "too many rings per thread");
+  }
+  CLM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_poisson, dim3(d.lmax + 1), dim3(kBlock), 0, s, alm, d.lmax);
+  CLM_LAUNCH_CHECK();
+  if ((st = synthesis(p, alm, s)) != CLM_OK) return st;
+  return ring_inverse(p, p->G, 1, p->slots[slot].psi_s, s);
+}
+
+clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* grad, void* hess,
+                            hipStream_t s) {
+  // theta sums G, G_t, G_tt into fields 0..2 of G ([field][ring][m]); G is
+  // sized for five fields in SHT-only plans
+  const int lmax = p->d.lmax;
+  const size_t per = size_t(p->nring_s) * (lmax + 1);
+  {
+    const size_t shm = 4 * size_t(lmax + 1) * sizeof(double);
+    dim3 grid(lmax + 1, (p->H + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<true>), grid, dim3(kBlock), shm, s,
+                       p->slots[slot].alm, p->ring_s, p->lam_mant, p->lam_scale, p->H,
+                       p->nring_s, lmax, p->G);
+    CLM_LAUNCH_CHECK();
+  }
+  // the five pixel-space sums, element-wise in place (each thread reads all
+  // three inputs of its (ring, m) slot before writing the five outputs)
+  hipLaunchKernelGGL(k_phi_fields, dim3((per + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p->G,
+                     p->nring_s, lmax, p->G);
+  CLM_LAUNCH_CHECK();
+  clm_status st = ring_inverse(p, p->G, 5, p->deriv, s);
+  if (st != CLM_OK) return st;
+  const dim3 g((p->npix_s + kBlock - 1) / kBlock);
+  if (out_fp64)
+    hipLaunchKernelGGL(k_covariant<double>, g, dim3(kBlock), 0, s, p->deriv, p->npix_s,
+                       p->ring_s, p->ringi_s, p->nring_s, p->r2n_s, order == CLM_ORDER_NESTED,
+                       static_cast<double*>(grad), static_cast<double*>(hess));
+  else
+    hipLaunchKernelGGL(k_covariant<float>, g, dim3(kBlock), 0, s, p->deriv, p->npix_s,
+                       p->ring_s, p->ringi_s, p->nring_s, p->r2n_s, order == CLM_ORDER_NESTED,
+                       static_cast<float*>(grad), static_cast<float*>(hess));
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+}  // namespace clm
+
+extern "C" clm_status clm_alm2map(const double* alm, int32_t lmax, int32_t nside, double* map,
+                                  hipStream_t stream) {
+  if (!alm || !map || lmax < 0 || nside < 1 || (nside & (nside - 1)) || nside > 1024)
+    return CLM_EINVAL;
+  clm_plan_desc d;
+  clm_plan_desc_default(&d, nside);
+  d.nside_sht = nside;
+  d.lmax = lmax < 1 ? 1 : lmax;
+  d.solver = CLM_SOLVER_SHT;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CLM_EHIP;
+  clm_plan pl = nullptr;
+  clm_status st = clm_plan_create(&d, dev, &pl);
+  if (st != CLM_OK) return st;
+  clm::Plan* p = pl;
+  const size_t bytes = size_t(p->nalm) * 16;
+  if (lmax < 1) {
+    // lmax = 0: only a_00; pad a_10, a_11 with zeros
+    (void)hipMemsetAsync(p->slots[0].alm, 0, bytes, stream);
+    (void)hipMemcpyAsync(p->slots[0].alm, alm, 16, hipMemcpyDeviceToDevice, stream);
+  } else {
+    (void)hipMemcpyAsync(p->slots[0].alm, alm, bytes, hipMemcpyDeviceToDevice, stream);
+  }
+  st = clm::synthesis(p, p->slots[0].alm, stream);
+  if (st == CLM_OK) st = clm::ring_inverse(p, p->G, 1, map, stream);
+  if (hipStreamSynchronize(stream) != hipSuccess && st == CLM_OK) st = CLM_EHIP;
+  clm_plan_destroy(pl);
+  return st;
+}

@@ -1,0 +1,298 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU
+oracle on the same seeded inputs, element by element.
+
+Tolerances: float64 paths agree to 1e-10 relative (the target for the FP64
+form); the float32 multigrid form agrees to 1e-6 relative on the potential
+u0 + du; float32 ray Jacobians (stored in float32 after every plane) to
+2e-6 absolute after a few planes."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import healpix as hp
+from oracle import mg as omg
+from oracle import rays as orays
+from oracle import sht as osht
+from paper_1210_3069_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def clm():
+    from paper_1210_3069_amd import clm as c
+    c.lib()
+    assert torch.cuda.is_available()
+    return c
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def report(tag, value):
+    print("PARITY %s %.3e" % (tag, value), flush=True)
+    return value
+
+
+# ---------------------------------------------------------------- pure SHT
+@pytest.fixture(scope="module")
+def c1_case():
+    N, lmax = 64, 128
+    alm = inputs.gaussian_alm(lmax, seed=1, amplitude=1.0)
+    kap = osht.alm2map(N, lmax, alm)
+    # the solve demeans the map first (the l = 0 term is set to zero, and
+    # HEALPix quadrature of a constant is not exactly l = 0)
+    palm = osht.poisson(lmax, osht.map2alm(N, lmax, kap - kap.mean()))
+    return dict(N=N, lmax=lmax, alm=alm, kap=kap, palm=palm,
+                psi=osht.alm2map(N, lmax, palm), der=osht.derivative_maps(N, lmax, palm))
+
+
+def test_alm2map_parity(clm, c1_case):
+    c = c1_case
+    a = torch.from_numpy(c["alm"]).cuda()
+    m = clm.alm2map(a, c["lmax"], c["N"]).cpu().numpy()
+    assert rel(m, c["kap"]) < 1e-12
+
+
+def test_alm2map_ragged_lmax(clm):
+    # lmax not tied to nside, above and below 2 N, and ring lengths shorter
+    # than lmax + 1 (aliasing)
+    for N, lmax in [(4, 37), (16, 7), (8, 16)]:
+        alm = inputs.gaussian_alm(lmax, seed=N + lmax, amplitude=1.0)
+        ref = osht.alm2map(N, lmax, alm)
+        got = clm.alm2map(torch.from_numpy(alm).cuda(), lmax, N).cpu().numpy()
+        assert rel(got, ref) < 1e-12, (N, lmax)
+
+
+def test_sht_poisson_parity(clm, c1_case):
+    c = c1_case
+    plan = clm.Plan(c["N"], nside_sht=c["N"], lmax=c["lmax"], solver="sht")
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    assert rel(plan.psi_alm().cpu().numpy(), c["palm"]) < 1e-10
+    assert rel(plan.psi_map().cpu().numpy(), c["psi"]) < 1e-10
+    g, h = plan.shear_at_pixels(order="ring")
+    g, h = g.cpu().numpy(), h.cpu().numpy()
+    d = c["der"]
+    assert rel(g[0], d["g_t"]) < 1e-10 and rel(g[1], d["g_p"]) < 1e-10
+    assert rel(h[0], d["U_tt"]) < 1e-10 and rel(h[1], d["U_pp"]) < 1e-10
+    assert rel(h[2], d["U_tp"]) < 1e-10
+    gn, hn = plan.shear_at_pixels(order="nested", fp64=False)
+    r = hp.nest2ring(c["N"], np.arange(12 * c["N"] ** 2))
+    assert rel(hn.cpu().numpy()[0], d["U_tt"][r]) < 1e-6
+    plan.sync_status()
+    plan.close()
+
+
+def test_sht_float32_input_and_batch(clm):
+    N, lmax = 16, 32
+    maps = [osht.alm2map(N, lmax, inputs.gaussian_alm(lmax, seed=40 + i, amplitude=1.0))
+            for i in range(3)]
+    k = torch.from_numpy(np.stack(maps)).float().cuda()
+    plan = clm.Plan(N, nside_sht=N, lmax=lmax, solver="sht", max_planes=3)
+    plan.poisson_solve(k)
+    for i in range(3):
+        m32 = maps[i].astype(np.float32).astype(np.float64)
+        ref = osht.poisson(lmax, osht.map2alm(N, lmax, m32 - m32.mean()))
+        assert rel(plan.psi_alm(i).cpu().numpy(), ref) < 1e-10
+    plan.close()
+
+
+# ---------------------------------------------------------------- SHT + MG
+MG_BUNDLES = [0, 37, 100, 191]
+
+
+@pytest.fixture(scope="module")
+def mg_case():
+    Nf, Ns, lmax, Nb = 64, 16, 32, 4
+    g = osht.alm2map(Nf, lmax, inputs.gaussian_alm(lmax, seed=3, sigma=0.5))
+    kap = np.exp(g) - np.mean(np.exp(g))
+    out = dict(Nf=Nf, Ns=Ns, lmax=lmax, Nb=Nb, kap=kap)
+    for n in (64, 256):
+        spec = omg.PatchSpec(Nf, Ns, lmax, Nb, ncell=n, vcycles=3)
+        out[n] = (spec, omg.solve_plane(spec, kap, MG_BUNDLES))
+    return out
+
+
+@pytest.mark.parametrize("n", [64, 256])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mg_patch_potential_parity(clm, mg_case, n, prec):
+    c = mg_case
+    spec, sol = c[n]
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=n, mg_vcycles=3, mg_prec=prec)
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    assert rel(plan.psi_alm().cpu().numpy(), sol["psi_alm"]) < 1e-10
+    assert rel(plan.psi_map().cpu().numpy(), sol["psi_sht"]) < 1e-10
+    tol_u = 1e-10 if prec == "fp64" else 1e-6
+    for b in MG_BUNDLES:
+        pt = sol["patches"][b]
+        ref = (pt["u0"] + pt["du"])[1:-1, 1:-1]
+        got = plan.patch_potential(b, 1)[0].cpu().numpy()
+        assert report("mg_u n=%d %s b=%d" % (n, prec, b), rel(got, ref)) < tol_u, b
+        # the correction itself (u - u0) to float32 rounding in the fp32 form
+        dref = pt["du"][1:-1, 1:-1]
+        dgot = got - pt["u0"][1:-1, 1:-1]
+        assert report("mg_du n=%d %s b=%d" % (n, prec, b), rel(dgot, dref)) < \
+            (1e-8 if prec == "fp64" else 2e-4), b
+    plan.sync_status()
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mg_shear_parity(clm, mg_case, prec):
+    c = mg_case
+    n = 256
+    spec, sol = c[n]
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=n, mg_vcycles=3, mg_prec=prec)
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    gN, hN = plan.shear_at_pixels(order="nested")
+    gR, hR = plan.shear_at_pixels(order="ring", fp64=False)
+    rng = np.random.default_rng(9)
+    th, ph = [], []
+    for b in MG_BUNDLES:
+        # random points well inside the bundle: perturb pixel centres
+        pix = b * 256 + rng.integers(0, 256, 8)
+        z, p, s = hp.pix2ang_nest(c["Nf"], pix)
+        t = np.arctan2(s, z) + rng.uniform(-2e-3, 2e-3, 8)
+        pp = p + rng.uniform(-2e-3, 2e-3, 8)
+        keep = hp.ang2pix_nest(c["Nb"], np.cos(t), pp) == b
+        th.append(t[keep])
+        ph.append(pp[keep])
+    th, ph = np.concatenate(th), np.concatenate(ph)
+    gP, hP = plan.shear_from_potential(torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda())
+    plan.sync_status()
+    gN, hN, gR, hR = (x.cpu().numpy() for x in (gN, hN, gR, hR))
+    gP, hP = gP.cpu().numpy(), hP.cpu().numpy()
+    tol = 1e-9 if prec == "fp64" else 2e-4
+    r2n = hp.ring2nest(c["Nf"], np.arange(12 * c["Nf"] ** 2))
+    for b in MG_BUNDLES:
+        pt = sol["patches"][b]
+        for p in range(b * 256, (b + 1) * 256, 13):
+            z, phh, s = hp.pix2ang_nest(c["Nf"], np.array([p]))
+            gr, Ur = omg.eval_point(spec, pt, np.arctan2(s[0], z[0]), phh[0])
+            ur = np.array([Ur[0, 0], Ur[1, 1], Ur[0, 1]])
+            scale_g, scale_u = np.abs(gr).max(), np.abs(ur).max()
+            assert np.abs(gN[:, p] - gr).max() < tol * scale_g, (b, p)
+            assert np.abs(hN[:, p] - ur).max() < tol * scale_u, (b, p)
+            rp = hp.nest2ring(c["Nf"], np.array([p]))[0]
+            assert r2n[rp] == p
+            assert np.abs(hR[:, rp] - ur).max() < max(tol, 2e-6) * scale_u
+    for k in range(th.size):
+        b = omg.bundle_of(spec, th[k], ph[k])
+        gr, Ur = omg.eval_point(spec, sol["patches"][b], th[k], ph[k])
+        ur = np.array([Ur[0, 0], Ur[1, 1], Ur[0, 1]])
+        assert np.abs(gP[:, k] - gr).max() < tol * np.abs(gr).max()
+        assert np.abs(hP[:, k] - ur).max() < tol * np.abs(ur).max()
+    plan.close()
+
+
+def test_points_outside_patch_are_flagged(clm, mg_case):
+    c = mg_case
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=64, mg_vcycles=1, mg_prec="fp64")
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    # empty request is fine
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    plan.shear_from_potential(e, e)
+    plan.sync_status()
+    # rays pushed far from their bundle leave the patch: NaN and a latched status
+    rays = plan.new_rays()
+    rays["phi"] += 1.0
+    chi = np.array([100.0, 200.0])
+    plan.ray_update(chi, 0, rays)
+    with pytest.raises(clm.ClmError) as ei:
+        plan.sync_status()
+    assert ei.value.status == clm.CLM_ERAY_LEFT_PATCH
+    assert torch.isnan(rays["A"]).any()
+    plan.sync_status()   # cleared
+    plan.close()
+
+
+# ---------------------------------------------------------------- rays
+def test_raytrace_parity(clm):
+    Nf, Ns, lmax, Nb, n = 64, 16, 32, 4, 64
+    nplanes = 3
+    chi = np.array([(m + 0.5) * 100.0 for m in range(nplanes)] + [nplanes * 100.0 + 50.0])
+    kaps = []
+    for m in range(nplanes):
+        sig = 0.2 + 0.2 * m
+        g = osht.alm2map(Nf, lmax, inputs.gaussian_alm(lmax, seed=100 + m, sigma=sig))
+        s = inputs.deflection_scale(lmax, sig, alpha_rms=20 * inputs.ARCMIN)
+        kaps.append(s * (np.exp(g) - np.mean(np.exp(g))))
+    kaps = np.stack(kaps)
+    bundles = [5, 77]
+    spec = omg.PatchSpec(Nf, Ns, lmax, Nb, ncell=n, vcycles=4)
+    sols = [omg.solve_plane(spec, kaps[m], bundles) for m in range(nplanes)]
+
+    # galaxies inside the two bundles, spread over the shells
+    rng = np.random.default_rng(200)
+    gth, gph, gchi = [], [], []
+    for b in bundles:
+        pix = b * 256 + rng.integers(0, 256, 6)
+        z, p, s = hp.pix2ang_nest(Nf, pix)
+        gth.append(np.arctan2(s, z) + rng.uniform(-3e-3, 3e-3, 6))
+        gph.append(p + rng.uniform(-3e-3, 3e-3, 6))
+        gchi.append(rng.uniform(10.0, chi[-1] + 40.0, 6))
+    gth, gph, gchi = map(np.concatenate, (gth, gph, gchi))
+    # keep galaxies whose four interpolation pixels lie in the two bundles
+    gpix, gw = hp.interp_weights(Nf, gth, gph)
+    r2n = hp.ring2nest(Nf, np.arange(12 * Nf * Nf))
+    inside = np.all(np.isin(r2n[gpix] >> 8, bundles), axis=0)
+    gth, gph, gchi, gpix, gw = gth[inside], gph[inside], gchi[inside], gpix[:, inside], gw[:, inside]
+    assert gth.size >= 6
+    # rays the oracle must follow: sample rays of the bundles plus each
+    # galaxy's four interpolation pixels
+    need = set(int(r2n[q]) for q in gpix.ravel())
+    need |= set(int(b * 256 + k) for b in bundles for k in range(0, 256, 29))
+    need = sorted(q for q in need if (q >> 8) in bundles)
+    ref = {}
+    for q in need:
+        z, p, s = hp.pix2ang_nest(Nf, np.array([q]))
+        r = orays.Ray(np.arctan2(s[0], z[0]), p[0])
+        hist = []
+        for m in range(nplanes):
+            th, ph = hp.vec2ang(r.n)
+            gr, Ur = omg.eval_point(spec, sols[m]["patches"][q >> 8], th, ph)
+            orays.ray_step(r, chi, m, gr, Ur)
+            hist.append((r.A.copy(), r.A_prev.copy()))
+        ref[q] = (r, hist)
+
+    plan = clm.Plan(Nf, nside_sht=Ns, lmax=lmax, nside_bundle=Nb, patch_cells=n,
+                    mg_vcycles=4, mg_prec="fp64")
+    rays = plan.new_rays()
+    gal = dict(theta=torch.from_numpy(gth).cuda(), phi=torch.from_numpy(gph).cuda(),
+               chi=torch.from_numpy(gchi).cuda(),
+               A=torch.full((4, gth.size), np.nan, dtype=torch.float32, device="cuda"))
+    plan.raytrace_planes(torch.from_numpy(kaps).cuda(), chi, 0, rays, galaxies=gal)
+    plan.sync_status()
+    th, ph = rays["theta"].cpu().numpy(), rays["phi"].cpu().numpy()
+    beta, A, Ap = (rays[k].cpu().numpy() for k in ("beta", "A", "A_prev"))
+    moved = 0.0
+    for q in need:
+        r, hist = ref[q]
+        t, p = hp.vec2ang(r.n)
+        assert abs(th[q] - t) < 1e-12
+        assert abs(np.angle(np.exp(1j * (ph[q] - p)))) < 1e-12
+        assert np.abs(beta[:, q] - r.beta).max() < 1e-12
+        assert np.abs(A[:, q] - r.A.ravel()).max() < 2e-6
+        assert np.abs(Ap[:, q] - r.A_prev.ravel()).max() < 2e-6
+        z0, p0, s0 = hp.pix2ang_nest(Nf, np.array([q]))
+        moved = max(moved, np.arccos(np.clip(hp.vec(z0, p0, s0)[0] @ r.n, -1, 1)))
+    assert moved > 1e-4        # the rays were really deflected
+    # galaxies: eq. gatraj with Jacobians interpolated on the image grid
+    Ag = gal["A"].cpu().numpy()
+    edges = orays.shell_edges(chi)
+    for i in range(gth.size):
+        k = int(np.searchsorted(edges, gchi[i], side="right") - 1)
+        if k == 0:
+            expect = np.eye(2).ravel()
+        else:
+            Ai = sum(gw[j, i] * ref[int(r2n[gpix[j, i]])][1][k - 1][0] for j in range(4))
+            Api = sum(gw[j, i] * ref[int(r2n[gpix[j, i]])][1][k - 1][1] for j in range(4))
+            w = orays.galaxy_weight(chi, k, gchi[i])
+            expect = ((1 - w) * Api + w * Ai).ravel()
+        assert np.abs(Ag[:, i] - expect).max() < 3e-6, (i, k)
+    plan.close()
