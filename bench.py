@@ -1,0 +1,242 @@
+"""Benchmark: SHT+MG lens-plane steps per second at HEALPix Nside 2048 on one
+MI355X.
+
+One step is one pass of the whole hot path over one lens plane:
+  kappa (device, float32, Nside 2048) -> demean + degrade to Nside 256 ->
+  SHT analysis (lmax 512) -> psi_lm -> synthesis -> 12,288 patches of 256^2
+  cells (bundles at Nside 32), 4 FAS V-cycles of red-black Gauss-Seidel ->
+  gradient and shear at all 50,331,648 pixel centres -> update of 50,331,648
+  rays (direction, position, Jacobian, transport) -> galaxies of the shell.
+Input: lognormal convergence (sigma_g 0.5, C_l ~ l^-2 up to lmax 512, seed 3)
+scaled to a 1 arcmin rms deflection; planes equally spaced in comoving
+distance to z = 1.5 (20 planes of 152.735 h^-1 Mpc); 1e6 galaxies uniform on
+the sphere with z ~ U[0.3, 1.5].  Inputs are resident in HBM before timing.
+
+Prints one JSON line (see the keys below)."""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NF, NS, LMAX, NB, NCELL, VCYC = 2048, 256, 512, 32, 256, 4
+DCHI = 3054.70 / 20.0
+NGAL = 1_000_000
+HBM_PEAK_GBS = 8000.0
+
+
+def bytes_model(stage, plan_n, nbundle, npix, ncyc):
+    """Algorithmic HBM bytes of one launch of a stage (float32 multigrid):
+    every array the step must read or write once, no halo re-reads."""
+    cells = nbundle * plan_n * plan_n
+    c1 = cells / 4
+    return {
+        # f' and du read, du written, ubar/rbar of the next level written; the
+        # first cycle starts from du = 0 and skips its read
+        "mg_pre_l0": cells * (4 + 4 + 4 + 2) - cells * 4 / ncyc,
+        # du, f' and the coarse u_H, ubar read, du written
+        "mg_post_l0": cells * (4 + 4 + 2 + 4),
+        "mg_pre_l1+": c1 * (4 + 4 + 4 + 4 + 2),
+        "mg_post_l1+": c1 * (4 + 4 + 2 + 4),
+        # ubar, rbar of the 64^2 level read, u written
+        "mg_lds": cells / 16 * 12,
+        # u0 (float64, with ghosts) and f' written, fine kappa read once
+        "patch_setup": nbundle * (plan_n + 2) ** 2 * 8 + cells * 4 + npix * 4,
+        # five float32 outputs per pixel, u0 + du over the bundle cores read once
+        "eval_pixels": npix * (20 + 12),
+        # theta, phi, beta, A, A_prev read and written, patch cores read once
+        "ray_update": npix * (2 * (8 + 8 + 24 + 16 + 16) + 12),
+    }.get(stage)
+
+
+def make_inputs(clm, torch, inputs, cosmo):
+    alm = torch.from_numpy(inputs.gaussian_alm(LMAX, seed=3, sigma=0.5)).cuda()
+    g = clm.alm2map(alm, LMAX, NF)
+    e = torch.exp(g)
+    s = inputs.deflection_scale(LMAX, 0.5)
+    kappa = (s * (e - e.mean())).float().contiguous()
+    del g, e
+    th, ph, z = inputs.galaxy_redshifts(NGAL, seed=200)
+    gal = dict(theta=torch.from_numpy(th).cuda(), phi=torch.from_numpy(ph).cuda(),
+               chi=torch.from_numpy(cosmo.chi_of_z(z)).cuda(),
+               A=torch.zeros(4, NGAL, dtype=torch.float32, device="cuda"))
+    return kappa, gal
+
+
+def run_form(clm, torch, kappa, gal, prec, steps, warmup):
+    plan = clm.Plan(NF, nside_sht=NS, lmax=LMAX, nside_bundle=NB, patch_cells=NCELL,
+                    mg_vcycles=VCYC, mg_prec=prec)
+    rays = plan.new_rays()
+    nplanes = warmup + steps
+    chi = (np.arange(nplanes + 1) + 0.5) * DCHI
+    gout = (torch.empty(2, plan.npix_fine, dtype=torch.float32, device="cuda"),
+            torch.empty(3, plan.npix_fine, dtype=torch.float32, device="cuda"))
+
+    def step(m):
+        plan.raytrace_planes(kappa, chi, m, rays, galaxies=gal)
+        plan.shear_at_pixels(order="nested", fp64=False, out=gout)
+
+    for m in range(warmup):
+        step(m)
+    torch.cuda.synchronize()
+    plan.sync_status()
+    plan.set_timing(True)
+    plan.get_timing()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter()
+    t0.record(stream)
+    for m in range(warmup, warmup + steps):
+        step(m)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall
+    ms = t0.elapsed_time(t1) / steps
+    stages = plan.get_timing()
+    plan.set_timing(False)
+    plan.sync_status()
+    return plan, rays, ms, wall, stages
+
+
+def cpu_baseline(torch, kappa, plan64, sample_bundles):
+    """The FP64 oracle, as it stands, on a bounded sample of the same plane:
+    the full SHT stage, then patch setup + V-cycles + shear at the bundle's
+    pixels + one ray step for `sample_bundles` bundles, scaled to one plane."""
+    from oracle import healpix as hp
+    from oracle import mg as omg
+    from oracle import rays as orays
+    kap = kappa.double().cpu().numpy()
+    spec = omg.PatchSpec(NF, NS, LMAX, NB, ncell=NCELL, vcycles=VCYC)
+    t = time.perf_counter()
+    mean, _, palm, psi = omg.sht_stage(spec, kap)
+    t_sht = time.perf_counter() - t
+    per = (NF // NB) ** 2
+    chi = np.array([0.5 * DCHI, 1.5 * DCHI])
+    t = time.perf_counter()
+    worst = 0.0
+    for b in sample_bundles:
+        R, u0, fp = omg.patch_setup(spec, b, kap, mean, psi)
+        du = omg.mg_solve(spec, fp)
+        patch = dict(R=R, u0=u0, du=du)
+        pix = np.arange(b * per, (b + 1) * per)
+        z, ph, s = hp.pix2ang_nest(NF, pix)
+        th = np.arctan2(s, z)
+        for k in range(per):
+            g, U = omg.eval_point(spec, patch, th[k], ph[k])
+            r = orays.Ray(th[k], ph[k])
+            orays.ray_step(r, chi, 0, g, U)
+        ug = plan64.patch_potential(int(b), 1)[0].cpu().numpy()
+        ur = (u0 + du)[1:-1, 1:-1]
+        worst = max(worst, float(np.abs(ug - ur).max() / np.abs(ur).max()))
+    t_patch = (time.perf_counter() - t) / len(sample_bundles)
+    t_plane = t_sht + t_patch * 12 * NB * NB
+    return dict(value=1.0 / t_plane, unit="plane solves/s", cores=1, kind="oracle",
+                sample="full SHT stage (%.1f s) + %d of %d patches (setup, 4 V-cycles, "
+                       "shear and one ray step at their %d pixels; %.1f s each), scaled "
+                       "to one plane" % (t_sht, len(sample_bundles), 12 * NB * NB, per,
+                                         t_patch),
+                gpu_fp64_vs_oracle_rel_err_u=worst)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.warmup + args.steps > 19:
+        print("warmup + steps must stay below the 20 planes to z = 1.5", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1210_3069_amd import clm, cosmo, inputs
+    clm.lib()
+    torch.cuda.set_device(0)
+    print("bench: generating inputs", file=sys.stderr, flush=True)
+    kappa, gal = make_inputs(clm, torch, inputs, cosmo)
+    torch.cuda.synchronize()
+    print("bench: fp32 form", file=sys.stderr, flush=True)
+    plan, rays, ms, wall, stages = run_form(clm, torch, kappa, gal, "fp32", args.steps,
+                                            args.warmup)
+    npix = plan.npix_fine
+    nbundle = 12 * NB * NB
+    sample = list(range(0, nbundle, 64))
+    u32 = torch.stack([plan.patch_potential(b, 1)[0] for b in sample]).cpu()
+    plan.close()
+    del plan, rays
+    torch.cuda.empty_cache()
+
+    per_stage = {}
+    for k, (tot, cnt) in stages.items():
+        per_stage[k] = dict(ms_per_step=tot / args.steps, launches_per_step=cnt / args.steps,
+                            ms_per_launch=tot / max(cnt, 1))
+        b = bytes_model(k, NCELL, nbundle, npix, VCYC)
+        if b is not None:
+            per_stage[k]["alg_GBps"] = b / (tot / cnt * 1e-3) / 1e9
+    dom = max((k for k in per_stage if bytes_model(k, NCELL, nbundle, npix, VCYC)),
+              key=lambda k: per_stage[k]["ms_per_step"])
+    b_dom = bytes_model(dom, NCELL, nbundle, npix, VCYC)
+    achieved = per_stage[dom]["alg_GBps"]
+    roofline = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=None,
+                    alg_bytes_per_launch=b_dom,
+                    ms_per_launch=per_stage[dom]["ms_per_launch"])
+
+    out = {
+        "metric": "SHT+MG plane solves/s @Nside 2048",
+        "value": 1000.0 / ms,
+        "unit": "plane solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "wall_s_timed": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "dtype_detail": "multigrid correction float32; SHT, u0, f', geometry and rays float64; "
+                        "ray Jacobians stored float32",
+        "data": "synthetic",
+        "config": {"workload": "one lens plane per step at Nside 2048: SHT Nside 256 lmax 512 "
+                               "+ MG 12288 patches 256^2, 4 V-cycles (2,2) + shear at "
+                               "50.3M pixels + 50.3M-ray update + 1e6 galaxies",
+                   "nside_fine": NF, "nside_sht": NS, "lmax": LMAX, "nside_bundle": NB,
+                   "patch_cells": NCELL, "vcycles": VCYC, "rays": npix, "galaxies": NGAL},
+        "ray_plane_updates_per_s": {
+            "end_to_end": npix * 1000.0 / ms,
+            "kernel_only": npix / (per_stage["ray_update"]["ms_per_launch"] * 1e-3)},
+        "stages": per_stage,
+        "roofline": roofline,
+    }
+    if not args.no_fp64:
+        print("bench: fp64 form", file=sys.stderr, flush=True)
+        plan64, rays64, ms64, _, _ = run_form(clm, torch, kappa, gal, "fp64", args.steps,
+                                              args.warmup)
+        u64 = torch.stack([plan64.patch_potential(b, 1)[0] for b in sample]).cpu()
+        d = (u32 - u64).double()
+        out["fp64_form"] = dict(ms_per_step=ms64, value=1000.0 / ms64,
+                                fp32_vs_fp64_rel_l2_u=float(d.norm() / u64.norm()),
+                                sampled_patches=len(sample))
+        if not args.no_cpu_baseline:
+            print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline(torch, kappa, plan64,
+                                               sample[: max(1, args.cpu_sample)])
+        plan64.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

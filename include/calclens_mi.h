@@ -109,6 +109,20 @@ size_t clm_plan_workspace_bytes(clm_plan plan);
 clm_status clm_plan_get_desc(clm_plan plan, clm_plan_desc* out_host);
 
 /*
+ * Per-stage kernel timing.  When enabled, every kernel launch of the plan is
+ * bracketed by two HIP events recorded on the launch stream (the events
+ * come from a pool owned by the plan; recording allocates only while the
+ * pool grows).  clm_plan_get_timing synchronises, adds up the elapsed time
+ * and launch count of each stage since the last reset, writes the stage
+ * names as a comma-separated list into names_host (truncated to len) and
+ * the totals into ms_host / count_host (max_stages entries), sets
+ * *nstages_host, and resets the accumulators.
+ */
+clm_status clm_plan_set_timing(clm_plan plan, int32_t enable);
+clm_status clm_plan_get_timing(clm_plan plan, char* names_host, size_t len, double* ms_host,
+                               int64_t* count_host, int32_t max_stages, int32_t* nstages_host);
+
+/*
  * Synthesis of a real field from a_lm (Sec. 3.2, the SHT synthesis):
  *   f(r, j) = sum_l a_l0 lambda_l0(theta_r)
  *             + 2 Re sum_{m>=1} [sum_l a_lm lambda_lm(theta_r)] e^{i m phi_rj}

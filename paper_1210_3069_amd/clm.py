@@ -64,6 +64,9 @@ _SIGS = {
     "clm_raytrace_planes": (_P, _P, _I32, ctypes.POINTER(_D), _I32, _I32, _I32, _D,
                             ctypes.POINTER(Rays), ctypes.POINTER(Galaxies), _P),
     "clm_ray_update": (_P, _I32, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays), _P),
+    "clm_plan_set_timing": (_P, _I32),
+    "clm_plan_get_timing": (_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_D),
+                            ctypes.POINTER(_I64), _I32, ctypes.POINTER(_I32)),
 }
 
 
@@ -166,6 +169,21 @@ class Plan:
     @property
     def workspace_bytes(self):
         return lib().clm_plan_workspace_bytes(self.h)
+
+    def set_timing(self, enable=True):
+        """Bracket every kernel launch of this plan with HIP events."""
+        self._check(lib().clm_plan_set_timing(self.h, int(enable)), "set_timing")
+
+    def get_timing(self):
+        """{stage: (total ms, launches)} since the last call (synchronises)."""
+        names = ctypes.create_string_buffer(4096)
+        ms = (ctypes.c_double * 64)()
+        cnt = (ctypes.c_int64 * 64)()
+        ns = ctypes.c_int32()
+        self._check(lib().clm_plan_get_timing(self.h, names, 4096, ms, cnt, 64,
+                                              ctypes.byref(ns)), "get_timing")
+        keys = names.value.decode().split(",") if names.value else []
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(keys[: ns.value])}
 
     def sync_status(self):
         """Synchronise and raise if a kernel latched an error."""

@@ -74,8 +74,39 @@ struct Plan {
 
   std::vector<Slot> slots;
 
+  // per-stage timing (off unless enabled)
+  bool timing = false;
+  std::vector<std::string> stage_names;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  int stage_id(const char* name);
+  hipEvent_t take_event();
+
   ~Plan();
 };
+
+// Brackets one kernel launch with timing events when timing is enabled.
+struct TimedLaunch {
+  Plan* p;
+  hipStream_t s;
+  int stage = -1;
+  hipEvent_t a = nullptr;
+  TimedLaunch(Plan* p_, hipStream_t s_, const char* name) : p(p_), s(s_) {
+    if (!p->timing) return;
+    stage = p->stage_id(name);
+    a = p->take_event();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~TimedLaunch() {
+    if (!p->timing || !a) return;
+    hipEvent_t b = p->take_event();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    p->recs.push_back({stage, a, b});
+  }
+};
+#define CLM_TIMED(p, s, name) ::clm::TimedLaunch clm_timed_##__LINE__(p, s, name)
 
 #define CLM_HIP(call)                                                        \
   do {                                                                       \

@@ -89,6 +89,7 @@ clm_status eval_points(Plan* p, int slot, const double* th, const double* ph, in
   a.hess = hess;
   a.status = p->status_dev;
   const dim3 g((npts + kBlock - 1) / kBlock);
+  CLM_TIMED(p, s, th ? "eval_points" : "eval_pixels");
   if (p->fp64mg) {
     if (out_fp64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eval<double, double>), g, dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eval<double, float>), g, dim3(kBlock), 0, s, a);

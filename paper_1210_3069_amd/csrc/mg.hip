@@ -556,8 +556,11 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     a.fprime = p->fprime;
     const size_t shm = size_t(a.tile + 2) * (a.tile + 2) * sizeof(double);
     if (allow_lds(p, k_patch_setup<T>, shm) != CLM_OK) return CLM_EHIP;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_patch_setup<T>), dim3(np * a.ntile * a.ntile),
-                       dim3(kBlock), shm, s, a);
+    {
+      CLM_TIMED(p, s, "patch_setup");
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_patch_setup<T>), dim3(np * a.ntile * a.ntile),
+                         dim3(kBlock), shm, s, a);
+    }
     CLM_LAUNCH_CHECK();
   }
   T* du = static_cast<T*>(sl.du);
@@ -608,8 +611,11 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       la.f_in = fp;
       la.u_out = du;
       la.fas_source = 0;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(np), dim3(kBlock), lds_bytes, s,
-                         la);
+      {
+        CLM_TIMED(p, s, "mg_lds");
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(np), dim3(kBlock), lds_bytes, s,
+                           la);
+      }
       CLM_LAUNCH_CHECK();
       continue;
     }
@@ -632,8 +638,11 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       a.rbar_out = static_cast<T*>(p->rbar[l + 1]);
       const size_t b = pre_bytes(a);
       if (allow_lds(p, k_mg_pre<T>, b) != CLM_OK) return CLM_EHIP;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_pre<T>), dim3(np * a.ntile * a.ntile),
-                         dim3(kBlock), b, s, a);
+      {
+        CLM_TIMED(p, s, l == 0 ? "mg_pre_l0" : "mg_pre_l1+");
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_pre<T>), dim3(np * a.ntile * a.ntile),
+                           dim3(kBlock), b, s, a);
+      }
       CLM_LAUNCH_CHECK();
     }
     // the LDS-resident levels
@@ -641,7 +650,10 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     la.f_in = static_cast<T*>(p->rbar[K]);
     la.u_out = static_cast<T*>(p->ulev[K]);
     la.fas_source = 1;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(np), dim3(kBlock), lds_bytes, s, la);
+    {
+      CLM_TIMED(p, s, "mg_lds");
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(np), dim3(kBlock), lds_bytes, s, la);
+    }
     CLM_LAUNCH_CHECK();
     // prolongation, correction and post-smoothing back up
     for (int l = K - 1; l >= 0; --l) {
@@ -659,8 +671,11 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       }
       const size_t b = post_bytes(a);
       if (allow_lds(p, k_mg_post<T>, b) != CLM_OK) return CLM_EHIP;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_post<T>), dim3(np * a.ntile * a.ntile),
-                         dim3(kBlock), b, s, a);
+      {
+        CLM_TIMED(p, s, l == 0 ? "mg_post_l0" : "mg_post_l1+");
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_post<T>), dim3(np * a.ntile * a.ntile),
+                           dim3(kBlock), b, s, a);
+      }
       CLM_LAUNCH_CHECK();
     }
   }

@@ -8,7 +8,27 @@
 
 namespace clm {
 
+int Plan::stage_id(const char* name) {
+  for (size_t i = 0; i < stage_names.size(); ++i)
+    if (stage_names[i] == name) return int(i);
+  stage_names.push_back(name);
+  return int(stage_names.size()) - 1;
+}
+
+hipEvent_t Plan::take_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
 Plan::~Plan() {
+  for (auto& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (auto e : pool) (void)hipEventDestroy(e);
   auto f = [](void* q) { if (q) (void)hipFree(q); };
   f(ring_s); f(ringi_s); f(ring_f); f(ringi_f); f(lam_mant); f(lam_scale);
   f(r2n_s); f(r2n_f); f(rot); f(coef); f(cinv); f(kap_s); f(F); f(G); f(red);
@@ -417,6 +437,46 @@ clm_status clm_plan_get_desc(clm_plan plan, clm_plan_desc* out) {
   if (!plan || !out) return CLM_EINVAL;
   *out = plan->d;
   return CLM_OK;
+}
+
+clm_status clm_plan_set_timing(clm_plan plan, int32_t enable) {
+  if (!plan) return CLM_EINVAL;
+  plan->timing = enable != 0;
+  return CLM_OK;
+}
+
+clm_status clm_plan_get_timing(clm_plan plan, char* names, size_t len, double* ms,
+                               int64_t* count, int32_t max_stages, int32_t* nstages) {
+  if (!plan || !names || len == 0 || !ms || !count || !nstages || max_stages < 1)
+    return CLM_EINVAL;
+  Plan* p = plan;
+  const int ns = int(p->stage_names.size());
+  std::vector<double> acc(ns, 0.0);
+  std::vector<int64_t> cnt(ns, 0);
+  clm_status st = CLM_OK;
+  for (auto& r : p->recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+      st = CLM_EHIP;
+    acc[r.stage] += t;
+    cnt[r.stage] += 1;
+    p->pool.push_back(r.a);
+    p->pool.push_back(r.b);
+  }
+  p->recs.clear();
+  std::string all;
+  for (int i = 0; i < ns; ++i) {
+    if (i) all += ",";
+    all += p->stage_names[i];
+  }
+  std::snprintf(names, len, "%s", all.c_str());
+  const int k = ns < max_stages ? ns : max_stages;
+  for (int i = 0; i < k; ++i) {
+    ms[i] = acc[i];
+    count[i] = cnt[i];
+  }
+  *nstages = k;
+  return st;
 }
 
 clm_status clm_plan_sync_status(clm_plan plan, hipStream_t stream) {

@@ -254,6 +254,7 @@ clm_status ray_update(Plan* p, int slot, const double* chi, int nchi, int m, dou
   a.Ap = r->A_prev;
   a.status = p->status_dev;
   const dim3 g((r->n + kBlock - 1) / kBlock);
+  CLM_TIMED(p, s, "ray_update");
   if (p->fp64mg)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ray_update<double>), g, dim3(kBlock), 0, s, a);
   else
@@ -285,6 +286,7 @@ clm_status galaxies_shell(Plan* p, const double* chi, int nchi, int k, double K,
   a.chi_km1 = k >= 1 ? chi[k - 1] : 0.0;
   a.chi_k = k <= N ? chi[k] : 0.0;
   a.K = K;
+  CLM_TIMED(p, s, "galaxies");
   hipLaunchKernelGGL(k_galaxies, dim3((gl->n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
   CLM_LAUNCH_CHECK();
   return CLM_OK;

@@ -6,6 +6,7 @@
 // Legendre kernels work one order m per workgroup with the north rings
 // spread over the threads, so the three-term recurrence in l runs in
 // registers and mirror rings are folded in with the (-1)^(l+m) parity.
+#include <algorithm>
 #include <cmath>
 
 #include "clm_internal.h"
@@ -70,71 +71,95 @@ __global__ void k_degrade(const T* kap, int64_t Nf, int64_t npix_s, const int* r
 }
 
 // ---------------------------------------------------------------- ring DFTs
+// Every HEALPix ring has n = 4k samples, so the twiddles e^{2 pi i t / n}
+// come from a quarter-wave sine table s[r] = sin(2 pi r / n), r = 0..n/4,
+// held in LDS: (n/4 + 1) doubles per ring.
+__device__ __forceinline__ void twiddle(const double* sq, int Q, int t, double& c, double& s) {
+  const int q = t / Q, r = t - q * Q;
+  const double sr = sq[r], cr = sq[Q - r];
+  switch (q) {
+    case 0: c = cr; s = sr; break;
+    case 1: c = -sr; s = cr; break;
+    case 2: c = -cr; s = -sr; break;
+    default: c = sr; s = -cr; break;
+  }
+}
+
+__device__ __forceinline__ void quarter_table(double* sq, int n) {
+  const int Q = n / 4;
+  for (int r = threadIdx.x; r <= Q; r += blockDim.x) sq[r] = sinpi(2.0 * double(r) / double(n));
+}
+
 // F_m(q) = e^{-i m phi0_q} sum_j f_{q,j} e^{-2 pi i (m mod n) j / n}, m = 0..lmax.
+// Direct DFT of the min(n, lmax+1) needed bins; rings shorter than lmax + 1
+// fold the higher orders onto their bins (HEALPix aliasing).
 __global__ void k_ring_forward(const double* map, const double* rt, const int* ri, int lmax,
                                double* F) {
   extern __shared__ double sm[];
   const int q = blockIdx.x;
-  const int n = ri[2 * q];
+  const int n = ri[2 * q], Q = n / 4;
   const int64_t first = ri[2 * q + 1];
-  double* f = sm;             // [n]
-  double* tw = sm + n;        // [n][2] cos, sin of 2 pi t / n
-  double* X = sm + 3 * n;     // [min(n, lmax+1)][2] DFT bins
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    f[j] = map[first + j];
-    double s, c;
-    sincospi(2.0 * double(j) / double(n), &s, &c);
-    tw[2 * j] = c;
-    tw[2 * j + 1] = s;
-  }
+  double* f = sm;              // [n]
+  double* sq = sm + n;         // [n/4 + 1]
+  double* X = sq + Q + 1;      // [n][2] when n <= lmax
+  for (int j = threadIdx.x; j < n; j += blockDim.x) f[j] = map[first + j];
+  quarter_table(sq, n);
   __syncthreads();
-  const int nb = n < lmax + 1 ? n : lmax + 1;
+  const double phi0 = rt[4 * q + 3];
+  double* out = F + size_t(q) * (lmax + 1) * 2;
+  const bool alias = n <= lmax;
+  const int nb = alias ? n : lmax + 1;
   for (int k = threadIdx.x; k < nb; k += blockDim.x) {
     double re = 0.0, im = 0.0;
     int t = 0;
     for (int j = 0; j < n; ++j) {
-      re += f[j] * tw[2 * t];
-      im -= f[j] * tw[2 * t + 1];
+      double c, s;
+      twiddle(sq, Q, t, c, s);
+      re += f[j] * c;
+      im -= f[j] * s;
       t += k;
       if (t >= n) t -= n;
     }
-    X[2 * k] = re;
-    X[2 * k + 1] = im;
+    if (alias) {
+      X[2 * k] = re;
+      X[2 * k + 1] = im;
+    } else {
+      double s, c;
+      sincos(double(k) * phi0, &s, &c);
+      out[2 * k] = c * re + s * im;       // (c - i s)(re + i im)
+      out[2 * k + 1] = c * im - s * re;
+    }
   }
+  if (!alias) return;
   __syncthreads();
-  const double phi0 = rt[4 * q + 3];
-  double* out = F + size_t(q) * (lmax + 1) * 2;
   for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
     const int k = m % n;
     double s, c;
     sincos(double(m) * phi0, &s, &c);
     const double xr = X[2 * k], xi = X[2 * k + 1];
-    out[2 * m] = c * xr + s * xi;       // (c - i s)(xr + i xi)
+    out[2 * m] = c * xr + s * xi;
     out[2 * m + 1] = c * xi - s * xr;
   }
 }
 
 // f_{q,j} = Re sum_{m=0}^{lmax} c_m G_m(q) e^{i m (phi0 + 2 pi j / n)}, c_0 = 1,
-// c_m = 2; nf fields [nf][ring][m] -> [nf][npix].
+// c_m = 2; nf fields [nf][ring][m] -> [nf][npix].  Orders are folded onto
+// k = m mod n first, then a direct sum over the min(n, lmax+1) bins.
 __global__ void k_ring_inverse(const double* G, int nring, const double* rt, const int* ri,
                                int lmax, int64_t npix, int nf, double* out) {
   extern __shared__ double sm[];
   const int q = blockIdx.x;
-  const int n = ri[2 * q];
+  const int n = ri[2 * q], Q = n / 4;
   const int64_t first = ri[2 * q + 1];
-  double* tw = sm;           // [n][2]
-  double* B = sm + 2 * n;    // [n][2]
+  const int nb = n <= lmax ? n : lmax + 1;
+  double* sq = sm;             // [n/4 + 1]
+  double* B = sm + Q + 1;      // [nb][2]
   const double phi0 = rt[4 * q + 3];
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    double s, c;
-    sincospi(2.0 * double(j) / double(n), &s, &c);
-    tw[2 * j] = c;
-    tw[2 * j + 1] = s;
-  }
+  quarter_table(sq, n);
   for (int fld = 0; fld < nf; ++fld) {
     const double* g = G + (size_t(fld) * nring + q) * (lmax + 1) * 2;
     __syncthreads();
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
       double br = 0.0, bi = 0.0;
       for (int m = k; m <= lmax; m += n) {
         double s, c;
@@ -151,8 +176,10 @@ __global__ void k_ring_inverse(const double* G, int nring, const double* rt, con
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
       double acc = 0.0;
       int t = 0;
-      for (int k = 0; k < n; ++k) {
-        acc += B[2 * k] * tw[2 * t] - B[2 * k + 1] * tw[2 * t + 1];
+      for (int k = 0; k < nb; ++k) {
+        double c, s;
+        twiddle(sq, Q, t, c, s);
+        acc += B[2 * k] * c - B[2 * k + 1] * s;
         t += j;
         if (t >= n) t -= n;
       }
@@ -419,18 +446,40 @@ template <int RPT>
 void launch_analysis(Plan* p, hipStream_t s, double* alm) {
   const int lmax = p->d.lmax;
   const size_t shm = (2 * size_t(lmax + 1) + 64 * (kBlock / 64) * 2) * sizeof(double);
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis<RPT>), dim3(lmax + 1), dim3(kBlock), shm, s,
-                     p->F, p->ring_s, p->lam_mant, p->lam_scale, p->H, p->nring_s, lmax,
-                     4.0 * kPi / double(p->npix_s), alm);
+  (void)allow_lds(p, k_analysis<RPT>, shm);
+  {
+    CLM_TIMED(p, s, "sht_analysis");
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis<RPT>), dim3(lmax + 1), dim3(kBlock), shm, s,
+                       p->F, p->ring_s, p->lam_mant, p->lam_scale, p->H, p->nring_s, lmax,
+                       4.0 * kPi / double(p->npix_s), alm);
+  }
+}
+
+// LDS of the ring kernels for the longest ring (4 nside) and lmax.
+size_t ring_fwd_lds(int nside, int lmax) {
+  size_t best = 0;
+  for (int n : {4 * nside, std::min(4 * nside, lmax - (lmax % 4))}) {
+    if (n < 4) continue;
+    size_t b = size_t(n) + n / 4 + 1 + (n <= lmax ? 2 * size_t(n) : 0);
+    best = std::max(best, b);
+  }
+  return best * sizeof(double);
+}
+
+size_t ring_inv_lds(int nside, int lmax) {
+  const size_t n = 4 * size_t(nside);
+  const size_t nb = n <= size_t(lmax) ? n : size_t(lmax) + 1;
+  return (n / 4 + 1 + 2 * nb) * sizeof(double);
 }
 
 clm_status ring_forward(Plan* p, const double* map, hipStream_t s) {
-  const int nmax = 4 * p->d.nside_sht;
-  const int nb = nmax < p->d.lmax + 1 ? nmax : p->d.lmax + 1;
-  const size_t shm = (3 * size_t(nmax) + 2 * size_t(nb)) * sizeof(double);
+  const size_t shm = ring_fwd_lds(p->d.nside_sht, p->d.lmax);
   if (allow_lds(p, k_ring_forward, shm) != CLM_OK) return CLM_EHIP;
-  hipLaunchKernelGGL(k_ring_forward, dim3(p->nring_s), dim3(kBlock), shm, s, map, p->ring_s,
-                     p->ringi_s, p->d.lmax, p->F);
+  {
+    CLM_TIMED(p, s, "sht_ring_forward");
+    hipLaunchKernelGGL(k_ring_forward, dim3(p->nring_s), dim3(kBlock), shm, s, map, p->ring_s,
+                       p->ringi_s, p->d.lmax, p->F);
+  }
   CLM_LAUNCH_CHECK();
   return CLM_OK;
 }
@@ -448,18 +497,24 @@ clm_status synthesis(Plan* p, const double* alm, hipStream_t s) {
   const int lmax = p->d.lmax;
   const size_t shm = 4 * size_t(lmax + 1) * sizeof(double);
   dim3 grid(lmax + 1, (p->H + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<false>), grid, dim3(kBlock), shm, s, alm,
-                     p->ring_s, p->lam_mant, p->lam_scale, p->H, p->nring_s, lmax, p->G);
+  if (allow_lds(p, k_synthesis<false>, shm) != CLM_OK) return CLM_EHIP;
+  {
+    CLM_TIMED(p, s, "sht_synthesis");
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<false>), grid, dim3(kBlock), shm, s, alm,
+                       p->ring_s, p->lam_mant, p->lam_scale, p->H, p->nring_s, lmax, p->G);
+  }
   CLM_LAUNCH_CHECK();
   return CLM_OK;
 }
 
 clm_status ring_inverse(Plan* p, const double* G, int nf, double* out, hipStream_t s) {
-  const int nmax = 4 * p->d.nside_sht;
-  const size_t shm = 4 * size_t(nmax) * sizeof(double);
+  const size_t shm = ring_inv_lds(p->d.nside_sht, p->d.lmax);
   if (allow_lds(p, k_ring_inverse, shm) != CLM_OK) return CLM_EHIP;
-  hipLaunchKernelGGL(k_ring_inverse, dim3(p->nring_s), dim3(kBlock), shm, s, G, p->nring_s,
-                     p->ring_s, p->ringi_s, p->d.lmax, p->npix_s, nf, out);
+  {
+    CLM_TIMED(p, s, "sht_ring_inverse");
+    hipLaunchKernelGGL(k_ring_inverse, dim3(p->nring_s), dim3(kBlock), shm, s, G, p->nring_s,
+                       p->ring_s, p->ringi_s, p->d.lmax, p->npix_s, nf, out);
+  }
   CLM_LAUNCH_CHECK();
   return CLM_OK;
 }
@@ -468,23 +523,32 @@ clm_status ring_inverse(Plan* p, const double* G, int nf, double* out, hipStream
 
 clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
   const clm_plan_desc& d = p->d;
-  if (4 * d.nside_sht > 4096)
-    return fail(p, CLM_EUNSUPPORTED, "ring transforms support nside_sht <= 1024");
+  if (ring_fwd_lds(d.nside_sht, d.lmax) > 160 * 1024 ||
+      ring_inv_lds(d.nside_sht, d.lmax) > 160 * 1024)
+    return fail(p, CLM_EUNSUPPORTED, "ring transforms exceed the LDS for this nside/lmax");
   const int nb = 1023;
   // mean of the fine map
+  {
+  CLM_TIMED(p, s, "mean");
   if (kappa_fp64)
     hipLaunchKernelGGL(k_partial_sum<double>, dim3(nb), dim3(kBlock), 0, s,
                        static_cast<const double*>(kappa), p->npix_f, p->red);
   else
     hipLaunchKernelGGL(k_partial_sum<float>, dim3(nb), dim3(kBlock), 0, s,
                        static_cast<const float*>(kappa), p->npix_f, p->red);
+  }
   CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_final_mean, dim3(1), dim3(kBlock), 0, s, p->red, nb,
-                     1.0 / double(p->npix_f));
+  {
+    CLM_TIMED(p, s, "mean");
+    hipLaunchKernelGGL(k_final_mean, dim3(1), dim3(kBlock), 0, s, p->red, nb,
+                       1.0 / double(p->npix_f));
+  }
   CLM_LAUNCH_CHECK();
   // degrade
   const int64_t ratio = d.nside_fine / d.nside_sht;
   const int64_t k2 = ratio * ratio;
+  {
+  CLM_TIMED(p, s, "degrade");
   if (kappa_fp64)
     hipLaunchKernelGGL(k_degrade<double>, dim3((p->npix_s + kBlock - 1) / kBlock),
                        dim3(kBlock), 0, s, static_cast<const double*>(kappa),
@@ -493,6 +557,7 @@ clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipSt
     hipLaunchKernelGGL(k_degrade<float>, dim3((p->npix_s + kBlock - 1) / kBlock),
                        dim3(kBlock), 0, s, static_cast<const float*>(kappa),
                        int64_t(d.nside_fine), p->npix_s, p->r2n_s, k2, p->red, p->kap_s);
+  }
   CLM_LAUNCH_CHECK();
   clm_status st = ring_forward(p, p->kap_s, s);
   if (st != CLM_OK) return st;
@@ -503,10 +568,14 @@ clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipSt
     case 2: launch_analysis<2>(p, s, alm); break;
     case 4: launch_analysis<4>(p, s, alm); break;
     case 8: launch_analysis<8>(p, s, alm); break;
+    case 16: launch_analysis<16>(p, s, alm); break;
     default: return fail(p, CLM_EUNSUPPORTED, "too many rings per thread");
   }
   CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_poisson, dim3(d.lmax + 1), dim3(kBlock), 0, s, alm, d.lmax);
+  {
+    CLM_TIMED(p, s, "sht_poisson");
+    hipLaunchKernelGGL(k_poisson, dim3(d.lmax + 1), dim3(kBlock), 0, s, alm, d.lmax);
+  }
   CLM_LAUNCH_CHECK();
   if ((st = synthesis(p, alm, s)) != CLM_OK) return st;
   return ring_inverse(p, p->G, 1, p->slots[slot].psi_s, s);
@@ -521,19 +590,27 @@ clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* gr
   {
     const size_t shm = 4 * size_t(lmax + 1) * sizeof(double);
     dim3 grid(lmax + 1, (p->H + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<true>), grid, dim3(kBlock), shm, s,
-                       p->slots[slot].alm, p->ring_s, p->lam_mant, p->lam_scale, p->H,
-                       p->nring_s, lmax, p->G);
+    if (allow_lds(p, k_synthesis<true>, shm) != CLM_OK) return CLM_EHIP;
+    {
+      CLM_TIMED(p, s, "sht_deriv_synthesis");
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<true>), grid, dim3(kBlock), shm, s,
+                         p->slots[slot].alm, p->ring_s, p->lam_mant, p->lam_scale, p->H,
+                         p->nring_s, lmax, p->G);
+    }
     CLM_LAUNCH_CHECK();
   }
   // the five pixel-space sums, element-wise in place (each thread reads all
   // three inputs of its (ring, m) slot before writing the five outputs)
-  hipLaunchKernelGGL(k_phi_fields, dim3((per + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p->G,
-                     p->nring_s, lmax, p->G);
+  {
+    CLM_TIMED(p, s, "sht_deriv_fields");
+    hipLaunchKernelGGL(k_phi_fields, dim3((per + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p->G,
+                       p->nring_s, lmax, p->G);
+  }
   CLM_LAUNCH_CHECK();
   clm_status st = ring_inverse(p, p->G, 5, p->deriv, s);
   if (st != CLM_OK) return st;
   const dim3 g((p->npix_s + kBlock - 1) / kBlock);
+  CLM_TIMED(p, s, "sht_covariant");
   if (out_fp64)
     hipLaunchKernelGGL(k_covariant<double>, g, dim3(kBlock), 0, s, p->deriv, p->npix_s,
                        p->ring_s, p->ringi_s, p->nring_s, p->r2n_s, order == CLM_ORDER_NESTED,
@@ -550,7 +627,7 @@ clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* gr
 
 extern "C" clm_status clm_alm2map(const double* alm, int32_t lmax, int32_t nside, double* map,
                                   hipStream_t stream) {
-  if (!alm || !map || lmax < 0 || nside < 1 || (nside & (nside - 1)) || nside > 1024)
+  if (!alm || !map || lmax < 0 || nside < 1 || (nside & (nside - 1)) || nside > 8192)
     return CLM_EINVAL;
   clm_plan_desc d;
   clm_plan_desc_default(&d, nside);
