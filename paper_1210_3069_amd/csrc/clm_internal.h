@@ -50,8 +50,10 @@ struct Plan {
   // tables
   double* ring_s = nullptr;     // [nring_s][4]: z, sin theta, theta, phi0
   int* ringi_s = nullptr;       // [nring_s][2]: n, first
+  double* ringx_s = nullptr;    // [nring_s + 1][2]: n/(2 pi), 1/(theta gap above)
   double* ring_f = nullptr;     // same for the fine grid
   int* ringi_f = nullptr;
+  double* ringx_f = nullptr;
   double* lam_mant = nullptr;   // [lmax+1][H] lambda_mm mantissa
   int* lam_scale = nullptr;     // [lmax+1][H] scale exponent (units of 2^800)
   int* r2n_s = nullptr;         // RING -> NESTED at nside_sht

@@ -134,9 +134,12 @@ __device__ __forceinline__ void pix2ang_ring(int64_t N, int64_t p, double& z, do
 
 // Ring tables on the device: rt[4*q + {0,1,2,3}] = z, sin, theta, phi0 and
 // ri[2*q + {0,1}] = pixels in ring, first pixel, for 0-based ring q.
+// rx[2 q] = n_q / (2 pi); rx[2 q + 1] = 1 / (theta_q - theta_{q-1}) with
+// theta_{-1} = 0, and rx[2 nring + 1] = 1 / (pi - theta_{nring-1}).
 struct Rings {
   const double* rt;
   const int* ri;
+  const double* rx;
   int nring;
   int N;
 };
@@ -145,12 +148,12 @@ struct Rings {
 // rings bracketing theta, pixels bracketing phi in each, linear weights;
 // above the first ring (below the last) the pole value is the mean of that
 // ring's four pixels.
-__device__ __forceinline__ void interp_weights(const Rings& R, double theta, double phi,
-                                               int64_t pix[4], double w[4]) {
+__device__ __forceinline__ void interp_weights(const Rings& R, double theta, double z,
+                                               double phi, int64_t pix[4], double w[4]) {
   const double twopi = 6.283185307179586476925286766559;
   const int N = R.N;
-  // first guess from the ring formulas, then exact bracketing on theta
-  const double z = cos(theta);
+  // first guess from the ring formulas (z = cos theta), then exact
+  // bracketing on theta
   double fr;
   if (z > 2.0 / 3.0)
     fr = N * sqrt(3.0 * (1.0 - z));
@@ -167,13 +170,13 @@ __device__ __forceinline__ void interp_weights(const Rings& R, double theta, dou
   auto pair = [&](int q, int64_t& a, int64_t& b, double& wp) {
     const int n = R.ri[2 * q];
     const int64_t first = R.ri[2 * q + 1];
-    const double t = (phi - R.rt[4 * q + 3]) * double(n) / twopi;
+    const double t = (phi - R.rt[4 * q + 3]) * R.rx[2 * q];
     const double fl = floor(t);
     wp = t - fl;
-    int64_t i1 = int64_t(fl) % n;
-    if (i1 < 0) i1 += n;
-    int64_t i2 = i1 + 1;
-    if (i2 == n) i2 = 0;
+    int i1 = int(fl);
+    while (i1 < 0) i1 += n;
+    while (i1 >= n) i1 -= n;
+    const int i2 = i1 + 1 == n ? 0 : i1 + 1;
     a = first + i1;
     b = first + i2;
   };
@@ -183,8 +186,7 @@ __device__ __forceinline__ void interp_weights(const Rings& R, double theta, dou
     double wa, wb;
     pair(g, a1, a2, wa);
     pair(g + 1, b1, b2, wb);
-    const double t1 = R.rt[4 * g + 2], t2 = R.rt[4 * (g + 1) + 2];
-    const double wt = (theta - t1) / (t2 - t1);
+    const double wt = (theta - R.rt[4 * g + 2]) * R.rx[2 * (g + 1) + 1];
     pix[0] = a1; pix[1] = a2; pix[2] = b1; pix[3] = b2;
     w[0] = (1 - wt) * (1 - wa);
     w[1] = (1 - wt) * wa;
@@ -194,7 +196,7 @@ __device__ __forceinline__ void interp_weights(const Rings& R, double theta, dou
     int64_t b1, b2;
     double wb;
     pair(0, b1, b2, wb);
-    const double wt = theta / R.rt[2];
+    const double wt = theta * R.rx[1];
     const double fac = (1.0 - wt) * 0.25;
     pix[0] = b1; pix[1] = b2; pix[2] = (b1 + 2) & 3; pix[3] = (b2 + 2) & 3;
     w[0] = wt * (1 - wb) + fac;
@@ -206,8 +208,7 @@ __device__ __forceinline__ void interp_weights(const Rings& R, double theta, dou
     int64_t a1, a2;
     double wa;
     pair(q, a1, a2, wa);
-    const double tq = R.rt[4 * q + 2];
-    const double wt = (theta - tq) / (3.14159265358979323846 - tq);
+    const double wt = (theta - R.rt[4 * q + 2]) * R.rx[2 * R.nring + 1];
     const int64_t base = R.ri[2 * q + 1];
     const double fac = wt * 0.25;
     pix[0] = a1; pix[1] = a2;
@@ -221,10 +222,11 @@ __device__ __forceinline__ void interp_weights(const Rings& R, double theta, dou
 }
 
 template <typename T>
-__device__ __forceinline__ double interp(const Rings& R, const T* map, double theta, double phi) {
+__device__ __forceinline__ double interp(const Rings& R, const T* map, double theta, double z,
+                                         double phi) {
   int64_t pix[4];
   double w[4];
-  interp_weights(R, theta, phi, pix, w);
+  interp_weights(R, theta, z, phi, pix, w);
   return w[0] * double(map[pix[0]]) + w[1] * double(map[pix[1]]) +
          w[2] * double(map[pix[2]]) + w[3] * double(map[pix[3]]);
 }

@@ -38,12 +38,6 @@ __device__ __forceinline__ int64_t xcd_block() {
   return (b % 8) * (nb / 8) + b / 8;
 }
 
-// Row coefficients of a level in LDS, as T: s_m, s_p, 1/s_c, area.
-template <typename T>
-struct RowC {
-  T sm, sp, isc, A;
-};
-
 // ------------------------------------------------------------ patch setup
 // u0 = interp(psi_SHT) at the cell centres; ghost u0 = 2 b - u0(adjacent)
 // with b = interp(psi_SHT) at the face midpoint (corner: patch corner);
@@ -62,42 +56,61 @@ struct SetupArgs {
   void* fprime;        // [patch][n^2] of T
 };
 
-__device__ __forceinline__ void patch_point(const double* R, double thp, double php,
-                                            double& th, double& ph) {
-  double st, ct, sp, cp;
-  sincos(thp, &st, &ct);
-  sincos(php, &sp, &cp);
-  const double x = st * cp, y = st * sp, z = ct;
-  const double vx = R[0] * x + R[3] * y + R[6] * z;
-  const double vy = R[1] * x + R[4] * y + R[7] * z;
-  const double vz = R[2] * x + R[5] * y + R[8] * z;
-  th = atan2(sqrt(vx * vx + vy * vy), vz);
+// Global direction of the patch point with sin/cos of theta' and phi':
+// v = R^T (sin th' cos ph', sin th' sin ph', cos th'); returns theta, z = cos
+// theta and phi in [0, 2 pi).
+__device__ __forceinline__ void patch_dir(const double* R, double st, double ct, double sp,
+                                          double cp, double& th, double& z, double& ph) {
+  const double x = st * cp, y = st * sp;
+  const double vx = R[0] * x + R[3] * y + R[6] * ct;
+  const double vy = R[1] * x + R[4] * y + R[7] * ct;
+  z = R[2] * x + R[5] * y + R[8] * ct;
+  th = atan2(sqrt(vx * vx + vy * vy), z);
   ph = atan2(vy, vx);
   if (ph < 0) ph += 2.0 * kPi;
 }
 
+// One block per 64 x 64 tile (or the whole patch if smaller).  Pass 1 visits
+// every cell of the tile plus one ring once: direction, u0 and (interior
+// cells) the source, with sin/cos of theta' and phi' tabulated per row and
+// column; pass 2 fills the patch ghosts from the face values; pass 3 forms
+// f' = f - L u0.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_patch_setup(SetupArgs a) {
-  extern __shared__ double shu[];  // [(tile+2)^2] u0 over the tile and one halo ring
+  extern __shared__ double shu[];
   const int64_t lb = xcd_block();
   const int tpp = a.ntile * a.ntile;
   const int64_t patch = lb / tpp;
   const int tt = int(lb % tpp);
   const int ti = tt / a.ntile, tj = tt % a.ntile;
   const int RR = a.tile + 2;
+  double* trig = shu + RR * RR;                          // [RR][4]: sin/cos th'_row, ph'_col
+  T* fsh = reinterpret_cast<T*>(trig + 4 * RR);           // [tile^2] source f (interior)
   const int i0 = ti * a.tile - 1, j0 = tj * a.tile - 1;
   const int n = a.n;
   const double* R = a.rot + 9 * patch;
   const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
-  // interior cells of the region
+  for (int r = threadIdx.x; r < RR; r += blockDim.x) {
+    sincos(th0 + (i0 + r + 0.5) * a.delta, &trig[4 * r], &trig[4 * r + 1]);
+    sincos(ph0 + (j0 + r + 0.5) * a.delta, &trig[4 * r + 2], &trig[4 * r + 3]);
+  }
+  __syncthreads();
+  const double mean = a.red[1023];
   for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
     const int li = idx / RR, lj = idx % RR;
     const int gi = i0 + li, gj = j0 + lj;
     double v = 0.0;
     if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
-      double th, ph;
-      patch_point(R, th0 + (gi + 0.5) * a.delta, ph0 + (gj + 0.5) * a.delta, th, ph);
-      v = hpx::interp(a.rs, a.psi_s, th, ph);
+      double th, z, ph;
+      patch_dir(R, trig[4 * li], trig[4 * li + 1], trig[4 * lj + 2], trig[4 * lj + 3], th, z,
+                ph);
+      v = hpx::interp(a.rs, a.psi_s, th, z, ph);
+      if (li >= 1 && li <= a.tile && lj >= 1 && lj <= a.tile) {
+        const double kv =
+            a.kappa_fp64 ? hpx::interp(a.rf, static_cast<const double*>(a.kappa), th, z, ph)
+                         : hpx::interp(a.rf, static_cast<const float*>(a.kappa), th, z, ph);
+        fsh[(li - 1) * a.tile + (lj - 1)] = T(2.0 * (kv - mean));
+      }
     }
     shu[idx] = v;
   }
@@ -108,50 +121,55 @@ __global__ __launch_bounds__(kBlock) void k_patch_setup(SetupArgs a) {
     const int gi = i0 + li, gj = j0 + lj;
     const bool gI = gi == -1 || gi == n, gJ = gj == -1 || gj == n;
     if (!(gI || gJ)) continue;
-    if ((gI && (gj < -1 || gj > n)) || (gJ && (gi < -1 || gi > n))) continue;
     double thp, php;
     int ai = li, aj = lj;  // adjacent interior cell
     if (gI) { thp = gi < 0 ? th0 : th0 + a.L; ai = gi < 0 ? li + 1 : li - 1; }
     else    { thp = th0 + (gi + 0.5) * a.delta; }
     if (gJ) { php = gj < 0 ? ph0 : ph0 + a.L; aj = gj < 0 ? lj + 1 : lj - 1; }
     else    { php = ph0 + (gj + 0.5) * a.delta; }
-    double th, ph;
-    patch_point(R, thp, php, th, ph);
-    const double b = hpx::interp(a.rs, a.psi_s, th, ph);
+    double st, ct, sp, cp, th, z, ph;
+    sincos(thp, &st, &ct);
+    sincos(php, &sp, &cp);
+    patch_dir(R, st, ct, sp, cp, th, z, ph);
+    const double b = hpx::interp(a.rs, a.psi_s, th, z, ph);
     shu[idx] = 2.0 * b - shu[ai * RR + aj];
   }
   __syncthreads();
-  const double mean = a.red[1023];
   const size_t G = size_t(n + 2);
   double* u0 = a.u0 + size_t(patch) * G * G;
   T* fp = static_cast<T*>(a.fprime) + size_t(patch) * n * n;
   for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
     const int li = idx / RR, lj = idx % RR;
     const int gi = i0 + li, gj = j0 + lj;
-    const bool interior = li >= 1 && li <= a.tile && lj >= 1 && lj <= a.tile;
     // write u0: the tile's cells, plus the patch ghosts beside this tile
     const bool own_i = (li >= 1 && li <= a.tile) || (gi == -1) || (gi == n);
     const bool own_j = (lj >= 1 && lj <= a.tile) || (gj == -1) || (gj == n);
-    if (own_i && own_j && gi >= -1 && gi <= n && gj >= -1 && gj <= n)
-      u0[size_t(gi + 1) * G + (gj + 1)] = shu[idx];
-    if (!interior) continue;
-    double th, ph;
-    patch_point(R, th0 + (gi + 0.5) * a.delta, ph0 + (gj + 0.5) * a.delta, th, ph);
-    const double kv = a.kappa_fp64 ? hpx::interp(a.rf, static_cast<const double*>(a.kappa), th, ph)
-                                   : hpx::interp(a.rf, static_cast<const float*>(a.kappa), th, ph);
-    const double f = 2.0 * (kv - mean);
+    if (own_i && own_j) u0[size_t(gi + 1) * G + (gj + 1)] = shu[idx];
+    if (!(li >= 1 && li <= a.tile && lj >= 1 && lj <= a.tile)) continue;
     const double* c = a.coef + 4 * gi;
     const double u = shu[idx];
     const double Lu = (c[0] * (shu[idx - RR] - u) + c[1] * (shu[idx + RR] - u) +
                        (shu[idx - 1] - 2.0 * u + shu[idx + 1]) / c[2]) / c[3];
-    fp[size_t(gi) * n + gj] = T(f - Lu);
+    fp[size_t(gi) * n + gj] = T(double(fsh[(li - 1) * a.tile + (lj - 1)]) - Lu);
   }
 }
 
 // ------------------------------------------------------------ tile kernels
+// A 64 x 64 tile plus an even halo of HH cells per side is processed by one
+// workgroup.  The region is cut into 2 x 2 quads aligned with the cells of
+// the next coarser level; each thread owns up to IT quads and keeps their
+// four u values and four sources f in registers.  u is mirrored in LDS,
+// columns split by parity (row stride Q) so that neighbouring quads of a
+// row sit at consecutive LDS addresses.  A red-black half sweep updates the
+// two cells of a quad that have the sweep's colour; their in-quad neighbours
+// come from registers, the others from LDS.  Cells outside the patch are
+// zero and never updated; a neighbour across the patch face is accounted
+// for in the diagonal (zero face value).
+constexpr int kTileBlock = 512;
+
 template <typename T>
 struct TileArgs {
-  int n, ntile, tile, hh, nu;
+  int n, ntile, nu;
   const double* coef;   // this level's rows
   const T* u_in;        // level iterate in (nullptr: zero), or ubar (level >= 1 pre)
   const T* f_in;        // source f (level 0 pre, all post), or rbar (level >= 1 pre)
@@ -164,134 +182,216 @@ struct TileArgs {
   int fas_source;       // pre on level >= 1: f = L u_in + f_in
 };
 
-// Load rows of coefficients for region rows [i0, i0 + RR) into LDS.
-template <typename T>
-__device__ __forceinline__ void load_rows(const double* coef, int n, int i0, int RR, RowC<T>* rc) {
-  for (int r = threadIdx.x; r < RR; r += blockDim.x) {
+template <typename T, int HH>
+struct QT {
+  static_assert(HH % 2 == 0, "quads must align with the coarse level");
+  static constexpr int RR = kTile + 2 * HH;    // region side
+  static constexpr int Q = RR / 2;             // quads per side
+  static constexpr int NQ = Q * Q;
+  static constexpr int IT = (NQ + kTileBlock - 1) / kTileBlock;
+  static constexpr int QH = HH / 2;            // first interior quad
+};
+
+template <typename T, int RR>
+struct QLds {
+  T uE[RR * (RR / 2)], uO[RR * (RR / 2)];
+  T sm[RR], sp[RR], isc[RR], A[RR], rD[RR];
+};
+
+template <typename T, int RR>
+__device__ __forceinline__ T& qcell(QLds<T, RR>& t, int li, int lj) {
+  return ((lj & 1) ? t.uO : t.uE)[li * (RR / 2) + (lj >> 1)];
+}
+
+template <typename T, int RR>
+__device__ __forceinline__ void qload_rows(QLds<T, RR>& t, const double* coef, int n, int i0) {
+  for (int r = threadIdx.x; r < RR; r += kTileBlock) {
     const int gi = i0 + r;
-    RowC<T> v{T(0), T(0), T(0), T(1)};
+    T sm = T(0), sp = T(0), isc = T(0), A = T(1), rD = T(0);
     if (gi >= 0 && gi < n) {
       const double* c = coef + 4 * gi;
-      v.sm = T(c[0]); v.sp = T(c[1]); v.isc = T(1.0 / c[2]); v.A = T(c[3]);
+      sm = T(c[0]);
+      sp = T(c[1]);
+      isc = T(1.0 / c[2]);
+      A = T(c[3]);
+      rD = T(1.0 / (c[0] + c[1] + 2.0 / c[2]));
     }
-    rc[r] = v;
+    t.sm[r] = sm; t.sp[r] = sp; t.isc[r] = isc; t.A[r] = A; t.rD[r] = rD;
   }
 }
 
-// (L u)_ij for a cell of the region, faces of the patch as zero Dirichlet
-// (a neighbour across the patch face is -u_ij).
-template <typename T>
-__device__ __forceinline__ T lap(const T* u, int RR, int li, int lj, int gi, int gj, int n,
-                                 const RowC<T>& c) {
-  const T uc = u[li * RR + lj];
-  const T up = gi > 0 ? u[(li - 1) * RR + lj] : -uc;
-  const T dn = gi < n - 1 ? u[(li + 1) * RR + lj] : -uc;
-  const T lf = gj > 0 ? u[li * RR + lj - 1] : -uc;
-  const T rt = gj < n - 1 ? u[li * RR + lj + 1] : -uc;
-  return (c.sm * (up - uc) + c.sp * (dn - uc) + (lf - T(2) * uc + rt) * c.isc) / c.A;
-}
+// Quad-owning thread state.
+template <typename T, int IT>
+struct QRegs {
+  T u[IT][4];   // (a, b) -> 2a + b
+  T f[IT][4];
+};
 
-// Gauss-Seidel solve of one cell (neighbours across the patch face fold
-// into the diagonal).
-template <typename T>
-__device__ __forceinline__ T gs_cell(const T* u, const T* f, int RR, int li, int lj, int gi,
-                                     int gj, int n, const RowC<T>& c) {
-  T num = -c.A * f[li * RR + lj];
-  T diag = c.sm + c.sp + T(2) * c.isc;
-  if (gi > 0) num += c.sm * u[(li - 1) * RR + lj]; else diag += c.sm;
-  if (gi < n - 1) num += c.sp * u[(li + 1) * RR + lj]; else diag += c.sp;
-  T lr = T(0);
-  if (gj > 0) lr += u[li * RR + lj - 1]; else diag += c.isc;
-  if (gj < n - 1) lr += u[li * RR + lj + 1]; else diag += c.isc;
-  num += lr * c.isc;
-  return num / diag;
-}
-
-// One red-black half sweep over the region cells at distance >= 1 from the
-// region edge that lie in the patch.
-template <typename T>
-__device__ __forceinline__ void half_sweep(T* u, const T* f, const RowC<T>* rc, int RR, int i0,
-                                           int j0, int n, int color) {
-  const int half = (RR - 1) / 2;  // cells of one colour per row, upper bound
-  const int total = (RR - 2) * half;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int li = 1 + idx / half;
-    const int gi = i0 + li;
-    const int off = (color + gi + j0 + 1) & 1;
-    const int lj = 1 + 2 * (idx % half) + off;
-    const int gj = j0 + lj;
-    if (lj > RR - 2 || gi < 0 || gi >= n || gj < 0 || gj >= n) continue;
-    u[li * RR + lj] = gs_cell(u, f, RR, li, lj, gi, gj, n, rc[li]);
+// Load u (registers and LDS) and f (registers) of the owned quads.
+template <typename T, int HH>
+__device__ __forceinline__ void qload(QLds<T, QT<T, HH>::RR>& t, QRegs<T, QT<T, HH>::IT>& r,
+                                      const T* u_in, const T* f_in, size_t pbase, int n,
+                                      int i0, int j0) {
+  using G = QT<T, HH>;
+#pragma unroll
+  for (int it = 0; it < G::IT; ++it) {
+    const int q = threadIdx.x + it * kTileBlock;
+    const int qi = q / G::Q, qj = q - qi * G::Q;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int gi = i0 + 2 * qi + a, gj = j0 + 2 * qj;
+      const bool in = q < G::NQ && gi >= 0 && gi < n && gj >= 0 && gj < n;
+      T u0 = T(0), u1 = T(0), f0 = T(0), f1 = T(0);
+      if (in) {
+        const size_t g = pbase + size_t(gi) * n + gj;
+        if (u_in) { u0 = u_in[g]; u1 = u_in[g + 1]; }
+        f0 = f_in[g];
+        f1 = f_in[g + 1];
+      }
+      r.u[it][2 * a] = u0; r.u[it][2 * a + 1] = u1;
+      r.f[it][2 * a] = f0; r.f[it][2 * a + 1] = f1;
+      if (q < G::NQ) {
+        const int li = 2 * qi + a;
+        t.uE[li * G::Q + qj] = u0;
+        t.uO[li * G::Q + qj] = u1;
+      }
+    }
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_pre(TileArgs<T> a) {
-  extern __shared__ unsigned char smem[];
-  const int RR = a.tile + 2 * a.hh;
-  T* u = reinterpret_cast<T*>(smem);
-  T* f = u + RR * RR;
-  RowC<T>* rc = reinterpret_cast<RowC<T>*>(f + RR * RR);
+// (L u) at cell (a, b) of quad (qi, qj): in-quad neighbours from registers,
+// the others from LDS; zero face value across the patch boundary.
+template <typename T, int HH>
+__device__ __forceinline__ T qlap(QLds<T, QT<T, HH>::RR>& t, const T* u4, int qi, int qj, int a,
+                                  int b, int i0, int j0, int n) {
+  constexpr int RR = QT<T, HH>::RR;
+  const int li = 2 * qi + a, lj = 2 * qj + b;
+  const int gi = i0 + li, gj = j0 + lj;
+  const T c = u4[2 * a + b];
+  T up = a ? u4[b] : (li > 0 ? qcell(t, li - 1, lj) : T(0));
+  T dn = a ? (li < RR - 1 ? qcell(t, li + 1, lj) : T(0)) : u4[2 + b];
+  T lf = b ? u4[2 * a] : (lj > 0 ? qcell(t, li, lj - 1) : T(0));
+  T rt = b ? (lj < RR - 1 ? qcell(t, li, lj + 1) : T(0)) : u4[2 * a + 1];
+  if (gi == 0) up = -c;
+  if (gi == n - 1) dn = -c;
+  if (gj == 0) lf = -c;
+  if (gj == n - 1) rt = -c;
+  return (t.sm[li] * (up - c) + t.sp[li] * (dn - c) + (lf - T(2) * c + rt) * t.isc[li]) / t.A[li];
+}
+
+// Red-black half sweep: the two cells of colour `color` in every owned quad
+// (i0, j0 even, so the colour of (a, b) is (a + b) % 2).
+template <typename T, int HH>
+__device__ __forceinline__ void qsweep(QLds<T, QT<T, HH>::RR>& t, QRegs<T, QT<T, HH>::IT>& r,
+                                       int color, int i0, int j0, int n) {
+  using G = QT<T, HH>;
+  constexpr int RR = G::RR;
+#pragma unroll
+  for (int it = 0; it < G::IT; ++it) {
+    const int q = threadIdx.x + it * kTileBlock;
+    if (q >= G::NQ) continue;
+    const int qi = q / G::Q, qj = q - qi * G::Q;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int a = s, b = (color + s) & 1;   // (0, color) and (1, 1 - color)
+      const int li = 2 * qi + a, lj = 2 * qj + b;
+      if (li == 0 || li == RR - 1 || lj == 0 || lj == RR - 1) continue;
+      const int gi = i0 + li, gj = j0 + lj;
+      if (gi < 0 || gi >= n || gj < 0 || gj >= n) continue;
+      T* u4 = r.u[it];
+      const T up = a ? u4[b] : qcell(t, li - 1, lj);
+      const T dn = a ? qcell(t, li + 1, lj) : u4[2 + b];
+      const T lf = b ? u4[2 * a] : qcell(t, li, lj - 1);
+      const T rt = b ? qcell(t, li, lj + 1) : u4[2 * a + 1];
+      const T sm = t.sm[li], sp = t.sp[li], isc = t.isc[li];
+      const T num = sm * up + sp * dn + isc * (lf + rt) - t.A[li] * r.f[it][2 * a + b];
+      T v;
+      if (gi == 0 || gi == n - 1 || gj == 0 || gj == n - 1) {
+        T diag = sm + sp + T(2) * isc;
+        if (gi == 0) diag += sm;
+        if (gi == n - 1) diag += sp;
+        if (gj == 0) diag += isc;
+        if (gj == n - 1) diag += isc;
+        v = num / diag;
+      } else {
+        v = num * t.rD[li];
+      }
+      u4[2 * a + b] = v;
+      qcell(t, li, lj) = v;
+    }
+  }
+}
+
+template <typename T, int HH>
+__global__ __launch_bounds__(kTileBlock) void k_mg_pre(TileArgs<T> a) {
+  using G = QT<T, HH>;
+  __shared__ QLds<T, G::RR> t;
+  QRegs<T, G::IT> r;
   const int64_t lb = xcd_block();
   const int tpp = a.ntile * a.ntile;
   const int64_t patch = lb / tpp;
   const int tt = int(lb % tpp);
-  const int i0 = (tt / a.ntile) * a.tile - a.hh, j0 = (tt % a.ntile) * a.tile - a.hh;
+  const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
   const int n = a.n;
   const size_t pbase = size_t(patch) * n * n;
-  load_rows(a.coef, n, i0, RR, rc);
-  for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
-    const int gi = i0 + idx / RR, gj = j0 + idx % RR;
-    const bool in = gi >= 0 && gi < n && gj >= 0 && gj < n;
-    const size_t g = pbase + size_t(gi) * n + gj;
-    u[idx] = (in && a.u_in) ? a.u_in[g] : T(0);
-    f[idx] = in ? a.f_in[g] : T(0);
-  }
+  qload_rows(t, a.coef, n, i0);
+  qload<T, HH>(t, r, a.u_in, a.f_in, pbase, n, i0, j0);
   __syncthreads();
   if (a.fas_source) {
-    // f = L_H ubar + rbar on the region cells away from its edge
-    for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
-      const int li = idx / RR, lj = idx % RR;
-      const int gi = i0 + li, gj = j0 + lj;
-      if (li < 1 || li > RR - 2 || lj < 1 || lj > RR - 2) continue;
-      if (gi < 0 || gi >= n || gj < 0 || gj >= n) continue;
-      f[idx] += lap(u, RR, li, lj, gi, gj, n, rc[li]);
+    // f = L_H ubar + rbar on the in-patch cells away from the region edge
+#pragma unroll
+    for (int it = 0; it < G::IT; ++it) {
+      const int q = threadIdx.x + it * kTileBlock;
+      if (q >= G::NQ) continue;
+      const int qi = q / G::Q, qj = q - qi * G::Q;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int li = 2 * qi + (c >> 1), lj = 2 * qj + (c & 1);
+        const int gi = i0 + li, gj = j0 + lj;
+        if (li >= 1 && li <= G::RR - 2 && lj >= 1 && lj <= G::RR - 2 && gi >= 0 && gi < n &&
+            gj >= 0 && gj < n)
+          r.f[it][c] += qlap<T, HH>(t, r.u[it], qi, qj, c >> 1, c & 1, i0, j0, n);
+      }
     }
-    __syncthreads();
   }
   for (int s = 0; s < a.nu; ++s) {
-    half_sweep(u, f, rc, RR, i0, j0, n, 0);
+    qsweep<T, HH>(t, r, 0, i0, j0, n);
     __syncthreads();
-    half_sweep(u, f, rc, RR, i0, j0, n, 1);
+    qsweep<T, HH>(t, r, 1, i0, j0, n);
     __syncthreads();
   }
-  // write the tile interior (and its source on coarse levels)
-  for (int idx = threadIdx.x; idx < a.tile * a.tile; idx += blockDim.x) {
-    const int li = a.hh + idx / a.tile, lj = a.hh + idx % a.tile;
-    const size_t g = pbase + size_t(i0 + li) * n + (j0 + lj);
-    a.u_out[g] = u[li * RR + lj];
-    if (a.fas_source) a.f_out[g] = f[li * RR + lj];
-  }
-  // residual and area-weighted restriction of the tile interior
-  const int th = a.tile / 2, nc = n / 2;
+  // interior quads: store u (and f), residual, area-weighted restriction
+  const int nc = n / 2;
   const size_t cbase = size_t(patch) * nc * nc;
-  for (int idx = threadIdx.x; idx < th * th; idx += blockDim.x) {
-    const int ci = idx / th, cj = idx % th;
-    const int li = a.hh + 2 * ci, lj = a.hh + 2 * cj;
-    const int gi = i0 + li, gj = j0 + lj;
-    T r[4], uu[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int di = k >> 1, dj = k & 1;
-      const int id = (li + di) * RR + lj + dj;
-      uu[k] = u[id];
-      r[k] = f[id] - lap(u, RR, li + di, lj + dj, gi + di, gj + dj, n, rc[li + di]);
+  for (int it = 0; it < G::IT; ++it) {
+    const int q = threadIdx.x + it * kTileBlock;
+    const int qi = q / G::Q, qj = q - qi * G::Q;
+    if (q >= G::NQ || qi < G::QH || qi >= G::QH + kTile / 2 || qj < G::QH ||
+        qj >= G::QH + kTile / 2)
+      continue;
+    const int gi = i0 + 2 * qi, gj = j0 + 2 * qj;
+    const size_t g = pbase + size_t(gi) * n + gj;
+    a.u_out[g] = r.u[it][0];
+    a.u_out[g + 1] = r.u[it][1];
+    a.u_out[g + n] = r.u[it][2];
+    a.u_out[g + n + 1] = r.u[it][3];
+    if (a.fas_source) {
+      a.f_out[g] = r.f[it][0];
+      a.f_out[g + 1] = r.f[it][1];
+      a.f_out[g + n] = r.f[it][2];
+      a.f_out[g + n + 1] = r.f[it][3];
     }
-    const T a0 = rc[li].A, a1 = rc[li + 1].A;
+    T res[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      res[c] = r.f[it][c] - qlap<T, HH>(t, r.u[it], qi, qj, c >> 1, c & 1, i0, j0, n);
+    const int li = 2 * qi;
+    const T a0 = t.A[li], a1 = t.A[li + 1];
     const T den = T(2) * (a0 + a1);
     const size_t gc = cbase + size_t(gi / 2) * nc + gj / 2;
-    a.ubar_out[gc] = (a0 * (uu[0] + uu[1]) + a1 * (uu[2] + uu[3])) / den;
-    a.rbar_out[gc] = (a0 * (r[0] + r[1]) + a1 * (r[2] + r[3])) / den;
+    a.ubar_out[gc] = (a0 * (r.u[it][0] + r.u[it][1]) + a1 * (r.u[it][2] + r.u[it][3])) / den;
+    a.rbar_out[gc] = (a0 * (res[0] + res[1]) + a1 * (res[2] + res[3])) / den;
   }
 }
 
@@ -307,61 +407,74 @@ __device__ __forceinline__ T prolong_cell(int gi, int gj, int n, EF e) {
          T(16);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_post(TileArgs<T> a) {
-  extern __shared__ unsigned char smem[];
-  const int RR = a.tile + 2 * a.hh;
-  const int CR = RR / 2 + 3;  // coarse rows/cols covering the region +- 1
-  T* u = reinterpret_cast<T*>(smem);
-  T* f = u + RR * RR;
-  T* e = f + RR * RR;
-  RowC<T>* rc = reinterpret_cast<RowC<T>*>(e + CR * CR);
+template <typename T, int HH>
+__global__ __launch_bounds__(kTileBlock) void k_mg_post(TileArgs<T> a) {
+  using G = QT<T, HH>;
+  constexpr int CR = G::Q + 2;  // coarse cells covering the region quads +- 1
+  __shared__ QLds<T, G::RR> t;
+  __shared__ T e[CR * CR];
+  QRegs<T, G::IT> r;
   const int64_t lb = xcd_block();
   const int tpp = a.ntile * a.ntile;
   const int64_t patch = lb / tpp;
   const int tt = int(lb % tpp);
-  const int i0 = (tt / a.ntile) * a.tile - a.hh, j0 = (tt % a.ntile) * a.tile - a.hh;
+  const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
   const int n = a.n, nc = n / 2;
   const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
-  const int ci0 = (i0 >> 1) - 1, cj0 = (j0 >> 1) - 1;  // floor division (i0 may be < 0)
-  load_rows(a.coef, n, i0, RR, rc);
-  for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
-    const int gi = i0 + idx / RR, gj = j0 + idx % RR;
-    const bool in = gi >= 0 && gi < n && gj >= 0 && gj < n;
-    const size_t g = pbase + size_t(gi) * n + gj;
-    u[idx] = in ? a.u_in[g] : T(0);
-    f[idx] = in ? a.f_in[g] : T(0);
-  }
-  for (int idx = threadIdx.x; idx < CR * CR; idx += blockDim.x) {
-    const int I = ci0 + idx / CR, J = cj0 + idx % CR;
+  const int ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // i0, j0 even
+  qload_rows(t, a.coef, n, i0);
+  qload<T, HH>(t, r, a.u_in, a.f_in, pbase, n, i0, j0);
+  for (int item = threadIdx.x; item < CR * CR; item += kTileBlock) {
+    const int I = ci0 + item / CR, J = cj0 + item % CR;
     T v = T(0);
     if (I >= 0 && I < nc && J >= 0 && J < nc) {
       const size_t g = cbase + size_t(I) * nc + J;
       v = a.uc[g] - a.ubarc[g];
     }
-    e[idx] = v;
+    e[item] = v;
   }
   __syncthreads();
   auto ef = [&](int I, int J) { return e[(I - ci0) * CR + (J - cj0)]; };
-  for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
-    const int gi = i0 + idx / RR, gj = j0 + idx % RR;
-    if (gi < 0 || gi >= n || gj < 0 || gj >= n) continue;
-    u[idx] += prolong_cell<T>(gi, gj, n, ef);
+#pragma unroll
+  for (int it = 0; it < G::IT; ++it) {
+    const int q = threadIdx.x + it * kTileBlock;
+    if (q >= G::NQ) continue;
+    const int qi = q / G::Q, qj = q - qi * G::Q;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int li = 2 * qi + (c >> 1), lj = 2 * qj + (c & 1);
+      const int gi = i0 + li, gj = j0 + lj;
+      if (gi < 0 || gi >= n || gj < 0 || gj >= n) continue;
+      r.u[it][c] += prolong_cell<T>(gi, gj, n, ef);
+      qcell(t, li, lj) = r.u[it][c];
+    }
   }
   __syncthreads();
   for (int s = 0; s < a.nu; ++s) {
-    half_sweep(u, f, rc, RR, i0, j0, n, 0);
+    qsweep<T, HH>(t, r, 0, i0, j0, n);
     __syncthreads();
-    half_sweep(u, f, rc, RR, i0, j0, n, 1);
+    qsweep<T, HH>(t, r, 1, i0, j0, n);
     __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < a.tile * a.tile; idx += blockDim.x) {
-    const int li = a.hh + idx / a.tile, lj = a.hh + idx % a.tile;
-    a.u_out[pbase + size_t(i0 + li) * n + (j0 + lj)] = u[li * RR + lj];
+#pragma unroll
+  for (int it = 0; it < G::IT; ++it) {
+    const int q = threadIdx.x + it * kTileBlock;
+    const int qi = q / G::Q, qj = q - qi * G::Q;
+    if (q >= G::NQ || qi < G::QH || qi >= G::QH + kTile / 2 || qj < G::QH ||
+        qj >= G::QH + kTile / 2)
+      continue;
+    const size_t g = pbase + size_t(i0 + 2 * qi) * n + (j0 + 2 * qj);
+    a.u_out[g] = r.u[it][0];
+    a.u_out[g + 1] = r.u[it][1];
+    a.u_out[g + n] = r.u[it][2];
+    a.u_out[g + n + 1] = r.u[it][3];
   }
 }
 
 // ------------------------------------------------------------ LDS levels
+// One workgroup per patch runs the V-cycle below level K entirely in LDS:
+// per level l: u, f (and ubar for l > K) as row-major n_l x n_l arrays, and
+// the level's row coefficients (s_m, s_p, 1/s_c, area, interior 1/diag).
 struct LdsLevels {
   int K, nlev, n0;        // first level handled here, number of levels, its size
   size_t crow[16];        // coefficient row offsets per level (absolute level index)
@@ -380,134 +493,175 @@ struct LdsArgs {
 };
 
 template <typename T>
-__device__ __forceinline__ T lap_g(const T* u, int n, int i, int j, const double* c) {
+struct LRows {
+  const T* sm;
+  const T* sp;
+  const T* isc;
+  const T* A;
+  const T* rD;
+};
+
+// (L u)_ij, zero face value across the patch boundary.
+template <typename T>
+__device__ __forceinline__ T lap_g(const T* u, int n, int i, int j, const LRows<T>& r) {
   const T uc = u[i * n + j];
   const T up = i > 0 ? u[(i - 1) * n + j] : -uc;
   const T dn = i < n - 1 ? u[(i + 1) * n + j] : -uc;
   const T lf = j > 0 ? u[i * n + j - 1] : -uc;
   const T rt = j < n - 1 ? u[i * n + j + 1] : -uc;
-  return (T(c[0]) * (up - uc) + T(c[1]) * (dn - uc) + (lf - T(2) * uc + rt) * T(1.0 / c[2])) /
-         T(c[3]);
+  return (r.sm[i] * (up - uc) + r.sp[i] * (dn - uc) + (lf - T(2) * uc + rt) * r.isc[i]) / r.A[i];
 }
 
 template <typename T>
-__device__ void lds_smooth(T* u, const T* f, int n, const double* coef, int sweeps) {
+__device__ void lds_smooth(T* u, const T* f, int n, int lg, const LRows<T>& r, int sweeps) {
+  const int half = n >> 1;
   for (int s = 0; s < sweeps; ++s) {
     for (int color = 0; color < 2; ++color) {
-      const int half = n / 2;
-      for (int idx = threadIdx.x; idx < n * half; idx += blockDim.x) {
-        const int i = idx / half;
-        const int j = 2 * (idx % half) + ((color + i) & 1);
-        const double* c = coef + 4 * i;
-        const T sm = T(c[0]), sp = T(c[1]), isc = T(1.0 / c[2]), A = T(c[3]);
-        T num = -A * f[i * n + j];
-        T diag = sm + sp + T(2) * isc;
-        if (i > 0) num += sm * u[(i - 1) * n + j]; else diag += sm;
-        if (i < n - 1) num += sp * u[(i + 1) * n + j]; else diag += sp;
+      for (int idx = threadIdx.x; idx < n * half; idx += kBlock) {
+        const int i = idx >> (lg - 1);
+        const int j = 2 * (idx & (half - 1)) + ((color + i) & 1);
+        const T sm = r.sm[i], sp = r.sp[i], isc = r.isc[i];
+        T num = -r.A[i] * f[i * n + j];
         T lr = T(0);
-        if (j > 0) lr += u[i * n + j - 1]; else diag += isc;
-        if (j < n - 1) lr += u[i * n + j + 1]; else diag += isc;
+        bool edge = false;
+        if (i > 0) num += sm * u[(i - 1) * n + j]; else edge = true;
+        if (i < n - 1) num += sp * u[(i + 1) * n + j]; else edge = true;
+        if (j > 0) lr += u[i * n + j - 1]; else edge = true;
+        if (j < n - 1) lr += u[i * n + j + 1]; else edge = true;
         num += lr * isc;
-        u[i * n + j] = num / diag;
+        if (edge) {
+          T diag = sm + sp + T(2) * isc;
+          if (i == 0) diag += sm;
+          if (i == n - 1) diag += sp;
+          if (j == 0) diag += isc;
+          if (j == n - 1) diag += isc;
+          u[i * n + j] = num / diag;
+        } else {
+          u[i * n + j] = num * r.rD[i];
+        }
       }
       __syncthreads();
     }
   }
 }
 
+// Pointers of level l inside the LDS block (levels K .. l-1 precede it).
+template <typename T>
+struct LLevel {
+  T* u;
+  T* f;
+  T* b;
+  LRows<T> r;
+};
+
+template <typename T>
+__device__ __forceinline__ LLevel<T> lds_level(unsigned char* smem, int K, int n0, int l) {
+  T* q = reinterpret_cast<T*>(smem);
+  for (int k = K; k < l; ++k) {
+    const int nn = n0 >> (k - K);
+    q += nn * nn * (k > K ? 3 : 2) + 5 * nn;
+  }
+  const int nn = n0 >> (l - K);
+  LLevel<T> v;
+  v.u = q;
+  v.f = q + nn * nn;
+  v.b = l > K ? q + 2 * nn * nn : nullptr;
+  T* rows = q + nn * nn * (l > K ? 3 : 2);
+  v.r = LRows<T>{rows, rows + nn, rows + 2 * nn, rows + 3 * nn, rows + 4 * nn};
+  return v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mg_lds(LdsArgs<T> a) {
   extern __shared__ unsigned char smem[];
   const int64_t patch = xcd_block();
-  const int K = a.lv.K, nl = a.lv.nlev;
-  // LDS: per level l >= K: u[n_l^2], f[n_l^2], ubar[n_l^2] (l > K)
-  T* base = reinterpret_cast<T*>(smem);
-  T* U[16];
-  T* Fv[16];
-  T* B[16];
-  {
-    T* q = base;
-    for (int l = K; l < nl; ++l) {
-      const int nn = a.lv.n0 >> (l - K);
-      U[l] = q; q += nn * nn;
-      Fv[l] = q; q += nn * nn;
-      if (l > K) { B[l] = q; q += nn * nn; }
+  const int K = a.lv.K, nl = a.lv.nlev, n0 = a.lv.n0;
+  for (int l = K; l < nl; ++l) {
+    const int nn = n0 >> (l - K);
+    const LLevel<T> L = lds_level<T>(smem, K, n0, l);
+    T* rows = const_cast<T*>(L.r.sm);
+    for (int i = threadIdx.x; i < nn; i += kBlock) {
+      const double* c = a.coef + a.lv.crow[l] + 4 * i;
+      rows[i] = T(c[0]);
+      rows[nn + i] = T(c[1]);
+      rows[2 * nn + i] = T(1.0 / c[2]);
+      rows[3 * nn + i] = T(c[3]);
+      rows[4 * nn + i] = T(1.0 / (c[0] + c[1] + 2.0 / c[2]));
     }
   }
-  const int n0 = a.lv.n0;
+  int lg0 = 0;
+  while ((1 << lg0) < n0) ++lg0;
   const size_t g0 = size_t(patch) * n0 * n0;
-  for (int idx = threadIdx.x; idx < n0 * n0; idx += blockDim.x) {
-    U[K][idx] = a.u_in ? a.u_in[g0 + idx] : T(0);
-    Fv[K][idx] = a.f_in[g0 + idx];
-  }
-  __syncthreads();
-  if (a.fas_source) {
-    const double* c = a.coef + a.lv.crow[K];
-    T tmp[16];
-    int cnt = 0;
-    for (int idx = threadIdx.x; idx < n0 * n0; idx += blockDim.x)
-      tmp[cnt++] = lap_g(U[K], n0, idx / n0, idx % n0, c + 4 * (idx / n0));
+  {
+    const LLevel<T> L = lds_level<T>(smem, K, n0, K);
+    for (int idx = threadIdx.x; idx < n0 * n0; idx += kBlock) {
+      L.u[idx] = a.u_in ? a.u_in[g0 + idx] : T(0);
+      L.f[idx] = a.f_in[g0 + idx];
+    }
     __syncthreads();
-    cnt = 0;
-    for (int idx = threadIdx.x; idx < n0 * n0; idx += blockDim.x) Fv[K][idx] += tmp[cnt++];
-    __syncthreads();
+    if (a.fas_source) {
+      // f = L ubar + rbar (reads u only, writes f only)
+      for (int idx = threadIdx.x; idx < n0 * n0; idx += kBlock)
+        L.f[idx] += lap_g(L.u, n0, idx >> lg0, idx & (n0 - 1), L.r);
+      __syncthreads();
+    }
   }
   // down
   for (int l = K; l < nl - 1; ++l) {
-    const int nn = n0 >> (l - K), nc = nn / 2;
-    const double* c = a.coef + a.lv.crow[l];
-    const double* cc = a.coef + a.lv.crow[l + 1];
-    lds_smooth(U[l], Fv[l], nn, c, a.nu1);
-    for (int idx = threadIdx.x; idx < nc * nc; idx += blockDim.x) {
-      const int I = idx / nc, J = idx % nc;
+    const int lg = lg0 - (l - K);
+    const int nn = 1 << lg, nc = nn >> 1;
+    const LLevel<T> L = lds_level<T>(smem, K, n0, l);
+    const LLevel<T> C = lds_level<T>(smem, K, n0, l + 1);
+    lds_smooth(L.u, L.f, nn, lg, L.r, a.nu1);
+    for (int idx = threadIdx.x; idx < nc * nc; idx += kBlock) {
+      const int I = idx >> (lg - 1), J = idx & (nc - 1);
       T r[4], uu[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int i = 2 * I + (k >> 1), j = 2 * J + (k & 1);
-        uu[k] = U[l][i * nn + j];
-        r[k] = Fv[l][i * nn + j] - lap_g(U[l], nn, i, j, c + 4 * i);
+        uu[k] = L.u[i * nn + j];
+        r[k] = L.f[i * nn + j] - lap_g(L.u, nn, i, j, L.r);
       }
-      const T a0 = T(c[4 * (2 * I) + 3]), a1 = T(c[4 * (2 * I + 1) + 3]);
+      const T a0 = L.r.A[2 * I], a1 = L.r.A[2 * I + 1];
       const T den = T(2) * (a0 + a1);
       const T ub = (a0 * (uu[0] + uu[1]) + a1 * (uu[2] + uu[3])) / den;
-      B[l + 1][idx] = ub;
-      U[l + 1][idx] = ub;
-      Fv[l + 1][idx] = (a0 * (r[0] + r[1]) + a1 * (r[2] + r[3])) / den;
+      C.b[idx] = ub;
+      C.u[idx] = ub;
+      C.f[idx] = (a0 * (r[0] + r[1]) + a1 * (r[2] + r[3])) / den;
     }
     __syncthreads();
     // f_H = L_H ubar + rbar
-    T tmp[4];
-    int cnt = 0;
-    for (int idx = threadIdx.x; idx < nc * nc; idx += blockDim.x)
-      tmp[cnt++] = lap_g(U[l + 1], nc, idx / nc, idx % nc, cc + 4 * (idx / nc));
-    __syncthreads();
-    cnt = 0;
-    for (int idx = threadIdx.x; idx < nc * nc; idx += blockDim.x) Fv[l + 1][idx] += tmp[cnt++];
+    for (int idx = threadIdx.x; idx < nc * nc; idx += kBlock)
+      C.f[idx] += lap_g(C.u, nc, idx >> (lg - 1), idx & (nc - 1), C.r);
     __syncthreads();
   }
   // coarsest: exact solve (float64)
   {
-    const int l = nl - 1;
+    const LLevel<T> L = lds_level<T>(smem, K, n0, nl - 1);
     double v = 0.0;
     if (threadIdx.x < 16) {
-      for (int k = 0; k < 16; ++k) v += a.cinv[threadIdx.x * 16 + k] * double(Fv[l][k]);
+      for (int k = 0; k < 16; ++k) v += a.cinv[threadIdx.x * 16 + k] * double(L.f[k]);
     }
     __syncthreads();
-    if (threadIdx.x < 16) U[l][threadIdx.x] = T(v);
+    if (threadIdx.x < 16) L.u[threadIdx.x] = T(v);
     __syncthreads();
   }
   // up
   for (int l = nl - 2; l >= K; --l) {
-    const int nn = n0 >> (l - K), nc = nn / 2;
-    const T* uc = U[l + 1];
-    const T* bc = B[l + 1];
-    auto ef = [&](int I, int J) { return uc[I * nc + J] - bc[I * nc + J]; };
-    for (int idx = threadIdx.x; idx < nn * nn; idx += blockDim.x)
-      U[l][idx] += prolong_cell<T>(idx / nn, idx % nn, nn, ef);
+    const int lg = lg0 - (l - K);
+    const int nn = 1 << lg, nc = nn >> 1;
+    const LLevel<T> L = lds_level<T>(smem, K, n0, l);
+    const LLevel<T> C = lds_level<T>(smem, K, n0, l + 1);
+    auto ef = [&](int I, int J) { return C.u[I * nc + J] - C.b[I * nc + J]; };
+    for (int idx = threadIdx.x; idx < nn * nn; idx += kBlock)
+      L.u[idx] += prolong_cell<T>(idx >> lg, idx & (nn - 1), nn, ef);
     __syncthreads();
-    lds_smooth(U[l], Fv[l], nn, a.coef + a.lv.crow[l], a.nu2);
+    lds_smooth(L.u, L.f, nn, lg, L.r, a.nu2);
   }
-  for (int idx = threadIdx.x; idx < n0 * n0; idx += blockDim.x) a.u_out[g0 + idx] = U[K][idx];
+  {
+    const LLevel<T> L = lds_level<T>(smem, K, n0, K);
+    for (int idx = threadIdx.x; idx < n0 * n0; idx += kBlock) a.u_out[g0 + idx] = L.u[idx];
+  }
 }
 
 // ------------------------------------------------------------ potential out
@@ -530,6 +684,36 @@ clm_status allow_lds(Plan* p, K kernel, size_t bytes) {
   return CLM_OK;
 }
 
+// Tile kernels are compiled per halo width: pre-smoothing needs 2 nu + 1
+// cells (nu sweeps plus the residual), post-smoothing 2 nu.
+template <typename T, int HH, bool PRE>
+clm_status launch_tile_hh(Plan* p, const TileArgs<T>& a, int64_t np, hipStream_t s) {
+  constexpr int RR = kTile + 2 * HH;
+  const dim3 grid(unsigned(np * a.ntile * a.ntile));
+  (void)RR;
+  if (PRE)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_pre<T, HH>), grid, dim3(kTileBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_post<T, HH>), grid, dim3(kTileBlock), 0, s, a);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+template <typename T, bool PRE>
+clm_status launch_tile(Plan* p, const TileArgs<T>& a, int64_t np, hipStream_t s) {
+  // halo: 2 nu + 1 (pre: sweeps plus the residual) or 2 nu (post), rounded
+  // up to even so that quads align with the coarse cells
+  const int hh = PRE ? 2 * a.nu + 2 : 2 * a.nu;
+  switch (hh) {
+    case 2: return launch_tile_hh<T, 2, PRE>(p, a, np, s);
+    case 4: return launch_tile_hh<T, 4, PRE>(p, a, np, s);
+    case 6: return launch_tile_hh<T, 6, PRE>(p, a, np, s);
+    case 8: return launch_tile_hh<T, 8, PRE>(p, a, np, s);
+    case 10: return launch_tile_hh<T, 10, PRE>(p, a, np, s);
+  }
+  return fail(p, CLM_EUNSUPPORTED, "sweep count outside 1..4");
+}
+
 template <typename T>
 clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
   const clm_plan_desc& d = p->d;
@@ -546,15 +730,16 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     a.delta = p->delta;
     a.rot = p->rot;
     a.coef = p->coef + p->lev[0].crow;
-    a.rs = hpx::Rings{p->ring_s, p->ringi_s, p->nring_s, d.nside_sht};
-    a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->nring_f, d.nside_fine};
+    a.rs = hpx::Rings{p->ring_s, p->ringi_s, p->ringx_s, p->nring_s, d.nside_sht};
+    a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->ringx_f, p->nring_f, d.nside_fine};
     a.psi_s = sl.psi_s;
     a.kappa = kappa;
     a.kappa_fp64 = kappa_fp64;
     a.red = p->red;
     a.u0 = sl.u0;
     a.fprime = p->fprime;
-    const size_t shm = size_t(a.tile + 2) * (a.tile + 2) * sizeof(double);
+    const size_t shm = (size_t(a.tile + 2) * (a.tile + 2) + 4 * size_t(a.tile + 2)) *
+                           sizeof(double) + size_t(a.tile) * a.tile * sizeof(T);
     if (allow_lds(p, k_patch_setup<T>, shm) != CLM_OK) return CLM_EHIP;
     {
       CLM_TIMED(p, s, "patch_setup");
@@ -580,7 +765,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
   size_t lds_elems = 0;
   for (int l = K; l < p->nlev; ++l) {
     const size_t nn = size_t(n >> l);
-    lds_elems += nn * nn * (l > K ? 3 : 2);
+    lds_elems += nn * nn * (l > K ? 3 : 2) + 5 * nn;
   }
   const size_t lds_bytes = lds_elems * sizeof(T);
   if (allow_lds(p, k_mg_lds<T>, lds_bytes) != CLM_OK) return CLM_EHIP;
@@ -588,22 +773,11 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
   auto tile_args = [&](int l, bool pre) {
     TileArgs<T> a{};
     a.n = n >> l;
-    a.tile = kTile;
     a.ntile = a.n / kTile;
     a.nu = pre ? d.nu_pre : d.nu_post;
-    a.hh = pre ? 2 * a.nu + 1 : 2 * a.nu;
     a.coef = p->coef + p->lev[l].crow;
     return a;
   };
-  auto pre_bytes = [&](const TileArgs<T>& a) {
-    const size_t RR = a.tile + 2 * a.hh;
-    return 2 * RR * RR * sizeof(T) + RR * sizeof(RowC<T>);
-  };
-  auto post_bytes = [&](const TileArgs<T>& a) {
-    const size_t RR = a.tile + 2 * a.hh, CR = RR / 2 + 3;
-    return (2 * RR * RR + CR * CR) * sizeof(T) + RR * sizeof(RowC<T>);
-  };
-
   for (int cyc = 0; cyc < d.mg_vcycles; ++cyc) {
     const bool first = cyc == 0;
     if (K == 0) {
@@ -636,14 +810,11 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       }
       a.ubar_out = static_cast<T*>(p->ubar[l + 1]);
       a.rbar_out = static_cast<T*>(p->rbar[l + 1]);
-      const size_t b = pre_bytes(a);
-      if (allow_lds(p, k_mg_pre<T>, b) != CLM_OK) return CLM_EHIP;
       {
         CLM_TIMED(p, s, l == 0 ? "mg_pre_l0" : "mg_pre_l1+");
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_pre<T>), dim3(np * a.ntile * a.ntile),
-                           dim3(kBlock), b, s, a);
+        const clm_status st = launch_tile<T, true>(p, a, np, s);
+        if (st != CLM_OK) return st;
       }
-      CLM_LAUNCH_CHECK();
     }
     // the LDS-resident levels
     la.u_in = static_cast<T*>(p->ubar[K]);
@@ -669,14 +840,11 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
         a.f_in = static_cast<T*>(p->flev[l]);
         a.u_out = static_cast<T*>(p->ulev2[l]);
       }
-      const size_t b = post_bytes(a);
-      if (allow_lds(p, k_mg_post<T>, b) != CLM_OK) return CLM_EHIP;
       {
         CLM_TIMED(p, s, l == 0 ? "mg_post_l0" : "mg_post_l1+");
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_post<T>), dim3(np * a.ntile * a.ntile),
-                           dim3(kBlock), b, s, a);
+        const clm_status st = launch_tile<T, false>(p, a, np, s);
+        if (st != CLM_OK) return st;
       }
-      CLM_LAUNCH_CHECK();
     }
   }
   return CLM_OK;

@@ -30,7 +30,8 @@ Plan::~Plan() {
   for (auto& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto e : pool) (void)hipEventDestroy(e);
   auto f = [](void* q) { if (q) (void)hipFree(q); };
-  f(ring_s); f(ringi_s); f(ring_f); f(ringi_f); f(lam_mant); f(lam_scale);
+  f(ring_s); f(ringi_s); f(ringx_s); f(ring_f); f(ringi_f); f(ringx_f); f(lam_mant);
+  f(lam_scale);
   f(r2n_s); f(r2n_f); f(rot); f(coef); f(cinv); f(kap_s); f(F); f(G); f(red);
   f(deriv); f(fprime); f(dutmp); f(status_dev);
   for (auto* q : ubar) f(q);
@@ -46,7 +47,7 @@ namespace {
 bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Host ring tables of a HEALPix grid (rings 1..4N-1 stored 0-based).
-void host_rings(int N, std::vector<double>& rt, std::vector<int>& ri) {
+void host_rings(int N, std::vector<double>& rt, std::vector<int>& ri, std::vector<double>& rx) {
   const int nr = 4 * N - 1;
   rt.assign(4 * nr, 0.0);
   ri.assign(2 * nr, 0);
@@ -83,6 +84,13 @@ void host_rings(int N, std::vector<double>& rt, std::vector<int>& ri) {
     ri[2 * q + 0] = int(n);
     ri[2 * q + 1] = int(first);
   }
+  // interpolation helpers: n/(2 pi) per ring, reciprocal theta gaps
+  rx.assign(2 * (nr + 1), 0.0);
+  for (int q = 0; q < nr; ++q) {
+    rx[2 * q] = double(ri[2 * q]) / (2.0 * pi);
+    rx[2 * q + 1] = 1.0 / (rt[4 * q + 2] - (q ? rt[4 * (q - 1) + 2] : 0.0));
+  }
+  rx[2 * nr + 1] = 1.0 / (pi - rt[4 * (nr - 1) + 2]);
 }
 
 // lambda_mm(theta_q) for the north rings, by the product recursion
@@ -180,18 +188,22 @@ bool invert(std::vector<double>& a, int n) {
 
 clm_status build_tables(Plan* p) {
   const clm_plan_desc& d = p->d;
-  std::vector<double> rt;
+  std::vector<double> rt, rx;
   std::vector<int> ri;
-  host_rings(d.nside_sht, rt, ri);
+  host_rings(d.nside_sht, rt, ri, rx);
   CLM_TRY(alloc(p, &p->ring_s, rt.size()));
   CLM_TRY(alloc(p, &p->ringi_s, ri.size()));
+  CLM_TRY(alloc(p, &p->ringx_s, rx.size()));
   CLM_HIP(hipMemcpy(p->ring_s, rt.data(), rt.size() * 8, hipMemcpyHostToDevice));
   CLM_HIP(hipMemcpy(p->ringi_s, ri.data(), ri.size() * 4, hipMemcpyHostToDevice));
-  host_rings(d.nside_fine, rt, ri);
+  CLM_HIP(hipMemcpy(p->ringx_s, rx.data(), rx.size() * 8, hipMemcpyHostToDevice));
+  host_rings(d.nside_fine, rt, ri, rx);
   CLM_TRY(alloc(p, &p->ring_f, rt.size()));
   CLM_TRY(alloc(p, &p->ringi_f, ri.size()));
+  CLM_TRY(alloc(p, &p->ringx_f, rx.size()));
   CLM_HIP(hipMemcpy(p->ring_f, rt.data(), rt.size() * 8, hipMemcpyHostToDevice));
   CLM_HIP(hipMemcpy(p->ringi_f, ri.data(), ri.size() * 4, hipMemcpyHostToDevice));
+  CLM_HIP(hipMemcpy(p->ringx_f, rx.data(), rx.size() * 8, hipMemcpyHostToDevice));
 
   // Legendre starting values on the north rings of the SHT grid
   CLM_TRY(alloc(p, &p->lam_mant, size_t(d.lmax + 1) * p->H));

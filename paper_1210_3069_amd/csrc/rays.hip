@@ -205,7 +205,7 @@ __global__ void k_galaxies(GalArgs a) {
                    (r_of(cg, a.K) * r_of(a.chi_k - a.chi_km1, a.K));
   int64_t pix[4];
   double wt[4];
-  hpx::interp_weights(a.rf, a.th[i], a.ph[i], pix, wt);
+  hpx::interp_weights(a.rf, a.th[i], cos(a.th[i]), a.ph[i], pix, wt);
   double Ai[4] = {0, 0, 0, 0}, Api[4] = {0, 0, 0, 0};
   for (int q = 0; q < 4; ++q) {
     const int64_t r = a.r2n_f[pix[q]];
@@ -270,7 +270,7 @@ clm_status galaxies_shell(Plan* p, const double* chi, int nchi, int k, double K,
   const int N = nchi - 1;
   auto edge = [&](int e) { return e == 0 ? 0.0 : 0.5 * (chi[e - 1] + chi[e]); };
   GalArgs a;
-  a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->nring_f, p->d.nside_fine};
+  a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->ringx_f, p->nring_f, p->d.nside_fine};
   a.r2n_f = p->r2n_f;
   a.nray = r->n;
   a.A = r->A;

@@ -90,23 +90,77 @@ __device__ __forceinline__ void quarter_table(double* sq, int n) {
   for (int r = threadIdx.x; r <= Q; r += blockDim.x) sq[r] = sinpi(2.0 * double(r) / double(n));
 }
 
+// In-place radix-2 FFT of a power-of-two length n (log2n) on interleaved
+// complex LDS data already in bit-reversed order; sign -1: forward
+// (e^{-2 pi i jk/n}), +1: inverse without scaling.
+__device__ __forceinline__ void fft_pow2(double* x, int n, const double* sq, int sign) {
+  const int Q = n / 4;
+  for (int len = 2; len <= n; len <<= 1) {
+    const int half = len >> 1, step = n / len;
+    for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
+      const int pos = b & (half - 1);
+      const int i = (b - pos) * 2 + pos, j = i + half;
+      double c, s;
+      twiddle(sq, Q, pos * step, c, s);
+      s *= sign;
+      const double xr = x[2 * j], xi = x[2 * j + 1];
+      const double tr = c * xr - s * xi, ti = c * xi + s * xr;
+      const double yr = x[2 * i], yi = x[2 * i + 1];
+      x[2 * j] = yr - tr;
+      x[2 * j + 1] = yi - ti;
+      x[2 * i] = yr + tr;
+      x[2 * i + 1] = yi + ti;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ bool is_pow2(int n) { return (n & (n - 1)) == 0; }
+
+__device__ __forceinline__ int bitrev(int j, int log2n) {
+  return int(__brev(unsigned(j)) >> (32 - log2n));
+}
+
 // F_m(q) = e^{-i m phi0_q} sum_j f_{q,j} e^{-2 pi i (m mod n) j / n}, m = 0..lmax.
-// Direct DFT of the min(n, lmax+1) needed bins; rings shorter than lmax + 1
-// fold the higher orders onto their bins (HEALPix aliasing).
+// Power-of-two rings: radix-2 FFT in LDS.  Other rings: direct DFT of the
+// min(n, lmax+1) needed bins.  Rings shorter than lmax + 1 fold the higher
+// orders onto their bins (HEALPix aliasing).
 __global__ void k_ring_forward(const double* map, const double* rt, const int* ri, int lmax,
                                double* F) {
   extern __shared__ double sm[];
   const int q = blockIdx.x;
   const int n = ri[2 * q], Q = n / 4;
   const int64_t first = ri[2 * q + 1];
+  const double phi0 = rt[4 * q + 3];
+  double* out = F + size_t(q) * (lmax + 1) * 2;
+  if (is_pow2(n)) {
+    double* sq = sm;             // [n/4 + 1]
+    double* X = sm + Q + 1;      // [n][2]
+    const int lg = __ffs(n) - 1;
+    quarter_table(sq, n);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const int r = bitrev(j, lg);
+      X[2 * r] = map[first + j];
+      X[2 * r + 1] = 0.0;
+    }
+    __syncthreads();
+    fft_pow2(X, n, sq, -1);
+    for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
+      const int k = m & (n - 1);
+      double s, c;
+      sincos(double(m) * phi0, &s, &c);
+      const double xr = X[2 * k], xi = X[2 * k + 1];
+      out[2 * m] = c * xr + s * xi;       // (c - i s)(xr + i xi)
+      out[2 * m + 1] = c * xi - s * xr;
+    }
+    return;
+  }
   double* f = sm;              // [n]
   double* sq = sm + n;         // [n/4 + 1]
   double* X = sq + Q + 1;      // [n][2] when n <= lmax
   for (int j = threadIdx.x; j < n; j += blockDim.x) f[j] = map[first + j];
   quarter_table(sq, n);
   __syncthreads();
-  const double phi0 = rt[4 * q + 3];
-  double* out = F + size_t(q) * (lmax + 1) * 2;
   const bool alias = n <= lmax;
   const int nb = alias ? n : lmax + 1;
   for (int k = threadIdx.x; k < nb; k += blockDim.x) {
@@ -151,10 +205,12 @@ __global__ void k_ring_inverse(const double* G, int nring, const double* rt, con
   const int q = blockIdx.x;
   const int n = ri[2 * q], Q = n / 4;
   const int64_t first = ri[2 * q + 1];
-  const int nb = n <= lmax ? n : lmax + 1;
+  const bool p2 = is_pow2(n);
+  const int nb = p2 ? n : (n <= lmax ? n : lmax + 1);
   double* sq = sm;             // [n/4 + 1]
   double* B = sm + Q + 1;      // [nb][2]
   const double phi0 = rt[4 * q + 3];
+  const int lg = __ffs(n) - 1;
   quarter_table(sq, n);
   for (int fld = 0; fld < nf; ++fld) {
     const double* g = G + (size_t(fld) * nring + q) * (lmax + 1) * 2;
@@ -169,10 +225,17 @@ __global__ void k_ring_inverse(const double* G, int nring, const double* rt, con
         br += cm * (c * gr - s * gi);
         bi += cm * (c * gi + s * gr);
       }
-      B[2 * k] = br;
-      B[2 * k + 1] = bi;
+      const int kk = p2 ? bitrev(k, lg) : k;
+      B[2 * kk] = br;
+      B[2 * kk + 1] = bi;
     }
     __syncthreads();
+    if (p2) {
+      fft_pow2(B, n, sq, +1);
+      for (int j = threadIdx.x; j < n; j += blockDim.x)
+        out[size_t(fld) * npix + first + j] = B[2 * j];
+      continue;
+    }
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
       double acc = 0.0;
       int t = 0;
@@ -456,20 +519,26 @@ void launch_analysis(Plan* p, hipStream_t s, double* alm) {
 }
 
 // LDS of the ring kernels for the longest ring (4 nside) and lmax.
+// (power-of-two rings: FFT buffer of n complex; others: direct sums)
 size_t ring_fwd_lds(int nside, int lmax) {
   size_t best = 0;
-  for (int n : {4 * nside, std::min(4 * nside, lmax - (lmax % 4))}) {
-    if (n < 4) continue;
-    size_t b = size_t(n) + n / 4 + 1 + (n <= lmax ? 2 * size_t(n) : 0);
+  for (int n = 4; n <= 4 * nside; n += 4) {
+    const bool p2 = (n & (n - 1)) == 0;
+    const size_t b = p2 ? size_t(n) / 4 + 1 + 2 * size_t(n)
+                        : size_t(n) + n / 4 + 1 + (n <= lmax ? 2 * size_t(n) : 0);
     best = std::max(best, b);
   }
   return best * sizeof(double);
 }
 
 size_t ring_inv_lds(int nside, int lmax) {
-  const size_t n = 4 * size_t(nside);
-  const size_t nb = n <= size_t(lmax) ? n : size_t(lmax) + 1;
-  return (n / 4 + 1 + 2 * nb) * sizeof(double);
+  size_t best = 0;
+  for (int n = 4; n <= 4 * nside; n += 4) {
+    const bool p2 = (n & (n - 1)) == 0;
+    const size_t nb = p2 ? size_t(n) : (n <= lmax ? size_t(n) : size_t(lmax) + 1);
+    best = std::max(best, size_t(n) / 4 + 1 + 2 * nb);
+  }
+  return best * sizeof(double);
 }
 
 clm_status ring_forward(Plan* p, const double* map, hipStream_t s) {
