@@ -144,59 +144,224 @@ struct Rings {
   int N;
 };
 
-// Four RING pixels and weights for bilinear interpolation at (theta, phi):
-// rings bracketing theta, pixels bracketing phi in each, linear weights;
-// above the first ring (below the last) the pole value is the mean of that
-// ring's four pixels.
-__device__ __forceinline__ void interp_weights(const Rings& R, double theta, double z,
-                                               double phi, int64_t pix[4], double w[4]) {
-  const double twopi = 6.283185307179586476925286766559;
-  const int N = R.N;
-  // first guess from the ring formulas (z = cos theta), then exact
-  // bracketing on theta
-  double fr;
-  if (z > 2.0 / 3.0)
-    fr = N * sqrt(3.0 * (1.0 - z));
-  else if (z < -2.0 / 3.0)
-    fr = 4.0 * N - N * sqrt(3.0 * (1.0 + z));
-  else
-    fr = N * (2.0 - 1.5 * z);
-  int g = int(floor(fr)) - 1;  // 0-based candidate
-  if (g < -1) g = -1;
-  if (g > R.nring - 1) g = R.nring - 1;
-  while (g + 1 < R.nring && R.rt[4 * (g + 1) + 2] <= theta) ++g;
-  while (g >= 0 && R.rt[4 * g + 2] > theta) --g;
+// atan(u), float64, for |u| <= 0.07: odd Taylor series to u^15 (remainder
+// below 2e-22 relative).
+__device__ __forceinline__ double atan_series(double u) {
+  const double u2 = u * u;
+  double s = -1.0 / 15.0;
+  s = fma(s, u2, 1.0 / 13.0);
+  s = fma(s, u2, -1.0 / 11.0);
+  s = fma(s, u2, 1.0 / 9.0);
+  s = fma(s, u2, -1.0 / 7.0);
+  s = fma(s, u2, 1.0 / 5.0);
+  s = fma(s, u2, -1.0 / 3.0);
+  return fma(s * u2, u, u);
+}
 
-  auto pair = [&](int q, int64_t& a, int64_t& b, double& wp) {
-    const int n = R.ri[2 * q];
-    const int64_t first = R.ri[2 * q + 1];
-    const double t = (phi - R.rt[4 * q + 3]) * R.rx[2 * q];
+// atan(k / 8), k = 0 .. 8, rounded to float64.
+static __constant__ double kAtanEighth[9] = {
+    0.0,
+    0.12435499454676144,
+    0.24497866312686414,
+    0.35877067027057225,
+    0.4636476090008061,
+    0.5585993153435624,
+    0.6435011087932844,
+    0.7188299996216245,
+    0.7853981633974483};
+
+// num / den, float64, for den > 0 of moderate size: hardware reciprocal,
+// two Newton steps and a residual correction of the quotient.
+__device__ __forceinline__ double div_pos(double num, double den) {
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  const double q = num * r;
+  return fma(r, fma(-den, q, num), q);
+}
+
+// atan2(y, x), float64, branch-free: reduce to u = min/max of |x|, |y| in
+// [0, 1]; with c = k/8 the nearest eighth, atan u = atan c + atan r,
+// r = (u - c) / (1 + u c), |r| <= 1/16; then undo the octant.  (0, 0) -> 0.
+__device__ __forceinline__ double atan2_r(double y, double x) {
+  const double ax = fabs(x), ay = fabs(y);
+  const double mx = fmax(ax, ay), mn = fmin(ax, ay);
+  const float ef = mx > 0.0 ? float(mn) / float(mx) : 0.0f;
+  const int k = min(int(fmaf(8.0f, ef, 0.5f)), 8);
+  const double c = 0.125 * k;
+  const double num = fma(-c, mx, mn), den = fma(c, mn, mx);
+  const double r = den > 0.0 ? div_pos(num, den) : 0.0;
+  double a = kAtanEighth[k] + atan_series(r);
+  if (ay > ax) a = 1.5707963267948966 - a;
+  if (x < 0.0) a = 3.141592653589793 - a;
+  return y < 0.0 ? -a : a;
+}
+
+// asin(s), float64: Taylor series (2k)!/(4^k (k!)^2 (2k+1)) s^(2k+1) to
+// s^13 for |s| < 0.05 (remainder < 1e-21), atan2(s, sqrt(1 - s^2))
+// otherwise.
+__device__ __forceinline__ double asin_small(double s) {
+  if (fabs(s) >= 0.05) return atan2_r(s, sqrt((1.0 - s) * (1.0 + s)));
+  const double s2 = s * s;
+  double p = 231.0 / 13312.0;
+  p = fma(p, s2, 63.0 / 2816.0);
+  p = fma(p, s2, 35.0 / 1152.0);
+  p = fma(p, s2, 5.0 / 112.0);
+  p = fma(p, s2, 3.0 / 40.0);
+  p = fma(p, s2, 1.0 / 6.0);
+  return fma(p * s2, s, s);
+}
+
+// Azimuth of (vx, vy) measured from a reference azimuth with cosine c and
+// sine s, in [-pi, pi]: the series atan of the quotient of the rotated
+// components when the offset is below 0.05 rad, atan2_r otherwise.
+__device__ __forceinline__ double dphi_of(double vx, double vy, double c, double s) {
+  const double cs = vx * c + vy * s, sn = vy * c - vx * s;
+  if (cs > 20.0 * fabs(sn)) return atan_series(div_pos(sn, cs));
+  return atan2_r(sn, cs);
+}
+
+// Ring-table accessors used by the interpolation.  A point is given by
+// z = cos theta, rho = sin theta and its azimuth as an offset dphi from the
+// table's reference azimuth phi_ref; t(q, dphi) is the point's coordinate
+// along ring q in pixel units, (phi - phi0_q) n_q / (2 pi).
+struct GlobalRingTab {
+  Rings R;
+  double phi_ref;
+  __device__ __forceinline__ int nring() const { return R.nring; }
+  __device__ __forceinline__ int N() const { return R.N; }
+  __device__ __forceinline__ double z(int q) const { return R.rt[4 * q]; }
+  __device__ __forceinline__ double s(int q) const { return R.rt[4 * q + 1]; }
+  __device__ __forceinline__ double t(int q, double dphi) const {
+    return (phi_ref - R.rt[4 * q + 3] + dphi) * R.rx[2 * q];
+  }
+  __device__ __forceinline__ double igap(int q) const { return R.rx[2 * q + 1]; }
+  __device__ __forceinline__ int n(int q) const { return R.ri[2 * q]; }
+  __device__ __forceinline__ int first(int q) const { return R.ri[2 * q + 1]; }
+  // rings held, and the range of the bracketing index (ring g and g + 1,
+  // or the pole gap, must be held)
+  __device__ __forceinline__ int qmin() const { return 0; }
+  __device__ __forceinline__ int qmax() const { return R.nring - 1; }
+  __device__ __forceinline__ int lo() const { return -1; }
+  __device__ __forceinline__ int hi() const { return R.nring - 1; }
+};
+
+// A contiguous range of rings base .. top copied to LDS (ring q at slot
+// q - base) for one reference azimuth.
+struct LdsRingTab {
+  double* zq;     // [cap] z
+  double* sq;     // [cap] sin theta
+  double* tq;     // [cap] (phi_ref - phi0) n / (2 pi)
+  double* kq;     // [cap] n / (2 pi)
+  double* gq;     // [cap + 1] 1 / theta gap above ring (last: south pole gap)
+  int* nq;        // [cap]
+  int* fq;        // [cap]
+  int base, top, nr, NN;
+  __device__ __forceinline__ int nring() const { return nr; }
+  __device__ __forceinline__ int N() const { return NN; }
+  __device__ __forceinline__ double z(int q) const { return zq[q - base]; }
+  __device__ __forceinline__ double s(int q) const { return sq[q - base]; }
+  __device__ __forceinline__ double t(int q, double dphi) const {
+    return fma(dphi, kq[q - base], tq[q - base]);
+  }
+  __device__ __forceinline__ double igap(int q) const { return gq[q - base]; }
+  __device__ __forceinline__ int n(int q) const { return nq[q - base]; }
+  __device__ __forceinline__ int first(int q) const { return fq[q - base]; }
+  __device__ __forceinline__ int qmin() const { return base; }
+  __device__ __forceinline__ int qmax() const { return top; }
+  __device__ __forceinline__ int lo() const { return base > 0 ? base : -1; }
+  __device__ __forceinline__ int hi() const { return top == nr - 1 ? top : top - 1; }
+  // all threads of the block: copy rings [b, t] of R (gap entries b .. t+1)
+  __device__ void fill(const Rings& R, int b, int t, double phi_ref) {
+    base = b; top = t; nr = R.nring; NN = R.N;
+    for (int k = threadIdx.x; k <= t - b + 1; k += blockDim.x) {
+      const int q = b + k;
+      if (q <= t) {
+        zq[k] = R.rt[4 * q]; sq[k] = R.rt[4 * q + 1];
+        kq[k] = R.rx[2 * q];
+        tq[k] = (phi_ref - R.rt[4 * q + 3]) * R.rx[2 * q];
+        nq[k] = R.ri[2 * q]; fq[k] = R.ri[2 * q + 1];
+      }
+      if (q <= R.nring) gq[k] = R.rx[2 * q + 1];
+    }
+  }
+};
+
+// Index of the last ring with z_q >= z (-1 above the first ring), kept in
+// [lo, hi] of the table.  The ring formulas of the HEALPix construction
+// (Sec. 2) give the continuous ring coordinate (ring i at i); its float32
+// value is off by less than one ring, and one exact comparison each way
+// settles the index.
+template <typename Tab>
+__device__ __forceinline__ int ring_above(const Tab& R, double z) {
+  const float N = float(R.N());
+  const float za = float(fabs(z));
+  float fr;
+  if (za > 2.0f / 3.0f) {
+    const float fp = N * sqrtf(fmaxf(float(3.0 * (1.0 - fabs(z))), 0.0f));
+    fr = z > 0 ? fp : 4.0f * N - fp;
+  } else {
+    fr = N * (2.0f - 1.5f * float(z));
+  }
+  const int lo = R.lo(), hi = R.hi();
+  int c = int(floorf(fr)) - 1;
+  c = min(max(c, lo), hi);
+  const double zb = R.z(min(c + 1, R.qmax()));  // ring below the guess
+  const double za0 = R.z(max(c, R.qmin()));     // the guess
+  if (c < hi && zb >= z)
+    ++c;
+  else if (c > lo && za0 < z)
+    --c;
+  return c;
+}
+
+// Four RING pixels and weights for bilinear interpolation at the point
+// (z, rho, dphi): rings bracketing theta, pixels bracketing phi in each,
+// linear weights; above the first ring (below the last) the pole value is
+// the mean of that ring's four pixels.  The theta offset from the upper ring
+// is asin(rho z_q - z sin theta_q).
+template <typename Tab>
+__device__ __forceinline__ void interp_weights_t(const Tab& R, double z, double rho, double dphi,
+                                                 int pix[4], double w[4]) {
+  const int g = ring_above(R, z);
+  const int nring = R.nring();
+
+  auto pair = [&](int q, int& a, int& b, double& wp) {
+    const int n = R.n(q);
+    const int first = R.first(q);
+    const double t = R.t(q, dphi);
     const double fl = floor(t);
     wp = t - fl;
     int i1 = int(fl);
-    while (i1 < 0) i1 += n;
-    while (i1 >= n) i1 -= n;
+    i1 += i1 < 0 ? n : 0;
+    i1 -= i1 >= n ? n : 0;
+    i1 = min(max(i1, 0), n - 1);  // azimuths outside (-pi, 3 pi) only
     const int i2 = i1 + 1 == n ? 0 : i1 + 1;
     a = first + i1;
     b = first + i2;
   };
+  // theta - theta_q for the ring above (theta_{-1} = 0 at the north pole)
+  auto dtheta = [&](int q) {
+    const double z1 = q >= 0 ? R.z(q) : 1.0, s1 = q >= 0 ? R.s(q) : 0.0;
+    return asin_small(fma(rho, z1, -z * s1));
+  };
 
-  if (g >= 0 && g < R.nring - 1) {
-    int64_t a1, a2, b1, b2;
+  if (g >= 0 && g < nring - 1) {
+    int a1, a2, b1, b2;
     double wa, wb;
     pair(g, a1, a2, wa);
     pair(g + 1, b1, b2, wb);
-    const double wt = (theta - R.rt[4 * g + 2]) * R.rx[2 * (g + 1) + 1];
+    const double wt = dtheta(g) * R.igap(g + 1);
     pix[0] = a1; pix[1] = a2; pix[2] = b1; pix[3] = b2;
     w[0] = (1 - wt) * (1 - wa);
     w[1] = (1 - wt) * wa;
     w[2] = wt * (1 - wb);
     w[3] = wt * wb;
   } else if (g < 0) {
-    int64_t b1, b2;
+    int b1, b2;
     double wb;
     pair(0, b1, b2, wb);
-    const double wt = theta * R.rx[1];
+    const double wt = dtheta(-1) * R.igap(0);
     const double fac = (1.0 - wt) * 0.25;
     pix[0] = b1; pix[1] = b2; pix[2] = (b1 + 2) & 3; pix[3] = (b2 + 2) & 3;
     w[0] = wt * (1 - wb) + fac;
@@ -204,12 +369,12 @@ __device__ __forceinline__ void interp_weights(const Rings& R, double theta, dou
     w[2] = fac;
     w[3] = fac;
   } else {
-    const int q = R.nring - 1;
-    int64_t a1, a2;
+    const int q = nring - 1;
+    int a1, a2;
     double wa;
     pair(q, a1, a2, wa);
-    const double wt = (theta - R.rt[4 * q + 2]) * R.rx[2 * R.nring + 1];
-    const int64_t base = R.ri[2 * q + 1];
+    const double wt = dtheta(q) * R.igap(nring);
+    const int base = R.first(q);
     const double fac = wt * 0.25;
     pix[0] = a1; pix[1] = a2;
     pix[2] = base + ((a1 - base + 2) & 3);
@@ -221,14 +386,26 @@ __device__ __forceinline__ void interp_weights(const Rings& R, double theta, dou
   }
 }
 
-template <typename T>
-__device__ __forceinline__ double interp(const Rings& R, const T* map, double theta, double z,
-                                         double phi) {
-  int64_t pix[4];
+// Interpolation at (z, rho, phi) from the global tables, phi in [0, 2 pi).
+__device__ __forceinline__ void interp_weights(const Rings& R, double z, double rho, double phi,
+                                               int pix[4], double w[4]) {
+  interp_weights_t(GlobalRingTab{R, phi}, z, rho, 0.0, pix, w);
+}
+
+template <typename T, typename Tab>
+__device__ __forceinline__ double interp_t(const Tab& R, const T* map, double z, double rho,
+                                           double dphi) {
+  int pix[4];
   double w[4];
-  interp_weights(R, theta, z, phi, pix, w);
+  interp_weights_t(R, z, rho, dphi, pix, w);
   return w[0] * double(map[pix[0]]) + w[1] * double(map[pix[1]]) +
          w[2] * double(map[pix[2]]) + w[3] * double(map[pix[3]]);
+}
+
+template <typename T>
+__device__ __forceinline__ double interp(const Rings& R, const T* map, double z, double rho,
+                                         double phi) {
+  return interp_t(GlobalRingTab{R, phi}, map, z, rho, 0.0);
 }
 
 }  // namespace hpx

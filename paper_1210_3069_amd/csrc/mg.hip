@@ -57,37 +57,157 @@ struct SetupArgs {
 };
 
 // Global direction of the patch point with sin/cos of theta' and phi':
-// v = R^T (sin th' cos ph', sin th' sin ph', cos th'); returns theta, z = cos
-// theta and phi in [0, 2 pi).
+// v = R^T (sin th' cos ph', sin th' sin ph', cos th'); returns z = cos theta,
+// rho = sin theta and the azimuth offset from a reference azimuth with
+// cosine/sine (cr, sr).
 __device__ __forceinline__ void patch_dir(const double* R, double st, double ct, double sp,
-                                          double cp, double& th, double& z, double& ph) {
+                                          double cp, double cr, double sr, double& z,
+                                          double& rho, double& dph) {
   const double x = st * cp, y = st * sp;
   const double vx = R[0] * x + R[3] * y + R[6] * ct;
   const double vy = R[1] * x + R[4] * y + R[7] * ct;
   z = R[2] * x + R[5] * y + R[8] * ct;
-  th = atan2(sqrt(vx * vx + vy * vy), z);
-  ph = atan2(vy, vx);
-  if (ph < 0) ph += 2.0 * kPi;
+  rho = sqrt(vx * vx + vy * vy);
+  dph = hpx::dphi_of(vx, vy, cr, sr);
 }
 
-// One block per 64 x 64 tile (or the whole patch if smaller).  Pass 1 visits
-// every cell of the tile plus one ring once: direction, u0 and (interior
-// cells) the source, with sin/cos of theta' and phi' tabulated per row and
-// column; pass 2 fills the patch ghosts from the face values; pass 3 forms
-// f' = f - L u0.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_patch_setup(SetupArgs a) {
-  extern __shared__ double shu[];
+// Rings of the two grids a setup block may copy to LDS (the tile's z range
+// plus one cell of slack; blocks whose range is wider read the global
+// tables).
+constexpr int kRingCapF = 256, kRingCapS = 64;
+constexpr int kSetupBlock = 512;
+
+template <int CAP>
+struct RingStore {
+  double z[CAP], s[CAP], t[CAP], k[CAP], g[CAP + 1];
+  int n[CAP], f[CAP];
+  __device__ hpx::LdsRingTab tab() {
+    hpx::LdsRingTab r;
+    r.zq = z; r.sq = s; r.tq = t; r.kq = k; r.gq = g; r.nq = n; r.fq = f;
+    return r;
+  }
+};
+
+// Reference azimuth of a setup block (the region centre's).
+struct PhiRef {
+  double phi, c, s;
+};
+
+// Pass 1 visits every cell of the tile plus one ring once: direction, u0 and
+// (interior cells) the source f, written to the f' array; pass 2 fills the
+// patch ghosts from the face values; pass 3 forms f' = f - L u0 (the thread
+// that wrote f reads it back).
+template <typename T, int TILE, typename TS, typename TF>
+__device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, double* shu,
+                             const double* trig, const double* R, const PhiRef& pr,
+                             int64_t patch, int i0, int j0) {
+  constexpr int RR = TILE + 2;
+  const int n = a.n;
+  const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
+  const double mean = a.red[1023];
+  const size_t G = size_t(n + 2);
+  double* u0 = a.u0 + size_t(patch) * G * G;
+  T* fp = static_cast<T*>(a.fprime) + size_t(patch) * n * n;
+  for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
+    const int li = idx / RR, lj = idx % RR;
+    const int gi = i0 + li, gj = j0 + lj;
+    double v = 0.0;
+    if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
+      double z, rho, dph;
+      patch_dir(R, trig[4 * li], trig[4 * li + 1], trig[4 * lj + 2], trig[4 * lj + 3], pr.c,
+                pr.s, z, rho, dph);
+      int ps[4];
+      double ws[4];
+      hpx::interp_weights_t(rs, z, rho, dph, ps, ws);
+      if (li >= 1 && li <= TILE && lj >= 1 && lj <= TILE) {
+        int pf[4];
+        double wf[4];
+        hpx::interp_weights_t(rf, z, rho, dph, pf, wf);
+        double k4[4];
+        if (a.kappa_fp64) {
+          const double* km = static_cast<const double*>(a.kappa);
+          for (int c = 0; c < 4; ++c) k4[c] = km[pf[c]];
+        } else {
+          const float* km = static_cast<const float*>(a.kappa);
+          for (int c = 0; c < 4; ++c) k4[c] = km[pf[c]];
+        }
+        v = ws[0] * a.psi_s[ps[0]] + ws[1] * a.psi_s[ps[1]] + ws[2] * a.psi_s[ps[2]] +
+            ws[3] * a.psi_s[ps[3]];
+        const double kv = wf[0] * k4[0] + wf[1] * k4[1] + wf[2] * k4[2] + wf[3] * k4[3];
+        fp[size_t(gi) * n + gj] = T(2.0 * (kv - mean));
+      } else {
+        v = ws[0] * a.psi_s[ps[0]] + ws[1] * a.psi_s[ps[1]] + ws[2] * a.psi_s[ps[2]] +
+            ws[3] * a.psi_s[ps[3]];
+      }
+    }
+    shu[idx] = v;
+  }
+  __syncthreads();
+  // ghost cells of the region (on the patch boundary); only blocks at the
+  // patch faces have any
+  if (i0 == -1 || j0 == -1 || i0 + TILE + 1 == n || j0 + TILE + 1 == n) {
+    for (int idx = threadIdx.x; idx < 4 * RR; idx += blockDim.x) {
+      // the region's outer ring: rows 0 and RR-1, then columns 0 and RR-1
+      const int side = idx / RR, r = idx % RR;
+      const int li = side == 0 ? 0 : side == 1 ? RR - 1 : r;
+      const int lj = side == 2 ? 0 : side == 3 ? RR - 1 : r;
+      if (side >= 2 && (r == 0 || r == RR - 1)) continue;  // corners once
+      const int gi = i0 + li, gj = j0 + lj;
+      const bool gI = gi == -1 || gi == n, gJ = gj == -1 || gj == n;
+      if (!(gI || gJ)) continue;
+      double thp, php;
+      int ai = li, aj = lj;  // adjacent interior cell
+      if (gI) { thp = gi < 0 ? th0 : th0 + a.L; ai = gi < 0 ? li + 1 : li - 1; }
+      else    { thp = th0 + (gi + 0.5) * a.delta; }
+      if (gJ) { php = gj < 0 ? ph0 : ph0 + a.L; aj = gj < 0 ? lj + 1 : lj - 1; }
+      else    { php = ph0 + (gj + 0.5) * a.delta; }
+      double st, ct, sp, cp, z, rho, dph;
+      sincos(thp, &st, &ct);
+      sincos(php, &sp, &cp);
+      patch_dir(R, st, ct, sp, cp, pr.c, pr.s, z, rho, dph);
+      const double b = hpx::interp_t(rs, a.psi_s, z, rho, dph);
+      shu[li * RR + lj] = 2.0 * b - shu[ai * RR + aj];
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
+    const int li = idx / RR, lj = idx % RR;
+    const int gi = i0 + li, gj = j0 + lj;
+    // write u0: the tile's cells, plus the patch ghosts beside this tile
+    const bool own_i = (li >= 1 && li <= TILE) || (gi == -1) || (gi == n);
+    const bool own_j = (lj >= 1 && lj <= TILE) || (gj == -1) || (gj == n);
+    if (own_i && own_j) u0[size_t(gi + 1) * G + (gj + 1)] = shu[idx];
+    if (!(li >= 1 && li <= TILE && lj >= 1 && lj <= TILE)) continue;
+    const double* c = a.coef + 4 * gi;
+    const double u = shu[idx];
+    const double Lu = (c[0] * (shu[idx - RR] - u) + c[1] * (shu[idx + RR] - u) +
+                       (shu[idx - 1] - 2.0 * u + shu[idx + 1]) / c[2]) / c[3];
+    T* fo = fp + size_t(gi) * n + gj;
+    *fo = T(double(*fo) - Lu);
+  }
+}
+
+// One block per TILE x TILE tile (TILE = 64, or the whole patch if smaller),
+// sin/cos of theta' and phi' tabulated per row and column.  The block first
+// bounds cos(theta) over its region, takes the region centre's azimuth as
+// reference and copies the rings of both grids that can bracket the region
+// into LDS.
+template <typename T, int TILE>
+__global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
+  constexpr int RR = TILE + 2;
+  __shared__ double shu[RR * RR];
+  __shared__ double trig[4 * RR];  // sin/cos th'_row, ph'_col
+  __shared__ RingStore<kRingCapF> ringf;
+  __shared__ RingStore<kRingCapS> rings;
+  __shared__ double zred[2 * (kSetupBlock / 64)];
+  __shared__ PhiRef pref;
+  __shared__ int rng[5];
   const int64_t lb = xcd_block();
   const int tpp = a.ntile * a.ntile;
   const int64_t patch = lb / tpp;
   const int tt = int(lb % tpp);
   const int ti = tt / a.ntile, tj = tt % a.ntile;
-  const int RR = a.tile + 2;
-  double* trig = shu + RR * RR;                          // [RR][4]: sin/cos th'_row, ph'_col
-  T* fsh = reinterpret_cast<T*>(trig + 4 * RR);           // [tile^2] source f (interior)
-  const int i0 = ti * a.tile - 1, j0 = tj * a.tile - 1;
-  const int n = a.n;
+  const int i0 = ti * TILE - 1, j0 = tj * TILE - 1;
   const double* R = a.rot + 9 * patch;
   const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
   for (int r = threadIdx.x; r < RR; r += blockDim.x) {
@@ -95,62 +215,69 @@ __global__ __launch_bounds__(kBlock) void k_patch_setup(SetupArgs a) {
     sincos(ph0 + (j0 + r + 0.5) * a.delta, &trig[4 * r + 2], &trig[4 * r + 3]);
   }
   __syncthreads();
-  const double mean = a.red[1023];
+  // z range of the region's cell centres; every point interpolated lies
+  // within half a cell of one of them
+  double zlo = 2.0, zhi = -2.0;
   for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
     const int li = idx / RR, lj = idx % RR;
-    const int gi = i0 + li, gj = j0 + lj;
-    double v = 0.0;
-    if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
-      double th, z, ph;
-      patch_dir(R, trig[4 * li], trig[4 * li + 1], trig[4 * lj + 2], trig[4 * lj + 3], th, z,
-                ph);
-      v = hpx::interp(a.rs, a.psi_s, th, z, ph);
-      if (li >= 1 && li <= a.tile && lj >= 1 && lj <= a.tile) {
-        const double kv =
-            a.kappa_fp64 ? hpx::interp(a.rf, static_cast<const double*>(a.kappa), th, z, ph)
-                         : hpx::interp(a.rf, static_cast<const float*>(a.kappa), th, z, ph);
-        fsh[(li - 1) * a.tile + (lj - 1)] = T(2.0 * (kv - mean));
-      }
+    const double st = trig[4 * li], ct = trig[4 * li + 1];
+    const double z = R[2] * st * trig[4 * lj + 3] + R[5] * st * trig[4 * lj + 2] + R[8] * ct;
+    zlo = fmin(zlo, z);
+    zhi = fmax(zhi, z);
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    zlo = fmin(zlo, __shfl_xor(zlo, o));
+    zhi = fmax(zhi, __shfl_xor(zhi, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    zred[2 * (threadIdx.x >> 6)] = zlo;
+    zred[2 * (threadIdx.x >> 6) + 1] = zhi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kSetupBlock / 64; ++w) {
+      zlo = fmin(zlo, zred[2 * w]);
+      zhi = fmax(zhi, zred[2 * w + 1]);
     }
-    shu[idx] = v;
+    const double lo = zlo - a.delta, hi = zhi + a.delta;
+    const hpx::GlobalRingTab gs{a.rs, 0.0}, gf{a.rf, 0.0};
+    const int bs = max(0, hpx::ring_above(gs, hi));
+    const int ts = min(a.rs.nring - 1, hpx::ring_above(gs, lo) + 1);
+    const int bf = max(0, hpx::ring_above(gf, hi));
+    const int tf = min(a.rf.nring - 1, hpx::ring_above(gf, lo) + 1);
+    rng[0] = bs; rng[1] = ts; rng[2] = bf; rng[3] = tf;
+    rng[4] = (ts - bs + 1 <= kRingCapS) && (tf - bf + 1 <= kRingCapF);
+    // reference azimuth: the region centre's, in [0, 2 pi)
+    double sc, cc, sp, cp;
+    sincos(th0 + (i0 + 0.5 * RR) * a.delta, &sc, &cc);
+    sincos(ph0 + (j0 + 0.5 * RR) * a.delta, &sp, &cp);
+    const double x = sc * cp, y = sc * sp;
+    const double vx = R[0] * x + R[3] * y + R[6] * cc;
+    const double vy = R[1] * x + R[4] * y + R[7] * cc;
+    const double rc = sqrt(vx * vx + vy * vy);
+    if (rc > 1e-12) {
+      double ph = atan2(vy, vx);
+      if (ph < 0) ph += 2.0 * kPi;
+      pref.phi = ph;
+      pref.c = vx / rc;
+      pref.s = vy / rc;
+    } else {
+      pref.phi = 0.0;
+      pref.c = 1.0;
+      pref.s = 0.0;
+    }
   }
   __syncthreads();
-  // ghost cells of the region (on the patch boundary)
-  for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
-    const int li = idx / RR, lj = idx % RR;
-    const int gi = i0 + li, gj = j0 + lj;
-    const bool gI = gi == -1 || gi == n, gJ = gj == -1 || gj == n;
-    if (!(gI || gJ)) continue;
-    double thp, php;
-    int ai = li, aj = lj;  // adjacent interior cell
-    if (gI) { thp = gi < 0 ? th0 : th0 + a.L; ai = gi < 0 ? li + 1 : li - 1; }
-    else    { thp = th0 + (gi + 0.5) * a.delta; }
-    if (gJ) { php = gj < 0 ? ph0 : ph0 + a.L; aj = gj < 0 ? lj + 1 : lj - 1; }
-    else    { php = ph0 + (gj + 0.5) * a.delta; }
-    double st, ct, sp, cp, th, z, ph;
-    sincos(thp, &st, &ct);
-    sincos(php, &sp, &cp);
-    patch_dir(R, st, ct, sp, cp, th, z, ph);
-    const double b = hpx::interp(a.rs, a.psi_s, th, z, ph);
-    shu[idx] = 2.0 * b - shu[ai * RR + aj];
-  }
-  __syncthreads();
-  const size_t G = size_t(n + 2);
-  double* u0 = a.u0 + size_t(patch) * G * G;
-  T* fp = static_cast<T*>(a.fprime) + size_t(patch) * n * n;
-  for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
-    const int li = idx / RR, lj = idx % RR;
-    const int gi = i0 + li, gj = j0 + lj;
-    // write u0: the tile's cells, plus the patch ghosts beside this tile
-    const bool own_i = (li >= 1 && li <= a.tile) || (gi == -1) || (gi == n);
-    const bool own_j = (lj >= 1 && lj <= a.tile) || (gj == -1) || (gj == n);
-    if (own_i && own_j) u0[size_t(gi + 1) * G + (gj + 1)] = shu[idx];
-    if (!(li >= 1 && li <= a.tile && lj >= 1 && lj <= a.tile)) continue;
-    const double* c = a.coef + 4 * gi;
-    const double u = shu[idx];
-    const double Lu = (c[0] * (shu[idx - RR] - u) + c[1] * (shu[idx + RR] - u) +
-                       (shu[idx - 1] - 2.0 * u + shu[idx + 1]) / c[2]) / c[3];
-    fp[size_t(gi) * n + gj] = T(double(fsh[(li - 1) * a.tile + (lj - 1)]) - Lu);
+  const PhiRef pr = pref;
+  if (rng[4]) {
+    hpx::LdsRingTab ts = rings.tab(), tf = ringf.tab();
+    ts.fill(a.rs, rng[0], rng[1], pr.phi);
+    tf.fill(a.rf, rng[2], rng[3], pr.phi);
+    __syncthreads();
+    setup_passes<T, TILE>(a, ts, tf, shu, trig, R, pr, patch, i0, j0);
+  } else {
+    setup_passes<T, TILE>(a, hpx::GlobalRingTab{a.rs, pr.phi}, hpx::GlobalRingTab{a.rf, pr.phi},
+                          shu, trig, R, pr, patch, i0, j0);
   }
 }
 
@@ -191,6 +318,26 @@ struct QT {
   static constexpr int IT = (NQ + kTileBlock - 1) / kTileBlock;
   static constexpr int QH = HH / 2;            // first interior quad
 };
+
+// Two adjacent cells of a row (even column, so the pair is aligned).
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+template <typename T>
+__device__ __forceinline__ void load2(const T* p, T& a, T& b) {
+  const typename Vec2<T>::type v = *reinterpret_cast<const typename Vec2<T>::type*>(p);
+  a = v.x;
+  b = v.y;
+}
+
+template <typename T>
+__device__ __forceinline__ void store2(T* p, T a, T b) {
+  typename Vec2<T>::type v;
+  v.x = a;
+  v.y = b;
+  *reinterpret_cast<typename Vec2<T>::type*>(p) = v;
+}
 
 template <typename T, int RR>
 struct QLds {
@@ -244,9 +391,8 @@ __device__ __forceinline__ void qload(QLds<T, QT<T, HH>::RR>& t, QRegs<T, QT<T, 
       T u0 = T(0), u1 = T(0), f0 = T(0), f1 = T(0);
       if (in) {
         const size_t g = pbase + size_t(gi) * n + gj;
-        if (u_in) { u0 = u_in[g]; u1 = u_in[g + 1]; }
-        f0 = f_in[g];
-        f1 = f_in[g + 1];
+        if (u_in) load2(u_in + g, u0, u1);
+        load2(f_in + g, f0, f1);
       }
       r.u[it][2 * a] = u0; r.u[it][2 * a + 1] = u1;
       r.f[it][2 * a] = f0; r.f[it][2 * a + 1] = f1;
@@ -372,15 +518,11 @@ __global__ __launch_bounds__(kTileBlock) void k_mg_pre(TileArgs<T> a) {
       continue;
     const int gi = i0 + 2 * qi, gj = j0 + 2 * qj;
     const size_t g = pbase + size_t(gi) * n + gj;
-    a.u_out[g] = r.u[it][0];
-    a.u_out[g + 1] = r.u[it][1];
-    a.u_out[g + n] = r.u[it][2];
-    a.u_out[g + n + 1] = r.u[it][3];
+    store2(a.u_out + g, r.u[it][0], r.u[it][1]);
+    store2(a.u_out + g + n, r.u[it][2], r.u[it][3]);
     if (a.fas_source) {
-      a.f_out[g] = r.f[it][0];
-      a.f_out[g + 1] = r.f[it][1];
-      a.f_out[g + n] = r.f[it][2];
-      a.f_out[g + n + 1] = r.f[it][3];
+      store2(a.f_out + g, r.f[it][0], r.f[it][1]);
+      store2(a.f_out + g + n, r.f[it][2], r.f[it][3]);
     }
     T res[4];
 #pragma unroll
@@ -464,10 +606,8 @@ __global__ __launch_bounds__(kTileBlock) void k_mg_post(TileArgs<T> a) {
         qj >= G::QH + kTile / 2)
       continue;
     const size_t g = pbase + size_t(i0 + 2 * qi) * n + (j0 + 2 * qj);
-    a.u_out[g] = r.u[it][0];
-    a.u_out[g + 1] = r.u[it][1];
-    a.u_out[g + n] = r.u[it][2];
-    a.u_out[g + n + 1] = r.u[it][3];
+    store2(a.u_out + g, r.u[it][0], r.u[it][1]);
+    store2(a.u_out + g + n, r.u[it][2], r.u[it][3]);
   }
 }
 
@@ -738,13 +878,15 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     a.red = p->red;
     a.u0 = sl.u0;
     a.fprime = p->fprime;
-    const size_t shm = (size_t(a.tile + 2) * (a.tile + 2) + 4 * size_t(a.tile + 2)) *
-                           sizeof(double) + size_t(a.tile) * a.tile * sizeof(T);
-    if (allow_lds(p, k_patch_setup<T>, shm) != CLM_OK) return CLM_EHIP;
+    const dim3 grid(unsigned(np * a.ntile * a.ntile));
     {
       CLM_TIMED(p, s, "patch_setup");
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_patch_setup<T>), dim3(np * a.ntile * a.ntile),
-                         dim3(kBlock), shm, s, a);
+      switch (a.tile) {
+        case 64: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_patch_setup<T, 64>), grid, dim3(kSetupBlock), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_patch_setup<T, 32>), grid, dim3(kSetupBlock), 0, s, a); break;
+        case 16: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_patch_setup<T, 16>), grid, dim3(kSetupBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_patch_setup<T, 8>), grid, dim3(kSetupBlock), 0, s, a); break;
+      }
     }
     CLM_LAUNCH_CHECK();
   }

@@ -203,9 +203,12 @@ __global__ void k_galaxies(GalArgs a) {
   }
   const double w = r_of(a.chi_k, a.K) * r_of(cg - a.chi_km1, a.K) /
                    (r_of(cg, a.K) * r_of(a.chi_k - a.chi_km1, a.K));
-  int64_t pix[4];
+  int pix[4];
   double wt[4];
-  hpx::interp_weights(a.rf, a.th[i], cos(a.th[i]), a.ph[i], pix, wt);
+  double s_th, c_th;
+  sincos(a.th[i], &s_th, &c_th);
+  const double ph = a.ph[i] - kTwoPi * floor(a.ph[i] / kTwoPi);
+  hpx::interp_weights(a.rf, c_th, s_th, ph, pix, wt);
   double Ai[4] = {0, 0, 0, 0}, Api[4] = {0, 0, 0, 0};
   for (int q = 0; q < 4; ++q) {
     const int64_t r = a.r2n_f[pix[q]];
