@@ -14,6 +14,9 @@ the sphere with z ~ U[0.3, 1.5].  Inputs are resident in HBM before timing.
 
 Prints one JSON line (see the keys below)."""
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -28,120 +31,143 @@ NF, NS, LMAX, NB, NCELL, VCYC = 2048, 256, 512, 32, 256, 4
 DCHI = 3054.70 / 20.0
 NGAL = 1_000_000
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2.txt")
 
 
-def bytes_model(stage, plan_n, nbundle, npix, ncyc):
-    """Algorithmic HBM bytes of one launch of a stage (float32 multigrid):
-    every array the step must read or write once, no halo re-reads."""
-    cells = nbundle * plan_n * plan_n
-    c1 = cells / 4
+def source_digest():
+    """sha256 over the HIP sources; counter figures taken from other sources
+    are stale."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1210_3069_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def stage_kernels(nbundle, ncell):
+    """rocprof kernel name fragment and grid size (work-items) of each timed
+    stage's kernel at this workload (float32 form)."""
+    t0 = (ncell // 64) ** 2
+    t1 = (ncell // 128) ** 2
     return {
-        # f' and du read, du written, ubar/rbar of the next level written; the
-        # first cycle starts from du = 0 and skips its read
-        "mg_pre_l0": cells * (4 + 4 + 4 + 2) - cells * 4 / ncyc,
-        # du, f' and the coarse u_H, ubar read, du written
-        "mg_post_l0": cells * (4 + 4 + 2 + 4),
-        "mg_pre_l1+": c1 * (4 + 4 + 4 + 4 + 2),
-        "mg_post_l1+": c1 * (4 + 4 + 2 + 4),
-        # ubar, rbar of the 64^2 level read, u written
-        "mg_lds": cells / 16 * 12,
-        # u0 (float64, with ghosts) and f' written, fine kappa read once
-        "patch_setup": nbundle * (plan_n + 2) ** 2 * 8 + cells * 4 + npix * 4,
-        # five float32 outputs per pixel, u0 + du over the bundle cores read once
-        "eval_pixels": npix * (20 + 12),
-        # theta, phi, beta, A, A_prev read and written, patch cores read once
-        "ray_update": npix * (2 * (8 + 8 + 24 + 16 + 16) + 12),
-    }.get(stage)
+        "patch_setup": ("k_patch_setup<float, 64>", nbundle * t0 * 512),
+        "mg_pre_l0": ("k_mg_pre<float", nbundle * t0 * 512),
+        "mg_post_l0": ("k_mg_post<float", nbundle * t0 * 512),
+        "mg_pre_l1+": ("k_mg_pre<float", nbundle * t1 * 512),
+        "mg_post_l1+": ("k_mg_post<float", nbundle * t1 * 512),
+        "mg_lds": ("k_mg_lds<float", None),
+        "eval_pixels": ("k_eval<float", None),
+        "ray_update": ("k_ray_update<float", None),
+    }
 
 
-def make_inputs(clm, torch, inputs, cosmo):
-    alm = torch.from_numpy(inputs.gaussian_alm(LMAX, seed=3, sigma=0.5)).cuda()
-    g = clm.alm2map(alm, LMAX, NF)
-    e = torch.exp(g)
-    s = inputs.deflection_scale(LMAX, 0.5)
-    kappa = (s * (e - e.mean())).float().contiguous()
-    del g, e
-    th, ph, z = inputs.galaxy_redshifts(NGAL, seed=200)
-    gal = dict(theta=torch.from_numpy(th).cuda(), phi=torch.from_numpy(ph).cuda(),
-               chi=torch.from_numpy(cosmo.chi_of_z(z)).cuda(),
-               A=torch.zeros(4, NGAL, dtype=torch.float32, device="cuda"))
-    return kappa, gal
+def read_traffic(stage):
+    """HBM bytes per launch of a stage from the committed counter summary, or
+    None if absent or taken from other sources."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        parts = ln.split()
+        if len(parts) == 3 and parts[0] == "traffic_bytes_per_launch":
+            kv[parts[1]] = float(parts[2])
+        elif len(parts) == 2 and parts[0] == "source_sha256":
+            kv["_sha"] = parts[1]
+    if kv.get("_sha") != source_digest():
+        return None
+    return kv.get(stage)
 
 
-def run_form(clm, torch, kappa, gal, prec, steps, warmup):
-    plan = clm.Plan(NF, nside_sht=NS, lmax=LMAX, nside_bundle=NB, patch_cells=NCELL,
-                    mg_vcycles=VCYC, mg_prec=prec)
-    rays = plan.new_rays()
-    nplanes = warmup + steps
-    chi = (np.arange(nplanes + 1) + 0.5) * DCHI
-    gout = (torch.empty(2, plan.npix_fine, dtype=torch.float32, device="cuda"),
-            torch.empty(3, plan.npix_fine, dtype=torch.float32, device="cuda"))
-
-    def step(m):
-        plan.raytrace_planes(kappa, chi, m, rays, galaxies=gal)
-        plan.shear_at_pixels(order="nested", fp64=False, out=gout)
-
-    for m in range(warmup):
-        step(m)
-    torch.cuda.synchronize()
-    plan.sync_status()
-    plan.set_timing(True)
-    plan.get_timing()
-    stream = torch.cuda.current_stream()
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter()
-    t0.record(stream)
-    for m in range(warmup, warmup + steps):
-        step(m)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall
-    ms = t0.elapsed_time(t1) / steps
-    stages = plan.get_timing()
-    plan.set_timing(False)
-    plan.sync_status()
-    return plan, rays, ms, wall, stages
+def short_name(k):
+    """Kernel name without namespaces, return type and parameter list."""
+    k = k.replace("(anonymous namespace)::", "").replace("clm::", "")
+    k = k[5:] if k.startswith("void ") else k
+    depth = 0
+    for i, ch in enumerate(k):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return k[:i]
+    return k
 
 
-def cpu_baseline(torch, kappa, plan64, sample_bundles):
-    """The FP64 oracle, as it stands, on a bounded sample of the same plane:
-    the full SHT stage, then patch setup + V-cycles + shear at the bundle's
-    pixels + one ray step for `sample_bundles` bundles, scaled to one plane."""
-    from oracle import healpix as hp
-    from oracle import mg as omg
-    from oracle import rays as orays
-    kap = kappa.double().cpu().numpy()
-    spec = omg.PatchSpec(NF, NS, LMAX, NB, ncell=NCELL, vcycles=VCYC)
-    t = time.perf_counter()
-    mean, _, palm, psi = omg.sht_stage(spec, kap)
-    t_sht = time.perf_counter() - t
-    per = (NF // NB) ** 2
-    chi = np.array([0.5 * DCHI, 1.5 * DCHI])
-    t = time.perf_counter()
-    worst = 0.0
-    for b in sample_bundles:
-        R, u0, fp = omg.patch_setup(spec, b, kap, mean, psi)
-        du = omg.mg_solve(spec, fp)
-        patch = dict(R=R, u0=u0, du=du)
-        pix = np.arange(b * per, (b + 1) * per)
-        z, ph, s = hp.pix2ang_nest(NF, pix)
-        th = np.arctan2(s, z)
-        for k in range(per):
-            g, U = omg.eval_point(spec, patch, th[k], ph[k])
-            r = orays.Ray(th[k], ph[k])
-            orays.ray_step(r, chi, 0, g, U)
-        ug = plan64.patch_potential(int(b), 1)[0].cpu().numpy()
-        ur = (u0 + du)[1:-1, 1:-1]
-        worst = max(worst, float(np.abs(ug - ur).max() / np.abs(ur).max()))
-    t_patch = (time.perf_counter() - t) / len(sample_bundles)
-    t_plane = t_sht + t_patch * 12 * NB * NB
-    return dict(value=1.0 / t_plane, unit="plane solves/s", cores=1, kind="oracle",
-                sample="full SHT stage (%.1f s) + %d of %d patches (setup, 4 V-cycles, "
-                       "shear and one ray step at their %d pixels; %.1f s each), scaled "
-                       "to one plane" % (t_sht, len(sample_bundles), 12 * NB * NB, per,
-                                         t_patch),
-                gpu_fp64_vs_oracle_rel_err_u=worst)
+def read_pmc(path, counter):
+    """{(kernel, grid): [mean value per dispatch, dispatches]} of one counter."""
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        key = (r["Kernel_Name"], int(r["Grid_Size"]))
+        v = acc.setdefault(key, [0.0, 0])
+        v[0] += float(r["Counter_Value"])
+        v[1] += 1
+    return {k: [v[0] / v[1], v[1]] for k, v in acc.items()}
+
+
+def summarize_pmc(fetch_csv, write_csv, fetch_cmd, write_cmd):
+    """Counter summary text: FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per
+    kernel, calibrated by the plain copy kernel of COPY_BYTES each way."""
+    fe, wr = read_pmc(fetch_csv, "FETCH_SIZE"), read_pmc(write_csv, "WRITE_SIZE")
+    copy = [k for k in fe if "neg_kernel" in k[0]]
+    if not copy:
+        raise SystemExit("no copy-calibration dispatch in " + fetch_csv)
+    cf = COPY_BYTES / (fe[copy[0]][0] * 1024.0)
+    cw = COPY_BYTES / (wr[copy[0]][0] * 1024.0)
+    out = ["# HBM traffic per dispatch, C2 workload (float32 form)",
+           "# fetch pass: " + fetch_cmd, "# write pass: " + write_cmd,
+           "# calibration: a copy kernel (torch.neg, float32) reading and writing "
+           "%d bytes reads FETCH_SIZE %.1f KiB and WRITE_SIZE %.1f KiB"
+           % (COPY_BYTES, fe[copy[0]][0], wr[copy[0]][0]),
+           "calibration_fetch %.6f" % cf, "calibration_write %.6f" % cw,
+           "source_sha256 " + source_digest(),
+           "# kernel | grid | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated GB"]
+    for k in sorted(fe, key=lambda k: -fe[k][0]):
+        w = wr.get(k, [0.0, 0])[0]
+        gb = (fe[k][0] * cf + w * cw) * 1024.0 / 1e9
+        out.append("# %s | %d | %d | %.1f | %.1f | %.4f" % (short_name(k[0])[:90], k[1], fe[k][1],
+                                                           fe[k][0], w, gb))
+    nb = 12 * NB * NB
+    for st, (frag, grid) in stage_kernels(nb, NCELL).items():
+        ks = [k for k in fe if frag in k[0] and (grid is None or k[1] == grid)]
+        if len(ks) == 1:
+            k = ks[0]
+            b = (fe[k][0] * cf + wr.get(k, [0.0])[0] * cw) * 1024.0
+            out.append("traffic_bytes_per_launch %s %.0f" % (st, b))
+    return "\n".join(out) + "\n"
+
+
+def summarize_stats(stats_csv, cmd):
+    """Kernel-trace summary text: per kernel calls and average duration, then
+    per kernel and grid size (the levels of one kernel differ in grid) from the
+    trace beside the statistics file."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    out = ["# rocprofv3 kernel statistics, C2 workload", "# command: " + cmd,
+           "# kernel | calls | average us | total ms | percent"]
+    for r in rows:
+        out.append("%s | %s | %.1f | %.3f | %.2f" % (
+            short_name(r["Name"])[:90], r["Calls"], float(r["AverageNs"]) / 1e3,
+            float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+    trace = stats_csv.replace("kernel_stats", "kernel_trace")
+    if os.path.exists(trace):
+        acc = {}
+        for r in csv.DictReader(open(trace)):
+            key = (short_name(r["Kernel_Name"]), int(r["Grid_Size_X"]))
+            v = acc.setdefault(key, [0, 0.0])
+            v[0] += 1
+            v[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        out.append("# per kernel and grid (work-items) from the trace: "
+                   "kernel | grid | calls | average us")
+        for k, v in sorted(acc.items(), key=lambda kv: -kv[1][1]):
+            if v[1] > 100.0:
+                out.append("%s | %d | %d | %.1f" % (k[0][:90], k[1], v[0], v[1] / v[0]))
+    return "\n".join(out) + "\n"
 
 
 def main():
@@ -152,7 +178,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="finish with a plain copy kernel of known size (counter calibration)")
+    ap.add_argument("--summarize-stats", nargs=2, metavar=("CSV", "CMD"),
+                    help="print a rocprofv3 --stats summary (no GPU)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FCMD", "WCMD"),
+                    help="print the HBM traffic summary of two --pmc passes (no GPU)")
     args = ap.parse_args()
+    if args.summarize_stats:
+        sys.stdout.write(summarize_stats(*args.summarize_stats))
+        return
+    if args.summarize_pmc:
+        sys.stdout.write(summarize_pmc(*args.summarize_pmc))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -189,10 +227,18 @@ def main():
               key=lambda k: per_stage[k]["ms_per_step"])
     b_dom = bytes_model(dom, NCELL, nbundle, npix, VCYC)
     achieved = per_stage[dom]["alg_GBps"]
+    traffic = read_traffic(dom)
     roofline = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None,
+                    frac=achieved / HBM_PEAK_GBS,
+                    traffic=None if traffic is None else traffic / 1e9,
+                    traffic_unit="GB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                     alg_bytes_per_launch=b_dom,
                     ms_per_launch=per_stage[dom]["ms_per_launch"])
+    for k in per_stage:
+        t = read_traffic(k)
+        if t is not None:
+            per_stage[k]["hbm_GB_per_launch"] = t / 1e9
+            per_stage[k]["hbm_GBps"] = t / (per_stage[k]["ms_per_launch"] * 1e-3) / 1e9
 
     out = {
         "metric": "SHT+MG plane solves/s @Nside 2048",
@@ -235,6 +281,13 @@ def main():
             out["cpu_baseline"] = cpu_baseline(torch, kappa, plan64,
                                                sample[: max(1, args.cpu_sample)])
         plan64.close()
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     print(json.dumps(out), flush=True)
 
 
