@@ -170,6 +170,120 @@ def summarize_stats(stats_csv, cmd):
     return "\n".join(out) + "\n"
 
 
+def bytes_model(stage, plan_n, nbundle, npix, ncyc):
+    """Algorithmic HBM bytes of one launch of a stage (float32 multigrid):
+    every array the step must read or write once, no halo re-reads."""
+    cells = nbundle * plan_n * plan_n
+    c1 = cells / 4
+    return {
+        # f' and du read, du written, ubar/rbar of the next level written; the
+        # first cycle starts from du = 0 and skips its read
+        "mg_pre_l0": cells * (4 + 4 + 4 + 2) - cells * 4 / ncyc,
+        # du, f' and the coarse u_H, ubar read, du written
+        "mg_post_l0": cells * (4 + 4 + 2 + 4),
+        "mg_pre_l1+": c1 * (4 + 4 + 4 + 4 + 2),
+        "mg_post_l1+": c1 * (4 + 4 + 2 + 4),
+        # ubar, rbar of the 64^2 level read, u written
+        "mg_lds": cells / 16 * 12,
+        # u0 (float64, with ghosts) and f' written, fine kappa read once
+        "patch_setup": nbundle * (plan_n + 2) ** 2 * 8 + cells * 4 + npix * 4,
+        # five float32 outputs per pixel, u0 + du over the bundle cores read once
+        "eval_pixels": npix * (20 + 12),
+        # theta, phi, beta, A, A_prev read and written, patch cores read once
+        "ray_update": npix * (2 * (8 + 8 + 24 + 16 + 16) + 12),
+    }.get(stage)
+
+
+def make_inputs(clm, torch, inputs, cosmo):
+    alm = torch.from_numpy(inputs.gaussian_alm(LMAX, seed=3, sigma=0.5)).cuda()
+    g = clm.alm2map(alm, LMAX, NF)
+    e = torch.exp(g)
+    s = inputs.deflection_scale(LMAX, 0.5)
+    kappa = (s * (e - e.mean())).float().contiguous()
+    del g, e
+    th, ph, z = inputs.galaxy_redshifts(NGAL, seed=200)
+    gal = dict(theta=torch.from_numpy(th).cuda(), phi=torch.from_numpy(ph).cuda(),
+               chi=torch.from_numpy(cosmo.chi_of_z(z)).cuda(),
+               A=torch.zeros(4, NGAL, dtype=torch.float32, device="cuda"))
+    return kappa, gal
+
+
+def run_form(clm, torch, kappa, gal, prec, steps, warmup):
+    plan = clm.Plan(NF, nside_sht=NS, lmax=LMAX, nside_bundle=NB, patch_cells=NCELL,
+                    mg_vcycles=VCYC, mg_prec=prec)
+    rays = plan.new_rays()
+    nplanes = warmup + steps
+    chi = (np.arange(nplanes + 1) + 0.5) * DCHI
+    gout = (torch.empty(2, plan.npix_fine, dtype=torch.float32, device="cuda"),
+            torch.empty(3, plan.npix_fine, dtype=torch.float32, device="cuda"))
+
+    def step(m):
+        plan.raytrace_planes(kappa, chi, m, rays, galaxies=gal)
+        plan.shear_at_pixels(order="nested", fp64=False, out=gout)
+
+    for m in range(warmup):
+        step(m)
+    torch.cuda.synchronize()
+    plan.sync_status()
+    plan.set_timing(True)
+    plan.get_timing()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter()
+    t0.record(stream)
+    for m in range(warmup, warmup + steps):
+        step(m)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall
+    ms = t0.elapsed_time(t1) / steps
+    stages = plan.get_timing()
+    plan.set_timing(False)
+    plan.sync_status()
+    return plan, rays, ms, wall, stages
+
+
+def cpu_baseline(torch, kappa, plan64, sample_bundles):
+    """The FP64 oracle, as it stands, on a bounded sample of the same plane:
+    the full SHT stage, then patch setup + V-cycles + shear at the bundle's
+    pixels + one ray step for `sample_bundles` bundles, scaled to one plane."""
+    from oracle import healpix as hp
+    from oracle import mg as omg
+    from oracle import rays as orays
+    kap = kappa.double().cpu().numpy()
+    spec = omg.PatchSpec(NF, NS, LMAX, NB, ncell=NCELL, vcycles=VCYC)
+    t = time.perf_counter()
+    mean, _, palm, psi = omg.sht_stage(spec, kap)
+    t_sht = time.perf_counter() - t
+    per = (NF // NB) ** 2
+    chi = np.array([0.5 * DCHI, 1.5 * DCHI])
+    t = time.perf_counter()
+    worst = 0.0
+    for b in sample_bundles:
+        R, u0, fp = omg.patch_setup(spec, b, kap, mean, psi)
+        du = omg.mg_solve(spec, fp)
+        patch = dict(R=R, u0=u0, du=du)
+        pix = np.arange(b * per, (b + 1) * per)
+        z, ph, s = hp.pix2ang_nest(NF, pix)
+        th = np.arctan2(s, z)
+        for k in range(per):
+            g, U = omg.eval_point(spec, patch, th[k], ph[k])
+            r = orays.Ray(th[k], ph[k])
+            orays.ray_step(r, chi, 0, g, U)
+        ug = plan64.patch_potential(int(b), 1)[0].cpu().numpy()
+        ur = (u0 + du)[1:-1, 1:-1]
+        worst = max(worst, float(np.abs(ug - ur).max() / np.abs(ur).max()))
+    t_patch = (time.perf_counter() - t) / len(sample_bundles)
+    t_plane = t_sht + t_patch * 12 * NB * NB
+    return dict(value=1.0 / t_plane, unit="plane solves/s", cores=1, kind="oracle",
+                sample="full SHT stage (%.1f s) + %d of %d patches (setup, 4 V-cycles, "
+                       "shear and one ray step at their %d pixels; %.1f s each), scaled "
+                       "to one plane" % (t_sht, len(sample_bundles), 12 * NB * NB, per,
+                                         t_patch),
+                gpu_fp64_vs_oracle_rel_err_u=worst)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -284,14 +284,16 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
 // ------------------------------------------------------------ tile kernels
 // A 64 x 64 tile plus an even halo of HH cells per side is processed by one
 // workgroup.  The region is cut into 2 x 2 quads aligned with the cells of
-// the next coarser level; each thread owns up to IT quads and keeps their
-// four u values and four sources f in registers.  u is mirrored in LDS,
-// columns split by parity (row stride Q) so that neighbouring quads of a
-// row sit at consecutive LDS addresses.  A red-black half sweep updates the
-// two cells of a quad that have the sweep's colour; their in-quad neighbours
-// come from registers, the others from LDS.  Cells outside the patch are
-// zero and never updated; a neighbour across the patch face is accounted
-// for in the diagonal (zero face value).
+// the next coarser level.  A thread owns IT quads of one quad row (columns
+// tr, tr + TPR, ...), so it keeps that row pair's coefficients once, and per
+// quad the four u values, the four sources times the cell area (A f) and
+// the four reciprocal diagonals, all in registers.  u is mirrored in LDS,
+// columns split by parity, with a guard ring of zeros, so that every
+// neighbour a quad reads sits at a fixed offset from one base index.  Cells
+// outside the patch carry a zero reciprocal diagonal and zero source, so
+// they stay zero; a neighbour across the patch face enters only through the
+// diagonal (zero face value).  Cells near the region edge read the guard
+// zeros; the halo is wide enough that this never reaches the tile.
 constexpr int kTileBlock = 512;
 
 template <typename T>
@@ -299,24 +301,33 @@ struct TileArgs {
   int n, ntile, nu;
   const double* coef;   // this level's rows
   const T* u_in;        // level iterate in (nullptr: zero), or ubar (level >= 1 pre)
-  const T* f_in;        // source f (level 0 pre, all post), or rbar (level >= 1 pre)
+  const T* f_in;        // source (level 0: f'; level >= 1 post: A f), or rbar (level >= 1 pre)
   T* u_out;
-  T* f_out;             // level >= 1 pre: the formed source
+  T* f_out;             // level >= 1 pre: the formed source, times the cell area
   T* ubar_out;          // pre: restricted iterate for the next level
   T* rbar_out;          // pre: restricted residual
   const T* uc;          // post: coarse result u_H
   const T* ubarc;       // post: coarse ubar
-  int fas_source;       // pre on level >= 1: f = L u_in + f_in
+  int fas_source;       // pre on level >= 1: A f = A L u_in + A f_in
+  int f_scaled;         // f_in already holds A f
 };
+
+constexpr int quads_per_thread(int q) {
+  int it = 1;
+  while (q * ((q + it - 1) / it) > kTileBlock) ++it;
+  return it;
+}
 
 template <typename T, int HH>
 struct QT {
   static_assert(HH % 2 == 0, "quads must align with the coarse level");
   static constexpr int RR = kTile + 2 * HH;    // region side
   static constexpr int Q = RR / 2;             // quads per side
-  static constexpr int NQ = Q * Q;
-  static constexpr int IT = (NQ + kTileBlock - 1) / kTileBlock;
+  static constexpr int IT = quads_per_thread(Q);
+  static constexpr int TPR = (Q + IT - 1) / IT;  // threads per quad row
   static constexpr int QH = HH / 2;            // first interior quad
+  static constexpr int S = Q + 2;              // parity-array row stride (guard columns)
+  static constexpr int PAR = (RR + 2) * S;     // cells per parity array (guard rows)
 };
 
 // Two adjacent cells of a row (even column, so the pair is aligned).
@@ -339,201 +350,357 @@ __device__ __forceinline__ void store2(T* p, T a, T b) {
   *reinterpret_cast<typename Vec2<T>::type*>(p) = v;
 }
 
-template <typename T, int RR>
+// LDS of a tile: u of cell (li, lj) at (lj & 1) * PAR + (li + 1) * S + (lj >> 1) + 1;
+// per region row the coefficients, the interior diagonal and its reciprocal.
+template <typename T, int HH>
 struct QLds {
-  T uE[RR * (RR / 2)], uO[RR * (RR / 2)];
-  T sm[RR], sp[RR], isc[RR], A[RR], rD[RR];
+  using G = QT<T, HH>;
+  T u[2 * G::PAR];
+  T sm[G::RR], sp[G::RR], isc[G::RR], A[G::RR], D[G::RR], rD[G::RR];
+  T rden[G::Q];   // 1 / (2 (A_2k + A_2k+1)): area weight of a quad row pair
 };
 
-template <typename T, int RR>
-__device__ __forceinline__ T& qcell(QLds<T, RR>& t, int li, int lj) {
-  return ((lj & 1) ? t.uO : t.uE)[li * (RR / 2) + (lj >> 1)];
-}
+// A thread's quad row pair (qi): rows 2 qi and 2 qi + 1 of the region.
+template <typename T>
+struct QRow {
+  T sm0, sp0, is0, sm1, sp1, is1;
+  int qi;
+  bool live;
+};
 
-template <typename T, int RR>
-__device__ __forceinline__ void qload_rows(QLds<T, RR>& t, const double* coef, int n, int i0) {
-  for (int r = threadIdx.x; r < RR; r += kTileBlock) {
+// Per owned quad (qi, qj): cells c = 2a + b at (2 qi + a, 2 qj + b).  b is
+// the LDS index of cell (2 qi - 1, 2 qj); every neighbour outside the quad
+// is at a fixed offset from it.
+template <typename T>
+struct Quad {
+  T u[4], ft[4], rD[4];
+  int b, qj;
+  bool live, edge;  // edge: a cell of the quad lies on the patch boundary
+};
+
+template <typename T, int HH>
+__device__ __forceinline__ void qload_rows(QLds<T, HH>& t, const double* coef, int n, int i0) {
+  using G = QT<T, HH>;
+  for (int r = threadIdx.x; r < G::RR; r += kTileBlock) {
     const int gi = i0 + r;
-    T sm = T(0), sp = T(0), isc = T(0), A = T(1), rD = T(0);
+    T sm = T(0), sp = T(0), isc = T(0), A = T(1), D = T(1), rD = T(1);
     if (gi >= 0 && gi < n) {
       const double* c = coef + 4 * gi;
+      const double d = c[0] + c[1] + 2.0 / c[2];
       sm = T(c[0]);
       sp = T(c[1]);
       isc = T(1.0 / c[2]);
       A = T(c[3]);
-      rD = T(1.0 / (c[0] + c[1] + 2.0 / c[2]));
+      D = T(d);
+      rD = T(1.0 / d);
     }
-    t.sm[r] = sm; t.sp[r] = sp; t.isc[r] = isc; t.A[r] = A; t.rD[r] = rD;
+    t.sm[r] = sm; t.sp[r] = sp; t.isc[r] = isc; t.A[r] = A; t.D[r] = D; t.rD[r] = rD;
   }
+  for (int k = threadIdx.x; k < G::Q; k += kTileBlock) {
+    const int gi = i0 + 2 * k;
+    double a0 = 1.0, a1 = 1.0;
+    if (gi >= 0 && gi + 1 < n) {
+      a0 = coef[4 * gi + 3];
+      a1 = coef[4 * gi + 7];
+    }
+    t.rden[k] = T(1.0 / (2.0 * (a0 + a1)));
+  }
+  // guard ring and every cell start at zero
+  for (int k = threadIdx.x; k < 2 * G::PAR; k += kTileBlock) t.u[k] = T(0);
 }
 
-// Quad-owning thread state.
-template <typename T, int IT>
-struct QRegs {
-  T u[IT][4];   // (a, b) -> 2a + b
-  T f[IT][4];
-};
+// Diagonal of the in-patch cell (gi, gj): the interior one plus, across a
+// patch face, the coefficient of the missing neighbour (ghost = -u).
+template <typename T>
+__device__ __forceinline__ T cell_diag(T D, T sm, T sp, T isc, int gi, int gj, int n) {
+  if (gi == 0) D += sm;
+  if (gi == n - 1) D += sp;
+  if (gj == 0) D += isc;
+  if (gj == n - 1) D += isc;
+  return D;
+}
 
-// Load u (registers and LDS) and f (registers) of the owned quads.
+// Set up the thread's row pair and quads: coefficients, A f, reciprocal
+// diagonals, u (in registers; written to LDS by qput after the zero fill is
+// visible).  u_in and f_in point at this patch's level array.
 template <typename T, int HH>
-__device__ __forceinline__ void qload(QLds<T, QT<T, HH>::RR>& t, QRegs<T, QT<T, HH>::IT>& r,
-                                      const T* u_in, const T* f_in, size_t pbase, int n,
+__device__ __forceinline__ void qinit(QLds<T, HH>& t, QRow<T>& rw, Quad<T> (&qd)[QT<T, HH>::IT],
+                                      const T* u_in, const T* f_in, bool f_scaled, int n,
                                       int i0, int j0) {
   using G = QT<T, HH>;
+  const int qi = threadIdx.x / G::TPR, tr = threadIdx.x - qi * G::TPR;
+  rw.live = qi < G::Q;
+  rw.qi = rw.live ? qi : 0;
+  const int li = 2 * rw.qi;
+  rw.sm0 = t.sm[li]; rw.sp0 = t.sp[li]; rw.is0 = t.isc[li];
+  rw.sm1 = t.sm[li + 1]; rw.sp1 = t.sp[li + 1]; rw.is1 = t.isc[li + 1];
+  const int gi0 = i0 + li;
 #pragma unroll
   for (int it = 0; it < G::IT; ++it) {
-    const int q = threadIdx.x + it * kTileBlock;
-    const int qi = q / G::Q, qj = q - qi * G::Q;
+    Quad<T>& Qd = qd[it];
+    const int qj = tr + it * G::TPR;
+    Qd.live = rw.live && qj < G::Q;
+    Qd.qj = Qd.live ? qj : 0;
+    Qd.b = 2 * rw.qi * G::S + Qd.qj + 1;
+    const int gj = j0 + 2 * Qd.qj;
+    Qd.edge = gi0 == 0 || gi0 + 1 == n - 1 || gj == 0 || gj + 1 == n - 1;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const int gi = i0 + 2 * qi + a, gj = j0 + 2 * qj;
-      const bool in = q < G::NQ && gi >= 0 && gi < n && gj >= 0 && gj < n;
-      T u0 = T(0), u1 = T(0), f0 = T(0), f1 = T(0);
+      const int gi = gi0 + a;
+      const bool in = Qd.live && gi >= 0 && gi < n && gj >= 0 && gj < n;
+      T u0 = T(0), u1 = T(0), f0 = T(0), f1 = T(0), r0 = T(0), r1 = T(0);
       if (in) {
-        const size_t g = pbase + size_t(gi) * n + gj;
+        const int g = gi * n + gj;
         if (u_in) load2(u_in + g, u0, u1);
         load2(f_in + g, f0, f1);
+        if (!f_scaled) {
+          const T A = t.A[li + a];
+          f0 *= A;
+          f1 *= A;
+        }
+        r0 = r1 = t.rD[li + a];
+        if (Qd.edge) {
+          const T D = t.D[li + a];
+          const T sm = a ? rw.sm1 : rw.sm0, sp = a ? rw.sp1 : rw.sp0;
+          const T isc = a ? rw.is1 : rw.is0;
+          const T d0 = cell_diag(D, sm, sp, isc, gi, gj, n);
+          const T d1 = cell_diag(D, sm, sp, isc, gi, gj + 1, n);
+          if (d0 != D) r0 = T(1) / d0;
+          if (d1 != D) r1 = T(1) / d1;
+        }
       }
-      r.u[it][2 * a] = u0; r.u[it][2 * a + 1] = u1;
-      r.f[it][2 * a] = f0; r.f[it][2 * a + 1] = f1;
-      if (q < G::NQ) {
-        const int li = 2 * qi + a;
-        t.uE[li * G::Q + qj] = u0;
-        t.uO[li * G::Q + qj] = u1;
-      }
+      Qd.u[2 * a] = u0; Qd.u[2 * a + 1] = u1;
+      Qd.ft[2 * a] = f0; Qd.ft[2 * a + 1] = f1;
+      Qd.rD[2 * a] = r0; Qd.rD[2 * a + 1] = r1;
     }
   }
 }
 
-// (L u) at cell (a, b) of quad (qi, qj): in-quad neighbours from registers,
-// the others from LDS; zero face value across the patch boundary.
+// Write the owned quads' u to LDS.
 template <typename T, int HH>
-__device__ __forceinline__ T qlap(QLds<T, QT<T, HH>::RR>& t, const T* u4, int qi, int qj, int a,
-                                  int b, int i0, int j0, int n) {
-  constexpr int RR = QT<T, HH>::RR;
-  const int li = 2 * qi + a, lj = 2 * qj + b;
-  const int gi = i0 + li, gj = j0 + lj;
-  const T c = u4[2 * a + b];
-  T up = a ? u4[b] : (li > 0 ? qcell(t, li - 1, lj) : T(0));
-  T dn = a ? (li < RR - 1 ? qcell(t, li + 1, lj) : T(0)) : u4[2 + b];
-  T lf = b ? u4[2 * a] : (lj > 0 ? qcell(t, li, lj - 1) : T(0));
-  T rt = b ? (lj < RR - 1 ? qcell(t, li, lj + 1) : T(0)) : u4[2 * a + 1];
-  if (gi == 0) up = -c;
-  if (gi == n - 1) dn = -c;
-  if (gj == 0) lf = -c;
-  if (gj == n - 1) rt = -c;
-  return (t.sm[li] * (up - c) + t.sp[li] * (dn - c) + (lf - T(2) * c + rt) * t.isc[li]) / t.A[li];
-}
-
-// Red-black half sweep: the two cells of colour `color` in every owned quad
-// (i0, j0 even, so the colour of (a, b) is (a + b) % 2).
-template <typename T, int HH>
-__device__ __forceinline__ void qsweep(QLds<T, QT<T, HH>::RR>& t, QRegs<T, QT<T, HH>::IT>& r,
-                                       int color, int i0, int j0, int n) {
+__device__ __forceinline__ void qput(QLds<T, HH>& t, const Quad<T> (&qd)[QT<T, HH>::IT]) {
   using G = QT<T, HH>;
-  constexpr int RR = G::RR;
 #pragma unroll
   for (int it = 0; it < G::IT; ++it) {
-    const int q = threadIdx.x + it * kTileBlock;
-    if (q >= G::NQ) continue;
-    const int qi = q / G::Q, qj = q - qi * G::Q;
+    const Quad<T>& Qd = qd[it];
+    if (!Qd.live) continue;
+    T* ub = t.u + Qd.b;
+    ub[G::S] = Qd.u[0];
+    ub[G::PAR + G::S] = Qd.u[1];
+    ub[2 * G::S] = Qd.u[2];
+    ub[G::PAR + 2 * G::S] = Qd.u[3];
+  }
+}
+
+// Red-black half sweep over the owned quads.
+template <typename T, int HH>
+__device__ __forceinline__ void qsweep(QLds<T, HH>& t, const QRow<T>& rw,
+                                       Quad<T> (&qd)[QT<T, HH>::IT], int color) {
+  using G = QT<T, HH>;
+  constexpr int S = G::S, P = G::PAR;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int a = s, b = (color + s) & 1;   // (0, color) and (1, 1 - color)
-      const int li = 2 * qi + a, lj = 2 * qj + b;
-      if (li == 0 || li == RR - 1 || lj == 0 || lj == RR - 1) continue;
-      const int gi = i0 + li, gj = j0 + lj;
-      if (gi < 0 || gi >= n || gj < 0 || gj >= n) continue;
-      T* u4 = r.u[it];
-      const T up = a ? u4[b] : qcell(t, li - 1, lj);
-      const T dn = a ? qcell(t, li + 1, lj) : u4[2 + b];
-      const T lf = b ? u4[2 * a] : qcell(t, li, lj - 1);
-      const T rt = b ? qcell(t, li, lj + 1) : u4[2 * a + 1];
-      const T sm = t.sm[li], sp = t.sp[li], isc = t.isc[li];
-      const T num = sm * up + sp * dn + isc * (lf + rt) - t.A[li] * r.f[it][2 * a + b];
-      T v;
-      if (gi == 0 || gi == n - 1 || gj == 0 || gj == n - 1) {
-        T diag = sm + sp + T(2) * isc;
-        if (gi == 0) diag += sm;
-        if (gi == n - 1) diag += sp;
-        if (gj == 0) diag += isc;
-        if (gj == n - 1) diag += isc;
-        v = num / diag;
-      } else {
-        v = num * t.rD[li];
-      }
-      u4[2 * a + b] = v;
-      qcell(t, li, lj) = v;
+  for (int it = 0; it < G::IT; ++it) {
+    Quad<T>& Qd = qd[it];
+    if (!Qd.live) continue;
+    T* ub = t.u + Qd.b;
+    if (color == 0) {
+      const T up = ub[0], lf = ub[P + S - 1], dn = ub[P + 3 * S], rt = ub[2 * S + 1];
+      const T v0 = (rw.sm0 * up + rw.sp0 * Qd.u[2] + rw.is0 * (lf + Qd.u[1]) - Qd.ft[0]) * Qd.rD[0];
+      const T v3 = (rw.sm1 * Qd.u[1] + rw.sp1 * dn + rw.is1 * (Qd.u[2] + rt) - Qd.ft[3]) * Qd.rD[3];
+      Qd.u[0] = v0;
+      Qd.u[3] = v3;
+      ub[S] = v0;
+      ub[P + 2 * S] = v3;
+    } else {
+      const T up = ub[P], rt = ub[S + 1], dn = ub[3 * S], lf = ub[P + 2 * S - 1];
+      const T v1 = (rw.sm0 * up + rw.sp0 * Qd.u[3] + rw.is0 * (Qd.u[0] + rt) - Qd.ft[1]) * Qd.rD[1];
+      const T v2 = (rw.sm1 * Qd.u[0] + rw.sp1 * dn + rw.is1 * (lf + Qd.u[3]) - Qd.ft[2]) * Qd.rD[2];
+      Qd.u[1] = v1;
+      Qd.u[2] = v2;
+      ub[P + S] = v1;
+      ub[2 * S] = v2;
     }
   }
+}
+
+// A (L u) of the four cells of a quad in difference form (neighbour minus
+// centre, which keeps the float32 residual free of cancellation); a
+// neighbour across the patch face is the ghost -u, so its coefficient
+// enters twice.
+template <typename T, int HH>
+__device__ __forceinline__ void qalap(const QLds<T, HH>& t, const QRow<T>& rw, const Quad<T>& Qd,
+                                      int gi, int gj, int n, T AL[4]) {
+  using G = QT<T, HH>;
+  constexpr int S = G::S, P = G::PAR;
+  const T* ub = t.u + Qd.b;
+  const T* u = Qd.u;
+  const T nb[4][4] = {{ub[0], u[2], ub[P + S - 1], u[1]},
+                      {ub[P], u[3], u[0], ub[S + 1]},
+                      {u[0], ub[3 * S], ub[P + 2 * S - 1], u[3]},
+                      {u[1], ub[P + 3 * S], u[2], ub[2 * S + 1]}};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int aa = c >> 1, bb = c & 1;
+    const T sm = aa ? rw.sm1 : rw.sm0, sp = aa ? rw.sp1 : rw.sp0, isc = aa ? rw.is1 : rw.is0;
+    const T x = u[c];
+    const int ci = gi + aa, cj = gj + bb;
+    T v = sm * (nb[c][0] - x) + sp * (nb[c][1] - x) + isc * ((nb[c][2] - x) + (nb[c][3] - x));
+    if (Qd.edge) {
+      if (ci == 0) v -= sm * x;
+      if (ci == n - 1) v -= sp * x;
+      if (cj == 0) v -= isc * x;
+      if (cj == n - 1) v -= isc * x;
+    }
+    AL[c] = v;
+  }
+}
+
+template <typename T, int HH>
+__device__ __forceinline__ bool interior_quad(const QRow<T>& rw, const Quad<T>& Qd) {
+  using G = QT<T, HH>;
+  return Qd.live && rw.qi >= G::QH && rw.qi < G::QH + kTile / 2 && Qd.qj >= G::QH &&
+         Qd.qj < G::QH + kTile / 2;
 }
 
 template <typename T, int HH>
 __global__ __launch_bounds__(kTileBlock) void k_mg_pre(TileArgs<T> a) {
   using G = QT<T, HH>;
-  __shared__ QLds<T, G::RR> t;
-  QRegs<T, G::IT> r;
+  __shared__ QLds<T, HH> t;
+  QRow<T> rw;
+  Quad<T> qd[G::IT];
   const int64_t lb = xcd_block();
   const int tpp = a.ntile * a.ntile;
   const int64_t patch = lb / tpp;
   const int tt = int(lb % tpp);
   const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
-  const int n = a.n;
-  const size_t pbase = size_t(patch) * n * n;
+  const int n = a.n, nc = n / 2;
+  const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
   qload_rows(t, a.coef, n, i0);
-  qload<T, HH>(t, r, a.u_in, a.f_in, pbase, n, i0, j0);
+  __syncthreads();
+  qinit<T, HH>(t, rw, qd, a.u_in ? a.u_in + pbase : nullptr, a.f_in + pbase, false, n, i0, j0);
+  qput<T, HH>(t, qd);
   __syncthreads();
   if (a.fas_source) {
-    // f = L_H ubar + rbar on the in-patch cells away from the region edge
+    // A f = A L_H ubar + A rbar on the in-patch cells
 #pragma unroll
     for (int it = 0; it < G::IT; ++it) {
-      const int q = threadIdx.x + it * kTileBlock;
-      if (q >= G::NQ) continue;
-      const int qi = q / G::Q, qj = q - qi * G::Q;
+      Quad<T>& Qd = qd[it];
+      if (!Qd.live) continue;
+      T AL[4];
+      qalap<T, HH>(t, rw, Qd, i0 + 2 * rw.qi, j0 + 2 * Qd.qj, n, AL);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int li = 2 * qi + (c >> 1), lj = 2 * qj + (c & 1);
-        const int gi = i0 + li, gj = j0 + lj;
-        if (li >= 1 && li <= G::RR - 2 && lj >= 1 && lj <= G::RR - 2 && gi >= 0 && gi < n &&
-            gj >= 0 && gj < n)
-          r.f[it][c] += qlap<T, HH>(t, r.u[it], qi, qj, c >> 1, c & 1, i0, j0, n);
-      }
+      for (int c = 0; c < 4; ++c) Qd.ft[c] = Qd.rD[c] != T(0) ? Qd.ft[c] + AL[c] : T(0);
     }
+    __syncthreads();
   }
   for (int s = 0; s < a.nu; ++s) {
-    qsweep<T, HH>(t, r, 0, i0, j0, n);
+    qsweep<T, HH>(t, rw, qd, 0);
     __syncthreads();
-    qsweep<T, HH>(t, r, 1, i0, j0, n);
+    qsweep<T, HH>(t, rw, qd, 1);
     __syncthreads();
   }
-  // interior quads: store u (and f), residual, area-weighted restriction
-  const int nc = n / 2;
-  const size_t cbase = size_t(patch) * nc * nc;
+  // interior quads: store u (and A f), residual, area-weighted restriction
+  T* uo = a.u_out + pbase;
+  T* ubo = a.ubar_out + cbase;
+  T* rbo = a.rbar_out + cbase;
+  const int li = 2 * rw.qi;
+  const T a0 = t.A[li], a1 = t.A[li + 1], rden = t.rden[rw.qi];
 #pragma unroll
   for (int it = 0; it < G::IT; ++it) {
-    const int q = threadIdx.x + it * kTileBlock;
-    const int qi = q / G::Q, qj = q - qi * G::Q;
-    if (q >= G::NQ || qi < G::QH || qi >= G::QH + kTile / 2 || qj < G::QH ||
-        qj >= G::QH + kTile / 2)
-      continue;
-    const int gi = i0 + 2 * qi, gj = j0 + 2 * qj;
-    const size_t g = pbase + size_t(gi) * n + gj;
-    store2(a.u_out + g, r.u[it][0], r.u[it][1]);
-    store2(a.u_out + g + n, r.u[it][2], r.u[it][3]);
+    Quad<T>& Qd = qd[it];
+    if (!interior_quad<T, HH>(rw, Qd)) continue;
+    const int gi = i0 + li, gj = j0 + 2 * Qd.qj;
+    const int g = gi * n + gj;
+    store2(uo + g, Qd.u[0], Qd.u[1]);
+    store2(uo + g + n, Qd.u[2], Qd.u[3]);
     if (a.fas_source) {
-      store2(a.f_out + g, r.f[it][0], r.f[it][1]);
-      store2(a.f_out + g + n, r.f[it][2], r.f[it][3]);
+      T* fo = a.f_out + pbase;
+      store2(fo + g, Qd.ft[0], Qd.ft[1]);
+      store2(fo + g + n, Qd.ft[2], Qd.ft[3]);
     }
-    T res[4];
+    // A r = A f - A L u, summed over the quad
+    T AL[4];
+    qalap<T, HH>(t, rw, Qd, gi, gj, n, AL);
+    const T ar = ((Qd.ft[0] - AL[0]) + (Qd.ft[1] - AL[1])) + ((Qd.ft[2] - AL[2]) + (Qd.ft[3] - AL[3]));
+    const int gc = (gi / 2) * nc + gj / 2;
+    ubo[gc] = (a0 * (Qd.u[0] + Qd.u[1]) + a1 * (Qd.u[2] + Qd.u[3])) * rden;
+    rbo[gc] = ar * rden;
+  }
+}
+
+template <typename T, int HH>
+__global__ __launch_bounds__(kTileBlock) void k_mg_post(TileArgs<T> a) {
+  using G = QT<T, HH>;
+  constexpr int CR = G::Q + 2;  // coarse cells covering the region quads +- 1
+  __shared__ QLds<T, HH> t;
+  __shared__ T e[CR * CR];
+  QRow<T> rw;
+  Quad<T> qd[G::IT];
+  const int64_t lb = xcd_block();
+  const int tpp = a.ntile * a.ntile;
+  const int64_t patch = lb / tpp;
+  const int tt = int(lb % tpp);
+  const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
+  const int n = a.n, nc = n / 2;
+  const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
+  const int ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // i0, j0 even
+  qload_rows(t, a.coef, n, i0);
+  for (int item = threadIdx.x; item < CR * CR; item += kTileBlock) {
+    const int I = ci0 + item / CR, J = cj0 + item % CR;
+    T v = T(0);
+    if (I >= 0 && I < nc && J >= 0 && J < nc) {
+      const size_t g = cbase + size_t(I) * nc + J;
+      v = a.uc[g] - a.ubarc[g];
+    }
+    e[item] = v;
+  }
+  __syncthreads();
+  qinit<T, HH>(t, rw, qd, a.u_in + pbase, a.f_in + pbase, a.f_scaled != 0, n, i0, j0);
+  // coarse correction: bilinear (9, 3, 3, 1)/16 of the parent and its
+  // neighbours toward the child, direct injection of the parent on the
+  // outermost fine ring
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      res[c] = r.f[it][c] - qlap<T, HH>(t, r.u[it], qi, qj, c >> 1, c & 1, i0, j0, n);
-    const int li = 2 * qi;
-    const T a0 = t.A[li], a1 = t.A[li + 1];
-    const T den = T(2) * (a0 + a1);
-    const size_t gc = cbase + size_t(gi / 2) * nc + gj / 2;
-    a.ubar_out[gc] = (a0 * (r.u[it][0] + r.u[it][1]) + a1 * (r.u[it][2] + r.u[it][3])) / den;
-    a.rbar_out[gc] = (a0 * (res[0] + res[1]) + a1 * (res[2] + res[3])) / den;
+  for (int it = 0; it < G::IT; ++it) {
+    Quad<T>& Qd = qd[it];
+    if (!Qd.live) continue;
+    const T* ec = e + (rw.qi + 1) * CR + (Qd.qj + 1);
+    const T c = ec[0];
+    const T nu = ec[-CR], nd = ec[CR], nl = ec[-1], nr = ec[1];
+    const T ul = ec[-CR - 1], ur = ec[-CR + 1], dl = ec[CR - 1], dr = ec[CR + 1];
+    const T p[4] = {(T(9) * c + T(3) * (nu + nl) + ul) * T(0.0625),
+                    (T(9) * c + T(3) * (nu + nr) + ur) * T(0.0625),
+                    (T(9) * c + T(3) * (nd + nl) + dl) * T(0.0625),
+                    (T(9) * c + T(3) * (nd + nr) + dr) * T(0.0625)};
+    const int gi = i0 + 2 * rw.qi, gj = j0 + 2 * Qd.qj;
+    if (Qd.edge) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int ci = gi + (k >> 1), cj = gj + (k & 1);
+        const bool ring = ci == 0 || ci == n - 1 || cj == 0 || cj == n - 1;
+        const T corr = ring ? c : p[k];
+        Qd.u[k] += Qd.rD[k] != T(0) ? corr : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Qd.u[k] += Qd.rD[k] != T(0) ? p[k] : T(0);
+    }
+  }
+  qput<T, HH>(t, qd);
+  __syncthreads();
+  for (int s = 0; s < a.nu; ++s) {
+    qsweep<T, HH>(t, rw, qd, 0);
+    __syncthreads();
+    qsweep<T, HH>(t, rw, qd, 1);
+    __syncthreads();
+  }
+  T* uo = a.u_out + pbase;
+#pragma unroll
+  for (int it = 0; it < G::IT; ++it) {
+    const Quad<T>& Qd = qd[it];
+    if (!interior_quad<T, HH>(rw, Qd)) continue;
+    const int g = (i0 + 2 * rw.qi) * n + (j0 + 2 * Qd.qj);
+    store2(uo + g, Qd.u[0], Qd.u[1]);
+    store2(uo + g + n, Qd.u[2], Qd.u[3]);
   }
 }
 
@@ -547,68 +714,6 @@ __device__ __forceinline__ T prolong_cell(int gi, int gj, int n, EF e) {
   const int di = (gi & 1) ? 1 : -1, dj = (gj & 1) ? 1 : -1;
   return (T(9) * e(I, J) + T(3) * e(I + di, J) + T(3) * e(I, J + dj) + e(I + di, J + dj)) /
          T(16);
-}
-
-template <typename T, int HH>
-__global__ __launch_bounds__(kTileBlock) void k_mg_post(TileArgs<T> a) {
-  using G = QT<T, HH>;
-  constexpr int CR = G::Q + 2;  // coarse cells covering the region quads +- 1
-  __shared__ QLds<T, G::RR> t;
-  __shared__ T e[CR * CR];
-  QRegs<T, G::IT> r;
-  const int64_t lb = xcd_block();
-  const int tpp = a.ntile * a.ntile;
-  const int64_t patch = lb / tpp;
-  const int tt = int(lb % tpp);
-  const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
-  const int n = a.n, nc = n / 2;
-  const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
-  const int ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // i0, j0 even
-  qload_rows(t, a.coef, n, i0);
-  qload<T, HH>(t, r, a.u_in, a.f_in, pbase, n, i0, j0);
-  for (int item = threadIdx.x; item < CR * CR; item += kTileBlock) {
-    const int I = ci0 + item / CR, J = cj0 + item % CR;
-    T v = T(0);
-    if (I >= 0 && I < nc && J >= 0 && J < nc) {
-      const size_t g = cbase + size_t(I) * nc + J;
-      v = a.uc[g] - a.ubarc[g];
-    }
-    e[item] = v;
-  }
-  __syncthreads();
-  auto ef = [&](int I, int J) { return e[(I - ci0) * CR + (J - cj0)]; };
-#pragma unroll
-  for (int it = 0; it < G::IT; ++it) {
-    const int q = threadIdx.x + it * kTileBlock;
-    if (q >= G::NQ) continue;
-    const int qi = q / G::Q, qj = q - qi * G::Q;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int li = 2 * qi + (c >> 1), lj = 2 * qj + (c & 1);
-      const int gi = i0 + li, gj = j0 + lj;
-      if (gi < 0 || gi >= n || gj < 0 || gj >= n) continue;
-      r.u[it][c] += prolong_cell<T>(gi, gj, n, ef);
-      qcell(t, li, lj) = r.u[it][c];
-    }
-  }
-  __syncthreads();
-  for (int s = 0; s < a.nu; ++s) {
-    qsweep<T, HH>(t, r, 0, i0, j0, n);
-    __syncthreads();
-    qsweep<T, HH>(t, r, 1, i0, j0, n);
-    __syncthreads();
-  }
-#pragma unroll
-  for (int it = 0; it < G::IT; ++it) {
-    const int q = threadIdx.x + it * kTileBlock;
-    const int qi = q / G::Q, qj = q - qi * G::Q;
-    if (q >= G::NQ || qi < G::QH || qi >= G::QH + kTile / 2 || qj < G::QH ||
-        qj >= G::QH + kTile / 2)
-      continue;
-    const size_t g = pbase + size_t(i0 + 2 * qi) * n + (j0 + 2 * qj);
-    store2(a.u_out + g, r.u[it][0], r.u[it][1]);
-    store2(a.u_out + g + n, r.u[it][2], r.u[it][3]);
-  }
 }
 
 // ------------------------------------------------------------ LDS levels
@@ -980,6 +1085,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       } else {
         a.u_in = static_cast<T*>(p->ulev[l]);
         a.f_in = static_cast<T*>(p->flev[l]);
+        a.f_scaled = 1;
         a.u_out = static_cast<T*>(p->ulev2[l]);
       }
       {
