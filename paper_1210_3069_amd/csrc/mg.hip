@@ -405,8 +405,20 @@ __device__ __forceinline__ void qload_rows(QLds<T, HH>& t, const double* coef, i
     }
     t.rden[k] = T(1.0 / (2.0 * (a0 + a1)));
   }
-  // guard ring and every cell start at zero
-  for (int k = threadIdx.x; k < 2 * G::PAR; k += kTileBlock) t.u[k] = T(0);
+  // the guard ring of both parity arrays is zero (every region cell is
+  // written by its quad)
+  constexpr int NG = 2 * G::S + 2 * G::RR;
+  for (int k = threadIdx.x; k < 2 * NG; k += kTileBlock) {
+    const int par = k / NG, g = k - par * NG;
+    int idx;
+    if (g < 2 * G::S)
+      idx = (g < G::S ? 0 : (G::RR + 1) * G::S) + (g % G::S);
+    else {
+      const int h = g - 2 * G::S, r = 1 + (h >> 1);
+      idx = r * G::S + ((h & 1) ? G::S - 1 : 0);
+    }
+    t.u[par * G::PAR + idx] = T(0);
+  }
 }
 
 // Diagonal of the in-patch cell (gi, gj): the interior one plus, across a
@@ -534,17 +546,18 @@ __device__ __forceinline__ void qalap(const QLds<T, HH>& t, const QRow<T>& rw, c
   constexpr int S = G::S, P = G::PAR;
   const T* ub = t.u + Qd.b;
   const T* u = Qd.u;
-  const T nb[4][4] = {{ub[0], u[2], ub[P + S - 1], u[1]},
-                      {ub[P], u[3], u[0], ub[S + 1]},
-                      {u[0], ub[3 * S], ub[P + 2 * S - 1], u[3]},
-                      {u[1], ub[P + 3 * S], u[2], ub[2 * S + 1]}};
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
+    const T nb0 = c == 0 ? ub[0] : c == 1 ? ub[P] : c == 2 ? u[0] : u[1];
+    const T nb1 = c == 0 ? u[2] : c == 1 ? u[3] : c == 2 ? ub[3 * S] : ub[P + 3 * S];
+    const T nb2 = c == 0 ? ub[P + S - 1] : c == 1 ? u[0] : c == 2 ? ub[P + 2 * S - 1] : u[2];
+    const T nb3 = c == 0 ? u[1] : c == 1 ? ub[S + 1] : c == 2 ? u[3] : ub[2 * S + 1];
+    const T nb[1][4] = {{nb0, nb1, nb2, nb3}};
     const int aa = c >> 1, bb = c & 1;
     const T sm = aa ? rw.sm1 : rw.sm0, sp = aa ? rw.sp1 : rw.sp0, isc = aa ? rw.is1 : rw.is0;
     const T x = u[c];
     const int ci = gi + aa, cj = gj + bb;
-    T v = sm * (nb[c][0] - x) + sp * (nb[c][1] - x) + isc * ((nb[c][2] - x) + (nb[c][3] - x));
+    T v = sm * (nb[0][0] - x) + sp * (nb[0][1] - x) + isc * ((nb[0][2] - x) + (nb[0][3] - x));
     if (Qd.edge) {
       if (ci == 0) v -= sm * x;
       if (ci == n - 1) v -= sp * x;
@@ -618,7 +631,9 @@ __global__ __launch_bounds__(kTileBlock) void k_mg_pre(TileArgs<T> a) {
       store2(fo + g, Qd.ft[0], Qd.ft[1]);
       store2(fo + g + n, Qd.ft[2], Qd.ft[3]);
     }
-    // A r = A f - A L u, summed over the quad
+    // A r = A f - A L u, summed over the quad (formed at all four cells:
+    // in float32 the cells the last half sweep updated carry the rounding
+    // of that update, which the coarse correction must see)
     T AL[4];
     qalap<T, HH>(t, rw, Qd, gi, gj, n, AL);
     const T ar = ((Qd.ft[0] - AL[0]) + (Qd.ft[1] - AL[1])) + ((Qd.ft[2] - AL[2]) + (Qd.ft[3] - AL[3]));
