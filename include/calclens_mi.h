@@ -59,7 +59,10 @@ typedef enum {
   CLM_EUNSUPPORTED = 7      /* valid request this build does not implement   */
 } clm_status;
 
-typedef enum { CLM_FP64 = 0, CLM_FP32 = 1 } clm_precision;
+/* Arithmetic forms.  CLM_BF16X3 (Legendre transforms only): each operand is
+ * split into bf16 hi + lo and the products hi*hi + hi*lo + lo*hi are
+ * accumulated in float32 on the matrix cores. */
+typedef enum { CLM_FP64 = 0, CLM_FP32 = 1, CLM_BF16X3 = 2 } clm_precision;
 typedef enum { CLM_SOLVER_SHT = 0, CLM_SOLVER_SHT_MG = 1 } clm_solver;
 typedef enum { CLM_ORDER_RING = 0, CLM_ORDER_NESTED = 1 } clm_order;
 
@@ -84,6 +87,11 @@ typedef struct {
   int32_t solver;        /* clm_solver                                         */
   int32_t mg_prec;       /* clm_precision of the multigrid correction          */
   int32_t max_planes;    /* solution slots held by the plan, >= 1              */
+  int32_t legendre_prec; /* clm_precision of the Legendre transforms: CLM_FP64
+                            (per plane, vector FP64), or CLM_FP32 / CLM_BF16X3
+                            (matrix cores; the planes of one clm_poisson_solve
+                            call are batched as GEMM columns, 16 at a time;
+                            the lambda_lm recurrence stays FP64)           */
 } clm_plan_desc;
 
 /* Fill *d with the defaults for a fine grid: nside_sht = nside_fine / 8

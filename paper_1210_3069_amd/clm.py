@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libcalclens_mi.so")
 
 CLM_OK, CLM_EINVAL, CLM_ENOMEM, CLM_EHIP = 0, 1, 2, 3
 CLM_ENOTCONV, CLM_ERAY_LEFT_PATCH, CLM_ENONFINITE, CLM_EUNSUPPORTED = 4, 5, 6, 7
-FP64, FP32 = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
 SOLVER_SHT, SOLVER_SHT_MG = 0, 1
 ORDER_RING, ORDER_NESTED = 0, 1
 
@@ -21,7 +21,8 @@ ORDER_RING, ORDER_NESTED = 0, 1
 class PlanDesc(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "nside_fine", "nside_sht", "lmax", "nside_bundle", "patch_factor", "patch_cells",
-        "mg_vcycles", "nu_pre", "nu_post", "solver", "mg_prec", "max_planes")]
+        "mg_vcycles", "nu_pre", "nu_post", "solver", "mg_prec", "max_planes",
+        "legendre_prec")]
 
 
 class Rays(ctypes.Structure):
@@ -125,8 +126,8 @@ class Plan:
         for k, v in kw.items():
             if k == "solver" and isinstance(v, str):
                 v = {"sht": SOLVER_SHT, "sht_mg": SOLVER_SHT_MG}[v]
-            if k == "mg_prec" and isinstance(v, str):
-                v = {"fp64": FP64, "fp32": FP32}[v]
+            if k in ("mg_prec", "legendre_prec") and isinstance(v, str):
+                v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}[v]
             setattr(d, k, int(v))
         dev = torch.cuda.current_device() if device is None else int(device)
         h = ctypes.c_void_p()

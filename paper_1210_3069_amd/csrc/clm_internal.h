@@ -61,12 +61,19 @@ struct Plan {
   double* rot = nullptr;        // [nbundle][9] patch rotations R_b
   double* coef = nullptr;       // level row coefficients
   double* cinv = nullptr;       // [16*16] inverse of the coarsest operator
+  double* rcoef = nullptr;      // [nalm][2] Legendre recurrence a_l, b_l (matrix-core SHT)
 
   // scratch
   double* kap_s = nullptr;      // [npix_s] degraded, demeaned kappa
   double* F = nullptr;          // [nring_s][lmax+1] complex
   double* G = nullptr;          // [5][nring_s][lmax+1] complex (synthesis)
   double* red = nullptr;        // [1024] reduction partials; red[1023] = mean
+  // matrix-core SHT of a batch of planes (legendre_prec FP32 / BF16X3)
+  int batch = 0;                // planes per GEMM batch (<= 16)
+  double* Fb = nullptr;         // [batch][nring_s][lmax+1] complex ring transforms
+  double* Gb = nullptr;         // [batch][nring_s][lmax+1] complex synthesis sums
+  float* apart = nullptr;       // [ring blocks][nalm][32] analysis partial sums
+  float* psib = nullptr;        // [nalm][32] psi_lm as GEMM columns
   double* deriv = nullptr;      // [5][npix_s] pure-SHT raw derivative maps
   void* fprime = nullptr;       // [npatch][n^2] T
   void* dutmp = nullptr;        // [npatch][n^2] T (ping-pong partner of du)
@@ -137,6 +144,14 @@ inline clm_status fail(Plan* p, clm_status s, const std::string& msg) {
 clm_status build_tables(Plan* p);                       // plan.hip
 clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot,
                      hipStream_t s);                    // sht.hip
+clm_status plane_mean(Plan* p, const void* kappa, int kappa_fp64,
+                      hipStream_t s);                   // sht.hip: red[1023] = mean
+clm_status sht_solve_batch(Plan* p, const void* kappa, int kappa_fp64, int first_slot,
+                           int nplanes, hipStream_t s);  // sht.hip
+int mfma_ring_blocks(int H);                             // sht_mfma.hip
+clm_status mfma_tables(Plan* p, hipStream_t s);
+clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s);
+clm_status mfma_synthesis(Plan* p, int first_slot, int P, hipStream_t s);
 clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64,
                             void* grad, void* hess, hipStream_t s);  // sht.hip
 clm_status mg_solve(Plan* p, const void* kappa, int kappa_fp64, int slot,

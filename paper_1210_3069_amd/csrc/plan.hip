@@ -33,6 +33,7 @@ Plan::~Plan() {
   f(ring_s); f(ringi_s); f(ringx_s); f(ring_f); f(ringi_f); f(ringx_f); f(lam_mant);
   f(lam_scale);
   f(r2n_s); f(r2n_f); f(rot); f(coef); f(cinv); f(kap_s); f(F); f(G); f(red);
+  f(rcoef); f(Fb); f(Gb); f(apart); f(psib);
   f(deriv); f(fprime); f(dutmp); f(status_dev);
   for (auto* q : ubar) f(q);
   for (auto* q : rbar) f(q);
@@ -319,7 +320,9 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
   const clm_plan_desc& d = *desc;
   if (!pow2(d.nside_fine) || !pow2(d.nside_sht) || d.nside_sht > d.nside_fine ||
       d.nside_fine > 8192 || d.lmax < 1 || d.max_planes < 1 ||
-      (d.solver != CLM_SOLVER_SHT && d.solver != CLM_SOLVER_SHT_MG))
+      (d.solver != CLM_SOLVER_SHT && d.solver != CLM_SOLVER_SHT_MG) ||
+      (d.legendre_prec != CLM_FP64 && d.legendre_prec != CLM_FP32 &&
+       d.legendre_prec != CLM_BF16X3))
     return CLM_EINVAL;
   if (d.solver == CLM_SOLVER_SHT && d.nside_sht != d.nside_fine) return CLM_EINVAL;
   if (d.solver == CLM_SOLVER_SHT_MG) {
@@ -375,6 +378,17 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
   if ((s = alloc(p, &p->red, 1024)) != CLM_OK) return bail(s);
   if ((s = alloc(p, &p->status_dev, 1)) != CLM_OK) return bail(s);
   if (hipMemset(p->status_dev, 0, sizeof(int)) != hipSuccess) return bail(CLM_EHIP);
+  if (d.legendre_prec != CLM_FP64) {
+    p->batch = d.max_planes < 16 ? d.max_planes : 16;
+    if ((s = alloc(p, &p->rcoef, size_t(p->nalm) * 2)) != CLM_OK) return bail(s);
+    if ((s = alloc(p, &p->Fb, size_t(nF) * p->batch)) != CLM_OK) return bail(s);
+    if ((s = alloc(p, &p->Gb, size_t(nF) * p->batch)) != CLM_OK) return bail(s);
+    if ((s = alloc(p, &p->psib, size_t(p->nalm) * 32)) != CLM_OK) return bail(s);
+    const int R = mfma_ring_blocks(p->H);
+    if (R > 1 && (s = alloc(p, &p->apart, size_t(R) * p->nalm * 32)) != CLM_OK) return bail(s);
+    if ((s = mfma_tables(p, nullptr)) != CLM_OK) return bail(s);
+    if (hipDeviceSynchronize() != hipSuccess) return bail(CLM_EHIP);
+  }
 
   const size_t esz = p->fp64mg ? 8 : 4;
   p->slots.resize(d.max_planes);
@@ -512,6 +526,23 @@ clm_status clm_poisson_solve(clm_plan plan, const void* kappa, int32_t kappa_is_
   Plan* p = plan;
   CLM_HIP(hipSetDevice(p->device));
   const size_t esz = kappa_is_fp64 ? 8 : 4;
+  if (p->batch > 0) {
+    // matrix-core Legendre transforms: planes batched as GEMM columns; the
+    // multigrid then runs per plane, after that plane's mean is taken again
+    for (int k0 = 0; k0 < nplanes; k0 += p->batch) {
+      const int nb = nplanes - k0 < p->batch ? nplanes - k0 : p->batch;
+      const char* kp = static_cast<const char*>(kappa) + size_t(k0) * p->npix_f * esz;
+      clm_status s = sht_solve_batch(p, kp, kappa_is_fp64, first_slot + k0, nb, stream);
+      if (s != CLM_OK) return s;
+      for (int k = 0; p->mg && k < nb; ++k) {
+        const char* kk = kp + size_t(k) * p->npix_f * esz;
+        if ((s = plane_mean(p, kk, kappa_is_fp64, stream)) != CLM_OK) return s;
+        if ((s = mg_solve(p, kk, kappa_is_fp64, first_slot + k0 + k, stream)) != CLM_OK)
+          return s;
+      }
+    }
+    return CLM_OK;
+  }
   for (int k = 0; k < nplanes; ++k) {
     const char* kp = static_cast<const char*>(kappa) + size_t(k) * p->npix_f * esz;
     clm_status s = sht_solve(p, kp, kappa_is_fp64, first_slot + k, stream);

@@ -541,13 +541,13 @@ size_t ring_inv_lds(int nside, int lmax) {
   return best * sizeof(double);
 }
 
-clm_status ring_forward(Plan* p, const double* map, hipStream_t s) {
+clm_status ring_forward(Plan* p, const double* map, double* F, hipStream_t s) {
   const size_t shm = ring_fwd_lds(p->d.nside_sht, p->d.lmax);
   if (allow_lds(p, k_ring_forward, shm) != CLM_OK) return CLM_EHIP;
   {
     CLM_TIMED(p, s, "sht_ring_forward");
     hipLaunchKernelGGL(k_ring_forward, dim3(p->nring_s), dim3(kBlock), shm, s, map, p->ring_s,
-                       p->ringi_s, p->d.lmax, p->F);
+                       p->ringi_s, p->d.lmax, F);
   }
   CLM_LAUNCH_CHECK();
   return CLM_OK;
@@ -590,21 +590,16 @@ clm_status ring_inverse(Plan* p, const double* G, int nf, double* out, hipStream
 
 }  // namespace
 
-clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
-  const clm_plan_desc& d = p->d;
-  if (ring_fwd_lds(d.nside_sht, d.lmax) > 160 * 1024 ||
-      ring_inv_lds(d.nside_sht, d.lmax) > 160 * 1024)
-    return fail(p, CLM_EUNSUPPORTED, "ring transforms exceed the LDS for this nside/lmax");
+clm_status plane_mean(Plan* p, const void* kappa, int kappa_fp64, hipStream_t s) {
   const int nb = 1023;
-  // mean of the fine map
   {
-  CLM_TIMED(p, s, "mean");
-  if (kappa_fp64)
-    hipLaunchKernelGGL(k_partial_sum<double>, dim3(nb), dim3(kBlock), 0, s,
-                       static_cast<const double*>(kappa), p->npix_f, p->red);
-  else
-    hipLaunchKernelGGL(k_partial_sum<float>, dim3(nb), dim3(kBlock), 0, s,
-                       static_cast<const float*>(kappa), p->npix_f, p->red);
+    CLM_TIMED(p, s, "mean");
+    if (kappa_fp64)
+      hipLaunchKernelGGL(k_partial_sum<double>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const double*>(kappa), p->npix_f, p->red);
+    else
+      hipLaunchKernelGGL(k_partial_sum<float>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const float*>(kappa), p->npix_f, p->red);
   }
   CLM_LAUNCH_CHECK();
   {
@@ -613,22 +608,49 @@ clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipSt
                        1.0 / double(p->npix_f));
   }
   CLM_LAUNCH_CHECK();
-  // degrade
+  return CLM_OK;
+}
+
+namespace {
+
+// Mean, demean + degrade to the SHT grid and the ring transforms into F.
+clm_status sht_front(Plan* p, const void* kappa, int kappa_fp64, double* F, hipStream_t s) {
+  const clm_plan_desc& d = p->d;
+  if (ring_fwd_lds(d.nside_sht, d.lmax) > 160 * 1024 ||
+      ring_inv_lds(d.nside_sht, d.lmax) > 160 * 1024)
+    return fail(p, CLM_EUNSUPPORTED, "ring transforms exceed the LDS for this nside/lmax");
+  clm_status st = plane_mean(p, kappa, kappa_fp64, s);
+  if (st != CLM_OK) return st;
   const int64_t ratio = d.nside_fine / d.nside_sht;
   const int64_t k2 = ratio * ratio;
   {
-  CLM_TIMED(p, s, "degrade");
-  if (kappa_fp64)
-    hipLaunchKernelGGL(k_degrade<double>, dim3((p->npix_s + kBlock - 1) / kBlock),
-                       dim3(kBlock), 0, s, static_cast<const double*>(kappa),
-                       int64_t(d.nside_fine), p->npix_s, p->r2n_s, k2, p->red, p->kap_s);
-  else
-    hipLaunchKernelGGL(k_degrade<float>, dim3((p->npix_s + kBlock - 1) / kBlock),
-                       dim3(kBlock), 0, s, static_cast<const float*>(kappa),
-                       int64_t(d.nside_fine), p->npix_s, p->r2n_s, k2, p->red, p->kap_s);
+    CLM_TIMED(p, s, "degrade");
+    if (kappa_fp64)
+      hipLaunchKernelGGL(k_degrade<double>, dim3((p->npix_s + kBlock - 1) / kBlock),
+                         dim3(kBlock), 0, s, static_cast<const double*>(kappa),
+                         int64_t(d.nside_fine), p->npix_s, p->r2n_s, k2, p->red, p->kap_s);
+    else
+      hipLaunchKernelGGL(k_degrade<float>, dim3((p->npix_s + kBlock - 1) / kBlock),
+                         dim3(kBlock), 0, s, static_cast<const float*>(kappa),
+                         int64_t(d.nside_fine), p->npix_s, p->r2n_s, k2, p->red, p->kap_s);
   }
   CLM_LAUNCH_CHECK();
-  clm_status st = ring_forward(p, p->kap_s, s);
+  return ring_forward(p, p->kap_s, F, s);
+}
+
+clm_status poisson(Plan* p, double* alm, hipStream_t s) {
+  {
+    CLM_TIMED(p, s, "sht_poisson");
+    hipLaunchKernelGGL(k_poisson, dim3(p->d.lmax + 1), dim3(kBlock), 0, s, alm, p->d.lmax);
+  }
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+}  // namespace
+
+clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
+  clm_status st = sht_front(p, kappa, kappa_fp64, p->F, s);
   if (st != CLM_OK) return st;
   double* alm = p->slots[slot].alm;
   const int rpt = rpt_for(p->H);
@@ -641,13 +663,29 @@ clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipSt
     default: return fail(p, CLM_EUNSUPPORTED, "too many rings per thread");
   }
   CLM_LAUNCH_CHECK();
-  {
-    CLM_TIMED(p, s, "sht_poisson");
-    hipLaunchKernelGGL(k_poisson, dim3(d.lmax + 1), dim3(kBlock), 0, s, alm, d.lmax);
-  }
-  CLM_LAUNCH_CHECK();
+  if ((st = poisson(p, alm, s)) != CLM_OK) return st;
   if ((st = synthesis(p, alm, s)) != CLM_OK) return st;
   return ring_inverse(p, p->G, 1, p->slots[slot].psi_s, s);
+}
+
+clm_status sht_solve_batch(Plan* p, const void* kappa, int kappa_fp64, int first_slot,
+                           int nplanes, hipStream_t s) {
+  if (nplanes < 1 || nplanes > p->batch) return fail(p, CLM_EINVAL, "batch size");
+  const size_t nF = size_t(p->nring_s) * (p->d.lmax + 1) * 2;
+  const size_t esz = kappa_fp64 ? 8 : 4;
+  clm_status st;
+  for (int k = 0; k < nplanes; ++k) {
+    const char* kp = static_cast<const char*>(kappa) + size_t(k) * p->npix_f * esz;
+    if ((st = sht_front(p, kp, kappa_fp64, p->Fb + k * nF, s)) != CLM_OK) return st;
+  }
+  if ((st = mfma_analysis(p, first_slot, nplanes, s)) != CLM_OK) return st;
+  for (int k = 0; k < nplanes; ++k)
+    if ((st = poisson(p, p->slots[first_slot + k].alm, s)) != CLM_OK) return st;
+  if ((st = mfma_synthesis(p, first_slot, nplanes, s)) != CLM_OK) return st;
+  for (int k = 0; k < nplanes; ++k)
+    if ((st = ring_inverse(p, p->Gb + k * nF, 1, p->slots[first_slot + k].psi_s, s)) != CLM_OK)
+      return st;
+  return CLM_OK;
 }
 
 clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* grad, void* hess,

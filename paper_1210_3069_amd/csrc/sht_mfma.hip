@@ -1,0 +1,454 @@
+// Batched Legendre transforms on the matrix cores (Sec. 3.1: the a_lm sum
+// over rings and its synthesis, in the SHT step of the SHT+MG solve).
+//
+// For a fixed m the analysis over P planes is a real matrix product
+//   a[l][c] = sum_q lambda_lm(theta_q) X[q][c],   c = 2 p + (re, im),
+// with X = F_m(q) + F_m(q') (l - m even) or F_m(q) - F_m(q') (l - m odd) on
+// the north rings q and their mirrors q' (the equator counted once), and the
+// synthesis is its transpose, G^{even/odd}[q][c] = sum_l lambda_lm(theta_q)
+// psi[l][c], north = even + odd, south = even - odd.  The planes are the
+// GEMM columns.  lambda_lm is never stored: each lane runs the scaled FP64
+// recurrence of one ring, 32 values of l at a time, and the wave stages the
+// values in LDS for the MFMA operands.
+//
+// Forms: FP32 (lambda and X rounded to float32, v_mfma_f32_16x16x4f32) and
+// BF16x3 (each operand split into bf16 hi + lo, products hi*hi + hi*lo +
+// lo*hi accumulated in float32 with v_mfma_f32_16x16x16bf16_1k).  The
+// recurrence, its scaling and the final weights stay in FP64.
+#include <cmath>
+
+#include "clm_internal.h"
+
+namespace clm {
+namespace {
+
+constexpr double kHugeB = 0x1p400;    // rescale threshold of the scaled recurrence
+constexpr double kSmallB = 0x1p-800;  // rescale factor
+constexpr int kStep = 32;             // values of l generated per step (16 per parity)
+constexpr int kCols = 32;             // GEMM columns: 2 x up to 16 planes
+constexpr int kMaxWaves = 16;
+constexpr int kBlk = 256;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+enum Form : int { kFP32 = 0, kBF16X3 = 1 };
+
+// Row stride (floats) of a wave's lambda tile [32 l][64 rings].  Analysis
+// reads, per lane, row 2 i + parity at a column group; synthesis reads
+// column 16 mb + i at rows 2 (4 j + k) + parity.
+template <int FORM> struct AnaStride { static constexpr int S = 65; };
+template <> struct AnaStride<kBF16X3> { static constexpr int S = 68; };
+constexpr int kSynStride = 72;
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = __bf16(x);
+  lo = __bf16(x - float(hi));
+}
+
+// One ring's recurrence for fixed m: p1 = the latest lambda, p2 the one
+// before, scale exponent s (< 0: below 2^-800 relative to the true value).
+struct Rec {
+  double z, p1, p2;
+  int s;
+};
+
+// lambda_lm at dl = l - m as float (0 below range), advancing the state for
+// dl >= 1: lambda_{m+1,m} = sqrt(2m+3) z lambda_mm, then
+// lambda_l = a_l (z lambda_{l-1} - b_l lambda_{l-2}).
+__device__ __forceinline__ float rec_value(Rec& r, int m, int dl, const double* rc) {
+  if (dl == 1) {
+    r.p2 = r.p1;
+    r.p1 = sqrt(2.0 * m + 3.0) * r.z * r.p2;
+  } else if (dl >= 2) {
+    const double a = rc[2 * dl], b = rc[2 * dl + 1];
+    const double p0 = a * (r.z * r.p1 - b * r.p2);
+    r.p2 = r.p1;
+    r.p1 = p0;
+    if (r.s < 0 && fabs(p0) > kHugeB) {
+      r.p1 *= kSmallB;
+      r.p2 *= kSmallB;
+      r.s += 1;
+    }
+  }
+  return r.s == 0 ? float(r.p1) : 0.0f;
+}
+
+struct MfmaArgs {
+  const double* F;         // analysis in: [P][nring][lmax+1] complex
+  double* G;               // synthesis out: [P][nring][lmax+1] complex
+  const double* rt;        // ring table [nring][4]
+  const double* lam_mant;  // [lmax+1][H]
+  const int* lam_scale;
+  const double* rc;        // recurrence coefficients (a, b) per (l, m), alm order
+  const float* psi;        // synthesis in: [nalm][32] (column c = 2 p + re/im)
+  float* part;             // analysis out with several ring blocks: [R][nalm][32]
+  double* alm[16];         // analysis out with one ring block: per plane
+  double w;                // analysis weight 4 pi / N_pix
+  int64_t nalm;
+  int H, nring, lmax, P, nwv;
+};
+
+__device__ __forceinline__ size_t alm_base(int m, int lmax) {
+  return size_t(m) * (2 * lmax + 1 - m) / 2 + m;  // index of (l = m, m)
+}
+
+__device__ __forceinline__ Rec rec_start(const MfmaArgs& a, int m, int q) {
+  Rec r{0.0, 0.0, 0.0, -1};
+  if (q < a.H) {
+    r.z = a.rt[4 * q];
+    r.p1 = a.lam_mant[size_t(m) * a.H + q];
+    r.s = a.lam_scale[size_t(m) * a.H + q];
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------- analysis
+// Grid (lmax + 1, R): one workgroup per m and block of 64 nwv rings; each
+// wave owns 64 rings for all l and keeps their X in registers.
+template <int FORM>
+__global__ __launch_bounds__(64 * kMaxWaves) void k_analysis_mfma(MfmaArgs a) {
+  constexpr int SA = AnaStride<FORM>::S;
+  constexpr int KB = FORM == kFP32 ? 16 : 4;   // k-blocks over the 64 rings
+  constexpr int KW = FORM == kFP32 ? 4 : 16;   // rings per k-block
+  __shared__ float tiles[kMaxWaves * kStep * SA];
+  const int m = blockIdx.x, rb = blockIdx.y;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nl = a.lmax - m + 1;
+  const int qb = (rb * a.nwv + w) * 64;  // first ring of this wave
+  float* tw = tiles + w * kStep * SA;
+  const double* rc = a.rc + 2 * alm_base(m, a.lmax);
+  Rec r = rec_start(a, m, qb + l);
+
+  // B operands: X^{even/odd} of the wave's rings for the 32 columns
+  const size_t pstride = size_t(a.nring) * (a.lmax + 1) * 2;
+  auto xval = [&](int ring, int c, int par) -> float {
+    const int p = c >> 1, ri = c & 1;
+    if (ring >= a.H || p >= a.P) return 0.0f;
+    const double* Fp = a.F + p * pstride;
+    const int qm = a.nring - 1 - ring;
+    const double fn = Fp[(size_t(ring) * (a.lmax + 1) + m) * 2 + ri];
+    if (qm == ring) return float(fn);
+    const double fs = Fp[(size_t(qm) * (a.lmax + 1) + m) * 2 + ri];
+    return float(par == 0 ? fn + fs : fn - fs);
+  };
+  float xs[2][KB][2];
+  bf4 xh[2][KB][2], xl[2][KB][2];
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int c = (l & 15) + 16 * nb;
+        if (FORM == kFP32) {
+          xs[par][j][nb] = xval(qb + KW * j + (l >> 4), c, par);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            __bf16 h, lo;
+            split_bf16(xval(qb + KW * j + 4 * (l >> 4) + e, c, par), h, lo);
+            xh[par][j][nb][e] = h;
+            xl[par][j][nb][e] = lo;
+          }
+        }
+      }
+
+  for (int dl0 = 0; dl0 < nl; dl0 += kStep) {
+    // lambda for dl0 .. dl0 + 31 of this lane's ring into the wave's tile
+    for (int d = 0; d < kStep; ++d) {
+      const int dl = dl0 + d;
+      tw[d * SA + l] = dl < nl ? rec_value(r, m, dl, rc) : 0.0f;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is written
+    f4 acc[2][2];
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) acc[par][nb] = f4{0.f, 0.f, 0.f, 0.f};
+    const int i = l & 15;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const float* row = tw + (2 * i + par) * SA;
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        if (FORM == kFP32) {
+          const float av = row[KW * j + (l >> 4)];
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[par][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, xs[par][j][nb],
+                                                               acc[par][nb], 0, 0, 0);
+        } else {
+          bf4 ah, al;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            __bf16 h, lo;
+            split_bf16(row[KW * j + 4 * (l >> 4) + e], h, lo);
+            ah[e] = h;
+            al[e] = lo;
+          }
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            acc[par][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, xh[par][j][nb],
+                                                                     acc[par][nb], 0, 0, 0);
+            acc[par][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, xl[par][j][nb],
+                                                                     acc[par][nb], 0, 0, 0);
+            acc[par][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, xh[par][j][nb],
+                                                                     acc[par][nb], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // this wave's partial sums into its own tile as [par][nb][i4][lane]
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int i4 = 0; i4 < 4; ++i4) tw[((par * 2 + nb) * 4 + i4) * 64 + l] = acc[par][nb][i4];
+    __syncthreads();
+    // sum over the waves; output row rr = local dl, column c.  The C
+    // fragment of row 4 (lane / 16) + i4 of an M tile, column lane % 16.
+    for (int t = threadIdx.x; t < kStep * kCols; t += blockDim.x) {
+      const int rr = t >> 5, c = t & 31;
+      const int par = rr & 1, ii = rr >> 1;
+      const int src = ((par * 2 + (c >> 4)) * 4 + (ii & 3)) * 64 + 16 * (ii >> 2) + (c & 15);
+      float sum = 0.0f;
+      for (int v = 0; v < a.nwv; ++v) sum += tiles[v * kStep * SA + src];
+      const int dl = dl0 + rr, p = c >> 1;
+      if (dl < nl && p < a.P) {
+        const size_t idx = alm_base(m, a.lmax) + dl;
+        if (gridDim.y == 1)
+          a.alm[p][2 * idx + (c & 1)] = a.w * double(sum);
+        else
+          a.part[(size_t(rb) * a.nalm + idx) * kCols + c] = sum;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Sum of the ring-block partials, weighted, into the planes' alm.
+__global__ void k_analysis_reduce(MfmaArgs a, int R) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= a.nalm * kCols) return;
+  const int64_t idx = t / kCols;
+  const int c = int(t % kCols), p = c >> 1;
+  if (p >= a.P) return;
+  double s = 0.0;
+  for (int k = 0; k < R; ++k) s += double(a.part[(size_t(k) * a.nalm + idx) * kCols + c]);
+  a.alm[p][2 * idx + (c & 1)] = a.w * s;
+}
+
+// psi_lm of the P planes as float GEMM columns [nalm][32].
+__global__ void k_pack_psi(MfmaArgs a, float* psi) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= a.nalm * kCols) return;
+  const int64_t idx = t / kCols;
+  const int c = int(t % kCols), p = c >> 1;
+  psi[t] = p < a.P ? float(a.alm[p][2 * idx + (c & 1)]) : 0.0f;
+}
+
+// --------------------------------------------------------------- synthesis
+// Grid (lmax + 1, ring blocks): each wave owns 64 rings (4 M tiles of 16)
+// and sums over all l, even and odd l - m apart.
+template <int FORM>
+__global__ __launch_bounds__(64 * kMaxWaves) void k_synthesis_mfma(MfmaArgs a) {
+  constexpr int SS = kSynStride;
+  __shared__ float tiles[kMaxWaves * kStep * SS];
+  const int m = blockIdx.x, rb = blockIdx.y;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nl = a.lmax - m + 1;
+  const int qb = (rb * a.nwv + w) * 64;
+  float* tw = tiles + w * kStep * SS;
+  const double* rc = a.rc + 2 * alm_base(m, a.lmax);
+  const float* pm = a.psi + alm_base(m, a.lmax) * kCols;
+  Rec r = rec_start(a, m, qb + l);
+  f4 acc[2][4][2];
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) acc[par][mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  const int i = l & 15, k = l >> 4;
+  for (int dl0 = 0; dl0 < nl; dl0 += kStep) {
+    for (int d = 0; d < kStep; ++d) {
+      const int dl = dl0 + d;
+      tw[d * SS + l] = dl < nl ? rec_value(r, m, dl, rc) : 0.0f;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      if (FORM == kFP32) {
+        // K blocks of 4 values of l of this parity: rows 2 (4 j + k) + par
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = 2 * (4 * j + k) + par, dl = dl0 + row;
+          float bv[2];
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            bv[nb] = dl < nl ? pm[size_t(dl) * kCols + i + 16 * nb] : 0.0f;
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb) {
+            const float av = tw[row * SS + 16 * mb + i];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+              acc[par][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[nb],
+                                                                     acc[par][mb][nb], 0, 0, 0);
+          }
+        }
+      } else {
+        // one K block of the 16 values of this parity: rows 2 (4 k + e) + par
+        bf4 bh[2], bl[2];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int dl = dl0 + 2 * (4 * k + e) + par;
+            __bf16 h, lo;
+            split_bf16(dl < nl ? pm[size_t(dl) * kCols + i + 16 * nb] : 0.0f, h, lo);
+            bh[nb][e] = h;
+            bl[nb][e] = lo;
+          }
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          bf4 ah, al;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            __bf16 h, lo;
+            split_bf16(tw[(2 * (4 * k + e) + par) * SS + 16 * mb + i], h, lo);
+            ah[e] = h;
+            al[e] = lo;
+          }
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            acc[par][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[nb],
+                                                                         acc[par][mb][nb], 0, 0, 0);
+            acc[par][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[nb],
+                                                                         acc[par][mb][nb], 0, 0, 0);
+            acc[par][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[nb],
+                                                                         acc[par][mb][nb], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // tile reads done before the next step
+  }
+  // C fragment: ring 16 mb + 4 (lane / 16) + i4, column lane % 16 + 16 nb
+  const size_t pstride = size_t(a.nring) * (a.lmax + 1) * 2;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int i4 = 0; i4 < 4; ++i4) {
+      const int q = qb + 16 * mb + 4 * k + i4;
+      if (q >= a.H) continue;
+      const int qm = a.nring - 1 - q;
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int c = i + 16 * nb, p = c >> 1, ri = c & 1;
+        if (p >= a.P) continue;
+        const double e = acc[0][mb][nb][i4], o = acc[1][mb][nb][i4];
+        double* Gp = a.G + p * pstride;
+        Gp[(size_t(q) * (a.lmax + 1) + m) * 2 + ri] = e + o;
+        if (qm != q) Gp[(size_t(qm) * (a.lmax + 1) + m) * 2 + ri] = e - o;
+      }
+    }
+}
+
+// Recurrence coefficients per (l, m) in alm order:
+// a_l = sqrt((4l^2-1)/(l^2-m^2)), b_l = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)).
+__global__ void k_recur_table(int lmax, double* rc) {
+  const int m = blockIdx.x;
+  const size_t base = alm_base(m, lmax);
+  for (int l = m + 2 + threadIdx.x; l <= lmax; l += blockDim.x) {
+    const double L = l, M = m;
+    rc[2 * (base + l - m)] = sqrt((4.0 * L * L - 1.0) / (L * L - M * M));
+    rc[2 * (base + l - m) + 1] =
+        sqrt(((L - 1.0) * (L - 1.0) - M * M) / (4.0 * (L - 1.0) * (L - 1.0) - 1.0));
+  }
+}
+
+MfmaArgs base_args(Plan* p, int first_slot, int P) {
+  MfmaArgs a{};
+  a.rt = p->ring_s;
+  a.lam_mant = p->lam_mant;
+  a.lam_scale = p->lam_scale;
+  a.rc = p->rcoef;
+  a.nalm = p->nalm;
+  a.H = p->H;
+  a.nring = p->nring_s;
+  a.lmax = p->d.lmax;
+  a.P = P;
+  a.nwv = p->H < 64 * kMaxWaves ? (p->H + 63) / 64 : kMaxWaves;
+  for (int k = 0; k < P; ++k) a.alm[k] = p->slots[first_slot + k].alm;
+  return a;
+}
+
+}  // namespace
+
+int mfma_ring_blocks(int H) {
+  const int nwv = H < 64 * kMaxWaves ? (H + 63) / 64 : kMaxWaves;
+  return (H + 64 * nwv - 1) / (64 * nwv);
+}
+
+clm_status mfma_tables(Plan* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_recur_table, dim3(p->d.lmax + 1), dim3(kBlk), 0, s, p->d.lmax, p->rcoef);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s) {
+  MfmaArgs a = base_args(p, first_slot, P);
+  a.F = p->Fb;
+  a.part = p->apart;
+  a.w = 4.0 * 3.14159265358979323846 / double(p->npix_s);
+  const int R = mfma_ring_blocks(p->H);
+  const dim3 grid(p->d.lmax + 1, R), block(64 * a.nwv);
+  {
+    CLM_TIMED(p, s, "sht_analysis_mfma");
+    if (p->d.legendre_prec == CLM_BF16X3)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_mfma<kBF16X3>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_mfma<kFP32>), grid, block, 0, s, a);
+  }
+  CLM_LAUNCH_CHECK();
+  if (R > 1) {
+    const int64_t n = p->nalm * kCols;
+    CLM_TIMED(p, s, "sht_analysis_reduce");
+    hipLaunchKernelGGL(k_analysis_reduce, dim3(unsigned((n + kBlk - 1) / kBlk)), dim3(kBlk), 0,
+                       s, a, R);
+  }
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+clm_status mfma_synthesis(Plan* p, int first_slot, int P, hipStream_t s) {
+  MfmaArgs a = base_args(p, first_slot, P);
+  a.G = p->Gb;
+  a.psi = p->psib;
+  const int64_t n = p->nalm * kCols;
+  {
+    CLM_TIMED(p, s, "sht_pack_psi");
+    hipLaunchKernelGGL(k_pack_psi, dim3(unsigned((n + kBlk - 1) / kBlk)), dim3(kBlk), 0, s, a,
+                       p->psib);
+  }
+  CLM_LAUNCH_CHECK();
+  const int R = mfma_ring_blocks(p->H);
+  const dim3 grid(p->d.lmax + 1, R), block(64 * a.nwv);
+  {
+    CLM_TIMED(p, s, "sht_synthesis_mfma");
+    if (p->d.legendre_prec == CLM_BF16X3)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis_mfma<kBF16X3>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis_mfma<kFP32>), grid, block, 0, s, a);
+  }
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+}  // namespace clm

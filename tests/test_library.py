@@ -42,7 +42,7 @@ def test_default_description(L):
 @pytest.mark.parametrize("field,value", [
     ("nside_fine", 100), ("nside_sht", 4096), ("patch_cells", 96), ("nu_pre", 0),
     ("mg_vcycles", 0), ("max_planes", 0), ("solver", 7), ("mg_prec", 9),
-    ("nside_bundle", 1)])
+    ("nside_bundle", 1), ("legendre_prec", 3), ("legendre_prec", -1)])
 def test_invalid_descriptions_rejected(L, field, value):
     from paper_1210_3069_amd import clm
     d = clm.PlanDesc()
