@@ -284,6 +284,77 @@ def cpu_baseline(torch, kappa, plan64, sample_bundles):
                 gpu_fp64_vs_oracle_rel_err_u=worst)
 
 
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0}
+
+
+def c4_run(clm, torch, inputs):
+    """Batched precision forms: 32 pure-SHT Poisson solves at Nside drawn
+    from {512, 1024, 2048} (lmax = 2 Nside, Gaussian kappa with sigma 0.5,
+    C_l ~ l^-2, seeds 400 + i), grouped by Nside as GEMM columns.  Each form
+    is timed over all planes; its psi maps are compared with the FP64 form's
+    (relative L2 per plane); the matrix-core kernels' algorithmic flops
+    (4 H n_lm per transform per plane, analysis and synthesis) over their
+    HIP-event time give the MFMA throughput."""
+    ns = inputs.c4_nsides()
+    groups = {}
+    for i, n in enumerate(ns):
+        groups.setdefault(n, []).append(i)
+    kap = {}
+    for n, idx in groups.items():
+        kap[n] = torch.stack([clm.alm2map(torch.from_numpy(
+            inputs.gaussian_alm(2 * n, seed=400 + i, sigma=0.5)).cuda(), 2 * n, n) for i in idx])
+    torch.cuda.synchronize()
+    out, ref = {}, {}
+    for form in ("fp64", "fp32", "bf16x3"):
+        ms_total, mfma_ms, flops, errs, stage_ms = 0.0, 0.0, 0.0, [], {}
+        for n, idx in sorted(groups.items()):
+            plan = clm.Plan(n, nside_sht=n, lmax=2 * n, solver="sht", max_planes=len(idx),
+                            legendre_prec=form)
+            plan.poisson_solve(kap[n][:1])          # first call: lazy set-up
+            torch.cuda.synchronize()
+            plan.set_timing(True)
+            plan.get_timing()
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record()
+            plan.poisson_solve(kap[n])
+            t1.record()
+            torch.cuda.synchronize()
+            ms_total += t0.elapsed_time(t1)
+            st = plan.get_timing()
+            plan.set_timing(False)
+            plan.sync_status()
+            mfma_ms += sum(st.get(k, (0.0, 0))[0] for k in ("sht_analysis_mfma",
+                                                           "sht_synthesis_mfma"))
+            for k, (tot, _) in st.items():
+                stage_ms[k] = stage_ms.get(k, 0.0) + tot
+            H = 2 * n
+            nlm = (2 * n + 1) * (2 * n + 2) // 2
+            flops += len(idx) * 2 * 4.0 * H * nlm
+            for k, i in enumerate(idx):
+                psi = plan.psi_map(k)
+                if form == "fp64":
+                    ref[i] = psi
+                else:
+                    errs.append(float((psi - ref[i]).norm() / ref[i].norm()))
+            plan.close()
+            del plan
+            torch.cuda.empty_cache()
+        rec = dict(planes_per_s=len(ns) * 1000.0 / ms_total, ms_all_planes=ms_total,
+                   stage_ms=stage_ms)
+        if form != "fp64":
+            tf = flops / (mfma_ms * 1e-3) / 1e12
+            rec.update(legendre_ms=mfma_ms, legendre_alg_tflops=tf,
+                       mfma_peak_tflops=MFMA_PEAK_TFLOPS[form],
+                       mfma_frac=tf * (3.0 if form == "bf16x3" else 1.0) / MFMA_PEAK_TFLOPS[form],
+                       max_rel_l2_psi_vs_fp64=max(errs), median_rel_l2_psi_vs_fp64=float(np.median(errs)),
+                       within_tolerance_1e6=bool(max(errs) <= 1e-6))
+        out[form] = rec
+    out["planes"] = {str(n): len(idx) for n, idx in sorted(groups.items())}
+    out["workload"] = ("32 planes, Nside from {512, 1024, 2048} (seed 4), lmax = 2 Nside, pure-SHT "
+                       "Poisson, planes of one Nside batched as GEMM columns (16 at a time)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +363,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2)
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the batched-precision workload (32 uneven pure-SHT planes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with a plain copy kernel of known size (counter calibration)")
     ap.add_argument("--summarize-stats", nargs=2, metavar=("CSV", "CMD"),
@@ -395,6 +468,9 @@ def main():
             out["cpu_baseline"] = cpu_baseline(torch, kappa, plan64,
                                                sample[: max(1, args.cpu_sample)])
         plan64.close()
+    if not args.no_c4:
+        print("bench: batched precision forms", file=sys.stderr, flush=True)
+        out["c4_precision_forms"] = c4_run(clm, torch, inputs)
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

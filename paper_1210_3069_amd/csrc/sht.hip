@@ -90,41 +90,88 @@ __device__ __forceinline__ void quarter_table(double* sq, int n) {
   for (int r = threadIdx.x; r <= Q; r += blockDim.x) sq[r] = sinpi(2.0 * double(r) / double(n));
 }
 
-// In-place radix-2 FFT of a power-of-two length n (log2n) on interleaved
-// complex LDS data already in bit-reversed order; sign -1: forward
-// (e^{-2 pi i jk/n}), +1: inverse without scaling.
-__device__ __forceinline__ void fft_pow2(double* x, int n, const double* sq, int sign) {
+__device__ __forceinline__ int bitrev(int j, int log2n) {
+  return log2n == 0 ? 0 : int(__brev(unsigned(j)) >> (32 - log2n));
+}
+
+// e^{sign 2 pi i t / n} for 0 <= t < n from the quarter-wave table.
+__device__ __forceinline__ void unit(const double* sq, int Q, int t, int sign, double& c,
+                                     double& s) {
+  twiddle(sq, Q, t, c, s);
+  s *= sign;
+}
+
+// Complex DFT of length h = 2^lg r (r odd) with kernel e^{sign 2 pi i jk/h},
+// from `in` to `out` (interleaved complex, distinct LDS arrays), for a ring
+// of n samples whose quarter-wave table is sq (h divides n).  Decimation in
+// time: the 2^lg subsequences of stride 2^lg get direct DFTs of length r
+// (block bitrev(b) holds subsequence b), then lg radix-2 stages combine
+// blocks of r 2^(s-1).  Twiddles of the odd DFT advance by quadrant and
+// remainder so the inner loop has no division.
+__device__ void dft_mixed(const double* in, double* out, int h, int lg, int r, const double* sq,
+                          int n, int sign) {
   const int Q = n / 4;
-  for (int len = 2; len <= n; len <<= 1) {
-    const int half = len >> 1, step = n / len;
-    for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
-      const int pos = b & (half - 1);
-      const int i = (b - pos) * 2 + pos, j = i + half;
+  const int nr = n / r;  // table step of e^{2 pi i / r}
+  for (int item = threadIdx.x; item < h; item += blockDim.x) {
+    const int bb = item / r, k = item - bb * r;
+    const int b = bitrev(bb, lg);
+    const int inc = int((int64_t(k) * nr) % n);
+    const int iq = inc / Q, ir = inc - iq * Q;
+    int q = 0, rem = 0;
+    double ar = 0.0, ai = 0.0;
+    for (int t = 0; t < r; ++t) {
+      const double zr = in[2 * ((t << lg) + b)], zi = in[2 * ((t << lg) + b) + 1];
+      const double sr = sq[rem], cr = sq[Q - rem];
+      const double u = (q & 1) ? sr : cr, v = (q & 1) ? cr : sr;
+      const double c = (q == 1 || q == 2) ? -u : u;
+      const double s = (q >= 2) ? -v : v;
+      const double ss = sign * s;
+      ar += zr * c - zi * ss;
+      ai += zr * ss + zi * c;
+      rem += ir;
+      q += iq;
+      if (rem >= Q) {
+        rem -= Q;
+        ++q;
+      }
+      q &= 3;
+    }
+    out[2 * item] = ar;
+    out[2 * item + 1] = ai;
+  }
+  __syncthreads();
+  for (int half = r; half < h; half <<= 1) {
+    const int L = 2 * half, step = n / L;
+    for (int item = threadIdx.x; item < h / 2; item += blockDim.x) {
+      const int blk = item / half, kk = item - blk * half;
+      const int i0 = blk * L + kk, i1 = i0 + half;
       double c, s;
-      twiddle(sq, Q, pos * step, c, s);
-      s *= sign;
-      const double xr = x[2 * j], xi = x[2 * j + 1];
+      unit(sq, Q, kk * step, sign, c, s);
+      const double xr = out[2 * i1], xi = out[2 * i1 + 1];
       const double tr = c * xr - s * xi, ti = c * xi + s * xr;
-      const double yr = x[2 * i], yi = x[2 * i + 1];
-      x[2 * j] = yr - tr;
-      x[2 * j + 1] = yi - ti;
-      x[2 * i] = yr + tr;
-      x[2 * i + 1] = yi + ti;
+      const double er = out[2 * i0], ei = out[2 * i0 + 1];
+      out[2 * i0] = er + tr;
+      out[2 * i0 + 1] = ei + ti;
+      out[2 * i1] = er - tr;
+      out[2 * i1 + 1] = ei - ti;
     }
     __syncthreads();
   }
 }
 
-__device__ __forceinline__ bool is_pow2(int n) { return (n & (n - 1)) == 0; }
-
-__device__ __forceinline__ int bitrev(int j, int log2n) {
-  return int(__brev(unsigned(j)) >> (32 - log2n));
+// h = n / 2 = 2^lg r with r odd.
+__device__ __forceinline__ void half_split(int n, int& h, int& lg, int& r) {
+  h = n / 2;
+  lg = __ffs(h) - 1;
+  r = h >> lg;
 }
 
-// F_m(q) = e^{-i m phi0_q} sum_j f_{q,j} e^{-2 pi i (m mod n) j / n}, m = 0..lmax.
-// Power-of-two rings: radix-2 FFT in LDS.  Other rings: direct DFT of the
-// min(n, lmax+1) needed bins.  Rings shorter than lmax + 1 fold the higher
-// orders onto their bins (HEALPix aliasing).
+// F_m(q) = e^{-i m phi0_q} sum_j f_{q,j} e^{-2 pi i (m mod n) j / n}, m = 0..lmax
+// (HEALPix aliasing for rings shorter than lmax + 1).  The real ring is read
+// as h = n/2 complex samples z_j = f_2j + i f_2j+1, transformed with
+// dft_mixed, and split: X_k = E_k + e^{-2 pi i k/n} O_k with
+// E_k = (Z_k + conj Z_{h-k}) / 2, O_k = (Z_k - conj Z_{h-k}) / 2i, and
+// X_{n-k} = conj X_k.
 __global__ void k_ring_forward(const double* map, const double* rt, const int* ri, int lmax,
                                double* F) {
   extern __shared__ double sm[];
@@ -133,90 +180,61 @@ __global__ void k_ring_forward(const double* map, const double* rt, const int* r
   const int64_t first = ri[2 * q + 1];
   const double phi0 = rt[4 * q + 3];
   double* out = F + size_t(q) * (lmax + 1) * 2;
-  if (is_pow2(n)) {
-    double* sq = sm;             // [n/4 + 1]
-    double* X = sm + Q + 1;      // [n][2]
-    const int lg = __ffs(n) - 1;
-    quarter_table(sq, n);
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      const int r = bitrev(j, lg);
-      X[2 * r] = map[first + j];
-      X[2 * r + 1] = 0.0;
-    }
-    __syncthreads();
-    fft_pow2(X, n, sq, -1);
-    for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
-      const int k = m & (n - 1);
-      double s, c;
-      sincos(double(m) * phi0, &s, &c);
-      const double xr = X[2 * k], xi = X[2 * k + 1];
-      out[2 * m] = c * xr + s * xi;       // (c - i s)(xr + i xi)
-      out[2 * m + 1] = c * xi - s * xr;
-    }
-    return;
-  }
-  double* f = sm;              // [n]
-  double* sq = sm + n;         // [n/4 + 1]
-  double* X = sq + Q + 1;      // [n][2] when n <= lmax
-  for (int j = threadIdx.x; j < n; j += blockDim.x) f[j] = map[first + j];
+  double* x = sm;              // [n] real samples = [h] complex z
+  double* Z = sm + n;          // [h] complex
+  double* sq = sm + 2 * n;     // [n/4 + 1]
+  for (int j = threadIdx.x; j < n; j += blockDim.x) x[j] = map[first + j];
   quarter_table(sq, n);
   __syncthreads();
-  const bool alias = n <= lmax;
-  const int nb = alias ? n : lmax + 1;
-  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-    double re = 0.0, im = 0.0;
-    int t = 0;
-    for (int j = 0; j < n; ++j) {
-      double c, s;
-      twiddle(sq, Q, t, c, s);
-      re += f[j] * c;
-      im -= f[j] * s;
-      t += k;
-      if (t >= n) t -= n;
-    }
-    if (alias) {
-      X[2 * k] = re;
-      X[2 * k + 1] = im;
-    } else {
-      double s, c;
-      sincos(double(k) * phi0, &s, &c);
-      out[2 * k] = c * re + s * im;       // (c - i s)(re + i im)
-      out[2 * k + 1] = c * im - s * re;
-    }
-  }
-  if (!alias) return;
-  __syncthreads();
+  int h, lg, r;
+  half_split(n, h, lg, r);
+  dft_mixed(x, Z, h, lg, r, sq, n, -1);
   for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
     const int k = m % n;
-    double s, c;
-    sincos(double(m) * phi0, &s, &c);
-    const double xr = X[2 * k], xi = X[2 * k + 1];
-    out[2 * m] = c * xr + s * xi;
-    out[2 * m + 1] = c * xi - s * xr;
+    const bool up = k > n / 2;
+    const int kk = up ? n - k : k;       // X_k = conj X_{n-k}
+    const int k1 = kk % h, k2 = (h - kk) % h;
+    const double zr = Z[2 * k1], zi = Z[2 * k1 + 1];
+    const double wr = Z[2 * k2], wi = -Z[2 * k2 + 1];  // conj Z_{h-k}
+    const double er = 0.5 * (zr + wr), ei = 0.5 * (zi + wi);
+    const double dr = zr - wr, di = zi - wi;
+    const double orr = 0.5 * di, oi = -0.5 * dr;       // (Z - conj) / 2i
+    double c, s;
+    unit(sq, Q, kk % n, -1, c, s);
+    double xr = er + c * orr - s * oi, xi = ei + c * oi + s * orr;
+    if (up) xi = -xi;
+    double sp, cp;
+    sincos(double(m) * phi0, &sp, &cp);
+    out[2 * m] = cp * xr + sp * xi;       // (cp - i sp)(xr + i xi)
+    out[2 * m + 1] = cp * xi - sp * xr;
   }
 }
 
 // f_{q,j} = Re sum_{m=0}^{lmax} c_m G_m(q) e^{i m (phi0 + 2 pi j / n)}, c_0 = 1,
-// c_m = 2; nf fields [nf][ring][m] -> [nf][npix].  Orders are folded onto
-// k = m mod n first, then a direct sum over the min(n, lmax+1) bins.
+// c_m = 2; nf fields [nf][ring][m] -> [nf][npix].  Orders fold onto
+// B_k = sum_{m = k mod n} c_m G_m e^{i m phi0}; the real part equals the
+// transform of the Hermitian C_k = (B_k + conj B_{n-k}) / 2, done at half
+// length: Y_k = (C_k + C_{k+h}) + i e^{2 pi i k/n} (C_k - C_{k+h}), z the
+// inverse DFT of Y, f_2j = Re z_j, f_2j+1 = Im z_j.
 __global__ void k_ring_inverse(const double* G, int nring, const double* rt, const int* ri,
                                int lmax, int64_t npix, int nf, double* out) {
   extern __shared__ double sm[];
   const int q = blockIdx.x;
   const int n = ri[2 * q], Q = n / 4;
   const int64_t first = ri[2 * q + 1];
-  const bool p2 = is_pow2(n);
-  const int nb = p2 ? n : (n <= lmax ? n : lmax + 1);
-  double* sq = sm;             // [n/4 + 1]
-  double* B = sm + Q + 1;      // [nb][2]
+  double* Y = sm;              // [h] complex
+  double* Z = sm + n;          // [h] complex
+  double* sq = sm + 2 * n;     // [n/4 + 1]
   const double phi0 = rt[4 * q + 3];
-  const int lg = __ffs(n) - 1;
+  int h, lg, r;
+  half_split(n, h, lg, r);
   quarter_table(sq, n);
   for (int fld = 0; fld < nf; ++fld) {
     const double* g = G + (size_t(fld) * nring + q) * (lmax + 1) * 2;
     __syncthreads();
-    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-      double br = 0.0, bi = 0.0;
+    auto bk = [&](int k, double& br, double& bi) {
+      br = 0.0;
+      bi = 0.0;
       for (int m = k; m <= lmax; m += n) {
         double s, c;
         sincos(double(m) * phi0, &s, &c);
@@ -225,28 +243,30 @@ __global__ void k_ring_inverse(const double* G, int nring, const double* rt, con
         br += cm * (c * gr - s * gi);
         bi += cm * (c * gi + s * gr);
       }
-      const int kk = p2 ? bitrev(k, lg) : k;
-      B[2 * kk] = br;
-      B[2 * kk + 1] = bi;
+    };
+    auto ck = [&](int k, double& cr, double& ci) {
+      double ar, ai, br, bi;
+      bk(k, ar, ai);
+      bk((n - k) % n, br, bi);
+      cr = 0.5 * (ar + br);
+      ci = 0.5 * (ai - bi);
+    };
+    for (int k = threadIdx.x; k < h; k += blockDim.x) {
+      double c1r, c1i, c2r, c2i;
+      ck(k, c1r, c1i);
+      ck(k + h, c2r, c2i);
+      double c, s;
+      unit(sq, Q, k, +1, c, s);
+      const double dr = c1r - c2r, di = c1i - c2i;
+      const double tr = c * dr - s * di, ti = c * di + s * dr;  // e^{i..} (C_k - C_k+h)
+      Y[2 * k] = (c1r + c2r) - ti;                              // + i (tr + i ti)
+      Y[2 * k + 1] = (c1i + c2i) + tr;
     }
     __syncthreads();
-    if (p2) {
-      fft_pow2(B, n, sq, +1);
-      for (int j = threadIdx.x; j < n; j += blockDim.x)
-        out[size_t(fld) * npix + first + j] = B[2 * j];
-      continue;
-    }
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      double acc = 0.0;
-      int t = 0;
-      for (int k = 0; k < nb; ++k) {
-        double c, s;
-        twiddle(sq, Q, t, c, s);
-        acc += B[2 * k] * c - B[2 * k + 1] * s;
-        t += j;
-        if (t >= n) t -= n;
-      }
-      out[size_t(fld) * npix + first + j] = acc;
+    dft_mixed(Y, Z, h, lg, r, sq, n, +1);
+    for (int j = threadIdx.x; j < h; j += blockDim.x) {
+      out[size_t(fld) * npix + first + 2 * j] = Z[2 * j];
+      out[size_t(fld) * npix + first + 2 * j + 1] = Z[2 * j + 1];
     }
   }
 }
@@ -518,28 +538,15 @@ void launch_analysis(Plan* p, hipStream_t s, double* alm) {
   }
 }
 
-// LDS of the ring kernels for the longest ring (4 nside) and lmax.
-// (power-of-two rings: FFT buffer of n complex; others: direct sums)
+// LDS of the ring kernels: two n-double arrays and the quarter-wave table
+// of the longest ring (4 nside samples).
 size_t ring_fwd_lds(int nside, int lmax) {
-  size_t best = 0;
-  for (int n = 4; n <= 4 * nside; n += 4) {
-    const bool p2 = (n & (n - 1)) == 0;
-    const size_t b = p2 ? size_t(n) / 4 + 1 + 2 * size_t(n)
-                        : size_t(n) + n / 4 + 1 + (n <= lmax ? 2 * size_t(n) : 0);
-    best = std::max(best, b);
-  }
-  return best * sizeof(double);
+  (void)lmax;
+  const size_t n = 4 * size_t(nside);
+  return (2 * n + n / 4 + 1) * sizeof(double);
 }
 
-size_t ring_inv_lds(int nside, int lmax) {
-  size_t best = 0;
-  for (int n = 4; n <= 4 * nside; n += 4) {
-    const bool p2 = (n & (n - 1)) == 0;
-    const size_t nb = p2 ? size_t(n) : (n <= lmax ? size_t(n) : size_t(lmax) + 1);
-    best = std::max(best, size_t(n) / 4 + 1 + 2 * nb);
-  }
-  return best * sizeof(double);
-}
+size_t ring_inv_lds(int nside, int lmax) { return ring_fwd_lds(nside, lmax); }
 
 clm_status ring_forward(Plan* p, const double* map, double* F, hipStream_t s) {
   const size_t shm = ring_fwd_lds(p->d.nside_sht, p->d.lmax);

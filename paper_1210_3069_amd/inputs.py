@@ -81,3 +81,10 @@ def galaxy_redshifts(n, seed, zmin=0.3, zmax=1.5):
 def multiplane_sigmas(nplanes=20, lo=0.1, hi=0.6):
     """Lognormal sigma_g per plane, growing linearly with plane index."""
     return lo + (hi - lo) * np.arange(nplanes) / max(nplanes - 1, 1)
+
+
+def c4_nsides(nplanes=32, seed=4):
+    """HEALPix resolution of each plane of the batched-precision workload:
+    drawn uniformly from {512, 1024, 2048}."""
+    rng = np.random.default_rng(seed)
+    return [(512, 1024, 2048)[k] for k in rng.integers(0, 3, nplanes)]
