@@ -316,14 +316,14 @@ __device__ __forceinline__ int ring_above(const Tab& R, double z) {
 }
 
 // Four RING pixels and weights for bilinear interpolation at the point
-// (z, rho, dphi): rings bracketing theta, pixels bracketing phi in each,
+// (z, rho, dphi) whose ring index from ring_above is g: rings bracketing
+// theta, pixels bracketing phi in each,
 // linear weights; above the first ring (below the last) the pole value is
 // the mean of that ring's four pixels.  The theta offset from the upper ring
 // is asin(rho z_q - z sin theta_q).
 template <typename Tab>
-__device__ __forceinline__ void interp_weights_t(const Tab& R, double z, double rho, double dphi,
-                                                 int pix[4], double w[4]) {
-  const int g = ring_above(R, z);
+__device__ __forceinline__ void interp_weights_g(const Tab& R, int g, double z, double rho,
+                                                 double dphi, int pix[4], double w[4]) {
   const int nring = R.nring();
 
   auto pair = [&](int q, int& a, int& b, double& wp) {
@@ -384,6 +384,12 @@ __device__ __forceinline__ void interp_weights_t(const Tab& R, double z, double 
     w[2] = fac;
     w[3] = fac;
   }
+}
+
+template <typename Tab>
+__device__ __forceinline__ void interp_weights_t(const Tab& R, double z, double rho, double dphi,
+                                                 int pix[4], double w[4]) {
+  interp_weights_g(R, ring_above(R, z), z, rho, dphi, pix, w);
 }
 
 // Interpolation at (z, rho, phi) from the global tables, phi in [0, 2 pi).

@@ -44,6 +44,7 @@ __device__ __forceinline__ int64_t xcd_block() {
 // f' = 2 (interp(kappa) - mean) - L u0 at the cell centres, float64.
 struct SetupArgs {
   int n, ntile, tile;
+  int ring_shift;       // log2(nside_fine / nside_sht)
   double L, delta;
   const double* rot;
   const double* coef;  // level-0 rows
@@ -94,12 +95,14 @@ struct PhiRef {
 };
 
 // Pass 1 visits every cell of the tile plus one ring once: direction, u0 and
-// (interior cells) the source f, written to the f' array; pass 2 fills the
-// patch ghosts from the face values; pass 3 forms f' = f - L u0 (the thread
-// that wrote f reads it back).
+// (interior cells) the source f, kept in LDS (fsh, float32 form) or written
+// to the f' array and read back by the same thread; pass 2 fills the patch
+// ghosts from the face values; pass 3 forms f' = f - L u0.  The SHT grid's
+// rings are the fine grid's rings ratio, 2 ratio, ... (nested HEALPix), so
+// the SHT ring index follows from the fine one: floor((g_f + 1) / ratio) - 1.
 template <typename T, int TILE, typename TS, typename TF>
 __device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, double* shu,
-                             const double* trig, const double* R, const PhiRef& pr,
+                             T* fsh, const double* trig, const double* R, const PhiRef& pr,
                              int64_t patch, int i0, int j0) {
   constexpr int RR = TILE + 2;
   const int n = a.n;
@@ -116,13 +119,15 @@ __device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, dou
       double z, rho, dph;
       patch_dir(R, trig[4 * li], trig[4 * li + 1], trig[4 * lj + 2], trig[4 * lj + 3], pr.c,
                 pr.s, z, rho, dph);
+      const int gf = hpx::ring_above(rf, z);
+      const int gs = min(max(((gf + 1) >> a.ring_shift) - 1, rs.lo()), rs.hi());
       int ps[4];
       double ws[4];
-      hpx::interp_weights_t(rs, z, rho, dph, ps, ws);
+      hpx::interp_weights_g(rs, gs, z, rho, dph, ps, ws);
       if (li >= 1 && li <= TILE && lj >= 1 && lj <= TILE) {
         int pf[4];
         double wf[4];
-        hpx::interp_weights_t(rf, z, rho, dph, pf, wf);
+        hpx::interp_weights_g(rf, gf, z, rho, dph, pf, wf);
         double k4[4];
         if (a.kappa_fp64) {
           const double* km = static_cast<const double*>(a.kappa);
@@ -134,7 +139,10 @@ __device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, dou
         v = ws[0] * a.psi_s[ps[0]] + ws[1] * a.psi_s[ps[1]] + ws[2] * a.psi_s[ps[2]] +
             ws[3] * a.psi_s[ps[3]];
         const double kv = wf[0] * k4[0] + wf[1] * k4[1] + wf[2] * k4[2] + wf[3] * k4[3];
-        fp[size_t(gi) * n + gj] = T(2.0 * (kv - mean));
+        if (fsh)
+          fsh[(li - 1) * TILE + (lj - 1)] = T(2.0 * (kv - mean));
+        else
+          fp[size_t(gi) * n + gj] = T(2.0 * (kv - mean));
       } else {
         v = ws[0] * a.psi_s[ps[0]] + ws[1] * a.psi_s[ps[1]] + ws[2] * a.psi_s[ps[2]] +
             ws[3] * a.psi_s[ps[3]];
@@ -183,7 +191,8 @@ __device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, dou
     const double Lu = (c[0] * (shu[idx - RR] - u) + c[1] * (shu[idx + RR] - u) +
                        (shu[idx - 1] - 2.0 * u + shu[idx + 1]) / c[2]) / c[3];
     T* fo = fp + size_t(gi) * n + gj;
-    *fo = T(double(*fo) - Lu);
+    const double f = fsh ? double(fsh[(li - 1) * TILE + (lj - 1)]) : double(*fo);
+    *fo = T(f - Lu);
   }
 }
 
@@ -200,6 +209,8 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
   __shared__ RingStore<kRingCapF> ringf;
   __shared__ RingStore<kRingCapS> rings;
   __shared__ double zred[2 * (kSetupBlock / 64)];
+  __shared__ T fshm[sizeof(T) == 4 ? TILE * TILE : 1];
+  T* fsh = sizeof(T) == 4 ? fshm : nullptr;
   __shared__ PhiRef pref;
   __shared__ int rng[5];
   const int64_t lb = xcd_block();
@@ -274,10 +285,10 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
     ts.fill(a.rs, rng[0], rng[1], pr.phi);
     tf.fill(a.rf, rng[2], rng[3], pr.phi);
     __syncthreads();
-    setup_passes<T, TILE>(a, ts, tf, shu, trig, R, pr, patch, i0, j0);
+    setup_passes<T, TILE>(a, ts, tf, shu, fsh, trig, R, pr, patch, i0, j0);
   } else {
     setup_passes<T, TILE>(a, hpx::GlobalRingTab{a.rs, pr.phi}, hpx::GlobalRingTab{a.rf, pr.phi},
-                          shu, trig, R, pr, patch, i0, j0);
+                          shu, fsh, trig, R, pr, patch, i0, j0);
   }
 }
 
@@ -992,6 +1003,8 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     a.coef = p->coef + p->lev[0].crow;
     a.rs = hpx::Rings{p->ring_s, p->ringi_s, p->ringx_s, p->nring_s, d.nside_sht};
     a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->ringx_f, p->nring_f, d.nside_fine};
+    a.ring_shift = 0;
+    while ((d.nside_sht << a.ring_shift) < d.nside_fine) ++a.ring_shift;
     a.psi_s = sl.psi_s;
     a.kappa = kappa;
     a.kappa_fp64 = kappa_fp64;
