@@ -92,6 +92,9 @@ typedef struct {
                             (matrix cores; the planes of one clm_poisson_solve
                             call are batched as GEMM columns, 16 at a time;
                             the lambda_lm recurrence stays FP64)           */
+  int32_t adjoint;       /* 1: also allocate the workspace of
+                            clm_shear_adjoint / clm_poisson_adjoint (FP64,
+                            about 4 x 8 bytes per finest cell); SHT+MG only */
 } clm_plan_desc;
 
 /* Fill *d with the defaults for a fine grid: nside_sht = nside_fine / 8
@@ -266,6 +269,32 @@ clm_status clm_raytrace_planes(clm_plan plan, const void* kappa_dev, int32_t kap
 clm_status clm_ray_update(clm_plan plan, int32_t slot, const double* chi_host, int32_t nchi,
                           int32_t m, double curvature_K, const clm_rays* rays,
                           hipStream_t stream);
+
+/*
+ * Adjoint of the solve (plans created with desc.adjoint = 1, SHT+MG solver).
+ * With the geometry and the fixed number of V-cycles the map kappa ->
+ * (gradient, covariant Hessian of psi at points) of Sec. 3.2 is linear, so
+ * the gradient of any loss of those outputs is its transpose applied to the
+ * loss's partial derivatives; no state of the forward solve is used.
+ *
+ * clm_shear_adjoint accumulates, for npts points (theta, phi: device FP64,
+ * same convention as clm_shear_from_potential), dgrad [2][npts] and dhess
+ * [3][npts] (U_tt, U_pp, U_tp; device FP64) into the plan's accumulator;
+ * it may be called several times.  A point outside its bundle's patch is
+ * skipped and latches CLM_ERAY_LEFT_PATCH.  Asynchronous on `stream`.
+ *
+ * clm_poisson_adjoint writes dkappa [12 nside_fine^2] (device FP64, RING):
+ * the transpose of the whole chain (patch setup, V-cycles, evaluation, SHT,
+ * degrade, demean) applied to the accumulated values, then clears the
+ * accumulator.  `slot` selects the plane whose solve the gradient belongs to
+ * (the transpose is the same for every slot).  CLM_EUNSUPPORTED for plans
+ * without the adjoint workspace.
+ */
+clm_status clm_shear_adjoint(clm_plan plan, int32_t slot, const double* theta_dev,
+                             const double* phi_dev, int64_t npts, const double* dgrad_dev,
+                             const double* dhess_dev, hipStream_t stream);
+clm_status clm_poisson_adjoint(clm_plan plan, int32_t slot, double* dkappa_dev,
+                               hipStream_t stream);
 
 #ifdef __cplusplus
 }

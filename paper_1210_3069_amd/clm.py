@@ -22,7 +22,7 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "nside_fine", "nside_sht", "lmax", "nside_bundle", "patch_factor", "patch_cells",
         "mg_vcycles", "nu_pre", "nu_post", "solver", "mg_prec", "max_planes",
-        "legendre_prec")]
+        "legendre_prec", "adjoint")]
 
 
 class Rays(ctypes.Structure):
@@ -65,6 +65,8 @@ _SIGS = {
     "clm_raytrace_planes": (_P, _P, _I32, ctypes.POINTER(_D), _I32, _I32, _I32, _D,
                             ctypes.POINTER(Rays), ctypes.POINTER(Galaxies), _P),
     "clm_ray_update": (_P, _I32, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays), _P),
+    "clm_shear_adjoint": (_P, _I32, _P, _P, _I64, _P, _P, _P),
+    "clm_poisson_adjoint": (_P, _I32, _P, _P),
     "clm_plan_set_timing": (_P, _I32),
     "clm_plan_get_timing": (_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_D),
                             ctypes.POINTER(_I64), _I32, ctypes.POINTER(_I32)),
@@ -230,6 +232,23 @@ class Plan:
                     "shear_from_potential")
         return g, h
 
+    def shear_adjoint(self, theta, phi, dgrad, dhess, slot=0):
+        """Accumulate the transpose of the point evaluation for dL/dgrad
+        [2, n] and dL/dhess [3, n] (float64 device tensors)."""
+        for t in (theta, phi, dgrad, dhess):
+            _dev(t, torch.float64)
+        n = theta.numel()
+        self._check(lib().clm_shear_adjoint(self.h, slot, _ptr(theta), _ptr(phi), n,
+                                            _ptr(dgrad), _ptr(dhess), _stream()),
+                    "shear_adjoint")
+
+    def poisson_adjoint(self, slot=0):
+        """dL/dkappa (fine RING map, float64) from the accumulated adjoints."""
+        out = torch.empty(self.npix_fine, dtype=torch.float64, device=self.device)
+        self._check(lib().clm_poisson_adjoint(self.h, slot, _ptr(out), _stream()),
+                    "poisson_adjoint")
+        return out
+
     def shear_at_pixels(self, slot=0, order="ring", fp64=True, out=None):
         o = ORDER_RING if order == "ring" else ORDER_NESTED
         dt = torch.float64 if fp64 else torch.float32
@@ -285,3 +304,29 @@ class Plan:
                                          chi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                          chi.size, m, K, ctypes.byref(s), _stream()),
                     "ray_update")
+
+
+class PoissonShearFn(torch.autograd.Function):
+    """kappa (fine RING map, float64) -> (grad [2, n], hess [3, n]) of psi at
+    the points (theta, phi), differentiable in kappa: the forward pass is
+    clm_poisson_solve + clm_shear_from_potential, the backward pass
+    clm_shear_adjoint + clm_poisson_adjoint.  The plan must be SHT+MG with
+    adjoint = 1."""
+
+    @staticmethod
+    def forward(ctx, kappa, theta, phi, plan, slot=0):
+        plan.poisson_solve(kappa.detach().contiguous(), first_slot=slot)
+        g, h = plan.shear_from_potential(theta, phi, slot=slot, fp64=True)
+        ctx.plan, ctx.slot = plan, slot
+        ctx.save_for_backward(theta, phi)
+        return g, h
+
+    @staticmethod
+    def backward(ctx, dg, dh):
+        theta, phi = ctx.saved_tensors
+        dg = torch.zeros(2, theta.numel(), dtype=torch.float64, device=theta.device) \
+            if dg is None else dg.contiguous().double()
+        dh = torch.zeros(3, theta.numel(), dtype=torch.float64, device=theta.device) \
+            if dh is None else dh.contiguous().double()
+        ctx.plan.shear_adjoint(theta, phi, dg, dh, slot=ctx.slot)
+        return ctx.plan.poisson_adjoint(slot=ctx.slot), None, None, None, None

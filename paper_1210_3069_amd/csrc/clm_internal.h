@@ -80,6 +80,13 @@ struct Plan {
   // per coarser tile level k (1 .. ktile), and the LDS level ktile:
   std::vector<void*> ubar, rbar, flev, ulev, ulev2;
   int* status_dev = nullptr;
+  // adjoint workspace (desc.adjoint): u0 + du bar per patch with ghosts, and
+  // per level the transposed V-cycle's u bar (two), f bar and a temporary
+  double* adj_ubar = nullptr;
+  std::vector<double*> adj_u, adj_v, adj_f, adj_w;
+  double* adj_psi = nullptr;    // [npix_s] psi_SHT bar
+  double* adj_ks = nullptr;     // [npix_s] kappa_SHT bar
+  double* adj_alm = nullptr;    // [nalm] complex
 
   std::vector<Slot> slots;
 
@@ -148,6 +155,12 @@ clm_status plane_mean(Plan* p, const void* kappa, int kappa_fp64,
                       hipStream_t s);                   // sht.hip: red[1023] = mean
 clm_status sht_solve_batch(Plan* p, const void* kappa, int kappa_fp64, int first_slot,
                            int nplanes, hipStream_t s);  // sht.hip
+clm_status sht_adjoint(Plan* p, const double* psibar, double* alm, double* ksbar,
+                       hipStream_t s);                   // sht.hip
+clm_status shear_adjoint(Plan* p, const double* th, const double* ph, int64_t npts,
+                         const double* gbar, const double* hbar,
+                         hipStream_t s);                 // adjoint.hip
+clm_status poisson_adjoint(Plan* p, double* dkappa, hipStream_t s);
 int mfma_ring_blocks(int H);                             // sht_mfma.hip
 clm_status mfma_tables(Plan* p, hipStream_t s);
 clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s);

@@ -41,6 +41,11 @@ Plan::~Plan() {
   for (auto* q : ulev) f(q);
   for (auto* q : ulev2) f(q);
   for (auto& s : slots) { f(s.alm); f(s.psi_s); f(s.u0); f(s.du); }
+  f(adj_ubar); f(adj_psi); f(adj_ks); f(adj_alm);
+  for (auto* q : adj_u) f(q);
+  for (auto* q : adj_v) f(q);
+  for (auto* q : adj_f) f(q);
+  for (auto* q : adj_w) f(q);
 }
 
 namespace {
@@ -149,6 +154,30 @@ clm_status alloc(Plan* p, T** ptr, size_t count) {
   p->bytes += count * sizeof(T);
   return CLM_OK;
 }
+
+clm_status adjoint_alloc(Plan* p) {
+  if (!p->mg) return CLM_OK;
+  const size_t G = size_t(p->n + 2) * (p->n + 2);
+  clm_status s;
+  if ((s = alloc(p, &p->adj_ubar, size_t(p->nbundle) * G)) != CLM_OK) return s;
+  p->adj_u.assign(p->nlev, nullptr);
+  p->adj_v.assign(p->nlev, nullptr);
+  p->adj_f.assign(p->nlev, nullptr);
+  p->adj_w.assign(p->nlev, nullptr);
+  for (int l = 0; l < p->nlev; ++l) {
+    const size_t c = size_t(p->nbundle) * (p->n >> l) * (p->n >> l);
+    if ((s = alloc(p, &p->adj_u[l], c)) != CLM_OK) return s;
+    if ((s = alloc(p, &p->adj_v[l], c)) != CLM_OK) return s;
+    if ((s = alloc(p, &p->adj_f[l], c)) != CLM_OK) return s;
+    if ((s = alloc(p, &p->adj_w[l], c)) != CLM_OK) return s;
+  }
+  if ((s = alloc(p, &p->adj_psi, size_t(p->npix_s))) != CLM_OK) return s;
+  if ((s = alloc(p, &p->adj_ks, size_t(p->npix_s))) != CLM_OK) return s;
+  if ((s = alloc(p, &p->adj_alm, size_t(p->nalm) * 2)) != CLM_OK) return s;
+  if (hipMemset(p->adj_ubar, 0, size_t(p->nbundle) * G * 8) != hipSuccess) return CLM_EHIP;
+  return CLM_OK;
+}
+
 
 #define CLM_TRY(x)                   \
   do {                               \
@@ -322,7 +351,7 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
       d.nside_fine > 8192 || d.lmax < 1 || d.max_planes < 1 ||
       (d.solver != CLM_SOLVER_SHT && d.solver != CLM_SOLVER_SHT_MG) ||
       (d.legendre_prec != CLM_FP64 && d.legendre_prec != CLM_FP32 &&
-       d.legendre_prec != CLM_BF16X3))
+       d.legendre_prec != CLM_BF16X3) || (d.adjoint != 0 && d.adjoint != 1))
     return CLM_EINVAL;
   if (d.solver == CLM_SOLVER_SHT && d.nside_sht != d.nside_fine) return CLM_EINVAL;
   if (d.solver == CLM_SOLVER_SHT_MG) {
@@ -378,6 +407,7 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
   if ((s = alloc(p, &p->red, 1024)) != CLM_OK) return bail(s);
   if ((s = alloc(p, &p->status_dev, 1)) != CLM_OK) return bail(s);
   if (hipMemset(p->status_dev, 0, sizeof(int)) != hipSuccess) return bail(CLM_EHIP);
+  if (d.adjoint && (s = adjoint_alloc(p)) != CLM_OK) return bail(s);
   if (d.legendre_prec != CLM_FP64) {
     p->batch = d.max_planes < 16 ? d.max_planes : 16;
     if ((s = alloc(p, &p->rcoef, size_t(p->nalm) * 2)) != CLM_OK) return bail(s);
@@ -649,3 +679,25 @@ clm_status clm_raytrace_planes(clm_plan plan, const void* kappa, int32_t kappa_i
 }
 
 }  // extern "C"
+
+clm_status clm_shear_adjoint(clm_plan plan, int32_t slot, const double* theta, const double* phi,
+                             int64_t npts, const double* dgrad, const double* dhess,
+                             hipStream_t stream) {
+  if (!plan || slot < 0 || slot >= plan->d.max_planes || npts < 0) return CLM_EINVAL;
+  Plan* p = plan;
+  if (!p->mg || !p->d.adjoint)
+    return fail(p, CLM_EUNSUPPORTED, "the adjoint needs an SHT+MG plan created with adjoint = 1");
+  if (npts == 0) return CLM_OK;
+  if (!theta || !phi || !dgrad || !dhess) return CLM_EINVAL;
+  CLM_HIP(hipSetDevice(p->device));
+  return shear_adjoint(p, theta, phi, npts, dgrad, dhess, stream);
+}
+
+clm_status clm_poisson_adjoint(clm_plan plan, int32_t slot, double* dkappa, hipStream_t stream) {
+  if (!plan || !dkappa || slot < 0 || slot >= plan->d.max_planes) return CLM_EINVAL;
+  Plan* p = plan;
+  if (!p->mg || !p->d.adjoint)
+    return fail(p, CLM_EUNSUPPORTED, "the adjoint needs an SHT+MG plan created with adjoint = 1");
+  CLM_HIP(hipSetDevice(p->device));
+  return poisson_adjoint(p, dkappa, stream);
+}

@@ -675,6 +675,30 @@ clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipSt
   return ring_inverse(p, p->G, 1, p->slots[slot].psi_s, s);
 }
 
+// Transpose of (SHT-grid kappa -> analysis -> Poisson -> synthesis): with the
+// uniform weight w = 4 pi / N_pix, synthesis^T is the unweighted analysis
+// with the m >= 1 terms doubled and analysis^T is w times the synthesis with
+// the m >= 1 terms halved; the factors cancel around the real diagonal
+// Poisson step, so the transpose is the same chain applied to psi bar.
+clm_status sht_adjoint(Plan* p, const double* psibar, double* alm, double* ksbar,
+                       hipStream_t s) {
+  clm_status st = ring_forward(p, psibar, p->F, s);
+  if (st != CLM_OK) return st;
+  const int rpt = rpt_for(p->H);
+  switch (rpt) {
+    case 1: launch_analysis<1>(p, s, alm); break;
+    case 2: launch_analysis<2>(p, s, alm); break;
+    case 4: launch_analysis<4>(p, s, alm); break;
+    case 8: launch_analysis<8>(p, s, alm); break;
+    case 16: launch_analysis<16>(p, s, alm); break;
+    default: return fail(p, CLM_EUNSUPPORTED, "too many rings per thread");
+  }
+  CLM_LAUNCH_CHECK();
+  if ((st = poisson(p, alm, s)) != CLM_OK) return st;
+  if ((st = synthesis(p, alm, s)) != CLM_OK) return st;
+  return ring_inverse(p, p->G, 1, ksbar, s);
+}
+
 clm_status sht_solve_batch(Plan* p, const void* kappa, int kappa_fp64, int first_slot,
                            int nplanes, hipStream_t s) {
   if (nplanes < 1 || nplanes > p->batch) return fail(p, CLM_EINVAL, "batch size");

@@ -340,3 +340,96 @@ def test_raytrace_parity(clm):
             expect = ((1 - w) * Api + w * Ai).ravel()
         assert np.abs(Ag[:, i] - expect).max() < 3e-6, (i, k)
     plan.close()
+
+
+# ---------------------------------------------------------------- adjoint (C5)
+@pytest.fixture(scope="module")
+def adj_case():
+    from oracle import adjoint as oadj
+    spec = omg.PatchSpec(16, 4, 8, 4, ncell=16, vcycles=2)
+    g = osht.alm2map(16, 32, inputs.gaussian_alm(32, seed=8, sigma=0.5))
+    kap = 0.01 * (np.exp(g) - np.mean(np.exp(g)))
+    th, ph = inputs.uniform_sphere(300, seed=9)
+    rng = np.random.default_rng(10)
+    g1o, g2o = 0.26 * rng.standard_normal(th.size), 0.26 * rng.standard_normal(th.size)
+    _, h = oadj.forward(spec, kap, th, ph)
+    chi2, hbar = oadj.shear_chi2(h, g1o, g2o)
+    grad = oadj.adjoint(spec, th, ph, np.zeros((2, th.size)), hbar)
+    return dict(spec=spec, kap=kap, th=th, ph=ph, g1o=g1o, g2o=g2o, chi2=chi2, grad=grad)
+
+
+def _adj_plan(clm, N, Ns, lmax, Nb, n, cyc):
+    return clm.Plan(N, nside_sht=Ns, lmax=lmax, nside_bundle=Nb, patch_cells=n,
+                    mg_vcycles=cyc, mg_prec="fp64", adjoint=1)
+
+
+def test_adjoint_gradient_matches_oracle(clm, adj_case):
+    c = adj_case
+    plan = _adj_plan(clm, 16, 4, 8, 4, 16, 2)
+    th, ph = torch.from_numpy(c["th"]).cuda(), torch.from_numpy(c["ph"]).cuda()
+    kap = torch.from_numpy(c["kap"]).cuda()
+    plan.poisson_solve(kap)
+    _, h = plan.shear_from_potential(th, ph)
+    hn = h.cpu().numpy()
+    r1 = 0.5 * (hn[0] - hn[1]) - c["g1o"]
+    r2 = hn[2] - c["g2o"]
+    hbar = torch.from_numpy(np.stack([r1, -r1, 2.0 * r2]) / 0.26 ** 2).cuda()
+    plan.shear_adjoint(th, ph, torch.zeros(2, th.numel(), dtype=torch.float64, device="cuda"), hbar)
+    grad = plan.poisson_adjoint().cpu().numpy()
+    e = rel(grad, c["grad"])
+    print("PARITY adjoint grad vs oracle %.3e" % e, flush=True)
+    assert e < 1e-10
+    plan.sync_status()
+    plan.close()
+
+
+def test_adjoint_dot_product_tile_levels(clm):
+    """<F kappa, y> = <kappa, F^T y> with the tile-level forward (patches of
+    256^2) and the adjoint on the GPU, FP64."""
+    N, Ns, lmax, Nb = 64, 16, 32, 4
+    plan = _adj_plan(clm, N, Ns, lmax, Nb, 256, 3)
+    rng = np.random.default_rng(11)
+    kap = torch.from_numpy(0.01 * rng.standard_normal(12 * N * N)).cuda()
+    th, ph = (torch.from_numpy(a).cuda() for a in inputs.uniform_sphere(2000, seed=12))
+    plan.poisson_solve(kap)
+    g, h = plan.shear_from_potential(th, ph)
+    gb = torch.from_numpy(rng.standard_normal((2, th.numel()))).cuda()
+    hb = torch.from_numpy(rng.standard_normal((3, th.numel()))).cuda()
+    plan.shear_adjoint(th, ph, gb, hb)
+    kb = plan.poisson_adjoint()
+    lhs = float((g * gb).sum() + (h * hb).sum())
+    rhs = float((kap * kb).sum())
+    e = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+    print("PARITY adjoint dot product %.3e (%.6e, %.6e)" % (e, lhs, rhs), flush=True)
+    assert e < 1e-10
+    plan.sync_status()
+    plan.close()
+
+
+def test_autograd_chi2_central_differences(clm):
+    """PoissonShearFn gradient of the shear chi^2 (exactly quadratic) against
+    central differences of the GPU forward."""
+    N = 32
+    plan = _adj_plan(clm, N, 8, 16, 4, 64, 2)
+    rng = np.random.default_rng(13)
+    kap0 = torch.from_numpy(0.01 * rng.standard_normal(12 * N * N)).cuda()
+    th, ph = (torch.from_numpy(a).cuda() for a in inputs.uniform_sphere(500, seed=14))
+    o1 = torch.from_numpy(0.26 * rng.standard_normal(th.numel())).cuda()
+    o2 = torch.from_numpy(0.26 * rng.standard_normal(th.numel())).cuda()
+
+    def chi2(k):
+        _, h = clm.PoissonShearFn.apply(k, th, ph, plan)
+        return (((0.5 * (h[0] - h[1]) - o1) ** 2 + (h[2] - o2) ** 2) / 0.26 ** 2).sum()
+
+    kap = kap0.clone().requires_grad_(True)
+    (grad,) = torch.autograd.grad(chi2(kap), kap)
+    step = 1e-3 * float(kap0.abs().mean())
+    for p in rng.choice(12 * N * N, 4, replace=False):
+        e = torch.zeros_like(kap0)
+        e[p] = step
+        fd = (float(chi2(kap0 + e)) - float(chi2(kap0 - e))) / (2 * step)
+        g = float(grad[p])
+        print("PARITY autograd pixel %d fd %.9e grad %.9e" % (p, fd, g), flush=True)
+        assert abs(fd - g) <= 1e-6 * (abs(g) + 1e-3 * float(grad.abs().max()))
+    plan.sync_status()
+    plan.close()
