@@ -355,6 +355,98 @@ def c4_run(clm, torch, inputs):
     return out
 
 
+def c5_run(clm, torch, inputs):
+    """Differentiation workload: 8 planes at Nside_fine (256, 512, 1024, 2048)
+    x 2 (Nside_sht = Nside / 8, lmax = 2 Nside_sht, bundles Nside / 64,
+    patches of 256^2, 4 V-cycles, FP64); lognormal kappa_true (sigma_g 0.5,
+    seeds 500 + i), 1e5 uniform positions per plane (700 + i), observed shear
+    = shear of kappa_true + N(0, 0.26^2) per component (600 + i); the chi^2
+    gradient is taken at another draw kappa_eval (900 + i).  Timed: forward
+    solve + shear at the points + transpose, per plane.  Checks: the dot
+    product <F x, y> = <x, F^T y> per plane and central differences of the
+    (exactly quadratic) chi^2 at random fine pixels (64 on the two smallest
+    planes, 8 on the others)."""
+    nsides = [256, 512, 1024, 2048] * 2
+    plans = {}
+    out = dict(planes=[], workload="8 planes Nside_fine 256..2048, 1e5 shear points each, "
+                                   "chi^2 gradient through SHT+MG (FP64)")
+    total_ms = 0.0
+    for i, N in enumerate(nsides):
+        if N not in plans:
+            plans[N] = clm.Plan(N, nside_sht=N // 8, lmax=N // 4, nside_bundle=N // 64,
+                                patch_cells=256, mg_vcycles=4, mg_prec="fp64", adjoint=1)
+        plan = plans[N]
+        lmax = N // 4
+
+        def lognormal(seed):
+            g = clm.alm2map(torch.from_numpy(inputs.gaussian_alm(lmax, seed=seed, sigma=0.5)).cuda(),
+                            lmax, N)
+            e = torch.exp(g)
+            return (inputs.deflection_scale(lmax, 0.5) * (e - e.mean())).contiguous()
+        k_true, k_eval = lognormal(500 + i), lognormal(900 + i)
+        th, ph = (torch.from_numpy(a).cuda() for a in inputs.uniform_sphere(100000, seed=700 + i))
+        rng = np.random.default_rng(600 + i)
+        plan.poisson_solve(k_true)
+        _, h = plan.shear_from_potential(th, ph)
+        o1 = 0.5 * (h[0] - h[1]) + torch.from_numpy(0.26 * rng.standard_normal(th.numel())).cuda()
+        o2 = h[2] + torch.from_numpy(0.26 * rng.standard_normal(th.numel())).cuda()
+
+        def chi2_of(k):
+            plan.poisson_solve(k)
+            _, hh = plan.shear_from_potential(th, ph)
+            r1, r2 = 0.5 * (hh[0] - hh[1]) - o1, hh[2] - o2
+            return float(((r1 * r1 + r2 * r2) / 0.26 ** 2).sum()), r1, r2
+
+        chi2_of(k_eval)                       # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c2, r1, r2 = chi2_of(k_eval)
+        hb = torch.stack([r1, -r1, 2.0 * r2]) / 0.26 ** 2
+        zero = torch.zeros(2, th.numel(), dtype=torch.float64, device="cuda")
+        plan.shear_adjoint(th, ph, zero, hb)
+        grad = plan.poisson_adjoint()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        total_ms += ms
+        # dot-product test with random (x, y)
+        x = torch.from_numpy(rng.standard_normal(plan.npix_fine) * float(k_eval.std())).cuda()
+        plan.poisson_solve(x)
+        g, hh = plan.shear_from_potential(th, ph)
+        gy = torch.from_numpy(rng.standard_normal((2, th.numel()))).cuda()
+        hy = torch.from_numpy(rng.standard_normal((3, th.numel()))).cuda()
+        plan.shear_adjoint(th, ph, gy, hy)
+        xt = plan.poisson_adjoint()
+        lhs, rhs = float((g * gy).sum() + (hh * hy).sum()), float((x * xt).sum())
+        # central differences
+        npx = 64 if N <= 512 else 8
+        step = 1e-3 * float(k_eval.pow(2).mean().sqrt())
+        worst = 0.0
+        gmax = float(grad.abs().max())
+        for p in rng.choice(plan.npix_fine, npx, replace=False):
+            e = torch.zeros_like(k_eval)
+            e[p] = step
+            fd = (chi2_of(k_eval + e)[0] - chi2_of(k_eval - e)[0]) / (2 * step)
+            worst = max(worst, abs(fd - float(grad[p])) / (abs(float(grad[p])) + 1e-3 * gmax))
+        # the loss is exactly quadratic: a large step removes the rounding of
+        # the chi^2 sums from the comparison
+        big = 10.0 * float(k_eval.pow(2).mean().sqrt())
+        worst_big = 0.0
+        for p in rng.choice(plan.npix_fine, 8, replace=False):
+            e = torch.zeros_like(k_eval)
+            e[p] = big
+            fd = (chi2_of(k_eval + e)[0] - chi2_of(k_eval - e)[0]) / (2 * big)
+            worst_big = max(worst_big, abs(fd - float(grad[p])) / (abs(float(grad[p])) + 1e-3 * gmax))
+        plan.sync_status()
+        out["planes"].append(dict(nside=N, ms_gradient=ms, chi2=c2,
+                                  dot_product_rel=abs(lhs - rhs) / max(abs(lhs), abs(rhs)),
+                                  fd_pixels=npx, fd_step=step, fd_max_rel=worst,
+                                  fd_max_rel_step_10rms=worst_big))
+    for pl in plans.values():
+        pl.close()
+    out["gradients_per_s"] = len(nsides) * 1000.0 / total_ms
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,6 +457,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--no-c4", action="store_true",
                     help="skip the batched-precision workload (32 uneven pure-SHT planes)")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the differentiation workload (8 planes, chi^2 gradient)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with a plain copy kernel of known size (counter calibration)")
     ap.add_argument("--summarize-stats", nargs=2, metavar=("CSV", "CMD"),
@@ -471,6 +565,9 @@ def main():
     if not args.no_c4:
         print("bench: batched precision forms", file=sys.stderr, flush=True)
         out["c4_precision_forms"] = c4_run(clm, torch, inputs)
+    if not args.no_c5:
+        print("bench: differentiation", file=sys.stderr, flush=True)
+        out["c5_gradient"] = c5_run(clm, torch, inputs)
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
