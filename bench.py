@@ -248,9 +248,11 @@ def cpu_baseline(torch, kappa, plan64, sample_bundles):
     """The FP64 oracle, as it stands, on a bounded sample of the same plane:
     the full SHT stage, then patch setup + V-cycles + shear at the bundle's
     pixels + one ray step for `sample_bundles` bundles, scaled to one plane."""
+    from threadpoolctl import threadpool_limits
     from oracle import healpix as hp
     from oracle import mg as omg
     from oracle import rays as orays
+    threadpool_limits(1)                 # the oracle as it stands, one core
     kap = kappa.double().cpu().numpy()
     spec = omg.PatchSpec(NF, NS, LMAX, NB, ncell=NCELL, vcycles=VCYC)
     t = time.perf_counter()
