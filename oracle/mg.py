@@ -259,6 +259,48 @@ def residual_norm(spec, du, fp):
     return np.sqrt(np.sum(A * r * r) / np.sum(A))
 
 
+def area_rms(x, area_rows):
+    """Area-weighted RMS of a cell field (rows weighted by their area)."""
+    A = area_rows[:, None] * np.ones_like(x)
+    return np.sqrt(np.sum(A * x * x) / np.sum(A))
+
+
+def eps_ratio(spec, du, fp):
+    """Stopping quantity of Sec. 3.2: epsilon = ||r_h|| / ||tau|| with the
+    residual r_h = f' - L_h du on the finest level and the relative
+    truncation error tau = L_H(R du) - R(L_h du) on the first coarse level,
+    both area-weighted RMS; du given with or without its ghost ring."""
+    c = level_coeffs(spec, spec.n)
+    cH = level_coeffs(spec, spec.n // 2)
+    x = du[1:-1, 1:-1] if du.shape[0] == spec.n + 2 else du
+
+    def L0(v, cc):
+        u = np.zeros((cc["n"] + 2, cc["n"] + 2))
+        u[1:-1, 1:-1] = v
+        return apply_L0(u, cc)
+
+    r = fp - L0(x, c)
+    tau = L0(restrict(x, c), cH) - restrict(L0(x, c), c)
+    nr, nt = area_rms(r, c["area"]), area_rms(tau, cH["area"])
+    if nt == 0.0:
+        return 0.0 if nr == 0.0 else np.inf
+    return nr / nt
+
+
+def mg_solve_eps(spec, fp, eps=0.1, max_cycles=20):
+    """V-cycles from du = 0 until eps_ratio < eps (Sec. 3.2), at most
+    max_cycles.  Returns (du, cycles, [epsilon after each cycle])."""
+    coeffs = all_coeffs(spec)
+    du = np.zeros((spec.n + 2, spec.n + 2))
+    hist = []
+    for k in range(max_cycles):
+        vcycle(spec, du, fp, 0, coeffs)
+        hist.append(eps_ratio(spec, du, fp))
+        if hist[-1] < eps:
+            return du, k + 1, hist
+    return du, max_cycles, hist
+
+
 # --------------------------------------------------------------------------
 # the plane solve
 # --------------------------------------------------------------------------

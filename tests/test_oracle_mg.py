@@ -220,3 +220,38 @@ def test_sht_mg_band_limited_field():
                            [exact["U_tp"][p], exact["U_pp"][p]]])
             assert np.abs(g - ge).max() < 0.01 * np.abs(ge).max()
             assert np.abs(U - Ue).max() < 0.01 * np.abs(Ue).max()
+
+
+def test_eps_rule_truncation_order_and_stopping():
+    """tau of a smooth field falls as Delta^2 (the truncation error of the
+    5-point operator); the residual of the exact discrete solution is zero;
+    the epsilon rule stops at the first cycle with epsilon < eps and then
+    equals the fixed-cycle iterate."""
+    R = mg.patch_rotation(4, 40)
+    fn = lambda t, p: _ylm_real(7, 2, t, p)
+    taus = []
+    for n in (32, 64, 128):
+        spec = _spec(n)
+        x = _cell_field(spec, R, n, fn, ghosts=0)
+        c, cH = mg.level_coeffs(spec, n), mg.level_coeffs(spec, n // 2)
+        L0 = lambda v, cc: mg.apply_L0(np.pad(v, 1), cc)
+        tau = L0(mg.restrict(x, c), cH) - mg.restrict(L0(x, c), c)
+        # away from the faces (where the ghost reflection dominates)
+        m = n // 8
+        taus.append(np.sqrt(np.mean(tau[m:-m, m:-m] ** 2)))
+    order = np.log2(np.array(taus[:-1]) / np.array(taus[1:]))
+    assert np.all(np.abs(order - 2.0) < 0.25), order
+    spec = _spec(64)
+    rng = np.random.default_rng(5)
+    f = rng.normal(size=(64, 64))
+    du_e, k, hist = mg.mg_solve_eps(spec, f, eps=1e-3, max_cycles=30)
+    assert hist[-1] < 1e-3 and all(h >= 1e-3 for h in hist[:-1])
+    assert np.all(np.diff(hist) < 0)
+    du_f = mg.mg_solve(spec, f, vcycles=k)
+    assert np.array_equal(du_e, du_f)
+    # exact discrete solution: zero residual, so epsilon -> 0
+    co = mg.all_coeffs(spec)
+    u = np.zeros((66, 66))
+    for _ in range(40):
+        mg.vcycle(spec, u, f, 0, co)
+    assert mg.eps_ratio(spec, u, f) < 1e-9
