@@ -53,7 +53,7 @@ typedef enum {
   CLM_EINVAL = 1,           /* bad argument, size or pointer                 */
   CLM_ENOMEM = 2,           /* workspace allocation failed                   */
   CLM_EHIP = 3,             /* a HIP runtime call or kernel launch failed    */
-  CLM_ENOTCONV = 4,         /* reserved: multigrid tolerance not reached     */
+  CLM_ENOTCONV = 4,         /* epsilon rule not met within mg_max_vcycles    */
   CLM_ERAY_LEFT_PATCH = 5,  /* a point fell outside its bundle's patch       */
   CLM_ENONFINITE = 6,       /* a non-finite value was produced               */
   CLM_EUNSUPPORTED = 7      /* valid request this build does not implement   */
@@ -81,7 +81,8 @@ typedef struct {
   int32_t nside_bundle;  /* power of two, <= nside_fine                        */
   int32_t patch_factor;  /* patch side / bundle side (Sec. 3.2: 4)             */
   int32_t patch_cells;   /* finest cells per side: power of two, 8..4096       */
-  int32_t mg_vcycles;    /* fixed number of V-cycles per solve, >= 1           */
+  int32_t mg_vcycles;    /* fixed number of V-cycles per solve (>= 1); 0: the
+                            epsilon rule below decides per patch             */
   int32_t nu_pre;        /* red-black sweeps before restriction, 1..4          */
   int32_t nu_post;       /* red-black sweeps after prolongation, 1..4          */
   int32_t solver;        /* clm_solver                                         */
@@ -92,9 +93,17 @@ typedef struct {
                             (matrix cores; the planes of one clm_poisson_solve
                             call are batched as GEMM columns, 16 at a time;
                             the lambda_lm recurrence stays FP64)           */
+  int32_t mg_max_vcycles; /* epsilon rule: at most this many V-cycles (>= 1) */
+  double mg_eps;         /* epsilon rule (Sec. 3.2): a patch stops after the
+                            first V-cycle with ||r_h|| / ||tau|| < mg_eps,
+                            r_h = f' - L_h du, tau = L_H(R du) - R(L_h du) on
+                            the first coarse level, area-weighted RMS norms;
+                            default 0.1.  Used only when mg_vcycles == 0;
+                            must be >= 0 in any case                      */
   int32_t adjoint;       /* 1: also allocate the workspace of
                             clm_shear_adjoint / clm_poisson_adjoint (FP64,
-                            about 4 x 8 bytes per finest cell); SHT+MG only */
+                            about 4 x 8 bytes per finest cell); SHT+MG
+                            with a fixed mg_vcycles > 0 only               */
 } clm_plan_desc;
 
 /* Fill *d with the defaults for a fine grid: nside_sht = nside_fine / 8
@@ -269,6 +278,18 @@ clm_status clm_raytrace_planes(clm_plan plan, const void* kappa_dev, int32_t kap
 clm_status clm_ray_update(clm_plan plan, int32_t slot, const double* chi_host, int32_t nchi,
                           int32_t m, double curvature_K, const clm_rays* rays,
                           hipStream_t stream);
+
+/*
+ * Multigrid convergence of the latest SHT+MG solve: per patch (bundle index
+ * order) the epsilon ratio after the patch's last V-cycle and the number of
+ * V-cycles it ran (device buffers of nbundle FP64 / int32 values).  The
+ * ratio is NaN when it was not measured (fixed count, mg_vcycles > 0).  After
+ * a clm_poisson_solve of several planes the values are the last plane's.  Under
+ * the epsilon rule a patch still above mg_eps after mg_max_vcycles latches
+ * CLM_ENOTCONV (returned by clm_plan_sync_status).
+ */
+clm_status clm_get_mg_convergence(clm_plan plan, double* eps_dev, int32_t* cycles_dev,
+                                  hipStream_t stream);
 
 /*
  * Adjoint of the solve (plans created with desc.adjoint = 1, SHT+MG solver).

@@ -22,7 +22,8 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "nside_fine", "nside_sht", "lmax", "nside_bundle", "patch_factor", "patch_cells",
         "mg_vcycles", "nu_pre", "nu_post", "solver", "mg_prec", "max_planes",
-        "legendre_prec", "adjoint")]
+        "legendre_prec", "mg_max_vcycles")] + [("mg_eps", ctypes.c_double),
+                                               ("adjoint", ctypes.c_int32)]
 
 
 class Rays(ctypes.Structure):
@@ -67,6 +68,7 @@ _SIGS = {
     "clm_ray_update": (_P, _I32, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays), _P),
     "clm_shear_adjoint": (_P, _I32, _P, _P, _I64, _P, _P, _P),
     "clm_poisson_adjoint": (_P, _I32, _P, _P),
+    "clm_get_mg_convergence": (_P, _P, _P, _P),
     "clm_plan_set_timing": (_P, _I32),
     "clm_plan_get_timing": (_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_D),
                             ctypes.POINTER(_I64), _I32, ctypes.POINTER(_I32)),
@@ -130,7 +132,7 @@ class Plan:
                 v = {"sht": SOLVER_SHT, "sht_mg": SOLVER_SHT_MG}[v]
             if k in ("mg_prec", "legendre_prec") and isinstance(v, str):
                 v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}[v]
-            setattr(d, k, int(v))
+            setattr(d, k, float(v) if k == "mg_eps" else int(v))
         dev = torch.cuda.current_device() if device is None else int(device)
         h = ctypes.c_void_p()
         st = L.clm_plan_create(ctypes.byref(d), dev, ctypes.byref(h))
@@ -202,6 +204,16 @@ class Plan:
             raise ValueError("kappa has %d pixels, plan expects %d" % (k.shape[1], self.npix_fine))
         self._check(lib().clm_poisson_solve(self.h, _ptr(k), int(k.dtype == torch.float64),
                                             first_slot, k.shape[0], _stream()), "poisson_solve")
+
+    def mg_convergence(self):
+        """(epsilon [nbundle] float64, V-cycles [nbundle] int32) of the latest
+        multigrid solve, per patch in bundle order."""
+        nb = 12 * self.desc["nside_bundle"] ** 2
+        eps = torch.empty(nb, dtype=torch.float64, device=self.device)
+        cyc = torch.empty(nb, dtype=torch.int32, device=self.device)
+        self._check(lib().clm_get_mg_convergence(self.h, _ptr(eps), _ptr(cyc), _stream()),
+                    "get_mg_convergence")
+        return eps, cyc
 
     def psi_alm(self, slot=0):
         out = torch.empty(nalm(self.lmax), 2, dtype=torch.float64, device=self.device)

@@ -14,7 +14,7 @@
 namespace clm {
 
 // Device-side latched conditions (bit flags in plan->status_dev).
-enum : int { ST_LEFT_PATCH = 1, ST_NONFINITE = 2 };
+enum : int { ST_LEFT_PATCH = 1, ST_NONFINITE = 2, ST_NOTCONV = 4 };
 
 // Largest multigrid level handled entirely inside one workgroup's LDS.
 constexpr int kLdsLevelMax = 64;
@@ -80,6 +80,9 @@ struct Plan {
   // per coarser tile level k (1 .. ktile), and the LDS level ktile:
   std::vector<void*> ubar, rbar, flev, ulev, ulev2;
   int* status_dev = nullptr;
+  double* mg_eps_dev = nullptr;   // [nbundle] epsilon ratio of the latest solve
+  int* mg_cycles_dev = nullptr;   // [nbundle] V-cycles run
+  int* mg_done_dev = nullptr;     // [nbundle] epsilon rule met
   // adjoint workspace (desc.adjoint): u0 + du bar per patch with ghosts, and
   // per level the transposed V-cycle's u bar (two), f bar and a temporary
   double* adj_ubar = nullptr;

@@ -321,6 +321,7 @@ struct TileArgs {
   const T* ubarc;       // post: coarse ubar
   int fas_source;       // pre on level >= 1: A f = A L u_in + A f_in
   int f_scaled;         // f_in already holds A f
+  const int* done;      // epsilon rule: patches that stopped (nullptr: none)
 };
 
 constexpr int quads_per_thread(int q) {
@@ -596,6 +597,7 @@ __global__ __launch_bounds__(kTileBlock) void k_mg_pre(TileArgs<T> a) {
   const int tpp = a.ntile * a.ntile;
   const int64_t patch = lb / tpp;
   const int tt = int(lb % tpp);
+  if (a.done && a.done[patch]) return;
   const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
   const int n = a.n, nc = n / 2;
   const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
@@ -670,6 +672,7 @@ __global__ __launch_bounds__(kTileBlock) void k_mg_post(TileArgs<T> a) {
   const int n = a.n, nc = n / 2;
   const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
   const int ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // i0, j0 even
+  if (a.done && a.done[patch]) return;
   qload_rows(t, a.coef, n, i0);
   for (int item = threadIdx.x; item < CR * CR; item += kTileBlock) {
     const int I = ci0 + item / CR, J = cj0 + item % CR;
@@ -761,6 +764,7 @@ struct LdsArgs {
   const T* f_in;          // K = 0: f'; K > 0: rbar_K
   T* u_out;
   int fas_source;
+  const int* done;        // epsilon rule: patches that stopped (nullptr: none)
 };
 
 template <typename T>
@@ -846,6 +850,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mg_lds(LdsArgs<T> a) {
   extern __shared__ unsigned char smem[];
   const int64_t patch = xcd_block();
+  if (a.done && a.done[patch]) return;
   const int K = a.lv.K, nl = a.lv.nlev, n0 = a.lv.n0;
   for (int l = K; l < nl; ++l) {
     const int nn = n0 >> (l - K);
@@ -933,6 +938,112 @@ __global__ __launch_bounds__(kBlock) void k_mg_lds(LdsArgs<T> a) {
     const LLevel<T> L = lds_level<T>(smem, K, n0, K);
     for (int idx = threadIdx.x; idx < n0 * n0; idx += kBlock) a.u_out[g0 + idx] = L.u[idx];
   }
+}
+
+// ------------------------------------------------------------ epsilon rule
+// epsilon = ||r_h|| / ||tau|| per patch (Sec. 3.2 stopping rule):
+// r_h = f' - L_h du on the finest level, tau = L_H(R du) - R(L_h du) on the
+// first coarse level, area-weighted RMS, accumulated in FP64; one block per
+// patch, one coarse cell (and its four children) per step.
+template <typename T>
+struct EpsArgs {
+  int n;
+  const double* c0;     // finest-level rows
+  const double* c1;     // first coarse level rows
+  const T* du;
+  const T* fp;
+  double eps;
+  int cycle;            // V-cycles run so far
+  int measure_only;     // 1: write epsilon only (fixed cycle count)
+  int* done;
+  int* cycles;
+  double* eps_out;
+};
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < int(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mg_eps(EpsArgs<T> a) {
+  __shared__ double red[kBlock / 64];
+  const int64_t patch = blockIdx.x;
+  if (!a.measure_only && a.done[patch]) return;
+  const int n = a.n, nc = n / 2;
+  const T* x = a.du + size_t(patch) * n * n;
+  const T* f = a.fp + size_t(patch) * n * n;
+  auto X = [&](int i, int j) -> double {  // zero face value: ghost = -interior
+    const int ii = min(max(i, 0), n - 1), jj = min(max(j, 0), n - 1);
+    const double v = double(x[ii * n + jj]);
+    return (ii != i || jj != j) ? -v : v;
+  };
+  auto Lh = [&](int i, int j) {
+    const double* c = a.c0 + 4 * i;
+    const double u = X(i, j);
+    return (c[0] * (X(i - 1, j) - u) + c[1] * (X(i + 1, j) - u) +
+            (X(i, j - 1) - 2.0 * u + X(i, j + 1)) / c[2]) / c[3];
+  };
+  auto Rst = [&](int I, int J, auto&& g) {
+    const double a0 = a.c0[4 * (2 * I) + 3], a1 = a.c0[4 * (2 * I + 1) + 3];
+    return (a0 * (g(2 * I, 2 * J) + g(2 * I, 2 * J + 1)) +
+            a1 * (g(2 * I + 1, 2 * J) + g(2 * I + 1, 2 * J + 1))) / (2.0 * (a0 + a1));
+  };
+  double sr = 0, sa = 0, st = 0, sb = 0;
+  for (int k = threadIdx.x; k < nc * nc; k += blockDim.x) {
+    const int I = k / nc, J = k % nc;
+    auto ub = [&](int P, int Q) { return Rst(P, Q, X); };
+    const double u = ub(I, J);
+    const double up = I > 0 ? ub(I - 1, J) : -u, dn = I < nc - 1 ? ub(I + 1, J) : -u;
+    const double lf = J > 0 ? ub(I, J - 1) : -u, rt = J < nc - 1 ? ub(I, J + 1) : -u;
+    const double* cH = a.c1 + 4 * I;
+    const double LH = (cH[0] * (up - u) + cH[1] * (dn - u) + (lf - 2.0 * u + rt) / cH[2]) / cH[3];
+    double lh[4];
+    for (int q = 0; q < 4; ++q) lh[q] = Lh(2 * I + (q >> 1), 2 * J + (q & 1));
+    const double a0 = a.c0[4 * (2 * I) + 3], a1 = a.c0[4 * (2 * I + 1) + 3];
+    const double RL = (a0 * (lh[0] + lh[1]) + a1 * (lh[2] + lh[3])) / (2.0 * (a0 + a1));
+    const double tau = LH - RL;
+    st += cH[3] * tau * tau;
+    sb += cH[3];
+    for (int q = 0; q < 4; ++q) {
+      const int i = 2 * I + (q >> 1), j = 2 * J + (q & 1);
+      const double r = double(f[i * n + j]) - lh[q];
+      const double A = a.c0[4 * i + 3];
+      sr += A * r * r;
+      sa += A;
+    }
+  }
+  sr = block_sum(sr, red);
+  sa = block_sum(sa, red);
+  st = block_sum(st, red);
+  sb = block_sum(sb, red);
+  if (threadIdx.x != 0) return;
+  const double nr = sqrt(sr / sa), nt = sqrt(st / sb);
+  const double e = nt > 0.0 ? nr / nt : (nr > 0.0 ? INFINITY : 0.0);
+  a.eps_out[patch] = e;
+  if (a.measure_only) return;
+  a.cycles[patch] = a.cycle;
+  if (e < a.eps) a.done[patch] = 1;
+}
+
+__global__ void k_fill_int(int64_t n, int v, int* y) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = v;
+}
+
+__global__ void k_fill_f64(int64_t n, double v, double* y) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = v;
+}
+
+__global__ void k_notconv(int64_t n, const int* done, int* status) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n && !done[t]) atomicOr(status, ST_NOTCONV);
 }
 
 // ------------------------------------------------------------ potential out
@@ -1045,16 +1156,52 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
   const size_t lds_bytes = lds_elems * sizeof(T);
   if (allow_lds(p, k_mg_lds<T>, lds_bytes) != CLM_OK) return CLM_EHIP;
 
+  // epsilon rule (mg_vcycles == 0): every patch runs V-cycles until its
+  // epsilon drops below mg_eps, at most mg_max_vcycles; patches that stopped
+  // skip the remaining cycles, so the host never waits on the device
+  const bool eps_mode = d.mg_vcycles == 0;
+  const int ncyc = eps_mode ? d.mg_max_vcycles : d.mg_vcycles;
+  const int* done = eps_mode ? p->mg_done_dev : nullptr;
   auto tile_args = [&](int l, bool pre) {
     TileArgs<T> a{};
     a.n = n >> l;
     a.ntile = a.n / kTile;
     a.nu = pre ? d.nu_pre : d.nu_post;
     a.coef = p->coef + p->lev[l].crow;
+    a.done = done;
     return a;
   };
-  for (int cyc = 0; cyc < d.mg_vcycles; ++cyc) {
+  const dim3 gfill(unsigned((np + kBlock - 1) / kBlock));
+  if (eps_mode) {
+    hipLaunchKernelGGL(k_fill_int, gfill, dim3(kBlock), 0, s, np, 0, p->mg_done_dev);
+    CLM_LAUNCH_CHECK();
+  } else {
+    hipLaunchKernelGGL(k_fill_int, gfill, dim3(kBlock), 0, s, np, d.mg_vcycles,
+                       p->mg_cycles_dev);
+    hipLaunchKernelGGL(k_fill_f64, gfill, dim3(kBlock), 0, s, np, double(NAN), p->mg_eps_dev);
+    CLM_LAUNCH_CHECK();
+  }
+  la.done = done;
+  for (int cyc = 0; cyc < ncyc; ++cyc) {
     const bool first = cyc == 0;
+    if (eps_mode && !first) {
+      EpsArgs<T> e{};
+      e.n = n;
+      e.c0 = p->coef + p->lev[0].crow;
+      e.c1 = p->coef + p->lev[1].crow;
+      e.du = du;
+      e.fp = fp;
+      e.eps = d.mg_eps;
+      e.cycle = cyc;
+      e.done = p->mg_done_dev;
+      e.cycles = p->mg_cycles_dev;
+      e.eps_out = p->mg_eps_dev;
+      {
+        CLM_TIMED(p, s, "mg_eps");
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_eps<T>), dim3(unsigned(np)), dim3(kBlock), 0, s, e);
+      }
+      CLM_LAUNCH_CHECK();
+    }
     if (K == 0) {
       la.u_in = first ? nullptr : du;
       la.f_in = fp;
@@ -1122,6 +1269,26 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
         if (st != CLM_OK) return st;
       }
     }
+  }
+  if (eps_mode) {
+    EpsArgs<T> e{};
+    e.n = n;
+    e.c0 = p->coef + p->lev[0].crow;
+    e.c1 = p->coef + p->lev[1].crow;
+    e.du = du;
+    e.fp = fp;
+    e.eps = d.mg_eps;
+    e.cycle = ncyc;
+    e.done = p->mg_done_dev;
+    e.cycles = p->mg_cycles_dev;
+    e.eps_out = p->mg_eps_dev;
+    {
+      CLM_TIMED(p, s, "mg_eps");
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_eps<T>), dim3(unsigned(np)), dim3(kBlock), 0, s, e);
+    }
+    hipLaunchKernelGGL(k_notconv, gfill, dim3(kBlock), 0, s, np,
+                       static_cast<const int*>(p->mg_done_dev), p->status_dev);
+    CLM_LAUNCH_CHECK();
   }
   return CLM_OK;
 }

@@ -42,6 +42,7 @@ Plan::~Plan() {
   for (auto* q : ulev2) f(q);
   for (auto& s : slots) { f(s.alm); f(s.psi_s); f(s.u0); f(s.du); }
   f(adj_ubar); f(adj_psi); f(adj_ks); f(adj_alm);
+  f(mg_eps_dev); f(mg_cycles_dev); f(mg_done_dev);
   for (auto* q : adj_u) f(q);
   for (auto* q : adj_v) f(q);
   for (auto* q : adj_f) f(q);
@@ -334,6 +335,8 @@ clm_status clm_plan_desc_default(clm_plan_desc* d, int32_t nside_fine) {
   const int64_t c = int64_t(4) * nside_fine / d->nside_bundle;
   d->patch_cells = int32_t(c > 256 ? c : 256);
   d->mg_vcycles = 4;
+  d->mg_max_vcycles = 20;
+  d->mg_eps = 0.1;
   d->nu_pre = 2;
   d->nu_post = 2;
   d->solver = CLM_SOLVER_SHT_MG;
@@ -357,8 +360,10 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
   if (d.solver == CLM_SOLVER_SHT_MG) {
     if (!pow2(d.nside_bundle) || d.nside_bundle > d.nside_fine || d.patch_factor < 1 ||
         !pow2(d.patch_cells) || d.patch_cells < 8 || d.patch_cells > 4096 ||
-        d.mg_vcycles < 1 || d.nu_pre < 1 || d.nu_pre > 4 || d.nu_post < 1 ||
-        d.nu_post > 4 || (d.mg_prec != CLM_FP32 && d.mg_prec != CLM_FP64))
+        d.mg_vcycles < 0 || (d.mg_vcycles == 0 && (d.mg_max_vcycles < 1 || !(d.mg_eps > 0))) ||
+        !(d.mg_eps >= 0) || d.nu_pre < 1 || d.nu_pre > 4 || d.nu_post < 1 ||
+        d.nu_post > 4 || (d.mg_prec != CLM_FP32 && d.mg_prec != CLM_FP64) ||
+        (d.adjoint && d.mg_vcycles == 0))
       return CLM_EINVAL;
     // the patch must stay far from the poles of its rotated frame
     const double side = std::sqrt(4.0 * 3.14159265358979323846 /
@@ -433,6 +438,11 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
       if ((s = alloc(p, &du, cells * esz)) != CLM_OK) return bail(s);
       sl.du = du;
     }
+  }
+  if (p->mg) {
+    if ((s = alloc(p, &p->mg_eps_dev, size_t(p->nbundle))) != CLM_OK) return bail(s);
+    if ((s = alloc(p, &p->mg_cycles_dev, size_t(p->nbundle))) != CLM_OK) return bail(s);
+    if ((s = alloc(p, &p->mg_done_dev, size_t(p->nbundle))) != CLM_OK) return bail(s);
   }
   if (p->mg) {
     const size_t cells = size_t(p->nbundle) * p->n * p->n;
@@ -545,6 +555,20 @@ clm_status clm_plan_sync_status(clm_plan plan, hipStream_t stream) {
   CLM_HIP(hipStreamSynchronize(stream));
   if (st & ST_LEFT_PATCH) return fail(p, CLM_ERAY_LEFT_PATCH, "a point left its bundle's patch");
   if (st & ST_NONFINITE) return fail(p, CLM_ENONFINITE, "non-finite value produced");
+  if (st & ST_NOTCONV)
+    return fail(p, CLM_ENOTCONV, "a patch did not meet mg_eps within mg_max_vcycles");
+  return CLM_OK;
+}
+
+clm_status clm_get_mg_convergence(clm_plan plan, double* eps_dev, int32_t* cycles_dev,
+                                  hipStream_t stream) {
+  if (!plan || !eps_dev || !cycles_dev) return CLM_EINVAL;
+  Plan* p = plan;
+  if (!p->mg) return fail(p, CLM_EUNSUPPORTED, "no multigrid in an SHT-only plan");
+  CLM_HIP(hipMemcpyAsync(eps_dev, p->mg_eps_dev, size_t(p->nbundle) * 8,
+                         hipMemcpyDeviceToDevice, stream));
+  CLM_HIP(hipMemcpyAsync(cycles_dev, p->mg_cycles_dev, size_t(p->nbundle) * 4,
+                         hipMemcpyDeviceToDevice, stream));
   return CLM_OK;
 }
 

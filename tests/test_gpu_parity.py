@@ -184,6 +184,67 @@ def test_mg_patch_potential_parity(clm, mg_case, n, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("n,prec,eps", [(64, "fp64", 1e-3), (256, "fp64", 5e-4),
+                                         (64, "fp32", 1e-2), (256, "fp32", 1e-2)])
+def test_mg_eps_rule_parity(clm, mg_case, n, prec, eps):
+    """The Sec. 3.2 stopping rule per patch: the number of V-cycles each
+    patch runs and its final epsilon match the oracle's mg_solve_eps (the
+    thresholds sit between the oracle's per-cycle values, at least a factor
+    1.3 from each), and the correction matches the oracle's after that many
+    cycles."""
+    c = mg_case
+    spec, sol = c[n]
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=n, mg_vcycles=0, mg_eps=eps, mg_max_vcycles=20,
+                    mg_prec=prec)
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    plan.sync_status()
+    e_gpu, k_gpu = (t.cpu().numpy() for t in plan.mg_convergence())
+    assert np.all((k_gpu >= 1) & (k_gpu <= 20)) and np.all(e_gpu < eps)
+    tol_e = 1e-9 if prec == "fp64" else 2e-2
+    for b in MG_BUNDLES:
+        pt = sol["patches"][b]
+        du, k, hist = omg.mg_solve_eps(spec, pt["fp"], eps, 20)
+        assert all(h > 1.3 * eps or h < eps / 1.3 for h in hist), hist
+        report("mg_eps n=%d %s b=%d cycles %d/%d eps" % (n, prec, b, k_gpu[b], k),
+               abs(e_gpu[b] - hist[-1]) / hist[-1])
+        assert k_gpu[b] == k, (b, k_gpu[b], k)
+        assert abs(e_gpu[b] - hist[-1]) <= tol_e * hist[-1], (b, e_gpu[b], hist[-1])
+        got = plan.patch_potential(b, 1)[0].cpu().numpy() - pt["u0"][1:-1, 1:-1]
+        assert report("mg_eps_du n=%d %s b=%d" % (n, prec, b), rel(got, du[1:-1, 1:-1])) < \
+            (1e-8 if prec == "fp64" else 2e-4), b
+    plan.close()
+
+
+def test_mg_eps_rule_not_converged_and_fixed_count(clm, mg_case):
+    """A patch still above mg_eps after mg_max_vcycles latches ENOTCONV,
+    with the epsilon of its last cycle reported; a fixed cycle count reports
+    that count and leaves epsilon unmeasured (NaN)."""
+    c = mg_case
+    spec, sol = c[256]
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=256, mg_vcycles=0, mg_eps=1e-6, mg_max_vcycles=2,
+                    mg_prec="fp64")
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    with pytest.raises(clm.ClmError) as ei:
+        plan.sync_status()
+    assert ei.value.status == clm.CLM_ENOTCONV
+    e_gpu, k_gpu = (t.cpu().numpy() for t in plan.mg_convergence())
+    assert np.all(k_gpu == 2)
+    for b in MG_BUNDLES:
+        _, _, hist = omg.mg_solve_eps(spec, sol["patches"][b]["fp"], 1e-6, 2)
+        assert abs(e_gpu[b] - hist[-1]) <= 1e-9 * hist[-1], (b, e_gpu[b], hist)
+    plan.sync_status()  # the latched condition was cleared
+    plan.close()
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=256, mg_vcycles=3)
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    plan.sync_status()
+    e_gpu, k_gpu = (t.cpu().numpy() for t in plan.mg_convergence())
+    assert np.all(k_gpu == 3) and np.all(np.isnan(e_gpu))
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_mg_shear_parity(clm, mg_case, prec):
     c = mg_case

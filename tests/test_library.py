@@ -37,17 +37,24 @@ def test_default_description(L):
     assert L.clm_plan_desc_default(ctypes.byref(d), 2048) == clm.CLM_OK
     assert (d.nside_sht, d.lmax, d.nside_bundle, d.patch_cells) == (256, 512, 32, 256)
     assert (d.mg_vcycles, d.nu_pre, d.nu_post, d.patch_factor) == (4, 2, 2, 4)
+    assert (d.mg_max_vcycles, d.mg_eps, d.adjoint) == (20, 0.1, 0)
+    assert ctypes.sizeof(d) == 72  # 14 int32, padding, a double, an int32
 
 
-@pytest.mark.parametrize("field,value", [
-    ("nside_fine", 100), ("nside_sht", 4096), ("patch_cells", 96), ("nu_pre", 0),
-    ("mg_vcycles", 0), ("max_planes", 0), ("solver", 7), ("mg_prec", 9),
-    ("nside_bundle", 1), ("legendre_prec", 3), ("legendre_prec", -1)])
-def test_invalid_descriptions_rejected(L, field, value):
+@pytest.mark.parametrize("fields", [
+    dict(nside_fine=100), dict(nside_sht=4096), dict(patch_cells=96), dict(nu_pre=0),
+    dict(mg_vcycles=-1), dict(max_planes=0), dict(solver=7), dict(mg_prec=9),
+    dict(nside_bundle=1), dict(legendre_prec=3), dict(legendre_prec=-1),
+    # the epsilon rule needs a positive threshold and cycle limit, and the
+    # adjoint a fixed cycle count
+    dict(mg_vcycles=0, mg_eps=0.0), dict(mg_vcycles=0, mg_max_vcycles=0),
+    dict(mg_eps=-1.0), dict(mg_eps=float("nan")), dict(mg_vcycles=0, adjoint=1)])
+def test_invalid_descriptions_rejected(L, fields):
     from paper_1210_3069_amd import clm
     d = clm.PlanDesc()
     L.clm_plan_desc_default(ctypes.byref(d), 2048)
-    setattr(d, field, value)
+    for field, value in fields.items():
+        setattr(d, field, value)
     h = ctypes.c_void_p()
     assert L.clm_plan_create(ctypes.byref(d), 0, ctypes.byref(h)) == clm.CLM_EINVAL
     assert not h.value
