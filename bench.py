@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 NF, NS, LMAX, NB, NCELL, VCYC = 2048, 256, 512, 32, 256, 4
+EPS_RULE = 0.1  # the typical convergence parameter of Sec. 3.2
 DCHI = 3054.70 / 20.0
 NGAL = 1_000_000
 HBM_PEAK_GBS = 8000.0
@@ -208,9 +209,9 @@ def make_inputs(clm, torch, inputs, cosmo):
     return kappa, gal
 
 
-def run_form(clm, torch, kappa, gal, prec, steps, warmup):
+def run_form(clm, torch, kappa, gal, prec, steps, warmup, vcycles=VCYC, eps=0.1):
     plan = clm.Plan(NF, nside_sht=NS, lmax=LMAX, nside_bundle=NB, patch_cells=NCELL,
-                    mg_vcycles=VCYC, mg_prec=prec)
+                    mg_vcycles=vcycles, mg_eps=eps, mg_max_vcycles=20, mg_prec=prec)
     rays = plan.new_rays()
     nplanes = warmup + steps
     chi = (np.arange(nplanes + 1) + 0.5) * DCHI
@@ -457,6 +458,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2)
+    ap.add_argument("--no-eps", action="store_true",
+                    help="skip the run under the epsilon stopping rule")
     ap.add_argument("--no-c4", action="store_true",
                     help="skip the batched-precision workload (32 uneven pure-SHT planes)")
     ap.add_argument("--no-c5", action="store_true",
@@ -564,6 +567,24 @@ def main():
             out["cpu_baseline"] = cpu_baseline(torch, kappa, plan64,
                                                sample[: max(1, args.cpu_sample)])
         plan64.close()
+    if not args.no_eps:
+        # the stopping rule of Sec. 3.2 in place of the fixed cycle count
+        print("bench: epsilon rule", file=sys.stderr, flush=True)
+        pe, re_, mse, _, st_e = run_form(clm, torch, kappa, gal, "fp32", args.steps,
+                                         args.warmup, vcycles=0, eps=EPS_RULE)
+        e, k = (t.cpu().numpy() for t in pe.mg_convergence())
+        ue = torch.stack([pe.patch_potential(b, 1)[0] for b in sample]).cpu()
+        d = (ue - u32).double()
+        out["eps_rule"] = dict(
+            mg_eps=EPS_RULE, ms_per_step=mse, value=1000.0 / mse,
+            vcycles_histogram={int(c): int((k == c).sum()) for c in np.unique(k)},
+            eps_max=float(e.max()), eps_median=float(np.median(e)),
+            mg_eps_ms_per_step=st_e.get("mg_eps", (0.0, 0))[0] / args.steps,
+            rel_l2_u_vs_fixed=float(d.norm() / u32.double().norm()),
+            note="convergence figures are the last plane's")
+        pe.close()
+        del pe, re_
+        torch.cuda.empty_cache()
     if not args.no_c4:
         print("bench: batched precision forms", file=sys.stderr, flush=True)
         out["c4_precision_forms"] = c4_run(clm, torch, inputs)

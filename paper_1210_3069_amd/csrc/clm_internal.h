@@ -16,6 +16,9 @@ namespace clm {
 // Device-side latched conditions (bit flags in plan->status_dev).
 enum : int { ST_LEFT_PATCH = 1, ST_NONFINITE = 2, ST_NOTCONV = 4 };
 
+// Epsilon rule: coarse cells per side of one partial-sum tile.
+constexpr int kEpsTile = 16;
+
 // Largest multigrid level handled entirely inside one workgroup's LDS.
 constexpr int kLdsLevelMax = 64;
 // Interior side of the multigrid tiles streamed through LDS on larger levels.
@@ -83,6 +86,9 @@ struct Plan {
   double* mg_eps_dev = nullptr;   // [nbundle] epsilon ratio of the latest solve
   int* mg_cycles_dev = nullptr;   // [nbundle] V-cycles run
   int* mg_done_dev = nullptr;     // [nbundle] epsilon rule met
+  double* mg_eps_part = nullptr;  // epsilon rule: [nbundle][tiles][4] partial sums
+  int* mg_active_dev = nullptr;   // epsilon rule: patches still above mg_eps
+  int* mg_active_host = nullptr;  // pinned copy of mg_active_dev
   // adjoint workspace (desc.adjoint): u0 + du bar per patch with ghosts, and
   // per level the transposed V-cycle's u bar (two), f bar and a temporary
   double* adj_ubar = nullptr;

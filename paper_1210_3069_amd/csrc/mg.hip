@@ -19,6 +19,7 @@
 // read and one write of the level (temporal blocking; the halo makes the
 // tile interior identical to the global sweep).  Levels <= kLdsLevelMax of
 // a patch are solved by one workgroup entirely in LDS.
+#include <algorithm>
 #include <cmath>
 
 #include "clm_internal.h"
@@ -943,92 +944,180 @@ __global__ __launch_bounds__(kBlock) void k_mg_lds(LdsArgs<T> a) {
 // ------------------------------------------------------------ epsilon rule
 // epsilon = ||r_h|| / ||tau|| per patch (Sec. 3.2 stopping rule):
 // r_h = f' - L_h du on the finest level, tau = L_H(R du) - R(L_h du) on the
-// first coarse level, area-weighted RMS, accumulated in FP64; one block per
-// patch, one coarse cell (and its four children) per step.
+// first coarse level, area-weighted RMS, accumulated in FP64.  One block per
+// tile of kEpsTC^2 coarse cells stages the fine correction (with its ghost
+// ring) and the restricted field in LDS and writes four partial sums; a
+// second kernel adds a patch's partials in a fixed order and applies the
+// threshold.
+constexpr int kEpsTC = kEpsTile;
+
 template <typename T>
 struct EpsArgs {
-  int n;
-  const double* c0;     // finest-level rows
+  int n;                // finest cells per side
+  int tc;               // coarse cells per tile side, min(kEpsTC, n / 2): 4, 8, 16
+  int ntile;            // tiles per side
+  const double* c0;     // finest-level rows (s_m, s_p, s_c, area)
   const double* c1;     // first coarse level rows
   const T* du;
   const T* fp;
+  const int* done;      // patches that already stopped
+  double* part;         // [patch][tile][4]: sum A r^2, sum A, sum A_H tau^2, sum A_H
+};
+
+template <typename T, int TC>
+__global__ __launch_bounds__(kBlock) void k_mg_eps(EpsArgs<T> a) {
+  constexpr int FS = 2 * TC + 4, CS = TC + 2, NW = kBlock / 64;
+  static_assert(TC * TC <= kBlock && FS <= 64, "one coarse cell per thread");
+  __shared__ double F[FS * FS];
+  __shared__ double U[CS * CS];
+  // rows: fine (s_m, s_p, 1/s_c, 1/A, A) for rows 2 I0 .. 2 (I0 + TC) - 1;
+  // coarse (s_m, s_p, 1/s_c, 1/A, A) for rows I0 .. I0 + TC - 1; restriction
+  // weights (w0, w1) for coarse rows I0 - 1 .. I0 + TC
+  __shared__ double RF[5][2 * TC], RC[5][TC], RW[2][CS];
+  __shared__ double red[4][NW];
+  const int tiles = a.ntile * a.ntile;
+  const int64_t patch = blockIdx.x / tiles;
+  const int tile = blockIdx.x % tiles;
+  if (a.done[patch]) return;
+  const int n = a.n, nc = n / 2;
+  const int I0 = (tile / a.ntile) * TC, J0 = (tile % a.ntile) * TC;
+  const T* x = a.du + size_t(patch) * n * n;
+  const T* f = a.fp + size_t(patch) * n * n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool cell = int(threadIdx.x) < TC * TC;
+  const int li = threadIdx.x / TC, lj = threadIdx.x % TC, I = I0 + li, J = J0 + lj;
+  // this thread's four f' values, requested before anything waits
+  double fq[4] = {0.0, 0.0, 0.0, 0.0};
+  if (cell)
+    for (int q = 0; q < 4; ++q)
+      fq[q] = double(f[size_t(2 * I + (q >> 1)) * n + 2 * J + (q & 1)]);
+  // fine rows / columns 2 I0 - 2 .. 2 (I0 + TC) + 1, one row per wave; the
+  // face ghost is -du of the cell it faces; cells two beyond the face are
+  // never used
+  constexpr int ROWS = (FS + NW - 1) / NW;
+  double fv[ROWS];
+#pragma unroll
+  for (int k = 0; k < ROWS; ++k) {
+    const int r = wv + k * NW;
+    const int i = 2 * I0 - 2 + r, j = 2 * J0 - 2 + lane;
+    double v = 0.0;
+    if (r < FS && lane < FS && i >= -1 && i <= n && j >= -1 && j <= n) {
+      const int ii = min(max(i, 0), n - 1), jj = min(max(j, 0), n - 1);
+      const bool gi = ii != i, gj = jj != j;
+      if (!(gi && gj)) {
+        v = double(x[size_t(ii) * n + jj]);
+        if (gi || gj) v = -v;
+      }
+    }
+    fv[k] = v;
+  }
+  if (threadIdx.x < 2 * TC) {
+    const double* c = a.c0 + 4 * (2 * I0 + threadIdx.x);
+    RF[0][threadIdx.x] = c[0];
+    RF[1][threadIdx.x] = c[1];
+    RF[2][threadIdx.x] = 1.0 / c[2];
+    RF[3][threadIdx.x] = 1.0 / c[3];
+    RF[4][threadIdx.x] = c[3];
+  } else if (threadIdx.x >= 64 && threadIdx.x < 64 + TC) {
+    const int t = threadIdx.x - 64;
+    const double* c = a.c1 + 4 * (I0 + t);
+    RC[0][t] = c[0];
+    RC[1][t] = c[1];
+    RC[2][t] = 1.0 / c[2];
+    RC[3][t] = 1.0 / c[3];
+    RC[4][t] = c[3];
+  } else if (threadIdx.x >= 128 && threadIdx.x < 128 + CS) {
+    const int t = threadIdx.x - 128, Ic = min(max(I0 - 1 + t, 0), nc - 1);
+    const double a0 = a.c0[4 * (2 * Ic) + 3], a1 = a.c0[4 * (2 * Ic + 1) + 3];
+    const double h = 1.0 / (2.0 * (a0 + a1));
+    RW[0][t] = a0 * h;
+    RW[1][t] = a1 * h;
+  }
+#pragma unroll
+  for (int k = 0; k < ROWS; ++k) {
+    const int r = wv + k * NW;
+    if (r < FS && lane < FS) F[r * FS + lane] = fv[k];
+  }
+  __syncthreads();
+  // area-weighted restriction R du on coarse rows I0 - 1 .. I0 + TC
+  for (int k = threadIdx.x; k < CS * CS; k += kBlock) {
+    const int r = k / CS, c = k % CS, Ic = I0 - 1 + r, Jc = J0 - 1 + c;
+    double v = 0.0;
+    if (Ic >= 0 && Ic < nc && Jc >= 0 && Jc < nc) {
+      const double* q = F + (2 * r) * FS + 2 * c;
+      v = RW[0][r] * (q[0] + q[1]) + RW[1][r] * (q[FS] + q[FS + 1]);
+    }
+    U[k] = v;
+  }
+  __syncthreads();
+  double sr = 0.0, sa = 0.0, st = 0.0, sb = 0.0;
+  if (cell) {
+    const double* uc = U + (li + 1) * CS + lj + 1;
+    const double u = uc[0];
+    // coarse ghosts: the negative of the interior cell (zero face value)
+    const double up = I > 0 ? uc[-CS] : -u, dn = I < nc - 1 ? uc[CS] : -u;
+    const double lf = J > 0 ? uc[-1] : -u, rt = J < nc - 1 ? uc[1] : -u;
+    const double LH =
+        (RC[0][li] * (up - u) + RC[1][li] * (dn - u) + (lf - 2.0 * u + rt) * RC[2][li]) *
+        RC[3][li];
+    double lh[4];
+    for (int q = 0; q < 4; ++q) {
+      const int fr = 2 * li + (q >> 1);
+      const double* v = F + (fr + 2) * FS + 2 * lj + 2 + (q & 1);
+      const double w = v[0];
+      lh[q] = (RF[0][fr] * (v[-FS] - w) + RF[1][fr] * (v[FS] - w) +
+               (v[-1] - 2.0 * w + v[1]) * RF[2][fr]) * RF[3][fr];
+      const double rr = fq[q] - lh[q];
+      sr += RF[4][fr] * rr * rr;
+      sa += RF[4][fr];
+    }
+    const double tau = LH - (RW[0][li + 1] * (lh[0] + lh[1]) + RW[1][li + 1] * (lh[2] + lh[3]));
+    st += RC[4][li] * tau * tau;
+    sb += RC[4][li];
+  }
+  double v4[4] = {sr, sa, st, sb};
+  for (int m = 0; m < 4; ++m) {
+    double v = v4[m];
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[m][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double v = 0.0;
+    for (int w = 0; w < NW; ++w) v += red[threadIdx.x][w];
+    a.part[(size_t(patch) * tiles + tile) * 4 + threadIdx.x] = v;
+  }
+}
+
+struct EpsFinal {
+  int tiles;
   double eps;
   int cycle;            // V-cycles run so far
-  int measure_only;     // 1: write epsilon only (fixed cycle count)
+  const double* part;
   int* done;
   int* cycles;
   double* eps_out;
+  int* active;          // patches still above the threshold (added to)
 };
 
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < int(blockDim.x >> 6); ++w) s += red[w];
-  return s;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_eps(EpsArgs<T> a) {
-  __shared__ double red[kBlock / 64];
+// one wave per patch: partial sums added in a fixed order
+__global__ __launch_bounds__(64) void k_mg_eps_final(EpsFinal a) {
   const int64_t patch = blockIdx.x;
-  if (!a.measure_only && a.done[patch]) return;
-  const int n = a.n, nc = n / 2;
-  const T* x = a.du + size_t(patch) * n * n;
-  const T* f = a.fp + size_t(patch) * n * n;
-  auto X = [&](int i, int j) -> double {  // zero face value: ghost = -interior
-    const int ii = min(max(i, 0), n - 1), jj = min(max(j, 0), n - 1);
-    const double v = double(x[ii * n + jj]);
-    return (ii != i || jj != j) ? -v : v;
-  };
-  auto Lh = [&](int i, int j) {
-    const double* c = a.c0 + 4 * i;
-    const double u = X(i, j);
-    return (c[0] * (X(i - 1, j) - u) + c[1] * (X(i + 1, j) - u) +
-            (X(i, j - 1) - 2.0 * u + X(i, j + 1)) / c[2]) / c[3];
-  };
-  auto Rst = [&](int I, int J, auto&& g) {
-    const double a0 = a.c0[4 * (2 * I) + 3], a1 = a.c0[4 * (2 * I + 1) + 3];
-    return (a0 * (g(2 * I, 2 * J) + g(2 * I, 2 * J + 1)) +
-            a1 * (g(2 * I + 1, 2 * J) + g(2 * I + 1, 2 * J + 1))) / (2.0 * (a0 + a1));
-  };
-  double sr = 0, sa = 0, st = 0, sb = 0;
-  for (int k = threadIdx.x; k < nc * nc; k += blockDim.x) {
-    const int I = k / nc, J = k % nc;
-    auto ub = [&](int P, int Q) { return Rst(P, Q, X); };
-    const double u = ub(I, J);
-    const double up = I > 0 ? ub(I - 1, J) : -u, dn = I < nc - 1 ? ub(I + 1, J) : -u;
-    const double lf = J > 0 ? ub(I, J - 1) : -u, rt = J < nc - 1 ? ub(I, J + 1) : -u;
-    const double* cH = a.c1 + 4 * I;
-    const double LH = (cH[0] * (up - u) + cH[1] * (dn - u) + (lf - 2.0 * u + rt) / cH[2]) / cH[3];
-    double lh[4];
-    for (int q = 0; q < 4; ++q) lh[q] = Lh(2 * I + (q >> 1), 2 * J + (q & 1));
-    const double a0 = a.c0[4 * (2 * I) + 3], a1 = a.c0[4 * (2 * I + 1) + 3];
-    const double RL = (a0 * (lh[0] + lh[1]) + a1 * (lh[2] + lh[3])) / (2.0 * (a0 + a1));
-    const double tau = LH - RL;
-    st += cH[3] * tau * tau;
-    sb += cH[3];
-    for (int q = 0; q < 4; ++q) {
-      const int i = 2 * I + (q >> 1), j = 2 * J + (q & 1);
-      const double r = double(f[i * n + j]) - lh[q];
-      const double A = a.c0[4 * i + 3];
-      sr += A * r * r;
-      sa += A;
-    }
-  }
-  sr = block_sum(sr, red);
-  sa = block_sum(sa, red);
-  st = block_sum(st, red);
-  sb = block_sum(sb, red);
+  if (a.done[patch]) return;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int t = threadIdx.x; t < a.tiles; t += 64)
+    for (int m = 0; m < 4; ++m) v[m] += a.part[(size_t(patch) * a.tiles + t) * 4 + m];
+  for (int m = 0; m < 4; ++m)
+    for (int o = 32; o >= 1; o >>= 1) v[m] += __shfl_xor(v[m], o);
   if (threadIdx.x != 0) return;
-  const double nr = sqrt(sr / sa), nt = sqrt(st / sb);
+  const double nr = sqrt(v[0] / v[1]), nt = sqrt(v[2] / v[3]);
   const double e = nt > 0.0 ? nr / nt : (nr > 0.0 ? INFINITY : 0.0);
   a.eps_out[patch] = e;
-  if (a.measure_only) return;
   a.cycles[patch] = a.cycle;
-  if (e < a.eps) a.done[patch] = 1;
+  if (e < a.eps)
+    a.done[patch] = 1;
+  else
+    atomicAdd(a.active, 1);
 }
 
 __global__ void k_fill_int(int64_t n, int v, int* y) {
@@ -1182,25 +1271,56 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     CLM_LAUNCH_CHECK();
   }
   la.done = done;
+  const int eps_tc = std::min(kEpsTC, n / 2), eps_nt = (n / 2) / eps_tc;
+  auto eps_eval = [&](int cycle) -> clm_status {
+    EpsArgs<T> e{};
+    e.n = n;
+    e.tc = eps_tc;
+    e.ntile = eps_nt;
+    e.c0 = p->coef + p->lev[0].crow;
+    e.c1 = p->coef + p->lev[1].crow;
+    e.du = du;
+    e.fp = fp;
+    e.done = p->mg_done_dev;
+    e.part = p->mg_eps_part;
+    EpsFinal g{};
+    g.tiles = eps_nt * eps_nt;
+    g.eps = d.mg_eps;
+    g.cycle = cycle;
+    g.part = p->mg_eps_part;
+    g.done = p->mg_done_dev;
+    g.cycles = p->mg_cycles_dev;
+    g.eps_out = p->mg_eps_dev;
+    g.active = p->mg_active_dev;
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, int64_t(1), 0, p->mg_active_dev);
+    {
+      CLM_TIMED(p, s, "mg_eps");
+      const dim3 ge(unsigned(np * g.tiles));
+      if (eps_tc == 16)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_eps<T, 16>), ge, dim3(kBlock), 0, s, e);
+      else if (eps_tc == 8)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_eps<T, 8>), ge, dim3(kBlock), 0, s, e);
+      else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_eps<T, 4>), ge, dim3(kBlock), 0, s, e);
+      hipLaunchKernelGGL(k_mg_eps_final, dim3(unsigned(np)), dim3(64), 0, s, g);
+    }
+    CLM_LAUNCH_CHECK();
+    return CLM_OK;
+  };
+  bool all_done = false;
   for (int cyc = 0; cyc < ncyc; ++cyc) {
     const bool first = cyc == 0;
     if (eps_mode && !first) {
-      EpsArgs<T> e{};
-      e.n = n;
-      e.c0 = p->coef + p->lev[0].crow;
-      e.c1 = p->coef + p->lev[1].crow;
-      e.du = du;
-      e.fp = fp;
-      e.eps = d.mg_eps;
-      e.cycle = cyc;
-      e.done = p->mg_done_dev;
-      e.cycles = p->mg_cycles_dev;
-      e.eps_out = p->mg_eps_dev;
-      {
-        CLM_TIMED(p, s, "mg_eps");
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_eps<T>), dim3(unsigned(np)), dim3(kBlock), 0, s, e);
+      // epsilon after cyc cycles; stop once every patch is below mg_eps
+      const clm_status st = eps_eval(cyc);
+      if (st != CLM_OK) return st;
+      CLM_HIP(hipMemcpyAsync(p->mg_active_host, p->mg_active_dev, sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+      CLM_HIP(hipStreamSynchronize(s));
+      if (*p->mg_active_host == 0) {
+        all_done = true;
+        break;
       }
-      CLM_LAUNCH_CHECK();
     }
     if (K == 0) {
       la.u_in = first ? nullptr : du;
@@ -1270,22 +1390,9 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       }
     }
   }
-  if (eps_mode) {
-    EpsArgs<T> e{};
-    e.n = n;
-    e.c0 = p->coef + p->lev[0].crow;
-    e.c1 = p->coef + p->lev[1].crow;
-    e.du = du;
-    e.fp = fp;
-    e.eps = d.mg_eps;
-    e.cycle = ncyc;
-    e.done = p->mg_done_dev;
-    e.cycles = p->mg_cycles_dev;
-    e.eps_out = p->mg_eps_dev;
-    {
-      CLM_TIMED(p, s, "mg_eps");
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_eps<T>), dim3(unsigned(np)), dim3(kBlock), 0, s, e);
-    }
+  if (eps_mode && !all_done) {
+    const clm_status st = eps_eval(ncyc);
+    if (st != CLM_OK) return st;
     hipLaunchKernelGGL(k_notconv, gfill, dim3(kBlock), 0, s, np,
                        static_cast<const int*>(p->mg_done_dev), p->status_dev);
     CLM_LAUNCH_CHECK();

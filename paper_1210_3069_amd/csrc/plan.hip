@@ -1,5 +1,6 @@
 // Plan creation, workspace, geometry tables and the small C-ABI entry points
 // (status, getters, dispatch to the stage launchers).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -42,7 +43,8 @@ Plan::~Plan() {
   for (auto* q : ulev2) f(q);
   for (auto& s : slots) { f(s.alm); f(s.psi_s); f(s.u0); f(s.du); }
   f(adj_ubar); f(adj_psi); f(adj_ks); f(adj_alm);
-  f(mg_eps_dev); f(mg_cycles_dev); f(mg_done_dev);
+  f(mg_eps_dev); f(mg_cycles_dev); f(mg_done_dev); f(mg_eps_part); f(mg_active_dev);
+  if (mg_active_host) (void)hipHostFree(mg_active_host);
   for (auto* q : adj_u) f(q);
   for (auto* q : adj_v) f(q);
   for (auto* q : adj_f) f(q);
@@ -443,6 +445,17 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
     if ((s = alloc(p, &p->mg_eps_dev, size_t(p->nbundle))) != CLM_OK) return bail(s);
     if ((s = alloc(p, &p->mg_cycles_dev, size_t(p->nbundle))) != CLM_OK) return bail(s);
     if ((s = alloc(p, &p->mg_done_dev, size_t(p->nbundle))) != CLM_OK) return bail(s);
+    if (d.mg_vcycles == 0) {
+      // epsilon rule: per-tile partial sums
+      const size_t nc = size_t(p->n / 2), tc = std::min<size_t>(kEpsTile, nc);
+      const size_t tiles = (nc / tc) * (nc / tc);
+      if ((s = alloc(p, &p->mg_eps_part, size_t(p->nbundle) * tiles * 4)) != CLM_OK)
+        return bail(s);
+      if ((s = alloc(p, &p->mg_active_dev, 1)) != CLM_OK) return bail(s);
+      if (hipHostMalloc(reinterpret_cast<void**>(&p->mg_active_host), sizeof(int)) !=
+          hipSuccess)
+        return bail(CLM_EHIP);
+    }
   }
   if (p->mg) {
     const size_t cells = size_t(p->nbundle) * p->n * p->n;
