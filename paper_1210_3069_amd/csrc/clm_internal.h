@@ -57,6 +57,9 @@ struct Plan {
   double* ring_f = nullptr;     // same for the fine grid
   int* ringi_f = nullptr;
   double* ringx_f = nullptr;
+  int64_t* blu_off = nullptr;   // [nring_s] chirp-filter table offset (doubles), -1: direct
+  double* blu = nullptr;        // chirp-filter transforms of the Bluestein rings
+  size_t ring_lds = 0;          // dynamic LDS of the ring kernels
   double* lam_mant = nullptr;   // [lmax+1][H] lambda_mm mantissa
   int* lam_scale = nullptr;     // [lmax+1][H] scale exponent (units of 2^800)
   int* r2n_s = nullptr;         // RING -> NESTED at nside_sht
@@ -162,6 +165,7 @@ clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot,
                      hipStream_t s);                    // sht.hip
 clm_status plane_mean(Plan* p, const void* kappa, int kappa_fp64,
                       hipStream_t s);                   // sht.hip: red[1023] = mean
+clm_status ring_plan(Plan* p);                          // sht.hip
 clm_status sht_solve_batch(Plan* p, const void* kappa, int kappa_fp64, int first_slot,
                            int nplanes, hipStream_t s);  // sht.hip
 clm_status sht_adjoint(Plan* p, const double* psibar, double* alm, double* ksbar,

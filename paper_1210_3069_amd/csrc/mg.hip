@@ -78,6 +78,7 @@ __device__ __forceinline__ void patch_dir(const double* R, double st, double ct,
 // tables).
 constexpr int kRingCapF = 256, kRingCapS = 64;
 constexpr int kSetupBlock = 512;
+constexpr int kLdsBlock = 1024;
 
 template <int CAP>
 struct RingStore {
@@ -103,8 +104,8 @@ struct PhiRef {
 // the SHT ring index follows from the fine one: floor((g_f + 1) / ratio) - 1.
 template <typename T, int TILE, typename TS, typename TF>
 __device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, double* shu,
-                             T* fsh, const double* trig, const double* R, const PhiRef& pr,
-                             int64_t patch, int i0, int j0) {
+                             T* fsh, const double* trig, const double* prow, const double* R,
+                             const PhiRef& pr, int64_t patch, int i0, int j0) {
   constexpr int RR = TILE + 2;
   const int n = a.n;
   const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
@@ -188,9 +189,10 @@ __device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, dou
     if (own_i && own_j) u0[size_t(gi + 1) * G + (gj + 1)] = shu[idx];
     if (!(li >= 1 && li <= TILE && lj >= 1 && lj <= TILE)) continue;
     const double* c = a.coef + 4 * gi;
+    const double* q = prow + 2 * (li - 1);  // 1 / s_c, 1 / A of the row
     const double u = shu[idx];
     const double Lu = (c[0] * (shu[idx - RR] - u) + c[1] * (shu[idx + RR] - u) +
-                       (shu[idx - 1] - 2.0 * u + shu[idx + 1]) / c[2]) / c[3];
+                       (shu[idx - 1] - 2.0 * u + shu[idx + 1]) * q[0]) * q[1];
     T* fo = fp + size_t(gi) * n + gj;
     const double f = fsh ? double(fsh[(li - 1) * TILE + (lj - 1)]) : double(*fo);
     *fo = T(f - Lu);
@@ -207,6 +209,7 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
   constexpr int RR = TILE + 2;
   __shared__ double shu[RR * RR];
   __shared__ double trig[4 * RR];  // sin/cos th'_row, ph'_col
+  __shared__ double prow[2 * TILE];  // 1 / s_c, 1 / area of the tile's rows
   __shared__ RingStore<kRingCapF> ringf;
   __shared__ RingStore<kRingCapS> rings;
   __shared__ double zred[2 * (kSetupBlock / 64)];
@@ -225,6 +228,11 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
   for (int r = threadIdx.x; r < RR; r += blockDim.x) {
     sincos(th0 + (i0 + r + 0.5) * a.delta, &trig[4 * r], &trig[4 * r + 1]);
     sincos(ph0 + (j0 + r + 0.5) * a.delta, &trig[4 * r + 2], &trig[4 * r + 3]);
+  }
+  for (int r = threadIdx.x; r < TILE; r += blockDim.x) {
+    const double* c = a.coef + 4 * (i0 + 1 + r);
+    prow[2 * r] = 1.0 / c[2];
+    prow[2 * r + 1] = 1.0 / c[3];
   }
   __syncthreads();
   // z range of the region's cell centres; every point interpolated lies
@@ -286,10 +294,10 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
     ts.fill(a.rs, rng[0], rng[1], pr.phi);
     tf.fill(a.rf, rng[2], rng[3], pr.phi);
     __syncthreads();
-    setup_passes<T, TILE>(a, ts, tf, shu, fsh, trig, R, pr, patch, i0, j0);
+    setup_passes<T, TILE>(a, ts, tf, shu, fsh, trig, prow, R, pr, patch, i0, j0);
   } else {
     setup_passes<T, TILE>(a, hpx::GlobalRingTab{a.rs, pr.phi}, hpx::GlobalRingTab{a.rf, pr.phi},
-                          shu, fsh, trig, R, pr, patch, i0, j0);
+                          shu, fsh, trig, prow, R, pr, patch, i0, j0);
   }
 }
 
@@ -748,6 +756,7 @@ __device__ __forceinline__ T prolong_cell(int gi, int gj, int n, EF e) {
 
 // ------------------------------------------------------------ LDS levels
 // One workgroup per patch runs the V-cycle below level K entirely in LDS:
+// 1024 threads, so the 64^2 level's half-sweeps take two cells per thread
 // per level l: u, f (and ubar for l > K) as row-major n_l x n_l arrays, and
 // the level's row coefficients (s_m, s_p, 1/s_c, area, interior 1/diag).
 struct LdsLevels {
@@ -793,7 +802,7 @@ __device__ void lds_smooth(T* u, const T* f, int n, int lg, const LRows<T>& r, i
   const int half = n >> 1;
   for (int s = 0; s < sweeps; ++s) {
     for (int color = 0; color < 2; ++color) {
-      for (int idx = threadIdx.x; idx < n * half; idx += kBlock) {
+      for (int idx = threadIdx.x; idx < n * half; idx += kLdsBlock) {
         const int i = idx >> (lg - 1);
         const int j = 2 * (idx & (half - 1)) + ((color + i) & 1);
         const T sm = r.sm[i], sp = r.sp[i], isc = r.isc[i];
@@ -848,7 +857,7 @@ __device__ __forceinline__ LLevel<T> lds_level(unsigned char* smem, int K, int n
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mg_lds(LdsArgs<T> a) {
+__global__ __launch_bounds__(kLdsBlock) void k_mg_lds(LdsArgs<T> a) {
   extern __shared__ unsigned char smem[];
   const int64_t patch = xcd_block();
   if (a.done && a.done[patch]) return;
@@ -857,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_lds(LdsArgs<T> a) {
     const int nn = n0 >> (l - K);
     const LLevel<T> L = lds_level<T>(smem, K, n0, l);
     T* rows = const_cast<T*>(L.r.sm);
-    for (int i = threadIdx.x; i < nn; i += kBlock) {
+    for (int i = threadIdx.x; i < nn; i += kLdsBlock) {
       const double* c = a.coef + a.lv.crow[l] + 4 * i;
       rows[i] = T(c[0]);
       rows[nn + i] = T(c[1]);
@@ -871,14 +880,14 @@ __global__ __launch_bounds__(kBlock) void k_mg_lds(LdsArgs<T> a) {
   const size_t g0 = size_t(patch) * n0 * n0;
   {
     const LLevel<T> L = lds_level<T>(smem, K, n0, K);
-    for (int idx = threadIdx.x; idx < n0 * n0; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < n0 * n0; idx += kLdsBlock) {
       L.u[idx] = a.u_in ? a.u_in[g0 + idx] : T(0);
       L.f[idx] = a.f_in[g0 + idx];
     }
     __syncthreads();
     if (a.fas_source) {
       // f = L ubar + rbar (reads u only, writes f only)
-      for (int idx = threadIdx.x; idx < n0 * n0; idx += kBlock)
+      for (int idx = threadIdx.x; idx < n0 * n0; idx += kLdsBlock)
         L.f[idx] += lap_g(L.u, n0, idx >> lg0, idx & (n0 - 1), L.r);
       __syncthreads();
     }
@@ -890,7 +899,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_lds(LdsArgs<T> a) {
     const LLevel<T> L = lds_level<T>(smem, K, n0, l);
     const LLevel<T> C = lds_level<T>(smem, K, n0, l + 1);
     lds_smooth(L.u, L.f, nn, lg, L.r, a.nu1);
-    for (int idx = threadIdx.x; idx < nc * nc; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < nc * nc; idx += kLdsBlock) {
       const int I = idx >> (lg - 1), J = idx & (nc - 1);
       T r[4], uu[4];
 #pragma unroll
@@ -908,7 +917,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_lds(LdsArgs<T> a) {
     }
     __syncthreads();
     // f_H = L_H ubar + rbar
-    for (int idx = threadIdx.x; idx < nc * nc; idx += kBlock)
+    for (int idx = threadIdx.x; idx < nc * nc; idx += kLdsBlock)
       C.f[idx] += lap_g(C.u, nc, idx >> (lg - 1), idx & (nc - 1), C.r);
     __syncthreads();
   }
@@ -930,14 +939,14 @@ __global__ __launch_bounds__(kBlock) void k_mg_lds(LdsArgs<T> a) {
     const LLevel<T> L = lds_level<T>(smem, K, n0, l);
     const LLevel<T> C = lds_level<T>(smem, K, n0, l + 1);
     auto ef = [&](int I, int J) { return C.u[I * nc + J] - C.b[I * nc + J]; };
-    for (int idx = threadIdx.x; idx < nn * nn; idx += kBlock)
+    for (int idx = threadIdx.x; idx < nn * nn; idx += kLdsBlock)
       L.u[idx] += prolong_cell<T>(idx >> lg, idx & (nn - 1), nn, ef);
     __syncthreads();
     lds_smooth(L.u, L.f, nn, lg, L.r, a.nu2);
   }
   {
     const LLevel<T> L = lds_level<T>(smem, K, n0, K);
-    for (int idx = threadIdx.x; idx < n0 * n0; idx += kBlock) a.u_out[g0 + idx] = L.u[idx];
+    for (int idx = threadIdx.x; idx < n0 * n0; idx += kLdsBlock) a.u_out[g0 + idx] = L.u[idx];
   }
 }
 
@@ -1329,7 +1338,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       la.fas_source = 0;
       {
         CLM_TIMED(p, s, "mg_lds");
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(np), dim3(kBlock), lds_bytes, s,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(np), dim3(kLdsBlock), lds_bytes, s,
                            la);
       }
       CLM_LAUNCH_CHECK();
@@ -1365,7 +1374,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     la.fas_source = 1;
     {
       CLM_TIMED(p, s, "mg_lds");
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(np), dim3(kBlock), lds_bytes, s, la);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(np), dim3(kLdsBlock), lds_bytes, s, la);
     }
     CLM_LAUNCH_CHECK();
     // prolongation, correction and post-smoothing back up

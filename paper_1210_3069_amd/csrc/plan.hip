@@ -32,7 +32,7 @@ Plan::~Plan() {
   for (auto e : pool) (void)hipEventDestroy(e);
   auto f = [](void* q) { if (q) (void)hipFree(q); };
   f(ring_s); f(ringi_s); f(ringx_s); f(ring_f); f(ringi_f); f(ringx_f); f(lam_mant);
-  f(lam_scale);
+  f(lam_scale); f(blu_off); f(blu);
   f(r2n_s); f(r2n_f); f(rot); f(coef); f(cinv); f(kap_s); f(F); f(G); f(red);
   f(rcoef); f(Fb); f(Gb); f(apart); f(psib);
   f(deriv); f(fprime); f(dutmp); f(status_dev);
@@ -237,6 +237,8 @@ clm_status build_tables(Plan* p) {
   CLM_HIP(hipMemcpy(p->ring_f, rt.data(), rt.size() * 8, hipMemcpyHostToDevice));
   CLM_HIP(hipMemcpy(p->ringi_f, ri.data(), ri.size() * 4, hipMemcpyHostToDevice));
   CLM_HIP(hipMemcpy(p->ringx_f, rx.data(), rx.size() * 8, hipMemcpyHostToDevice));
+
+  CLM_TRY(ring_plan(p));
 
   // Legendre starting values on the north rings of the SHT grid
   CLM_TRY(alloc(p, &p->lam_mant, size_t(d.lmax + 1) * p->H));

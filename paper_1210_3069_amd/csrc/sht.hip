@@ -8,6 +8,7 @@
 // registers and mirror rings are folded in with the (-1)^(l+m) parity.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "clm_internal.h"
 #include "healpix_dev.h"
@@ -166,29 +167,193 @@ __device__ __forceinline__ void half_split(int n, int& h, int& lg, int& r) {
   r = h >> lg;
 }
 
+// Rings whose half length h = 2^lg r has an odd factor r above kDirectOdd
+// use Bluestein's chirp transform instead of the direct odd DFT (cost h r):
+// with w_k = e^{-i pi k^2 / h} and jk = (j^2 + k^2 - (k - j)^2) / 2,
+// X_k = w_k sum_j (z_j w_j) conj(w_{k-j}), a cyclic convolution of length
+// M = 2^lgM >= 2h - 1 done by two power-of-two FFTs and a product with the
+// transform of the chirp filter, tabulated per ring length at plan time.
+constexpr int kRingBlock = 1024;
+constexpr int kDirectOdd = 32;
+
+__host__ __device__ inline int lg_ceil(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// e^{sign 2 pi i t / M}, M = 4 * 2^lgQ, from the quarter-wave table of M.
+__device__ __forceinline__ void unit_p2(const double* sq, int lgQ, int t, int sign, double& c,
+                                        double& s) {
+  const int Q = 1 << lgQ, q = (t >> lgQ) & 3, r = t & (Q - 1);
+  const double sr = sq[r], cr = sq[Q - r];
+  switch (q) {
+    case 0: c = cr; s = sr; break;
+    case 1: c = -sr; s = cr; break;
+    case 2: c = -cr; s = -sr; break;
+    default: c = sr; s = -cr; break;
+  }
+  s *= sign;
+}
+
+// Radix-2 decimation in frequency, kernel e^{-2 pi i jk / M}: natural
+// order in, bit-reversed order out (in place, interleaved complex).
+__device__ void fft_dif(double* A, int lgM, const double* sq) {
+  const int M = 1 << lgM;
+  for (int ls = lgM - 1; ls >= 0; --ls) {
+    const int span = 1 << ls;
+    for (int item = threadIdx.x; item < M / 2; item += blockDim.x) {
+      const int kk = item & (span - 1), i0 = ((item >> ls) << (ls + 1)) + kk, i1 = i0 + span;
+      double c, s;
+      unit_p2(sq, lgM - 2, kk << (lgM - 1 - ls), -1, c, s);
+      const double ar = A[2 * i0], ai = A[2 * i0 + 1], br = A[2 * i1], bi = A[2 * i1 + 1];
+      A[2 * i0] = ar + br;
+      A[2 * i0 + 1] = ai + bi;
+      const double dr = ar - br, di = ai - bi;
+      A[2 * i1] = dr * c - di * s;
+      A[2 * i1 + 1] = dr * s + di * c;
+    }
+    __syncthreads();
+  }
+}
+
+// Radix-2 decimation in time, kernel e^{+2 pi i jk / M}: bit-reversed order
+// in, natural order out, unnormalised.
+__device__ void fft_dit_inv(double* A, int lgM, const double* sq) {
+  const int M = 1 << lgM;
+  for (int ls = 0; ls < lgM; ++ls) {
+    const int span = 1 << ls;
+    for (int item = threadIdx.x; item < M / 2; item += blockDim.x) {
+      const int kk = item & (span - 1), i0 = ((item >> ls) << (ls + 1)) + kk, i1 = i0 + span;
+      double c, s;
+      unit_p2(sq, lgM - 2, kk << (lgM - 1 - ls), +1, c, s);
+      const double xr = A[2 * i1], xi = A[2 * i1 + 1];
+      const double tr = c * xr - s * xi, ti = c * xi + s * xr;
+      const double er = A[2 * i0], ei = A[2 * i0 + 1];
+      A[2 * i0] = er + tr;
+      A[2 * i0 + 1] = ei + ti;
+      A[2 * i1] = er - tr;
+      A[2 * i1 + 1] = ei - ti;
+    }
+    __syncthreads();
+  }
+}
+
+// Chirp w_k = e^{-i pi k^2 / h} = c - i s, k^2 reduced modulo 2h exactly.
+__device__ __forceinline__ void chirp(int k, int h, double& c, double& s) {
+  const int64_t q = (int64_t(k) * k) % (2 * int64_t(h));
+  sincospi(double(q) / double(h), &s, &c);
+}
+
+// A holds a_k = z_k w_k (k < h) and zeros up to M: on return A_k holds M times
+// the cyclic convolution (a * b)_k, natural order; Bh = DFT_M(b) of the filter
+// b_k = conj w_k (b_{M-k} = b_k), bit-reversed order.
+__device__ void bluestein_core(double* A, int lgM, const double* sq, const double* Bh) {
+  fft_dif(A, lgM, sq);
+  for (int p = threadIdx.x; p < (1 << lgM); p += blockDim.x) {
+    const double ar = A[2 * p], ai = A[2 * p + 1], br = Bh[2 * p], bi = Bh[2 * p + 1];
+    A[2 * p] = ar * br - ai * bi;
+    A[2 * p + 1] = ar * bi + ai * br;
+  }
+  __syncthreads();
+  fft_dit_inv(A, lgM, sq);
+}
+
+// Transform of the chirp filter for ring length lens[b] (one block each),
+// written bit-reversed at blu + offs[b].
+__global__ __launch_bounds__(kRingBlock) void k_blu_table(const int* lens, const int64_t* offs,
+                                                          double* blu) {
+  extern __shared__ double sm[];
+  const int h = lens[blockIdx.x] / 2, lgM = lg_ceil(2 * h - 1), M = 1 << lgM;
+  double* A = sm;
+  double* sq = sm + 2 * M;
+  for (int k = threadIdx.x; k < M; k += blockDim.x) {
+    const int j = k < h ? k : (k > M - h ? M - k : -1);
+    double c = 0.0, s = 0.0;
+    if (j >= 0) chirp(j, h, c, s);
+    A[2 * k] = c;  // conj w_j = c + i s
+    A[2 * k + 1] = s;
+  }
+  quarter_table(sq, M);
+  __syncthreads();
+  fft_dif(A, lgM, sq);
+  double* out = blu + offs[blockIdx.x];
+  for (int k = threadIdx.x; k < 2 * M; k += blockDim.x) out[k] = A[k];
+}
+
+// e^{sign 2 pi i t / n} of a ring: from its quarter-wave table when it is
+// in LDS (direct path), else by sincospi.
+__device__ __forceinline__ void ring_unit(const double* sq, int n, int t, int sign, double& c,
+                                          double& s) {
+  if (sq) {
+    unit(sq, n / 4, t, sign, c, s);
+  } else {
+    sincospi(2.0 * double(t) / double(n), &s, &c);
+    s *= sign;
+  }
+}
+
 // F_m(q) = e^{-i m phi0_q} sum_j f_{q,j} e^{-2 pi i (m mod n) j / n}, m = 0..lmax
 // (HEALPix aliasing for rings shorter than lmax + 1).  The real ring is read
 // as h = n/2 complex samples z_j = f_2j + i f_2j+1, transformed with
 // dft_mixed, and split: X_k = E_k + e^{-2 pi i k/n} O_k with
 // E_k = (Z_k + conj Z_{h-k}) / 2, O_k = (Z_k - conj Z_{h-k}) / 2i, and
 // X_{n-k} = conj X_k.
-__global__ void k_ring_forward(const double* map, const double* rt, const int* ri, int lmax,
-                               double* F) {
+__global__ __launch_bounds__(kRingBlock) void k_ring_forward(const double* map, const double* rt,
+                                                             const int* ri, const int64_t* boff,
+                                                             const double* blu, int lmax,
+                                                             double* F) {
   extern __shared__ double sm[];
   const int q = blockIdx.x;
-  const int n = ri[2 * q], Q = n / 4;
+  const int n = ri[2 * q], h = n / 2;
   const int64_t first = ri[2 * q + 1];
   const double phi0 = rt[4 * q + 3];
   double* out = F + size_t(q) * (lmax + 1) * 2;
-  double* x = sm;              // [n] real samples = [h] complex z
-  double* Z = sm + n;          // [h] complex
-  double* sq = sm + 2 * n;     // [n/4 + 1]
-  for (int j = threadIdx.x; j < n; j += blockDim.x) x[j] = map[first + j];
-  quarter_table(sq, n);
-  __syncthreads();
-  int h, lg, r;
-  half_split(n, h, lg, r);
-  dft_mixed(x, Z, h, lg, r, sq, n, -1);
+  const int64_t bo = boff[q];
+  const double* Z;           // [h] complex half-length transform, natural order
+  const double* sq = nullptr;
+  if (bo < 0) {
+    double* x = sm;            // [n] real samples = [h] complex z
+    double* Zs = sm + n;       // [h] complex
+    double* sqn = sm + 2 * n;  // [n/4 + 1]
+    for (int j = threadIdx.x; j < n; j += blockDim.x) x[j] = map[first + j];
+    quarter_table(sqn, n);
+    __syncthreads();
+    int hh, lg, r;
+    half_split(n, hh, lg, r);
+    dft_mixed(x, Zs, hh, lg, r, sqn, n, -1);
+    Z = Zs;
+    sq = sqn;
+  } else {
+    const int lgM = lg_ceil(2 * h - 1), M = 1 << lgM;
+    double* A = sm;            // [M] complex
+    double* sqM = sm + 2 * M;  // [M/4 + 1]
+    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+      double ar = 0.0, ai = 0.0;
+      if (k < h) {
+        const double zr = map[first + 2 * k], zi = map[first + 2 * k + 1];
+        double c, s;
+        chirp(k, h, c, s);
+        ar = zr * c + zi * s;
+        ai = zi * c - zr * s;
+      }
+      A[2 * k] = ar;
+      A[2 * k + 1] = ai;
+    }
+    quarter_table(sqM, M);
+    __syncthreads();
+    bluestein_core(A, lgM, sqM, blu + bo);
+    const double inv = 1.0 / double(M);
+    for (int k = threadIdx.x; k < h; k += blockDim.x) {
+      double c, s;
+      chirp(k, h, c, s);
+      const double cr = A[2 * k] * inv, ci = A[2 * k + 1] * inv;
+      A[2 * k] = cr * c + ci * s;
+      A[2 * k + 1] = ci * c - cr * s;
+    }
+    __syncthreads();
+    Z = A;
+  }
   for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
     const int k = m % n;
     const bool up = k > n / 2;
@@ -200,7 +365,7 @@ __global__ void k_ring_forward(const double* map, const double* rt, const int* r
     const double dr = zr - wr, di = zi - wi;
     const double orr = 0.5 * di, oi = -0.5 * dr;       // (Z - conj) / 2i
     double c, s;
-    unit(sq, Q, kk % n, -1, c, s);
+    ring_unit(sq, n, kk % n, -1, c, s);
     double xr = er + c * orr - s * oi, xi = ei + c * oi + s * orr;
     if (up) xi = -xi;
     double sp, cp;
@@ -216,19 +381,28 @@ __global__ void k_ring_forward(const double* map, const double* rt, const int* r
 // transform of the Hermitian C_k = (B_k + conj B_{n-k}) / 2, done at half
 // length: Y_k = (C_k + C_{k+h}) + i e^{2 pi i k/n} (C_k - C_{k+h}), z the
 // inverse DFT of Y, f_2j = Re z_j, f_2j+1 = Im z_j.
-__global__ void k_ring_inverse(const double* G, int nring, const double* rt, const int* ri,
-                               int lmax, int64_t npix, int nf, double* out) {
+__global__ __launch_bounds__(kRingBlock) void k_ring_inverse(const double* G, int nring,
+                                                             const double* rt, const int* ri,
+                                                             const int64_t* boff,
+                                                             const double* blu, int lmax,
+                                                             int64_t npix, int nf, double* out) {
   extern __shared__ double sm[];
   const int q = blockIdx.x;
-  const int n = ri[2 * q], Q = n / 4;
+  const int n = ri[2 * q];
   const int64_t first = ri[2 * q + 1];
-  double* Y = sm;              // [h] complex
-  double* Z = sm + n;          // [h] complex
-  double* sq = sm + 2 * n;     // [n/4 + 1]
   const double phi0 = rt[4 * q + 3];
+  const int64_t bo = boff[q];
   int h, lg, r;
   half_split(n, h, lg, r);
-  quarter_table(sq, n);
+  const int lgM = bo < 0 ? 0 : lg_ceil(2 * h - 1), M = 1 << lgM;
+  // direct path: Y [h] complex, Z [h] complex, quarter table of n;
+  // Bluestein: A [M] complex, quarter table of M
+  double* sq = bo < 0 ? sm + 2 * n : nullptr;
+  double* sqM = sm + 2 * M;
+  if (bo < 0)
+    quarter_table(sq, n);
+  else
+    quarter_table(sqM, M);
   for (int fld = 0; fld < nf; ++fld) {
     const double* g = G + (size_t(fld) * nring + q) * (lmax + 1) * 2;
     __syncthreads();
@@ -251,22 +425,53 @@ __global__ void k_ring_inverse(const double* G, int nring, const double* rt, con
       cr = 0.5 * (ar + br);
       ci = 0.5 * (ai - bi);
     };
-    for (int k = threadIdx.x; k < h; k += blockDim.x) {
+    // Y_k = (C_k + C_{k+h}) + i e^{2 pi i k/n} (C_k - C_{k+h})
+    auto yk = [&](int k, double& yr, double& yi) {
       double c1r, c1i, c2r, c2i;
       ck(k, c1r, c1i);
       ck(k + h, c2r, c2i);
       double c, s;
-      unit(sq, Q, k, +1, c, s);
+      ring_unit(sq, n, k, +1, c, s);
       const double dr = c1r - c2r, di = c1i - c2i;
-      const double tr = c * dr - s * di, ti = c * di + s * dr;  // e^{i..} (C_k - C_k+h)
-      Y[2 * k] = (c1r + c2r) - ti;                              // + i (tr + i ti)
-      Y[2 * k + 1] = (c1i + c2i) + tr;
-    }
-    __syncthreads();
-    dft_mixed(Y, Z, h, lg, r, sq, n, +1);
-    for (int j = threadIdx.x; j < h; j += blockDim.x) {
-      out[size_t(fld) * npix + first + 2 * j] = Z[2 * j];
-      out[size_t(fld) * npix + first + 2 * j + 1] = Z[2 * j + 1];
+      const double tr = c * dr - s * di, ti = c * di + s * dr;
+      yr = (c1r + c2r) - ti;
+      yi = (c1i + c2i) + tr;
+    };
+    if (bo < 0) {
+      double* Y = sm;
+      double* Z = sm + n;
+      for (int k = threadIdx.x; k < h; k += blockDim.x) yk(k, Y[2 * k], Y[2 * k + 1]);
+      __syncthreads();
+      dft_mixed(Y, Z, h, lg, r, sq, n, +1);
+      for (int j = threadIdx.x; j < h; j += blockDim.x) {
+        out[size_t(fld) * npix + first + 2 * j] = Z[2 * j];
+        out[size_t(fld) * npix + first + 2 * j + 1] = Z[2 * j + 1];
+      }
+    } else {
+      // the e^{+...} transform as conj(DFT^-(conj Y))
+      double* A = sm;
+      for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        double ar = 0.0, ai = 0.0;
+        if (k < h) {
+          double yr, yi, c, s;
+          yk(k, yr, yi);
+          chirp(k, h, c, s);
+          ar = yr * c - yi * s;    // (yr - i yi)(c - i s)
+          ai = -yi * c - yr * s;
+        }
+        A[2 * k] = ar;
+        A[2 * k + 1] = ai;
+      }
+      __syncthreads();
+      bluestein_core(A, lgM, sqM, blu + bo);
+      const double inv = 1.0 / double(M);
+      for (int j = threadIdx.x; j < h; j += blockDim.x) {
+        double c, s;
+        chirp(j, h, c, s);
+        const double cr = A[2 * j] * inv, ci = A[2 * j + 1] * inv;
+        out[size_t(fld) * npix + first + 2 * j] = cr * c + ci * s;
+        out[size_t(fld) * npix + first + 2 * j + 1] = -(ci * c - cr * s);
+      }
     }
   }
 }
@@ -538,23 +743,12 @@ void launch_analysis(Plan* p, hipStream_t s, double* alm) {
   }
 }
 
-// LDS of the ring kernels: two n-double arrays and the quarter-wave table
-// of the longest ring (4 nside samples).
-size_t ring_fwd_lds(int nside, int lmax) {
-  (void)lmax;
-  const size_t n = 4 * size_t(nside);
-  return (2 * n + n / 4 + 1) * sizeof(double);
-}
-
-size_t ring_inv_lds(int nside, int lmax) { return ring_fwd_lds(nside, lmax); }
-
 clm_status ring_forward(Plan* p, const double* map, double* F, hipStream_t s) {
-  const size_t shm = ring_fwd_lds(p->d.nside_sht, p->d.lmax);
-  if (allow_lds(p, k_ring_forward, shm) != CLM_OK) return CLM_EHIP;
+  if (allow_lds(p, k_ring_forward, p->ring_lds) != CLM_OK) return CLM_EHIP;
   {
     CLM_TIMED(p, s, "sht_ring_forward");
-    hipLaunchKernelGGL(k_ring_forward, dim3(p->nring_s), dim3(kBlock), shm, s, map, p->ring_s,
-                       p->ringi_s, p->d.lmax, F);
+    hipLaunchKernelGGL(k_ring_forward, dim3(p->nring_s), dim3(kRingBlock), p->ring_lds, s, map,
+                       p->ring_s, p->ringi_s, p->blu_off, p->blu, p->d.lmax, F);
   }
   CLM_LAUNCH_CHECK();
   return CLM_OK;
@@ -584,18 +778,80 @@ clm_status synthesis(Plan* p, const double* alm, hipStream_t s) {
 }
 
 clm_status ring_inverse(Plan* p, const double* G, int nf, double* out, hipStream_t s) {
-  const size_t shm = ring_inv_lds(p->d.nside_sht, p->d.lmax);
-  if (allow_lds(p, k_ring_inverse, shm) != CLM_OK) return CLM_EHIP;
+  if (allow_lds(p, k_ring_inverse, p->ring_lds) != CLM_OK) return CLM_EHIP;
   {
     CLM_TIMED(p, s, "sht_ring_inverse");
-    hipLaunchKernelGGL(k_ring_inverse, dim3(p->nring_s), dim3(kBlock), shm, s, G, p->nring_s,
-                       p->ring_s, p->ringi_s, p->d.lmax, p->npix_s, nf, out);
+    hipLaunchKernelGGL(k_ring_inverse, dim3(p->nring_s), dim3(kRingBlock), p->ring_lds, s, G,
+                       p->nring_s, p->ring_s, p->ringi_s, p->blu_off, p->blu, p->d.lmax,
+                       p->npix_s, nf, out);
   }
   CLM_LAUNCH_CHECK();
   return CLM_OK;
 }
 
 }  // namespace
+
+// Ring-transform plan of the SHT grid: which rings take Bluestein's
+// transform (offset of their chirp-filter table, else -1), the tables, and
+// the dynamic LDS of the ring kernels (the largest ring's need).
+clm_status ring_plan(Plan* p) {
+  const int N = p->d.nside_sht, nr = p->nring_s;
+  std::vector<int64_t> off(nr, -1);
+  std::vector<int> lens;
+  std::vector<int64_t> loff;
+  int64_t total = 0;
+  size_t lds = 0;
+  for (int q = 0; q < nr; ++q) {
+    const int ring = q + 1, i = std::min(ring, 4 * N - ring);
+    const int n = i < N ? 4 * i : 4 * N, h = n / 2;
+    int r = h;
+    while (!(r & 1)) r >>= 1;
+    if (r <= kDirectOdd) {
+      lds = std::max(lds, size_t(2 * n + n / 4 + 1) * sizeof(double));
+      continue;
+    }
+    size_t k = 0;
+    while (k < lens.size() && lens[k] != n) ++k;
+    if (k == lens.size()) {
+      const int64_t M = int64_t(1) << lg_ceil(2 * h - 1);
+      lens.push_back(n);
+      loff.push_back(total);
+      total += 2 * M;
+      lds = std::max(lds, size_t(2 * M + M / 4 + 1) * sizeof(double));
+    }
+    off[q] = loff[k];
+  }
+  p->ring_lds = lds;
+  if (hipMalloc(&p->blu_off, size_t(nr) * sizeof(int64_t)) != hipSuccess)
+    return fail(p, CLM_ENOMEM, "hipMalloc failed (ring plan)");
+  CLM_HIP(hipMemcpy(p->blu_off, off.data(), off.size() * 8, hipMemcpyHostToDevice));
+  if (lens.empty() || lds > 160 * 1024) return CLM_OK;  // oversize: rejected at solve time
+  if (hipMalloc(&p->blu, size_t(total) * sizeof(double)) != hipSuccess)
+    return fail(p, CLM_ENOMEM, "hipMalloc failed (ring plan)");
+  int* dl = nullptr;
+  int64_t* dof = nullptr;
+  CLM_HIP(hipMalloc(&dl, lens.size() * sizeof(int)));
+  if (hipMalloc(&dof, loff.size() * sizeof(int64_t)) != hipSuccess) {
+    (void)hipFree(dl);
+    return fail(p, CLM_ENOMEM, "hipMalloc failed");
+  }
+  clm_status st = CLM_OK;
+  if (hipMemcpy(dl, lens.data(), lens.size() * sizeof(int), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(dof, loff.data(), loff.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      allow_lds(p, k_blu_table, lds) != CLM_OK) {
+    st = fail(p, CLM_EHIP, "ring plan set-up failed");
+  } else {
+    hipLaunchKernelGGL(k_blu_table, dim3(unsigned(lens.size())), dim3(kRingBlock), lds, 0, dl,
+                       dof, p->blu);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+      st = fail(p, CLM_EHIP, "ring plan kernel failed");
+  }
+  (void)hipFree(dl);
+  (void)hipFree(dof);
+  return st;
+}
 
 clm_status plane_mean(Plan* p, const void* kappa, int kappa_fp64, hipStream_t s) {
   const int nb = 1023;
@@ -623,9 +879,8 @@ namespace {
 // Mean, demean + degrade to the SHT grid and the ring transforms into F.
 clm_status sht_front(Plan* p, const void* kappa, int kappa_fp64, double* F, hipStream_t s) {
   const clm_plan_desc& d = p->d;
-  if (ring_fwd_lds(d.nside_sht, d.lmax) > 160 * 1024 ||
-      ring_inv_lds(d.nside_sht, d.lmax) > 160 * 1024)
-    return fail(p, CLM_EUNSUPPORTED, "ring transforms exceed the LDS for this nside/lmax");
+  if (p->ring_lds > 160 * 1024)
+    return fail(p, CLM_EUNSUPPORTED, "ring transforms exceed the LDS for this nside");
   clm_status st = plane_mean(p, kappa, kappa_fp64, s);
   if (st != CLM_OK) return st;
   const int64_t ratio = d.nside_fine / d.nside_sht;

@@ -66,6 +66,25 @@ def test_alm2map_ragged_lmax(clm):
         assert rel(got, ref) < 1e-12, (N, lmax)
 
 
+@pytest.mark.parametrize("N,lmax", [(256, 300), (512, 200), (1024, 48)])
+def test_ring_transforms_long_odd_rings(clm, N, lmax):
+    """Polar-cap rings of 4i samples whose odd factor exceeds the direct-DFT
+    limit go through the chirp (Bluestein) transform: synthesis (inverse
+    ring transforms) and analysis + Poisson (forward) against the oracle,
+    whose ring DFTs are plain FFTs of each ring."""
+    alm = inputs.gaussian_alm(lmax, seed=N + lmax, amplitude=1.0)
+    ref = osht.alm2map(N, lmax, alm)
+    got = clm.alm2map(torch.from_numpy(alm).cuda(), lmax, N).cpu().numpy()
+    assert report("ring_inverse N=%d lmax=%d" % (N, lmax), rel(got, ref)) < 1e-12
+    plan = clm.Plan(N, nside_sht=N, lmax=lmax, solver="sht")
+    plan.poisson_solve(torch.from_numpy(ref).cuda())
+    palm = osht.poisson(lmax, osht.map2alm(N, lmax, ref - ref.mean()))
+    assert report("ring_forward N=%d lmax=%d" % (N, lmax),
+                  rel(plan.psi_alm().cpu().numpy(), palm)) < 1e-10
+    plan.sync_status()
+    plan.close()
+
+
 def test_sht_poisson_parity(clm, c1_case):
     c = c1_case
     plan = clm.Plan(c["N"], nside_sht=c["N"], lmax=c["lmax"], solver="sht")
