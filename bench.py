@@ -290,6 +290,58 @@ def cpu_baseline(torch, kappa, plan64, sample_bundles):
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0}
 
 
+def c3_run(clm, torch, inputs, cosmo, gal):
+    """Multiplane ray tracing: 20 lens planes at chi_m = (m + 1/2) dchi to
+    z = 1.5, each an Nside 2048 lognormal kappa (sigma_g 0.1 -> 0.6 with the
+    plane index, C_l ~ l^-2 to lmax 2048, seeds 100 + m, scaled to a 1 arcmin
+    rms deflection), solved by SHT at Nside 1024 / lmax 2048 + MG (12,288
+    patches of 256^2, 4 V-cycles, float32 correction), 50.3M rays and the
+    1e6 galaxies.  Inputs are generated on the GPU before timing; the 20
+    plane steps (solve, shear, ray update, galaxies) are timed together."""
+    nplanes, ns3, l3 = 20, 1024, 2048
+    sig = inputs.multiplane_sigmas(nplanes)
+    kap = torch.empty(nplanes, 12 * NF * NF, dtype=torch.float32, device="cuda")
+    for m in range(nplanes):
+        alm = torch.from_numpy(inputs.gaussian_alm(l3, seed=100 + m, sigma=sig[m])).cuda()
+        e = torch.exp(clm.alm2map(alm, l3, NF))
+        kap[m] = (inputs.deflection_scale(l3, sig[m]) * (e - e.mean())).float()
+        del e
+    plan = clm.Plan(NF, nside_sht=ns3, lmax=l3, nside_bundle=NB, patch_cells=NCELL,
+                    mg_vcycles=VCYC, mg_prec="fp32")
+    rays = plan.new_rays()
+    chi = (np.arange(nplanes + 1) + 0.5) * DCHI
+    gal["A"].zero_()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.get_timing()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for m in range(nplanes):
+        plan.raytrace_planes(kap[m], chi, m, rays, galaxies=gal)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    stages = plan.get_timing()
+    plan.set_timing(False)
+    plan.sync_status()
+    npix = plan.npix_fine
+    A = gal["A"].double()
+    ru = stages.get("ray_update", (0.0, 1))
+    out = dict(
+        planes=nplanes, nside_sht=ns3, lmax=l3, ms_all_planes=ms, ms_per_plane=ms / nplanes,
+        ray_plane_updates_per_s=dict(end_to_end=npix * nplanes / (ms * 1e-3),
+                                     kernel_only=npix / (ru[0] / ru[1] * 1e-3)),
+        stage_ms={k: v[0] for k, v in stages.items()},
+        galaxies=int(gal["theta"].numel()),
+        galaxies_with_A=int((A.abs().sum(0) > 0).sum()),
+        galaxy_A_finite=bool(torch.isfinite(A).all()))
+    plan.close()
+    del plan, rays, kap
+    torch.cuda.empty_cache()
+    return out
+
+
 def c4_run(clm, torch, inputs):
     """Batched precision forms: 32 pure-SHT Poisson solves at Nside drawn
     from {512, 1024, 2048} (lmax = 2 Nside, Gaussian kappa with sigma 0.5,
@@ -460,6 +512,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--no-eps", action="store_true",
                     help="skip the run under the epsilon stopping rule")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 20-plane ray tracing run")
     ap.add_argument("--no-c4", action="store_true",
                     help="skip the batched-precision workload (32 uneven pure-SHT planes)")
     ap.add_argument("--no-c5", action="store_true",
@@ -585,6 +639,9 @@ def main():
         pe.close()
         del pe, re_
         torch.cuda.empty_cache()
+    if not args.no_c3:
+        print("bench: multiplane ray tracing", file=sys.stderr, flush=True)
+        out["c3_multiplane"] = c3_run(clm, torch, inputs, cosmo, gal)
     if not args.no_c4:
         print("bench: batched precision forms", file=sys.stderr, flush=True)
         out["c4_precision_forms"] = c4_run(clm, torch, inputs)

@@ -392,6 +392,8 @@ __global__ __launch_bounds__(kRingBlock) void k_ring_inverse(const double* G, in
   const int64_t first = ri[2 * q + 1];
   const double phi0 = rt[4 * q + 3];
   const int64_t bo = boff[q];
+  // e^{i n phi0} = +-1: n phi0 is a multiple of pi on every HEALPix ring
+  const double sig = cos(double(n) * phi0) > 0.0 ? 1.0 : -1.0;
   int h, lg, r;
   half_split(n, h, lg, r);
   const int lgM = bo < 0 ? 0 : lg_ceil(2 * h - 1), M = 1 << lgM;
@@ -406,22 +408,27 @@ __global__ __launch_bounds__(kRingBlock) void k_ring_inverse(const double* G, in
   for (int fld = 0; fld < nf; ++fld) {
     const double* g = G + (size_t(fld) * nring + q) * (lmax + 1) * 2;
     __syncthreads();
-    auto bk = [&](int k, double& br, double& bi) {
+    // B_k with (c, s) = e^{i k phi0}; e^{i (k + t n) phi0} = sig^t e^{i k phi0}
+    auto bk = [&](int k, double c, double s, double& br, double& bi) {
       br = 0.0;
       bi = 0.0;
+      double sg = 1.0;
       for (int m = k; m <= lmax; m += n) {
-        double s, c;
-        sincos(double(m) * phi0, &s, &c);
-        const double cm = m == 0 ? 1.0 : 2.0;
+        const double cm = m == 0 ? sg : 2.0 * sg;
         const double gr = g[2 * m], gi = g[2 * m + 1];
         br += cm * (c * gr - s * gi);
         bi += cm * (c * gi + s * gr);
+        sg *= sig;
       }
     };
     auto ck = [&](int k, double& cr, double& ci) {
-      double ar, ai, br, bi;
-      bk(k, ar, ai);
-      bk((n - k) % n, br, bi);
+      double ar, ai, br, bi, s, c;
+      sincos(double(k) * phi0, &s, &c);
+      bk(k, c, s, ar, ai);
+      if (k == 0)
+        bk(0, 1.0, 0.0, br, bi);
+      else
+        bk(n - k, sig * c, -sig * s, br, bi);  // e^{i (n - k) phi0} = sig conj e^{i k phi0}
       cr = 0.5 * (ar + br);
       ci = 0.5 * (ai - bi);
     };
