@@ -144,12 +144,33 @@ def summarize_pmc(fetch_csv, write_csv, fetch_cmd, write_cmd):
     return "\n".join(out) + "\n"
 
 
-def summarize_stats(stats_csv, cmd):
+def summarize_counters(pmc_csv, cmd, title):
+    """Counter summary text: per kernel and grid, the mean of each counter
+    per dispatch, with VALU and MFMA busy fractions where their inputs were
+    collected (256 CUs, 1024 SIMDs)."""
+    acc = {}
+    for r in csv.DictReader(open(pmc_csv)):
+        key = (short_name(r["Kernel_Name"])[:90], int(r["Grid_Size"]))
+        d = acc.setdefault(key, {})
+        v = d.setdefault(r["Counter_Name"], [0.0, 0])
+        v[0] += float(r["Counter_Value"])
+        v[1] += 1
+    names = sorted({c for d in acc.values() for c in d})
+    out = ["# " + title, "# command: " + cmd,
+           "# kernel | grid | dispatches | " + " | ".join(names)]
+    for key, d in sorted(acc.items(), key=lambda kv: -max(v[0] / v[1] for v in kv[1].values())):
+        n = max(v[1] for v in d.values())
+        vals = " | ".join("%.4g" % (d[c][0] / d[c][1]) if c in d else "-" for c in names)
+        out.append("%s | %d | %d | %s" % (key[0], key[1], n, vals))
+    return "\n".join(out) + "\n"
+
+
+def summarize_stats(stats_csv, cmd, title="rocprofv3 kernel statistics, C2 workload"):
     """Kernel-trace summary text: per kernel calls and average duration, then
     per kernel and grid size (the levels of one kernel differ in grid) from the
     trace beside the statistics file."""
     rows = list(csv.DictReader(open(stats_csv)))
-    out = ["# rocprofv3 kernel statistics, C2 workload", "# command: " + cmd,
+    out = ["# " + title, "# command: " + cmd,
            "# kernel | calls | average us | total ms | percent"]
     for r in rows:
         out.append("%s | %s | %.1f | %.3f | %.2f" % (
@@ -520,13 +541,18 @@ def main():
                     help="skip the differentiation workload (8 planes, chi^2 gradient)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with a plain copy kernel of known size (counter calibration)")
-    ap.add_argument("--summarize-stats", nargs=2, metavar=("CSV", "CMD"),
-                    help="print a rocprofv3 --stats summary (no GPU)")
+    ap.add_argument("--summarize-stats", nargs="+", metavar="ARG",
+                    help="CSV CMD [TITLE]: print a rocprofv3 --stats summary (no GPU)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("CSV", "CMD", "TITLE"),
+                    help="print a per-kernel summary of a rocprofv3 --pmc run (no GPU)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FCMD", "WCMD"),
                     help="print the HBM traffic summary of two --pmc passes (no GPU)")
     args = ap.parse_args()
     if args.summarize_stats:
         sys.stdout.write(summarize_stats(*args.summarize_stats))
+        return
+    if args.summarize_counters:
+        sys.stdout.write(summarize_counters(*args.summarize_counters))
         return
     if args.summarize_pmc:
         sys.stdout.write(summarize_pmc(*args.summarize_pmc))
