@@ -20,7 +20,12 @@
  *     workspace, allocated once in clm_plan_create and freed in
  *     clm_plan_destroy.
  *   - Calls are asynchronous on the given stream (0 = the null stream) and
- *     never synchronise, except clm_plan_sync_status and clm_plan_timing.
+ *     never synchronise, except clm_plan_sync_status, clm_plan_get_timing,
+ *     clm_alm2map and a solve under the epsilon rule (which reads one
+ *     counter per V-cycle).  The other solve, evaluation, ray and adjoint
+ *     calls launch kernels only (no allocation, memset or host wait), so
+ *     they may be captured in a HIP graph once each has run eagerly on the
+ *     plan (the first call of a kernel may set its LDS attribute).
  *   - kappa is the standard convergence; the solve uses lap psi = 2 kappa
  *     (the paper's kappa^(m) is twice the standard one, Sec. 2.1), so
  *     psi_lm = -2 kappa_lm / (l (l+1)) with psi_00 = 0 (Sec. 3.2).
@@ -278,6 +283,21 @@ clm_status clm_raytrace_planes(clm_plan plan, const void* kappa_dev, int32_t kap
 clm_status clm_ray_update(clm_plan plan, int32_t slot, const double* chi_host, int32_t nchi,
                           int32_t m, double curvature_K, const clm_rays* rays,
                           hipStream_t stream);
+
+/*
+ * The reduced galaxy step of App. D (eq. gatraj) for shell k alone, with the
+ * rays' current Jacobians taken as A^(k) (rays->A) and A^(k-1)
+ * (rays->A_prev): the step clm_raytrace_planes takes after the ray update
+ * through plane k - 1 (k = 0: A_g = I).  For callers that drive
+ * clm_poisson_solve and clm_ray_update themselves.  Galaxies whose chi lies
+ * in shell k (between the midpoints around chi_k; the last shell is open
+ * above) get A_g; the others are left untouched.  chi_host, nchi and
+ * curvature_K as for clm_raytrace_planes; 0 <= k < nchi.  Asynchronous on
+ * `stream`.
+ */
+clm_status clm_galaxies_shell(clm_plan plan, const double* chi_host, int32_t nchi, int32_t k,
+                              double curvature_K, const clm_rays* rays,
+                              const clm_galaxies* galaxies, hipStream_t stream);
 
 /*
  * Multigrid convergence of the latest SHT+MG solve: per patch (bundle index

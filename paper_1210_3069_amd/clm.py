@@ -66,6 +66,8 @@ _SIGS = {
     "clm_raytrace_planes": (_P, _P, _I32, ctypes.POINTER(_D), _I32, _I32, _I32, _D,
                             ctypes.POINTER(Rays), ctypes.POINTER(Galaxies), _P),
     "clm_ray_update": (_P, _I32, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays), _P),
+    "clm_galaxies_shell": (_P, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays),
+                           ctypes.POINTER(Galaxies), _P),
     "clm_shear_adjoint": (_P, _I32, _P, _P, _I64, _P, _P, _P),
     "clm_poisson_adjoint": (_P, _I32, _P, _P),
     "clm_get_mg_convergence": (_P, _P, _P, _P),
@@ -308,6 +310,18 @@ class Plan:
             self.h, _ptr(k), int(k.dtype == torch.float64),
             chi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), chi.size, first_plane,
             k.shape[0], K, ctypes.byref(s), gp, _stream()), "raytrace_planes")
+
+    def galaxies_shell(self, chi, k, rays, galaxies, K=0.0):
+        """eq. gatraj for the galaxies of shell k from the rays' current
+        A (= A^(k)) and A_prev (= A^(k-1))."""
+        chi = np.ascontiguousarray(chi, dtype=np.float64)
+        s = self._rays_struct(rays)
+        g = Galaxies(galaxies["theta"].data_ptr(), galaxies["phi"].data_ptr(),
+                     galaxies["chi"].data_ptr(), galaxies["A"].data_ptr(),
+                     galaxies["theta"].numel())
+        cp = chi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._check(lib().clm_galaxies_shell(self.h, cp, chi.size, k, K, ctypes.byref(s),
+                                             ctypes.byref(g), _stream()), "galaxies_shell")
 
     def ray_update(self, chi, m, rays, slot=0, K=0.0):
         chi = np.ascontiguousarray(chi, dtype=np.float64)

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "calclens_mi.h"
@@ -60,6 +61,7 @@ struct Plan {
   int64_t* blu_off = nullptr;   // [nring_s] chirp-filter table offset (doubles), -1: direct
   double* blu = nullptr;        // chirp-filter transforms of the Bluestein rings
   size_t ring_lds = 0;          // dynamic LDS of the ring kernels
+  std::vector<std::pair<const void*, size_t>> lds_set;  // LDS opt-ins made
   double* lam_mant = nullptr;   // [lmax+1][H] lambda_mm mantissa
   int* lam_scale = nullptr;     // [lmax+1][H] scale exponent (units of 2^800)
   int* r2n_s = nullptr;         // RING -> NESTED at nside_sht
@@ -157,6 +159,18 @@ struct TimedLaunch {
 inline clm_status fail(Plan* p, clm_status s, const std::string& msg) {
   if (p) p->err = msg;
   return s;
+}
+
+// Dynamic LDS above 64 KiB needs an explicit opt-in per kernel.  A plan asks
+// once per kernel and size, so later calls (and calls under stream capture)
+// make no attribute call.
+inline clm_status lds_opt_in(Plan* p, const void* fn, size_t bytes) {
+  if (bytes <= 65536) return CLM_OK;
+  for (const auto& e : p->lds_set)
+    if (e.first == fn && e.second >= bytes) return CLM_OK;
+  CLM_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+  p->lds_set.emplace_back(fn, bytes);
+  return CLM_OK;
 }
 
 // ---- stage launchers (each returns CLM_OK or an error recorded in p->err)

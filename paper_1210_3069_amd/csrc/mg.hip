@@ -1158,10 +1158,7 @@ __global__ void k_potential(const double* u0, const T* du, int n, int64_t first,
 
 template <typename K>
 clm_status allow_lds(Plan* p, K kernel, size_t bytes) {
-  if (bytes > 65536)
-    CLM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
-  return CLM_OK;
+  return lds_opt_in(p, reinterpret_cast<const void*>(kernel), bytes);
 }
 
 // Tile kernels are compiled per halo width: pre-smoothing needs 2 nu + 1

@@ -764,10 +764,7 @@ clm_status ring_forward(Plan* p, const double* map, double* F, hipStream_t s) {
 // LDS above 64 KiB needs an explicit opt-in per kernel.
 template <typename K>
 clm_status allow_lds(Plan* p, K kernel, size_t bytes) {
-  if (bytes > 65536)
-    CLM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
-  return CLM_OK;
+  return lds_opt_in(p, reinterpret_cast<const void*>(kernel), bytes);
 }
 
 clm_status synthesis(Plan* p, const double* alm, hipStream_t s) {

@@ -419,6 +419,81 @@ def test_raytrace_parity(clm):
             w = orays.galaxy_weight(chi, k, gchi[i])
             expect = ((1 - w) * Api + w * Ai).ravel()
         assert np.abs(Ag[:, i] - expect).max() < 3e-6, (i, k)
+    # the same run driven plane by plane through clm_poisson_solve,
+    # clm_ray_update and clm_galaxies_shell gives identical results
+    rays2 = plan.new_rays()
+    gal2 = dict(gal, A=torch.full_like(gal["A"], np.nan))
+    plan.galaxies_shell(chi, 0, rays2, gal2)
+    for m in range(nplanes):
+        plan.poisson_solve(torch.from_numpy(kaps[m]).cuda())
+        plan.ray_update(chi, m, rays2)
+        plan.galaxies_shell(chi, m + 1, rays2, gal2)
+    plan.sync_status()
+    for key in ("theta", "phi", "beta", "A", "A_prev"):
+        assert torch.equal(rays2[key], rays[key]), key
+    assert torch.equal(gal2["A"], gal["A"])
+    plan.close()
+
+
+def _capture(fn):
+    """fn's launches captured into a graph on a side stream (after one eager
+    warm-up call there), as torch.cuda.graph does."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g
+
+
+@pytest.mark.parametrize("kind", ["sht_mg_fp32", "sht_batched_fp32"])
+def test_graph_capture_replays_match_eager(clm, kind):
+    """The fixed-cycle solve path makes no allocation, memset or host wait,
+    so it can be captured in a HIP graph: every replay (with eager work and
+    synchronisation between replays) reproduces the eager outputs bit for
+    bit."""
+    if kind == "sht_mg_fp32":
+        N, lmax = 64, 32
+        g0 = osht.alm2map(N, lmax, inputs.gaussian_alm(lmax, seed=3, sigma=0.5))
+        k = torch.from_numpy(np.exp(g0) - np.mean(np.exp(g0))).cuda()
+        plan = clm.Plan(N, nside_sht=16, lmax=lmax, nside_bundle=4, patch_cells=256,
+                        mg_vcycles=3, mg_prec="fp32")
+        outs = (torch.empty(2, plan.npix_fine, dtype=torch.float32, device="cuda"),
+                torch.empty(3, plan.npix_fine, dtype=torch.float32, device="cuda"))
+
+        def run():
+            plan.poisson_solve(k)
+            plan.shear_at_pixels(order="nested", fp64=False, out=outs)
+    else:
+        N, lmax, P = 128, 256, 5
+        k = torch.stack([clm.alm2map(torch.from_numpy(
+            inputs.gaussian_alm(lmax, seed=90 + i, amplitude=1.0)).cuda(), lmax, N)
+            for i in range(P)])
+        plan = clm.Plan(N, nside_sht=N, lmax=lmax, solver="sht", max_planes=P,
+                        legendre_prec="fp32")
+        outs = (torch.empty(P, plan.npix_sht, dtype=torch.float64, device="cuda"),)
+
+        def run():
+            plan.poisson_solve(k)
+            for i in range(P):
+                outs[0][i].copy_(plan.psi_map(i))
+    run()
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    g = _capture(run)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), (kind, rep)
+        plan.sync_status()
     plan.close()
 
 
