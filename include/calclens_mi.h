@@ -108,7 +108,14 @@ typedef struct {
   int32_t adjoint;       /* 1: also allocate the workspace of
                             clm_shear_adjoint / clm_poisson_adjoint (FP64,
                             about 4 x 8 bytes per finest cell); SHT+MG
-                            with a fixed mg_vcycles > 0 only               */
+                            with a fixed mg_vcycles > 0 and
+                            analysis_iters = 0 only                       */
+  int32_t analysis_iters; /* Jacobi refinements of the analysis, 0..16
+                            (default 0): a_lm <- a_lm + A(f - S a_lm), S the
+                            synthesis and A the quadrature analysis on the
+                            nside_sht grid, which drives HEALPix's inexact
+                            quadrature toward the band-limited solution;
+                            legendre_prec = CLM_FP64 only                 */
 } clm_plan_desc;
 
 /* Fill *d with the defaults for a fine grid: nside_sht = nside_fine / 8

@@ -23,7 +23,8 @@ class PlanDesc(ctypes.Structure):
         "nside_fine", "nside_sht", "lmax", "nside_bundle", "patch_factor", "patch_cells",
         "mg_vcycles", "nu_pre", "nu_post", "solver", "mg_prec", "max_planes",
         "legendre_prec", "mg_max_vcycles")] + [("mg_eps", ctypes.c_double),
-                                               ("adjoint", ctypes.c_int32)]
+                                               ("adjoint", ctypes.c_int32),
+                                               ("analysis_iters", ctypes.c_int32)]
 
 
 class Rays(ctypes.Structure):

@@ -83,6 +83,8 @@ struct Plan {
   float* apart = nullptr;       // [ring blocks][nalm][32] analysis partial sums
   float* psib = nullptr;        // [nalm][32] psi_lm as GEMM columns
   double* deriv = nullptr;      // [5][npix_s] pure-SHT raw derivative maps
+  double* iter_map = nullptr;   // [npix_s] analysis refinement: f - S a
+  double* iter_alm = nullptr;   // [nalm] complex: its analysis
   void* fprime = nullptr;       // [npatch][n^2] T
   void* dutmp = nullptr;        // [npatch][n^2] T (ping-pong partner of du)
   // per coarser tile level k (1 .. ktile), and the LDS level ktile:

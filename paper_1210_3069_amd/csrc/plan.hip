@@ -35,7 +35,7 @@ Plan::~Plan() {
   f(lam_scale); f(blu_off); f(blu);
   f(r2n_s); f(r2n_f); f(rot); f(coef); f(cinv); f(kap_s); f(F); f(G); f(red);
   f(rcoef); f(Fb); f(Gb); f(apart); f(psib);
-  f(deriv); f(fprime); f(dutmp); f(status_dev);
+  f(deriv); f(fprime); f(dutmp); f(status_dev); f(iter_map); f(iter_alm);
   for (auto* q : ubar) f(q);
   for (auto* q : rbar) f(q);
   for (auto* q : flev) f(q);
@@ -358,7 +358,9 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
       d.nside_fine > 8192 || d.lmax < 1 || d.max_planes < 1 ||
       (d.solver != CLM_SOLVER_SHT && d.solver != CLM_SOLVER_SHT_MG) ||
       (d.legendre_prec != CLM_FP64 && d.legendre_prec != CLM_FP32 &&
-       d.legendre_prec != CLM_BF16X3) || (d.adjoint != 0 && d.adjoint != 1))
+       d.legendre_prec != CLM_BF16X3) || (d.adjoint != 0 && d.adjoint != 1) ||
+      d.analysis_iters < 0 || d.analysis_iters > 16 ||
+      (d.analysis_iters > 0 && (d.legendre_prec != CLM_FP64 || d.adjoint)))
     return CLM_EINVAL;
   if (d.solver == CLM_SOLVER_SHT && d.nside_sht != d.nside_fine) return CLM_EINVAL;
   if (d.solver == CLM_SOLVER_SHT_MG) {
@@ -411,6 +413,10 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
 
   const int64_t nF = int64_t(p->nring_s) * (d.lmax + 1) * 2;
   if ((s = alloc(p, &p->kap_s, size_t(p->npix_s))) != CLM_OK) return bail(s);
+  if (d.analysis_iters > 0) {
+    if ((s = alloc(p, &p->iter_map, size_t(p->npix_s))) != CLM_OK) return bail(s);
+    if ((s = alloc(p, &p->iter_alm, size_t(p->nalm) * 2)) != CLM_OK) return bail(s);
+  }
   if ((s = alloc(p, &p->F, size_t(nF))) != CLM_OK) return bail(s);
   if ((s = alloc(p, &p->G, size_t(nF) * (p->mg ? 1 : 5))) != CLM_OK) return bail(s);
   if ((s = alloc(p, &p->red, 1024)) != CLM_OK) return bail(s);

@@ -913,14 +913,9 @@ clm_status poisson(Plan* p, double* alm, hipStream_t s) {
   return CLM_OK;
 }
 
-}  // namespace
-
-clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
-  clm_status st = sht_front(p, kappa, kappa_fp64, p->F, s);
-  if (st != CLM_OK) return st;
-  double* alm = p->slots[slot].alm;
-  const int rpt = rpt_for(p->H);
-  switch (rpt) {
+// a_lm of the ring transforms in p->F (FP64 Legendre analysis).
+clm_status analysis(Plan* p, double* alm, hipStream_t s) {
+  switch (rpt_for(p->H)) {
     case 1: launch_analysis<1>(p, s, alm); break;
     case 2: launch_analysis<2>(p, s, alm); break;
     case 4: launch_analysis<4>(p, s, alm); break;
@@ -929,6 +924,48 @@ clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipSt
     default: return fail(p, CLM_EUNSUPPORTED, "too many rings per thread");
   }
   CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+// y = x - y and y = y + x, elementwise.
+__global__ void k_sub_from(int64_t n, const double* x, double* y) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = x[t] - y[t];
+}
+
+__global__ void k_add_to(int64_t n, const double* x, double* y) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) y[t] += x[t];
+}
+
+}  // namespace
+
+clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
+  clm_status st = sht_front(p, kappa, kappa_fp64, p->F, s);
+  if (st != CLM_OK) return st;
+  double* alm = p->slots[slot].alm;
+  if ((st = analysis(p, alm, s)) != CLM_OK) return st;
+  // Jacobi refinement: a <- a + A(f - S a), f the degraded, demeaned map
+  for (int it = 0; it < p->d.analysis_iters; ++it) {
+    if ((st = synthesis(p, alm, s)) != CLM_OK) return st;
+    if ((st = ring_inverse(p, p->G, 1, p->iter_map, s)) != CLM_OK) return st;
+    {
+      CLM_TIMED(p, s, "sht_refine");
+      hipLaunchKernelGGL(k_sub_from, dim3(unsigned((p->npix_s + kBlock - 1) / kBlock)),
+                         dim3(kBlock), 0, s, p->npix_s, static_cast<const double*>(p->kap_s),
+                         p->iter_map);
+    }
+    CLM_LAUNCH_CHECK();
+    if ((st = ring_forward(p, p->iter_map, p->F, s)) != CLM_OK) return st;
+    if ((st = analysis(p, p->iter_alm, s)) != CLM_OK) return st;
+    {
+      CLM_TIMED(p, s, "sht_refine");
+      hipLaunchKernelGGL(k_add_to, dim3(unsigned((2 * p->nalm + kBlock - 1) / kBlock)),
+                         dim3(kBlock), 0, s, 2 * p->nalm,
+                         static_cast<const double*>(p->iter_alm), alm);
+    }
+    CLM_LAUNCH_CHECK();
+  }
   if ((st = poisson(p, alm, s)) != CLM_OK) return st;
   if ((st = synthesis(p, alm, s)) != CLM_OK) return st;
   return ring_inverse(p, p->G, 1, p->slots[slot].psi_s, s);

@@ -38,7 +38,8 @@ def test_default_description(L):
     assert (d.nside_sht, d.lmax, d.nside_bundle, d.patch_cells) == (256, 512, 32, 256)
     assert (d.mg_vcycles, d.nu_pre, d.nu_post, d.patch_factor) == (4, 2, 2, 4)
     assert (d.mg_max_vcycles, d.mg_eps, d.adjoint) == (20, 0.1, 0)
-    assert ctypes.sizeof(d) == 72  # 14 int32, padding, a double, an int32
+    assert d.analysis_iters == 0
+    assert ctypes.sizeof(d) == 72  # 14 int32, padding, a double, two int32
 
 
 @pytest.mark.parametrize("fields", [
@@ -48,7 +49,10 @@ def test_default_description(L):
     # the epsilon rule needs a positive threshold and cycle limit, and the
     # adjoint a fixed cycle count
     dict(mg_vcycles=0, mg_eps=0.0), dict(mg_vcycles=0, mg_max_vcycles=0),
-    dict(mg_eps=-1.0), dict(mg_eps=float("nan")), dict(mg_vcycles=0, adjoint=1)])
+    dict(mg_eps=-1.0), dict(mg_eps=float("nan")), dict(mg_vcycles=0, adjoint=1),
+    # analysis refinement: 0..16, FP64 Legendre transforms, no adjoint
+    dict(analysis_iters=17), dict(analysis_iters=-1), dict(analysis_iters=1, legendre_prec=1),
+    dict(analysis_iters=2, adjoint=1)])
 def test_invalid_descriptions_rejected(L, fields):
     from paper_1210_3069_amd import clm
     d = clm.PlanDesc()
