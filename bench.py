@@ -57,6 +57,7 @@ def stage_kernels(nbundle, ncell):
         "patch_setup": ("k_patch_setup<float, 64>", nbundle * t0 * 512),
         "mg_pre_l0": ("k_mg_pre<float", nbundle * t0 * 512),
         "mg_post_l0": ("k_mg_post<float", nbundle * t0 * 512),
+        "mg_postpre_l0": ("k_mg_postpre<float", nbundle * t0 * 1024),
         "mg_pre_l1+": ("k_mg_pre<float", nbundle * t1 * 512),
         "mg_post_l1+": ("k_mg_post<float", nbundle * t1 * 512),
         "mg_lds": ("k_mg_lds<float", None),
@@ -192,15 +193,22 @@ def summarize_stats(stats_csv, cmd, title="rocprofv3 kernel statistics, C2 workl
     return "\n".join(out) + "\n"
 
 
-def bytes_model(stage, plan_n, nbundle, npix, ncyc):
+def bytes_model(stage, plan_n, nbundle, npix, ncyc, launches=None):
     """Algorithmic HBM bytes of one launch of a stage (float32 multigrid):
-    every array the step must read or write once, no halo re-reads."""
+    every array the step must read or write once, no halo re-reads.
+    `launches` (per step) tells the finest level's pre-smoothing of the
+    first cycle only (fused smoothing) from one per cycle."""
     cells = nbundle * plan_n * plan_n
     c1 = cells / 4
+    first_only = launches is not None and launches <= 1
     return {
         # f' and du read, du written, ubar/rbar of the next level written; the
         # first cycle starts from du = 0 and skips its read
-        "mg_pre_l0": cells * (4 + 4 + 4 + 2) - cells * 4 / ncyc,
+        "mg_pre_l0": cells * (4 + 4 + 2) if first_only
+        else cells * (4 + 4 + 4 + 2) - cells * 4 / ncyc,
+        # post-smoothing of a cycle fused with the next pre-smoothing: du, f'
+        # and the coarse u_H, ubar read; du, ubar, rbar written
+        "mg_postpre_l0": cells * (4 + 4 + 2 + 4 + 2),
         # du, f' and the coarse u_H, ubar read, du written
         "mg_post_l0": cells * (4 + 4 + 2 + 4),
         "mg_pre_l1+": c1 * (4 + 4 + 4 + 4 + 2),
@@ -586,12 +594,13 @@ def main():
     for k, (tot, cnt) in stages.items():
         per_stage[k] = dict(ms_per_step=tot / args.steps, launches_per_step=cnt / args.steps,
                             ms_per_launch=tot / max(cnt, 1))
-        b = bytes_model(k, NCELL, nbundle, npix, VCYC)
+        b = bytes_model(k, NCELL, nbundle, npix, VCYC, cnt / args.steps)
         if b is not None:
             per_stage[k]["alg_GBps"] = b / (tot / cnt * 1e-3) / 1e9
-    dom = max((k for k in per_stage if bytes_model(k, NCELL, nbundle, npix, VCYC)),
+    lps = {k: v["launches_per_step"] for k, v in per_stage.items()}
+    dom = max((k for k in per_stage if bytes_model(k, NCELL, nbundle, npix, VCYC, lps[k])),
               key=lambda k: per_stage[k]["ms_per_step"])
-    b_dom = bytes_model(dom, NCELL, nbundle, npix, VCYC)
+    b_dom = bytes_model(dom, NCELL, nbundle, npix, VCYC, lps[dom])
     achieved = per_stage[dom]["alg_GBps"]
     traffic = read_traffic(dom)
     roofline = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",

@@ -319,6 +319,7 @@ constexpr int kTileBlock = 512;
 template <typename T>
 struct TileArgs {
   int n, ntile, nu;
+  int nu2;              // fused post + pre: the pre-smoothing sweeps
   const double* coef;   // this level's rows
   const T* u_in;        // level iterate in (nullptr: zero), or ubar (level >= 1 pre)
   const T* f_in;        // source (level 0: f'; level >= 1 post: A f), or rbar (level >= 1 pre)
@@ -333,9 +334,13 @@ struct TileArgs {
   const int* done;      // epsilon rule: patches that stopped (nullptr: none)
 };
 
-constexpr int quads_per_thread(int q) {
+// Threads per tile workgroup: the widest halos (fused smoothing) take 1024 so
+// that a thread keeps no more than two quads in registers.
+constexpr int tile_threads(int hh) { return hh >= 10 ? 2 * kTileBlock : kTileBlock; }
+
+constexpr int quads_per_thread(int q, int nt) {
   int it = 1;
-  while (q * ((q + it - 1) / it) > kTileBlock) ++it;
+  while (q * ((q + it - 1) / it) > nt) ++it;
   return it;
 }
 
@@ -344,7 +349,8 @@ struct QT {
   static_assert(HH % 2 == 0, "quads must align with the coarse level");
   static constexpr int RR = kTile + 2 * HH;    // region side
   static constexpr int Q = RR / 2;             // quads per side
-  static constexpr int IT = quads_per_thread(Q);
+  static constexpr int NT = tile_threads(HH);
+  static constexpr int IT = quads_per_thread(Q, NT);
   static constexpr int TPR = (Q + IT - 1) / IT;  // threads per quad row
   static constexpr int QH = HH / 2;            // first interior quad
   static constexpr int S = Q + 2;              // parity-array row stride (guard columns)
@@ -402,7 +408,7 @@ struct Quad {
 template <typename T, int HH>
 __device__ __forceinline__ void qload_rows(QLds<T, HH>& t, const double* coef, int n, int i0) {
   using G = QT<T, HH>;
-  for (int r = threadIdx.x; r < G::RR; r += kTileBlock) {
+  for (int r = threadIdx.x; r < G::RR; r += G::NT) {
     const int gi = i0 + r;
     T sm = T(0), sp = T(0), isc = T(0), A = T(1), D = T(1), rD = T(1);
     if (gi >= 0 && gi < n) {
@@ -417,7 +423,7 @@ __device__ __forceinline__ void qload_rows(QLds<T, HH>& t, const double* coef, i
     }
     t.sm[r] = sm; t.sp[r] = sp; t.isc[r] = isc; t.A[r] = A; t.D[r] = D; t.rD[r] = rD;
   }
-  for (int k = threadIdx.x; k < G::Q; k += kTileBlock) {
+  for (int k = threadIdx.x; k < G::Q; k += G::NT) {
     const int gi = i0 + 2 * k;
     double a0 = 1.0, a1 = 1.0;
     if (gi >= 0 && gi + 1 < n) {
@@ -429,7 +435,7 @@ __device__ __forceinline__ void qload_rows(QLds<T, HH>& t, const double* coef, i
   // the guard ring of both parity arrays is zero (every region cell is
   // written by its quad)
   constexpr int NG = 2 * G::S + 2 * G::RR;
-  for (int k = threadIdx.x; k < 2 * NG; k += kTileBlock) {
+  for (int k = threadIdx.x; k < 2 * NG; k += G::NT) {
     const int par = k / NG, g = k - par * NG;
     int idx;
     if (g < 2 * G::S)
@@ -596,8 +602,102 @@ __device__ __forceinline__ bool interior_quad(const QRow<T>& rw, const Quad<T>& 
          Qd.qj < G::QH + kTile / 2;
 }
 
+// End of pre-smoothing: the interior quads store u (and A f), form the
+// residual and the area-weighted restrictions of u and of the residual.
 template <typename T, int HH>
-__global__ __launch_bounds__(kTileBlock) void k_mg_pre(TileArgs<T> a) {
+__device__ __forceinline__ void pre_epilogue(const TileArgs<T>& a, const QLds<T, HH>& t,
+                                             const QRow<T>& rw,
+                                             const Quad<T> (&qd)[QT<T, HH>::IT], int i0, int j0,
+                                             size_t pbase, size_t cbase) {
+  using G = QT<T, HH>;
+  const int n = a.n, nc = n / 2;
+  T* uo = a.u_out + pbase;
+  T* ubo = a.ubar_out + cbase;
+  T* rbo = a.rbar_out + cbase;
+  const int li = 2 * rw.qi;
+  const T a0 = t.A[li], a1 = t.A[li + 1], rden = t.rden[rw.qi];
+#pragma unroll
+  for (int it = 0; it < G::IT; ++it) {
+    const Quad<T>& Qd = qd[it];
+    if (!interior_quad<T, HH>(rw, Qd)) continue;
+    const int gi = i0 + li, gj = j0 + 2 * Qd.qj;
+    const int g = gi * n + gj;
+    store2(uo + g, Qd.u[0], Qd.u[1]);
+    store2(uo + g + n, Qd.u[2], Qd.u[3]);
+    if (a.fas_source) {
+      T* fo = a.f_out + pbase;
+      store2(fo + g, Qd.ft[0], Qd.ft[1]);
+      store2(fo + g + n, Qd.ft[2], Qd.ft[3]);
+    }
+    // A r = A f - A L u, summed over the quad (formed at all four cells:
+    // in float32 the cells the last half sweep updated carry the rounding
+    // of that update, which the coarse correction must see)
+    T AL[4];
+    qalap<T, HH>(t, rw, Qd, gi, gj, n, AL);
+    const T ar = ((Qd.ft[0] - AL[0]) + (Qd.ft[1] - AL[1])) + ((Qd.ft[2] - AL[2]) + (Qd.ft[3] - AL[3]));
+    const int gc = (gi / 2) * nc + gj / 2;
+    ubo[gc] = (a0 * (Qd.u[0] + Qd.u[1]) + a1 * (Qd.u[2] + Qd.u[3])) * rden;
+    rbo[gc] = ar * rden;
+  }
+}
+
+// Coarse correction e = u_H - ubar on the coarse cells covering the region
+// (+- 1 cell), then added to the owned quads: bilinear (9, 3, 3, 1)/16 of
+// the parent and its neighbours toward the child, direct injection of the
+// parent on the outermost fine ring.
+template <typename T, int HH>
+__device__ __forceinline__ void load_correction(const TileArgs<T>& a, T* e, size_t cbase, int i0,
+                                                int j0) {
+  using G = QT<T, HH>;
+  constexpr int CR = G::Q + 2;
+  const int nc = a.n / 2, ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // i0, j0 even
+  for (int item = threadIdx.x; item < CR * CR; item += G::NT) {
+    const int I = ci0 + item / CR, J = cj0 + item % CR;
+    T v = T(0);
+    if (I >= 0 && I < nc && J >= 0 && J < nc) {
+      const size_t g = cbase + size_t(I) * nc + J;
+      v = a.uc[g] - a.ubarc[g];
+    }
+    e[item] = v;
+  }
+}
+
+template <typename T, int HH>
+__device__ __forceinline__ void apply_correction(const T* e, const QRow<T>& rw,
+                                                 Quad<T> (&qd)[QT<T, HH>::IT], int i0, int j0,
+                                                 int n) {
+  using G = QT<T, HH>;
+  constexpr int CR = G::Q + 2;
+#pragma unroll
+  for (int it = 0; it < G::IT; ++it) {
+    Quad<T>& Qd = qd[it];
+    if (!Qd.live) continue;
+    const T* ec = e + (rw.qi + 1) * CR + (Qd.qj + 1);
+    const T c = ec[0];
+    const T nu = ec[-CR], nd = ec[CR], nl = ec[-1], nr = ec[1];
+    const T ul = ec[-CR - 1], ur = ec[-CR + 1], dl = ec[CR - 1], dr = ec[CR + 1];
+    const T p[4] = {(T(9) * c + T(3) * (nu + nl) + ul) * T(0.0625),
+                    (T(9) * c + T(3) * (nu + nr) + ur) * T(0.0625),
+                    (T(9) * c + T(3) * (nd + nl) + dl) * T(0.0625),
+                    (T(9) * c + T(3) * (nd + nr) + dr) * T(0.0625)};
+    const int gi = i0 + 2 * rw.qi, gj = j0 + 2 * Qd.qj;
+    if (Qd.edge) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int ci = gi + (k >> 1), cj = gj + (k & 1);
+        const bool ring = ci == 0 || ci == n - 1 || cj == 0 || cj == n - 1;
+        const T corr = ring ? c : p[k];
+        Qd.u[k] += Qd.rD[k] != T(0) ? corr : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Qd.u[k] += Qd.rD[k] != T(0) ? p[k] : T(0);
+    }
+  }
+}
+
+template <typename T, int HH>
+__global__ __launch_bounds__(tile_threads(HH)) void k_mg_pre(TileArgs<T> a) {
   using G = QT<T, HH>;
   __shared__ QLds<T, HH> t;
   QRow<T> rw;
@@ -634,39 +734,11 @@ __global__ __launch_bounds__(kTileBlock) void k_mg_pre(TileArgs<T> a) {
     qsweep<T, HH>(t, rw, qd, 1);
     __syncthreads();
   }
-  // interior quads: store u (and A f), residual, area-weighted restriction
-  T* uo = a.u_out + pbase;
-  T* ubo = a.ubar_out + cbase;
-  T* rbo = a.rbar_out + cbase;
-  const int li = 2 * rw.qi;
-  const T a0 = t.A[li], a1 = t.A[li + 1], rden = t.rden[rw.qi];
-#pragma unroll
-  for (int it = 0; it < G::IT; ++it) {
-    Quad<T>& Qd = qd[it];
-    if (!interior_quad<T, HH>(rw, Qd)) continue;
-    const int gi = i0 + li, gj = j0 + 2 * Qd.qj;
-    const int g = gi * n + gj;
-    store2(uo + g, Qd.u[0], Qd.u[1]);
-    store2(uo + g + n, Qd.u[2], Qd.u[3]);
-    if (a.fas_source) {
-      T* fo = a.f_out + pbase;
-      store2(fo + g, Qd.ft[0], Qd.ft[1]);
-      store2(fo + g + n, Qd.ft[2], Qd.ft[3]);
-    }
-    // A r = A f - A L u, summed over the quad (formed at all four cells:
-    // in float32 the cells the last half sweep updated carry the rounding
-    // of that update, which the coarse correction must see)
-    T AL[4];
-    qalap<T, HH>(t, rw, Qd, gi, gj, n, AL);
-    const T ar = ((Qd.ft[0] - AL[0]) + (Qd.ft[1] - AL[1])) + ((Qd.ft[2] - AL[2]) + (Qd.ft[3] - AL[3]));
-    const int gc = (gi / 2) * nc + gj / 2;
-    ubo[gc] = (a0 * (Qd.u[0] + Qd.u[1]) + a1 * (Qd.u[2] + Qd.u[3])) * rden;
-    rbo[gc] = ar * rden;
-  }
+  pre_epilogue<T, HH>(a, t, rw, qd, i0, j0, pbase, cbase);
 }
 
 template <typename T, int HH>
-__global__ __launch_bounds__(kTileBlock) void k_mg_post(TileArgs<T> a) {
+__global__ __launch_bounds__(tile_threads(HH)) void k_mg_post(TileArgs<T> a) {
   using G = QT<T, HH>;
   constexpr int CR = G::Q + 2;  // coarse cells covering the region quads +- 1
   __shared__ QLds<T, HH> t;
@@ -680,49 +752,12 @@ __global__ __launch_bounds__(kTileBlock) void k_mg_post(TileArgs<T> a) {
   const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
   const int n = a.n, nc = n / 2;
   const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
-  const int ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // i0, j0 even
   if (a.done && a.done[patch]) return;
   qload_rows(t, a.coef, n, i0);
-  for (int item = threadIdx.x; item < CR * CR; item += kTileBlock) {
-    const int I = ci0 + item / CR, J = cj0 + item % CR;
-    T v = T(0);
-    if (I >= 0 && I < nc && J >= 0 && J < nc) {
-      const size_t g = cbase + size_t(I) * nc + J;
-      v = a.uc[g] - a.ubarc[g];
-    }
-    e[item] = v;
-  }
+  load_correction<T, HH>(a, e, cbase, i0, j0);
   __syncthreads();
   qinit<T, HH>(t, rw, qd, a.u_in + pbase, a.f_in + pbase, a.f_scaled != 0, n, i0, j0);
-  // coarse correction: bilinear (9, 3, 3, 1)/16 of the parent and its
-  // neighbours toward the child, direct injection of the parent on the
-  // outermost fine ring
-#pragma unroll
-  for (int it = 0; it < G::IT; ++it) {
-    Quad<T>& Qd = qd[it];
-    if (!Qd.live) continue;
-    const T* ec = e + (rw.qi + 1) * CR + (Qd.qj + 1);
-    const T c = ec[0];
-    const T nu = ec[-CR], nd = ec[CR], nl = ec[-1], nr = ec[1];
-    const T ul = ec[-CR - 1], ur = ec[-CR + 1], dl = ec[CR - 1], dr = ec[CR + 1];
-    const T p[4] = {(T(9) * c + T(3) * (nu + nl) + ul) * T(0.0625),
-                    (T(9) * c + T(3) * (nu + nr) + ur) * T(0.0625),
-                    (T(9) * c + T(3) * (nd + nl) + dl) * T(0.0625),
-                    (T(9) * c + T(3) * (nd + nr) + dr) * T(0.0625)};
-    const int gi = i0 + 2 * rw.qi, gj = j0 + 2 * Qd.qj;
-    if (Qd.edge) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int ci = gi + (k >> 1), cj = gj + (k & 1);
-        const bool ring = ci == 0 || ci == n - 1 || cj == 0 || cj == n - 1;
-        const T corr = ring ? c : p[k];
-        Qd.u[k] += Qd.rD[k] != T(0) ? corr : T(0);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) Qd.u[k] += Qd.rD[k] != T(0) ? p[k] : T(0);
-    }
-  }
+  apply_correction<T, HH>(e, rw, qd, i0, j0, n);
   qput<T, HH>(t, qd);
   __syncthreads();
   for (int s = 0; s < a.nu; ++s) {
@@ -740,6 +775,43 @@ __global__ __launch_bounds__(kTileBlock) void k_mg_post(TileArgs<T> a) {
     store2(uo + g, Qd.u[0], Qd.u[1]);
     store2(uo + g + n, Qd.u[2], Qd.u[3]);
   }
+}
+
+// Finest level: the post-smoothing of one V-cycle and the pre-smoothing of
+// the next in one pass.  The region carries the halos of both (2 (nu_post +
+// nu_pre) + 2 cells: every sweep plus the residual), so the corrected and
+// smoothed iterate of the finished cycle never leaves LDS; the kernel writes
+// what the next cycle's pre-smoothing writes: u and the restrictions of u
+// and of the residual.
+template <typename T, int HH>
+__global__ __launch_bounds__(tile_threads(HH)) void k_mg_postpre(TileArgs<T> a) {
+  using G = QT<T, HH>;
+  constexpr int CR = G::Q + 2;
+  __shared__ QLds<T, HH> t;
+  __shared__ T e[CR * CR];
+  QRow<T> rw;
+  Quad<T> qd[G::IT];
+  const int64_t lb = xcd_block();
+  const int tpp = a.ntile * a.ntile;
+  const int64_t patch = lb / tpp;
+  const int tt = int(lb % tpp);
+  const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
+  const int n = a.n, nc = n / 2;
+  const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
+  qload_rows(t, a.coef, n, i0);
+  load_correction<T, HH>(a, e, cbase, i0, j0);
+  __syncthreads();
+  qinit<T, HH>(t, rw, qd, a.u_in + pbase, a.f_in + pbase, false, n, i0, j0);
+  apply_correction<T, HH>(e, rw, qd, i0, j0, n);
+  qput<T, HH>(t, qd);
+  __syncthreads();
+  for (int s = 0; s < a.nu + a.nu2; ++s) {
+    qsweep<T, HH>(t, rw, qd, 0);
+    __syncthreads();
+    qsweep<T, HH>(t, rw, qd, 1);
+    __syncthreads();
+  }
+  pre_epilogue<T, HH>(a, t, rw, qd, i0, j0, pbase, cbase);
 }
 
 // Coarse correction e = u_H - ubar prolonged to a fine cell: bilinear
@@ -1169,9 +1241,32 @@ clm_status launch_tile_hh(Plan* p, const TileArgs<T>& a, int64_t np, hipStream_t
   const dim3 grid(unsigned(np * a.ntile * a.ntile));
   (void)RR;
   if (PRE)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_pre<T, HH>), grid, dim3(kTileBlock), 0, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_pre<T, HH>), grid, dim3(QT<T, HH>::NT), 0, s, a);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_post<T, HH>), grid, dim3(kTileBlock), 0, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_post<T, HH>), grid, dim3(QT<T, HH>::NT), 0, s, a);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+template <typename T>
+clm_status launch_postpre(Plan* p, const TileArgs<T>& a, int64_t np, hipStream_t s) {
+  const dim3 grid(unsigned(np * a.ntile * a.ntile));
+  switch (2 * (a.nu + a.nu2) + 2) {
+    case 6:
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_postpre<T, 6>), grid, dim3(QT<T, 6>::NT), 0, s,
+                         a);
+      break;
+    case 8:
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_postpre<T, 8>), grid, dim3(QT<T, 8>::NT), 0, s,
+                         a);
+      break;
+    case 10:
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_postpre<T, 10>), grid, dim3(QT<T, 10>::NT), 0, s,
+                         a);
+      break;
+    default:
+      return fail(p, CLM_EUNSUPPORTED, "fused smoothing needs nu_pre + nu_post <= 4");
+  }
   CLM_LAUNCH_CHECK();
   return CLM_OK;
 }
@@ -1314,6 +1409,13 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     return CLM_OK;
   };
   bool all_done = false;
+  // With a fixed cycle count the finest level's post-smoothing of a cycle
+  // and the pre-smoothing of the next run as one kernel; the pre-smoothed
+  // iterate then alternates between du and dt, starting so that the last
+  // cycle's post-smoothing reads dt and writes du.
+  const bool fuse = !eps_mode && K >= 1 && d.nu_pre + d.nu_post <= 4 && sizeof(T) == 4;
+  T* cur = fuse && ((ncyc - 1) & 1) ? du : dt;  // pre-smoothed finest iterate
+  bool have_pre = false;                        // formed by the fused kernel
   for (int cyc = 0; cyc < ncyc; ++cyc) {
     const bool first = cyc == 0;
     if (eps_mode && !first) {
@@ -1343,11 +1445,12 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     }
     // pre-smoothing, residual and restriction on the tile levels
     for (int l = 0; l < K; ++l) {
+      if (l == 0 && have_pre) continue;
       TileArgs<T> a = tile_args(l, true);
       if (l == 0) {
         a.u_in = first ? nullptr : du;
         a.f_in = fp;
-        a.u_out = dt;
+        a.u_out = cur;
         a.fas_source = 0;
       } else {
         a.u_in = static_cast<T*>(p->ubar[l]);
@@ -1379,10 +1482,31 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       TileArgs<T> a = tile_args(l, false);
       a.uc = static_cast<T*>(l + 1 == K ? p->ulev[K] : p->ulev2[l + 1]);
       a.ubarc = static_cast<T*>(p->ubar[l + 1]);
+      if (l == 0 && fuse && cyc + 1 < ncyc) {
+        // post-smoothing of this cycle + pre-smoothing of the next
+        T* nxt = cur == dt ? du : dt;
+        a.nu = d.nu_post;
+        a.nu2 = d.nu_pre;
+        a.u_in = cur;
+        a.f_in = fp;
+        a.u_out = nxt;
+        a.ubar_out = static_cast<T*>(p->ubar[1]);
+        a.rbar_out = static_cast<T*>(p->rbar[1]);
+        {
+          CLM_TIMED(p, s, "mg_postpre_l0");
+          const clm_status st = launch_postpre<T>(p, a, np, s);
+          if (st != CLM_OK) return st;
+        }
+        cur = nxt;
+        have_pre = true;
+        continue;
+      }
       if (l == 0) {
+        if (cur != dt) return fail(p, CLM_EHIP, "multigrid buffer order");
         a.u_in = dt;
         a.f_in = fp;
         a.u_out = du;
+        have_pre = false;
       } else {
         a.u_in = static_cast<T*>(p->ulev[l]);
         a.f_in = static_cast<T*>(p->flev[l]);

@@ -22,6 +22,9 @@ def test_bytes_model_mg_level0():
     cells = 12288 * 256 * 256
     assert bench.bytes_model("mg_post_l0", 256, 12288, 12 * 2048 ** 2, 4) == cells * 14
     assert bench.bytes_model("mg_pre_l0", 256, 12288, 12 * 2048 ** 2, 4) == cells * 13
+    # fused smoothing: the finest pre-smoothing runs in the first cycle only
+    assert bench.bytes_model("mg_pre_l0", 256, 12288, 12 * 2048 ** 2, 4, 1.0) == cells * 10
+    assert bench.bytes_model("mg_postpre_l0", 256, 12288, 12 * 2048 ** 2, 4, 3.0) == cells * 16
     assert bench.bytes_model("unknown", 256, 12288, 1, 4) is None
 
 
