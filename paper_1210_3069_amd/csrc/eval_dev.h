@@ -72,9 +72,11 @@ __device__ __forceinline__ Stencil d2_stencil(int c, int n) {
   return s;
 }
 
-// Raw partials at cell (i, j) with the general (edge-aware) stencils.
+// Stencil sums of the raw partials at cell (i, j) with the general
+// (edge-aware) stencils: 12 h psi_t', 12 h psi_p', 12 h^2 psi_t't',
+// 12 h^2 psi_p'p', 144 h^2 psi_t'p'.
 template <typename T>
-__device__ void partials_general(const double* u0, const T* du, int n, int i, int j, double h,
+__device__ void partials_general(const double* u0, const T* du, int n, int i, int j,
                                  double out[5]) {
   const Stencil a1 = d1_stencil(i, n), b1 = d1_stencil(j, n);
   const Stencil a2 = d2_stencil(i, n), b2 = d2_stencil(j, n);
@@ -90,11 +92,11 @@ __device__ void partials_general(const double* u0, const T* du, int n, int i, in
       row += b1.w[q] * patch_u(u0, du, n, i + a1.first + k, j + b1.first + q);
     ptp += a1.w[k] * row;
   }
-  out[0] = pt / (12 * h);
-  out[1] = pp / (12 * h);
-  out[2] = ptt / (12 * h * h);
-  out[3] = ppp / (12 * h * h);
-  out[4] = ptp / (144 * h * h);
+  out[0] = pt;
+  out[1] = pp;
+  out[2] = ptt;
+  out[3] = ppp;
+  out[4] = ptp;
 }
 
 // g = (g_t, g_p), U = (U_tt, U_pp, U_tp) of psi at unit vector v in patch b,
@@ -111,9 +113,9 @@ __device__ bool eval_patch(const PatchField& P, int64_t b, double vx, double vy,
   const double thp = atan2(sp_, pz);
   const double php = atan2(py, px);
   const int n = P.n;
-  const double h = P.delta;
-  const double fi = (thp - (pi / 2 - P.L / 2)) / h - 0.5;
-  const double fj = (php + P.L / 2) / h - 0.5;
+  const double ih = 1.0 / P.delta;
+  const double fi = (thp - (pi / 2 - P.L / 2)) * ih - 0.5;
+  const double fj = (php + P.L / 2) * ih - 0.5;
   const double ffi = floor(fi), ffj = floor(fj);
   if (!(ffi >= 0 && ffi <= n - 2 && ffj >= 0 && ffj <= n - 2)) return false;
   const int i0 = int(ffi), j0 = int(ffj);
@@ -150,29 +152,33 @@ __device__ bool eval_patch(const PatchField& P, int64_t b, double vx, double vy,
         for (int q = 0; q < 4; ++q) row += c1[q] * w[r + o1[a]][c + o1[q]];
         ptp += c1[a] * row;
       }
-      Pc[k][0] = pt / (12 * h);
-      Pc[k][1] = pp / (12 * h);
-      Pc[k][2] = ptt / (12 * h * h);
-      Pc[k][3] = ppp / (12 * h * h);
-      Pc[k][4] = ptp / (144 * h * h);
+      // stencil sums; the 1/(12 h), 1/(12 h^2), 1/(144 h^2) factors are
+      // applied once after the interpolation (it is linear)
+      Pc[k][0] = pt;
+      Pc[k][1] = pp;
+      Pc[k][2] = ptt;
+      Pc[k][3] = ppp;
+      Pc[k][4] = ptp;
     }
   } else {
     for (int k = 0; k < 4; ++k)
-      partials_general<T>(u0, du, n, i0 + (k >> 1), j0 + (k & 1), h, Pc[k]);
+      partials_general<T>(u0, du, n, i0 + (k >> 1), j0 + (k & 1), Pc[k]);
   }
+  const double i1 = ih / 12, i2 = ih * ih / 12;
+  const double sc[5] = {i1, i1, i2, i2, i2 / 12};
   double Pv[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q)
-    Pv[q] = (1 - t) * (1 - s) * Pc[0][q] + (1 - t) * s * Pc[1][q] + t * (1 - s) * Pc[2][q] +
-            t * s * Pc[3][q];
+    Pv[q] = ((1 - t) * (1 - s) * Pc[0][q] + (1 - t) * s * Pc[1][q] + t * (1 - s) * Pc[2][q] +
+             t * s * Pc[3][q]) * sc[q];
   // covariant components in the patch frame at the point (App. A)
-  const double st = sp_, ct = pz;
-  const double gpt = Pv[0], gpp = Pv[1] / st;
+  const double st = sp_, ct = pz, ist = 1.0 / st;
+  const double gpt = Pv[0], gpp = Pv[1] * ist;
   const double Utt = Pv[2];
-  const double Upp = Pv[3] / (st * st) + (ct / st) * Pv[0];
-  const double Utp = Pv[4] / st - ct * Pv[1] / (st * st);
+  const double Upp = Pv[3] * ist * ist + (ct * ist) * Pv[0];
+  const double Utp = Pv[4] * ist - ct * Pv[1] * ist * ist;
   // patch basis at the point, in global coordinates: R^T (theta'-hat, phi'-hat)
-  const double cpp = px / st, spp = py / st;
+  const double cpp = px * ist, spp = py * ist;
   const double et_p[3] = {ct * cpp, ct * spp, -st};
   const double ep_p[3] = {-spp, cpp, 0.0};
   double etp[3], epp[3];
@@ -182,8 +188,8 @@ __device__ bool eval_patch(const PatchField& P, int64_t b, double vx, double vy,
     epp[k] = R[k] * ep_p[0] + R[3 + k] * ep_p[1] + R[6 + k] * ep_p[2];
   }
   // global basis at the point
-  const double sg = sqrt(vx * vx + vy * vy);
-  const double cph = vx / sg, sph = vy / sg;
+  const double sg = sqrt(vx * vx + vy * vy), isg = 1.0 / sg;
+  const double cph = vx * isg, sph = vy * isg;
   const double et[3] = {vz * cph, vz * sph, -sg};
   const double ep[3] = {-sph, cph, 0.0};
   const double q00 = et[0] * etp[0] + et[1] * etp[1] + et[2] * etp[2];
