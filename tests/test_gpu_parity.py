@@ -186,7 +186,8 @@ def test_sht_matrix_core_large_against_fp64(clm, N):
 
 
 # ---------------------------------------------------------------- SHT + MG
-MG_BUNDLES = [0, 37, 100, 191]
+# 15 and 128 hold the north and south poles (their patches contain them)
+MG_BUNDLES = [0, 15, 37, 100, 128, 191]
 
 
 @pytest.fixture(scope="module")
@@ -284,6 +285,48 @@ def test_mg_eps_rule_not_converged_and_fixed_count(clm, mg_case):
     plan.sync_status()
     e_gpu, k_gpu = (t.cpu().numpy() for t in plan.mg_convergence())
     assert np.all(k_gpu == 3) and np.all(np.isnan(e_gpu))
+    plan.close()
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_mg_smallest_patches(clm, mg_case, n):
+    """The smallest patches (8^2 and 16^2: two and three levels, all in LDS)
+    against the oracle, polar bundles included."""
+    c = mg_case
+    spec = omg.PatchSpec(c["Nf"], c["Ns"], c["lmax"], c["Nb"], ncell=n, vcycles=3)
+    sol = omg.solve_plane(spec, c["kap"], MG_BUNDLES)
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=n, mg_vcycles=3, mg_prec="fp64")
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    for b in MG_BUNDLES:
+        pt = sol["patches"][b]
+        got = plan.patch_potential(b, 1)[0].cpu().numpy()
+        assert report("mg_small n=%d b=%d" % (n, b), rel(got, (pt["u0"] + pt["du"])[1:-1, 1:-1])) < 1e-10
+    plan.sync_status()
+    plan.close()
+
+
+def test_degenerate_inputs(clm):
+    """A constant convergence has no potential and no shear: the SHT side is
+    exactly zero (the monopole is removed exactly), the patch side is zero
+    up to the rounding of the interpolation weights' sum; empty point and
+    galaxy sets are valid no-ops."""
+    N = 64
+    plan = clm.Plan(N, nside_sht=16, lmax=32, nside_bundle=4, patch_cells=64, mg_vcycles=2)
+    k = torch.full((12 * N * N,), 0.37, dtype=torch.float32, device="cuda")
+    plan.poisson_solve(k)
+    assert torch.count_nonzero(plan.psi_alm()).item() == 0
+    assert torch.count_nonzero(plan.psi_map()).item() == 0
+    assert plan.patch_potential(0, 192).abs().max().item() < 1e-15
+    g, h = plan.shear_at_pixels(order="ring")
+    assert g.abs().max().item() < 1e-10 and h.abs().max().item() < 1e-10
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    g0, h0 = plan.shear_from_potential(e, e)
+    assert g0.shape == (2, 0) and h0.shape == (3, 0)
+    rays = plan.new_rays()
+    gal = dict(theta=e, phi=e, chi=e, A=torch.empty(4, 0, dtype=torch.float32, device="cuda"))
+    plan.galaxies_shell(np.array([100.0, 200.0]), 0, rays, gal)
+    plan.sync_status()
     plan.close()
 
 
