@@ -82,7 +82,7 @@ typedef enum { CLM_ORDER_RING = 0, CLM_ORDER_NESTED = 1 } clm_order;
 typedef struct {
   int32_t nside_fine;    /* power of two >= 1: ray / output grid               */
   int32_t nside_sht;     /* power of two, <= nside_fine (SHT solver: == fine)  */
-  int32_t lmax;          /* >= 1; default 2 * nside_sht                        */
+  int32_t lmax;          /* 1 .. 2^20; default 2 * nside_sht                   */
   int32_t nside_bundle;  /* power of two, <= nside_fine                        */
   int32_t patch_factor;  /* patch side / bundle side (Sec. 3.2: 4)             */
   int32_t patch_cells;   /* finest cells per side: power of two, 8..4096       */

@@ -355,7 +355,7 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
   if (!desc) return CLM_EINVAL;
   const clm_plan_desc& d = *desc;
   if (!pow2(d.nside_fine) || !pow2(d.nside_sht) || d.nside_sht > d.nside_fine ||
-      d.nside_fine > 8192 || d.lmax < 1 || d.max_planes < 1 ||
+      d.nside_fine > 8192 || d.lmax < 1 || d.lmax > (1 << 20) || d.max_planes < 1 ||
       (d.solver != CLM_SOLVER_SHT && d.solver != CLM_SOLVER_SHT_MG) ||
       (d.legendre_prec != CLM_FP64 && d.legendre_prec != CLM_FP32 &&
        d.legendre_prec != CLM_BF16X3) || (d.adjoint != 0 && d.adjoint != 1) ||

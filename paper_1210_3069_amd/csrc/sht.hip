@@ -75,8 +75,31 @@ __global__ void k_degrade(const T* kap, int64_t Nf, int64_t npix_s, const int* r
 // Every HEALPix ring has n = 4k samples, so the twiddles e^{2 pi i t / n}
 // come from a quarter-wave sine table s[r] = sin(2 pi r / n), r = 0..n/4,
 // held in LDS: (n/4 + 1) doubles per ring.
+// Quadrant q = t / Q and remainder r of 0 <= t < 4 Q, by comparisons.
+__device__ __forceinline__ void quadrant(int t, int Q, int& q, int& r) {
+  q = 0;
+  r = t;
+  if (r >= Q) { r -= Q; ++q; }
+  if (r >= Q) { r -= Q; ++q; }
+  if (r >= Q) { r -= Q; ++q; }
+}
+
+// a / d for 0 <= a < 2^22 and d >= 1: the float quotient is within one of
+// the true one, and one comparison each way settles it.
+__device__ __forceinline__ int div_small(int a, int d, float inv_d) {
+  int q = int(float(a) * inv_d);
+  const int r = a - q * d;
+  if (r < 0)
+    --q;
+  else if (r >= d)
+    ++q;
+  return q;
+}
+
+// e^{2 pi i t / n}, 0 <= t < n = 4 Q, from the quarter-wave table.
 __device__ __forceinline__ void twiddle(const double* sq, int Q, int t, double& c, double& s) {
-  const int q = t / Q, r = t - q * Q;
+  int q, r;
+  quadrant(t, Q, q, r);
   const double sr = sq[r], cr = sq[Q - r];
   switch (q) {
     case 0: c = cr; s = sr; break;
@@ -113,11 +136,13 @@ __device__ void dft_mixed(const double* in, double* out, int h, int lg, int r, c
                           int n, int sign) {
   const int Q = n / 4;
   const int nr = n / r;  // table step of e^{2 pi i / r}
+  const float inv_r = 1.0f / float(r);
   for (int item = threadIdx.x; item < h; item += blockDim.x) {
-    const int bb = item / r, k = item - bb * r;
+    const int bb = div_small(item, r, inv_r), k = item - bb * r;
     const int b = bitrev(bb, lg);
-    const int inc = int((int64_t(k) * nr) % n);
-    const int iq = inc / Q, ir = inc - iq * Q;
+    const int inc = k * nr;  // < n
+    int iq, ir;
+    quadrant(inc, Q, iq, ir);
     int q = 0, rem = 0;
     double ar = 0.0, ai = 0.0;
     for (int t = 0; t < r; ++t) {
@@ -143,8 +168,9 @@ __device__ void dft_mixed(const double* in, double* out, int h, int lg, int r, c
   __syncthreads();
   for (int half = r; half < h; half <<= 1) {
     const int L = 2 * half, step = n / L;
+    const float inv_half = 1.0f / float(half);
     for (int item = threadIdx.x; item < h / 2; item += blockDim.x) {
-      const int blk = item / half, kk = item - blk * half;
+      const int blk = div_small(item, half, inv_half), kk = item - blk * half;
       const int i0 = blk * L + kk, i1 = i0 + half;
       double c, s;
       unit(sq, Q, kk * step, sign, c, s);
@@ -239,10 +265,15 @@ __device__ void fft_dit_inv(double* A, int lgM, const double* sq) {
   }
 }
 
-// Chirp w_k = e^{-i pi k^2 / h} = c - i s, k^2 reduced modulo 2h exactly.
+// Chirp w_k = e^{-i pi k^2 / h} = c - i s, k^2 reduced modulo 2h exactly
+// (k^2 < 2^53: the floating-point quotient is off by at most one, fixed by
+// one comparison each way).
 __device__ __forceinline__ void chirp(int k, int h, double& c, double& s) {
-  const int64_t q = (int64_t(k) * k) % (2 * int64_t(h));
-  sincospi(double(q) / double(h), &s, &c);
+  const double k2 = double(k) * double(k), d = 2.0 * double(h);
+  double q = k2 - d * floor(k2 * (1.0 / d));
+  if (q < 0.0) q += d;
+  if (q >= d) q -= d;
+  sincospi(q * (1.0 / double(h)), &s, &c);
 }
 
 // A holds a_k = z_k w_k (k < h) and zeros up to M: on return A_k holds M times
@@ -354,18 +385,19 @@ __global__ __launch_bounds__(kRingBlock) void k_ring_forward(const double* map, 
     __syncthreads();
     Z = A;
   }
+  const float inv_n = 1.0f / float(n);
   for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
-    const int k = m % n;
+    const int k = m - n * div_small(m, n, inv_n);  // m mod n
     const bool up = k > n / 2;
-    const int kk = up ? n - k : k;       // X_k = conj X_{n-k}
-    const int k1 = kk % h, k2 = (h - kk) % h;
+    const int kk = up ? n - k : k;       // X_k = conj X_{n-k}, kk <= h
+    const int k1 = kk == h ? 0 : kk, k2 = kk == 0 ? 0 : h - kk;
     const double zr = Z[2 * k1], zi = Z[2 * k1 + 1];
     const double wr = Z[2 * k2], wi = -Z[2 * k2 + 1];  // conj Z_{h-k}
     const double er = 0.5 * (zr + wr), ei = 0.5 * (zi + wi);
     const double dr = zr - wr, di = zi - wi;
     const double orr = 0.5 * di, oi = -0.5 * dr;       // (Z - conj) / 2i
     double c, s;
-    ring_unit(sq, n, kk % n, -1, c, s);
+    ring_unit(sq, n, kk, -1, c, s);
     double xr = er + c * orr - s * oi, xi = ei + c * oi + s * orr;
     if (up) xi = -xi;
     double sp, cp;

@@ -45,7 +45,7 @@ def test_default_description(L):
 @pytest.mark.parametrize("fields", [
     dict(nside_fine=100), dict(nside_sht=4096), dict(patch_cells=96), dict(nu_pre=0),
     dict(mg_vcycles=-1), dict(max_planes=0), dict(solver=7), dict(mg_prec=9),
-    dict(nside_bundle=1), dict(legendre_prec=3), dict(legendre_prec=-1),
+    dict(nside_bundle=1), dict(legendre_prec=3), dict(legendre_prec=-1), dict(lmax=(1 << 20) + 1),
     # the epsilon rule needs a positive threshold and cycle limit, and the
     # adjoint a fixed cycle count
     dict(mg_vcycles=0, mg_eps=0.0), dict(mg_vcycles=0, mg_max_vcycles=0),
