@@ -334,14 +334,23 @@ struct TileArgs {
   const int* done;      // epsilon rule: patches that stopped (nullptr: none)
 };
 
-// Threads per tile workgroup: the widest halos (fused smoothing) take 1024 so
-// that a thread keeps no more than two quads in registers.
+// Quads per region side, threads per workgroup and threads per quad row.
+// The widest halos (fused smoothing) take 1024 threads with TPR = 2 S mod 64,
+// S = Q + 2 the LDS row stride: a wave's quad rows, 2 S floats apart, then
+// land on successive banks of the 64-bank LDS (no bank conflicts in the
+// sweeps).  The others take 512 threads and the fewest quads per thread,
+// which measured faster than the conflict-free mapping on 1024 threads.
+constexpr int tile_q(int hh) { return (kTile + 2 * hh) / 2; }
 constexpr int tile_threads(int hh) { return hh >= 10 ? 2 * kTileBlock : kTileBlock; }
-
 constexpr int quads_per_thread(int q, int nt) {
   int it = 1;
   while (q * ((q + it - 1) / it) > nt) ++it;
   return it;
+}
+constexpr int tile_tpr(int hh) {
+  return hh >= 10 ? (2 * (tile_q(hh) + 2)) % 64
+                  : (tile_q(hh) + quads_per_thread(tile_q(hh), kTileBlock) - 1) /
+                        quads_per_thread(tile_q(hh), kTileBlock);
 }
 
 template <typename T, int HH>
@@ -350,8 +359,9 @@ struct QT {
   static constexpr int RR = kTile + 2 * HH;    // region side
   static constexpr int Q = RR / 2;             // quads per side
   static constexpr int NT = tile_threads(HH);
-  static constexpr int IT = quads_per_thread(Q, NT);
-  static constexpr int TPR = (Q + IT - 1) / IT;  // threads per quad row
+  static constexpr int TPR = tile_tpr(HH);       // threads per quad row
+  static constexpr int IT = (Q + TPR - 1) / TPR; // quads per thread
+  static_assert(TPR >= 8 && Q * TPR <= NT, "quad rows must fit the workgroup");
   static constexpr int QH = HH / 2;            // first interior quad
   static constexpr int S = Q + 2;              // parity-array row stride (guard columns)
   static constexpr int PAR = (RR + 2) * S;     // cells per parity array (guard rows)
