@@ -283,7 +283,9 @@ struct SetupTArgs {
   int64_t np;
   double L, delta;
   hpx::Rings rs, rf;
-  double* psibar;       // SHT RING map
+  double* psibar;       // SHT RING maps: ncopy private copies of npix_s each
+  int64_t npix_s;
+  int ncopy;
   double* kbar;         // fine RING map
 };
 
@@ -349,8 +351,19 @@ __global__ void k_adj_setup_cells(SetupTArgs a) {
   const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
   double z, rho, ph;
   patch_point(R, th0 + (i + 0.5) * a.delta, ph0 + (j + 0.5) * a.delta, z, rho, ph);
-  scatter(a.rs, a.psibar, z, rho, ph, v);
+  // each block adds into its own copy of the small SHT-grid map: millions of
+  // cells map to each SHT pixel, and one shared map serialises the atomics
+  scatter(a.rs, a.psibar + (blockIdx.x % a.ncopy) * a.npix_s, z, rho, ph, v);
   scatter(a.rf, a.kbar, z, rho, ph, 2.0 * fb[c]);
+}
+
+// out[p] = sum of the ncopy private copies at p.
+__global__ void k_sum_copies(int ncopy, int64_t n, const double* in, double* out) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double v = 0.0;
+  for (int k = 0; k < ncopy; ++k) v += in[k * n + t];
+  out[t] = v;
 }
 
 // Ghost cells: u0_g = 2 b - u0(adjacent), b = interp(psi) on the face
@@ -376,7 +389,7 @@ __global__ void k_adj_setup_ghosts(SetupTArgs a) {
   const double php = gj < 0 ? ph0 : gj == n ? ph0 + a.L : ph0 + (gj + 0.5) * a.delta;
   double z, rho, ph;
   patch_point(a.rot + 9 * b, thp, php, z, rho, ph);
-  scatter(a.rs, a.psibar, z, rho, ph, 2.0 * v);
+  scatter(a.rs, a.psibar + (blockIdx.x % a.ncopy) * a.npix_s, z, rho, ph, 2.0 * v);
 }
 
 // -------------------------------------------------------- degrade^T, demean^T
@@ -514,8 +527,9 @@ clm_status poisson_adjoint(Plan* p, double* dkappa, hipStream_t s) {
     for (int cyc = 0; cyc < p->d.mg_vcycles; ++cyc)
       if ((st = vcycle_T(p, 0, s)) != CLM_OK) return st;
   }
-  // setup^T into the SHT-grid and fine maps
-  hipLaunchKernelGGL(k_fill, grid_for(p->npix_s), dim3(kBlk), 0, s, p->npix_s, 0.0, p->adj_psi);
+  // setup^T into the SHT-grid (private copies) and fine maps
+  const int64_t npriv = int64_t(p->adj_ncopy) * p->npix_s;
+  hipLaunchKernelGGL(k_fill, grid_for(npriv), dim3(kBlk), 0, s, npriv, 0.0, p->adj_psi_priv);
   CLM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_fill, grid_for(p->npix_f), dim3(kBlk), 0, s, p->npix_f, 0.0, dkappa);
   CLM_LAUNCH_CHECK();
@@ -529,12 +543,16 @@ clm_status poisson_adjoint(Plan* p, double* dkappa, hipStream_t s) {
   a.delta = p->delta;
   a.rs = hpx::Rings{p->ring_s, p->ringi_s, p->ringx_s, p->nring_s, p->d.nside_sht};
   a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->ringx_f, p->nring_f, p->d.nside_fine};
-  a.psibar = p->adj_psi;
+  a.psibar = p->adj_psi_priv;
+  a.npix_s = p->npix_s;
+  a.ncopy = p->adj_ncopy;
   a.kbar = dkappa;
   {
     CLM_TIMED(p, s, "adj_setup");
     hipLaunchKernelGGL(k_adj_setup_cells, grid_for(cells), dim3(kBlk), 0, s, a);
     hipLaunchKernelGGL(k_adj_setup_ghosts, grid_for(np * (4 * n + 4)), dim3(kBlk), 0, s, a);
+    hipLaunchKernelGGL(k_sum_copies, grid_for(p->npix_s), dim3(kBlk), 0, s, p->adj_ncopy,
+                       p->npix_s, static_cast<const double*>(p->adj_psi_priv), p->adj_psi);
   }
   CLM_LAUNCH_CHECK();
   // SHT^T: psi_SHT bar -> kappa_SHT bar

@@ -101,6 +101,8 @@ struct Plan {
   double* adj_ubar = nullptr;
   std::vector<double*> adj_u, adj_v, adj_f, adj_w;
   double* adj_psi = nullptr;    // [npix_s] psi_SHT bar
+  double* adj_psi_priv = nullptr;  // [adj_ncopy][npix_s] per-block copies of psi_SHT bar
+  int adj_ncopy = 1;
   double* adj_ks = nullptr;     // [npix_s] kappa_SHT bar
   double* adj_alm = nullptr;    // [nalm] complex
 
