@@ -28,14 +28,17 @@ constexpr double kPi = 3.14159265358979323846;
 
 inline dim3 grid_for(int64_t n) { return dim3(unsigned((n + kBlk - 1) / kBlk)); }
 
-// Row coefficients of a level: s_m, s_p, s_c, area per row.
+// Row coefficients of a level: s_m, s_p, s_c, area per row (c), and the
+// reciprocals 1 / s_c, 1 / area (q), so that no kernel divides per cell.
 struct Rows {
   const double* c;
+  const double* q;
   int n;
   __device__ double sm(int i) const { return c[4 * i]; }
   __device__ double sp(int i) const { return c[4 * i + 1]; }
-  __device__ double isc(int i) const { return 1.0 / c[4 * i + 2]; }
+  __device__ double isc(int i) const { return q[4 * i]; }
   __device__ double A(int i) const { return c[4 * i + 3]; }
+  __device__ double rA(int i) const { return q[4 * i + 1]; }
   // full diagonal: a neighbour across the patch face is the ghost -u
   __device__ double D(int i, int j) const {
     double d = sm(i) + sp(i) + 2.0 * isc(i);
@@ -174,28 +177,230 @@ __global__ void k_adj_split(const double* ubar, int n, int64_t np, double* dub) 
 }
 
 // -------------------------------------------------------- multigrid^T
-// Transposed red-black half sweep of colour col on a level:
-//   out = in with colour-col cells zeroed, plus for every other cell the
-//   coefficients its colour-col neighbours give it times in/D there;
-//   fbar -= A in / D on colour-col cells.
-__global__ void k_hs_T(Rows r, int64_t np, int col, const double* in, double* out,
-                       double* fbar) {
-  const int n = r.n;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= np * n * n) return;
-  const int c = int(t % (int64_t(n) * n)), i = c / n, j = c % n;
-  const double* x = in + (t - c);
-  if (((i + j) & 1) == col) {
-    out[t] = 0.0;
-    fbar[t] -= r.A(i) * x[c] / r.D(i, j);
-    return;
+// Transposed red-black smoothing.  One half sweep of colour c maps (x, fbar)
+// to (y, fbar'):
+//   colour-c cells:     y = 0, fbar -= A x / D;
+//   other cells:        y = x + sum over their colour-c neighbours q of
+//                       (q's stencil coefficient towards the cell) x_q / D_q.
+// A launch runs S successive half sweeps on a tile of TT^2 cells held in LDS
+// with a halo of S cells.  Every half sweep updates the same set of cells
+// (rows 1 .. W-2 of the W^2 LDS region); the cells near the region's edge
+// that lose their inputs hold garbage, which moves inwards one cell per half
+// sweep and never reaches the tile.  Cells are kept in LDS scaled by 1 / D
+// while they are read as colour-c cells, so an update reads its neighbours
+// as they are.  The cells of a row are taken in pairs (2q, 2q + 1): a pair
+// holds one cell of each colour, and one thread owns it in every half
+// sweep, accumulating the pair's f bar in registers.
+//
+// The launch that starts the transposed pre-smoothing first applies, on
+// every loaded cell, the transpose of the coarse-grid correction of the
+// forward cycle (area-weighted restriction R and level operator L0):
+//   v = R^T fbar_H,  u += R^T e - L0^T v,  fbar += v.
+template <int TT, int S, int NT>
+struct SmGeom {
+  static constexpr int W = TT + 2 * S;          // LDS side
+  static constexpr int HP = W / 2;              // column pairs per row
+  static constexpr int NPair = (W - 2) * HP;    // pairs of rows 1 .. W-2
+  static constexpr int P = (NPair + NT - 1) / NT;   // pairs per thread
+  static constexpr int Ld = (W * W + NT - 1) / NT;  // loads per thread
+  static constexpr int R = W + 2;               // row-table rows (one more each side)
+  static constexpr int C = TT / 2 + S + 2;      // coarse rows / columns under a tile
+  // dynamic LDS: tile, row table (8 per row), coarse e and fbar_H
+  static constexpr size_t Lds = 8 * (size_t(W) * W + 8 * R + 2 * C * C);
+  static_assert(S % 2 == 0 && S >= 2, "half sweeps come in whole sweeps");
+};
+
+struct SmoothTArgs {
+  Rows r;             // this level
+  int tiles;          // tiles per patch side
+  int c0;             // colour of the first half sweep
+  int remap;          // XCD-contiguous block order
+  const double* in;   // [np][n][n] u bar
+  double* out;        // [np][n][n]
+  double* fbar;       // [np][n][n], updated in place
+  const double* e;    // coarse u-bar correction [np][n/2][n/2], or null
+  const double* fH;   // coarse f bar [np][n/2][n/2] (with e)
+};
+
+template <int TT, int S, int NT>
+__global__ __launch_bounds__(NT) void k_smooth_T(SmoothTArgs a) {
+  using G = SmGeom<TT, S, NT>;
+  constexpr int W = G::W, HP = G::HP, RR = G::R, CC = G::C;
+  extern __shared__ double sm_[];
+  double* X = sm_;                 // [W][W]
+  // per row: s_m, s_p, 1/s_c, area, 1/area, R^T weight, and 1/D for the
+  // interior columns and for the two face columns (levels have n >= 8);
+  // zero on rows outside the patch
+  double* RT = X + W * W;          // [8][RR]
+  double* CE = RT + 8 * RR;        // [CC][CC] coarse e
+  double* CF = CE + CC * CC;       // [CC][CC] coarse fbar_H
+  const int n = a.r.n, tid = threadIdx.x;
+  // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+  // range of tiles so that neighbouring tiles share its L2 for their halos.
+  int64_t bid = blockIdx.x;
+  if (a.remap) {
+    const int64_t per = gridDim.x / 8;
+    bid = (bid & 7) * per + (bid >> 3);
   }
-  double v = x[c];
-  if (i > 0) v += r.sp(i - 1) * x[c - n] / r.D(i - 1, j);
-  if (i < n - 1) v += r.sm(i + 1) * x[c + n] / r.D(i + 1, j);
-  if (j > 0) v += r.isc(i) * x[c - 1] / r.D(i, j - 1);
-  if (j < n - 1) v += r.isc(i) * x[c + 1] / r.D(i, j + 1);
-  out[t] = v;
+  const int t2 = a.tiles * a.tiles;
+  const int64_t b = bid / t2;
+  const int tt = int(bid - b * t2);
+  const int i0 = (tt / a.tiles) * TT, j0 = (tt % a.tiles) * TT;
+  const size_t base = size_t(b) * n * n;
+  auto inside = [&](int i, int j) { return unsigned(i) < unsigned(n) && unsigned(j) < unsigned(n); };
+  // pair m of this thread: LDS row r (1 .. W-2), first column 2q
+  auto pair_rq = [&](int m, int& r, int& q) {
+    const int k = tid + m * NT;
+    r = 1 + k / HP;
+    q = k - (r - 1) * HP;
+    return k < G::NPair;
+  };
+  auto in_tile = [&](int r, int q) { return r >= S && r < S + TT && 2 * q >= S && 2 * q < S + TT; };
+  // all global loads first: u bar on the tile and its halo (0 outside the
+  // patch), f bar of the pairs of the tile this thread owns
+  double xv[G::Ld];
+#pragma unroll
+  for (int m = 0; m < G::Ld; ++m) {
+    const int idx = tid + m * NT;
+    const int ri = idx / W, rj = idx - ri * W;
+    const int i = i0 + ri - S, j = j0 + rj - S;
+    xv[m] = idx < W * W && inside(i, j) ? a.in[base + size_t(i) * n + j] : 0.0;
+  }
+  double2 fb[G::P];
+#pragma unroll
+  for (int m = 0; m < G::P; ++m) {
+    int r, q;
+    const bool ok = pair_rq(m, r, q) && in_tile(r, q);
+    fb[m] = ok ? *reinterpret_cast<const double2*>(a.fbar + base + size_t(i0 + r - S) * n +
+                                                   j0 + 2 * q - S)
+               : make_double2(0.0, 0.0);
+  }
+  for (int k = tid; k < RR; k += NT) {
+    const int i = i0 - S - 1 + k;
+    const bool ok = i >= 0 && i < n;
+    const double d = ok ? a.r.D(i, 1) : 1.0;  // row faces included, no column face
+    const int I2 = i & ~1;
+    RT[0 * RR + k] = ok ? a.r.sm(i) : 0.0;
+    RT[1 * RR + k] = ok ? a.r.sp(i) : 0.0;
+    RT[2 * RR + k] = ok ? a.r.isc(i) : 0.0;
+    RT[3 * RR + k] = ok ? a.r.A(i) : 0.0;
+    RT[4 * RR + k] = ok ? a.r.rA(i) : 0.0;
+    RT[5 * RR + k] = ok ? a.r.A(i) / (2.0 * (a.r.A(I2) + a.r.A(I2 + 1))) : 0.0;
+    RT[6 * RR + k] = ok ? 1.0 / d : 0.0;
+    RT[7 * RR + k] = ok ? 1.0 / (d + a.r.isc(i)) : 0.0;
+  }
+  // coarse tiles under rows / columns i0 - S - 1 .. i0 + TT + S
+  const int nc = n >> 1;
+  constexpr int CW = ((TT + S) >> 1) + ((S + 2) >> 1) + 1;
+  static_assert(CW <= CC, "coarse tile");
+  const int cI0 = (i0 >> 1) - ((S + 2) >> 1), cJ0 = (j0 >> 1) - ((S + 2) >> 1);
+  if (a.e) {
+    const size_t cb = size_t(b) * nc * nc;
+    for (int idx = tid; idx < CW * CW; idx += NT) {
+      const int ci = idx / CW, cj = idx - ci * CW;
+      const int I = cI0 + ci, J = cJ0 + cj;
+      if (I < 0 || I >= nc || J < 0 || J >= nc) continue;
+      CE[ci * CC + cj] = a.e[cb + size_t(I) * nc + J];
+      CF[ci * CC + cj] = a.fH[cb + size_t(I) * nc + J];
+    }
+  }
+  __syncthreads();
+  // row-table entry t of global row i
+  auto rt = [&](int t, int i) { return RT[t * RR + i - (i0 - S - 1)]; };
+  // 1 / full diagonal at (i, j)
+  auto diag = [&](int i, int j) { return rt(j == 0 || j == n - 1 ? 7 : 6, i); };
+  // coarse value of the cell (i, j)
+  auto cv = [&](const double* Cm, int i, int j) {
+    return Cm[((i >> 1) - cI0) * CC + (j >> 1) - cJ0];
+  };
+  // R^T fbar_H at a cell of the patch
+  auto vv = [&](int i, int j) { return rt(5, i) * cv(CF, i, j); };
+#pragma unroll
+  for (int m = 0; m < G::Ld; ++m) {
+    const int idx = tid + m * NT;
+    if (idx >= W * W) continue;
+    const int ri = idx / W, rj = idx - ri * W;
+    const int i = i0 + ri - S, j = j0 + rj - S;
+    double x = xv[m];
+    if (inside(i, j)) {
+      if (a.e) {
+        // u += R^T e - L0^T v at (i, j); full diagonal D (faces: ghost = -u)
+        const double ra = rt(4, i), is = rt(2, i);
+        double d = rt(0, i) + rt(1, i) + 2.0 * is;
+        if (i == 0) d += rt(0, i);
+        if (i == n - 1) d += rt(1, i);
+        if (j == 0) d += is;
+        if (j == n - 1) d += is;
+        double l0 = -d * vv(i, j) * ra;
+        if (i > 0) l0 += rt(1, i - 1) * vv(i - 1, j) * rt(4, i - 1);
+        if (i < n - 1) l0 += rt(0, i + 1) * vv(i + 1, j) * rt(4, i + 1);
+        if (j > 0) l0 += is * vv(i, j - 1) * ra;
+        if (j < n - 1) l0 += is * vv(i, j + 1) * ra;
+        x += rt(5, i) * cv(CE, i, j) - l0;
+      }
+      // the first half sweep reads its colour-c0 cells scaled by 1 / D
+      if (((ri + rj) & 1) == a.c0) x *= diag(i, j);
+    }
+    X[idx] = x;
+  }
+  if (a.e) {
+#pragma unroll
+    for (int m = 0; m < G::P; ++m) {
+      int r, q;
+      if (!pair_rq(m, r, q) || !in_tile(r, q)) continue;
+      const int i = i0 + r - S, j = j0 + 2 * q - S;
+      fb[m].x += vv(i, j);
+      fb[m].y += vv(i, j + 1);
+    }
+  }
+  __syncthreads();
+  double vlast[G::P];
+#pragma unroll
+  for (int h = 0; h < S; ++h) {
+    const int c = a.c0 ^ (h & 1);
+#pragma unroll
+    for (int m = 0; m < G::P; ++m) {
+      int r, q;
+      if (!pair_rq(m, r, q)) continue;
+      const int second = (1 + c + r) & 1;  // the pair's cell not of colour c
+      const int col = 2 * q + second;
+      const int i = i0 + r - S, j = j0 + col - S;
+      if (!inside(i, j)) continue;
+      const int x = r * W + col, k = r + 1;
+      double v = h == 0 ? X[x] : 0.0;
+      v += RT[1 * RR + k - 1] * X[x - W] + RT[0 * RR + k + 1] * X[x + W] +
+           RT[2 * RR + k] * (X[x - 1] + X[x + 1]);
+      const bool tile = in_tile(r, q);
+      const double A = RT[3 * RR + k];
+      double fd = 0.0;
+      // this cell was of colour c0 in the first half sweep
+      if (h == 1) fd -= A * X[x];
+      if (h < S - 1) {
+        const double z = v * diag(i, j);
+        X[x] = z;
+        fd -= A * z;
+      } else {
+        vlast[m] = v;
+      }
+      if (tile) {
+        if (second) fb[m].y += fd;
+        else fb[m].x += fd;
+      }
+    }
+    if (h < S - 1) __syncthreads();
+  }
+  // the last half sweep's colour is zero; the other cells hold its results
+  const int clast = a.c0 ^ ((S - 1) & 1);
+#pragma unroll
+  for (int m = 0; m < G::P; ++m) {
+    int r, q;
+    if (!pair_rq(m, r, q) || !in_tile(r, q)) continue;
+    const size_t g = base + size_t(i0 + r - S) * n + j0 + 2 * q - S;
+    const int second = (1 + clast + r) & 1;
+    *reinterpret_cast<double2*>(a.out + g) =
+        second ? make_double2(0.0, vlast[m]) : make_double2(vlast[m], 0.0);
+    *reinterpret_cast<double2*>(a.fbar + g) = fb[m];
+  }
 }
 
 // y += s L0^T x (L0: the level operator on a correction with zero face
@@ -206,24 +411,12 @@ __global__ void k_L0_T(Rows r, int64_t np, const double* xin, double s, double* 
   if (t >= np * n * n) return;
   const int c = int(t % (int64_t(n) * n)), i = c / n, j = c % n;
   const double* x = xin + (t - c);
-  double v = -r.D(i, j) * x[c] / r.A(i);
-  if (i > 0) v += r.sp(i - 1) * x[c - n] / r.A(i - 1);
-  if (i < n - 1) v += r.sm(i + 1) * x[c + n] / r.A(i + 1);
-  if (j > 0) v += r.isc(i) * x[c - 1] / r.A(i);
-  if (j < n - 1) v += r.isc(i) * x[c + 1] / r.A(i);
+  double v = -r.D(i, j) * x[c] * r.rA(i);
+  if (i > 0) v += r.sp(i - 1) * x[c - n] * r.rA(i - 1);
+  if (i < n - 1) v += r.sm(i + 1) * x[c + n] * r.rA(i + 1);
+  if (j > 0) v += r.isc(i) * x[c - 1] * r.rA(i);
+  if (j < n - 1) v += r.isc(i) * x[c + 1] * r.rA(i);
   y[t] += s * v;
-}
-
-// x_fine += s R^T y_coarse (area-weighted restriction).
-__global__ void k_restrict_T(Rows rf, int64_t np, const double* yc, double s, double* xf) {
-  const int n = rf.n, nc = n / 2;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= np * n * n) return;
-  const int64_t b = t / (int64_t(n) * n);
-  const int c = int(t % (int64_t(n) * n)), i = c / n, j = c % n;
-  const int I = i >> 1, J = j >> 1;
-  const double a0 = rf.A(2 * I), a1 = rf.A(2 * I + 1);
-  xf[t] += s * rf.A(i) / (2.0 * (a0 + a1)) * yc[size_t(b) * nc * nc + I * nc + J];
 }
 
 // e_coarse = P^T x_fine (bilinear 9/3/3/1, direct injection on the
@@ -317,7 +510,7 @@ __device__ double u0bar_at(const SetupTArgs& a, const double* ub, const double* 
                            int j) {
   const int n = a.r.n, G = n + 2;
   double v = ub[(i + 1) * G + (j + 1)];
-  auto f = [&](int r, int q) { return fb[r * n + q] / a.r.A(r); };
+  auto f = [&](int r, int q) { return fb[r * n + q] * a.r.rA(r); };
   if (i >= 0 && i < n && j >= 0 && j < n) v += (a.r.sm(i) + a.r.sp(i) + 2.0 * a.r.isc(i)) * f(i, j);
   // cells whose stencil reads (i, j), with minus sign of -L
   if (i + 1 >= 0 && i + 1 < n && j >= 0 && j < n) v -= a.r.sm(i + 1) * f(i + 1, j);
@@ -407,12 +600,83 @@ __global__ void k_sub_mean(int64_t n, const double* red, double* y) {
   if (t < n) y[t] -= red[1023];
 }
 
+// Reciprocal row table (1 / s_c, 1 / area, two unused) of every level, laid
+// out like the coefficient table.
+__global__ void k_rrows(int64_t nrows, const double* c, double* q) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nrows) return;
+  const double* r = c + 4 * t;
+  q[4 * t] = 1.0 / r[2];
+  q[4 * t + 1] = 1.0 / r[3];
+  q[4 * t + 2] = 0.0;
+  q[4 * t + 3] = 0.0;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host side
 namespace {
 
-Rows rows(Plan* p, int l) { return Rows{p->coef + p->lev[l].crow, p->n >> l}; }
+Rows rows(Plan* p, int l) {
+  return Rows{p->coef + p->lev[l].crow, p->adj_rrows + p->lev[l].crow, p->n >> l};
+}
+
+template <int TT, int S, int NT>
+clm_status launch_smooth_T(Plan* p, const SmoothTArgs& a, int64_t nblk, hipStream_t s) {
+  using G = SmGeom<TT, S, NT>;
+  const auto kern = k_smooth_T<TT, S, NT>;
+  clm_status st = lds_opt_in(p, reinterpret_cast<const void*>(kern), G::Lds);
+  if (st != CLM_OK) return st;
+  hipLaunchKernelGGL(kern, dim3(unsigned(nblk)), dim3(NT), G::Lds, s, a);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+template <int TT, int NT>
+clm_status launch_smooth_T(Plan* p, const SmoothTArgs& a, int S, int64_t nblk, hipStream_t s) {
+  return S == 4 ? launch_smooth_T<TT, 4, NT>(p, a, nblk, s)
+                : launch_smooth_T<TT, 2, NT>(p, a, nblk, s);
+}
+
+// Transposed smoothing of level l (n >= 8): 2 nu half sweeps, the first of
+// colour 1, in launches of 4 half sweeps and a last one of 2 for odd nu; the
+// first launch applies the coarse-correction transpose when e is given.
+// Tiles are 64^2 cells, or the whole patch on smaller levels.  u and v swap
+// per launch.
+clm_status smooth_T(Plan* p, int l, int nu, const double* e, const double* fH, double*& u,
+                    double*& v, double* f, hipStream_t s) {
+  const int n = p->n >> l;
+  const int T = std::min(64, n);
+  SmoothTArgs a;
+  a.r = rows(p, l);
+  a.tiles = n / T;
+  a.fbar = f;
+  a.e = e;
+  a.fH = fH;
+  const int64_t nblk = int64_t(p->nbundle) * a.tiles * a.tiles;
+  a.remap = nblk % 8 == 0;
+  int left = 2 * nu;
+  a.c0 = 1;
+  while (left > 0) {
+    const int S = left >= 4 ? 4 : 2;
+    a.in = u;
+    a.out = v;
+    clm_status st;
+    switch (T) {
+      case 64: st = launch_smooth_T<64, 512>(p, a, S, nblk, s); break;
+      case 32: st = launch_smooth_T<32, 256>(p, a, S, nblk, s); break;
+      case 16: st = launch_smooth_T<16, 128>(p, a, S, nblk, s); break;
+      case 8: st = launch_smooth_T<8, 64>(p, a, S, nblk, s); break;
+      default: return fail(p, CLM_EINVAL, "smoothing level side must be a power of 2 >= 8");
+    }
+    if (st != CLM_OK) return st;
+    std::swap(u, v);
+    left -= S;
+    a.e = nullptr;
+    a.fH = nullptr;
+  }
+  return CLM_OK;
+}
 
 // Transpose of one V-cycle on level l: ubar_out in adj_u[l] -> ubar_in in
 // adj_u[l], fbar added to adj_f[l] (the caller zeroes it).
@@ -422,7 +686,6 @@ clm_status vcycle_T(Plan* p, int l, hipStream_t s) {
   double* u = p->adj_u[l];
   double* v = p->adj_v[l];
   double* f = p->adj_f[l];
-  const Rows r = rows(p, l);
   if (n <= 4) {
     hipLaunchKernelGGL(k_coarsest_T, grid_for(np * 16), dim3(kBlk), 0, s, p->cinv, np, u, f);
     CLM_LAUNCH_CHECK();
@@ -430,17 +693,8 @@ clm_status vcycle_T(Plan* p, int l, hipStream_t s) {
     CLM_LAUNCH_CHECK();
     return CLM_OK;
   }
-  auto smooth_T = [&](int sweeps) -> clm_status {
-    for (int k = 0; k < sweeps; ++k)
-      for (int col = 1; col >= 0; --col) {
-        hipLaunchKernelGGL(k_hs_T, grid_for(cells), dim3(kBlk), 0, s, r, np, col, u, v, f);
-        CLM_LAUNCH_CHECK();
-        std::swap(u, v);
-      }
-    return CLM_OK;
-  };
   clm_status st;
-  if ((st = smooth_T(p->d.nu_post)) != CLM_OK) return st;
+  if ((st = smooth_T(p, l, p->d.nu_post, nullptr, nullptr, u, v, f, s)) != CLM_OK) return st;
   // coarse level l + 1: e = P^T ubar; ubar_H out = e
   const int nc = n / 2;
   const int64_t ccells = np * nc * nc;
@@ -463,18 +717,8 @@ clm_status vcycle_T(Plan* p, int l, hipStream_t s) {
   CLM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_L0_T, grid_for(ccells), dim3(kBlk), 0, s, rows(p, l + 1), np, fH, 1.0, e);
   CLM_LAUNCH_CHECK();
-  // u += R^T ubar_bar; r = R^T fbar_H: f += r, u -= L^T r  (r in v)
-  hipLaunchKernelGGL(k_restrict_T, grid_for(cells), dim3(kBlk), 0, s, r, np, e, 1.0, u);
-  CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_fill, grid_for(cells), dim3(kBlk), 0, s, cells, 0.0, v);
-  CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_restrict_T, grid_for(cells), dim3(kBlk), 0, s, r, np, fH, 1.0, v);
-  CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_axpy, grid_for(cells), dim3(kBlk), 0, s, cells, 1.0, v, f);
-  CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_L0_T, grid_for(cells), dim3(kBlk), 0, s, r, np, v, -1.0, u);
-  CLM_LAUNCH_CHECK();
-  if ((st = smooth_T(p->d.nu_pre)) != CLM_OK) return st;
+  // u += R^T ubar_bar, v = R^T fbar_H: f += v, u -= L0^T v; then smoothing
+  if ((st = smooth_T(p, l, p->d.nu_pre, e, fH, u, v, f, s)) != CLM_OK) return st;
   // the smoothing ping-pong may have left the result in the partner array
   if (u != p->adj_u[l]) {
     hipLaunchKernelGGL(k_fill, grid_for(cells), dim3(kBlk), 0, s, cells, 0.0, p->adj_u[l]);
@@ -486,6 +730,15 @@ clm_status vcycle_T(Plan* p, int l, hipStream_t s) {
 }
 
 }  // namespace
+
+clm_status adjoint_tables(Plan* p) {
+  int64_t nrows = 0;
+  for (int l = 0; l < p->nlev; ++l) nrows += p->n >> l;
+  hipLaunchKernelGGL(k_rrows, grid_for(nrows), dim3(kBlk), 0, 0, nrows,
+                     static_cast<const double*>(p->coef), p->adj_rrows);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
 
 clm_status shear_adjoint(Plan* p, const double* th, const double* ph, int64_t npts,
                          const double* gbar, const double* hbar, hipStream_t s) {

@@ -102,6 +102,7 @@ struct Plan {
   std::vector<double*> adj_u, adj_v, adj_f, adj_w;
   double* adj_psi = nullptr;    // [npix_s] psi_SHT bar
   double* adj_psi_priv = nullptr;  // [adj_ncopy][npix_s] per-block copies of psi_SHT bar
+  double* adj_rrows = nullptr;  // reciprocal row table, laid out like coef
   int adj_ncopy = 1;
   double* adj_ks = nullptr;     // [npix_s] kappa_SHT bar
   double* adj_alm = nullptr;    // [nalm] complex
@@ -192,6 +193,7 @@ clm_status shear_adjoint(Plan* p, const double* th, const double* ph, int64_t np
                          const double* gbar, const double* hbar,
                          hipStream_t s);                 // adjoint.hip
 clm_status poisson_adjoint(Plan* p, double* dkappa, hipStream_t s);
+clm_status adjoint_tables(Plan* p);                      // adjoint.hip
 int mfma_ring_blocks(int H);                             // sht_mfma.hip
 clm_status mfma_tables(Plan* p, hipStream_t s);
 clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s);

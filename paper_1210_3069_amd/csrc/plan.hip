@@ -42,7 +42,7 @@ Plan::~Plan() {
   for (auto* q : ulev) f(q);
   for (auto* q : ulev2) f(q);
   for (auto& s : slots) { f(s.alm); f(s.psi_s); f(s.u0); f(s.du); }
-  f(adj_ubar); f(adj_psi); f(adj_ks); f(adj_alm); f(adj_psi_priv);
+  f(adj_ubar); f(adj_psi); f(adj_ks); f(adj_alm); f(adj_psi_priv); f(adj_rrows);
   f(mg_eps_dev); f(mg_cycles_dev); f(mg_done_dev); f(mg_eps_part); f(mg_active_dev);
   if (mg_active_host) (void)hipHostFree(mg_active_host);
   for (auto* q : adj_u) f(q);
@@ -182,7 +182,10 @@ clm_status adjoint_alloc(Plan* p) {
   if ((s = alloc(p, &p->adj_ks, size_t(p->npix_s))) != CLM_OK) return s;
   if ((s = alloc(p, &p->adj_alm, size_t(p->nalm) * 2)) != CLM_OK) return s;
   if (hipMemset(p->adj_ubar, 0, size_t(p->nbundle) * G * 8) != hipSuccess) return CLM_EHIP;
-  return CLM_OK;
+  size_t nrows = 0;
+  for (int l = 0; l < p->nlev; ++l) nrows += size_t(p->n >> l);
+  if ((s = alloc(p, &p->adj_rrows, 4 * nrows)) != CLM_OK) return s;
+  return adjoint_tables(p);
 }
 
 

@@ -579,9 +579,9 @@ def adj_case():
     return dict(spec=spec, kap=kap, th=th, ph=ph, g1o=g1o, g2o=g2o, chi2=chi2, grad=grad)
 
 
-def _adj_plan(clm, N, Ns, lmax, Nb, n, cyc):
+def _adj_plan(clm, N, Ns, lmax, Nb, n, cyc, nu_pre=2, nu_post=2):
     return clm.Plan(N, nside_sht=Ns, lmax=lmax, nside_bundle=Nb, patch_cells=n,
-                    mg_vcycles=cyc, mg_prec="fp64", adjoint=1)
+                    mg_vcycles=cyc, mg_prec="fp64", adjoint=1, nu_pre=nu_pre, nu_post=nu_post)
 
 
 def test_adjoint_gradient_matches_oracle(clm, adj_case):
@@ -604,11 +604,13 @@ def test_adjoint_gradient_matches_oracle(clm, adj_case):
     plan.close()
 
 
-def test_adjoint_dot_product_tile_levels(clm):
+@pytest.mark.parametrize("nu", [(2, 2), (3, 1), (1, 4)])
+def test_adjoint_dot_product_tile_levels(clm, nu):
     """<F kappa, y> = <kappa, F^T y> with the tile-level forward (patches of
-    256^2) and the adjoint on the GPU, FP64."""
+    256^2) and the adjoint on the GPU, FP64; sweep counts whose transposed
+    smoothing spans one launch, a 4 + 2 split and a 4 + 4 split."""
     N, Ns, lmax, Nb = 64, 16, 32, 4
-    plan = _adj_plan(clm, N, Ns, lmax, Nb, 256, 3)
+    plan = _adj_plan(clm, N, Ns, lmax, Nb, 256, 3, *nu)
     rng = np.random.default_rng(11)
     kap = torch.from_numpy(0.01 * rng.standard_normal(12 * N * N)).cuda()
     th, ph = (torch.from_numpy(a).cuda() for a in inputs.uniform_sphere(2000, seed=12))
