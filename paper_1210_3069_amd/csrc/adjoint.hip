@@ -520,34 +520,106 @@ __device__ double u0bar_at(const SetupTArgs& a, const double* ub, const double* 
   return v;
 }
 
+// Block-local accumulation of scattered map contributions: an open-addressed
+// hash table in LDS keyed by pixel.  A block adds its contributions there and
+// then issues one global atomic per distinct pixel (neighbouring cells share
+// most of their interpolation pixels).  A contribution that finds no slot
+// within kProbe probes goes to the map directly.
+constexpr int kProbe = 16;
+
+template <int LG>
+struct LdsMapAcc {
+  static constexpr int HS = 1 << LG;
+  int* key;      // [HS], -1: empty
+  double* val;   // [HS]
+  __device__ void clear() {
+    for (int s = threadIdx.x; s < HS; s += blockDim.x) {
+      key[s] = -1;
+      val[s] = 0.0;
+    }
+  }
+  __device__ void add(double* map, int pix, double v) {
+    unsigned h = (unsigned(pix) * 2654435761u) >> (32 - LG);
+    for (int k = 0; k < kProbe; ++k) {
+      const int old = atomicCAS(&key[h], -1, pix);
+      if (old == -1 || old == pix) {
+        atomicAdd(&val[h], v);
+        return;
+      }
+      h = (h + 1) & (HS - 1);
+    }
+    atomicAdd(map + pix, v);
+  }
+  __device__ void flush(double* map) const {
+    for (int s = threadIdx.x; s < HS; s += blockDim.x)
+      if (key[s] >= 0) atomicAdd(map + key[s], val[s]);
+  }
+};
+
 // Interior cells: u0 = interp(psi) and the ghosts' -u0(adjacent) folded in;
-// f = 2 interp(kappa') with f bar = f' bar.
-__global__ void k_adj_setup_cells(SetupTArgs a) {
+// f = 2 interp(kappa') with f bar = f' bar.  A block takes a 16 x 16 tile
+// of one patch (patches of 8^2 cells: 4 whole patches), so that its cells
+// share interpolation pixels.
+constexpr int kSetupTile = 16;
+
+__global__ __launch_bounds__(kBlk) void k_adj_setup_cells(SetupTArgs a) {
+  static_assert(kBlk == kSetupTile * kSetupTile, "one cell per thread");
+  __shared__ int pk[256], fk[1024];
+  __shared__ double pv[256], fv[1024];
+  LdsMapAcc<8> accp{pk, pv};
+  LdsMapAcc<10> accf{fk, fv};
+  accp.clear();
+  accf.clear();
   const int n = a.r.n;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.np * n * n) return;
-  const int64_t b = t / (int64_t(n) * n);
-  const int c = int(t % (int64_t(n) * n)), i = c / n, j = c % n;
-  const int G = n + 2;
-  const double* ub = a.ubar + size_t(b) * G * G;
-  const double* fb = a.fpb + size_t(b) * n * n;
-  double v = u0bar_at(a, ub, fb, i, j);
-  if (i == 0) v -= u0bar_at(a, ub, fb, -1, j);
-  if (i == n - 1) v -= u0bar_at(a, ub, fb, n, j);
-  if (j == 0) v -= u0bar_at(a, ub, fb, i, -1);
-  if (j == n - 1) v -= u0bar_at(a, ub, fb, i, n);
-  if (i == 0 && j == 0) v -= u0bar_at(a, ub, fb, -1, -1);
-  if (i == 0 && j == n - 1) v -= u0bar_at(a, ub, fb, -1, n);
-  if (i == n - 1 && j == 0) v -= u0bar_at(a, ub, fb, n, -1);
-  if (i == n - 1 && j == n - 1) v -= u0bar_at(a, ub, fb, n, n);
-  const double* R = a.rot + 9 * b;
-  const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
-  double z, rho, ph;
-  patch_point(R, th0 + (i + 0.5) * a.delta, ph0 + (j + 0.5) * a.delta, z, rho, ph);
+  const bool live = t < a.np * n * n;
+  int64_t b;
+  int i, j;
+  if (n >= kSetupTile) {
+    const int nt = n / kSetupTile;
+    const int64_t tile = int64_t(blockIdx.x);
+    b = tile / (int64_t(nt) * nt);
+    const int tl = int(tile - b * nt * nt);
+    i = (tl / nt) * kSetupTile + threadIdx.x / kSetupTile;
+    j = (tl % nt) * kSetupTile + threadIdx.x % kSetupTile;
+  } else {
+    b = t / (int64_t(n) * n);
+    const int c = int(t - b * n * n);
+    i = c / n;
+    j = c % n;
+  }
   // each block adds into its own copy of the small SHT-grid map: millions of
   // cells map to each SHT pixel, and one shared map serialises the atomics
-  scatter(a.rs, a.psibar + (blockIdx.x % a.ncopy) * a.npix_s, z, rho, ph, v);
-  scatter(a.rf, a.kbar, z, rho, ph, 2.0 * fb[c]);
+  double* psib = a.psibar + (blockIdx.x % a.ncopy) * a.npix_s;
+  __syncthreads();
+  if (live) {
+    const int G = n + 2;
+    const double* ub = a.ubar + size_t(b) * G * G;
+    const double* fb = a.fpb + size_t(b) * n * n;
+    double v = u0bar_at(a, ub, fb, i, j);
+    if (i == 0) v -= u0bar_at(a, ub, fb, -1, j);
+    if (i == n - 1) v -= u0bar_at(a, ub, fb, n, j);
+    if (j == 0) v -= u0bar_at(a, ub, fb, i, -1);
+    if (j == n - 1) v -= u0bar_at(a, ub, fb, i, n);
+    if (i == 0 && j == 0) v -= u0bar_at(a, ub, fb, -1, -1);
+    if (i == 0 && j == n - 1) v -= u0bar_at(a, ub, fb, -1, n);
+    if (i == n - 1 && j == 0) v -= u0bar_at(a, ub, fb, n, -1);
+    if (i == n - 1 && j == n - 1) v -= u0bar_at(a, ub, fb, n, n);
+    const double* R = a.rot + 9 * b;
+    const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
+    double z, rho, ph;
+    patch_point(R, th0 + (i + 0.5) * a.delta, ph0 + (j + 0.5) * a.delta, z, rho, ph);
+    int pix[4];
+    double w[4];
+    hpx::interp_weights(a.rs, z, rho, ph, pix, w);
+    for (int c = 0; c < 4; ++c) accp.add(psib, pix[c], w[c] * v);
+    const double fv2 = 2.0 * fb[i * n + j];
+    hpx::interp_weights(a.rf, z, rho, ph, pix, w);
+    for (int c = 0; c < 4; ++c) accf.add(a.kbar, pix[c], w[c] * fv2);
+  }
+  __syncthreads();
+  accp.flush(psib);
+  accf.flush(a.kbar);
 }
 
 // out[p] = sum of the ncopy private copies at p.
