@@ -403,9 +403,9 @@ __global__ __launch_bounds__(NT) void k_smooth_T(SmoothTArgs a) {
   }
 }
 
-// y += s L0^T x (L0: the level operator on a correction with zero face
-// values, rows scaled by 1 / area).
-__global__ void k_L0_T(Rows r, int64_t np, const double* xin, double s, double* y) {
+// e = -e + u bar_H + L0^T f bar_H on a coarse level (L0: the level operator
+// on a correction with zero face values, rows scaled by 1 / area).
+__global__ void k_corr_T(Rows r, int64_t np, const double* uH, const double* xin, double* e) {
   const int n = r.n;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= np * n * n) return;
@@ -416,12 +416,14 @@ __global__ void k_L0_T(Rows r, int64_t np, const double* xin, double s, double* 
   if (i < n - 1) v += r.sm(i + 1) * x[c + n] * r.rA(i + 1);
   if (j > 0) v += r.isc(i) * x[c - 1] * r.rA(i);
   if (j < n - 1) v += r.isc(i) * x[c + 1] * r.rA(i);
-  y[t] += s * v;
+  e[t] = uH[t] - e[t] + v;
 }
 
 // e_coarse = P^T x_fine (bilinear 9/3/3/1, direct injection on the
 // outermost fine ring); gather over the 4 x 4 fine window of a coarse cell.
-__global__ void k_prolong_T(int n, int64_t np, const double* xf, double* ec) {
+// The coarse cycle then starts from u bar_H = e and f bar_H = 0.
+__global__ void k_prolong_T(int n, int64_t np, const double* xf, double* ec, double* uH,
+                            double* fH) {
   const int nc = n / 2;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= np * nc * nc) return;
@@ -444,6 +446,8 @@ __global__ void k_prolong_T(int n, int64_t np, const double* xf, double* ec) {
     }
   }
   ec[t] = v;
+  uH[t] = v;
+  fH[t] = 0.0;
 }
 
 // fbar = Cinv^T ubar on the coarsest 4 x 4 level.
@@ -455,11 +459,6 @@ __global__ void k_coarsest_T(const double* cinv, int64_t np, const double* ub, d
   double v = 0.0;
   for (int q = 0; q < 16; ++q) v += cinv[q * 16 + k] * ub[b * 16 + q];
   fb[t] = v;
-}
-
-__global__ void k_axpy(int64_t n, double s, const double* x, double* y) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < n) y[t] += s * x[t];
 }
 
 __global__ void k_fill(int64_t n, double v, double* y) {
@@ -773,31 +772,18 @@ clm_status vcycle_T(Plan* p, int l, hipStream_t s) {
   double* uH = p->adj_u[l + 1];
   double* fH = p->adj_f[l + 1];
   double* e = p->adj_w[l + 1];
-  hipLaunchKernelGGL(k_prolong_T, grid_for(ccells), dim3(kBlk), 0, s, n, np, u, e);
-  CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_fill, grid_for(ccells), dim3(kBlk), 0, s, ccells, 0.0, uH);
-  CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_axpy, grid_for(ccells), dim3(kBlk), 0, s, ccells, 1.0, e, uH);
-  CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_fill, grid_for(ccells), dim3(kBlk), 0, s, ccells, 0.0, fH);
+  hipLaunchKernelGGL(k_prolong_T, grid_for(ccells), dim3(kBlk), 0, s, n, np, u, e, uH, fH);
   CLM_LAUNCH_CHECK();
   if ((st = vcycle_T(p, l + 1, s)) != CLM_OK) return st;
   // ubar_bar = -e + ubar_H in + L_H^T fbar_H  (into e)
-  hipLaunchKernelGGL(k_axpy, grid_for(ccells), dim3(kBlk), 0, s, ccells, -2.0, e, e);
-  CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_axpy, grid_for(ccells), dim3(kBlk), 0, s, ccells, 1.0, p->adj_u[l + 1], e);
-  CLM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_L0_T, grid_for(ccells), dim3(kBlk), 0, s, rows(p, l + 1), np, fH, 1.0, e);
+  hipLaunchKernelGGL(k_corr_T, grid_for(ccells), dim3(kBlk), 0, s, rows(p, l + 1), np,
+                     static_cast<const double*>(uH), static_cast<const double*>(fH), e);
   CLM_LAUNCH_CHECK();
   // u += R^T ubar_bar, v = R^T fbar_H: f += v, u -= L0^T v; then smoothing
   if ((st = smooth_T(p, l, p->d.nu_pre, e, fH, u, v, f, s)) != CLM_OK) return st;
   // the smoothing ping-pong may have left the result in the partner array
-  if (u != p->adj_u[l]) {
-    hipLaunchKernelGGL(k_fill, grid_for(cells), dim3(kBlk), 0, s, cells, 0.0, p->adj_u[l]);
-    CLM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_axpy, grid_for(cells), dim3(kBlk), 0, s, cells, 1.0, u, p->adj_u[l]);
-    CLM_LAUNCH_CHECK();
-  }
+  if (u != p->adj_u[l])
+    CLM_HIP(hipMemcpyAsync(p->adj_u[l], u, size_t(cells) * 8, hipMemcpyDeviceToDevice, s));
   return CLM_OK;
 }
 
