@@ -295,13 +295,25 @@ __global__ __launch_bounds__(NT) void k_smooth_T(SmoothTArgs a) {
   static_assert(CW <= CC, "coarse tile");
   const int cI0 = (i0 >> 1) - ((S + 2) >> 1), cJ0 = (j0 >> 1) - ((S + 2) >> 1);
   if (a.e) {
+    constexpr int NC = (CW * CW + NT - 1) / NT;
     const size_t cb = size_t(b) * nc * nc;
-    for (int idx = tid; idx < CW * CW; idx += NT) {
+    double ce[NC], cf[NC];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      const int idx = tid + m * NT;
       const int ci = idx / CW, cj = idx - ci * CW;
       const int I = cI0 + ci, J = cJ0 + cj;
-      if (I < 0 || I >= nc || J < 0 || J >= nc) continue;
-      CE[ci * CC + cj] = a.e[cb + size_t(I) * nc + J];
-      CF[ci * CC + cj] = a.fH[cb + size_t(I) * nc + J];
+      const bool ok = idx < CW * CW && I >= 0 && I < nc && J >= 0 && J < nc;
+      ce[m] = ok ? a.e[cb + size_t(I) * nc + J] : 0.0;
+      cf[m] = ok ? a.fH[cb + size_t(I) * nc + J] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      const int idx = tid + m * NT;
+      if (idx >= CW * CW) continue;
+      const int ci = idx / CW, cj = idx - ci * CW;
+      CE[ci * CC + cj] = ce[m];
+      CF[ci * CC + cj] = cf[m];
     }
   }
   __syncthreads();
