@@ -481,12 +481,14 @@ def c5_run(clm, torch, inputs):
             r1, r2 = 0.5 * (hh[0] - hh[1]) - o1, hh[2] - o2
             return float(((r1 * r1 + r2 * r2) / 0.26 ** 2).sum()), r1, r2
 
-        chi2_of(k_eval)                       # warm
+        zero = torch.zeros(2, th.numel(), dtype=torch.float64, device="cuda")
+        _, r1, r2 = chi2_of(k_eval)           # warm: forward and transpose
+        plan.shear_adjoint(th, ph, zero, torch.stack([r1, -r1, 2.0 * r2]) / 0.26 ** 2)
+        plan.poisson_adjoint()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         c2, r1, r2 = chi2_of(k_eval)
         hb = torch.stack([r1, -r1, 2.0 * r2]) / 0.26 ** 2
-        zero = torch.zeros(2, th.numel(), dtype=torch.float64, device="cuda")
         plan.shear_adjoint(th, ph, zero, hb)
         grad = plan.poisson_adjoint()
         torch.cuda.synchronize()
