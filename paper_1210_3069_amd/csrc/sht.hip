@@ -114,10 +114,6 @@ __device__ __forceinline__ void quarter_table(double* sq, int n) {
   for (int r = threadIdx.x; r <= Q; r += blockDim.x) sq[r] = sinpi(2.0 * double(r) / double(n));
 }
 
-__device__ __forceinline__ int bitrev(int j, int log2n) {
-  return log2n == 0 ? 0 : int(__brev(unsigned(j)) >> (32 - log2n));
-}
-
 // e^{sign 2 pi i t / n} for 0 <= t < n from the quarter-wave table.
 __device__ __forceinline__ void unit(const double* sq, int Q, int t, int sign, double& c,
                                      double& s) {
@@ -126,64 +122,68 @@ __device__ __forceinline__ void unit(const double* sq, int Q, int t, int sign, d
 }
 
 // Complex DFT of length h = 2^lg r (r odd) with kernel e^{sign 2 pi i jk/h},
-// from `in` to `out` (interleaved complex, distinct LDS arrays), for a ring
-// of n samples whose quarter-wave table is sq (h divides n).  Decimation in
-// time: the 2^lg subsequences of stride 2^lg get direct DFTs of length r
-// (block bitrev(b) holds subsequence b), then lg radix-2 stages combine
-// blocks of r 2^(s-1).  Twiddles of the odd DFT advance by quadrant and
-// remainder so the inner loop has no division.
-__device__ void dft_mixed(const double* in, double* out, int h, int lg, int r, const double* sq,
-                          int n, int sign) {
-  const int Q = n / 4;
-  const int nr = n / r;  // table step of e^{2 pi i / r}
-  const float inv_r = 1.0f / float(r);
-  for (int item = threadIdx.x; item < h; item += blockDim.x) {
-    const int bb = div_small(item, r, inv_r), k = item - bb * r;
-    const int b = bitrev(bb, lg);
-    const int inc = k * nr;  // < n
-    int iq, ir;
-    quadrant(inc, Q, iq, ir);
-    int q = 0, rem = 0;
-    double ar = 0.0, ai = 0.0;
-    for (int t = 0; t < r; ++t) {
-      const double zr = in[2 * ((t << lg) + b)], zi = in[2 * ((t << lg) + b) + 1];
-      const double sr = sq[rem], cr = sq[Q - rem];
-      const double u = (q & 1) ? sr : cr, v = (q & 1) ? cr : sr;
-      const double c = (q == 1 || q == 2) ? -u : u;
-      const double s = (q >= 2) ? -v : v;
-      const double ss = sign * s;
-      ar += zr * c - zi * ss;
-      ai += zr * ss + zi * c;
-      rem += ir;
-      q += iq;
-      if (rem >= Q) {
-        rem -= Q;
-        ++q;
-      }
-      q &= 3;
-    }
-    out[2 * item] = ar;
-    out[2 * item + 1] = ai;
-  }
-  __syncthreads();
-  for (int half = r; half < h; half <<= 1) {
-    const int L = 2 * half, step = n / L;
-    const float inv_half = 1.0f / float(half);
-    for (int item = threadIdx.x; item < h / 2; item += blockDim.x) {
-      const int blk = div_small(item, half, inv_half), kk = item - blk * half;
-      const int i0 = blk * L + kk, i1 = i0 + half;
+// for a ring of n = 2h samples whose quarter-wave table is sq.  Stockham
+// order, natural order in and out with no permutation pass: lg radix-2
+// stages (stage s joins the pairs h/2 apart into sub-transforms of length
+// 2^(s+1)), then one stage of direct r-point sums.  The stages ping-pong
+// between the LDS arrays a (holding the input, overwritten) and b; the
+// return value is the one holding the result.  Complex values move as
+// 16-byte pairs, and every stage reads consecutive elements per lane.
+// Twiddles of the odd stage advance by quadrant and remainder so its inner
+// loop has no division.
+__device__ double* dft_mixed(double* a, double* b, int h, int lg, int r, const double* sq, int n,
+                             int sign) {
+  const int Q = n / 4, hh = h / 2;
+  double2* src = reinterpret_cast<double2*>(a);
+  double2* dst = reinterpret_cast<double2*>(b);
+  for (int st = 0; st < lg; ++st) {
+    const int ns = 1 << st;
+    for (int j = threadIdx.x; j < hh; j += blockDim.x) {
+      const int k = j & (ns - 1);
       double c, s;
-      unit(sq, Q, kk * step, sign, c, s);
-      const double xr = out[2 * i1], xi = out[2 * i1 + 1];
-      const double tr = c * xr - s * xi, ti = c * xi + s * xr;
-      const double er = out[2 * i0], ei = out[2 * i0 + 1];
-      out[2 * i0] = er + tr;
-      out[2 * i0 + 1] = ei + ti;
-      out[2 * i1] = er - tr;
-      out[2 * i1 + 1] = ei - ti;
+      unit(sq, Q, k * (h >> st), sign, c, s);  // e^{sign 2 pi i k / (2 ns)}
+      const double2 x0 = src[j], x1 = src[j + hh];
+      const double tr = x1.x * c - x1.y * s, ti = x1.x * s + x1.y * c;
+      const int d = ((j >> st) << (st + 1)) + k;
+      dst[d] = make_double2(x0.x + tr, x0.y + ti);
+      dst[d + ns] = make_double2(x0.x - tr, x0.y - ti);
     }
     __syncthreads();
+    double2* t = src;
+    src = dst;
+    dst = t;
   }
+  if (r > 1) {
+    // X_item = sum_t Y_{k + t ns} e^{sign 2 pi i t item / h}, k = item mod ns
+    const int ns = 1 << lg;
+    for (int item = threadIdx.x; item < h; item += blockDim.x) {
+      const int k = item & (ns - 1);
+      int iq, ir;
+      quadrant(2 * item, Q, iq, ir);  // angle step 2 item / n
+      int q = 0, rem = 0;
+      double ar = 0.0, ai = 0.0;
+      for (int t = 0; t < r; ++t) {
+        const double2 z = src[k + t * ns];
+        const double sr = sq[rem], cr = sq[Q - rem];
+        const double u = (q & 1) ? sr : cr, v = (q & 1) ? cr : sr;
+        const double c = (q == 1 || q == 2) ? -u : u;
+        const double ss = sign * ((q >= 2) ? -v : v);
+        ar += z.x * c - z.y * ss;
+        ai += z.x * ss + z.y * c;
+        rem += ir;
+        q += iq;
+        if (rem >= Q) {
+          rem -= Q;
+          ++q;
+        }
+        q &= 3;
+      }
+      dst[item] = make_double2(ar, ai);
+    }
+    __syncthreads();
+    src = dst;
+  }
+  return reinterpret_cast<double*>(src);
 }
 
 // h = n / 2 = 2^lg r with r odd.
@@ -232,12 +232,11 @@ __device__ void fft_dif(double* A, int lgM, const double* sq) {
       const int kk = item & (span - 1), i0 = ((item >> ls) << (ls + 1)) + kk, i1 = i0 + span;
       double c, s;
       unit_p2(sq, lgM - 2, kk << (lgM - 1 - ls), -1, c, s);
-      const double ar = A[2 * i0], ai = A[2 * i0 + 1], br = A[2 * i1], bi = A[2 * i1 + 1];
-      A[2 * i0] = ar + br;
-      A[2 * i0 + 1] = ai + bi;
-      const double dr = ar - br, di = ai - bi;
-      A[2 * i1] = dr * c - di * s;
-      A[2 * i1 + 1] = dr * s + di * c;
+      double2* A2 = reinterpret_cast<double2*>(A);
+      const double2 x0 = A2[i0], x1 = A2[i1];
+      const double dr = x0.x - x1.x, di = x0.y - x1.y;
+      A2[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
+      A2[i1] = make_double2(dr * c - di * s, dr * s + di * c);
     }
     __syncthreads();
   }
@@ -253,13 +252,11 @@ __device__ void fft_dit_inv(double* A, int lgM, const double* sq) {
       const int kk = item & (span - 1), i0 = ((item >> ls) << (ls + 1)) + kk, i1 = i0 + span;
       double c, s;
       unit_p2(sq, lgM - 2, kk << (lgM - 1 - ls), +1, c, s);
-      const double xr = A[2 * i1], xi = A[2 * i1 + 1];
-      const double tr = c * xr - s * xi, ti = c * xi + s * xr;
-      const double er = A[2 * i0], ei = A[2 * i0 + 1];
-      A[2 * i0] = er + tr;
-      A[2 * i0 + 1] = ei + ti;
-      A[2 * i1] = er - tr;
-      A[2 * i1 + 1] = ei - ti;
+      double2* A2 = reinterpret_cast<double2*>(A);
+      const double2 x0 = A2[i0], x1 = A2[i1];
+      const double tr = c * x1.x - s * x1.y, ti = c * x1.y + s * x1.x;
+      A2[i0] = make_double2(x0.x + tr, x0.y + ti);
+      A2[i1] = make_double2(x0.x - tr, x0.y - ti);
     }
     __syncthreads();
   }
@@ -281,10 +278,11 @@ __device__ __forceinline__ void chirp(int k, int h, double& c, double& s) {
 // b_k = conj w_k (b_{M-k} = b_k), bit-reversed order.
 __device__ void bluestein_core(double* A, int lgM, const double* sq, const double* Bh) {
   fft_dif(A, lgM, sq);
+  double2* A2 = reinterpret_cast<double2*>(A);
+  const double2* B2 = reinterpret_cast<const double2*>(Bh);
   for (int p = threadIdx.x; p < (1 << lgM); p += blockDim.x) {
-    const double ar = A[2 * p], ai = A[2 * p + 1], br = Bh[2 * p], bi = Bh[2 * p + 1];
-    A[2 * p] = ar * br - ai * bi;
-    A[2 * p + 1] = ar * bi + ai * br;
+    const double2 x = A2[p], y = B2[p];
+    A2[p] = make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
   }
   __syncthreads();
   fft_dit_inv(A, lgM, sq);
@@ -352,8 +350,7 @@ __global__ __launch_bounds__(kRingBlock) void k_ring_forward(const double* map, 
     __syncthreads();
     int hh, lg, r;
     half_split(n, hh, lg, r);
-    dft_mixed(x, Zs, hh, lg, r, sqn, n, -1);
-    Z = Zs;
+    Z = dft_mixed(x, Zs, hh, lg, r, sqn, n, -1);
     sq = sqn;
   } else {
     const int lgM = lg_ceil(2 * h - 1), M = 1 << lgM;
@@ -481,10 +478,10 @@ __global__ __launch_bounds__(kRingBlock) void k_ring_inverse(const double* G, in
       double* Z = sm + n;
       for (int k = threadIdx.x; k < h; k += blockDim.x) yk(k, Y[2 * k], Y[2 * k + 1]);
       __syncthreads();
-      dft_mixed(Y, Z, h, lg, r, sq, n, +1);
+      const double* Zr = dft_mixed(Y, Z, h, lg, r, sq, n, +1);
       for (int j = threadIdx.x; j < h; j += blockDim.x) {
-        out[size_t(fld) * npix + first + 2 * j] = Z[2 * j];
-        out[size_t(fld) * npix + first + 2 * j + 1] = Z[2 * j + 1];
+        out[size_t(fld) * npix + first + 2 * j] = Zr[2 * j];
+        out[size_t(fld) * npix + first + 2 * j + 1] = Zr[2 * j + 1];
       }
     } else {
       // the e^{+...} transform as conj(DFT^-(conj Y))
