@@ -55,13 +55,12 @@ struct Rec {
 
 // lambda_lm at dl = l - m as float (0 below range), advancing the state for
 // dl >= 1: lambda_{m+1,m} = sqrt(2m+3) z lambda_mm, then
-// lambda_l = a_l (z lambda_{l-1} - b_l lambda_{l-2}).
-__device__ __forceinline__ float rec_value(Rec& r, int m, int dl, const double* rc) {
+// lambda_l = a_l (z lambda_{l-1} - b_l lambda_{l-2}) with (a, b) = (a_l, b_l).
+__device__ __forceinline__ float rec_value(Rec& r, int m, int dl, double a, double b) {
   if (dl == 1) {
     r.p2 = r.p1;
     r.p1 = sqrt(2.0 * m + 3.0) * r.z * r.p2;
   } else if (dl >= 2) {
-    const double a = rc[2 * dl], b = rc[2 * dl + 1];
     const double p0 = a * (r.z * r.p1 - b * r.p2);
     r.p2 = r.p1;
     r.p1 = p0;
@@ -72,6 +71,22 @@ __device__ __forceinline__ float rec_value(Rec& r, int m, int dl, const double* 
     }
   }
   return r.s == 0 ? float(r.p1) : 0.0f;
+}
+
+// The recurrence coefficients of a step of kStep values of l are read with
+// one vector load a step ahead, lane t holding rc[2 dl0 + t] (a_l, b_l
+// interleaved); each value is then taken from its lane as a wave-uniform
+// scalar, so the recurrence never waits on memory.
+__device__ __forceinline__ double rc_fetch(const double* rc, int dl0, int nl, int lane) {
+  const int t = 2 * dl0 + lane;
+  return t < 2 * nl ? rc[t] : 0.0;
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(int(bits), lane);
+  const unsigned hi = __builtin_amdgcn_readlane(int(bits >> 32), lane);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
 struct MfmaArgs {
@@ -154,12 +169,17 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_analysis_mfma(MfmaArgs a) {
         }
       }
 
+  double rcv = rc_fetch(rc, 0, nl, l);
   for (int dl0 = 0; dl0 < nl; dl0 += kStep) {
+    const double rcn = rc_fetch(rc, dl0 + kStep, nl, l);  // next step's, in flight
     // lambda for dl0 .. dl0 + 31 of this lane's ring into the wave's tile
+#pragma unroll
     for (int d = 0; d < kStep; ++d) {
       const int dl = dl0 + d;
-      tw[d * SA + l] = dl < nl ? rec_value(r, m, dl, rc) : 0.0f;
+      tw[d * SA + l] =
+          dl < nl ? rec_value(r, m, dl, lane_value(rcv, 2 * d), lane_value(rcv, 2 * d + 1)) : 0.0f;
     }
+    rcv = rcn;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is written
     f4 acc[2][2];
@@ -274,11 +294,32 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_synthesis_mfma(MfmaArgs a) {
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) acc[par][mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
   const int i = l & 15, k = l >> 4;
+  // psi operands of a step: per parity, 4 values of l (k-blocks) x 2 column
+  // blocks, loaded before the step's recurrence so that it hides their
+  // latency
+  auto psi_fetch = [&](int dl0, float (&v)[2][4][2]) {
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const int dl = FORM == kFP32 ? dl0 + 2 * (4 * j + k) + par : dl0 + 2 * (4 * k + j) + par;
+          v[par][j][nb] = dl < nl ? pm[size_t(dl) * kCols + i + 16 * nb] : 0.0f;
+        }
+  };
+  float pv[2][4][2];
+  double rcv = rc_fetch(rc, 0, nl, l);
   for (int dl0 = 0; dl0 < nl; dl0 += kStep) {
+    const double rcn = rc_fetch(rc, dl0 + kStep, nl, l);  // next step's, in flight
+    psi_fetch(dl0, pv);
+#pragma unroll
     for (int d = 0; d < kStep; ++d) {
       const int dl = dl0 + d;
-      tw[d * SS + l] = dl < nl ? rec_value(r, m, dl, rc) : 0.0f;
+      tw[d * SS + l] =
+          dl < nl ? rec_value(r, m, dl, lane_value(rcv, 2 * d), lane_value(rcv, 2 * d + 1)) : 0.0f;
     }
+    rcv = rcn;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);
 #pragma unroll
@@ -287,11 +328,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_synthesis_mfma(MfmaArgs a) {
         // K blocks of 4 values of l of this parity: rows 2 (4 j + k) + par
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int row = 2 * (4 * j + k) + par, dl = dl0 + row;
-          float bv[2];
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb)
-            bv[nb] = dl < nl ? pm[size_t(dl) * kCols + i + 16 * nb] : 0.0f;
+          const int row = 2 * (4 * j + k) + par;
+          const float* bv = pv[par][j];
 #pragma unroll
           for (int mb = 0; mb < 4; ++mb) {
             const float av = tw[row * SS + 16 * mb + i];
@@ -308,9 +346,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_synthesis_mfma(MfmaArgs a) {
         for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int dl = dl0 + 2 * (4 * k + e) + par;
             __bf16 h, lo;
-            split_bf16(dl < nl ? pm[size_t(dl) * kCols + i + 16 * nb] : 0.0f, h, lo);
+            split_bf16(pv[par][e][nb], h, lo);
             bh[nb][e] = h;
             bl[nb][e] = lo;
           }
