@@ -26,7 +26,8 @@ constexpr double kHugeB = 0x1p400;    // rescale threshold of the scaled recurre
 constexpr double kSmallB = 0x1p-800;  // rescale factor
 constexpr int kStep = 32;             // values of l generated per step (16 per parity)
 constexpr int kCols = 32;             // GEMM columns: 2 x up to 16 planes
-constexpr int kMaxWaves = 16;
+constexpr int kMaxWaves = 16;        // waves of a synthesis workgroup
+constexpr int kAnaWaves = 8;         // waves of an analysis workgroup (two fit per CU)
 constexpr int kBlk = 256;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -104,6 +105,11 @@ struct MfmaArgs {
   int H, nring, lmax, P, nwv;
 };
 
+// Waves per workgroup over H rings (64 rings per wave).
+__host__ __device__ inline int ring_waves(int H, int maxw) {
+  return H < 64 * maxw ? (H + 63) / 64 : maxw;
+}
+
 __device__ __forceinline__ size_t alm_base(int m, int lmax) {
   return size_t(m) * (2 * lmax + 1 - m) / 2 + m;  // index of (l = m, m)
 }
@@ -120,13 +126,16 @@ __device__ __forceinline__ Rec rec_start(const MfmaArgs& a, int m, int q) {
 
 // ---------------------------------------------------------------- analysis
 // Grid (lmax + 1, R): one workgroup per m and block of 64 nwv rings; each
-// wave owns 64 rings for all l and keeps their X in registers.
+// wave owns 64 rings for all l and keeps their X in registers.  The waves'
+// partial sums are added in a fixed order (results do not depend on
+// scheduling).  Workgroups of 8 waves leave room for two per CU, so one
+// workgroup's recurrence runs beside the other's matrix products.
 template <int FORM>
-__global__ __launch_bounds__(64 * kMaxWaves) void k_analysis_mfma(MfmaArgs a) {
+__global__ __launch_bounds__(64 * kAnaWaves, 4) void k_analysis_mfma(MfmaArgs a) {
   constexpr int SA = AnaStride<FORM>::S;
   constexpr int KB = FORM == kFP32 ? 16 : 4;   // k-blocks over the 64 rings
   constexpr int KW = FORM == kFP32 ? 4 : 16;   // rings per k-block
-  __shared__ float tiles[kMaxWaves * kStep * SA];
+  __shared__ float tiles[kAnaWaves * kStep * SA];
   const int m = blockIdx.x, rb = blockIdx.y;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int nl = a.lmax - m + 1;
@@ -421,17 +430,19 @@ MfmaArgs base_args(Plan* p, int first_slot, int P) {
   a.nring = p->nring_s;
   a.lmax = p->d.lmax;
   a.P = P;
-  a.nwv = p->H < 64 * kMaxWaves ? (p->H + 63) / 64 : kMaxWaves;
   for (int k = 0; k < P; ++k) a.alm[k] = p->slots[first_slot + k].alm;
   return a;
 }
 
-}  // namespace
-
-int mfma_ring_blocks(int H) {
-  const int nwv = H < 64 * kMaxWaves ? (H + 63) / 64 : kMaxWaves;
+int ring_blocks(int H, int maxw) {
+  const int nwv = ring_waves(H, maxw);
   return (H + 64 * nwv - 1) / (64 * nwv);
 }
+
+}  // namespace
+
+// Ring blocks of the analysis (its partial sums are [R][nalm][32]).
+int mfma_ring_blocks(int H) { return ring_blocks(H, kAnaWaves); }
 
 clm_status mfma_tables(Plan* p, hipStream_t s) {
   hipLaunchKernelGGL(k_recur_table, dim3(p->d.lmax + 1), dim3(kBlk), 0, s, p->d.lmax, p->rcoef);
@@ -444,7 +455,8 @@ clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s) {
   a.F = p->Fb;
   a.part = p->apart;
   a.w = 4.0 * 3.14159265358979323846 / double(p->npix_s);
-  const int R = mfma_ring_blocks(p->H);
+  a.nwv = ring_waves(p->H, kAnaWaves);
+  const int R = ring_blocks(p->H, kAnaWaves);
   const dim3 grid(p->d.lmax + 1, R), block(64 * a.nwv);
   {
     CLM_TIMED(p, s, "sht_analysis_mfma");
@@ -475,7 +487,8 @@ clm_status mfma_synthesis(Plan* p, int first_slot, int P, hipStream_t s) {
                        p->psib);
   }
   CLM_LAUNCH_CHECK();
-  const int R = mfma_ring_blocks(p->H);
+  a.nwv = ring_waves(p->H, kMaxWaves);
+  const int R = ring_blocks(p->H, kMaxWaves);
   const dim3 grid(p->d.lmax + 1, R), block(64 * a.nwv);
   {
     CLM_TIMED(p, s, "sht_synthesis_mfma");
