@@ -322,6 +322,24 @@ __device__ __forceinline__ void ring_unit(const double* sq, int n, int t, int si
   }
 }
 
+// e^{i pi k / n} for 0 <= k < 2n on a ring whose azimuth offset is pi / n
+// (shifted) or 0: e^{2 pi i (k/2) / n} from the quarter-wave table, times
+// (c1, s1) = e^{i pi / n} for odd k.
+__device__ __forceinline__ void half_unit(const double* sq, int n, int k, bool shifted, double c1,
+                                          double s1, double& c, double& s) {
+  if (!shifted) {
+    c = 1.0;
+    s = 0.0;
+    return;
+  }
+  unit(sq, n / 4, k >> 1, +1, c, s);
+  if (k & 1) {
+    const double cc = c * c1 - s * s1;
+    s = c * s1 + s * c1;
+    c = cc;
+  }
+}
+
 // F_m(q) = e^{-i m phi0_q} sum_j f_{q,j} e^{-2 pi i (m mod n) j / n}, m = 0..lmax
 // (HEALPix aliasing for rings shorter than lmax + 1).  The real ring is read
 // as h = n/2 complex samples z_j = f_2j + i f_2j+1, transformed with
@@ -382,7 +400,11 @@ __global__ __launch_bounds__(kRingBlock) void k_ring_forward(const double* map, 
     __syncthreads();
     Z = A;
   }
-  const float inv_n = 1.0f / float(n);
+  const float inv_n = 1.0f / float(n), inv_2n = 0.5f / float(n);
+  // phi0 is pi / n (shifted ring) or 0
+  const bool shifted = phi0 > 0.0;
+  double c1 = 1.0, s1 = 0.0;
+  if (sq) sincospi(1.0 / double(n), &s1, &c1);
   for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
     const int k = m - n * div_small(m, n, inv_n);  // m mod n
     const bool up = k > n / 2;
@@ -398,7 +420,10 @@ __global__ __launch_bounds__(kRingBlock) void k_ring_forward(const double* map, 
     double xr = er + c * orr - s * oi, xi = ei + c * oi + s * orr;
     if (up) xi = -xi;
     double sp, cp;
-    sincos(double(m) * phi0, &sp, &cp);
+    if (sq)
+      half_unit(sq, n, m - 2 * n * div_small(m, 2 * n, inv_2n), shifted, c1, s1, cp, sp);
+    else
+      sincos(double(m) * phi0, &sp, &cp);
     out[2 * m] = cp * xr + sp * xi;       // (cp - i sp)(xr + i xi)
     out[2 * m + 1] = cp * xi - sp * xr;
   }
@@ -476,7 +501,63 @@ __global__ __launch_bounds__(kRingBlock) void k_ring_inverse(const double* G, in
     if (bo < 0) {
       double* Y = sm;
       double* Z = sm + n;
-      for (int k = threadIdx.x; k < h; k += blockDim.x) yk(k, Y[2 * k], Y[2 * k + 1]);
+      // B_k for 0 <= k < n into both work arrays: the m = k terms of four
+      // indices are loaded together, the aliased m = k + t n (short rings)
+      // after them
+      double2* B = reinterpret_cast<double2*>(sm);
+      const double2* g2 = reinterpret_cast<const double2*>(g);
+      const bool shifted = sig < 0.0;  // phi0 = pi / n
+      double c1, s1;
+      sincospi(1.0 / double(n), &s1, &c1);
+      constexpr int U = 4;
+      for (int k0 = threadIdx.x; k0 < n; k0 += U * blockDim.x) {
+        double2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * blockDim.x;
+          v[u] = k < n && k <= lmax ? g2[k] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * blockDim.x;
+          if (k >= n) continue;
+          const double c0 = k == 0 ? 1.0 : 2.0;
+          double gr = c0 * v[u].x, gi = c0 * v[u].y, sg = sig;
+          for (int m = k + n; m <= lmax; m += n) {
+            const double2 w = g2[m];
+            gr += 2.0 * sg * w.x;
+            gi += 2.0 * sg * w.y;
+            sg *= sig;
+          }
+          double c, s;
+          half_unit(sq, n, k, shifted, c1, s1, c, s);
+          B[k] = make_double2(c * gr - s * gi, c * gi + s * gr);
+        }
+      }
+      __syncthreads();
+      // Y_k and Y_{h-k} from B_k, B_{n-k}, B_{k+h}, B_{h-k}: the thread of k
+      // alone reads and writes positions k and h - k (the others lie above h)
+      for (int k = threadIdx.x; k <= h / 2; k += blockDim.x) {
+        const double2 bk = B[k], bnk = B[k == 0 ? 0 : n - k];
+        const double2 bkh = B[k + h], bhk = B[h - k];
+        // C_j = (B_j + conj B_{n-j}) / 2
+        const double2 ck = make_double2(0.5 * (bk.x + bnk.x), 0.5 * (bk.y - bnk.y));
+        const double2 ckh = make_double2(0.5 * (bkh.x + bhk.x), 0.5 * (bkh.y - bhk.y));
+        const double2 chk = make_double2(0.5 * (bhk.x + bkh.x), 0.5 * (bhk.y - bkh.y));
+        const double2 cnk = make_double2(0.5 * (bnk.x + bk.x), 0.5 * (bnk.y - bk.y));
+        auto yval = [&](int kk, double2 a, double2 b) {
+          double c, s;
+          ring_unit(sq, n, kk, +1, c, s);
+          const double dr = a.x - b.x, di = a.y - b.y;
+          const double tr = c * dr - s * di, ti = c * di + s * dr;
+          return make_double2((a.x + b.x) - ti, (a.y + b.y) + tr);
+        };
+        const double2 yk0 = yval(k, ck, ckh);
+        // Y_{h-k} from C_{h-k} and C_{n-k} (C_{h-k+h} = C_{n-k})
+        const double2 yk1 = yval(h - k, chk, cnk);
+        B[k] = yk0;
+        if (k > 0 && h - k != k) B[h - k] = yk1;
+      }
       __syncthreads();
       const double* Zr = dft_mixed(Y, Z, h, lg, r, sq, n, +1);
       for (int j = threadIdx.x; j < h; j += blockDim.x) {
