@@ -227,6 +227,29 @@ def test_mg_patch_potential_parity(clm, mg_case, n, prec):
     plan.close()
 
 
+def test_mg_fp32_form_tracks_fp64_form(clm, mg_case):
+    """The float32 multigrid form at 4 V-cycles of (2, 2) sweeps, where the
+    finest level's post- and pre-smoothing run fused, against the float64
+    form on the same plane.  u0 is float64 in both forms, so they differ
+    only through the float32 correction du = u - u0 (u0 from the oracle):
+    float32 rounding, well below the bound, which exposes kernel-level errors
+    that the looser oracle tolerance of the float32 form would let through."""
+    c = mg_case
+    spec, sol = c[256]
+    kap = torch.from_numpy(c["kap"]).cuda()
+    du = {}
+    for prec in ("fp32", "fp64"):
+        plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                        patch_cells=256, mg_vcycles=4, mg_prec=prec)
+        plan.poisson_solve(kap)
+        du[prec] = np.stack([plan.patch_potential(b, 1)[0].cpu().numpy() -
+                             sol["patches"][b]["u0"][1:-1, 1:-1] for b in MG_BUNDLES])
+        plan.sync_status()
+        plan.close()
+    e = report("mg_du fp32 form vs fp64 form (4 cycles, fused)", rel(du["fp32"], du["fp64"]))
+    assert e < 1e-5
+
+
 @pytest.mark.parametrize("n,prec,eps", [(64, "fp64", 1e-3), (256, "fp64", 5e-4),
                                          (64, "fp32", 1e-2), (256, "fp32", 1e-2)])
 def test_mg_eps_rule_parity(clm, mg_case, n, prec, eps):
