@@ -89,6 +89,10 @@ struct Plan {
   void* dutmp = nullptr;        // [npatch][n^2] T (ping-pong partner of du)
   // per coarser tile level k (1 .. ktile), and the LDS level ktile:
   std::vector<void*> ubar, rbar, flev, ulev, ulev2;
+  // second level-1 ubar: the fused finest-level smoothing reads the
+  // restricted iterate of its cycle from one and writes the next cycle's to
+  // the other (one array would let a block read a neighbour's new values)
+  void* ubar1b = nullptr;
   int* status_dev = nullptr;
   double* mg_eps_dev = nullptr;   // [nbundle] epsilon ratio of the latest solve
   int* mg_cycles_dev = nullptr;   // [nbundle] V-cycles run

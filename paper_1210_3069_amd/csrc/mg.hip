@@ -1423,9 +1423,14 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
   // and the pre-smoothing of the next run as one kernel; the pre-smoothed
   // iterate then alternates between du and dt, starting so that the last
   // cycle's post-smoothing reads dt and writes du.
-  const bool fuse = !eps_mode && K >= 1 && d.nu_pre + d.nu_post <= 4 && sizeof(T) == 4;
+  const bool fuse = !eps_mode && K >= 1 && d.nu_pre + d.nu_post <= 4;
   T* cur = fuse && ((ncyc - 1) & 1) ? du : dt;  // pre-smoothed finest iterate
   bool have_pre = false;                        // formed by the fused kernel
+  if (fuse && !p->ubar1b) return fail(p, CLM_EHIP, "fused smoothing without its buffers");
+  // the restricted iterate of level l (level 1 alternates with ubar1b under
+  // fused smoothing)
+  void* ub1 = K >= 1 ? p->ubar[1] : nullptr;
+  auto ubar_at = [&](int l) { return static_cast<T*>(l == 1 ? ub1 : p->ubar[l]); };
   for (int cyc = 0; cyc < ncyc; ++cyc) {
     const bool first = cyc == 0;
     if (eps_mode && !first) {
@@ -1463,13 +1468,13 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
         a.u_out = cur;
         a.fas_source = 0;
       } else {
-        a.u_in = static_cast<T*>(p->ubar[l]);
+        a.u_in = ubar_at(l);
         a.f_in = static_cast<T*>(p->rbar[l]);
         a.u_out = static_cast<T*>(p->ulev[l]);
         a.f_out = static_cast<T*>(p->flev[l]);
         a.fas_source = 1;
       }
-      a.ubar_out = static_cast<T*>(p->ubar[l + 1]);
+      a.ubar_out = ubar_at(l + 1);
       a.rbar_out = static_cast<T*>(p->rbar[l + 1]);
       {
         CLM_TIMED(p, s, l == 0 ? "mg_pre_l0" : "mg_pre_l1+");
@@ -1478,7 +1483,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       }
     }
     // the LDS-resident levels
-    la.u_in = static_cast<T*>(p->ubar[K]);
+    la.u_in = ubar_at(K);
     la.f_in = static_cast<T*>(p->rbar[K]);
     la.u_out = static_cast<T*>(p->ulev[K]);
     la.fas_source = 1;
@@ -1491,7 +1496,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     for (int l = K - 1; l >= 0; --l) {
       TileArgs<T> a = tile_args(l, false);
       a.uc = static_cast<T*>(l + 1 == K ? p->ulev[K] : p->ulev2[l + 1]);
-      a.ubarc = static_cast<T*>(p->ubar[l + 1]);
+      a.ubarc = ubar_at(l + 1);
       if (l == 0 && fuse && cyc + 1 < ncyc) {
         // post-smoothing of this cycle + pre-smoothing of the next
         T* nxt = cur == dt ? du : dt;
@@ -1500,13 +1505,17 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
         a.u_in = cur;
         a.f_in = fp;
         a.u_out = nxt;
-        a.ubar_out = static_cast<T*>(p->ubar[1]);
+        // the correction reads this cycle's restricted iterate (a.ubarc);
+        // the next cycle's goes to the other level-1 array
+        void* ub1n = ub1 == p->ubar[1] ? p->ubar1b : p->ubar[1];
+        a.ubar_out = static_cast<T*>(ub1n);
         a.rbar_out = static_cast<T*>(p->rbar[1]);
         {
           CLM_TIMED(p, s, "mg_postpre_l0");
           const clm_status st = launch_postpre<T>(p, a, np, s);
           if (st != CLM_OK) return st;
         }
+        ub1 = ub1n;
         cur = nxt;
         have_pre = true;
         continue;

@@ -37,6 +37,7 @@ Plan::~Plan() {
   f(rcoef); f(Fb); f(Gb); f(apart); f(psib);
   f(deriv); f(fprime); f(dutmp); f(status_dev); f(iter_map); f(iter_alm);
   for (auto* q : ubar) f(q);
+  f(ubar1b);
   for (auto* q : rbar) f(q);
   for (auto* q : flev) f(q);
   for (auto* q : ulev) f(q);
@@ -499,6 +500,10 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
         p->flev[l] = q;
         if ((s = alloc(p, &q, c * esz)) != CLM_OK) return bail(s);
         p->ulev2[l] = q;
+      }
+      if (l == 1 && d.mg_vcycles > 0) {
+        if ((s = alloc(p, &q, c * esz)) != CLM_OK) return bail(s);
+        p->ubar1b = q;
       }
     }
   } else {
