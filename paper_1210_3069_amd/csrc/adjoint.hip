@@ -100,7 +100,8 @@ __global__ __launch_bounds__(kBlk) void k_adj_eval(EvalTArgs a) {
   const double py = R[3] * vx + R[4] * vy + R[5] * vz;
   const double pz = R[6] * vx + R[7] * vy + R[8] * vz;
   const double st = sqrt(px * px + py * py), ct = pz;
-  const double thp = atan2(st, pz), php = atan2(py, px);
+  // the point's patch coordinates exactly as the forward evaluation takes them
+  const double thp = kPi / 2 - hpx::asin_small(pz), php = hpx::dphi_of(px, py, 1.0, 0.0);
   const int n = a.n;
   const double h = a.delta;
   const double fi = (thp - (kPi / 2 - a.L / 2)) / h - 0.5;

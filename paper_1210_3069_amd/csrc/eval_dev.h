@@ -10,6 +10,8 @@
 
 #include <cstdint>
 
+#include "healpix_dev.h"
+
 namespace clm {
 
 struct PatchField {
@@ -110,8 +112,10 @@ __device__ bool eval_patch(const PatchField& P, int64_t b, double vx, double vy,
   const double py = R[3] * vx + R[4] * vy + R[5] * vz;
   const double pz = R[6] * vx + R[7] * vy + R[8] * vz;
   const double sp_ = sqrt(px * px + py * py);  // sin theta'
-  const double thp = atan2(sp_, pz);
-  const double php = atan2(py, px);
+  // theta' = pi/2 - asin(cos theta') and phi' = atan(py / px): series near
+  // the patch centre, where every point of the bundle lies
+  const double thp = pi / 2 - hpx::asin_small(pz);
+  const double php = hpx::dphi_of(px, py, 1.0, 0.0);
   const int n = P.n;
   const double ih = 1.0 / P.delta;
   const double fi = (thp - (pi / 2 - P.L / 2)) * ih - 0.5;

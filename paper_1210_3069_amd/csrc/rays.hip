@@ -37,6 +37,19 @@ __global__ void k_rays_init(int64_t Nf, int64_t n, double* th, double* ph, doubl
   }
 }
 
+// v rotated counter-clockwise about unit axis k by the angle with cosine c
+// and sine s (Rodrigues); omc = 1 - c.
+__device__ __forceinline__ void rotate_cs(const double k[3], double c, double s, double omc,
+                                          const double v[3], double out[3]) {
+  const double kv = k[0] * v[0] + k[1] * v[1] + k[2] * v[2];
+  const double cx = k[1] * v[2] - k[2] * v[1];
+  const double cy = k[2] * v[0] - k[0] * v[2];
+  const double cz = k[0] * v[1] - k[1] * v[0];
+  out[0] = v[0] * c + cx * s + k[0] * kv * omc;
+  out[1] = v[1] * c + cy * s + k[1] * kv * omc;
+  out[2] = v[2] * c + cz * s + k[2] * kv * omc;
+}
+
 // v rotated by angle w counter-clockwise about unit axis k (Rodrigues).
 __device__ __forceinline__ void rotate(const double k[3], double w, const double v[3],
                                        double out[3]) {
@@ -135,9 +148,12 @@ __global__ __launch_bounds__(kBlock) void k_ray_update(RayArgs a) {
   double rt[3], rp[3];
   if (sn > 0) {
     ax[0] /= sn; ax[1] /= sn; ax[2] /= sn;
-    const double w = atan2(sn, nv[0] * nn[0] + nv[1] * nn[1] + nv[2] * nn[2]);
-    rotate(ax, w, et, rt);
-    rotate(ax, w, ep, rp);
+    // the angle between the unit vectors: cosine n.n', sine |n x n'|;
+    // 1 - cos = sin^2 / (1 + cos) without cancellation
+    const double cw = nv[0] * nn[0] + nv[1] * nn[1] + nv[2] * nn[2];
+    const double omc = sn * sn / (1.0 + cw);
+    rotate_cs(ax, cw, sn, omc, et, rt);
+    rotate_cs(ax, cw, sn, omc, ep, rp);
   } else {
     for (int k = 0; k < 3; ++k) { rt[k] = et[k]; rp[k] = ep[k]; }
   }
@@ -156,9 +172,9 @@ __global__ __launch_bounds__(kBlock) void k_ray_update(RayArgs a) {
   };
   transport(A0, a.Ap);
   transport(An, a.A);
-  double phn = atan2(nn[1], nn[0]);
+  double phn = hpx::atan2_r(nn[1], nn[0]);
   if (phn < 0) phn += kTwoPi;
-  a.th[i] = atan2(sqrt(nn[0] * nn[0] + nn[1] * nn[1]), nn[2]);
+  a.th[i] = hpx::atan2_r(sqrt(nn[0] * nn[0] + nn[1] * nn[1]), nn[2]);
   a.ph[i] = phn;
   a.beta[i] = b[0];
   a.beta[n + i] = b[1];
