@@ -8,12 +8,17 @@
 //   evaluation at points (bilinear weights, 4th-order stencils, App. A
 //   metric terms, rotation)                    -> k_adj_eval (scatter)
 //   u = u0 + du, du ghosts = -interior          -> k_adj_split
-//   fixed V-cycles from du = 0                  -> mg_transpose (per level)
+//   fixed V-cycles from du = 0                  -> vcycle_T per cycle: smoothing
+//                                                  (k_smooth_T, LDS tiles, with
+//                                                  the coarse correction as its
+//                                                  prologue), k_prolong_T,
+//                                                  k_corr_T, k_coarsest_T
 //   f' = 2 interp(kappa') - L u0, u0 from psi_SHT (cells, face ghosts)
 //                                               -> k_adj_setup_cells / _ghosts
 //   analysis, Poisson factor, synthesis         -> sht_adjoint (sht.hip)
 //   degrade to the SHT grid, demean             -> k_adj_degrade, k_sub_mean
-// Everything runs in FP64 on plain per-level arrays (no temporal blocking).
+// Everything runs in FP64 on plain per-level arrays; the smoothing blocks
+// several half sweeps in LDS.
 #include <cmath>
 
 #include "clm_internal.h"

@@ -125,12 +125,12 @@ __device__ __forceinline__ void unit(const double* sq, int Q, int t, int sign, d
 // for a ring of n = 2h samples whose quarter-wave table is sq.  Stockham
 // order, natural order in and out with no permutation pass: lg radix-2
 // stages (stage s joins the pairs h/2 apart into sub-transforms of length
-// 2^(s+1)), then one stage of direct r-point sums.  The stages ping-pong
-// between the LDS arrays a (holding the input, overwritten) and b; the
-// return value is the one holding the result.  Complex values move as
-// 16-byte pairs, and every stage reads consecutive elements per lane.
-// Twiddles of the odd stage advance by quadrant and remainder so its inner
-// loop has no division.
+// 2^(s+1)), then one stage of direct p-point sums per odd prime factor p of
+// r.  The stages ping-pong between the LDS arrays a (holding the input,
+// overwritten) and b; the return value is the one holding the result.
+// Complex values move as 16-byte pairs, and every stage reads consecutive
+// elements per lane.  Twiddles of the odd stages advance by quadrant and
+// remainder so their inner loops have no division.
 __device__ double* dft_mixed(double* a, double* b, int h, int lg, int r, const double* sq, int n,
                              int sign) {
   const int Q = n / 4, hh = h / 2;
@@ -153,35 +153,47 @@ __device__ double* dft_mixed(double* a, double* b, int h, int lg, int r, const d
     src = dst;
     dst = t;
   }
-  if (r > 1) {
-    // X_item = sum_t Y_{k + t ns} e^{sign 2 pi i t item / h}, k = item mod ns
-    const int ns = 1 << lg;
-    for (int item = threadIdx.x; item < h; item += blockDim.x) {
-      const int k = item & (ns - 1);
-      int iq, ir;
-      quadrant(2 * item, Q, iq, ir);  // angle step 2 item / n
-      int q = 0, rem = 0;
-      double ar = 0.0, ai = 0.0;
-      for (int t = 0; t < r; ++t) {
-        const double2 z = src[k + t * ns];
-        const double sr = sq[rem], cr = sq[Q - rem];
-        const double u = (q & 1) ? sr : cr, v = (q & 1) ? cr : sr;
-        const double c = (q == 1 || q == 2) ? -u : u;
-        const double ss = sign * ((q >= 2) ? -v : v);
-        ar += z.x * c - z.y * ss;
-        ai += z.x * ss + z.y * c;
-        rem += ir;
-        q += iq;
-        if (rem >= Q) {
-          rem -= Q;
-          ++q;
+  // odd prime factors, smallest first: stage of radix R on sub-transforms of
+  // length ns; output item = jh ns R + u ns + k takes
+  // sum_t Y_{jh ns + k + t h/R} e^{sign 2 pi i t (u ns + k) / (ns R)}
+  int ns = 1 << lg, rr = r;
+  for (int R = 3; rr > 1; R += 2) {
+    while (rr % R == 0) {
+      rr /= R;
+      const int nsR = ns * R, hR = h / R, step = n / nsR;
+      const float inv_nsR = 1.0f / float(nsR), inv_ns = 1.0f / float(ns);
+      for (int item = threadIdx.x; item < h; item += blockDim.x) {
+        const int jh = div_small(item, nsR, inv_nsR), rem = item - jh * nsR;
+        const int u = div_small(rem, ns, inv_ns), k = rem - u * ns;
+        const int j = jh * ns + k;
+        int iq, ir;
+        quadrant(rem * step, Q, iq, ir);  // angle step rem / (ns R) in units of 2 pi
+        int q = 0, re = 0;
+        double ar = 0.0, ai = 0.0;
+        for (int t = 0; t < R; ++t) {
+          const double2 z = src[j + t * hR];
+          const double sr = sq[re], cr = sq[Q - re];
+          const double uu = (q & 1) ? sr : cr, vv = (q & 1) ? cr : sr;
+          const double c = (q == 1 || q == 2) ? -uu : uu;
+          const double ss = sign * ((q >= 2) ? -vv : vv);
+          ar += z.x * c - z.y * ss;
+          ai += z.x * ss + z.y * c;
+          re += ir;
+          q += iq;
+          if (re >= Q) {
+            re -= Q;
+            ++q;
+          }
+          q &= 3;
         }
-        q &= 3;
+        dst[item] = make_double2(ar, ai);
       }
-      dst[item] = make_double2(ar, ai);
+      __syncthreads();
+      double2* t = src;
+      src = dst;
+      dst = t;
+      ns = nsR;
     }
-    __syncthreads();
-    src = dst;
   }
   return reinterpret_cast<double*>(src);
 }
@@ -193,14 +205,27 @@ __device__ __forceinline__ void half_split(int n, int& h, int& lg, int& r) {
   r = h >> lg;
 }
 
-// Rings whose half length h = 2^lg r has an odd factor r above kDirectOdd
-// use Bluestein's chirp transform instead of the direct odd DFT (cost h r):
+// Rings whose half length h = 2^lg r has odd prime factors summing above
+// kDirectFactorSum use Bluestein's chirp transform instead of the direct odd
+// stages (cost h times that sum):
 // with w_k = e^{-i pi k^2 / h} and jk = (j^2 + k^2 - (k - j)^2) / 2,
 // X_k = w_k sum_j (z_j w_j) conj(w_{k-j}), a cyclic convolution of length
 // M = 2^lgM >= 2h - 1 done by two power-of-two FFTs and a product with the
 // transform of the chirp filter, tabulated per ring length at plan time.
 constexpr int kRingBlock = 1024;
-constexpr int kDirectOdd = 32;
+// Rings whose odd prime factors sum to at most this take the direct stages
+// (cost about h times that sum); the others Bluestein (about 56 h).
+constexpr int kDirectFactorSum = 64;
+
+__host__ __device__ inline int odd_factor_sum(int r) {
+  int sum = 0;
+  for (int p = 3; r > 1; p += 2)
+    while (r % p == 0) {
+      r /= p;
+      sum += p;
+    }
+  return sum;
+}
 
 __host__ __device__ inline int lg_ceil(int v) {
   int l = 0;
@@ -920,7 +945,7 @@ clm_status ring_plan(Plan* p) {
     const int n = i < N ? 4 * i : 4 * N, h = n / 2;
     int r = h;
     while (!(r & 1)) r >>= 1;
-    if (r <= kDirectOdd) {
+    if (odd_factor_sum(r) <= kDirectFactorSum) {
       lds = std::max(lds, size_t(2 * n + n / 4 + 1) * sizeof(double));
       continue;
     }
