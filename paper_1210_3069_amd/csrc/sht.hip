@@ -26,6 +26,36 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// v moved across lanes by a DPP pattern (both 32-bit halves); lanes of rows
+// outside ROW_MASK read 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, ROW_MASK, 0xF, false);
+  const unsigned hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double(
+      static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave, returned wave-uniform: quad permutes and
+// row mirrors give every lane its row's sum, row broadcasts 15 and 31 carry
+// the lower rows into the last one, and lane 63 holds the total.  Register
+// moves only (the xor shuffles go through the LDS crossbar), so the
+// latency chain is short.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_move<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);       // row_half_mirror
+  v += dpp_move<0x140>(v);       // row_mirror
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(int(b), 63);
+  const unsigned hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
+  return __longlong_as_double(
+      static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 // ---------------------------------------------------------------- mean
 template <typename T>
 __global__ void k_partial_sum(const T* x, int64_t n, double* out) {
@@ -709,8 +739,8 @@ __global__ __launch_bounds__(kBlock) void k_analysis(const double* F, const doub
         if (dl & 1) { sr += v * fmr[k]; si += v * fmi[k]; }
         else        { sr += v * fpr[k]; si += v * fpi[k]; }
       }
-      sr = wave_sum(sr);
-      si = wave_sum(si);
+      sr = wave_total(sr);
+      si = wave_total(si);
       if (lane == 0) {
         part[(c * (kBlock / 64) + wv) * 2] = sr;
         part[(c * (kBlock / 64) + wv) * 2 + 1] = si;
