@@ -17,6 +17,14 @@ namespace clm {
 namespace {
 
 constexpr int kBlock = 256;
+
+// FP64 Legendre workgroups: as many threads as the rings need, up to 1024
+// (512 for 8 rings per thread, 256 for 16, whose registers allow no more).
+// The per-m tables of a workgroup fill most of the LDS, so one workgroup
+// runs per CU and its size sets the waves that hide the recurrence's
+// latency.
+constexpr int leg_threads_max(int rpt) { return rpt <= 4 ? 1024 : rpt == 8 ? 512 : 256; }
+inline int round64(int v) { return (v + 63) / 64 * 64; }
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kHuge = 0x1p400;    // rescale threshold of the scaled recurrence
 constexpr double kSmall = 0x1p-800;  // rescale factor
@@ -682,7 +690,7 @@ __device__ __forceinline__ void recur_step(Recur& r, double z, double a, double 
 // a_lm = w sum_{north q} lambda_lm(theta_q) [F_m(q) + (-1)^(l+m) F_m(q')],
 // the equator counted once; one workgroup per m.
 template <int RPT>
-__global__ __launch_bounds__(kBlock) void k_analysis(const double* F, const double* rt,
+__global__ __launch_bounds__(leg_threads_max(RPT)) void k_analysis(const double* F, const double* rt,
                                                      const double* lam_mant,
                                                      const int* lam_scale, int H, int nring,
                                                      int lmax, double w, double* alm) {
@@ -691,7 +699,8 @@ __global__ __launch_bounds__(kBlock) void k_analysis(const double* F, const doub
   const int nl = lmax - m + 1;
   double* a = sm;                 // [nl]
   double* b = sm + nl;            // [nl]
-  double* part = sm + 2 * nl;     // [64][kBlock/64][2]
+  double* part = sm + 2 * nl;     // [64][waves][2]
+  const int nw = blockDim.x >> 6;
   recur_coeffs(m, lmax, a, b);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
@@ -699,7 +708,7 @@ __global__ __launch_bounds__(kBlock) void k_analysis(const double* F, const doub
   Recur st[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int q = threadIdx.x + k * kBlock;
+    const int q = threadIdx.x + k * blockDim.x;
     if (q < H) {
       z[k] = rt[4 * q];
       const int qm = nring - 1 - q;
@@ -742,17 +751,17 @@ __global__ __launch_bounds__(kBlock) void k_analysis(const double* F, const doub
       sr = wave_total(sr);
       si = wave_total(si);
       if (lane == 0) {
-        part[(c * (kBlock / 64) + wv) * 2] = sr;
-        part[(c * (kBlock / 64) + wv) * 2 + 1] = si;
+        part[(c * nw + wv) * 2] = sr;
+        part[(c * nw + wv) * 2 + 1] = si;
       }
     }
     __syncthreads();
     if (threadIdx.x < cnt) {
       const int c = threadIdx.x;
       double sr = 0.0, si = 0.0;
-      for (int v = 0; v < kBlock / 64; ++v) {
-        sr += part[(c * (kBlock / 64) + v) * 2];
-        si += part[(c * (kBlock / 64) + v) * 2 + 1];
+      for (int v = 0; v < nw; ++v) {
+        sr += part[(c * nw + v) * 2];
+        si += part[(c * nw + v) * 2 + 1];
       }
       const size_t idx = size_t(m) * (2 * lmax + 1 - m) / 2 + (m + l0 + c);
       alm[2 * idx] = w * sr;
@@ -780,7 +789,7 @@ __global__ void k_poisson(double* alm, int lmax) {
 // d2lambda = -cot dlambda - (l(l+1) - m^2/sin^2) lambda.
 // Output fields (DERIV): 0 = G, 1 = G_t, 2 = G_tt  ([field][ring][m]).
 template <bool DERIV>
-__global__ __launch_bounds__(kBlock) void k_synthesis(const double* alm, const double* rt,
+__global__ __launch_bounds__(1024) void k_synthesis(const double* alm, const double* rt,
                                                       const double* lam_mant,
                                                       const int* lam_scale, int H, int nring,
                                                       int lmax, double* G) {
@@ -895,21 +904,26 @@ __global__ void k_covariant(const double* D, int64_t npix, const double* rt, con
 template <typename K>
 clm_status allow_lds(Plan* p, K kernel, size_t bytes);
 
-int rpt_for(int H) {
-  int r = (H + kBlock - 1) / kBlock;
-  int k = 1;
-  while (k < r) k <<= 1;
+// Rings per thread of the analysis: 4 (each wave reduces its partial sums
+// once per l, so fewer rings per thread pay that more often), fewer while
+// the grid would hold under 16 waves per CU, more when one workgroup would
+// not cover the H north rings.
+int rpt_for(int H, int lmax) {
+  int k = 4;
+  while (k > 1 && int64_t(lmax + 1) * (H / (64 * k)) < 16 * 256) k >>= 1;
+  while (k <= 16 && k * leg_threads_max(k) < H) k <<= 1;
   return k;
 }
 
 template <int RPT>
 void launch_analysis(Plan* p, hipStream_t s, double* alm) {
   const int lmax = p->d.lmax;
-  const size_t shm = (2 * size_t(lmax + 1) + 64 * (kBlock / 64) * 2) * sizeof(double);
+  const int nt = std::min(leg_threads_max(RPT), round64((p->H + RPT - 1) / RPT));
+  const size_t shm = (2 * size_t(lmax + 1) + 64 * size_t(nt / 64) * 2) * sizeof(double);
   (void)allow_lds(p, k_analysis<RPT>, shm);
   {
     CLM_TIMED(p, s, "sht_analysis");
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis<RPT>), dim3(lmax + 1), dim3(kBlock), shm, s,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis<RPT>), dim3(lmax + 1), dim3(nt), shm, s,
                        p->F, p->ring_s, p->lam_mant, p->lam_scale, p->H, p->nring_s, lmax,
                        4.0 * kPi / double(p->npix_s), alm);
   }
@@ -935,11 +949,12 @@ clm_status allow_lds(Plan* p, K kernel, size_t bytes) {
 clm_status synthesis(Plan* p, const double* alm, hipStream_t s) {
   const int lmax = p->d.lmax;
   const size_t shm = 4 * size_t(lmax + 1) * sizeof(double);
-  dim3 grid(lmax + 1, (p->H + kBlock - 1) / kBlock);
+  const int nt = std::min(1024, round64(p->H));
+  dim3 grid(lmax + 1, (p->H + nt - 1) / nt);
   if (allow_lds(p, k_synthesis<false>, shm) != CLM_OK) return CLM_EHIP;
   {
     CLM_TIMED(p, s, "sht_synthesis");
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<false>), grid, dim3(kBlock), shm, s, alm,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<false>), grid, dim3(nt), shm, s, alm,
                        p->ring_s, p->lam_mant, p->lam_scale, p->H, p->nring_s, lmax, p->G);
   }
   CLM_LAUNCH_CHECK();
@@ -1080,7 +1095,7 @@ clm_status poisson(Plan* p, double* alm, hipStream_t s) {
 
 // a_lm of the ring transforms in p->F (FP64 Legendre analysis).
 clm_status analysis(Plan* p, double* alm, hipStream_t s) {
-  switch (rpt_for(p->H)) {
+  switch (rpt_for(p->H, p->d.lmax)) {
     case 1: launch_analysis<1>(p, s, alm); break;
     case 2: launch_analysis<2>(p, s, alm); break;
     case 4: launch_analysis<4>(p, s, alm); break;
@@ -1145,7 +1160,7 @@ clm_status sht_adjoint(Plan* p, const double* psibar, double* alm, double* ksbar
                        hipStream_t s) {
   clm_status st = ring_forward(p, psibar, p->F, s);
   if (st != CLM_OK) return st;
-  const int rpt = rpt_for(p->H);
+  const int rpt = rpt_for(p->H, p->d.lmax);
   switch (rpt) {
     case 1: launch_analysis<1>(p, s, alm); break;
     case 2: launch_analysis<2>(p, s, alm); break;
@@ -1188,11 +1203,12 @@ clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* gr
   const size_t per = size_t(p->nring_s) * (lmax + 1);
   {
     const size_t shm = 4 * size_t(lmax + 1) * sizeof(double);
-    dim3 grid(lmax + 1, (p->H + kBlock - 1) / kBlock);
+    const int nt = std::min(1024, round64(p->H));
+    dim3 grid(lmax + 1, (p->H + nt - 1) / nt);
     if (allow_lds(p, k_synthesis<true>, shm) != CLM_OK) return CLM_EHIP;
     {
       CLM_TIMED(p, s, "sht_deriv_synthesis");
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<true>), grid, dim3(kBlock), shm, s,
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<true>), grid, dim3(nt), shm, s,
                          p->slots[slot].alm, p->ring_s, p->lam_mant, p->lam_scale, p->H,
                          p->nring_s, lmax, p->G);
     }
