@@ -74,31 +74,40 @@ __device__ __forceinline__ Stencil d2_stencil(int c, int n) {
   return s;
 }
 
-// Stencil sums of the raw partials at cell (i, j) with the general
-// (edge-aware) stencils: 12 h psi_t', 12 h psi_p', 12 h^2 psi_t't',
+// Raw stencil sums at one cell: 12 h psi_t', 12 h psi_p', 12 h^2 psi_t't',
 // 12 h^2 psi_p'p', 144 h^2 psi_t'p'.
+struct Partials {
+  double pt, pp, ptt, ppp, ptp;
+};
+
+// Stencil sums at cell (i, j) with the general (edge-aware) stencils.  Only
+// cells within two of the patch face take them; the loops stay rolled so
+// this path does not raise the register count of the centred one.
 template <typename T>
-__device__ void partials_general(const double* u0, const T* du, int n, int i, int j,
-                                 double out[5]) {
+__device__ __forceinline__ Partials partials_general(const double* u0, const T* du, int n,
+                                                     int i, int j) {
   const Stencil a1 = d1_stencil(i, n), b1 = d1_stencil(j, n);
   const Stencil a2 = d2_stencil(i, n), b2 = d2_stencil(j, n);
-  double pt = 0, pp = 0, ptt = 0, ppp = 0, ptp = 0;
-  for (int k = 0; k < a1.len; ++k) pt += a1.w[k] * patch_u(u0, du, n, i + a1.first + k, j);
-  for (int k = 0; k < b1.len; ++k) pp += b1.w[k] * patch_u(u0, du, n, i, j + b1.first + k);
-  for (int k = 0; k < a2.len; ++k) ptt += a2.w[k] * patch_u(u0, du, n, i + a2.first + k, j);
-  for (int k = 0; k < b2.len; ++k) ppp += b2.w[k] * patch_u(u0, du, n, i, j + b2.first + k);
+  Partials r{0, 0, 0, 0, 0};
+#pragma unroll 1
+  for (int k = 0; k < 6; ++k) {
+    if (k < a1.len) {
+      r.pt += a1.w[k] * patch_u(u0, du, n, i + a1.first + k, j);
+      r.pp += b1.w[k] * patch_u(u0, du, n, i, j + b1.first + k);
+    }
+    if (k < a2.len) r.ptt += a2.w[k] * patch_u(u0, du, n, i + a2.first + k, j);
+    if (k < b2.len) r.ppp += b2.w[k] * patch_u(u0, du, n, i, j + b2.first + k);
+  }
+#pragma unroll 1
   for (int k = 0; k < a1.len; ++k) {
     if (a1.w[k] == 0) continue;
     double row = 0;
+#pragma unroll 1
     for (int q = 0; q < b1.len; ++q)
       row += b1.w[q] * patch_u(u0, du, n, i + a1.first + k, j + b1.first + q);
-    ptp += a1.w[k] * row;
+    r.ptp += a1.w[k] * row;
   }
-  out[0] = pt;
-  out[1] = pp;
-  out[2] = ptt;
-  out[3] = ppp;
-  out[4] = ptp;
+  return r;
 }
 
 // g = (g_t, g_p), U = (U_tt, U_pp, U_tp) of psi at unit vector v in patch b,
@@ -126,55 +135,62 @@ __device__ bool eval_patch(const PatchField& P, int64_t b, double vx, double vy,
   const double t = fi - ffi, s = fj - ffj;
   const double* u0 = P.u0 + size_t(b) * (n + 2) * (n + 2);
   const T* du = static_cast<const T*>(P.du) + size_t(b) * n * n;
-  double Pc[4][5];
+  // bilinear interpolation of the four cells' stencil sums, accumulated as
+  // each cell's sums are formed (the interpolation is linear); the 1/(12 h),
+  // 1/(12 h^2), 1/(144 h^2) factors are applied once afterwards
+  double Pv0 = 0, Pv1 = 0, Pv2 = 0, Pv3 = 0, Pv4 = 0;
   if (i0 >= 2 && i0 + 3 <= n - 1 && j0 >= 2 && j0 + 3 <= n - 1) {
-    // centred stencils only: a 6 x 6 window of u around the four cells
-    double w[6][6];
+    // centred stencils only, over the 6 x 6 window of u around the four
+    // cells (rows and columns i0-2 .. i0+3, j0-2 .. j0+3).  The bilinear
+    // weights and the 1-D stencils combine into per-row and per-column
+    // weight vectors (the 2-D stencils are products of 1-D ones), so each
+    // sum is a row weight times a column weight times u, taken row by row.
+    const double t0 = 1 - t, t1 = t, s0 = 1 - s, s1 = s;
+    // first derivative (1, -8, 0, 8, -1) and second (-1, 16, -30, 16, -1)
+    // about window rows 2 and 3, weighted t0 and t1
+    const double r1[6] = {t0, -8 * t0 + t1, -8 * t1, 8 * t0, -t0 + 8 * t1, -t1};
+    const double r2[6] = {-t0, 16 * t0 - t1, -30 * t0 + 16 * t1, 16 * t0 - 30 * t1,
+                          -t0 + 16 * t1, -t1};
+    const double c1[6] = {s0, -8 * s0 + s1, -8 * s1, 8 * s0, -s0 + 8 * s1, -s1};
+    const double c2[6] = {-s0, 16 * s0 - s1, -30 * s0 + 16 * s1, 16 * s0 - 30 * s1,
+                          -s0 + 16 * s1, -s1};
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
       const double* ur = u0 + (i0 - 2 + r + 1) * (n + 2) + (j0 - 2 + 1);
       const T* dr = du + (i0 - 2 + r) * n + (j0 - 2);
+      double w[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) w[r][c] = ur[c] + double(dr[c]);
-    }
-    const double c1[4] = {1, -8, 8, -1};
-    const int o1[4] = {-2, -1, 1, 2};
+      for (int c = 0; c < 6; ++c) w[c] = ur[c] + double(dr[c]);
+      const double wi = s0 * w[2] + s1 * w[3];  // interpolated along the row
+      double w1 = 0;                            // first derivative along the row
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = 2 + (k >> 1), c = 2 + (k & 1);
-      const double pt = w[r - 2][c] - 8 * w[r - 1][c] + 8 * w[r + 1][c] - w[r + 2][c];
-      const double pp = w[r][c - 2] - 8 * w[r][c - 1] + 8 * w[r][c + 1] - w[r][c + 2];
-      const double ptt = -w[r - 2][c] + 16 * w[r - 1][c] - 30 * w[r][c] + 16 * w[r + 1][c] -
-                         w[r + 2][c];
-      const double ppp = -w[r][c - 2] + 16 * w[r][c - 1] - 30 * w[r][c] + 16 * w[r][c + 1] -
-                         w[r][c + 2];
-      double ptp = 0;
+      for (int c = 0; c < 6; ++c) w1 += c1[c] * w[c];
+      Pv0 += r1[r] * wi;
+      Pv2 += r2[r] * wi;
+      Pv4 += r1[r] * w1;
+      if (r == 2 || r == 3) {
+        double w2 = 0;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        double row = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) row += c1[q] * w[r + o1[a]][c + o1[q]];
-        ptp += c1[a] * row;
+        for (int c = 0; c < 6; ++c) w2 += c2[c] * w[c];
+        const double tr = r == 2 ? t0 : t1;
+        Pv1 += tr * w1;
+        Pv3 += tr * w2;
       }
-      // stencil sums; the 1/(12 h), 1/(12 h^2), 1/(144 h^2) factors are
-      // applied once after the interpolation (it is linear)
-      Pc[k][0] = pt;
-      Pc[k][1] = pp;
-      Pc[k][2] = ptt;
-      Pc[k][3] = ppp;
-      Pc[k][4] = ptp;
     }
   } else {
-    for (int k = 0; k < 4; ++k)
-      partials_general<T>(u0, du, n, i0 + (k >> 1), j0 + (k & 1), Pc[k]);
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+      const Partials c = partials_general<T>(u0, du, n, i0 + (k >> 1), j0 + (k & 1));
+      const double bw = ((k >> 1) ? t : 1 - t) * ((k & 1) ? s : 1 - s);
+      Pv0 += bw * c.pt;
+      Pv1 += bw * c.pp;
+      Pv2 += bw * c.ptt;
+      Pv3 += bw * c.ppp;
+      Pv4 += bw * c.ptp;
+    }
   }
   const double i1 = ih / 12, i2 = ih * ih / 12;
-  const double sc[5] = {i1, i1, i2, i2, i2 / 12};
-  double Pv[5];
-#pragma unroll
-  for (int q = 0; q < 5; ++q)
-    Pv[q] = ((1 - t) * (1 - s) * Pc[0][q] + (1 - t) * s * Pc[1][q] + t * (1 - s) * Pc[2][q] +
-             t * s * Pc[3][q]) * sc[q];
+  const double Pv[5] = {Pv0 * i1, Pv1 * i1, Pv2 * i2, Pv3 * i2, Pv4 * (i2 / 12)};
   // covariant components in the patch frame at the point (App. A)
   const double st = sp_, ct = pz, ist = 1.0 / st;
   const double gpt = Pv[0], gpp = Pv[1] * ist;
