@@ -78,7 +78,7 @@ __device__ __forceinline__ void patch_dir(const double* R, double st, double ct,
 // tables).
 constexpr int kRingCapF = 256, kRingCapS = 64;
 constexpr int kSetupBlock = 512;
-constexpr int kLdsBlock = 1024;
+constexpr int kLdsBlock = 512;
 
 template <int CAP>
 struct RingStore {
@@ -838,9 +838,11 @@ __device__ __forceinline__ T prolong_cell(int gi, int gj, int n, EF e) {
 
 // ------------------------------------------------------------ LDS levels
 // One workgroup per patch runs the V-cycle below level K entirely in LDS:
-// 1024 threads, so the 64^2 level's half-sweeps take two cells per thread
-// per level l: u, f (and ubar for l > K) as row-major n_l x n_l arrays, and
-// the level's row coefficients (s_m, s_p, 1/s_c, area, interior 1/diag).
+// 512 threads, so the 64^2 level's half-sweeps take four cells per thread
+// (fewer threads sit idle on the coarser levels, and in float32 three such
+// workgroups share a CU's LDS, against two of 1024 threads).  Per level l:
+// u, f (and ubar for l > K) as row-major n_l x n_l arrays, and the level's
+// row coefficients (s_m, s_p, 1/s_c, area, interior 1/diag).
 struct LdsLevels {
   int K, nlev, n0;        // first level handled here, number of levels, its size
   size_t crow[16];        // coefficient row offsets per level (absolute level index)
