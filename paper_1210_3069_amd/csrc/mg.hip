@@ -235,11 +235,16 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
     prow[2 * r + 1] = 1.0 / c[3];
   }
   __syncthreads();
-  // z range of the region's cell centres; every point interpolated lies
-  // within half a cell of one of them
+  // z range of the region's cell centres.  z = cos(distance to the pole)
+  // has no extremum inside the region unless a pole lies in it (handled
+  // below), so the boundary cells bound it to within half a cell (the
+  // largest gap to a boundary point between two of them); every point
+  // interpolated lies within half a cell of a cell centre.
   double zlo = 2.0, zhi = -2.0;
-  for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
-    const int li = idx / RR, lj = idx % RR;
+  for (int idx = threadIdx.x; idx < 4 * (RR - 1); idx += blockDim.x) {
+    const int side = idx / (RR - 1), r = idx % (RR - 1);
+    const int li = side == 0 ? 0 : side == 1 ? r : side == 2 ? RR - 1 : RR - 1 - r;
+    const int lj = side == 0 ? r : side == 1 ? RR - 1 : side == 2 ? RR - 1 - r : 0;
     const double st = trig[4 * li], ct = trig[4 * li + 1];
     const double z = R[2] * st * trig[4 * lj + 3] + R[5] * st * trig[4 * lj + 2] + R[8] * ct;
     zlo = fmin(zlo, z);
@@ -259,7 +264,17 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
       zlo = fmin(zlo, zred[2 * w]);
       zhi = fmax(zhi, zred[2 * w + 1]);
     }
-    const double lo = zlo - a.delta, hi = zhi + a.delta;
+    // region centre; a pole closer to it than the region's side may lie in
+    // the region, and then opens the range up to it
+    double sc, cc, sp, cp;
+    sincos(th0 + (i0 + 0.5 * RR) * a.delta, &sc, &cc);
+    sincos(ph0 + (j0 + 0.5 * RR) * a.delta, &sp, &cp);
+    const double x = sc * cp, y = sc * sp;
+    const double zc = R[2] * x + R[5] * y + R[8] * cc;
+    const double cr = cos(RR * a.delta);
+    if (zc > cr) zhi = 1.0;
+    if (zc < -cr) zlo = -1.0;
+    const double lo = zlo - 2.0 * a.delta, hi = zhi + 2.0 * a.delta;
     const hpx::GlobalRingTab gs{a.rs, 0.0}, gf{a.rf, 0.0};
     const int bs = max(0, hpx::ring_above(gs, hi));
     const int ts = min(a.rs.nring - 1, hpx::ring_above(gs, lo) + 1);
@@ -268,10 +283,6 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
     rng[0] = bs; rng[1] = ts; rng[2] = bf; rng[3] = tf;
     rng[4] = (ts - bs + 1 <= kRingCapS) && (tf - bf + 1 <= kRingCapF);
     // reference azimuth: the region centre's, in [0, 2 pi)
-    double sc, cc, sp, cp;
-    sincos(th0 + (i0 + 0.5 * RR) * a.delta, &sc, &cc);
-    sincos(ph0 + (j0 + 0.5 * RR) * a.delta, &sp, &cp);
-    const double x = sc * cp, y = sc * sp;
     const double vx = R[0] * x + R[3] * y + R[6] * cc;
     const double vy = R[1] * x + R[4] * y + R[7] * cc;
     const double rc = sqrt(vx * vx + vy * vy);

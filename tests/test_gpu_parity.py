@@ -402,6 +402,59 @@ def test_mg_shear_parity(clm, mg_case, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_shear_edge_stencils(clm, mg_case, prec):
+    """Points in the outer two cell rows / columns of a patch take the
+    one-sided stencils (Sec. 3.2).  With patch factor 1 (patch = bundle) the
+    bundle's corners reach the patch faces, so points along the patch axes
+    close to a face still belong to the bundle whose patch holds them."""
+    c = mg_case
+    n, bl = 64, [37, 100]
+    spec = omg.PatchSpec(c["Nf"], c["Ns"], c["lmax"], c["Nb"], factor=1, ncell=n, vcycles=2)
+    sol = omg.solve_plane(spec, c["kap"], bl)
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_factor=1, patch_cells=n, mg_vcycles=2, mg_prec=prec)
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    mid = n / 2 - 0.5
+    # fractional cell coordinates (fi, fj): first / last two cells of each
+    # axis, the other coordinate near the middle
+    near = [0.2, 0.7, 1.4, 2.6]
+    fij = [(f, mid + 0.3) for f in near] + [(n - 2 - f, mid - 0.4) for f in near] + \
+          [(mid + 0.2, f) for f in near] + [(mid - 0.3, n - 2 - f) for f in near]
+    th, ph, owner, cells = [], [], [], []
+    for b in bl:
+        R = sol["patches"][b]["R"]
+        for fi, fj in fij:
+            thp = np.pi / 2 - spec.L / 2 + (fi + 0.5) * spec.delta
+            php = -spec.L / 2 + (fj + 0.5) * spec.delta
+            t, p = omg.patch_dirs(spec, R, thp, php)
+            t, p = float(t), float(p) % (2 * np.pi)
+            if omg.bundle_of(spec, t, p) != b:
+                continue
+            th.append(t)
+            ph.append(p)
+            owner.append(b)
+            cells.append((int(np.floor(fi)), int(np.floor(fj))))
+    # the set must reach the one-sided stencils on every face
+    i0s, j0s = [cc[0] for cc in cells], [cc[1] for cc in cells]
+    assert min(i0s) <= 1 and max(i0s) >= n - 3 and min(j0s) <= 1 and max(j0s) >= n - 3
+    gP, hP = plan.shear_from_potential(torch.tensor(th, dtype=torch.float64, device="cuda"),
+                                       torch.tensor(ph, dtype=torch.float64, device="cuda"))
+    plan.sync_status()
+    gP, hP = gP.cpu().numpy(), hP.cpu().numpy()
+    tol = 1e-9 if prec == "fp64" else 2e-4
+    worst = 0.0
+    for k, b in enumerate(owner):
+        gr, Ur = omg.eval_point(spec, sol["patches"][b], th[k], ph[k])
+        ur = np.array([Ur[0, 0], Ur[1, 1], Ur[0, 1]])
+        eg = np.abs(gP[:, k] - gr).max() / np.abs(gr).max()
+        eu = np.abs(hP[:, k] - ur).max() / np.abs(ur).max()
+        worst = max(worst, eg, eu)
+        assert eg < tol and eu < tol, (b, cells[k], eg, eu)
+    report("shear_edge %s" % prec, worst)
+    plan.close()
+
+
 def test_points_outside_patch_are_flagged(clm, mg_case):
     c = mg_case
     plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
