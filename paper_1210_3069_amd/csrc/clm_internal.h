@@ -20,6 +20,9 @@ enum : int { ST_LEFT_PATCH = 1, ST_NONFINITE = 2, ST_NOTCONV = 4 };
 // Epsilon rule: coarse cells per side of one partial-sum tile.
 constexpr int kEpsTile = 16;
 
+// Bytes of one patch-setup tile's geometry record.
+constexpr int kSetupMetaBytes = 48;
+
 // Largest multigrid level handled entirely inside one workgroup's LDS.
 constexpr int kLdsLevelMax = 64;
 // Interior side of the multigrid tiles streamed through LDS on larger levels.
@@ -93,6 +96,10 @@ struct Plan {
   // restricted iterate of its cycle from one and writes the next cycle's to
   // the other (one array would let a block read a neighbour's new values)
   void* ubar1b = nullptr;
+  // per patch-setup tile (nbundle x tiles per patch): the ring ranges of both
+  // grids that bracket the tile's region and its reference azimuth, which
+  // depend on the plan's geometry only (kSetupMetaBytes each)
+  char* setup_meta = nullptr;
   int* status_dev = nullptr;
   double* mg_eps_dev = nullptr;   // [nbundle] epsilon ratio of the latest solve
   int* mg_cycles_dev = nullptr;   // [nbundle] V-cycles run
@@ -206,6 +213,8 @@ clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64,
                             void* grad, void* hess, hipStream_t s);  // sht.hip
 clm_status mg_solve(Plan* p, const void* kappa, int kappa_fp64, int slot,
                     hipStream_t s);                     // mg.hip
+int64_t setup_tiles(const Plan* p);                     // mg.hip: patch-setup tiles
+clm_status setup_tables(Plan* p, hipStream_t s);        // mg.hip: fills setup_meta
 clm_status mg_patch_potential(Plan* p, int slot, int64_t first, int64_t np,
                               double* out, hipStream_t s);  // mg.hip
 clm_status eval_points(Plan* p, int slot, const double* th, const double* ph,

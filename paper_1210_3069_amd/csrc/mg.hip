@@ -43,6 +43,16 @@ __device__ __forceinline__ int64_t xcd_block() {
 // u0 = interp(psi_SHT) at the cell centres; ghost u0 = 2 b - u0(adjacent)
 // with b = interp(psi_SHT) at the face midpoint (corner: patch corner);
 // f' = 2 (interp(kappa) - mean) - L u0 at the cell centres, float64.
+// Geometry of one setup tile's region, fixed by the plan: the ring ranges of
+// both grids that can bracket its points, whether both fit the LDS ring
+// stores, and the reference azimuth (the region centre's).
+struct SetupMeta {
+  double phi, c, s;      // reference azimuth in [0, 2 pi), its cosine and sine
+  int bs, ts, bf, tf;    // SHT-grid rings bs .. ts, fine-grid rings bf .. tf
+  int lds, pad;
+};
+static_assert(sizeof(SetupMeta) == kSetupMetaBytes, "setup record size");
+
 struct SetupArgs {
   int n, ntile, tile;
   int ring_shift;       // log2(nside_fine / nside_sht)
@@ -56,6 +66,7 @@ struct SetupArgs {
   const double* red;   // red[1023] = mean of kappa
   double* u0;          // [patch][(n+2)^2]
   void* fprime;        // [patch][n^2] of T
+  SetupMeta* meta;     // [patch][tile]
 };
 
 // Global direction of the patch point with sin/cos of theta' and phi':
@@ -199,54 +210,44 @@ __device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, dou
   }
 }
 
-// One block per TILE x TILE tile (TILE = 64, or the whole patch if smaller),
-// sin/cos of theta' and phi' tabulated per row and column.  The block first
-// bounds cos(theta) over its region, takes the region centre's azimuth as
-// reference and copies the rings of both grids that can bracket the region
-// into LDS.
-template <typename T, int TILE>
-__global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
-  constexpr int RR = TILE + 2;
-  __shared__ double shu[RR * RR];
-  __shared__ double trig[4 * RR];  // sin/cos th'_row, ph'_col
-  __shared__ double prow[2 * TILE];  // 1 / s_c, 1 / area of the tile's rows
-  __shared__ RingStore<kRingCapF> ringf;
-  __shared__ RingStore<kRingCapS> rings;
-  __shared__ double zred[2 * (kSetupBlock / 64)];
-  __shared__ T fshm[sizeof(T) == 4 ? TILE * TILE : 1];
-  T* fsh = sizeof(T) == 4 ? fshm : nullptr;
-  __shared__ PhiRef pref;
-  __shared__ int rng[5];
-  const int64_t lb = xcd_block();
-  const int tpp = a.ntile * a.ntile;
-  const int64_t patch = lb / tpp;
+// The region of setup tile lb (TILE x TILE cells plus one ring) of its patch:
+// patch index and the region's first cell (i0, j0).
+struct SetupTile {
+  int64_t patch;
+  int i0, j0;
+};
+
+__device__ __forceinline__ SetupTile setup_tile(int64_t lb, int ntile, int tile) {
+  const int tpp = ntile * ntile;
   const int tt = int(lb % tpp);
-  const int ti = tt / a.ntile, tj = tt % a.ntile;
-  const int i0 = ti * TILE - 1, j0 = tj * TILE - 1;
-  const double* R = a.rot + 9 * patch;
+  return SetupTile{lb / tpp, (tt / ntile) * tile - 1, (tt % ntile) * tile - 1};
+}
+
+// Built once per plan, one block per setup tile: bound cos(theta) over the
+// region, pick the rings of both grids that can bracket its points, and take
+// the region centre's azimuth as reference.  z = cos(distance to the pole)
+// has no extremum inside the region unless a pole lies in it (then the range
+// opens up to it), so the region's boundary cells bound it to within half a
+// cell (the largest gap from a boundary point to the nearest boundary
+// centre); every point interpolated lies within half a cell of a cell centre.
+constexpr int kMetaBlock = 256;
+
+__global__ __launch_bounds__(kMetaBlock) void k_setup_meta(SetupArgs a) {
+  __shared__ double zred[2 * (kMetaBlock / 64)];
+  const int64_t lb = blockIdx.x;
+  const SetupTile st = setup_tile(lb, a.ntile, a.tile);
+  const int RR = a.tile + 2;
+  const double* R = a.rot + 9 * st.patch;
   const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
-  for (int r = threadIdx.x; r < RR; r += blockDim.x) {
-    sincos(th0 + (i0 + r + 0.5) * a.delta, &trig[4 * r], &trig[4 * r + 1]);
-    sincos(ph0 + (j0 + r + 0.5) * a.delta, &trig[4 * r + 2], &trig[4 * r + 3]);
-  }
-  for (int r = threadIdx.x; r < TILE; r += blockDim.x) {
-    const double* c = a.coef + 4 * (i0 + 1 + r);
-    prow[2 * r] = 1.0 / c[2];
-    prow[2 * r + 1] = 1.0 / c[3];
-  }
-  __syncthreads();
-  // z range of the region's cell centres.  z = cos(distance to the pole)
-  // has no extremum inside the region unless a pole lies in it (handled
-  // below), so the boundary cells bound it to within half a cell (the
-  // largest gap to a boundary point between two of them); every point
-  // interpolated lies within half a cell of a cell centre.
   double zlo = 2.0, zhi = -2.0;
   for (int idx = threadIdx.x; idx < 4 * (RR - 1); idx += blockDim.x) {
     const int side = idx / (RR - 1), r = idx % (RR - 1);
     const int li = side == 0 ? 0 : side == 1 ? r : side == 2 ? RR - 1 : RR - 1 - r;
     const int lj = side == 0 ? r : side == 1 ? RR - 1 : side == 2 ? RR - 1 - r : 0;
-    const double st = trig[4 * li], ct = trig[4 * li + 1];
-    const double z = R[2] * st * trig[4 * lj + 3] + R[5] * st * trig[4 * lj + 2] + R[8] * ct;
+    double s_t, c_t, s_p, c_p;
+    sincos(th0 + (st.i0 + li + 0.5) * a.delta, &s_t, &c_t);
+    sincos(ph0 + (st.j0 + lj + 0.5) * a.delta, &s_p, &c_p);
+    const double z = R[2] * s_t * c_p + R[5] * s_t * s_p + R[8] * c_t;
     zlo = fmin(zlo, z);
     zhi = fmax(zhi, z);
   }
@@ -259,54 +260,86 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
     zred[2 * (threadIdx.x >> 6) + 1] = zhi;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < kSetupBlock / 64; ++w) {
-      zlo = fmin(zlo, zred[2 * w]);
-      zhi = fmax(zhi, zred[2 * w + 1]);
-    }
-    // region centre; a pole closer to it than the region's side may lie in
-    // the region, and then opens the range up to it
-    double sc, cc, sp, cp;
-    sincos(th0 + (i0 + 0.5 * RR) * a.delta, &sc, &cc);
-    sincos(ph0 + (j0 + 0.5 * RR) * a.delta, &sp, &cp);
-    const double x = sc * cp, y = sc * sp;
-    const double zc = R[2] * x + R[5] * y + R[8] * cc;
-    const double cr = cos(RR * a.delta);
-    if (zc > cr) zhi = 1.0;
-    if (zc < -cr) zlo = -1.0;
-    const double lo = zlo - 2.0 * a.delta, hi = zhi + 2.0 * a.delta;
-    const hpx::GlobalRingTab gs{a.rs, 0.0}, gf{a.rf, 0.0};
-    const int bs = max(0, hpx::ring_above(gs, hi));
-    const int ts = min(a.rs.nring - 1, hpx::ring_above(gs, lo) + 1);
-    const int bf = max(0, hpx::ring_above(gf, hi));
-    const int tf = min(a.rf.nring - 1, hpx::ring_above(gf, lo) + 1);
-    rng[0] = bs; rng[1] = ts; rng[2] = bf; rng[3] = tf;
-    rng[4] = (ts - bs + 1 <= kRingCapS) && (tf - bf + 1 <= kRingCapF);
-    // reference azimuth: the region centre's, in [0, 2 pi)
-    const double vx = R[0] * x + R[3] * y + R[6] * cc;
-    const double vy = R[1] * x + R[4] * y + R[7] * cc;
-    const double rc = sqrt(vx * vx + vy * vy);
-    if (rc > 1e-12) {
-      double ph = atan2(vy, vx);
-      if (ph < 0) ph += 2.0 * kPi;
-      pref.phi = ph;
-      pref.c = vx / rc;
-      pref.s = vy / rc;
-    } else {
-      pref.phi = 0.0;
-      pref.c = 1.0;
-      pref.s = 0.0;
-    }
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < kMetaBlock / 64; ++w) {
+    zlo = fmin(zlo, zred[2 * w]);
+    zhi = fmax(zhi, zred[2 * w + 1]);
   }
-  __syncthreads();
-  const PhiRef pr = pref;
-  if (rng[4]) {
+  // region centre; a pole closer to it than the region's side may lie in it
+  double sc, cc, sp, cp;
+  sincos(th0 + (st.i0 + 0.5 * RR) * a.delta, &sc, &cc);
+  sincos(ph0 + (st.j0 + 0.5 * RR) * a.delta, &sp, &cp);
+  const double x = sc * cp, y = sc * sp;
+  const double zc = R[2] * x + R[5] * y + R[8] * cc;
+  const double cr = cos(RR * a.delta);
+  if (zc > cr) zhi = 1.0;
+  if (zc < -cr) zlo = -1.0;
+  const double lo = zlo - 2.0 * a.delta, hi = zhi + 2.0 * a.delta;
+  const hpx::GlobalRingTab gs{a.rs, 0.0}, gf{a.rf, 0.0};
+  SetupMeta m;
+  m.bs = max(0, hpx::ring_above(gs, hi));
+  m.ts = min(a.rs.nring - 1, hpx::ring_above(gs, lo) + 1);
+  m.bf = max(0, hpx::ring_above(gf, hi));
+  m.tf = min(a.rf.nring - 1, hpx::ring_above(gf, lo) + 1);
+  m.lds = (m.ts - m.bs + 1 <= kRingCapS) && (m.tf - m.bf + 1 <= kRingCapF);
+  m.pad = 0;
+  // reference azimuth: the region centre's, in [0, 2 pi)
+  const double vx = R[0] * x + R[3] * y + R[6] * cc;
+  const double vy = R[1] * x + R[4] * y + R[7] * cc;
+  const double rc = sqrt(vx * vx + vy * vy);
+  if (rc > 1e-12) {
+    double ph = atan2(vy, vx);
+    if (ph < 0) ph += 2.0 * kPi;
+    m.phi = ph;
+    m.c = vx / rc;
+    m.s = vy / rc;
+  } else {
+    m.phi = 0.0;
+    m.c = 1.0;
+    m.s = 0.0;
+  }
+  a.meta[lb] = m;
+}
+
+// One block per TILE x TILE tile (TILE = 64, or the whole patch if smaller),
+// sin/cos of theta' and phi' tabulated per row and column.  The block copies
+// the rings of both grids that its plan-time record names into LDS (or reads
+// the global tables when they do not fit).
+template <typename T, int TILE>
+__global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
+  constexpr int RR = TILE + 2;
+  __shared__ double shu[RR * RR];
+  __shared__ double trig[4 * RR];  // sin/cos th'_row, ph'_col
+  __shared__ double prow[2 * TILE];  // 1 / s_c, 1 / area of the tile's rows
+  __shared__ RingStore<kRingCapF> ringf;
+  __shared__ RingStore<kRingCapS> rings;
+  __shared__ T fshm[sizeof(T) == 4 ? TILE * TILE : 1];
+  T* fsh = sizeof(T) == 4 ? fshm : nullptr;
+  const int64_t lb = xcd_block();
+  const SetupTile st = setup_tile(lb, a.ntile, TILE);
+  const int64_t patch = st.patch;
+  const int i0 = st.i0, j0 = st.j0;
+  const double* R = a.rot + 9 * patch;
+  const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
+  const SetupMeta& m = a.meta[lb];
+  const PhiRef pr{m.phi, m.c, m.s};
+  for (int r = threadIdx.x; r < RR; r += blockDim.x) {
+    sincos(th0 + (i0 + r + 0.5) * a.delta, &trig[4 * r], &trig[4 * r + 1]);
+    sincos(ph0 + (j0 + r + 0.5) * a.delta, &trig[4 * r + 2], &trig[4 * r + 3]);
+  }
+  for (int r = threadIdx.x; r < TILE; r += blockDim.x) {
+    const double* c = a.coef + 4 * (i0 + 1 + r);
+    prow[2 * r] = 1.0 / c[2];
+    prow[2 * r + 1] = 1.0 / c[3];
+  }
+  if (m.lds) {
     hpx::LdsRingTab ts = rings.tab(), tf = ringf.tab();
-    ts.fill(a.rs, rng[0], rng[1], pr.phi);
-    tf.fill(a.rf, rng[2], rng[3], pr.phi);
+    ts.fill(a.rs, m.bs, m.ts, pr.phi);
+    tf.fill(a.rf, m.bf, m.tf, pr.phi);
     __syncthreads();
     setup_passes<T, TILE>(a, ts, tf, shu, fsh, trig, prow, R, pr, patch, i0, j0);
   } else {
+    __syncthreads();
     setup_passes<T, TILE>(a, hpx::GlobalRingTab{a.rs, pr.phi}, hpx::GlobalRingTab{a.rf, pr.phi},
                           shu, fsh, trig, prow, R, pr, patch, i0, j0);
   }
@@ -1309,6 +1342,25 @@ clm_status launch_tile(Plan* p, const TileArgs<T>& a, int64_t np, hipStream_t s)
   return fail(p, CLM_EUNSUPPORTED, "sweep count outside 1..4");
 }
 
+// The plan's patch geometry as the setup kernels take it.
+SetupArgs setup_geometry(const Plan* p) {
+  const clm_plan_desc& d = p->d;
+  SetupArgs a{};
+  a.n = p->n;
+  a.tile = p->n < kTile ? p->n : kTile;
+  a.ntile = p->n / a.tile;
+  a.L = p->L;
+  a.delta = p->delta;
+  a.rot = p->rot;
+  a.coef = p->coef + p->lev[0].crow;
+  a.rs = hpx::Rings{p->ring_s, p->ringi_s, p->ringx_s, p->nring_s, d.nside_sht};
+  a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->ringx_f, p->nring_f, d.nside_fine};
+  a.ring_shift = 0;
+  while ((d.nside_sht << a.ring_shift) < d.nside_fine) ++a.ring_shift;
+  a.meta = reinterpret_cast<SetupMeta*>(p->setup_meta);
+  return a;
+}
+
 template <typename T>
 clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
   const clm_plan_desc& d = p->d;
@@ -1317,18 +1369,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
   const int64_t np = p->nbundle;
   // patch setup
   {
-    SetupArgs a;
-    a.n = n;
-    a.tile = n < kTile ? n : kTile;
-    a.ntile = n / a.tile;
-    a.L = p->L;
-    a.delta = p->delta;
-    a.rot = p->rot;
-    a.coef = p->coef + p->lev[0].crow;
-    a.rs = hpx::Rings{p->ring_s, p->ringi_s, p->ringx_s, p->nring_s, d.nside_sht};
-    a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->ringx_f, p->nring_f, d.nside_fine};
-    a.ring_shift = 0;
-    while ((d.nside_sht << a.ring_shift) < d.nside_fine) ++a.ring_shift;
+    SetupArgs a = setup_geometry(p);
     a.psi_s = sl.psi_s;
     a.kappa = kappa;
     a.kappa_fp64 = kappa_fp64;
@@ -1563,6 +1604,20 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
 }
 
 }  // namespace
+
+int64_t setup_tiles(const Plan* p) {
+  const int tile = p->n < kTile ? p->n : kTile;
+  return p->nbundle * (p->n / tile) * (p->n / tile);
+}
+
+clm_status setup_tables(Plan* p, hipStream_t s) {
+  const SetupArgs a = setup_geometry(p);
+  const int64_t nt = setup_tiles(p);
+  if (nt == 0) return CLM_OK;
+  hipLaunchKernelGGL(k_setup_meta, dim3(unsigned(nt)), dim3(kMetaBlock), 0, s, a);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
 
 clm_status mg_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
   if (p->nlev > 16) return fail(p, CLM_EUNSUPPORTED, "too many multigrid levels");

@@ -38,6 +38,7 @@ Plan::~Plan() {
   f(deriv); f(fprime); f(dutmp); f(status_dev); f(iter_map); f(iter_alm);
   for (auto* q : ubar) f(q);
   f(ubar1b);
+  f(setup_meta);
   for (auto* q : rbar) f(q);
   for (auto* q : flev) f(q);
   for (auto* q : ulev) f(q);
@@ -506,6 +507,9 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
         p->ubar1b = q;
       }
     }
+    if ((s = alloc(p, &p->setup_meta, size_t(setup_tiles(p)) * kSetupMetaBytes)) != CLM_OK)
+      return bail(s);
+    if ((s = setup_tables(p, nullptr)) != CLM_OK) return bail(s);
   } else {
     if ((s = alloc(p, &p->deriv, size_t(p->npix_s) * 5)) != CLM_OK) return bail(s);
   }
