@@ -126,7 +126,8 @@ clm_status clm_plan_desc_default(clm_plan_desc* d, int32_t nside_fine);
 
 /* Create a plan on HIP device `device`: validates *desc, allocates all
  * workspace and builds the geometry tables (ring tables, Legendre starting
- * values, NESTED/RING maps, patch rotations, multigrid coefficients).
+ * values, NESTED/RING maps, patch rotations, multigrid coefficients, and
+ * per patch-setup tile its ring ranges and reference azimuth).
  * Synchronises the device once.  *out is NULL on failure. */
 clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out);
 clm_status clm_plan_destroy(clm_plan plan);
