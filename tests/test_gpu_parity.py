@@ -227,6 +227,36 @@ def test_mg_patch_potential_parity(clm, mg_case, n, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mg_wide_patch_global_ring_tables(clm, prec):
+    """Setup tiles whose region spans more rings than a block's LDS ring
+    stores hold (256 of the fine grid) interpolate from the global ring
+    tables.  Patches of about 1 rad (bundles at Nside 2, patch factor 2) on
+    a Nside 512 fine grid span some 700 fine rings each."""
+    Nf, Ns, lmax, Nb, n = 512, 32, 64, 2, 64
+    g = osht.alm2map(Nf, lmax, inputs.gaussian_alm(lmax, seed=5, sigma=0.5))
+    kap = np.exp(g) - np.mean(np.exp(g))
+    spec = omg.PatchSpec(Nf, Ns, lmax, Nb, factor=2, ncell=n, vcycles=2)
+    bl = [5, 20]
+    sol = omg.solve_plane(spec, kap, bl)
+    rt = hp.ring_table(Nf)
+    for b in bl:
+        th, _ = omg.patch_cell_dirs(spec, sol["patches"][b]["R"])
+        z = np.cos(th)
+        assert np.sum((rt["z"] >= z.min()) & (rt["z"] <= z.max())) > 256
+    plan = clm.Plan(Nf, nside_sht=Ns, lmax=lmax, nside_bundle=Nb, patch_factor=2,
+                    patch_cells=n, mg_vcycles=2, mg_prec=prec)
+    plan.poisson_solve(torch.from_numpy(kap).cuda())
+    tol_u = 1e-10 if prec == "fp64" else 1e-6
+    for b in bl:
+        pt = sol["patches"][b]
+        ref = (pt["u0"] + pt["du"])[1:-1, 1:-1]
+        got = plan.patch_potential(b, 1)[0].cpu().numpy()
+        assert report("wide patch %s b=%d" % (prec, b), rel(got, ref)) < tol_u, b
+    plan.sync_status()
+    plan.close()
+
+
 def test_mg_fp32_form_tracks_fp64_form(clm, mg_case):
     """The float32 multigrid form at 4 V-cycles of (2, 2) sweeps, where the
     finest level's post- and pre-smoothing run fused, against the float64
