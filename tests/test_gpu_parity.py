@@ -161,6 +161,27 @@ def test_sht_batched_matrix_core_forms(clm, form, tol):
     plan.close()
 
 
+def test_sht_matrix_core_several_batches(clm):
+    """18 planes: one full GEMM batch of 16 and a ragged batch of 2, each
+    plane against the FP64 oracle (the kappa offset and slot of the second
+    batch)."""
+    N, lmax, P = 16, 40, 18
+    maps = [osht.alm2map(N, lmax, inputs.gaussian_alm(lmax, seed=90 + i, amplitude=1.0))
+            for i in range(P)]
+    k = torch.from_numpy(np.stack(maps)).cuda()
+    plan = clm.Plan(N, nside_sht=N, lmax=lmax, solver="sht", max_planes=P, legendre_prec="fp32")
+    plan.poisson_solve(k)
+    worst = 0.0
+    for i in range(P):
+        ref = osht.poisson(lmax, osht.map2alm(N, lmax, maps[i] - maps[i].mean()))
+        e = rel(plan.psi_alm(i).cpu().numpy(), ref)
+        worst = max(worst, e)
+        assert e < 5e-6, (i, e)
+    report("sht_fp32 18 planes", worst)
+    plan.sync_status()
+    plan.close()
+
+
 @pytest.mark.parametrize("N", [512, 1024])
 def test_sht_matrix_core_large_against_fp64(clm, N):
     """Full-size ring counts (one ring block at Nside 512; two blocks whose
