@@ -278,6 +278,30 @@ def test_mg_wide_patch_global_ring_tables(clm, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mg_float32_kappa_input(clm, mg_case, prec):
+    """A float32 convergence map (the input type of the Nside 2048 workload):
+    the mean, the degrade to the SHT grid and the setup's fine-map gathers
+    read float32; the oracle takes the same values widened to float64."""
+    c = mg_case
+    n = 64
+    k32 = c["kap"].astype(np.float32)
+    spec = omg.PatchSpec(c["Nf"], c["Ns"], c["lmax"], c["Nb"], ncell=n, vcycles=3)
+    sol = omg.solve_plane(spec, k32.astype(np.float64), MG_BUNDLES[:3])
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=n, mg_vcycles=3, mg_prec=prec)
+    plan.poisson_solve(torch.from_numpy(k32).cuda())
+    assert rel(plan.psi_alm().cpu().numpy(), sol["psi_alm"]) < 1e-10
+    tol_u = 1e-10 if prec == "fp64" else 1e-6
+    for b in MG_BUNDLES[:3]:
+        pt = sol["patches"][b]
+        ref = (pt["u0"] + pt["du"])[1:-1, 1:-1]
+        got = plan.patch_potential(b, 1)[0].cpu().numpy()
+        assert report("mg_u float32 kappa %s b=%d" % (prec, b), rel(got, ref)) < tol_u, b
+    plan.sync_status()
+    plan.close()
+
+
 def test_mg_fp32_form_tracks_fp64_form(clm, mg_case):
     """The float32 multigrid form at 4 V-cycles of (2, 2) sweeps, where the
     finest level's post- and pre-smoothing run fused, against the float64
