@@ -302,6 +302,31 @@ def test_mg_float32_kappa_input(clm, mg_case, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("nu", [(1, 3), (3, 1), (1, 1), (4, 4)])
+def test_mg_sweep_counts(clm, mg_case, nu):
+    """Other (nu_pre, nu_post) than (2, 2) on a tiled finest level (n = 128):
+    fused post + pre smoothing when nu_pre + nu_post <= 4 (halo 2 (nu_pre +
+    nu_post) + 2), separate pre and post tiles otherwise; FP64 against the
+    oracle."""
+    c = mg_case
+    n = 128
+    spec = omg.PatchSpec(c["Nf"], c["Ns"], c["lmax"], c["Nb"], ncell=n, nu1=nu[0], nu2=nu[1],
+                         vcycles=3)
+    bl = MG_BUNDLES[1:4]
+    sol = omg.solve_plane(spec, c["kap"], bl)
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=n, mg_vcycles=3, mg_prec="fp64", nu_pre=nu[0], nu_post=nu[1])
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    for b in bl:
+        pt = sol["patches"][b]
+        dref = pt["du"][1:-1, 1:-1]
+        got = plan.patch_potential(b, 1)[0].cpu().numpy()
+        e = rel(got - pt["u0"][1:-1, 1:-1], dref)
+        assert report("mg_du nu=%s b=%d" % (nu, b), e) < 1e-8, b
+    plan.sync_status()
+    plan.close()
+
+
 def test_mg_fp32_form_tracks_fp64_form(clm, mg_case):
     """The float32 multigrid form at 4 V-cycles of (2, 2) sweeps, where the
     finest level's post- and pre-smoothing run fused, against the float64
