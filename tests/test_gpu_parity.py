@@ -327,6 +327,30 @@ def test_mg_sweep_counts(clm, mg_case, nu):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_mg_three_tile_levels(clm, mg_case, prec):
+    """n = 512: levels 512, 256 and 128 streamed as tiles (level 2 keeps its
+    own source and second iterate), 64 and below in LDS."""
+    c = mg_case
+    n = 512
+    spec = omg.PatchSpec(c["Nf"], c["Ns"], c["lmax"], c["Nb"], ncell=n, vcycles=2)
+    bl = [37, 100]
+    sol = omg.solve_plane(spec, c["kap"], bl)
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=n, mg_vcycles=2, mg_prec=prec)
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    for b in bl:
+        pt = sol["patches"][b]
+        ref = (pt["u0"] + pt["du"])[1:-1, 1:-1]
+        got = plan.patch_potential(b, 1)[0].cpu().numpy()
+        assert report("mg_u n=512 %s b=%d" % (prec, b), rel(got, ref)) < \
+            (1e-10 if prec == "fp64" else 1e-6), b
+        e = rel(got - pt["u0"][1:-1, 1:-1], pt["du"][1:-1, 1:-1])
+        assert report("mg_du n=512 %s b=%d" % (prec, b), e) < (1e-8 if prec == "fp64" else 2e-4)
+    plan.sync_status()
+    plan.close()
+
+
 def test_mg_fp32_form_tracks_fp64_form(clm, mg_case):
     """The float32 multigrid form at 4 V-cycles of (2, 2) sweeps, where the
     finest level's post- and pre-smoothing run fused, against the float64
