@@ -45,23 +45,38 @@ __device__ __forceinline__ double dpp_move(double v) {
       static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
-// Sum over the 64 lanes of a wave, returned wave-uniform: quad permutes and
-// row mirrors give every lane its row's sum, row broadcasts 15 and 31 carry
-// the lower rows into the last one, and lane 63 holds the total.  Register
-// moves only (the xor shuffles go through the LDS crossbar), so the
-// latency chain is short.
-__device__ __forceinline__ double wave_total(double v) {
-  v += dpp_move<0xB1>(v);        // quad_perm [1, 0, 3, 2]
-  v += dpp_move<0x4E>(v);        // quad_perm [2, 3, 0, 1]
-  v += dpp_move<0x141>(v);       // row_half_mirror
-  v += dpp_move<0x140>(v);       // row_mirror
-  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane(int(b), 63);
-  const unsigned hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
-  return __longlong_as_double(
-      static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+// Sums over the 64 lanes of a wave of 16 values per lane at once, by
+// recursive halving: at the exchanges with lane masks 32, 16 (shuffles), 15
+// and 7 (row mirror, half-row mirror) a lane keeps half of its values, the
+// half picked by one of its own lane bits (5, 4, 3, 2), adds the partner's
+// copy of that half and hands over the other; masks 2 and 1 (quad permutes)
+// then finish the sum.  The six masks span all six lane bits, so lane L ends
+// with the wave total of value L >> 2.  17 exchanges instead of the 96 of
+// sixteen separate reductions.
+__device__ __forceinline__ double wave_sum16(const double (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+  double v8[8], v4[4], v2[2];
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double send = b5 ? v[j] : v[j + 8], keep = b5 ? v[j + 8] : v[j];
+    v8[j] = keep + __shfl_xor(send, 32);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double send = b4 ? v8[j] : v8[j + 4], keep = b4 ? v8[j + 4] : v8[j];
+    v4[j] = keep + __shfl_xor(send, 16);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const double send = b3 ? v4[j] : v4[j + 2], keep = b3 ? v4[j + 2] : v4[j];
+    v2[j] = keep + dpp_move<0x140>(send);  // row_mirror: lane ^ 15 in its row
+  }
+  const double send = b2 ? v2[0] : v2[1], keep = b2 ? v2[1] : v2[0];
+  double t = keep + dpp_move<0x141>(send);  // row_half_mirror: lane ^ 7
+  t += dpp_move<0x4E>(t);                   // quad_perm [2, 3, 0, 1]: lane ^ 2
+  t += dpp_move<0xB1>(t);                   // quad_perm [1, 0, 3, 2]: lane ^ 1
+  return t;
 }
 
 // ---------------------------------------------------------------- mean
@@ -732,28 +747,36 @@ __global__ __launch_bounds__(leg_threads_max(RPT)) void k_analysis(const double*
   __syncthreads();
   for (int l0 = 0; l0 < nl; l0 += 64) {
     const int cnt = nl - l0 < 64 ? nl - l0 : 64;
-    for (int c = 0; c < cnt; ++c) {
-      const int dl = l0 + c;  // l - m
-      double sr = 0.0, si = 0.0;
+    // eight l at a time: their real and imaginary ring sums reduced over
+    // the wave together
+    for (int c0 = 0; c0 < cnt; c0 += 8) {
+      double acc[16];
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        if (dl == 1) {
-          // lambda_{m+1,m} = sqrt(2m+3) z lambda_mm
-          st[k].p2 = st[k].p1;
-          st[k].p1 = sqrt(2.0 * m + 3.0) * z[k] * st[k].p2;
-        } else if (dl >= 2) {
-          recur_step(st[k], z[k], a[dl], b[dl]);
+      for (int cc = 0; cc < 8; ++cc) {
+        const int dl = l0 + c0 + cc;  // l - m
+        double sr = 0.0, si = 0.0;
+        if (c0 + cc < cnt) {
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) {
+            if (dl == 1) {
+              // lambda_{m+1,m} = sqrt(2m+3) z lambda_mm
+              st[k].p2 = st[k].p1;
+              st[k].p1 = sqrt(2.0 * m + 3.0) * z[k] * st[k].p2;
+            } else if (dl >= 2) {
+              recur_step(st[k], z[k], a[dl], b[dl]);
+            }
+            const double v = recur_value(st[k]);
+            if (dl & 1) { sr += v * fmr[k]; si += v * fmi[k]; }
+            else        { sr += v * fpr[k]; si += v * fpi[k]; }
+          }
         }
-        const double v = recur_value(st[k]);
-        if (dl & 1) { sr += v * fmr[k]; si += v * fmi[k]; }
-        else        { sr += v * fpr[k]; si += v * fpi[k]; }
+        acc[2 * cc] = sr;
+        acc[2 * cc + 1] = si;
       }
-      sr = wave_total(sr);
-      si = wave_total(si);
-      if (lane == 0) {
-        part[(c * nw + wv) * 2] = sr;
-        part[(c * nw + wv) * 2 + 1] = si;
-      }
+      const double tot = wave_sum16(acc);
+      const int idx = lane >> 2;  // 2 cc + (0: real, 1: imaginary)
+      const int c = c0 + (idx >> 1);
+      if ((lane & 3) == 0 && c < cnt) part[(c * nw + wv) * 2 + (idx & 1)] = tot;
     }
     __syncthreads();
     if (threadIdx.x < cnt) {
