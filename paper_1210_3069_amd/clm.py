@@ -83,7 +83,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libcalclens_mi.so is not built: run __graft_entry__.build()")
+            raise RuntimeError("libcalclens_mi.so is not built: run python -m paper_1210_3069_amd.build")
         L = ctypes.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)
