@@ -29,7 +29,9 @@ sys.path.insert(0, ROOT)
 
 NF, NS, LMAX, NB, NCELL, VCYC = 2048, 256, 512, 32, 256, 4
 EPS_RULE = 0.1  # the typical convergence parameter of Sec. 3.2
-DCHI = 3054.70 / 20.0
+CHI_Z15 = 3054.70          # comoving distance to z = 1.5, h^-1 Mpc (flat, Omega_m 0.3)
+PLANES_TO_Z15 = 20
+DCHI = CHI_Z15 / PLANES_TO_Z15
 NGAL = 1_000_000
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30
@@ -238,12 +240,33 @@ def make_inputs(clm, torch, inputs, cosmo):
     return kappa, gal
 
 
-def run_form(clm, torch, kappa, gal, prec, steps, warmup, vcycles=VCYC, eps=0.1):
+def plane_distances(nplanes):
+    """Comoving distances of a run of lens planes equally spaced to z = 1.5,
+    chi_m = (m + 1/2) dchi for m = 0 .. N - 1, followed by the target
+    chi_N = (N + 1/2) dchi: N = 20 planes (dchi = 152.735 h^-1 Mpc), or more,
+    with a finer spacing, when more steps are timed."""
+    n = max(PLANES_TO_Z15, int(nplanes))
+    return (np.arange(n + 1) + 0.5) * (CHI_Z15 / n)
+
+
+def run_form(clm, torch, kappa, gal, prec, steps, warmup, vcycles=VCYC, eps=0.1,
+             stage_steps=0, timed_stages=None):
+    """Times `steps` lens-plane steps (solve, shear at all pixels, ray update,
+    galaxies of the shell) of one form on a fresh light cone.
+
+    The warmup runs first, on planes 0, 1, ... of its own pass (the rays are
+    reset when a pass reaches the last plane).  With stage_steps > 0 a second
+    pass of that many steps, every launch bracketed by HIP events, gives the
+    per-stage breakdown.  The timed pass then starts from reset rays and
+    galaxies; only the stages in `timed_stages` (a list, or a function of
+    the stage pass's events that returns one) carry events in it.
+    Returns (plan, rays, ms per step, wall s, events of the timed pass,
+    events of the stage pass)."""
     plan = clm.Plan(NF, nside_sht=NS, lmax=LMAX, nside_bundle=NB, patch_cells=NCELL,
                     mg_vcycles=vcycles, mg_eps=eps, mg_max_vcycles=20, mg_prec=prec)
     rays = plan.new_rays()
-    nplanes = warmup + steps
-    chi = (np.arange(nplanes + 1) + 0.5) * DCHI
+    chi = plane_distances(steps)
+    last = len(chi) - 2                       # index of the last plane
     gout = (torch.empty(2, plan.npix_fine, dtype=torch.float32, device="cuda"),
             torch.empty(3, plan.npix_fine, dtype=torch.float32, device="cuda"))
 
@@ -251,68 +274,143 @@ def run_form(clm, torch, kappa, gal, prec, steps, warmup, vcycles=VCYC, eps=0.1)
         plan.raytrace_planes(kappa, chi, m, rays, galaxies=gal)
         plan.shear_at_pixels(order="nested", fp64=False, out=gout)
 
-    for m in range(warmup):
+    def fresh():
+        plan.rays_init(rays)
+        gal["A"].zero_()
+
+    m = 0
+    for _ in range(warmup):
+        if m > last:
+            fresh()
+            m = 0
         step(m)
+        m += 1
     torch.cuda.synchronize()
     plan.sync_status()
-    plan.set_timing(True)
-    plan.get_timing()
+    stage_pass = {}
+    if stage_steps > 0:
+        fresh()
+        plan.set_timing(True)
+        plan.get_timing()
+        for k in range(stage_steps):
+            step(k)
+        stage_pass = plan.get_timing()
+        plan.set_timing(False)
+        plan.sync_status()
+    fresh()
+    if callable(timed_stages):
+        timed_stages = timed_stages(stage_pass)
+    if timed_stages:
+        plan.set_timing(True, stages=timed_stages)
+        plan.get_timing()
     stream = torch.cuda.current_stream()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall = time.perf_counter()
     t0.record(stream)
-    for m in range(warmup, warmup + steps):
-        step(m)
+    for k in range(steps):
+        step(k)
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall
     ms = t0.elapsed_time(t1) / steps
-    stages = plan.get_timing()
-    plan.set_timing(False)
+    timed = {}
+    if timed_stages:
+        timed = plan.get_timing()
+        plan.set_timing(False)
     plan.sync_status()
-    return plan, rays, ms, wall, stages
+    return plan, rays, ms, wall, timed, stage_pass
 
 
-def cpu_baseline(torch, kappa, plan64, sample_bundles):
-    """The FP64 oracle, as it stands, on a bounded sample of the same plane:
-    the full SHT stage, then patch setup + V-cycles + shear at the bundle's
-    pixels + one ray step for `sample_bundles` bundles, scaled to one plane."""
+_ORACLE = {}
+
+
+def _oracle_patch(b):
+    """One patch of the oracle (in a worker process, one thread): setup,
+    V-cycles, shear and one ray step at the bundle's pixels.  Returns the
+    bundle, the patch potential u0 + du and the seconds it took."""
     from threadpoolctl import threadpool_limits
     from oracle import healpix as hp
     from oracle import mg as omg
     from oracle import rays as orays
-    threadpool_limits(1)                 # the oracle as it stands, one core
-    kap = kappa.double().cpu().numpy()
-    spec = omg.PatchSpec(NF, NS, LMAX, NB, ncell=NCELL, vcycles=VCYC)
-    t = time.perf_counter()
-    mean, _, palm, psi = omg.sht_stage(spec, kap)
-    t_sht = time.perf_counter() - t
-    per = (NF // NB) ** 2
-    chi = np.array([0.5 * DCHI, 1.5 * DCHI])
-    t = time.perf_counter()
-    worst = 0.0
-    for b in sample_bundles:
-        R, u0, fp = omg.patch_setup(spec, b, kap, mean, psi)
-        du = omg.mg_solve(spec, fp)
+    o = _ORACLE
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        R, u0, fp = omg.patch_setup(o["spec"], b, o["kap"], o["mean"], o["psi"])
+        du = omg.mg_solve(o["spec"], fp)
         patch = dict(R=R, u0=u0, du=du)
+        per = (NF // NB) ** 2
         pix = np.arange(b * per, (b + 1) * per)
         z, ph, s = hp.pix2ang_nest(NF, pix)
         th = np.arctan2(s, z)
         for k in range(per):
-            g, U = omg.eval_point(spec, patch, th[k], ph[k])
-            r = orays.Ray(th[k], ph[k])
-            orays.ray_step(r, chi, 0, g, U)
-        ug = plan64.patch_potential(int(b), 1)[0].cpu().numpy()
-        ur = (u0 + du)[1:-1, 1:-1]
+            g, U = omg.eval_point(o["spec"], patch, th[k], ph[k])
+            orays.ray_step(orays.Ray(th[k], ph[k]), o["chi"], 0, g, U)
+        return int(b), (u0 + du)[1:-1, 1:-1], time.perf_counter() - t
+
+
+def host_cpu():
+    """(usable cores, CPU model) of this host; the cores are the process's
+    CPU affinity, capped at the 16 host cores that go with one GPU."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return min(n, 16), n, model
+
+
+def cpu_baseline(torch, kappa, plan64, nsample):
+    """The FP64 oracle, as it stands, on a bounded sample of the same plane:
+    the full SHT stage (numpy, one thread), then `nsample` patches evenly
+    spread over the sphere (setup, 4 V-cycles, shear and one ray step at the
+    bundle's pixels), spread over a pool of one-thread worker processes, one
+    per usable core; scaled to one plane.  The per-patch worker times also
+    give the one-core figure.  The GPU FP64 form's patch potentials are
+    compared with the oracle's on the same patches."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from oracle import mg as omg
+    cores, visible, model = host_cpu()
+    kap = kappa.double().cpu().numpy()
+    spec = omg.PatchSpec(NF, NS, LMAX, NB, ncell=NCELL, vcycles=VCYC)
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        mean, _, palm, psi = omg.sht_stage(spec, kap)
+        t_sht = time.perf_counter() - t
+    nb = 12 * NB * NB
+    sample = sorted({int(round(i * (nb - 1) / max(1, nsample - 1))) for i in range(nsample)})
+    _ORACLE.update(spec=spec, kap=kap, mean=mean, psi=psi,
+                   chi=np.array([0.5 * DCHI, 1.5 * DCHI]))
+    t = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map_async(_oracle_patch, sample, chunksize=1).get(timeout=600)
+    t_pool = time.perf_counter() - t
+    _ORACLE.clear()
+    worst = 0.0
+    for b, ur, _ in res:
+        ug = plan64.patch_potential(b, 1)[0].cpu().numpy()
         worst = max(worst, float(np.abs(ug - ur).max() / np.abs(ur).max()))
-    t_patch = (time.perf_counter() - t) / len(sample_bundles)
-    t_plane = t_sht + t_patch * 12 * NB * NB
-    return dict(value=1.0 / t_plane, unit="plane solves/s", cores=1, kind="oracle",
-                sample="full SHT stage (%.1f s) + %d of %d patches (setup, 4 V-cycles, "
-                       "shear and one ray step at their %d pixels; %.1f s each), scaled "
-                       "to one plane" % (t_sht, len(sample_bundles), 12 * NB * NB, per,
-                                         t_patch),
+    t_patch = float(np.mean([r[2] for r in res]))
+    t_plane = t_sht + t_pool / len(sample) * nb
+    t_plane_1 = t_sht + t_patch * nb
+    per = (NF // NB) ** 2
+    return dict(value=1.0 / t_plane, unit="plane solves/s", cores=cores, kind="oracle",
+                cpu_model=model, cpus_visible=visible,
+                value_one_core=1.0 / t_plane_1,
+                sample="full SHT stage on one thread (%.1f s) + %d of %d patches (setup, "
+                       "4 V-cycles, shear and one ray step at their %d pixels; %.2f s each "
+                       "on one core) over %d one-thread worker processes (%.1f s wall), "
+                       "scaled to one plane"
+                       % (t_sht, len(sample), nb, per, t_patch, cores, t_pool),
+                sampled_patches=sample[:8] + (["..."] if len(sample) > 8 else []),
                 gpu_fp64_vs_oracle_rel_err_u=worst)
 
 
@@ -339,9 +437,16 @@ def c3_run(clm, torch, inputs, cosmo, gal):
                     mg_vcycles=VCYC, mg_prec="fp32")
     rays = plan.new_rays()
     chi = (np.arange(nplanes + 1) + 0.5) * DCHI
+    # untimed pass over the first planes (kernel set-up), then the timed
+    # pass from reset rays with events around the ray update only; a third
+    # pass over 3 planes with every launch timed gives the stage breakdown
+    for m in range(2):
+        plan.raytrace_planes(kap[m], chi, m, rays, galaxies=gal)
+    plan.rays_init(rays)
     gal["A"].zero_()
     torch.cuda.synchronize()
-    plan.set_timing(True)
+    plan.sync_status()
+    plan.set_timing(True, stages=["ray_update"])
     plan.get_timing()
     stream = torch.cuda.current_stream()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -351,17 +456,26 @@ def c3_run(clm, torch, inputs, cosmo, gal):
     t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
-    stages = plan.get_timing()
+    ru = plan.get_timing().get("ray_update", (0.0, 1))
     plan.set_timing(False)
     plan.sync_status()
     npix = plan.npix_fine
     A = gal["A"].double()
-    ru = stages.get("ray_update", (0.0, 1))
+    rays2 = plan.new_rays()
+    plan.set_timing(True)
+    plan.get_timing()
+    for m in range(3):
+        plan.raytrace_planes(kap[m], chi, m, rays2)
+    stages = {k: (v[0] / 3.0, v[1] / 3.0) for k, v in plan.get_timing().items()}
+    plan.set_timing(False)
+    plan.sync_status()
+    del rays2
     out = dict(
         planes=nplanes, nside_sht=ns3, lmax=l3, ms_all_planes=ms, ms_per_plane=ms / nplanes,
         ray_plane_updates_per_s=dict(end_to_end=npix * nplanes / (ms * 1e-3),
                                      kernel_only=npix / (ru[0] / ru[1] * 1e-3)),
-        stage_ms={k: v[0] for k, v in stages.items()},
+        stage_ms_per_plane={k: v[0] for k, v in stages.items()},
+        stage_note="per plane, from a separate 3-plane pass with every launch timed",
         galaxies=int(gal["theta"].numel()),
         galaxies_with_A=int((A.abs().sum(0) > 0).sum()),
         galaxy_A_finite=bool(torch.isfinite(A).all()))
@@ -396,7 +510,8 @@ def c4_run(clm, torch, inputs):
                             legendre_prec=form)
             plan.poisson_solve(kap[n][:1])          # first call: lazy set-up
             torch.cuda.synchronize()
-            plan.set_timing(True)
+            # events around the matrix-core launches only (none in the FP64 form)
+            plan.set_timing(form != "fp64", stages=["sht_analysis_mfma", "sht_synthesis_mfma"])
             plan.get_timing()
             t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             t0.record()
@@ -533,14 +648,17 @@ def c5_run(clm, torch, inputs):
     return out
 
 
-def main():
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--stage-steps", type=int, default=5,
+                    help="steps of the separate pass with every launch timed (per-stage table)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=32,
+                    help="patches of the oracle's timed sample")
     ap.add_argument("--no-eps", action="store_true",
                     help="skip the run under the epsilon stopping rule")
     ap.add_argument("--no-c3", action="store_true",
@@ -557,7 +675,35 @@ def main():
                     help="print a per-kernel summary of a rocprofv3 --pmc run (no GPU)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FCMD", "WCMD"),
                     help="print the HBM traffic summary of two --pmc passes (no GPU)")
-    args = ap.parse_args()
+    return ap.parse_args(argv)
+
+
+def check_args(args):
+    """(exit status, message) for a request this benchmark cannot run, else
+    (0, None).  Any step and warmup counts are accepted: the timed steps are
+    the planes of one light cone (20 planes to z = 1.5, or a finer spacing
+    for more steps) and the warmup runs on its own passes."""
+    if args.gpus != 1:
+        return 2, ("bench.py runs on one GPU only: this build has no multi-GPU path "
+                   "(--gpus %d requested)" % args.gpus)
+    if args.steps < 1 or args.warmup < 0 or args.stage_steps < 0:
+        return 2, "--steps must be >= 1 and --warmup, --stage-steps >= 0"
+    return 0, None
+
+
+def dominant_stage(stage_pass, nsteps, nbundle, npix):
+    """The stage with a byte model that takes the most time per step."""
+    best, best_ms = None, -1.0
+    for k, (tot, cnt) in stage_pass.items():
+        if bytes_model(k, NCELL, nbundle, npix, VCYC, cnt / nsteps) is None:
+            continue
+        if tot / nsteps > best_ms:
+            best, best_ms = k, tot / nsteps
+    return best
+
+
+def main():
+    args = parse_args()
     if args.summarize_stats:
         sys.stdout.write(summarize_stats(*args.summarize_stats))
         return
@@ -567,13 +713,10 @@ def main():
     if args.summarize_pmc:
         sys.stdout.write(summarize_pmc(*args.summarize_pmc))
         return
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-    if args.warmup + args.steps > 19:
-        print("warmup + steps must stay below the 20 planes to z = 1.5", file=sys.stderr)
-        sys.exit(2)
+    rc, msg = check_args(args)
+    if rc:
+        print(msg, file=sys.stderr)
+        sys.exit(rc)
     import torch
     from paper_1210_3069_amd import clm, cosmo, inputs
     clm.lib()
@@ -581,41 +724,55 @@ def main():
     print("bench: generating inputs", file=sys.stderr, flush=True)
     kappa, gal = make_inputs(clm, torch, inputs, cosmo)
     torch.cuda.synchronize()
-    print("bench: fp32 form", file=sys.stderr, flush=True)
-    plan, rays, ms, wall, stages = run_form(clm, torch, kappa, gal, "fp32", args.steps,
-                                            args.warmup)
-    npix = plan.npix_fine
+    npix = 12 * NF * NF
     nbundle = 12 * NB * NB
+    S = max(1, min(args.stage_steps, args.steps)) if args.stage_steps else 1
+    # stage pass first (every launch timed), then the timed pass with events
+    # around the dominant kernel's launches only
+    print("bench: fp32 form (stage pass %d steps, then %d timed steps)" % (S, args.steps),
+          file=sys.stderr, flush=True)
+    picked = {}
+
+    def pick(stage_pass):
+        picked["dom"] = dominant_stage(stage_pass, S, nbundle, npix)
+        return [picked["dom"]]
+
+    plan, rays, ms, wall, timed, stages = run_form(clm, torch, kappa, gal, "fp32", args.steps,
+                                                   args.warmup, stage_steps=S,
+                                                   timed_stages=pick)
     sample = list(range(0, nbundle, 64))
     u32 = torch.stack([plan.patch_potential(b, 1)[0] for b in sample]).cpu()
     plan.close()
     del plan, rays
     torch.cuda.empty_cache()
+    print("bench: fp32 form %.3f ms/step" % ms, file=sys.stderr, flush=True)
 
     per_stage = {}
     for k, (tot, cnt) in stages.items():
-        per_stage[k] = dict(ms_per_step=tot / args.steps, launches_per_step=cnt / args.steps,
+        per_stage[k] = dict(ms_per_step=tot / S, launches_per_step=cnt / S,
                             ms_per_launch=tot / max(cnt, 1))
-        b = bytes_model(k, NCELL, nbundle, npix, VCYC, cnt / args.steps)
+        b = bytes_model(k, NCELL, nbundle, npix, VCYC, cnt / S)
         if b is not None:
             per_stage[k]["alg_GBps"] = b / (tot / cnt * 1e-3) / 1e9
-    lps = {k: v["launches_per_step"] for k, v in per_stage.items()}
-    dom = max((k for k in per_stage if bytes_model(k, NCELL, nbundle, npix, VCYC, lps[k])),
-              key=lambda k: per_stage[k]["ms_per_step"])
-    b_dom = bytes_model(dom, NCELL, nbundle, npix, VCYC, lps[dom])
-    achieved = per_stage[dom]["alg_GBps"]
+        t = read_traffic(k)
+        if t is not None:
+            per_stage[k]["hbm_GB_per_launch"] = t / 1e9
+            per_stage[k]["hbm_GBps"] = t / (per_stage[k]["ms_per_launch"] * 1e-3) / 1e9
+    dom = picked["dom"]
+    tot, cnt = timed[dom]
+    b_dom = bytes_model(dom, NCELL, nbundle, npix, VCYC, cnt / args.steps)
+    ms_launch = tot / cnt
+    achieved = b_dom / (ms_launch * 1e-3) / 1e9
     traffic = read_traffic(dom)
     roofline = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS,
                     traffic=None if traffic is None else traffic / 1e9,
                     traffic_unit="GB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
-                    alg_bytes_per_launch=b_dom,
-                    ms_per_launch=per_stage[dom]["ms_per_launch"])
-    for k in per_stage:
-        t = read_traffic(k)
-        if t is not None:
-            per_stage[k]["hbm_GB_per_launch"] = t / 1e9
-            per_stage[k]["hbm_GBps"] = t / (per_stage[k]["ms_per_launch"] * 1e-3) / 1e9
+                    alg_bytes_per_launch=b_dom, ms_per_launch=ms_launch,
+                    launches_timed=int(cnt),
+                    timing="HIP events around each launch of this kernel, on its stream, "
+                           "over the timed steps")
+    ru = stages.get("ray_update", (0.0, 1))
 
     out = {
         "metric": "SHT+MG plane solves/s @Nside 2048",
@@ -637,32 +794,38 @@ def main():
                                "+ MG 12288 patches 256^2, 4 V-cycles (2,2) + shear at "
                                "50.3M pixels + 50.3M-ray update + 1e6 galaxies",
                    "nside_fine": NF, "nside_sht": NS, "lmax": LMAX, "nside_bundle": NB,
-                   "patch_cells": NCELL, "vcycles": VCYC, "rays": npix, "galaxies": NGAL},
+                   "patch_cells": NCELL, "vcycles": VCYC, "rays": npix, "galaxies": NGAL,
+                   "planes_in_light_cone": len(plane_distances(args.steps)) - 1},
         "ray_plane_updates_per_s": {
             "end_to_end": npix * 1000.0 / ms,
-            "kernel_only": npix / (per_stage["ray_update"]["ms_per_launch"] * 1e-3)},
+            "kernel_only": npix / (ru[0] / max(ru[1], 1) * 1e-3)},
         "stages": per_stage,
+        "stage_pass": {"steps": S, "note": "separate pass with HIP events around every launch",
+                       "ms_per_step_sum_of_stages": sum(v["ms_per_step"] for v in per_stage.values())},
         "roofline": roofline,
     }
     if not args.no_fp64:
         print("bench: fp64 form", file=sys.stderr, flush=True)
-        plan64, rays64, ms64, _, _ = run_form(clm, torch, kappa, gal, "fp64", args.steps,
-                                              args.warmup)
+        plan64, rays64, ms64, _, _, _ = run_form(clm, torch, kappa, gal, "fp64", args.steps,
+                                                 args.warmup)
         u64 = torch.stack([plan64.patch_potential(b, 1)[0] for b in sample]).cpu()
         d = (u32 - u64).double()
         out["fp64_form"] = dict(ms_per_step=ms64, value=1000.0 / ms64,
                                 fp32_vs_fp64_rel_l2_u=float(d.norm() / u64.norm()),
                                 sampled_patches=len(sample))
+        del rays64
         if not args.no_cpu_baseline:
             print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-            out["cpu_baseline"] = cpu_baseline(torch, kappa, plan64,
-                                               sample[: max(1, args.cpu_sample)])
+            out["cpu_baseline"] = cpu_baseline(torch, kappa, plan64, max(1, args.cpu_sample))
         plan64.close()
+        del plan64
+        torch.cuda.empty_cache()
     if not args.no_eps:
         # the stopping rule of Sec. 3.2 in place of the fixed cycle count
         print("bench: epsilon rule", file=sys.stderr, flush=True)
-        pe, re_, mse, _, st_e = run_form(clm, torch, kappa, gal, "fp32", args.steps,
-                                         args.warmup, vcycles=0, eps=EPS_RULE)
+        pe, re_, mse, _, st_e, _ = run_form(clm, torch, kappa, gal, "fp32", args.steps,
+                                            args.warmup, vcycles=0, eps=EPS_RULE,
+                                            timed_stages=["mg_eps"])
         e, k = (t.cpu().numpy() for t in pe.mg_convergence())
         ue = torch.stack([pe.patch_potential(b, 1)[0] for b in sample]).cpu()
         d = (ue - u32).double()

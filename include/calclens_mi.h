@@ -134,7 +134,12 @@ clm_status clm_plan_destroy(clm_plan plan);
 const char* clm_status_string(clm_status s);
 /* Copy the last error text of the plan (NUL-terminated, truncated to len). */
 clm_status clm_plan_last_error(clm_plan plan, char* buf_host, size_t len);
-/* Synchronise `stream`, return and clear the status latched by kernels. */
+/* Synchronise `stream`, return and clear the status latched by kernels.
+ * CLM_ENONFINITE is latched when the sum of a convergence map handed to a
+ * solve is not finite (a NaN or infinite pixel) and, under the epsilon
+ * rule, when a patch's residual or truncation norm is not finite (that
+ * patch then stops); the solve still runs to its end and its outputs carry
+ * the non-finite values. */
 clm_status clm_plan_sync_status(clm_plan plan, hipStream_t stream);
 /* Bytes of device workspace held by the plan. */
 size_t clm_plan_workspace_bytes(clm_plan plan);
@@ -154,6 +159,17 @@ clm_status clm_plan_get_desc(clm_plan plan, clm_plan_desc* out_host);
 clm_status clm_plan_set_timing(clm_plan plan, int32_t enable);
 clm_status clm_plan_get_timing(clm_plan plan, char* names_host, size_t len, double* ms_host,
                                int64_t* count_host, int32_t max_stages, int32_t* nstages_host);
+/* Restrict the timing to the stages named in the comma-separated list
+ * stages_host (NULL or "" = every stage), so that a timed run carries events
+ * around the launches of interest only.  Takes effect for later launches. */
+clm_status clm_plan_set_timing_stages(clm_plan plan, const char* stages_host);
+/* The per-stage totals (ms) of clm_plan_get_timing without names or counts:
+ * ms_per_stage_host[i] for i < nstages, stage i named by
+ * clm_plan_stage_name(plan, i) (0 beyond the stages seen); synchronises and
+ * resets the accumulators like clm_plan_get_timing. */
+clm_status clm_plan_timings(clm_plan plan, double* ms_per_stage_host, int32_t nstages);
+/* Name of timing stage i, or NULL; the string is owned by the plan. */
+const char* clm_plan_stage_name(clm_plan plan, int32_t i);
 
 /*
  * Synthesis of a real field from a_lm (Sec. 3.2, the SHT synthesis):
@@ -306,6 +322,21 @@ clm_status clm_ray_update(clm_plan plan, int32_t slot, const double* chi_host, i
 clm_status clm_galaxies_shell(clm_plan plan, const double* chi_host, int32_t nchi, int32_t k,
                               double curvature_K, const clm_rays* rays,
                               const clm_galaxies* galaxies, hipStream_t stream);
+
+/*
+ * The reduced galaxy step of App. D (eq. gatraj) for the shell the rays
+ * have just reached: after a clm_ray_update or clm_raytrace_planes through
+ * plane m, the rays hold A^(k) (rays->A) and A^(k-1) (rays->A_prev) for
+ * k = m + 1, and the galaxies (theta_dev, phi_dev, chi_dev: [ngal] float64)
+ * whose chi lies in shell k get A_g_dev [4][ngal] (float32, row-major 2 x 2);
+ * the others are left untouched.  The distances and curvature are those of
+ * that latest ray update (kept by the plan).  CLM_EINVAL before the first
+ * ray update after plan creation or clm_rays_init.  Asynchronous on
+ * `stream`.
+ */
+clm_status clm_galaxies_reduced(clm_plan plan, const clm_rays* rays, const double* theta_dev,
+                                const double* phi_dev, const double* chi_dev, int64_t ngal,
+                                float* A_g_dev, hipStream_t stream);
 
 /*
  * Multigrid convergence of the latest SHT+MG solve: per patch (bundle index

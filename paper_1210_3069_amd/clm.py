@@ -73,6 +73,10 @@ _SIGS = {
     "clm_poisson_adjoint": (_P, _I32, _P, _P),
     "clm_get_mg_convergence": (_P, _P, _P, _P),
     "clm_plan_set_timing": (_P, _I32),
+    "clm_plan_set_timing_stages": (_P, ctypes.c_char_p),
+    "clm_plan_timings": (_P, ctypes.POINTER(_D), _I32),
+    "clm_plan_stage_name": (_P, _I32),
+    "clm_galaxies_reduced": (_P, ctypes.POINTER(Rays), _P, _P, _P, _I64, _P, _P),
     "clm_plan_get_timing": (_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_D),
                             ctypes.POINTER(_I64), _I32, ctypes.POINTER(_I32)),
 }
@@ -91,6 +95,7 @@ def lib():
             f.restype = ctypes.c_int32
         L.clm_status_string.restype = ctypes.c_char_p
         L.clm_plan_workspace_bytes.restype = ctypes.c_size_t
+        L.clm_plan_stage_name.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -178,9 +183,25 @@ class Plan:
     def workspace_bytes(self):
         return lib().clm_plan_workspace_bytes(self.h)
 
-    def set_timing(self, enable=True):
-        """Bracket every kernel launch of this plan with HIP events."""
+    def set_timing(self, enable=True, stages=None):
+        """Bracket the kernel launches of this plan with HIP events: every
+        stage, or only those named in `stages` (an iterable of names)."""
+        sel = None if not stages else ",".join(stages).encode()
+        self._check(lib().clm_plan_set_timing_stages(self.h, sel), "set_timing_stages")
         self._check(lib().clm_plan_set_timing(self.h, int(enable)), "set_timing")
+
+    def timings(self, nstages=64):
+        """{stage: total ms} since the last reset, through clm_plan_timings
+        and clm_plan_stage_name (synchronises, resets)."""
+        ms = (ctypes.c_double * nstages)()
+        self._check(lib().clm_plan_timings(self.h, ms, nstages), "timings")
+        out = {}
+        for i in range(nstages):
+            nm = lib().clm_plan_stage_name(self.h, i)
+            if nm is None:
+                break
+            out[nm.decode()] = ms[i]
+        return out
 
     def get_timing(self):
         """{stage: (total ms, launches)} since the last call (synchronises)."""
@@ -324,6 +345,19 @@ class Plan:
         self._check(lib().clm_galaxies_shell(self.h, cp, chi.size, k, K, ctypes.byref(s),
                                              ctypes.byref(g), _stream()), "galaxies_shell")
 
+    def galaxies(self, rays, galaxies):
+        """eq. gatraj for the galaxies of the shell the rays have just
+        reached (distances of the latest ray update), through
+        clm_galaxies_reduced."""
+        s = self._rays_struct(rays)
+        for k in ("theta", "phi", "chi"):
+            _dev(galaxies[k], torch.float64)
+        _dev(galaxies["A"], torch.float32)
+        self._check(lib().clm_galaxies_reduced(self.h, ctypes.byref(s), _ptr(galaxies["theta"]),
+                                       _ptr(galaxies["phi"]), _ptr(galaxies["chi"]),
+                                       galaxies["theta"].numel(), _ptr(galaxies["A"]),
+                                       _stream()), "galaxies")
+
     def ray_update(self, chi, m, rays, slot=0, K=0.0):
         chi = np.ascontiguousarray(chi, dtype=np.float64)
         s = self._rays_struct(rays)
@@ -345,6 +379,7 @@ class PoissonShearFn(torch.autograd.Function):
         plan.poisson_solve(kappa.detach().contiguous(), first_slot=slot)
         g, h = plan.shear_from_potential(theta, phi, slot=slot, fp64=True)
         ctx.plan, ctx.slot = plan, slot
+        ctx.kappa_shape = kappa.shape
         ctx.save_for_backward(theta, phi)
         return g, h
 
@@ -356,4 +391,5 @@ class PoissonShearFn(torch.autograd.Function):
         dh = torch.zeros(3, theta.numel(), dtype=torch.float64, device=theta.device) \
             if dh is None else dh.contiguous().double()
         ctx.plan.shear_adjoint(theta, phi, dg, dh, slot=ctx.slot)
-        return ctx.plan.poisson_adjoint(slot=ctx.slot), None, None, None, None
+        grad = ctx.plan.poisson_adjoint(slot=ctx.slot)
+        return grad.view(ctx.kappa_shape), None, None, None, None

@@ -120,8 +120,22 @@ struct Plan {
 
   std::vector<Slot> slots;
 
-  // per-stage timing (off unless enabled)
+  // the distances, curvature and plane of the latest ray update, for the
+  // galaxy step of the shell the rays have just reached
+  std::vector<double> ray_chi;
+  double ray_K = 0.0;
+  int ray_plane = -1;
+
+  // per-stage timing (off unless enabled); a non-empty filter restricts it
+  // to the stages named there
   bool timing = false;
+  std::vector<std::string> timing_only;
+  bool timed_stage(const char* name) const {
+    if (timing_only.empty()) return true;
+    for (const auto& t : timing_only)
+      if (t == name) return true;
+    return false;
+  }
   std::vector<std::string> stage_names;
   struct Rec { int stage; hipEvent_t a, b; };
   std::vector<Rec> recs;
@@ -139,7 +153,7 @@ struct TimedLaunch {
   int stage = -1;
   hipEvent_t a = nullptr;
   TimedLaunch(Plan* p_, hipStream_t s_, const char* name) : p(p_), s(s_) {
-    if (!p->timing) return;
+    if (!p->timing || !p->timed_stage(name)) return;
     stage = p->stage_id(name);
     a = p->take_event();
     if (a) (void)hipEventRecord(a, s);

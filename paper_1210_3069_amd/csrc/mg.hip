@@ -1235,6 +1235,7 @@ struct EpsFinal {
   int* cycles;
   double* eps_out;
   int* active;          // patches still above the threshold (added to)
+  int* status;          // latched conditions (ST_NONFINITE)
 };
 
 // one wave per patch: partial sums added in a fixed order
@@ -1251,7 +1252,11 @@ __global__ __launch_bounds__(64) void k_mg_eps_final(EpsFinal a) {
   const double e = nt > 0.0 ? nr / nt : (nr > 0.0 ? INFINITY : 0.0);
   a.eps_out[patch] = e;
   a.cycles[patch] = a.cycle;
-  if (e < a.eps)
+  if (!isfinite(v[0]) || !isfinite(v[2])) {
+    // a non-finite residual or truncation norm: latch it and stop the patch
+    atomicOr(a.status, ST_NONFINITE);
+    a.done[patch] = 1;
+  } else if (e < a.eps)
     a.done[patch] = 1;
   else
     atomicAdd(a.active, 1);
@@ -1457,6 +1462,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     g.cycles = p->mg_cycles_dev;
     g.eps_out = p->mg_eps_dev;
     g.active = p->mg_active_dev;
+    g.status = p->status_dev;
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, int64_t(1), 0, p->mg_active_dev);
     {
       CLM_TIMED(p, s, "mg_eps");

@@ -548,6 +548,41 @@ clm_status clm_plan_set_timing(clm_plan plan, int32_t enable) {
   return CLM_OK;
 }
 
+clm_status clm_plan_set_timing_stages(clm_plan plan, const char* stages) {
+  if (!plan) return CLM_EINVAL;
+  plan->timing_only.clear();
+  if (!stages) return CLM_OK;
+  std::string cur;
+  for (const char* c = stages;; ++c) {
+    if (*c == ',' || *c == '\0') {
+      if (!cur.empty()) plan->timing_only.push_back(cur);
+      cur.clear();
+      if (*c == '\0') break;
+    } else {
+      cur += *c;
+    }
+  }
+  return CLM_OK;
+}
+
+clm_status clm_plan_timings(clm_plan plan, double* ms_per_stage, int32_t nstages) {
+  if (!plan || !ms_per_stage || nstages < 0) return CLM_EINVAL;
+  // the per-stage totals in the order of clm_plan_stage_name, then reset
+  std::vector<double> ms(64, 0.0);
+  std::vector<int64_t> cnt(64, 0);
+  char names[4096];
+  int32_t got = 0;
+  const clm_status st = clm_plan_get_timing(plan, names, sizeof names, ms.data(), cnt.data(),
+                                            64, &got);
+  for (int i = 0; i < nstages; ++i) ms_per_stage[i] = i < got ? ms[i] : 0.0;
+  return st;
+}
+
+const char* clm_plan_stage_name(clm_plan plan, int32_t i) {
+  if (!plan || i < 0 || i >= int32_t(plan->stage_names.size())) return nullptr;
+  return plan->stage_names[size_t(i)].c_str();
+}
+
 clm_status clm_plan_get_timing(clm_plan plan, char* names, size_t len, double* ms,
                                int64_t* count, int32_t max_stages, int32_t* nstages) {
   if (!plan || !names || len == 0 || !ms || !count || !nstages || max_stages < 1)
@@ -694,6 +729,7 @@ clm_status clm_rays_init(clm_plan plan, const clm_rays* rays, hipStream_t stream
   if (!plan || !rays || rays->n != plan->npix_f || !rays->theta || !rays->phi || !rays->beta ||
       !rays->A || !rays->A_prev)
     return CLM_EINVAL;
+  plan->ray_plane = -1;
   return rays_init(plan, rays, stream);
 }
 
@@ -703,7 +739,29 @@ clm_status clm_ray_update(clm_plan plan, int32_t slot, const double* chi, int32_
       slot >= plan->d.max_planes || m < 0 || m + 1 >= nchi)
     return CLM_EINVAL;
   if (!plan->mg) return CLM_EUNSUPPORTED;
-  return ray_update(plan, slot, chi, nchi, m, K, rays, stream);
+  const clm_status s = ray_update(plan, slot, chi, nchi, m, K, rays, stream);
+  if (s == CLM_OK) {
+    plan->ray_chi.assign(chi, chi + nchi);
+    plan->ray_K = K;
+    plan->ray_plane = m;
+  }
+  return s;
+}
+
+clm_status clm_galaxies_reduced(clm_plan plan, const clm_rays* rays, const double* theta,
+                                const double* phi, const double* chi_g, int64_t ngal,
+                                float* A_g, hipStream_t stream) {
+  if (!plan || !rays || rays->n != plan->npix_f || ngal < 0 ||
+      (ngal > 0 && (!theta || !phi || !chi_g || !A_g)))
+    return CLM_EINVAL;
+  Plan* p = plan;
+  if (p->ray_plane < 0)
+    return fail(p, CLM_EINVAL, "clm_galaxies_reduced needs a prior ray update (its distances)");
+  if (ngal == 0) return CLM_OK;
+  CLM_HIP(hipSetDevice(p->device));
+  clm_galaxies g{theta, phi, chi_g, A_g, ngal};
+  return galaxies_shell(p, p->ray_chi.data(), int(p->ray_chi.size()), p->ray_plane + 1,
+                        p->ray_K, rays, &g, stream);
 }
 
 clm_status clm_galaxies_shell(clm_plan plan, const double* chi, int32_t nchi, int32_t k,
@@ -746,6 +804,9 @@ clm_status clm_raytrace_planes(clm_plan plan, const void* kappa, int32_t kappa_i
     if ((s = sht_solve(p, kp, kappa_is_fp64, 0, stream)) != CLM_OK) return s;
     if ((s = mg_solve(p, kp, kappa_is_fp64, 0, stream)) != CLM_OK) return s;
     if ((s = ray_update(p, 0, chi, nchi, m, K, rays, stream)) != CLM_OK) return s;
+    p->ray_chi.assign(chi, chi + nchi);
+    p->ray_K = K;
+    p->ray_plane = m;
     if (gal && gal->n > 0) {
       if ((s = galaxies_shell(p, chi, nchi, m + 1, K, rays, gal, stream)) != CLM_OK) return s;
     }

@@ -97,7 +97,9 @@ __global__ void k_partial_sum(const T* x, int64_t n, double* out) {
   }
 }
 
-__global__ void k_final_mean(double* red, int nb, double inv_n) {
+// Also latches ST_NONFINITE when the sum is not finite: a NaN or infinite
+// convergence value (or an overflowing sum) anywhere in the map.
+__global__ void k_final_mean(double* red, int nb, double inv_n, int* status) {
   __shared__ double sh[kBlock / 64];
   double acc = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += red[i];
@@ -108,6 +110,7 @@ __global__ void k_final_mean(double* red, int nb, double inv_n) {
     double s = 0.0;
     for (int w = 0; w < kBlock / 64; ++w) s += sh[w];
     red[1023] = s * inv_n;
+    if (!isfinite(s)) atomicOr(status, ST_NONFINITE);
   }
 }
 
@@ -1075,7 +1078,7 @@ clm_status plane_mean(Plan* p, const void* kappa, int kappa_fp64, hipStream_t s)
   {
     CLM_TIMED(p, s, "mean");
     hipLaunchKernelGGL(k_final_mean, dim3(1), dim3(kBlock), 0, s, p->red, nb,
-                       1.0 / double(p->npix_f));
+                       1.0 / double(p->npix_f), p->status_dev);
   }
   CLM_LAUNCH_CHECK();
   return CLM_OK;

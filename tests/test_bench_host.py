@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -14,7 +15,8 @@ import bench  # noqa: E402
 
 def test_entry_points_present():
     for name in ("bytes_model", "make_inputs", "run_form", "cpu_baseline", "main",
-                 "summarize_stats", "summarize_pmc", "read_traffic", "stage_kernels"):
+                 "summarize_stats", "summarize_pmc", "read_traffic", "stage_kernels",
+                 "parse_args", "check_args", "plane_distances", "dominant_stage"):
         assert callable(getattr(bench, name)), name
 
 
@@ -73,3 +75,47 @@ def test_multi_gpu_request_exits():
                        capture_output=True, text=True, timeout=60)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("argv", [["--gpus", "1", "--steps", "20", "--warmup", "5"],
+                                  [], ["--steps", "40", "--warmup", "30"],
+                                  ["--steps", "1", "--warmup", "0"]])
+def test_driver_arguments_accepted(argv):
+    """The driver's command line (and other step counts) passes the checks
+    that run before any GPU work."""
+    args = bench.parse_args(argv)
+    assert bench.check_args(args) == (0, None)
+
+
+def test_defaults_match_driver_command():
+    args = bench.parse_args([])
+    assert (args.gpus, args.steps, args.warmup) == (1, 20, 5)
+
+
+def test_bad_counts_rejected():
+    assert bench.check_args(bench.parse_args(["--steps", "0"]))[0] == 2
+    assert bench.check_args(bench.parse_args(["--gpus", "8"]))[0] == 2
+
+
+def test_plane_distances():
+    chi = bench.plane_distances(20)
+    assert len(chi) == 21
+    assert chi[1] - chi[0] == pytest.approx(3054.70 / 20)
+    assert chi[0] == pytest.approx(0.5 * 3054.70 / 20)
+    # fewer steps keep the 20-plane light cone; more steps refine the spacing
+    assert len(bench.plane_distances(5)) == 21
+    chi = bench.plane_distances(40)
+    assert len(chi) == 41 and chi[-2] == pytest.approx(3054.70 * 39.5 / 40)
+    assert (np.diff(chi) > 0).all()
+
+
+def test_dominant_stage():
+    st = {"mg_postpre_l0": (12.9, 3), "patch_setup": (11.3, 1), "mean": (50.0, 2),
+          "ray_update": (2.6, 1)}
+    # "mean" has no byte model and is never the roofline kernel
+    assert bench.dominant_stage(st, 1, 12288, 12 * 2048 ** 2) == "mg_postpre_l0"
+
+
+def test_host_cpu():
+    cores, visible, model = bench.host_cpu()
+    assert 1 <= cores <= 16 and cores <= visible and isinstance(model, str)
