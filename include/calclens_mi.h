@@ -183,6 +183,23 @@ clm_status clm_alm2map(const double* alm_dev, int32_t lmax, int32_t nside,
                        double* map_dev, hipStream_t stream);
 
 /*
+ * clm_alm2map for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, result and layout as clm_alm2map, but nothing is
+ * allocated, freed or synchronised: all tables and intermediates live in a
+ * 16 MiB file-scope device array, one per GPU, held by the library until the
+ * process ends, and rebuilt by every call on `stream`.  Limits: 1 <= lmax
+ * <= 512 and nside a power of two <= 256; larger requests return
+ * CLM_EUNSUPPORTED and launch nothing (CLM_EINVAL for null pointers, lmax < 1
+ * or an nside that is not a power of two).  Calls on one GPU share that
+ * array, so calls that overlap in time on one GPU (other streams, other
+ * threads) race and must be ordered by the caller.  Asynchronous on
+ * `stream`, so it may be captured in a HIP graph.
+ */
+clm_status clm_alm2map_noalloc(const double* alm_dev, int32_t lmax, int32_t nside,
+                               double* map_dev, hipStream_t stream);
+
+/*
  * The plane Poisson solve (Sec. 3.2).  kappa_dev: [nplanes][12 nside_fine^2]
  * standard convergence, RING order, float64 (kappa_is_fp64 = 1) or float32.
  * Plane p of the batch goes to solution slot first_slot + p

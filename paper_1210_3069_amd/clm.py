@@ -57,6 +57,7 @@ _SIGS = {
     "clm_plan_workspace_bytes": (_P,),
     "clm_plan_get_desc": (_P, ctypes.POINTER(PlanDesc)),
     "clm_alm2map": (_P, _I32, _I32, _P, _P),
+    "clm_alm2map_noalloc": (_P, _I32, _I32, _P, _P),
     "clm_poisson_solve": (_P, _P, _I32, _I32, _I32, _P),
     "clm_get_psi_alm": (_P, _I32, _P, _P),
     "clm_get_psi_map": (_P, _I32, _P, _P),
@@ -125,6 +126,27 @@ def alm2map(alm, lmax, nside):
     st = lib().clm_alm2map(_ptr(a), lmax, nside, _ptr(out), _stream())
     if st != CLM_OK:
         raise ClmError(st, "clm_alm2map failed: %s" % lib().clm_status_string(st).decode())
+    return out
+
+
+NOALLOC_MAX_NSIDE, NOALLOC_MAX_LMAX = 256, 512
+
+
+def alm2map_noalloc(alm, lmax, nside, out):
+    """alm2map into the caller's `out` (float64 [12 nside^2] on the GPU)
+    through clm_alm2map_noalloc: the library allocates nothing and the call
+    may be captured in a graph (nside <= 256, lmax <= 512)."""
+    a = torch.view_as_real(_dev(alm, torch.complex128))
+    _dev(out, torch.float64)
+    if out.numel() != 12 * nside * nside:
+        raise ValueError("out has %d values, expected %d" % (out.numel(), 12 * nside * nside))
+    st = lib().clm_alm2map_noalloc(_ptr(a), lmax, nside, _ptr(out), _stream())
+    if st == CLM_EUNSUPPORTED:
+        raise ClmError(st, "clm_alm2map_noalloc: nside %d / lmax %d beyond its limits "
+                           "(nside <= %d, lmax <= %d)" % (nside, lmax, NOALLOC_MAX_NSIDE,
+                                                          NOALLOC_MAX_LMAX))
+    if st != CLM_OK:
+        raise ClmError(st, "clm_alm2map_noalloc failed: %s" % lib().clm_status_string(st).decode())
     return out
 
 

@@ -203,6 +203,10 @@ inline clm_status lds_opt_in(Plan* p, const void* fn, size_t bytes) {
   return CLM_OK;
 }
 
+// lambda_mm(theta) of the north rings (rt: ring table, H rings), mantissa
+// and scale exponent [lmax+1][H] (sht.hip; launched at plan creation).
+__global__ void k_lambda_mm(const double* rt, int H, int lmax, double* mant, int* scale);
+
 // ---- stage launchers (each returns CLM_OK or an error recorded in p->err)
 clm_status build_tables(Plan* p);                       // plan.hip
 clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot,

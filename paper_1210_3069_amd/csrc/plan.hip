@@ -104,29 +104,6 @@ void host_rings(int N, std::vector<double>& rt, std::vector<int>& ri, std::vecto
   rx[2 * nr + 1] = 1.0 / (pi - rt[4 * (nr - 1) + 2]);
 }
 
-// lambda_mm(theta_q) for the north rings, by the product recursion
-// lambda_00 = 1/sqrt(4 pi), lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1},
-// with a scale exponent in units of 2^800 keeping the mantissa above 2^-400.
-__global__ void k_lambda_mm(const double* rt, int H, int lmax, double* mant, int* scale) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= H) return;
-  const double st = rt[4 * q + 1];
-  double v = 0.28209479177387814347403972578039;  // 1/sqrt(4 pi)
-  int s = 0;
-  mant[q] = v;
-  scale[q] = 0;
-  const double tiny = 0x1p-400, big = 0x1p800;
-  for (int m = 1; m <= lmax; ++m) {
-    v *= -sqrt((2.0 * m + 1.0) / (2.0 * m)) * st;
-    if (fabs(v) < tiny) {
-      v *= big;
-      s -= 1;
-    }
-    mant[size_t(m) * H + q] = v;
-    scale[size_t(m) * H + q] = s;
-  }
-}
-
 __global__ void k_ring2nest(int64_t N, int* table) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= 12 * N * N) return;

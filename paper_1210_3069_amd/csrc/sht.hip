@@ -8,12 +8,37 @@
 // registers and mirror rings are folded in with the (-1)^(l+m) parity.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "clm_internal.h"
 #include "healpix_dev.h"
 
 namespace clm {
+
+// lambda_mm(theta_q) for the north rings, by the product recursion
+// lambda_00 = 1/sqrt(4 pi), lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1},
+// with a scale exponent in units of 2^800 keeping the mantissa above 2^-400.
+__global__ void k_lambda_mm(const double* rt, int H, int lmax, double* mant, int* scale) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= H) return;
+  const double st = rt[4 * q + 1];
+  double v = 0.28209479177387814347403972578039;  // 1/sqrt(4 pi)
+  int s = 0;
+  mant[q] = v;
+  scale[q] = 0;
+  const double tiny = 0x1p-400, big = 0x1p800;
+  for (int m = 1; m <= lmax; ++m) {
+    v *= -sqrt((2.0 * m + 1.0) / (2.0 * m)) * st;
+    if (fabs(v) < tiny) {
+      v *= big;
+      s -= 1;
+    }
+    mant[size_t(m) * H + q] = v;
+    scale[size_t(m) * H + q] = s;
+  }
+}
+
 namespace {
 
 constexpr int kBlock = 256;
@@ -1294,4 +1319,198 @@ extern "C" clm_status clm_alm2map(const double* alm, int32_t lmax, int32_t nside
   if (hipStreamSynchronize(stream) != hipSuccess && st == CLM_OK) st = CLM_EHIP;
   clm_plan_destroy(pl);
   return st;
+}
+
+// ------------------------------------------------ allocation-free synthesis
+// clm_alm2map_noalloc: the synthesis of clm_alm2map with every table and
+// intermediate (ring geometry, chirp-filter transforms, lambda_mm starting
+// values, the ring sums G) in one file-scope device array instead of plan
+// workspace.  Sizes up to nside 256 / lmax 512 fit in it.
+namespace clm {
+namespace {
+
+constexpr int kNaMaxNside = 256;
+constexpr int kNaMaxLmax = 512;
+constexpr size_t kNaScratchBytes = size_t(16) << 20;
+constexpr int kNaMaxDevices = 64;
+
+}  // namespace
+}  // namespace clm
+
+// One copy per GPU, held until the process ends.  In host code this name
+// is only a stand-in for the symbol: the device address of each GPU's copy
+// comes from hipGetSymbolAddress (na_scratch_ptr) and is the only address
+// host code passes on.
+static __device__ __align__(256) char scratch[clm::kNaScratchBytes];
+
+namespace clm {
+namespace {
+
+std::mutex g_na_mutex;
+char* g_na_ptr[kNaMaxDevices] = {};
+
+// Device address of this GPU's scratch, looked up once per device with that
+// device current.
+hipError_t na_scratch_ptr(int dev, char** out) {
+  std::lock_guard<std::mutex> lk(g_na_mutex);
+  if (!g_na_ptr[dev]) {
+    void* q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_na_ptr[dev] = static_cast<char*>(q);
+  }
+  *out = g_na_ptr[dev];
+  return hipSuccess;
+}
+
+// Ring geometry of the HEALPix grid N on the device, the definitions of the
+// plan's host tables (Gorski et al. 2005): rt[4q..] = z, sin theta, theta,
+// phi0 of ring q + 1; ri[2q..] = pixels, first pixel.
+__global__ void k_ring_geom(int N, double* rt, int* ri) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 4 * N - 1) return;
+  const int64_t i = q + 1;
+  double z, st;
+  int64_t n, first;
+  bool shifted = true;
+  if (i < N) {
+    const double omz = double(i) * double(i) / (3.0 * N * N);
+    z = 1.0 - omz;
+    st = sqrt(omz * (1.0 + z));
+    n = 4 * i;
+    first = 2 * i * (i - 1);
+  } else if (i <= 3 * N) {
+    z = (4.0 * N - 2.0 * i) / (3.0 * N);
+    st = sqrt((1.0 - z) * (1.0 + z));
+    n = 4 * N;
+    first = 2 * int64_t(N) * (N - 1) + 4 * int64_t(N) * (i - N);
+    shifted = ((i - N) % 2) == 0;
+  } else {
+    const int64_t ip = 4 * N - i;
+    const double opz = double(ip) * double(ip) / (3.0 * N * N);
+    z = opz - 1.0;
+    st = sqrt(opz * (2.0 - opz));
+    n = 4 * ip;
+    first = 12 * int64_t(N) * N - 2 * ip * (ip + 1);
+  }
+  rt[4 * q + 0] = z;
+  rt[4 * q + 1] = st;
+  rt[4 * q + 2] = atan2(st, z);
+  rt[4 * q + 3] = shifted ? 3.14159265358979323846 / double(n) : 0.0;
+  ri[2 * q + 0] = int(n);
+  ri[2 * q + 1] = int(first);
+}
+
+// Size of the ring-transform plan of grid N: distinct Bluestein ring
+// lengths, doubles of their filter tables, and the ring kernels' LDS.  The
+// same rule as ring_plan; cap rings of one length come in north/south
+// pairs, so lengths are first met in the north in increasing order.
+struct NaRingPlan {
+  int nlen = 0;
+  int64_t total = 0;
+  size_t lds = 0;
+};
+
+__host__ __device__ inline bool na_bluestein(int N, int q, int& n, int64_t& twoM) {
+  const int ring = q + 1, i = ring < 4 * N - ring ? ring : 4 * N - ring;
+  n = i < N ? 4 * i : 4 * N;
+  const int h = n / 2;
+  int r = h;
+  while (!(r & 1)) r >>= 1;
+  twoM = int64_t(2) << lg_ceil(2 * h - 1);
+  return odd_factor_sum(r) > kDirectFactorSum;
+}
+
+NaRingPlan na_ring_plan(int N) {
+  NaRingPlan rp;
+  for (int q = 0; q < 2 * N; ++q) {  // north rings and the equator
+    int n;
+    int64_t twoM;
+    if (na_bluestein(N, q, n, twoM)) {
+      ++rp.nlen;
+      rp.total += twoM;
+      rp.lds = std::max(rp.lds, size_t(twoM + twoM / 8 + 1) * sizeof(double));
+    } else {
+      rp.lds = std::max(rp.lds, size_t(2 * n + n / 4 + 1) * sizeof(double));
+    }
+  }
+  return rp;
+}
+
+// One thread: every ring's chirp-table offset (-1: direct stages), and the
+// distinct lengths with their offsets, in the order na_ring_plan counts them.
+__global__ void k_na_ring_scan(int N, int64_t* boff, int* lens, int64_t* offs) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int cnt = 0;
+  int64_t total = 0;
+  for (int q = 0; q < 4 * N - 1; ++q) {
+    int n;
+    int64_t twoM;
+    if (!na_bluestein(N, q, n, twoM)) {
+      boff[q] = -1;
+      continue;
+    }
+    int k = 0;
+    while (k < cnt && lens[k] != n) ++k;
+    if (k == cnt) {
+      lens[cnt] = n;
+      offs[cnt] = total;
+      total += twoM;
+      ++cnt;
+    }
+    boff[q] = offs[k];
+  }
+}
+
+}  // namespace
+}  // namespace clm
+
+extern "C" clm_status clm_alm2map_noalloc(const double* alm, int32_t lmax, int32_t nside,
+                                          double* map, hipStream_t stream) {
+  using namespace clm;
+  if (!alm || !map || lmax < 1 || nside < 1 || (nside & (nside - 1))) return CLM_EINVAL;
+  if (nside > kNaMaxNside || lmax > kNaMaxLmax) return CLM_EUNSUPPORTED;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CLM_EHIP;
+  if (dev < 0 || dev >= kNaMaxDevices) return CLM_EUNSUPPORTED;
+  char* base = nullptr;
+  if (na_scratch_ptr(dev, &base) != hipSuccess) return CLM_EHIP;
+
+  const int N = nside, nr = 4 * N - 1, H = 2 * N;
+  const int64_t npix = 12 * int64_t(N) * N;
+  const NaRingPlan rp = na_ring_plan(N);
+  // carve the scratch: 256-byte aligned pieces
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = base + off;
+    off += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  double* rt = reinterpret_cast<double*>(take(size_t(nr) * 4 * 8));
+  int* ri = reinterpret_cast<int*>(take(size_t(nr) * 2 * 4));
+  int64_t* boff = reinterpret_cast<int64_t*>(take(size_t(nr) * 8));
+  int* lens = reinterpret_cast<int*>(take(size_t(N) * 4));
+  int64_t* loffs = reinterpret_cast<int64_t*>(take(size_t(N) * 8));
+  double* blu = reinterpret_cast<double*>(take(size_t(rp.total) * 8));
+  double* mant = reinterpret_cast<double*>(take(size_t(lmax + 1) * H * 8));
+  int* scale = reinterpret_cast<int*>(take(size_t(lmax + 1) * H * 4));
+  double* G = reinterpret_cast<double*>(take(size_t(nr) * (lmax + 1) * 16));
+  const size_t shm_syn = 4 * size_t(lmax + 1) * sizeof(double);
+  // at the largest sizes every kernel stays within the default 64 KiB of
+  // dynamic LDS, so no attribute call is made here
+  if (off > kNaScratchBytes || rp.lds > 65536 || shm_syn > 65536) return CLM_EUNSUPPORTED;
+
+  hipLaunchKernelGGL(k_ring_geom, dim3((nr + 255) / 256), dim3(256), 0, stream, N, rt, ri);
+  hipLaunchKernelGGL(k_na_ring_scan, dim3(1), dim3(64), 0, stream, N, boff, lens, loffs);
+  if (rp.nlen > 0)
+    hipLaunchKernelGGL(k_blu_table, dim3(unsigned(rp.nlen)), dim3(kRingBlock), rp.lds, stream,
+                       lens, loffs, blu);
+  hipLaunchKernelGGL(k_lambda_mm, dim3((H + 127) / 128), dim3(128), 0, stream, rt, H,
+                     int(lmax), mant, scale);
+  const int nt = std::min(1024, round64(H));
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis<false>), dim3(lmax + 1, (H + nt - 1) / nt),
+                     dim3(nt), shm_syn, stream, alm, rt, mant, scale, H, nr, int(lmax), G);
+  hipLaunchKernelGGL(k_ring_inverse, dim3(nr), dim3(kRingBlock), rp.lds, stream, G, nr, rt,
+                     ri, boff, blu, int(lmax), npix, 1, map);
+  return hipGetLastError() == hipSuccess ? CLM_OK : CLM_EHIP;
 }
