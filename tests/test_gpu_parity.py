@@ -603,8 +603,11 @@ def test_points_outside_patch_are_flagged(clm, mg_case):
 
 # ---------------------------------------------------------------- rays
 def test_raytrace_parity(clm):
+    """Five planes; sample rays of four bundles, two of them the bundles at
+    the poles (15 and 128), against the oracle's ray steps; galaxies of
+    those bundles against eq. gatraj with the oracle's ray Jacobians."""
     Nf, Ns, lmax, Nb, n = 64, 16, 32, 4, 64
-    nplanes = 3
+    nplanes = 5
     chi = np.array([(m + 0.5) * 100.0 for m in range(nplanes)] + [nplanes * 100.0 + 50.0])
     kaps = []
     for m in range(nplanes):
@@ -613,7 +616,7 @@ def test_raytrace_parity(clm):
         s = inputs.deflection_scale(lmax, sig, alpha_rms=20 * inputs.ARCMIN)
         kaps.append(s * (np.exp(g) - np.mean(np.exp(g))))
     kaps = np.stack(kaps)
-    bundles = [5, 77]
+    bundles = [5, 15, 77, 128]
     spec = omg.PatchSpec(Nf, Ns, lmax, Nb, ncell=n, vcycles=4)
     sols = [omg.solve_plane(spec, kaps[m], bundles) for m in range(nplanes)]
 
