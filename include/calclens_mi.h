@@ -64,10 +64,12 @@ typedef enum {
   CLM_EUNSUPPORTED = 7      /* valid request this build does not implement   */
 } clm_status;
 
-/* Arithmetic forms.  CLM_BF16X3 (Legendre transforms only): each operand is
- * split into bf16 hi + lo and the products hi*hi + hi*lo + lo*hi are
- * accumulated in float32 on the matrix cores. */
-typedef enum { CLM_FP64 = 0, CLM_FP32 = 1, CLM_BF16X3 = 2 } clm_precision;
+/* Arithmetic forms.  CLM_BF16X3 and CLM_BF16X6 (Legendre transforms only):
+ * each float32 operand is split into bf16 terms, hi + lo (BF16X3) or hi +
+ * mid + lo (BF16X6), and the products hi*hi + hi*lo + lo*hi (BF16X3) or
+ * hi*hi + hi*mid + mid*hi + hi*lo + lo*hi + mid*mid (BF16X6) are accumulated
+ * in float32 on the matrix cores. */
+typedef enum { CLM_FP64 = 0, CLM_FP32 = 1, CLM_BF16X3 = 2, CLM_BF16X6 = 3 } clm_precision;
 typedef enum { CLM_SOLVER_SHT = 0, CLM_SOLVER_SHT_MG = 1 } clm_solver;
 typedef enum { CLM_ORDER_RING = 0, CLM_ORDER_NESTED = 1 } clm_order;
 
@@ -95,8 +97,9 @@ typedef struct {
   int32_t max_planes;    /* solution slots held by the plan, >= 1              */
   int32_t legendre_prec; /* clm_precision of the Legendre transforms: CLM_FP64
                             (per plane, vector FP64), or CLM_FP32 / CLM_BF16X3
-                            (matrix cores; the planes of one clm_poisson_solve
-                            call are batched as GEMM columns, 16 at a time;
+                            / CLM_BF16X6 (matrix cores; the planes of one
+                            clm_poisson_solve call are batched as GEMM
+                            columns, 16 at a time;
                             the lambda_lm recurrence stays FP64)           */
   int32_t mg_max_vcycles; /* epsilon rule: at most this many V-cycles (>= 1) */
   double mg_eps;         /* epsilon rule (Sec. 3.2): a patch stops after the

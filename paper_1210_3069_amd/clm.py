@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libcalclens_mi.so")
 
 CLM_OK, CLM_EINVAL, CLM_ENOMEM, CLM_EHIP = 0, 1, 2, 3
 CLM_ENOTCONV, CLM_ERAY_LEFT_PATCH, CLM_ENONFINITE, CLM_EUNSUPPORTED = 4, 5, 6, 7
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 SOLVER_SHT, SOLVER_SHT_MG = 0, 1
 ORDER_RING, ORDER_NESTED = 0, 1
 
@@ -161,7 +161,7 @@ class Plan:
             if k == "solver" and isinstance(v, str):
                 v = {"sht": SOLVER_SHT, "sht_mg": SOLVER_SHT_MG}[v]
             if k in ("mg_prec", "legendre_prec") and isinstance(v, str):
-                v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}[v]
+                v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}[v]
             setattr(d, k, float(v) if k == "mg_eps" else int(v))
         dev = torch.cuda.current_device() if device is None else int(device)
         h = ctypes.c_void_p()

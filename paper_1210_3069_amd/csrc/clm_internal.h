@@ -79,7 +79,7 @@ struct Plan {
   double* F = nullptr;          // [nring_s][lmax+1] complex
   double* G = nullptr;          // [5][nring_s][lmax+1] complex (synthesis)
   double* red = nullptr;        // [1024] reduction partials; red[1023] = mean
-  // matrix-core SHT of a batch of planes (legendre_prec FP32 / BF16X3)
+  // matrix-core SHT of a batch of planes (legendre_prec FP32 / BF16X3 / BF16X6)
   int batch = 0;                // planes per GEMM batch (<= 16)
   double* Fb = nullptr;         // [batch][nring_s][lmax+1] complex ring transforms
   double* Gb = nullptr;         // [batch][nring_s][lmax+1] complex synthesis sums

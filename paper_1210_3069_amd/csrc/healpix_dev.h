@@ -197,11 +197,10 @@ __device__ __forceinline__ double atan2_r(double y, double x) {
   return y < 0.0 ? -a : a;
 }
 
-// asin(s), float64: Taylor series (2k)!/(4^k (k!)^2 (2k+1)) s^(2k+1) to
-// s^13 for |s| < 0.05 (remainder < 1e-21), atan2(s, sqrt(1 - s^2))
-// otherwise.
-__device__ __forceinline__ double asin_small(double s) {
-  if (fabs(s) >= 0.05) return atan2_r(s, sqrt((1.0 - s) * (1.0 + s)));
+// asin(s), float64, for |s| < 0.05: Taylor series (2k)!/(4^k (k!)^2 (2k+1))
+// s^(2k+1) to s^13 (remainder < 1e-21); asin_small adds atan2(s, sqrt(1 -
+// s^2)) for larger |s|.
+__device__ __forceinline__ double asin_series(double s) {
   const double s2 = s * s;
   double p = 231.0 / 13312.0;
   p = fma(p, s2, 63.0 / 2816.0);
@@ -210,6 +209,17 @@ __device__ __forceinline__ double asin_small(double s) {
   p = fma(p, s2, 3.0 / 40.0);
   p = fma(p, s2, 1.0 / 6.0);
   return fma(p * s2, s, s);
+}
+
+__device__ __forceinline__ double asin_small(double s) {
+  if (fabs(s) >= 0.05) return atan2_r(s, sqrt((1.0 - s) * (1.0 + s)));
+  return asin_series(s);
+}
+
+// asin(s) for |s| < 0.004: s + s^3/6 + 3 s^5/40 (remainder below 1e-18).
+__device__ __forceinline__ double asin_short(double s) {
+  const double s2 = s * s;
+  return fma(fma(3.0 / 40.0, s2, 1.0 / 6.0) * s2, s, s);
 }
 
 // Azimuth of (vx, vy) measured from a reference azimuth with cosine c and
@@ -298,7 +308,7 @@ __device__ __forceinline__ int ring_above(const Tab& R, double z) {
   const float za = float(fabs(z));
   float fr;
   if (za > 2.0f / 3.0f) {
-    const float fp = N * sqrtf(fmaxf(float(3.0 * (1.0 - fabs(z))), 0.0f));
+    const float fp = N * __builtin_amdgcn_sqrtf(fmaxf(float(3.0 * (1.0 - fabs(z))), 0.0f));
     fr = z > 0 ? fp : 4.0f * N - fp;
   } else {
     fr = N * (2.0f - 1.5f * float(z));

@@ -87,20 +87,9 @@ __device__ __forceinline__ void patch_dir(const double* R, double st, double ct,
 // Rings of the two grids a setup block may copy to LDS (the tile's z range
 // plus one cell of slack; blocks whose range is wider read the global
 // tables).
-constexpr int kRingCapF = 256, kRingCapS = 64;
+constexpr int kRingCapF = 192, kRingCapS = 48;
 constexpr int kSetupBlock = 512;
 constexpr int kLdsBlock = 512;
-
-template <int CAP>
-struct RingStore {
-  double z[CAP], s[CAP], t[CAP], k[CAP], g[CAP + 1];
-  int n[CAP], f[CAP];
-  __device__ hpx::LdsRingTab tab() {
-    hpx::LdsRingTab r;
-    r.zq = z; r.sq = s; r.tq = t; r.kq = k; r.gq = g; r.nq = n; r.fq = f;
-    return r;
-  }
-};
 
 // Reference azimuth of a setup block (the region centre's).
 struct PhiRef {
@@ -113,16 +102,15 @@ struct PhiRef {
 // ghosts from the face values; pass 3 forms f' = f - L u0.  The SHT grid's
 // rings are the fine grid's rings ratio, 2 ratio, ... (nested HEALPix), so
 // the SHT ring index follows from the fine one: floor((g_f + 1) / ratio) - 1.
+// This pass 1 reads the global ring tables (regions wider than the LDS
+// ring stores); setup_pass1_rec below is the LDS form.
 template <typename T, int TILE, typename TS, typename TF>
-__device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, double* shu,
-                             T* fsh, const double* trig, const double* prow, const double* R,
-                             const PhiRef& pr, int64_t patch, int i0, int j0) {
+__device__ void setup_pass1(const SetupArgs& a, const TS& rs, const TF& rf, double* shu,
+                            T* fsh, const double* rowc, const double* colc, const double* R,
+                            const PhiRef& pr, int64_t patch, int i0, int j0) {
   constexpr int RR = TILE + 2;
   const int n = a.n;
-  const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
   const double mean = a.red[1023];
-  const size_t G = size_t(n + 2);
-  double* u0 = a.u0 + size_t(patch) * G * G;
   T* fp = static_cast<T*>(a.fprime) + size_t(patch) * n * n;
   for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
     const int li = idx / RR, lj = idx % RR;
@@ -130,7 +118,7 @@ __device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, dou
     double v = 0.0;
     if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
       double z, rho, dph;
-      patch_dir(R, trig[4 * li], trig[4 * li + 1], trig[4 * lj + 2], trig[4 * lj + 3], pr.c,
+      patch_dir(R, rowc[12 * li + 9], rowc[12 * li + 10], colc[2 * lj + 1], colc[2 * lj], pr.c,
                 pr.s, z, rho, dph);
       const int gf = hpx::ring_above(rf, z);
       const int gs = min(max(((gf + 1) >> a.ring_shift) - 1, rs.lo()), rs.hi());
@@ -163,6 +151,22 @@ __device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, dou
     }
     shu[idx] = v;
   }
+}
+
+// Passes 2 and 3 (after pass 1 filled shu and the sources): the patch
+// ghosts from the face values, then f' = f - L u0 and the u0 writes.  prow
+// holds per tile row c_minus, c_plus, 1 / s_c, 1 / area.
+template <typename T, int TILE>
+__device__ void setup_passes23(const SetupArgs& a, double* shu, const T* fsh,
+                               const double* prow, const double* R, const PhiRef& pr,
+                               int64_t patch, int i0, int j0) {
+  constexpr int RR = TILE + 2;
+  const int n = a.n;
+  const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
+  const size_t G = size_t(n + 2);
+  double* u0 = a.u0 + size_t(patch) * G * G;
+  T* fp = static_cast<T*>(a.fprime) + size_t(patch) * n * n;
+  const hpx::GlobalRingTab rs{a.rs, pr.phi};
   __syncthreads();
   // ghost cells of the region (on the patch boundary); only blocks at the
   // patch faces have any
@@ -199,14 +203,187 @@ __device__ void setup_passes(const SetupArgs& a, const TS& rs, const TF& rf, dou
     const bool own_j = (lj >= 1 && lj <= TILE) || (gj == -1) || (gj == n);
     if (own_i && own_j) u0[size_t(gi + 1) * G + (gj + 1)] = shu[idx];
     if (!(li >= 1 && li <= TILE && lj >= 1 && lj <= TILE)) continue;
-    const double* c = a.coef + 4 * gi;
-    const double* q = prow + 2 * (li - 1);  // 1 / s_c, 1 / A of the row
+    const double* q = prow + 4 * (li - 1);  // c_minus, c_plus, 1 / s_c, 1 / A of the row
     const double u = shu[idx];
-    const double Lu = (c[0] * (shu[idx - RR] - u) + c[1] * (shu[idx + RR] - u) +
-                       (shu[idx - 1] - 2.0 * u + shu[idx + 1]) * q[0]) * q[1];
+    const double Lu = (q[0] * (shu[idx - RR] - u) + q[1] * (shu[idx + RR] - u) +
+                       (shu[idx - 1] - 2.0 * u + shu[idx + 1]) * q[2]) * q[3];
     T* fo = fp + size_t(gi) * n + gj;
     const double f = fsh ? double(fsh[(li - 1) * TILE + (lj - 1)]) : double(*fo);
     *fo = T(f - Lu);
+  }
+}
+
+// ---- setup with the ring stores as records (the LDS case)
+// One ring of a block's LDS ring store: everything the interpolation reads
+// for that ring in one 64-byte record, so each access is one base address.
+struct alignas(16) SetupRing {
+  double z, s;     // cos theta, sin theta
+  double k, t0;    // n / (2 pi); (phi_ref - phi0) n / (2 pi)
+  double gbelow;   // 1 / (theta_{q+1} - theta_q) (last ring: 1 / (pi - theta_q))
+  double off;      // fine rings: theta_q - theta of the SHT ring above them
+                   // (0 above the first SHT ring); 0 for SHT rings
+  int n, first;
+};
+static_assert(sizeof(SetupRing) == 64, "ring record size");
+
+// Ring-table view of a record store for hpx::ring_above.
+struct RecTab {
+  const SetupRing* r;
+  int base, top, nr, NN;
+  __device__ __forceinline__ int N() const { return NN; }
+  __device__ __forceinline__ double z(int q) const { return r[q - base].z; }
+  __device__ __forceinline__ int qmin() const { return base; }
+  __device__ __forceinline__ int qmax() const { return top; }
+  __device__ __forceinline__ int lo() const { return base > 0 ? base : -1; }
+  __device__ __forceinline__ int hi() const { return top == nr - 1 ? top : top - 1; }
+};
+
+// All threads of the block: rings b .. t of grid R into the record store;
+// fine rings (shift >= 0) also get their offset to the SHT ring above,
+// from the SHT grid's theta column rt_s.
+__device__ void fill_records(SetupRing* st, const hpx::Rings& R, int b, int t, double phi_ref,
+                             int shift, const double* rt_s) {
+  for (int k = threadIdx.x; k <= t - b; k += blockDim.x) {
+    const int q = b + k;
+    SetupRing r;
+    r.z = R.rt[4 * q];
+    r.s = R.rt[4 * q + 1];
+    r.k = R.rx[2 * q];
+    r.t0 = (phi_ref - R.rt[4 * q + 3]) * R.rx[2 * q];
+    r.gbelow = R.rx[2 * (q + 1) + 1];
+    r.off = 0.0;
+    if (shift >= 0) {
+      const int gs = ((q + 1) >> shift) - 1;
+      r.off = R.rt[4 * q + 2] - (gs >= 0 ? rt_s[4 * gs + 2] : 0.0);
+    }
+    r.n = R.ri[2 * q];
+    r.first = R.ri[2 * q + 1];
+    st[k] = r;
+  }
+}
+
+// The two pixels of ring r around azimuth offset dphi and the weight of the
+// second.
+__device__ __forceinline__ void rec_pair(const SetupRing& r, double dphi, int& a, int& b,
+                                         double& wp) {
+  const double t = fma(dphi, r.k, r.t0);
+  const double fl = floor(t);
+  wp = t - fl;
+  int i1 = int(fl);
+  i1 += i1 < 0 ? r.n : 0;
+  i1 -= i1 >= r.n ? r.n : 0;
+  i1 = min(max(i1, 0), r.n - 1);  // azimuths outside (-pi, 3 pi) only
+  a = r.first + i1;
+  b = i1 + 1 == r.n ? r.first : a + 1;
+}
+
+// Bilinear weights between rings A (above) and B (below) for a point at
+// theta - theta_A = dth.
+__device__ __forceinline__ void rec_weights(const SetupRing& A, const SetupRing& B, double dth,
+                                            double dphi, int pix[4], double w[4]) {
+  int a1, a2, b1, b2;
+  double wa, wb;
+  rec_pair(A, dphi, a1, a2, wa);
+  rec_pair(B, dphi, b1, b2, wb);
+  const double wt = dth * A.gbelow;
+  pix[0] = a1; pix[1] = a2; pix[2] = b1; pix[3] = b2;
+  w[0] = (1 - wt) * (1 - wa);
+  w[1] = (1 - wt) * wa;
+  w[2] = wt * (1 - wb);
+  w[3] = wt * wb;
+}
+
+// Pass 1 of the setup with record stores: the global direction of a cell
+// from per-row coefficients (z, and the cos/sin-weighted components along
+// the reference azimuth, each A + B cos phi' + C sin phi') and the column's
+// cos/sin phi'; rho and 1 / rho from the hardware reciprocal square root
+// refined by two Newton steps; the azimuth offset as asin(sn / rho).  The
+// fine-grid theta offset comes from its upper ring, the SHT grid's from it
+// plus the tabulated difference of the two rings' colatitudes.  Cells whose
+// rings are not both in the stores (poles, wide regions) and azimuth
+// offsets beyond the series take the general path on the global tables.
+template <typename T, int TILE>
+__device__ void setup_pass1_rec(const SetupArgs& a, const SetupRing* rf, const SetupMeta& m,
+                                const SetupRing* rs, double* shu, T* fsh, const double* rowc,
+                                const double* colc, const PhiRef& pr, int64_t patch, int i0,
+                                int j0) {
+  constexpr int RR = TILE + 2;
+  const int n = a.n;
+  const double mean = a.red[1023];
+  T* fp = static_cast<T*>(a.fprime) + size_t(patch) * n * n;
+  const RecTab tf{rf, m.bf, m.tf, a.rf.nring, a.rf.N};
+  const hpx::GlobalRingTab gfs{a.rf, pr.phi}, gss{a.rs, pr.phi};
+  for (int idx = threadIdx.x; idx < RR * RR; idx += blockDim.x) {
+    const int li = idx / RR, lj = idx - li * RR;
+    const int gi = i0 + li, gj = j0 + lj;
+    double v = 0.0;
+    if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
+      const double* rc = rowc + 12 * li;
+      const double cp = colc[2 * lj], sp = colc[2 * lj + 1];
+      const double z = fma(rc[2], sp, fma(rc[1], cp, rc[0]));
+      const double cs = fma(rc[5], sp, fma(rc[4], cp, rc[3]));
+      const double sn = fma(rc[8], sp, fma(rc[7], cp, rc[6]));
+      const double r2 = fma(cs, cs, sn * sn);
+      double rho = 0.0, irho = 0.0, dphi;
+      bool fast = r2 > 1e-20;
+      if (fast) {
+        // Goldschmidt iterations on the hardware estimate of 1 / sqrt(r2)
+        const double y = __builtin_amdgcn_rsq(r2);
+        double g = r2 * y, h = 0.5 * y;
+        double e = fma(-g, h, 0.5);
+        g = fma(g, e, g);
+        h = fma(h, e, h);
+        e = fma(-g, h, 0.5);
+        g = fma(g, e, g);
+        h = fma(h, e, h);
+        rho = g;
+        irho = 2.0 * h;
+      } else {
+        rho = sqrt(r2);
+      }
+      const double sd = sn * irho;
+      if (fast && cs > 0.0 && fabs(sd) < 0.05) {
+        dphi = hpx::asin_small(sd);
+      } else {
+        dphi = hpx::atan2_r(sn, cs);
+        if (!fast) rho = sqrt(r2);
+      }
+      const int gf = hpx::ring_above(tf, z);
+      int ps[4], pf[4];
+      double ws[4], wf[4];
+      const bool inner = li >= 1 && li <= TILE && lj >= 1 && lj <= TILE;
+      const int gsr = ((gf + 1) >> a.ring_shift) - 1;
+      if (fast && gf >= m.bf && gf < m.tf) {
+        const SetupRing& A = rf[gf - m.bf];
+        const double dthf = hpx::asin_small(fma(rho, A.z, -z * A.s));
+        if (inner) rec_weights(A, rf[gf - m.bf + 1], dthf, dphi, pf, wf);
+        if (gsr >= m.bs && gsr < m.ts)
+          rec_weights(rs[gsr - m.bs], rs[gsr - m.bs + 1], dthf + A.off, dphi, ps, ws);
+        else
+          hpx::interp_weights_g(gss, min(max(gsr, -1), a.rs.nring - 1), z, rho, dphi, ps, ws);
+      } else {
+        if (inner) hpx::interp_weights_g(gfs, gf, z, rho, dphi, pf, wf);
+        hpx::interp_weights_g(gss, min(max(gsr, -1), a.rs.nring - 1), z, rho, dphi, ps, ws);
+      }
+      v = ws[0] * a.psi_s[ps[0]] + ws[1] * a.psi_s[ps[1]] + ws[2] * a.psi_s[ps[2]] +
+          ws[3] * a.psi_s[ps[3]];
+      if (inner) {
+        double kv;
+        if (a.kappa_fp64) {
+          const double* km = static_cast<const double*>(a.kappa);
+          kv = wf[0] * km[pf[0]] + wf[1] * km[pf[1]] + wf[2] * km[pf[2]] + wf[3] * km[pf[3]];
+        } else {
+          const float* km = static_cast<const float*>(a.kappa);
+          kv = wf[0] * double(km[pf[0]]) + wf[1] * double(km[pf[1]]) +
+               wf[2] * double(km[pf[2]]) + wf[3] * double(km[pf[3]]);
+        }
+        if (fsh)
+          fsh[(li - 1) * TILE + (lj - 1)] = T(2.0 * (kv - mean));
+        else
+          fp[size_t(gi) * n + gj] = T(2.0 * (kv - mean));
+      }
+    }
+    shu[idx] = v;
   }
 }
 
@@ -301,18 +478,20 @@ __global__ __launch_bounds__(kMetaBlock) void k_setup_meta(SetupArgs a) {
   a.meta[lb] = m;
 }
 
-// One block per TILE x TILE tile (TILE = 64, or the whole patch if smaller),
-// sin/cos of theta' and phi' tabulated per row and column.  The block copies
-// the rings of both grids that its plan-time record names into LDS (or reads
-// the global tables when they do not fit).
+// One block per TILE x TILE tile (TILE = 64, or the whole patch if smaller).
+// Per region row: sin/cos theta' and the coefficients of the cell direction
+// in cos/sin phi'; per column cos/sin phi'.  The block copies the rings of
+// both grids that its plan-time record names into LDS as ring records (or
+// reads the global tables when they do not fit).
 template <typename T, int TILE>
 __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
   constexpr int RR = TILE + 2;
   __shared__ double shu[RR * RR];
-  __shared__ double trig[4 * RR];  // sin/cos th'_row, ph'_col
-  __shared__ double prow[2 * TILE];  // 1 / s_c, 1 / area of the tile's rows
-  __shared__ RingStore<kRingCapF> ringf;
-  __shared__ RingStore<kRingCapS> rings;
+  __shared__ double rowc[12 * RR];   // z, cs, sn: A, B, C each; sin, cos theta'; pad
+  __shared__ double colc[2 * RR];    // cos, sin phi'
+  __shared__ double prow[4 * TILE];  // c_minus, c_plus, 1 / s_c, 1 / area per tile row
+  __shared__ SetupRing recf[kRingCapF];
+  __shared__ SetupRing recs[kRingCapS];
   __shared__ T fshm[sizeof(T) == 4 ? TILE * TILE : 1];
   T* fsh = sizeof(T) == 4 ? fshm : nullptr;
   const int64_t lb = xcd_block();
@@ -324,25 +503,45 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
   const SetupMeta& m = a.meta[lb];
   const PhiRef pr{m.phi, m.c, m.s};
   for (int r = threadIdx.x; r < RR; r += blockDim.x) {
-    sincos(th0 + (i0 + r + 0.5) * a.delta, &trig[4 * r], &trig[4 * r + 1]);
-    sincos(ph0 + (j0 + r + 0.5) * a.delta, &trig[4 * r + 2], &trig[4 * r + 3]);
+    double s_t, c_t, s_p, c_p;
+    sincos(th0 + (i0 + r + 0.5) * a.delta, &s_t, &c_t);
+    sincos(ph0 + (j0 + r + 0.5) * a.delta, &s_p, &c_p);
+    colc[2 * r] = c_p;
+    colc[2 * r + 1] = s_p;
+    // v = R^T (s_t c_p, s_t s_p, c_t); cs, sn: v_x, v_y turned by the
+    // reference azimuth (cs = v_x c + v_y s, sn = v_y c - v_x s)
+    double* rc = rowc + 12 * r;
+    rc[0] = R[8] * c_t;
+    rc[1] = R[2] * s_t;
+    rc[2] = R[5] * s_t;
+    rc[3] = (R[6] * pr.c + R[7] * pr.s) * c_t;
+    rc[4] = (R[0] * pr.c + R[1] * pr.s) * s_t;
+    rc[5] = (R[3] * pr.c + R[4] * pr.s) * s_t;
+    rc[6] = (R[7] * pr.c - R[6] * pr.s) * c_t;
+    rc[7] = (R[1] * pr.c - R[0] * pr.s) * s_t;
+    rc[8] = (R[4] * pr.c - R[3] * pr.s) * s_t;
+    rc[9] = s_t;
+    rc[10] = c_t;
+    rc[11] = 0.0;
   }
   for (int r = threadIdx.x; r < TILE; r += blockDim.x) {
     const double* c = a.coef + 4 * (i0 + 1 + r);
-    prow[2 * r] = 1.0 / c[2];
-    prow[2 * r + 1] = 1.0 / c[3];
+    prow[4 * r] = c[0];
+    prow[4 * r + 1] = c[1];
+    prow[4 * r + 2] = 1.0 / c[2];
+    prow[4 * r + 3] = 1.0 / c[3];
   }
   if (m.lds) {
-    hpx::LdsRingTab ts = rings.tab(), tf = ringf.tab();
-    ts.fill(a.rs, m.bs, m.ts, pr.phi);
-    tf.fill(a.rf, m.bf, m.tf, pr.phi);
+    fill_records(recs, a.rs, m.bs, m.ts, pr.phi, -1, nullptr);
+    fill_records(recf, a.rf, m.bf, m.tf, pr.phi, a.ring_shift, a.rs.rt);
     __syncthreads();
-    setup_passes<T, TILE>(a, ts, tf, shu, fsh, trig, prow, R, pr, patch, i0, j0);
+    setup_pass1_rec<T, TILE>(a, recf, m, recs, shu, fsh, rowc, colc, pr, patch, i0, j0);
   } else {
     __syncthreads();
-    setup_passes<T, TILE>(a, hpx::GlobalRingTab{a.rs, pr.phi}, hpx::GlobalRingTab{a.rf, pr.phi},
-                          shu, fsh, trig, prow, R, pr, patch, i0, j0);
+    setup_pass1<T, TILE>(a, hpx::GlobalRingTab{a.rs, pr.phi}, hpx::GlobalRingTab{a.rf, pr.phi},
+                         shu, fsh, rowc, colc, R, pr, patch, i0, j0);
   }
+  setup_passes23<T, TILE>(a, shu, fsh, prow, R, pr, patch, i0, j0);
 }
 
 // ------------------------------------------------------------ tile kernels

@@ -344,7 +344,7 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
       d.nside_fine > 8192 || d.lmax < 1 || d.lmax > (1 << 20) || d.max_planes < 1 ||
       (d.solver != CLM_SOLVER_SHT && d.solver != CLM_SOLVER_SHT_MG) ||
       (d.legendre_prec != CLM_FP64 && d.legendre_prec != CLM_FP32 &&
-       d.legendre_prec != CLM_BF16X3) || (d.adjoint != 0 && d.adjoint != 1) ||
+       d.legendre_prec != CLM_BF16X3 && d.legendre_prec != CLM_BF16X6) || (d.adjoint != 0 && d.adjoint != 1) ||
       d.analysis_iters < 0 || d.analysis_iters > 16 ||
       (d.analysis_iters > 0 && (d.legendre_prec != CLM_FP64 || d.adjoint)))
     return CLM_EINVAL;

@@ -11,10 +11,14 @@
 // recurrence of one ring, 32 values of l at a time, and the wave stages the
 // values in LDS for the MFMA operands.
 //
-// Forms: FP32 (lambda and X rounded to float32, v_mfma_f32_16x16x4f32) and
-// BF16x3 (each operand split into bf16 hi + lo, products hi*hi + hi*lo +
-// lo*hi accumulated in float32 with v_mfma_f32_16x16x16bf16_1k).  The
-// recurrence, its scaling and the final weights stay in FP64.
+// Forms: FP32 (lambda and X rounded to float32, v_mfma_f32_16x16x4f32),
+// BF16x3 (each float32 operand split into bf16 hi + lo, products hi*hi +
+// hi*lo + lo*hi) and BF16x6 (split into hi + mid + lo, products hi*hi +
+// hi*mid + mid*hi + hi*lo + lo*hi + mid*mid), both accumulated in float32
+// on the double-K bf16 matrix instructions (v_mfma_f32_16x16x32_bf16 in the
+// analysis, v_mfma_f32_32x32x16_bf16 in the synthesis).  The recurrence, its
+// scaling and the final weights stay in FP64; the waves' partial sums are
+// added in FP64.
 #include <cmath>
 
 #include "clm_internal.h"
@@ -31,20 +35,42 @@ constexpr int kAnaWaves = 8;         // waves of an analysis workgroup (two fit 
 constexpr int kBlk = 256;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-enum Form : int { kFP32 = 0, kBF16X3 = 1 };
+enum Form : int { kFP32 = 0, kBF16X3 = 1, kBF16X6 = 2 };
+
+// bf16 terms of a split operand, and the products summed: (i, j) = term i
+// of the lambda operand times term j of the other, smallest first.
+template <int FORM> struct Split;
+template <> struct Split<kBF16X3> {
+  static constexpr int NS = 2, NP = 3;
+  static constexpr int A[NP] = {1, 0, 0}, B[NP] = {0, 1, 0};
+};
+template <> struct Split<kBF16X6> {
+  static constexpr int NS = 3, NP = 6;
+  static constexpr int A[NP] = {1, 2, 0, 1, 0, 0}, B[NP] = {1, 0, 2, 0, 1, 0};
+};
+template <> struct Split<kFP32> { static constexpr int NS = 1, NP = 1; };
 
 // Row stride (floats) of a wave's lambda tile [32 l][64 rings].  Analysis
 // reads, per lane, row 2 i + parity at a column group; synthesis reads
-// column 16 mb + i at rows 2 (4 j + k) + parity.
-template <int FORM> struct AnaStride { static constexpr int S = 65; };
-template <> struct AnaStride<kBF16X3> { static constexpr int S = 68; };
+// column 16 mb + i (float32) or 32 mt + i (bf16) at rows of one parity.
+template <int FORM> struct AnaStride { static constexpr int S = 68; };
+template <> struct AnaStride<kFP32> { static constexpr int S = 65; };
 constexpr int kSynStride = 72;
 
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = __bf16(x);
-  lo = __bf16(x - float(hi));
+// x = sum of NS bf16 terms (each the rounding of the remainder), into
+// element e of the operand vectors t[0..NS-1].
+template <int NS>
+__device__ __forceinline__ void split_into(float x, bf8 (&t)[NS], int e) {
+  float r = x;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const __bf16 h = __bf16(r);
+    t[k][e] = h;
+    r -= float(h);
+  }
 }
 
 // One ring's recurrence for fixed m: p1 = the latest lambda, p2 the one
@@ -133,8 +159,9 @@ __device__ __forceinline__ Rec rec_start(const MfmaArgs& a, int m, int q) {
 template <int FORM>
 __global__ __launch_bounds__(64 * kAnaWaves, 4) void k_analysis_mfma(MfmaArgs a) {
   constexpr int SA = AnaStride<FORM>::S;
-  constexpr int KB = FORM == kFP32 ? 16 : 4;   // k-blocks over the 64 rings
-  constexpr int KW = FORM == kFP32 ? 4 : 16;   // rings per k-block
+  constexpr int NS = Split<FORM>::NS;
+  constexpr int KB = FORM == kFP32 ? 16 : 2;   // k-blocks over the 64 rings
+  constexpr int KW = FORM == kFP32 ? 4 : 32;   // rings per k-block
   __shared__ float tiles[kAnaWaves * kStep * SA];
   const int m = blockIdx.x, rb = blockIdx.y;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -157,7 +184,7 @@ __global__ __launch_bounds__(64 * kAnaWaves, 4) void k_analysis_mfma(MfmaArgs a)
     return float(par == 0 ? fn + fs : fn - fs);
   };
   float xs[2][KB][2];
-  bf4 xh[2][KB][2], xl[2][KB][2];
+  bf8 xb[2][KB][2][NS];
 #pragma unroll
   for (int par = 0; par < 2; ++par)
 #pragma unroll
@@ -165,16 +192,12 @@ __global__ __launch_bounds__(64 * kAnaWaves, 4) void k_analysis_mfma(MfmaArgs a)
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) {
         const int c = (l & 15) + 16 * nb;
-        if (FORM == kFP32) {
+        if constexpr (FORM == kFP32) {
           xs[par][j][nb] = xval(qb + KW * j + (l >> 4), c, par);
         } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            __bf16 h, lo;
-            split_bf16(xval(qb + KW * j + 4 * (l >> 4) + e, c, par), h, lo);
-            xh[par][j][nb][e] = h;
-            xl[par][j][nb][e] = lo;
-          }
+          for (int e = 0; e < 8; ++e)
+            split_into<NS>(xval(qb + KW * j + 8 * (l >> 4) + e, c, par), xb[par][j][nb], e);
         }
       }
 
@@ -202,30 +225,24 @@ __global__ __launch_bounds__(64 * kAnaWaves, 4) void k_analysis_mfma(MfmaArgs a)
       const float* row = tw + (2 * i + par) * SA;
 #pragma unroll
       for (int j = 0; j < KB; ++j) {
-        if (FORM == kFP32) {
+        if constexpr (FORM == kFP32) {
           const float av = row[KW * j + (l >> 4)];
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb)
             acc[par][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, xs[par][j][nb],
                                                                acc[par][nb], 0, 0, 0);
         } else {
-          bf4 ah, al;
+          // A: row i of the M tile, rings 8 (lane / 16) + e of the k-block
+          bf8 ab[NS];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            __bf16 h, lo;
-            split_bf16(row[KW * j + 4 * (l >> 4) + e], h, lo);
-            ah[e] = h;
-            al[e] = lo;
-          }
+          for (int e = 0; e < 8; ++e) split_into<NS>(row[KW * j + 8 * (l >> 4) + e], ab, e);
 #pragma unroll
-          for (int nb = 0; nb < 2; ++nb) {
-            acc[par][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, xh[par][j][nb],
-                                                                     acc[par][nb], 0, 0, 0);
-            acc[par][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, xl[par][j][nb],
-                                                                     acc[par][nb], 0, 0, 0);
-            acc[par][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, xh[par][j][nb],
-                                                                     acc[par][nb], 0, 0, 0);
-          }
+          for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int q = 0; q < Split<FORM>::NP; ++q)
+              acc[par][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  ab[Split<FORM>::A[q]], xb[par][j][nb][Split<FORM>::B[q]], acc[par][nb], 0, 0,
+                  0);
         }
       }
     }
@@ -238,21 +255,22 @@ __global__ __launch_bounds__(64 * kAnaWaves, 4) void k_analysis_mfma(MfmaArgs a)
 #pragma unroll
         for (int i4 = 0; i4 < 4; ++i4) tw[((par * 2 + nb) * 4 + i4) * 64 + l] = acc[par][nb][i4];
     __syncthreads();
-    // sum over the waves; output row rr = local dl, column c.  The C
-    // fragment of row 4 (lane / 16) + i4 of an M tile, column lane % 16.
+    // sum over the waves (in FP64, fixed order); output row rr = local dl,
+    // column c.  The C fragment of row 4 (lane / 16) + i4 of an M tile,
+    // column lane % 16.
     for (int t = threadIdx.x; t < kStep * kCols; t += blockDim.x) {
       const int rr = t >> 5, c = t & 31;
       const int par = rr & 1, ii = rr >> 1;
       const int src = ((par * 2 + (c >> 4)) * 4 + (ii & 3)) * 64 + 16 * (ii >> 2) + (c & 15);
-      float sum = 0.0f;
-      for (int v = 0; v < a.nwv; ++v) sum += tiles[v * kStep * SA + src];
+      double sum = 0.0;
+      for (int v = 0; v < a.nwv; ++v) sum += double(tiles[v * kStep * SA + src]);
       const int dl = dl0 + rr, p = c >> 1;
       if (dl < nl && p < a.P) {
         const size_t idx = alm_base(m, a.lmax) + dl;
         if (gridDim.y == 1)
-          a.alm[p][2 * idx + (c & 1)] = a.w * double(sum);
+          a.alm[p][2 * idx + (c & 1)] = a.w * sum;
         else
-          a.part[(size_t(rb) * a.nalm + idx) * kCols + c] = sum;
+          a.part[(size_t(rb) * a.nalm + idx) * kCols + c] = float(sum);
       }
     }
     __syncthreads();
@@ -286,6 +304,7 @@ __global__ void k_pack_psi(MfmaArgs a, float* psi) {
 template <int FORM>
 __global__ __launch_bounds__(64 * kMaxWaves) void k_synthesis_mfma(MfmaArgs a) {
   constexpr int SS = kSynStride;
+  constexpr int NS = Split<FORM>::NS;
   __shared__ float tiles[kMaxWaves * kStep * SS];
   const int m = blockIdx.x, rb = blockIdx.y;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -295,29 +314,48 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_synthesis_mfma(MfmaArgs a) {
   const double* rc = a.rc + 2 * alm_base(m, a.lmax);
   const float* pm = a.psi + alm_base(m, a.lmax) * kCols;
   Rec r = rec_start(a, m, qb + l);
+  // float32 form: 16 x 16 tiles, acc[par][mb][nb] (rings 16 mb + ..,
+  // columns 16 nb + ..); bf16 forms: 32 x 32 tiles, accb[par][mt] (rings
+  // 32 mt + .., all 32 columns)
   f4 acc[2][4][2];
-#pragma unroll
-  for (int par = 0; par < 2; ++par)
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) acc[par][mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
-  const int i = l & 15, k = l >> 4;
-  // psi operands of a step: per parity, 4 values of l (k-blocks) x 2 column
-  // blocks, loaded before the step's recurrence so that it hides their
-  // latency
-  auto psi_fetch = [&](int dl0, float (&v)[2][4][2]) {
+  f16v accb[2][2];
+  if constexpr (FORM == kFP32) {
 #pragma unroll
     for (int par = 0; par < 2; ++par)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          const int dl = FORM == kFP32 ? dl0 + 2 * (4 * j + k) + par : dl0 + 2 * (4 * k + j) + par;
-          v[par][j][nb] = dl < nl ? pm[size_t(dl) * kCols + i + 16 * nb] : 0.0f;
+        for (int nb = 0; nb < 2; ++nb) acc[par][mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  } else {
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) accb[par][mt][v] = 0.f;
+  }
+  const int i = l & 15, k = l >> 4;
+  // psi operands of a step, loaded before the step's recurrence so that it
+  // hides their latency.  float32: per parity, 4 values of l (k-blocks) x 2
+  // column blocks; bf16: per parity the 8 values of l 2 (8 (lane / 32) + e)
+  // + parity at column lane % 32.
+  auto psi_fetch = [&](int dl0, float (&v)[2][8]) {
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        int dl, col;
+        if constexpr (FORM == kFP32) {
+          dl = dl0 + 2 * (4 * (e >> 1) + k) + par;
+          col = i + 16 * (e & 1);
+        } else {
+          dl = dl0 + 2 * (8 * (l >> 5) + e) + par;
+          col = l & 31;
         }
+        v[par][e] = dl < nl ? pm[size_t(dl) * kCols + col] : 0.0f;
+      }
   };
-  float pv[2][4][2];
+  float pv[2][8];
   double rcv = rc_fetch(rc, 0, nl, l);
   for (int dl0 = 0; dl0 < nl; dl0 += kStep) {
     const double rcn = rc_fetch(rc, dl0 + kStep, nl, l);  // next step's, in flight
@@ -333,77 +371,70 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_synthesis_mfma(MfmaArgs a) {
     __builtin_amdgcn_s_waitcnt(0xc07f);
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
-      if (FORM == kFP32) {
+      if constexpr (FORM == kFP32) {
         // K blocks of 4 values of l of this parity: rows 2 (4 j + k) + par
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int row = 2 * (4 * j + k) + par;
-          const float* bv = pv[par][j];
 #pragma unroll
           for (int mb = 0; mb < 4; ++mb) {
             const float av = tw[row * SS + 16 * mb + i];
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb)
-              acc[par][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[nb],
-                                                                     acc[par][mb][nb], 0, 0, 0);
+              acc[par][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                  av, pv[par][2 * j + nb], acc[par][mb][nb], 0, 0, 0);
           }
         }
       } else {
-        // one K block of the 16 values of this parity: rows 2 (4 k + e) + par
-        bf4 bh[2], bl[2];
+        // the 16 values of l of this parity as one K block: B row
+        // 8 (lane / 32) + e, column lane % 32; A ring 32 mt + lane % 32
+        bf8 bb[NS];
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+        for (int e = 0; e < 8; ++e) split_into<NS>(pv[par][e], bb, e);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            __bf16 h, lo;
-            split_bf16(pv[par][e][nb], h, lo);
-            bh[nb][e] = h;
-            bl[nb][e] = lo;
-          }
+        for (int mt = 0; mt < 2; ++mt) {
+          bf8 ab[NS];
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          bf4 ah, al;
+          for (int e = 0; e < 8; ++e)
+            split_into<NS>(tw[(2 * (8 * (l >> 5) + e) + par) * SS + 32 * mt + (l & 31)], ab, e);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            __bf16 h, lo;
-            split_bf16(tw[(2 * (4 * k + e) + par) * SS + 16 * mb + i], h, lo);
-            ah[e] = h;
-            al[e] = lo;
-          }
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb) {
-            acc[par][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[nb],
-                                                                         acc[par][mb][nb], 0, 0, 0);
-            acc[par][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[nb],
-                                                                         acc[par][mb][nb], 0, 0, 0);
-            acc[par][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[nb],
-                                                                         acc[par][mb][nb], 0, 0, 0);
-          }
+          for (int q = 0; q < Split<FORM>::NP; ++q)
+            accb[par][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                ab[Split<FORM>::A[q]], bb[Split<FORM>::B[q]], accb[par][mt], 0, 0, 0);
         }
       }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);  // tile reads done before the next step
   }
-  // C fragment: ring 16 mb + 4 (lane / 16) + i4, column lane % 16 + 16 nb
   const size_t pstride = size_t(a.nring) * (a.lmax + 1) * 2;
+  auto put = [&](int q, int c, double e, double o) {
+    const int p = c >> 1, ri = c & 1;
+    if (q >= a.H || p >= a.P) return;
+    const int qm = a.nring - 1 - q;
+    double* Gp = a.G + p * pstride;
+    Gp[(size_t(q) * (a.lmax + 1) + m) * 2 + ri] = e + o;
+    if (qm != q) Gp[(size_t(qm) * (a.lmax + 1) + m) * 2 + ri] = e - o;
+  };
+  if constexpr (FORM == kFP32) {
+    // C fragment: ring 16 mb + 4 (lane / 16) + i4, column lane % 16 + 16 nb
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+    for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int i4 = 0; i4 < 4; ++i4) {
-      const int q = qb + 16 * mb + 4 * k + i4;
-      if (q >= a.H) continue;
-      const int qm = a.nring - 1 - q;
+      for (int i4 = 0; i4 < 4; ++i4)
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const int c = i + 16 * nb, p = c >> 1, ri = c & 1;
-        if (p >= a.P) continue;
-        const double e = acc[0][mb][nb][i4], o = acc[1][mb][nb][i4];
-        double* Gp = a.G + p * pstride;
-        Gp[(size_t(q) * (a.lmax + 1) + m) * 2 + ri] = e + o;
-        if (qm != q) Gp[(size_t(qm) * (a.lmax + 1) + m) * 2 + ri] = e - o;
-      }
-    }
+        for (int nb = 0; nb < 2; ++nb)
+          put(qb + 16 * mb + 4 * k + i4, i + 16 * nb, acc[0][mb][nb][i4], acc[1][mb][nb][i4]);
+  } else {
+    // C fragment of a 32 x 32 tile: column lane % 32, row
+    // 8 (v / 4) + 4 (lane / 32) + v % 4 for element v
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v)
+        put(qb + 32 * mt + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3), l & 31, accb[0][mt][v],
+            accb[1][mt][v]);
+  }
 }
 
 // Recurrence coefficients per (l, m) in alm order:
@@ -462,6 +493,8 @@ clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s) {
     CLM_TIMED(p, s, "sht_analysis_mfma");
     if (p->d.legendre_prec == CLM_BF16X3)
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_mfma<kBF16X3>), grid, block, 0, s, a);
+    else if (p->d.legendre_prec == CLM_BF16X6)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_mfma<kBF16X6>), grid, block, 0, s, a);
     else
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_mfma<kFP32>), grid, block, 0, s, a);
   }
@@ -494,6 +527,8 @@ clm_status mfma_synthesis(Plan* p, int first_slot, int P, hipStream_t s) {
     CLM_TIMED(p, s, "sht_synthesis_mfma");
     if (p->d.legendre_prec == CLM_BF16X3)
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis_mfma<kBF16X3>), grid, block, 0, s, a);
+    else if (p->d.legendre_prec == CLM_BF16X6)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis_mfma<kBF16X6>), grid, block, 0, s, a);
     else
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis_mfma<kFP32>), grid, block, 0, s, a);
   }

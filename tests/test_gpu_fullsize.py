@@ -10,8 +10,8 @@
   seconds), scaled to a 1 arcmin rms deflection.
 * The pure-SHT Poisson solve at Nside 512 / lmax 1024 (the smallest plane of
   the batched-precision workload): psi_lm and the psi map of the FP64 form
-  element by element, and the matrix-core FP32 and BF16x3 forms with their
-  error stated as the relative L2 norm of the psi map."""
+  element by element, and the matrix-core FP32, BF16x3 and BF16x6 forms
+  with their error stated as the relative L2 norm of the psi map."""
 import numpy as np
 import pytest
 import torch
@@ -114,10 +114,11 @@ def sht512_case():
     return dict(N=N, lmax=lmax, kap=kap, palm=palm, psi=psi)
 
 
-# FP32: the relative L2 error of the psi map must meet 1e-6.  BF16x3 (hi*hi +
-# hi*lo + lo*hi in float32) is reported as outside 1e-6: its bound here is the
-# measured level (about 5e-6) with a margin.
-@pytest.mark.parametrize("form,tol_l2", [("fp64", 1e-12), ("fp32", 1e-6), ("bf16x3", 2e-5)])
+# FP32 and BF16x6: the relative L2 error of the psi map must meet 1e-6.
+# BF16x3 (hi*hi + hi*lo + lo*hi in float32) is reported as outside 1e-6: its
+# bound here is the measured level (about 5e-6) with a margin.
+@pytest.mark.parametrize("form,tol_l2", [("fp64", 1e-12), ("fp32", 1e-6), ("bf16x3", 2e-5),
+                                         ("bf16x6", 1e-6)])
 def test_sht_nside512_lmax1024_against_oracle(clm, sht512_case, form, tol_l2):
     c = sht512_case
     print("case: SHT Nside 512 lmax 1024, %s Legendre" % form, flush=True)

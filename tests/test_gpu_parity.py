@@ -141,7 +141,7 @@ def test_sht_float32_input_and_batch(clm):
     plan.close()
 
 
-@pytest.mark.parametrize("form,tol", [("fp32", 5e-6), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("form,tol", [("fp32", 5e-6), ("bf16x3", 1e-4), ("bf16x6", 5e-6)])
 def test_sht_batched_matrix_core_forms(clm, form, tol):
     """Planes batched as GEMM columns (ragged: 5 planes), Legendre transforms
     on the matrix cores, against the FP64 oracle plane by plane."""
@@ -185,15 +185,16 @@ def test_sht_matrix_core_several_batches(clm):
 @pytest.mark.parametrize("N", [512, 1024])
 def test_sht_matrix_core_large_against_fp64(clm, N):
     """Full-size ring counts (one ring block at Nside 512; two blocks whose
-    partial sums are reduced at Nside 1024): FP32 and BF16x3 forms against
-    the FP64 GPU form (itself pinned to the oracle above), 3 planes."""
+    partial sums are reduced at Nside 1024): the matrix-core forms against
+    the FP64 GPU form, 3 planes, max-norm relative error of the psi map
+    (the oracle comparison at Nside 512 is in the full-size tests)."""
     lmax, P = 2 * N, 3
     alm = [torch.from_numpy(inputs.gaussian_alm(lmax, seed=70 + i, amplitude=1.0)).cuda()
            for i in range(P)]
     k = torch.stack([clm.alm2map(a, lmax, N) for a in alm])
     ref = clm.Plan(N, nside_sht=N, lmax=lmax, solver="sht", max_planes=P)
     ref.poisson_solve(k)
-    for form, tol in (("fp32", 2e-5), ("bf16x3", 1e-3)):
+    for form, tol in (("fp32", 2e-5), ("bf16x3", 1e-3), ("bf16x6", 2e-5)):
         plan = clm.Plan(N, nside_sht=N, lmax=lmax, solver="sht", max_planes=P,
                         legendre_prec=form)
         plan.poisson_solve(k)
