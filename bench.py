@@ -535,49 +535,105 @@ def c4_run(clm, torch, inputs):
     torch.cuda.synchronize()
     out, ref = {}, {}
     oracle_err = {}
+    order = sorted(groups, reverse=True)          # largest grid first
     for form in ("fp64", "fp32", "bf16x3", "bf16x6"):
         ms_total, mfma_ms, flops, errs, stage_ms = 0.0, 0.0, 0.0, [], {}
-        for n, idx in sorted(groups.items()):
-            plan = clm.Plan(n, nside_sht=n, lmax=2 * n, solver="sht", max_planes=len(idx),
-                            legendre_prec=form)
-            plan.poisson_solve(kap[n][:1])          # first call: lazy set-up
+        extra = {}
+        if form == "fp64":
+            # the FP64 form: vector Legendre transforms, one plan per grid
+            for n in order:
+                idx = groups[n]
+                plan = clm.Plan(n, nside_sht=n, lmax=2 * n, solver="sht", max_planes=len(idx),
+                                legendre_prec=form)
+                plan.poisson_solve(kap[n][:1])          # first call: lazy set-up
+                torch.cuda.synchronize()
+                t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0.record()
+                plan.poisson_solve(kap[n])
+                t1.record()
+                torch.cuda.synchronize()
+                ms_total += t0.elapsed_time(t1)
+                plan.sync_status()
+                for k, i in enumerate(idx):
+                    psi = plan.psi_map(k)
+                    if i in psi_or:
+                        oracle_err.setdefault(form, []).append(
+                            float((psi.cpu() - psi_or[i]).norm() / psi_or[i].norm()))
+                    ref[i] = psi
+                plan.close()
+                del plan
+                torch.cuda.empty_cache()
+        else:
+            # the matrix-core forms: all grids in one clm_poisson_solve_multi
+            # call (one persistent analysis and one synthesis launch), shapes
+            # from the autotuner at plan creation
+            t = time.perf_counter()
+            plans = [clm.Plan(n, nside_sht=n, lmax=2 * n, solver="sht",
+                              max_planes=len(groups[n]), legendre_prec=form) for n in order]
+            t_create = time.perf_counter() - t
+            ks = [kap[n] for n in order]
+            clm.poisson_solve_multi(plans, ks)       # warm
             torch.cuda.synchronize()
-            # events around the matrix-core launches only (none in the FP64 form)
-            plan.set_timing(form != "fp64", stages=["sht_analysis_mfma", "sht_synthesis_mfma"])
-            plan.get_timing()
             t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             t0.record()
-            plan.poisson_solve(kap[n])
+            clm.poisson_solve_multi(plans, ks)
             t1.record()
             torch.cuda.synchronize()
-            ms_total += t0.elapsed_time(t1)
-            st = plan.get_timing()
-            plan.set_timing(False)
-            plan.sync_status()
-            mfma_ms += sum(st.get(k, (0.0, 0))[0] for k in ("sht_analysis_mfma",
-                                                           "sht_synthesis_mfma"))
-            for k, (tot, _) in st.items():
-                stage_ms[k] = stage_ms.get(k, 0.0) + tot
-            H = 2 * n
-            nlm = (2 * n + 1) * (2 * n + 2) // 2
-            flops += len(idx) * 2 * 4.0 * H * nlm
-            for k, i in enumerate(idx):
-                psi = plan.psi_map(k)
-                if i in psi_or:
-                    pc = psi.cpu()
-                    oracle_err.setdefault(form, []).append(
-                        float((pc - psi_or[i]).norm() / psi_or[i].norm()))
-                if form == "fp64":
-                    ref[i] = psi
-                else:
+            ms_total = t0.elapsed_time(t1)
+            # a second pass with events around the two persistent launches
+            plans[0].set_timing(True, stages=["sht_analysis_mfma", "sht_synthesis_mfma"])
+            plans[0].get_timing()
+            clm.poisson_solve_multi(plans, ks)
+            st = plans[0].get_timing()
+            plans[0].set_timing(False)
+            mfma_ms = sum(st.get(k, (0.0, 0))[0] for k in ("sht_analysis_mfma",
+                                                          "sht_synthesis_mfma"))
+            stage_ms = {k: v[0] for k, v in st.items() if v[1]}
+            # the same call captured in a HIP graph and replayed
+            graph = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream()
+            cs.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(cs):
+                with torch.cuda.graph(graph, stream=cs):
+                    clm.poisson_solve_multi(plans, ks)
+            torch.cuda.current_stream().wait_stream(cs)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            t0.record()
+            for _ in range(3):
+                graph.replay()
+            t1.record()
+            torch.cuda.synchronize()
+            ms_graph = t0.elapsed_time(t1) / 3
+            for pl in plans:
+                pl.sync_status()
+            extra = dict(graph_ms_all_planes=ms_graph, graph_planes_per_s=len(ns) * 1000.0 / ms_graph,
+                         plan_create_s=t_create,
+                         autotuned_waves={str(n): [pl.desc["mfma_ana_waves"], pl.desc["mfma_syn_waves"]]
+                                          for n, pl in zip(order, plans)},
+                         launches="one persistent analysis and one persistent synthesis launch "
+                                  "over the three grids (waves per workgroup of the Nside %d "
+                                  "plan)" % order[0])
+            for n, pl in zip(order, plans):
+                H = 2 * n
+                nlm = (2 * n + 1) * (2 * n + 2) // 2
+                flops += len(groups[n]) * 2 * 4.0 * H * nlm
+                for k, i in enumerate(groups[n]):
+                    psi = pl.psi_map(k)
+                    if i in psi_or:
+                        oracle_err.setdefault(form, []).append(
+                            float((psi.cpu() - psi_or[i]).norm() / psi_or[i].norm()))
                     errs.append(float((psi - ref[i]).norm() / ref[i].norm()))
-            plan.close()
-            del plan
+            del graph
+            for pl in plans:
+                pl.close()
+            del plans
             torch.cuda.empty_cache()
         oe = oracle_err.get(form, [])
         tol = 1e-10 if form == "fp64" else 1e-6
         rec = dict(planes_per_s=len(ns) * 1000.0 / ms_total, ms_all_planes=ms_total,
-                   stage_ms=stage_ms,
+                   stage_ms=stage_ms, **extra,
                    vs_oracle=dict(planes=len(oe), nside=n_or, max_rel_l2_psi=max(oe),
                                   median_rel_l2_psi=float(np.median(oe)), tolerance=tol,
                                   within_tolerance=bool(max(oe) <= tol)))
@@ -596,7 +652,8 @@ def c4_run(clm, torch, inputs):
                      "oracle's own synthesis" % (len(groups[n_or]), n_or,
                                                  min(cores, len(groups[n_or])), t_or))
     out["workload"] = ("32 planes, Nside from {512, 1024, 2048} (seed 4), lmax = 2 Nside, pure-SHT "
-                       "Poisson, planes of one Nside batched as GEMM columns (16 at a time)")
+                       "Poisson; matrix-core forms: planes of one Nside are the GEMM columns, "
+                       "the three grids share one persistent launch per Legendre stage")
     return out
 
 

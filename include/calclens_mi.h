@@ -119,6 +119,14 @@ typedef struct {
                             nside_sht grid, which drives HEALPix's inexact
                             quadrature toward the band-limited solution;
                             legendre_prec = CLM_FP64 only                 */
+  int32_t mfma_ana_waves; /* matrix-core forms: waves per workgroup of the
+                            analysis (8 or 16) and of the synthesis (8, 12
+                            or 16); 0 (default): chosen at plan creation by
+                            timing each shape on a full batch (kept for
+                            later plans of the same device, grid, lmax,
+                            form and batch); the choice is readable with
+                            clm_plan_get_desc                             */
+  int32_t mfma_syn_waves;
 } clm_plan_desc;
 
 /* Fill *d with the defaults for a fine grid: nside_sht = nside_fine / 8
@@ -227,6 +235,26 @@ clm_status clm_alm2map_noalloc(const double* alm_dev, int32_t lmax, int32_t nsid
  */
 clm_status clm_poisson_solve(clm_plan plan, const void* kappa_dev, int32_t kappa_is_fp64,
                              int32_t first_slot, int32_t nplanes, hipStream_t stream);
+
+/*
+ * The plane Poisson solve of several plans at once, for batches of planes
+ * of different grids (nside, lmax) in the matrix-core forms: plans[0 ..
+ * nplans-1] (1 <= nplans <= 4, one device, one legendre_prec other than
+ * CLM_FP64), kappa_dev[i] the [nplanes[i]][12 nside_fine_i^2] convergence
+ * of plan i (float64 if kappa_is_fp64[i], else float32; nplanes[i] <=
+ * max_planes of plan i, planes to slots 0 ..).  Per round of up to 16
+ * planes of every plan, the Legendre analysis of all plans is one
+ * persistent launch (workgroups take (plan, m, ring block) items from a
+ * counter, largest first) and so is the synthesis, with the waves per
+ * workgroup of plans[0]; the ring transforms and the Poisson step run per
+ * plane.  Results as clm_poisson_solve (SHT+MG plans then run their
+ * multigrid per plane).  Asynchronous on `stream`, launches kernels only,
+ * so it may be captured in a HIP graph.
+ */
+clm_status clm_poisson_solve_multi(const clm_plan* plans, int32_t nplans,
+                                   const void* const* kappa_dev,
+                                   const int32_t* kappa_is_fp64, const int32_t* nplanes,
+                                   hipStream_t stream);
 
 /* Copies out of a solution slot (device destinations):
  *   psi_alm: [nalm(lmax)] complex128; psi_map: [12 nside_sht^2] float64;

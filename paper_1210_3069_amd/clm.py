@@ -24,7 +24,9 @@ class PlanDesc(ctypes.Structure):
         "mg_vcycles", "nu_pre", "nu_post", "solver", "mg_prec", "max_planes",
         "legendre_prec", "mg_max_vcycles")] + [("mg_eps", ctypes.c_double),
                                                ("adjoint", ctypes.c_int32),
-                                               ("analysis_iters", ctypes.c_int32)]
+                                               ("analysis_iters", ctypes.c_int32),
+                                               ("mfma_ana_waves", ctypes.c_int32),
+                                               ("mfma_syn_waves", ctypes.c_int32)]
 
 
 class Rays(ctypes.Structure):
@@ -59,6 +61,8 @@ _SIGS = {
     "clm_alm2map": (_P, _I32, _I32, _P, _P),
     "clm_alm2map_noalloc": (_P, _I32, _I32, _P, _P),
     "clm_poisson_solve": (_P, _P, _I32, _I32, _I32, _P),
+    "clm_poisson_solve_multi": (ctypes.POINTER(_P), _I32, ctypes.POINTER(_P),
+                                ctypes.POINTER(_I32), ctypes.POINTER(_I32), _P),
     "clm_get_psi_alm": (_P, _I32, _P, _P),
     "clm_get_psi_map": (_P, _I32, _P, _P),
     "clm_get_patch_potential": (_P, _I32, _I64, _I64, _P, _P),
@@ -148,6 +152,31 @@ def alm2map_noalloc(alm, lmax, nside, out):
     if st != CLM_OK:
         raise ClmError(st, "clm_alm2map_noalloc failed: %s" % lib().clm_status_string(st).decode())
     return out
+
+
+def poisson_solve_multi(plans, kappas):
+    """clm_poisson_solve_multi: the planes kappas[i] ([P_i, npix_i] or
+    [npix_i], float64 or float32, on the GPU) of plans[i] (matrix-core forms,
+    up to 4 plans) solved with one persistent Legendre launch per round of
+    up to 16 planes per plan."""
+    n = len(plans)
+    if n != len(kappas) or not 1 <= n <= 4:
+        raise ValueError("1 to 4 plans, one convergence batch each")
+    ks = []
+    for pl, k in zip(plans, kappas):
+        k = k if k.dim() == 2 else k.reshape(1, -1)
+        if k.dtype not in (torch.float64, torch.float32):
+            raise ValueError("kappa must be float64 or float32")
+        _dev(k, k.dtype)
+        if k.shape[1] != pl.npix_fine:
+            raise ValueError("kappa has %d pixels, plan expects %d" % (k.shape[1], pl.npix_fine))
+        ks.append(k)
+    hs = (ctypes.c_void_p * n)(*[pl.h.value for pl in plans])
+    kp = (ctypes.c_void_p * n)(*[k.data_ptr() for k in ks])
+    f64 = (ctypes.c_int32 * n)(*[int(k.dtype == torch.float64) for k in ks])
+    npl = (ctypes.c_int32 * n)(*[k.shape[0] for k in ks])
+    plans[0]._check(lib().clm_poisson_solve_multi(hs, n, kp, f64, npl, _stream()),
+                    "poisson_solve_multi")
 
 
 class Plan:

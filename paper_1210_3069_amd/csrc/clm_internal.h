@@ -81,6 +81,10 @@ struct Plan {
   double* red = nullptr;        // [1024] reduction partials; red[1023] = mean
   // matrix-core SHT of a batch of planes (legendre_prec FP32 / BF16X3 / BF16X6)
   int batch = 0;                // planes per GEMM batch (<= 16)
+  int ncu = 0;                  // compute units of the device
+  int ana_nw = 8, syn_nw = 16;  // waves per workgroup of the matrix-core kernels
+  int* mfma_ctr = nullptr;      // work counter of their persistent launches
+  std::vector<std::pair<std::string, float>> tune_ms;  // autotuner timings
   double* Fb = nullptr;         // [batch][nring_s][lmax+1] complex ring transforms
   double* Gb = nullptr;         // [batch][nring_s][lmax+1] complex synthesis sums
   float* apart = nullptr;       // [ring blocks][nalm][32] analysis partial sums
@@ -177,6 +181,15 @@ struct TimedLaunch {
     }                                                                        \
   } while (0)
 
+#define CLM_HIP_P(plan, call)                                               \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      (plan)->err = std::string(#call) + ": " + hipGetErrorString(e_);       \
+      return CLM_EHIP;                                                       \
+    }                                                                        \
+  } while (0)
+
 #define CLM_LAUNCH_CHECK()                                                   \
   do {                                                                       \
     hipError_t e_ = hipGetLastError();                                       \
@@ -223,7 +236,19 @@ clm_status shear_adjoint(Plan* p, const double* th, const double* ph, int64_t np
                          hipStream_t s);                 // adjoint.hip
 clm_status poisson_adjoint(Plan* p, double* dkappa, hipStream_t s);
 clm_status adjoint_tables(Plan* p);                      // adjoint.hip
+// One grid's share of a persistent matrix-core launch: plan, first slot and
+// number of planes (the plan's Fb / Gb hold their ring sums).
+struct MfmaGroup {
+  Plan* p;
+  int first_slot, P;
+};
 int mfma_ring_blocks(int H);                             // sht_mfma.hip
+clm_status mfma_autotune(Plan* p);
+clm_status mfma_analysis_multi(const MfmaGroup* gs, int ng, hipStream_t s);
+clm_status mfma_synthesis_multi(const MfmaGroup* gs, int ng, hipStream_t s);
+clm_status sht_solve_multi(Plan* const* ps, int n, const void* const* kappa,
+                           const int32_t* kappa_fp64, const int32_t* nplanes,
+                           hipStream_t s);                // sht.hip
 clm_status mfma_tables(Plan* p, hipStream_t s);
 clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s);
 clm_status mfma_synthesis(Plan* p, int first_slot, int P, hipStream_t s);

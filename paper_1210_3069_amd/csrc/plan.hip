@@ -34,7 +34,7 @@ Plan::~Plan() {
   f(ring_s); f(ringi_s); f(ringx_s); f(ring_f); f(ringi_f); f(ringx_f); f(lam_mant);
   f(lam_scale); f(blu_off); f(blu);
   f(r2n_s); f(r2n_f); f(rot); f(coef); f(cinv); f(kap_s); f(F); f(G); f(red);
-  f(rcoef); f(Fb); f(Gb); f(apart); f(psib);
+  f(rcoef); f(Fb); f(Gb); f(apart); f(psib); f(mfma_ctr);
   f(deriv); f(fprime); f(dutmp); f(status_dev); f(iter_map); f(iter_alm);
   for (auto* q : ubar) f(q);
   f(ubar1b);
@@ -344,9 +344,12 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
       d.nside_fine > 8192 || d.lmax < 1 || d.lmax > (1 << 20) || d.max_planes < 1 ||
       (d.solver != CLM_SOLVER_SHT && d.solver != CLM_SOLVER_SHT_MG) ||
       (d.legendre_prec != CLM_FP64 && d.legendre_prec != CLM_FP32 &&
-       d.legendre_prec != CLM_BF16X3 && d.legendre_prec != CLM_BF16X6) || (d.adjoint != 0 && d.adjoint != 1) ||
-      d.analysis_iters < 0 || d.analysis_iters > 16 ||
-      (d.analysis_iters > 0 && (d.legendre_prec != CLM_FP64 || d.adjoint)))
+       d.legendre_prec != CLM_BF16X3 && d.legendre_prec != CLM_BF16X6) ||
+      (d.adjoint != 0 && d.adjoint != 1) || d.analysis_iters < 0 || d.analysis_iters > 16 ||
+      (d.analysis_iters > 0 && (d.legendre_prec != CLM_FP64 || d.adjoint)) ||
+      (d.mfma_ana_waves != 0 && d.mfma_ana_waves != 8 && d.mfma_ana_waves != 16) ||
+      (d.mfma_syn_waves != 0 && d.mfma_syn_waves != 8 && d.mfma_syn_waves != 12 &&
+       d.mfma_syn_waves != 16))
     return CLM_EINVAL;
   if (d.solver == CLM_SOLVER_SHT && d.nside_sht != d.nside_fine) return CLM_EINVAL;
   if (d.solver == CLM_SOLVER_SHT_MG) {
@@ -411,6 +414,10 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
   if (d.adjoint && (s = adjoint_alloc(p)) != CLM_OK) return bail(s);
   if (d.legendre_prec != CLM_FP64) {
     p->batch = d.max_planes < 16 ? d.max_planes : 16;
+    if (hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, device) !=
+        hipSuccess)
+      return bail(CLM_EHIP);
+    if ((s = alloc(p, &p->mfma_ctr, 4)) != CLM_OK) return bail(s);
     if ((s = alloc(p, &p->rcoef, size_t(p->nalm) * 2)) != CLM_OK) return bail(s);
     if ((s = alloc(p, &p->Fb, size_t(nF) * p->batch)) != CLM_OK) return bail(s);
     if ((s = alloc(p, &p->Gb, size_t(nF) * p->batch)) != CLM_OK) return bail(s);
@@ -434,6 +441,10 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
       if ((s = alloc(p, &du, cells * esz)) != CLM_OK) return bail(s);
       sl.du = du;
     }
+  }
+  if (d.legendre_prec != CLM_FP64) {
+    if ((s = mfma_autotune(p)) != CLM_OK) return bail(s);
+    if (hipDeviceSynchronize() != hipSuccess) return bail(CLM_EHIP);
   }
   if (p->mg) {
     if ((s = alloc(p, &p->mg_eps_dev, size_t(p->nbundle))) != CLM_OK) return bail(s);
@@ -656,6 +667,27 @@ clm_status clm_poisson_solve(clm_plan plan, const void* kappa, int32_t kappa_is_
     }
   }
   return CLM_OK;
+}
+
+clm_status clm_poisson_solve_multi(const clm_plan* plans, int32_t nplans,
+                                   const void* const* kappa, const int32_t* kappa_is_fp64,
+                                   const int32_t* nplanes, hipStream_t stream) {
+  if (!plans || !kappa || !kappa_is_fp64 || !nplanes || nplans < 1 || nplans > 4)
+    return CLM_EINVAL;
+  Plan* ps[4];
+  for (int i = 0; i < nplans; ++i) {
+    ps[i] = plans[i];
+    if (!ps[i] || !kappa[i] || nplanes[i] < 1 || nplanes[i] > ps[i]->d.max_planes)
+      return CLM_EINVAL;
+    if (ps[i]->batch == 0 || ps[i]->d.legendre_prec != ps[0]->d.legendre_prec ||
+        ps[i]->device != ps[0]->device)
+      return fail(ps[0], CLM_EINVAL,
+                  "clm_poisson_solve_multi: one device and one matrix-core form for all plans");
+    for (int j = 0; j < i; ++j)
+      if (ps[j] == ps[i]) return fail(ps[0], CLM_EINVAL, "a plan appears twice");
+  }
+  CLM_HIP_P(ps[0], hipSetDevice(ps[0]->device));
+  return sht_solve_multi(ps, nplans, kappa, kappa_is_fp64, nplanes, stream);
 }
 
 clm_status clm_get_psi_alm(clm_plan plan, int32_t slot, double* out, hipStream_t stream) {

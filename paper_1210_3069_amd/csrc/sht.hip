@@ -1246,6 +1246,59 @@ clm_status sht_solve_batch(Plan* p, const void* kappa, int kappa_fp64, int first
   return CLM_OK;
 }
 
+clm_status sht_solve_multi(Plan* const* ps, int n, const void* const* kappa,
+                           const int32_t* kappa_fp64, const int32_t* nplanes, hipStream_t s) {
+  int rounds = 0;
+  for (int i = 0; i < n; ++i)
+    rounds = std::max(rounds, (nplanes[i] + ps[i]->batch - 1) / ps[i]->batch);
+  clm_status st;
+  for (int r = 0; r < rounds; ++r) {
+    MfmaGroup gs[4];
+    int ng = 0;
+    for (int i = 0; i < n; ++i) {
+      Plan* p = ps[i];
+      const int k0 = r * p->batch;
+      if (k0 >= nplanes[i]) continue;
+      const int nb = std::min(p->batch, nplanes[i] - k0);
+      const size_t nF = size_t(p->nring_s) * (p->d.lmax + 1) * 2;
+      const size_t esz = kappa_fp64[i] ? 8 : 4;
+      for (int k = 0; k < nb; ++k) {
+        const char* kp = static_cast<const char*>(kappa[i]) + size_t(k0 + k) * p->npix_f * esz;
+        if ((st = sht_front(p, kp, kappa_fp64[i], p->Fb + k * nF, s)) != CLM_OK) return st;
+      }
+      gs[ng++] = MfmaGroup{p, k0, nb};
+    }
+    if ((st = mfma_analysis_multi(gs, ng, s)) != CLM_OK) return st;
+    for (int g = 0; g < ng; ++g)
+      for (int k = 0; k < gs[g].P; ++k)
+        if ((st = poisson(gs[g].p, gs[g].p->slots[gs[g].first_slot + k].alm, s)) != CLM_OK)
+          return st;
+    if ((st = mfma_synthesis_multi(gs, ng, s)) != CLM_OK) return st;
+    for (int g = 0; g < ng; ++g) {
+      Plan* p = gs[g].p;
+      const size_t nF = size_t(p->nring_s) * (p->d.lmax + 1) * 2;
+      for (int k = 0; k < gs[g].P; ++k)
+        if ((st = ring_inverse(p, p->Gb + k * nF, 1, p->slots[gs[g].first_slot + k].psi_s, s)) !=
+            CLM_OK)
+          return st;
+    }
+    // SHT+MG plans: the multigrid of each plane, after its mean is taken again
+    for (int g = 0; g < ng; ++g) {
+      Plan* p = gs[g].p;
+      if (!p->mg) continue;
+      const int i = int(std::find(ps, ps + n, p) - ps);
+      const size_t esz = kappa_fp64[i] ? 8 : 4;
+      for (int k = 0; k < gs[g].P; ++k) {
+        const int slot = gs[g].first_slot + k;
+        const char* kp = static_cast<const char*>(kappa[i]) + size_t(slot) * p->npix_f * esz;
+        if ((st = plane_mean(p, kp, kappa_fp64[i], s)) != CLM_OK) return st;
+        if ((st = mg_solve(p, kp, kappa_fp64[i], slot, s)) != CLM_OK) return st;
+      }
+    }
+  }
+  return CLM_OK;
+}
+
 clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* grad, void* hess,
                             hipStream_t s) {
   // theta sums G, G_t, G_tt into fields 0..2 of G ([field][ring][m]); G is

@@ -19,7 +19,12 @@
 // analysis, v_mfma_f32_32x32x16_bf16 in the synthesis).  The recurrence, its
 // scaling and the final weights stay in FP64; the waves' partial sums are
 // added in FP64.
+#include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
 
 #include "clm_internal.h"
 
@@ -30,9 +35,8 @@ constexpr double kHugeB = 0x1p400;    // rescale threshold of the scaled recurre
 constexpr double kSmallB = 0x1p-800;  // rescale factor
 constexpr int kStep = 32;             // values of l generated per step (16 per parity)
 constexpr int kCols = 32;             // GEMM columns: 2 x up to 16 planes
-constexpr int kMaxWaves = 16;        // waves of a synthesis workgroup
-constexpr int kAnaWaves = 8;         // waves of an analysis workgroup (two fit per CU)
 constexpr int kBlk = 256;
+constexpr int kMaxGroups = 4;         // plans (grids) of one persistent launch
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f16v __attribute__((ext_vector_type(16)));
@@ -128,12 +132,38 @@ struct MfmaArgs {
   double* alm[16];         // analysis out with one ring block: per plane
   double w;                // analysis weight 4 pi / N_pix
   int64_t nalm;
-  int H, nring, lmax, P, nwv;
+  int H, nring, lmax, P;
+  int nwv;                 // waves of a workgroup (64 rings each)
+  int R;                   // ring blocks: ceil(H / (64 nwv))
 };
 
-// Waves per workgroup over H rings (64 rings per wave).
-__host__ __device__ inline int ring_waves(int H, int maxw) {
-  return H < 64 * maxw ? (H + 63) / 64 : maxw;
+// The work of one persistent launch: up to kMaxGroups grids (plans), whose
+// items (m, ring block) are numbered group by group, m ascending (the
+// largest sums first), ring block fastest; workgroups take the next item
+// from a counter in device memory until none is left.
+struct MfmaMulti {
+  MfmaArgs g[kMaxGroups];
+  int start[kMaxGroups + 1];  // first item of each group; start[ng] = all items
+  int R[kMaxGroups];          // ring blocks of each group
+  int ng;
+  int* ctr;                   // zero before the launch
+};
+
+// The next item of a persistent workgroup (block-uniform), or -1.
+__device__ __forceinline__ int next_item(const MfmaMulti& mm, int* slot, int& g, int& m,
+                                         int& rb) {
+  __syncthreads();  // every thread has read the previous item
+  if (threadIdx.x == 0) *slot = atomicAdd(mm.ctr, 1);
+  __syncthreads();
+  const int t = *slot;
+  if (t >= mm.start[mm.ng]) return -1;
+  g = 0;
+  while (g + 1 < mm.ng && t >= mm.start[g + 1]) ++g;
+  const int lt = t - mm.start[g];
+  const int R = mm.R[g];
+  m = lt / R;
+  rb = lt - m * R;
+  return t;
 }
 
 __device__ __forceinline__ size_t alm_base(int m, int lmax) {
@@ -151,19 +181,17 @@ __device__ __forceinline__ Rec rec_start(const MfmaArgs& a, int m, int q) {
 }
 
 // ---------------------------------------------------------------- analysis
-// Grid (lmax + 1, R): one workgroup per m and block of 64 nwv rings; each
-// wave owns 64 rings for all l and keeps their X in registers.  The waves'
-// partial sums are added in a fixed order (results do not depend on
-// scheduling).  Workgroups of 8 waves leave room for two per CU, so one
-// workgroup's recurrence runs beside the other's matrix products.
-template <int FORM>
-__global__ __launch_bounds__(64 * kAnaWaves, 4) void k_analysis_mfma(MfmaArgs a) {
+// One item: order m, block of 64 NW rings; each wave owns 64 rings for all
+// l and keeps their X in registers.  The waves' partial sums are added in a
+// fixed order (results do not depend on scheduling).  With 8 waves two
+// workgroups fit per CU, so one's recurrence runs beside the other's matrix
+// products.
+template <int FORM, int NW>
+__device__ __forceinline__ void analysis_item(const MfmaArgs& a, int m, int rb, float* tiles) {
   constexpr int SA = AnaStride<FORM>::S;
   constexpr int NS = Split<FORM>::NS;
   constexpr int KB = FORM == kFP32 ? 16 : 2;   // k-blocks over the 64 rings
   constexpr int KW = FORM == kFP32 ? 4 : 32;   // rings per k-block
-  __shared__ float tiles[kAnaWaves * kStep * SA];
-  const int m = blockIdx.x, rb = blockIdx.y;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int nl = a.lmax - m + 1;
   const int qb = (rb * a.nwv + w) * 64;  // first ring of this wave
@@ -263,11 +291,12 @@ __global__ __launch_bounds__(64 * kAnaWaves, 4) void k_analysis_mfma(MfmaArgs a)
       const int par = rr & 1, ii = rr >> 1;
       const int src = ((par * 2 + (c >> 4)) * 4 + (ii & 3)) * 64 + 16 * (ii >> 2) + (c & 15);
       double sum = 0.0;
-      for (int v = 0; v < a.nwv; ++v) sum += double(tiles[v * kStep * SA + src]);
+#pragma unroll
+      for (int v = 0; v < NW; ++v) sum += double(tiles[v * kStep * SA + src]);
       const int dl = dl0 + rr, p = c >> 1;
       if (dl < nl && p < a.P) {
         const size_t idx = alm_base(m, a.lmax) + dl;
-        if (gridDim.y == 1)
+        if (a.R == 1)
           a.alm[p][2 * idx + (c & 1)] = a.w * sum;
         else
           a.part[(size_t(rb) * a.nalm + idx) * kCols + c] = float(sum);
@@ -275,6 +304,27 @@ __global__ __launch_bounds__(64 * kAnaWaves, 4) void k_analysis_mfma(MfmaArgs a)
     }
     __syncthreads();
   }
+}
+
+// The groups' arguments are copied to LDS once (indexing the kernel
+// argument by the item's group would copy it to scratch memory).
+__device__ __forceinline__ void load_groups(const MfmaMulti& mm, MfmaArgs* ga) {
+  if (threadIdx.x == 0) {
+    ga[0] = mm.g[0];
+    ga[1] = mm.g[1];
+    ga[2] = mm.g[2];
+    ga[3] = mm.g[3];
+  }
+}
+
+template <int FORM, int NW>
+__global__ __launch_bounds__(64 * NW, 32 / NW) void k_analysis_mfma(MfmaMulti mm) {
+  __shared__ float tiles[NW * kStep * AnaStride<FORM>::S];
+  __shared__ MfmaArgs ga[kMaxGroups];
+  __shared__ int slot;
+  load_groups(mm, ga);
+  int g, m, rb;
+  while (next_item(mm, &slot, g, m, rb) >= 0) analysis_item<FORM, NW>(ga[g], m, rb, tiles);
 }
 
 // Sum of the ring-block partials, weighted, into the planes' alm.
@@ -299,14 +349,12 @@ __global__ void k_pack_psi(MfmaArgs a, float* psi) {
 }
 
 // --------------------------------------------------------------- synthesis
-// Grid (lmax + 1, ring blocks): each wave owns 64 rings (4 M tiles of 16)
-// and sums over all l, even and odd l - m apart.
-template <int FORM>
-__global__ __launch_bounds__(64 * kMaxWaves) void k_synthesis_mfma(MfmaArgs a) {
+// One item: order m, block of 64 NW rings; each wave owns 64 rings and sums
+// over all l, even and odd l - m apart.
+template <int FORM, int NW>
+__device__ __forceinline__ void synthesis_item(const MfmaArgs& a, int m, int rb, float* tiles) {
   constexpr int SS = kSynStride;
   constexpr int NS = Split<FORM>::NS;
-  __shared__ float tiles[kMaxWaves * kStep * SS];
-  const int m = blockIdx.x, rb = blockIdx.y;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int nl = a.lmax - m + 1;
   const int qb = (rb * a.nwv + w) * 64;
@@ -437,6 +485,16 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_synthesis_mfma(MfmaArgs a) {
   }
 }
 
+template <int FORM, int NW>
+__global__ __launch_bounds__(64 * NW) void k_synthesis_mfma(MfmaMulti mm) {
+  __shared__ float tiles[NW * kStep * kSynStride];
+  __shared__ MfmaArgs ga[kMaxGroups];
+  __shared__ int slot;
+  load_groups(mm, ga);
+  int g, m, rb;
+  while (next_item(mm, &slot, g, m, rb) >= 0) synthesis_item<FORM, NW>(ga[g], m, rb, tiles);
+}
+
 // Recurrence coefficients per (l, m) in alm order:
 // a_l = sqrt((4l^2-1)/(l^2-m^2)), b_l = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)).
 __global__ void k_recur_table(int lmax, double* rc) {
@@ -465,15 +523,151 @@ MfmaArgs base_args(Plan* p, int first_slot, int P) {
   return a;
 }
 
-int ring_blocks(int H, int maxw) {
-  const int nwv = ring_waves(H, maxw);
-  return (H + 64 * nwv - 1) / (64 * nwv);
+int ring_blocks_nw(int H, int nw) { return (H + 64 * nw - 1) / (64 * nw); }
+
+__global__ void k_zero_int(int* x) { *x = 0; }
+
+// Workgroups of a persistent launch: as many as fit on the device at once
+// (LDS and wave slots per CU), at most one per item.
+int persistent_blocks(const Plan* p, size_t lds, int nw, int items) {
+  int per_cu = int((160 * 1024) / (lds + 256));
+  per_cu = std::min(per_cu, 32 / nw);
+  per_cu = std::max(per_cu, 1);
+  return std::max(1, std::min(items, per_cu * p->ncu));
+}
+
+// Shapes the autotuner chooses from: waves per workgroup.
+constexpr int kAnaNW[] = {8, 16};
+constexpr int kSynNW[] = {8, 12, 16};
+
+template <int FORM, int NW>
+void launch_ana(const MfmaMulti& mm, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_mfma<FORM, NW>), dim3(blocks), dim3(64 * NW), 0,
+                     s, mm);
+}
+
+template <int FORM, int NW>
+void launch_syn(const MfmaMulti& mm, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis_mfma<FORM, NW>), dim3(blocks), dim3(64 * NW), 0,
+                     s, mm);
+}
+
+template <int FORM>
+bool dispatch_ana(int nw, const MfmaMulti& mm, int blocks, hipStream_t s) {
+  switch (nw) {
+    case 8: launch_ana<FORM, 8>(mm, blocks, s); return true;
+    case 16: launch_ana<FORM, 16>(mm, blocks, s); return true;
+    default: return false;
+  }
+}
+
+template <int FORM>
+bool dispatch_syn(int nw, const MfmaMulti& mm, int blocks, hipStream_t s) {
+  switch (nw) {
+    case 8: launch_syn<FORM, 8>(mm, blocks, s); return true;
+    case 12: launch_syn<FORM, 12>(mm, blocks, s); return true;
+    case 16: launch_syn<FORM, 16>(mm, blocks, s); return true;
+    default: return false;
+  }
+}
+
+int form_of(const Plan* p) {
+  return p->d.legendre_prec == CLM_BF16X3 ? kBF16X3
+         : p->d.legendre_prec == CLM_BF16X6 ? kBF16X6 : kFP32;
+}
+
+// One persistent analysis launch over the groups (plan, first slot,
+// planes), then the ring-block partial sums of each group that has several.
+clm_status analysis_groups(const MfmaGroup* gs, int ng, int nw, hipStream_t s) {
+  Plan* p = gs[0].p;
+  MfmaMulti mm{};
+  mm.ng = ng;
+  mm.ctr = p->mfma_ctr;
+  int items = 0;
+  for (int k = 0; k < ng; ++k) {
+    MfmaArgs& a = mm.g[k];
+    a = base_args(gs[k].p, gs[k].first_slot, gs[k].P);
+    a.F = gs[k].p->Fb;
+    a.part = gs[k].p->apart;
+    a.w = 4.0 * 3.14159265358979323846 / double(gs[k].p->npix_s);
+    a.nwv = nw;
+    a.R = ring_blocks_nw(a.H, nw);
+    mm.R[k] = a.R;
+    mm.start[k] = items;
+    items += (a.lmax + 1) * a.R;
+  }
+  mm.start[ng] = items;
+  const int form = form_of(p);
+  const size_t lds = size_t(nw) * kStep * (form == kFP32 ? 65 : 68) * 4 + sizeof(mm.g);
+  const int blocks = persistent_blocks(p, lds, nw, items);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, p->mfma_ctr);
+  {
+    CLM_TIMED(p, s, "sht_analysis_mfma");
+    const bool ok = form == kBF16X3   ? dispatch_ana<kBF16X3>(nw, mm, blocks, s)
+                    : form == kBF16X6 ? dispatch_ana<kBF16X6>(nw, mm, blocks, s)
+                                      : dispatch_ana<kFP32>(nw, mm, blocks, s);
+    if (!ok) return fail(p, CLM_EINVAL, "no analysis shape with that many waves");
+  }
+  CLM_LAUNCH_CHECK();
+  for (int k = 0; k < ng; ++k) {
+    const MfmaArgs& a = mm.g[k];
+    if (a.R == 1) continue;
+    const int64_t n = a.nalm * kCols;
+    CLM_TIMED(p, s, "sht_analysis_reduce");
+    hipLaunchKernelGGL(k_analysis_reduce, dim3(unsigned((n + kBlk - 1) / kBlk)), dim3(kBlk), 0,
+                       s, a, a.R);
+  }
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+// psi_lm of each group packed as GEMM columns, then one persistent
+// synthesis launch over the groups.
+clm_status synthesis_groups(const MfmaGroup* gs, int ng, int nw, hipStream_t s) {
+  Plan* p = gs[0].p;
+  MfmaMulti mm{};
+  mm.ng = ng;
+  mm.ctr = p->mfma_ctr;
+  int items = 0;
+  for (int k = 0; k < ng; ++k) {
+    MfmaArgs& a = mm.g[k];
+    a = base_args(gs[k].p, gs[k].first_slot, gs[k].P);
+    a.G = gs[k].p->Gb;
+    a.psi = gs[k].p->psib;
+    a.nwv = nw;
+    a.R = ring_blocks_nw(a.H, nw);
+    mm.R[k] = a.R;
+    mm.start[k] = items;
+    items += (a.lmax + 1) * a.R;
+    const int64_t n = a.nalm * kCols;
+    {
+      CLM_TIMED(p, s, "sht_pack_psi");
+      hipLaunchKernelGGL(k_pack_psi, dim3(unsigned((n + kBlk - 1) / kBlk)), dim3(kBlk), 0, s, a,
+                         gs[k].p->psib);
+    }
+    CLM_LAUNCH_CHECK();
+  }
+  mm.start[ng] = items;
+  const int form = form_of(p);
+  const size_t lds = size_t(nw) * kStep * kSynStride * 4 + sizeof(mm.g);
+  const int blocks = persistent_blocks(p, lds, nw, items);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, p->mfma_ctr);
+  {
+    CLM_TIMED(p, s, "sht_synthesis_mfma");
+    const bool ok = form == kBF16X3   ? dispatch_syn<kBF16X3>(nw, mm, blocks, s)
+                    : form == kBF16X6 ? dispatch_syn<kBF16X6>(nw, mm, blocks, s)
+                                      : dispatch_syn<kFP32>(nw, mm, blocks, s);
+    if (!ok) return fail(p, CLM_EINVAL, "no synthesis shape with that many waves");
+  }
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
 }
 
 }  // namespace
 
-// Ring blocks of the analysis (its partial sums are [R][nalm][32]).
-int mfma_ring_blocks(int H) { return ring_blocks(H, kAnaWaves); }
+// Ring blocks of the analysis at the fewest waves the autotuner may pick
+// (its partial sums are [R][nalm][32]).
+int mfma_ring_blocks(int H) { return ring_blocks_nw(H, kAnaNW[0]); }
 
 clm_status mfma_tables(Plan* p, hipStream_t s) {
   hipLaunchKernelGGL(k_recur_table, dim3(p->d.lmax + 1), dim3(kBlk), 0, s, p->d.lmax, p->rcoef);
@@ -482,57 +676,107 @@ clm_status mfma_tables(Plan* p, hipStream_t s) {
 }
 
 clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s) {
-  MfmaArgs a = base_args(p, first_slot, P);
-  a.F = p->Fb;
-  a.part = p->apart;
-  a.w = 4.0 * 3.14159265358979323846 / double(p->npix_s);
-  a.nwv = ring_waves(p->H, kAnaWaves);
-  const int R = ring_blocks(p->H, kAnaWaves);
-  const dim3 grid(p->d.lmax + 1, R), block(64 * a.nwv);
-  {
-    CLM_TIMED(p, s, "sht_analysis_mfma");
-    if (p->d.legendre_prec == CLM_BF16X3)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_mfma<kBF16X3>), grid, block, 0, s, a);
-    else if (p->d.legendre_prec == CLM_BF16X6)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_mfma<kBF16X6>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_mfma<kFP32>), grid, block, 0, s, a);
-  }
-  CLM_LAUNCH_CHECK();
-  if (R > 1) {
-    const int64_t n = p->nalm * kCols;
-    CLM_TIMED(p, s, "sht_analysis_reduce");
-    hipLaunchKernelGGL(k_analysis_reduce, dim3(unsigned((n + kBlk - 1) / kBlk)), dim3(kBlk), 0,
-                       s, a, R);
-  }
-  CLM_LAUNCH_CHECK();
-  return CLM_OK;
+  const MfmaGroup g{p, first_slot, P};
+  return analysis_groups(&g, 1, p->ana_nw, s);
 }
 
 clm_status mfma_synthesis(Plan* p, int first_slot, int P, hipStream_t s) {
-  MfmaArgs a = base_args(p, first_slot, P);
-  a.G = p->Gb;
-  a.psi = p->psib;
-  const int64_t n = p->nalm * kCols;
-  {
-    CLM_TIMED(p, s, "sht_pack_psi");
-    hipLaunchKernelGGL(k_pack_psi, dim3(unsigned((n + kBlk - 1) / kBlk)), dim3(kBlk), 0, s, a,
-                       p->psib);
+  const MfmaGroup g{p, first_slot, P};
+  return synthesis_groups(&g, 1, p->syn_nw, s);
+}
+
+clm_status mfma_analysis_multi(const MfmaGroup* gs, int ng, hipStream_t s) {
+  if (ng < 1 || ng > kMaxGroups) return fail(gs[0].p, CLM_EINVAL, "1 to 4 plans per launch");
+  return analysis_groups(gs, ng, gs[0].p->ana_nw, s);
+}
+
+clm_status mfma_synthesis_multi(const MfmaGroup* gs, int ng, hipStream_t s) {
+  if (ng < 1 || ng > kMaxGroups) return fail(gs[0].p, CLM_EINVAL, "1 to 4 plans per launch");
+  return synthesis_groups(gs, ng, gs[0].p->syn_nw, s);
+}
+
+// The autotuner: waves per workgroup of the analysis and of the synthesis,
+// chosen by timing each shape on the plan's own buffers with a full batch
+// (kept, for plans of the same device, grid, lmax, form and batch, for the
+// life of the process).  Shapes given in the description are kept.
+namespace {
+struct TuneKey {
+  int dev, nside, lmax, form, batch;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, nside, lmax, form, batch) <
+           std::tie(o.dev, o.nside, o.lmax, o.form, o.batch);
   }
-  CLM_LAUNCH_CHECK();
-  a.nwv = ring_waves(p->H, kMaxWaves);
-  const int R = ring_blocks(p->H, kMaxWaves);
-  const dim3 grid(p->d.lmax + 1, R), block(64 * a.nwv);
-  {
-    CLM_TIMED(p, s, "sht_synthesis_mfma");
-    if (p->d.legendre_prec == CLM_BF16X3)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis_mfma<kBF16X3>), grid, block, 0, s, a);
-    else if (p->d.legendre_prec == CLM_BF16X6)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis_mfma<kBF16X6>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_synthesis_mfma<kFP32>), grid, block, 0, s, a);
+};
+std::mutex g_tune_mutex;
+std::map<TuneKey, std::pair<int, int>> g_tuned;
+
+template <typename F>
+float time_launch(F f, clm_status& st) {
+  hipEvent_t a = nullptr, b = nullptr;
+  float best = 1e30f;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    st = CLM_EHIP;
+    return best;
   }
-  CLM_LAUNCH_CHECK();
+  for (int rep = 0; rep < 3 && st == CLM_OK; ++rep) {
+    (void)hipEventRecord(a, nullptr);
+    st = f();
+    (void)hipEventRecord(b, nullptr);
+    float ms = 0.f;
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      st = CLM_EHIP;
+    if (rep > 0) best = std::min(best, ms);  // the first launch is a warm-up
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+}  // namespace
+
+clm_status mfma_autotune(Plan* p) {
+  const clm_plan_desc& d = p->d;
+  const TuneKey key{p->device, d.nside_sht, d.lmax, form_of(p), p->batch};
+  int ana = d.mfma_ana_waves, syn = d.mfma_syn_waves;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      if (ana == 0) ana = it->second.first;
+      if (syn == 0) syn = it->second.second;
+    }
+  }
+  const size_t nF = size_t(p->nring_s) * (d.lmax + 1) * 2;
+  if (ana == 0 || syn == 0) {
+    if (hipMemset(p->Fb, 0, nF * p->batch * 8) != hipSuccess ||
+        hipMemset(p->psib, 0, size_t(p->nalm) * kCols * 4) != hipSuccess)
+      return fail(p, CLM_EHIP, "autotune set-up failed");
+  }
+  clm_status st = CLM_OK;
+  const MfmaGroup g{p, 0, p->batch};
+  if (ana == 0) {
+    float best = 1e30f;
+    for (int nw : kAnaNW) {
+      const float t = time_launch([&] { return analysis_groups(&g, 1, nw, nullptr); }, st);
+      if (st != CLM_OK) return st;
+      p->tune_ms.push_back({std::string("analysis_waves_") + std::to_string(nw), t});
+      if (t < best) { best = t; ana = nw; }
+    }
+  }
+  if (syn == 0) {
+    float best = 1e30f;
+    for (int nw : kSynNW) {
+      const float t = time_launch([&] { return synthesis_groups(&g, 1, nw, nullptr); }, st);
+      if (st != CLM_OK) return st;
+      p->tune_ms.push_back({std::string("synthesis_waves_") + std::to_string(nw), t});
+      if (t < best) { best = t; syn = nw; }
+    }
+  }
+  p->ana_nw = ana;
+  p->syn_nw = syn;
+  p->d.mfma_ana_waves = ana;
+  p->d.mfma_syn_waves = syn;
+  std::lock_guard<std::mutex> lk(g_tune_mutex);
+  g_tuned[key] = {ana, syn};
   return CLM_OK;
 }
 

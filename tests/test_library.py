@@ -39,13 +39,15 @@ def test_default_description(L):
     assert (d.mg_vcycles, d.nu_pre, d.nu_post, d.patch_factor) == (4, 2, 2, 4)
     assert (d.mg_max_vcycles, d.mg_eps, d.adjoint) == (20, 0.1, 0)
     assert d.analysis_iters == 0
-    assert ctypes.sizeof(d) == 72  # 14 int32, padding, a double, two int32
+    assert (d.mfma_ana_waves, d.mfma_syn_waves) == (0, 0)
+    assert ctypes.sizeof(d) == 80  # 14 int32, padding, a double, four int32
 
 
 @pytest.mark.parametrize("fields", [
     dict(nside_fine=100), dict(nside_sht=4096), dict(patch_cells=96), dict(nu_pre=0),
     dict(mg_vcycles=-1), dict(max_planes=0), dict(solver=7), dict(mg_prec=9),
-    dict(nside_bundle=1), dict(legendre_prec=3), dict(legendre_prec=-1), dict(lmax=(1 << 20) + 1),
+    dict(nside_bundle=1), dict(legendre_prec=4), dict(legendre_prec=-1),
+    dict(mfma_ana_waves=4), dict(mfma_syn_waves=10), dict(lmax=(1 << 20) + 1),
     # the epsilon rule needs a positive threshold and cycle limit, and the
     # adjoint a fixed cycle count
     dict(mg_vcycles=0, mg_eps=0.0), dict(mg_vcycles=0, mg_max_vcycles=0),
