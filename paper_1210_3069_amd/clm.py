@@ -3,6 +3,7 @@ tensors are passed by device pointer together with the current HIP stream;
 every step of the computation runs in the library's kernels.  Raises when
 the library is missing or a call fails; there is no fallback path."""
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -179,8 +180,46 @@ def poisson_solve_multi(plans, kappas):
                     "poisson_solve_multi")
 
 
+def tune_cache_path():
+    """JSON file of the autotuner's choices: $CALCLENS_MI_TUNE_CACHE, else
+    ~/.cache/calclens_mi/autotune.json."""
+    return os.environ.get("CALCLENS_MI_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "calclens_mi", "autotune.json")
+
+
+def _tune_key(dev, d):
+    batch = min(d.max_planes, 16)
+    return "%s|nside %d|lmax %d|form %d|batch %d" % (torch.cuda.get_device_name(dev), d.nside_sht,
+                                                     d.lmax, d.legendre_prec, batch)
+
+
+def _tune_load():
+    try:
+        with open(tune_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _tune_store(key, ana, syn):
+    path = tune_cache_path()
+    table = _tune_load()
+    table[key] = [int(ana), int(syn)]
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home keeps the in-process choice only
+
+
 class Plan:
-    """A solver plan (workspace on the current device)."""
+    """A solver plan (workspace on the current device).  Matrix-core plans
+    whose workgroup shapes are not given take them from the autotuner's JSON
+    cache (tune_cache_path()) or, on a miss, from the library's autotuner,
+    whose choice is then added to the cache."""
 
     def __init__(self, nside_fine, device=None, **kw):
         L = lib()
@@ -193,6 +232,14 @@ class Plan:
                 v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}[v]
             setattr(d, k, float(v) if k == "mg_eps" else int(v))
         dev = torch.cuda.current_device() if device is None else int(device)
+        tune_key = None
+        if d.legendre_prec != FP64 and (d.mfma_ana_waves == 0 or d.mfma_syn_waves == 0):
+            tune_key = _tune_key(dev, d)
+            hit = _tune_load().get(tune_key)
+            if hit and len(hit) == 2:
+                d.mfma_ana_waves = d.mfma_ana_waves or int(hit[0])
+                d.mfma_syn_waves = d.mfma_syn_waves or int(hit[1])
+                tune_key = None
         h = ctypes.c_void_p()
         st = L.clm_plan_create(ctypes.byref(d), dev, ctypes.byref(h))
         if st != CLM_OK:
@@ -206,6 +253,8 @@ class Plan:
         self.npix_fine = 12 * nf * nf
         self.npix_sht = 12 * self.desc["nside_sht"] ** 2
         self.lmax = self.desc["lmax"]
+        if tune_key is not None:
+            _tune_store(tune_key, self.desc["mfma_ana_waves"], self.desc["mfma_syn_waves"])
 
     def _check(self, st, what, h="self"):
         if st == CLM_OK:

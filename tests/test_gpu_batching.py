@@ -97,13 +97,27 @@ def test_multi_graph_replays(clm, maps):
         pl.close()
 
 
-def test_autotuner_choice(clm):
-    """Shapes left at 0 are chosen at plan creation among the built ones;
+def test_autotuner_choice(clm, tmp_path, monkeypatch):
+    """Shapes left at 0 are chosen at plan creation among the built ones and
+    kept in the JSON cache, which the next plan of that grid and form reads;
     given shapes are kept; an unknown shape is rejected."""
+    import json
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("CALCLENS_MI_TUNE_CACHE", str(cache))
     pl = clm.Plan(64, nside_sht=64, lmax=128, solver="sht", max_planes=4,
                   legendre_prec="bf16x6")
-    assert pl.desc["mfma_ana_waves"] in (8, 16)
-    assert pl.desc["mfma_syn_waves"] in (8, 12, 16)
+    pick = (pl.desc["mfma_ana_waves"], pl.desc["mfma_syn_waves"])
+    assert pick[0] in (8, 16) and pick[1] in (8, 12, 16)
+    pl.close()
+    table = json.loads(cache.read_text())
+    assert list(table.values()) == [list(pick)]
+    # a planted entry is what the next plan of the same key uses
+    key = list(table)[0]
+    other = (16, 12) if pick != (16, 12) else (8, 8)
+    cache.write_text(json.dumps({key: list(other)}))
+    pl = clm.Plan(64, nside_sht=64, lmax=128, solver="sht", max_planes=4,
+                  legendre_prec="bf16x6")
+    assert (pl.desc["mfma_ana_waves"], pl.desc["mfma_syn_waves"]) == other
     pl.close()
     pl = clm.Plan(64, nside_sht=64, lmax=128, solver="sht", max_planes=4,
                   legendre_prec="fp32", mfma_ana_waves=16, mfma_syn_waves=12)

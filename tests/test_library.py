@@ -72,3 +72,19 @@ def test_null_arguments_rejected(L):
     assert L.clm_poisson_solve(None, None, 1, 0, 1, None) == clm.CLM_EINVAL
     assert L.clm_plan_destroy(None) == clm.CLM_EINVAL
     assert L.clm_status_string(5) == b"a point left its bundle's patch"
+
+
+def test_tune_cache_roundtrip(tmp_path, monkeypatch):
+    """The autotuner's JSON cache: stored choices are read back; a missing or
+    unreadable file reads as empty."""
+    from paper_1210_3069_amd import clm
+    path = tmp_path / "sub" / "tune.json"
+    monkeypatch.setenv("CALCLENS_MI_TUNE_CACHE", str(path))
+    assert clm.tune_cache_path() == str(path)
+    assert clm._tune_load() == {}
+    clm._tune_store("gpu|nside 512|lmax 1024|form 1|batch 6", 8, 16)
+    clm._tune_store("gpu|nside 2048|lmax 4096|form 3|batch 15", 16, 12)
+    assert clm._tune_load() == {"gpu|nside 512|lmax 1024|form 1|batch 6": [8, 16],
+                                "gpu|nside 2048|lmax 4096|form 3|batch 15": [16, 12]}
+    path.write_text("not json")
+    assert clm._tune_load() == {}
