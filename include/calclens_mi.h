@@ -372,6 +372,36 @@ clm_status clm_galaxies_shell(clm_plan plan, const double* chi_host, int32_t nch
                               const clm_galaxies* galaxies, hipStream_t stream);
 
 /*
+ * Galaxy images by the grid search (Sec. 2.3, Sec. 3.3, App. D) for the
+ * galaxies of shell k (chi between the midpoints around chi_k; the last
+ * shell open above), after the ray update through plane k - 1 (rays at
+ * chi_k with A^(k) in rays->A and A^(k-1) in rays->A_prev).  The image
+ * plane is covered by triangles of ray pixel centres (those of consecutive
+ * rings merged in azimuth; two per polar cap).  Each ray is moved from chi_k
+ * to the galaxy's chi along its direction (no further deflection, the root
+ * of eq. posprop of least |lambda|); a triangle whose three rays there
+ * enclose the galaxy (barycentric coordinates >= 0 in the plane tangent at
+ * the galaxy, gnomonic projection) gives the image: the same coordinates
+ * applied to the triangle's pixel centres.  The search covers the triangles
+ * within search_radius (rad, at most 0.02; 0: two fine-pixel sizes) of the
+ * predicted image (the galaxy moved by the image - source offset of its
+ * pixel's ray), nearest first, then within twice that of the galaxy.  The Jacobian at the image is the
+ * HEALPix four-point interpolation of the rays' A^(k-1) and A^(k), each
+ * parallel transported to the image (App. B), combined by eq. gatraj, in
+ * the (theta-hat, phi-hat) basis at the image.  Shell 0: image = galaxy,
+ * A = I.  Outputs for the shell's galaxies: theta_img_dev, phi_img_dev
+ * [ngal] float64, found_dev [ngal] int32 (0: no image within the search,
+ * NaN outputs) and galaxies->A [4][ngal] float32; other galaxies are left
+ * untouched.  chi_host, nchi and curvature_K as for clm_raytrace_planes.
+ * Asynchronous on `stream`.
+ */
+clm_status clm_galaxy_images(clm_plan plan, const double* chi_host, int32_t nchi, int32_t k,
+                             double curvature_K, const clm_rays* rays,
+                             const clm_galaxies* galaxies, double search_radius,
+                             double* theta_img_dev, double* phi_img_dev, int32_t* found_dev,
+                             hipStream_t stream);
+
+/*
  * The reduced galaxy step of App. D (eq. gatraj) for the shell the rays
  * have just reached: after a clm_ray_update or clm_raytrace_planes through
  * plane m, the rays hold A^(k) (rays->A) and A^(k-1) (rays->A_prev) for

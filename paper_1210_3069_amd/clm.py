@@ -83,6 +83,8 @@ _SIGS = {
     "clm_plan_timings": (_P, ctypes.POINTER(_D), _I32),
     "clm_plan_stage_name": (_P, _I32),
     "clm_galaxies_reduced": (_P, ctypes.POINTER(Rays), _P, _P, _P, _I64, _P, _P),
+    "clm_galaxy_images": (_P, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays),
+                          ctypes.POINTER(Galaxies), _D, _P, _P, _P, _P),
     "clm_plan_get_timing": (_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_D),
                             ctypes.POINTER(_I64), _I32, ctypes.POINTER(_I32)),
 }
@@ -457,6 +459,25 @@ class Plan:
                                        _ptr(galaxies["phi"]), _ptr(galaxies["chi"]),
                                        galaxies["theta"].numel(), _ptr(galaxies["A"]),
                                        _stream()), "galaxies")
+
+    def galaxy_images(self, chi, k, rays, galaxies, radius=0.0, K=0.0):
+        """The grid search for the images of the galaxies of shell k (after the
+        ray update through plane k - 1): returns (theta_img, phi_img, found)
+        device tensors [ngal] and writes galaxies["A"] (the Jacobian at the
+        image) for the shell's galaxies."""
+        chi = np.ascontiguousarray(chi, dtype=np.float64)
+        s = self._rays_struct(rays)
+        n = galaxies["theta"].numel()
+        g = Galaxies(galaxies["theta"].data_ptr(), galaxies["phi"].data_ptr(),
+                     galaxies["chi"].data_ptr(), galaxies["A"].data_ptr(), n)
+        th = torch.full((n,), float("nan"), dtype=torch.float64, device=self.device)
+        ph = torch.full((n,), float("nan"), dtype=torch.float64, device=self.device)
+        fd = torch.zeros(n, dtype=torch.int32, device=self.device)
+        self._check(lib().clm_galaxy_images(self.h, chi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            chi.size, k, K, ctypes.byref(s), ctypes.byref(g),
+                                            float(radius), _ptr(th), _ptr(ph), _ptr(fd),
+                                            _stream()), "galaxy_images")
+        return th, ph, fd
 
     def ray_update(self, chi, m, rays, slot=0, K=0.0):
         chi = np.ascontiguousarray(chi, dtype=np.float64)

@@ -269,6 +269,10 @@ clm_status ray_update(Plan* p, int slot, const double* chi, int nchi, int m,
 clm_status galaxies_shell(Plan* p, const double* chi, int nchi, int k, double K,
                           const clm_rays* r, const clm_galaxies* g,
                           hipStream_t s);               // rays.hip
+clm_status galaxy_images(Plan* p, const double* chi, int nchi, int k, double K,
+                         const clm_rays* r, const clm_galaxies* g, double radius,
+                         double* th_img, double* ph_img, int* found,
+                         hipStream_t s);                // rays.hip
 
 inline int ilog2(int64_t v) {
   int k = 0;

@@ -787,6 +787,24 @@ clm_status clm_galaxies_shell(clm_plan plan, const double* chi, int32_t nchi, in
   return galaxies_shell(p, chi, nchi, k, K, rays, gal, stream);
 }
 
+clm_status clm_galaxy_images(clm_plan plan, const double* chi, int32_t nchi, int32_t k,
+                             double K, const clm_rays* rays, const clm_galaxies* gal,
+                             double search_radius, double* theta_img, double* phi_img,
+                             int32_t* found, hipStream_t stream) {
+  if (!plan || !chi || !rays || !gal || rays->n != plan->npix_f || k < 0 || k >= nchi ||
+      gal->n < 0 || !(search_radius >= 0) || search_radius > 0.02 ||
+      (gal->n > 0 && (!gal->theta || !gal->phi || !gal->chi || !gal->A || !theta_img ||
+                      !phi_img || !found)))
+    return CLM_EINVAL;
+  for (int q = 1; q < nchi; ++q)
+    if (!(chi[q] > chi[q - 1]) || !(chi[0] > 0)) return CLM_EINVAL;
+  if (gal->n == 0) return CLM_OK;
+  Plan* p = plan;
+  CLM_HIP(hipSetDevice(p->device));
+  return galaxy_images(p, chi, nchi, k, K, rays, gal, search_radius, theta_img, phi_img, found,
+                       stream);
+}
+
 clm_status clm_raytrace_planes(clm_plan plan, const void* kappa, int32_t kappa_is_fp64,
                                const double* chi, int32_t nchi, int32_t first_plane,
                                int32_t nplanes, double K, const clm_rays* rays,

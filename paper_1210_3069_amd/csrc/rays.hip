@@ -236,7 +236,355 @@ __global__ void k_galaxies(GalArgs a) {
   for (int k = 0; k < 4; ++k) a.Ag[k * ng + i] = float((1.0 - w) * Api[k] + w * Ai[k]);
 }
 
+// ---------------------------------------------------------------- images
+// The grid search for galaxy images (Sec. 2.3, Sec. 3.3, App. D).  The
+// image-plane triangles join the pixel centres of consecutive rings: the
+// two rings' centres merged in azimuth, each merge step adding the
+// triangle of the current pair and the next vertex; the four pixels of
+// each polar ring close the caps.  A triangle of the band between rings A
+// and B that advances on A from vertex j to j + 1 has its apex at the last
+// vertex of B before A's vertex j + 1 in azimuth, found in integers from
+// the rings' pixel counts and half-pixel shifts.
+struct ImgArgs {
+  hpx::Rings rf;
+  const int* r2n_f;
+  int64_t nray;
+  const double* rth;      // ray angular positions at chi_k
+  const double* rph;
+  const double* beta;     // [3][nray]
+  const float* A;
+  const float* Ap;
+  const double* th;       // galaxies
+  const double* ph;
+  const double* chi;
+  float* Ag;
+  double* th_img;
+  double* ph_img;
+  int* found;
+  int64_t ngal;
+  double lo, hi;          // shell [lo, hi)
+  int k;
+  double chi_km1, chi_k, K;
+  double radius;          // search radius around the predicted image (rad)
+};
+
+struct RingGeo {
+  int n, first, s;        // pixels, first pixel, half-pixel shift of the azimuths
+  double z, st, phi0;
+};
+
+__device__ __forceinline__ RingGeo ring_geo(const hpx::Rings& R, int q) {
+  RingGeo g;
+  g.n = R.ri[2 * q];
+  g.first = R.ri[2 * q + 1];
+  g.z = R.rt[4 * q];
+  g.st = R.rt[4 * q + 1];
+  g.phi0 = R.rt[4 * q + 3];
+  g.s = g.phi0 != 0.0 ? 1 : 0;
+  return g;
+}
+
+__device__ __forceinline__ void ring_vec(const RingGeo& g, int j, double v[3]) {
+  double sp, cp;
+  sincospi(2.0 * (double(j) + 0.5 * g.s) / double(g.n), &sp, &cp);
+  v[0] = g.st * cp;
+  v[1] = g.st * sp;
+  v[2] = g.z;
+}
+
+// Last vertex of ring B before vertex jn of ring A in azimuth (cyclic).
+__device__ __forceinline__ int pred_vertex(int jn, const RingGeo& a, const RingGeo& b) {
+  const int64_t X = (2 * int64_t(jn) + a.s) * b.n - int64_t(b.s) * a.n;
+  const int64_t d = 2 * int64_t(a.n);
+  int64_t k = X >= 0 ? (X + d - 1) / d - 1 : -((-X) / d) - 1;
+  k %= b.n;
+  if (k < 0) k += b.n;
+  return int(k);
+}
+
+// A ray moved along its direction from radius c0 to c1 (the root of
+// eq. posprop of least |lambda|), as a unit vector.
+__device__ __forceinline__ void ray_at(const ImgArgs& a, int64_t r, double c1, double out[3],
+                                       double nr[3]) {
+  double st, ct, sp, cp;
+  sincos(a.rth[r], &st, &ct);
+  sincos(a.rph[r], &sp, &cp);
+  nr[0] = st * cp;
+  nr[1] = st * sp;
+  nr[2] = ct;
+  const double b3[3] = {a.beta[r], a.beta[a.nray + r], a.beta[2 * a.nray + r]};
+  const double x[3] = {a.chi_k * nr[0], a.chi_k * nr[1], a.chi_k * nr[2]};
+  const double bb = x[0] * b3[0] + x[1] * b3[1] + x[2] * b3[2];
+  const double q = c1 * c1 - a.chi_k * a.chi_k;
+  const double lam = q / (bb + sqrt(bb * bb + q));
+  double y[3] = {x[0] + lam * b3[0], x[1] + lam * b3[1], x[2] + lam * b3[2]};
+  const double yl = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+  out[0] = y[0] / yl;
+  out[1] = y[1] / yl;
+  out[2] = y[2] / yl;
+}
+
+// Triangle (RING pixels pa, pb, pc with image-plane vectors va, vb, vc):
+// true, with the image, when the galaxy g lies in its source triangle
+// (barycentric coordinates >= 0 after gnomonic projection about g).
+__device__ bool try_triangle(const ImgArgs& a, const double g[3], double cg, const int pix[3],
+                             const double (&vimg)[3][3], double img[3]) {
+  double P[3][3];
+  for (int i = 0; i < 3; ++i) {
+    double sv[3], nr[3];
+    ray_at(a, a.r2n_f[pix[i]], cg, sv, nr);
+    const double dg = sv[0] * g[0] + sv[1] * g[1] + sv[2] * g[2];
+    if (!(dg > 0.0)) return false;
+    for (int c = 0; c < 3; ++c) P[i][c] = sv[c] / dg - g[c];
+  }
+  double e1[3], e2[3], r[3];
+  for (int c = 0; c < 3; ++c) {
+    e1[c] = P[1][c] - P[0][c];
+    e2[c] = P[2][c] - P[0][c];
+    r[c] = -P[0][c];
+  }
+  const double m00 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+  const double m01 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+  const double m11 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+  const double r0 = r[0] * e1[0] + r[1] * e1[1] + r[2] * e1[2];
+  const double r1 = r[0] * e2[0] + r[1] * e2[1] + r[2] * e2[2];
+  const double det = m00 * m11 - m01 * m01;
+  if (!(det > 0.0)) return false;
+  const double b1 = (r0 * m11 - r1 * m01) / det;
+  const double b2 = (m00 * r1 - m01 * r0) / det;
+  const double b0 = 1.0 - b1 - b2;
+  if (!(b0 >= 0.0 && b1 >= 0.0 && b2 >= 0.0)) return false;
+  const double b[3] = {b0, b1, b2};
+  double s3[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 3; ++i) {
+    const double d = vimg[i][0] * g[0] + vimg[i][1] * g[1] + vimg[i][2] * g[2];
+    for (int c = 0; c < 3; ++c) s3[c] += b[i] * vimg[i][c] / d;
+  }
+  const double l = sqrt(s3[0] * s3[0] + s3[1] * s3[1] + s3[2] * s3[2]);
+  for (int c = 0; c < 3; ++c) img[c] = s3[c] / l;
+  return true;
+}
+
+// The triangles of the bands whose rings lie within `radius` of the unit
+// vector c, in azimuth windows around c, nearest first (the central band,
+// then the neighbours on both sides; in a band the nearest vertices
+// first); stops at the first triangle whose source triangle holds g.
+__device__ bool search_images(const ImgArgs& a, const double g[3], double cg, const double c[3],
+                              double radius, double img[3]) {
+  const hpx::Rings& R = a.rf;
+  const int N = R.N, nring = R.nring;
+  const double pi = 3.14159265358979323846;
+  const double zc = c[2], rc = sqrt(c[0] * c[0] + c[1] * c[1]);
+  double phc = hpx::atan2_r(c[1], c[0]);
+  if (phc < 0) phc += 2.0 * pi;
+  const hpx::GlobalRingTab tab{R, 0.0};
+  const int gc = hpx::ring_above(tab, zc);
+  // ring spacing is at most about 1.2 / N in colatitude
+  const int W = int(radius * N * 1.25) + 1;
+  const double dphi = radius / fmax(rc, 1e-300) + pi / (2.0 * N);
+  for (int dq = 0; dq <= 2 * W; ++dq) {
+    const int q = gc + ((dq & 1) ? -(dq + 1) / 2 : dq / 2);
+    if (q < -1 || q > nring - 1) continue;
+    if (q == -1 || q == nring - 1) {
+      const RingGeo cap = ring_geo(R, q == -1 ? 0 : nring - 1);
+      double v[4][3];
+      for (int j = 0; j < 4; ++j) ring_vec(cap, j, v[j]);
+      const int order[2][3] = {{0, 1, 2}, {0, 2, 3}};
+      for (int t = 0; t < 2; ++t) {
+        int pix[3];
+        double vi[3][3];
+        for (int i = 0; i < 3; ++i) {
+          // the vertex order does not change the test
+          const int j = order[t][i];
+          pix[i] = cap.first + j;
+          for (int cc = 0; cc < 3; ++cc) vi[i][cc] = v[j][cc];
+        }
+        if (try_triangle(a, g, cg, pix, vi, img)) return true;
+      }
+      continue;
+    }
+    const RingGeo A = ring_geo(R, q), B = ring_geo(R, q + 1);
+    // vertices j of each ring around the azimuth of c, nearest first
+    // (the window is capped at a full ring: near the poles dphi is large)
+    const int ha = int(fmin(dphi * A.n / (2.0 * pi), double(A.n))) + 1;
+    const int hb = int(fmin(dphi * B.n / (2.0 * pi), double(B.n))) + 1;
+    const int na = 2 * ha + 1 >= A.n ? A.n : 2 * ha + 1;
+    const int nb = 2 * hb + 1 >= B.n ? B.n : 2 * hb + 1;
+    const int ja = int(floor(phc * A.n / (2.0 * pi) - 0.5 * A.s));
+    const int jb = int(floor(phc * B.n / (2.0 * pi) - 0.5 * B.s));
+    for (int t = 0; t < na + nb; ++t) {
+      const bool sa = t < na;
+      const RingGeo& P = sa ? A : B;
+      const RingGeo& Q = sa ? B : A;
+      const int o = sa ? t : t - na;
+      int j = (sa ? ja : jb) + ((o & 1) ? -(o + 1) / 2 : o / 2);
+      j %= P.n;
+      if (j < 0) j += P.n;
+      const int jn = j + 1 == P.n ? 0 : j + 1;
+      const int kq = pred_vertex(jn, P, Q);
+      int pix[3] = {P.first + j, Q.first + kq, P.first + jn};
+      double vi[3][3];
+      ring_vec(P, j, vi[0]);
+      ring_vec(Q, kq, vi[1]);
+      ring_vec(P, jn, vi[2]);
+      if (try_triangle(a, g, cg, pix, vi, img)) return true;
+    }
+  }
+  return false;
+}
+
+// Four-point interpolation at the image of the ray Jacobians, each
+// transported from its ray's position to the image (App. B), and eq. gatraj.
+__device__ void image_jacobian(const ImgArgs& a, const double img[3], double w, double Ag[4]) {
+  const double pi = 3.14159265358979323846;
+  const double rho = sqrt(img[0] * img[0] + img[1] * img[1]);
+  double ph = hpx::atan2_r(img[1], img[0]);
+  if (ph < 0) ph += 2.0 * pi;
+  int pix[4];
+  double wt[4];
+  hpx::interp_weights(a.rf, img[2], rho, ph, pix, wt);
+  double et1[3], ep1[3];
+  basis(img, et1, ep1);
+  double S[4] = {0, 0, 0, 0}, Sp[4] = {0, 0, 0, 0};
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r = a.r2n_f[pix[q]];
+    double st, ct, sp, cp;
+    sincos(a.rth[r], &st, &ct);
+    sincos(a.rph[r], &sp, &cp);
+    const double nv[3] = {st * cp, st * sp, ct};
+    double et[3], ep[3];
+    basis(nv, et, ep);
+    double ax[3] = {nv[1] * img[2] - nv[2] * img[1], nv[2] * img[0] - nv[0] * img[2],
+                    nv[0] * img[1] - nv[1] * img[0]};
+    const double sn = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    double rt[3], rp[3];
+    if (sn > 0) {
+      ax[0] /= sn; ax[1] /= sn; ax[2] /= sn;
+      const double cw = nv[0] * img[0] + nv[1] * img[1] + nv[2] * img[2];
+      const double omc = sn * sn / (1.0 + cw);
+      rotate_cs(ax, cw, sn, omc, et, rt);
+      rotate_cs(ax, cw, sn, omc, ep, rp);
+    } else {
+      for (int c = 0; c < 3; ++c) { rt[c] = et[c]; rp[c] = ep[c]; }
+    }
+    const double M[4] = {et1[0] * rt[0] + et1[1] * rt[1] + et1[2] * rt[2],
+                         et1[0] * rp[0] + et1[1] * rp[1] + et1[2] * rp[2],
+                         ep1[0] * rt[0] + ep1[1] * rt[1] + ep1[2] * rt[2],
+                         ep1[0] * rp[0] + ep1[1] * rp[1] + ep1[2] * rp[2]};
+    auto add = [&](const float* src, double acc[4]) {
+      const double X[4] = {double(src[r]), double(src[a.nray + r]), double(src[2 * a.nray + r]),
+                           double(src[3 * a.nray + r])};
+      const double t00 = M[0] * X[0] + M[1] * X[2], t01 = M[0] * X[1] + M[1] * X[3];
+      const double t10 = M[2] * X[0] + M[3] * X[2], t11 = M[2] * X[1] + M[3] * X[3];
+      acc[0] += wt[q] * (t00 * M[0] + t01 * M[1]);
+      acc[1] += wt[q] * (t00 * M[2] + t01 * M[3]);
+      acc[2] += wt[q] * (t10 * M[0] + t11 * M[1]);
+      acc[3] += wt[q] * (t10 * M[2] + t11 * M[3]);
+    };
+    add(a.A, S);
+    add(a.Ap, Sp);
+  }
+  for (int c = 0; c < 4; ++c) Ag[c] = (1.0 - w) * Sp[c] + w * S[c];
+}
+
+// One galaxy per thread: the image search around a predicted image (the
+// galaxy moved by the offset between its pixel's image and source
+// positions), then once more around the galaxy itself with twice the
+// radius; galaxies not found get NaN and found = 0.
+__global__ __launch_bounds__(kBlock) void k_galaxy_images(ImgArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.ngal) return;
+  const double cg = a.chi[i];
+  if (!(cg >= a.lo && cg < a.hi)) return;
+  const int64_t ng = a.ngal;
+  if (a.k == 0) {
+    a.th_img[i] = a.th[i];
+    a.ph_img[i] = a.ph[i];
+    a.found[i] = 1;
+    a.Ag[i] = 1.f; a.Ag[ng + i] = 0.f; a.Ag[2 * ng + i] = 0.f; a.Ag[3 * ng + i] = 1.f;
+    return;
+  }
+  double st, ct, sp, cp;
+  sincos(a.th[i], &st, &ct);
+  sincos(a.ph[i], &sp, &cp);
+  const double g[3] = {st * cp, st * sp, ct};
+  // predicted image: g plus the image - source offset of the pixel at g
+  const double pi = 3.14159265358979323846;
+  double ph = a.ph[i] - 2.0 * pi * floor(a.ph[i] / (2.0 * pi));
+  int pix4[4];
+  double w4[4];
+  hpx::interp_weights(a.rf, ct, st, ph, pix4, w4);
+  int best = 0;
+  for (int q = 1; q < 4; ++q)
+    if (w4[q] > w4[best]) best = q;
+  double z0, s0, p0;
+  hpx::pix2ang_ring(a.rf.N, pix4[best], z0, s0, p0);
+  const double v0[3] = {s0 * cos(p0), s0 * sin(p0), z0};
+  double src0[3], nr0[3];
+  ray_at(a, a.r2n_f[pix4[best]], cg, src0, nr0);
+  double c[3] = {g[0] + v0[0] - src0[0], g[1] + v0[1] - src0[1], g[2] + v0[2] - src0[2]};
+  const double cl = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  c[0] /= cl; c[1] /= cl; c[2] /= cl;
+  double img[3];
+  bool ok = search_images(a, g, cg, c, a.radius, img);
+  if (!ok) ok = search_images(a, g, cg, g, 2.0 * a.radius, img);
+  if (!ok) {
+    a.th_img[i] = NAN;
+    a.ph_img[i] = NAN;
+    a.found[i] = 0;
+    for (int q = 0; q < 4; ++q) a.Ag[q * ng + i] = NAN;
+    return;
+  }
+  const double w = r_of(a.chi_k, a.K) * r_of(cg - a.chi_km1, a.K) /
+                   (r_of(cg, a.K) * r_of(a.chi_k - a.chi_km1, a.K));
+  double Ag[4];
+  image_jacobian(a, img, w, Ag);
+  for (int q = 0; q < 4; ++q) a.Ag[q * ng + i] = float(Ag[q]);
+  double phi = hpx::atan2_r(img[1], img[0]);
+  if (phi < 0) phi += 2.0 * pi;
+  a.th_img[i] = hpx::atan2_r(sqrt(img[0] * img[0] + img[1] * img[1]), img[2]);
+  a.ph_img[i] = phi;
+  a.found[i] = 1;
+}
+
 }  // namespace
+
+clm_status galaxy_images(Plan* p, const double* chi, int nchi, int k, double K,
+                         const clm_rays* r, const clm_galaxies* gl, double radius,
+                         double* th_img, double* ph_img, int* found, hipStream_t s) {
+  const int N = nchi - 1;
+  auto edge = [&](int e) { return e == 0 ? 0.0 : 0.5 * (chi[e - 1] + chi[e]); };
+  ImgArgs a;
+  a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->ringx_f, p->nring_f, p->d.nside_fine};
+  a.r2n_f = p->r2n_f;
+  a.nray = r->n;
+  a.rth = r->theta;
+  a.rph = r->phi;
+  a.beta = r->beta;
+  a.A = r->A;
+  a.Ap = r->A_prev;
+  a.th = gl->theta;
+  a.ph = gl->phi;
+  a.chi = gl->chi;
+  a.Ag = gl->A;
+  a.th_img = th_img;
+  a.ph_img = ph_img;
+  a.found = found;
+  a.ngal = gl->n;
+  a.k = k;
+  a.lo = edge(k);
+  a.hi = k < N ? edge(k + 1) : INFINITY;
+  a.chi_km1 = k >= 1 ? chi[k - 1] : 0.0;
+  a.chi_k = k <= N ? chi[k] : 0.0;
+  a.K = K;
+  a.radius = radius > 0 ? radius : 2.0 * std::sqrt(4.0 * 3.14159265358979323846 /
+                                                   double(p->npix_f));
+  CLM_TIMED(p, s, "galaxy_images");
+  hipLaunchKernelGGL(k_galaxy_images, dim3((gl->n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     a);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
 
 clm_status rays_init(Plan* p, const clm_rays* r, hipStream_t s) {
   hipLaunchKernelGGL(k_rays_init, dim3((r->n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,

@@ -1,0 +1,143 @@
+"""GPU parity of the galaxy-image grid search (clm_galaxy_images) with the
+oracle (Sec. 2.3, Sec. 3.3, App. D).
+
+The ray state is synthetic and seeded: the rays of an Nside 64 grid at their
+pixel centres displaced by a smooth random rotation field (a fraction of a
+pixel), directions tilted slightly from the positions, and Jacobians near
+the identity (float32, as the ray state stores them).  The same state goes
+to the library and to the oracle; galaxies (some near the poles) are given
+in one shell.  Image positions are compared to 1e-12 rad, Jacobians to the
+float32 level.  End to end: with zero convergence every image is its
+source; with weak lensing every galaxy of a shell has an image."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import healpix as hp
+from oracle import images as im
+from paper_1210_3069_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+PIXEL = lambda N: np.sqrt(4 * np.pi / (12 * N * N))
+
+
+@pytest.fixture(scope="module")
+def clm():
+    from paper_1210_3069_amd import clm as c
+    c.lib()
+    assert torch.cuda.is_available()
+    return c
+
+
+def synthetic_rays(N, seed, shift):
+    """NESTED-order ray state: positions = pixel centres turned by a smooth
+    rotation field of about `shift` rad, directions tilted by 1e-3 rad,
+    Jacobians I + 0.05 (smooth fields), rounded to float32."""
+    rng = np.random.default_rng(seed)
+    a, b, c, d = (rng.standard_normal(3) for _ in range(4))
+    a *= shift / np.linalg.norm(a)
+    b *= shift / np.linalg.norm(b)
+    n_pix = 12 * N * N
+    z, ph, s = hp.pix2ang_nest(N, np.arange(n_pix))
+    n = hp.vec(z, ph, s)
+    pos = n + np.cross(a, n) + (n @ c)[:, None] * np.cross(b, n)
+    pos /= np.linalg.norm(pos, axis=1)[:, None]
+    beta = pos + 1e-3 * np.cross(d / np.linalg.norm(d), pos)
+    beta /= np.linalg.norm(beta, axis=1)[:, None]
+    th, phi = hp.vec2ang(pos)
+    A = np.stack([1 + 0.05 * np.sin(3 * th), 0.05 * np.cos(2 * phi),
+                  0.03 * np.sin(phi + th), 1 - 0.04 * np.cos(th)]).astype(np.float32)
+    Ap = np.stack([1 + 0.02 * np.cos(th), 0.01 * np.sin(phi),
+                   -0.02 * np.sin(2 * th), 1 + 0.03 * np.sin(phi)]).astype(np.float32)
+    return dict(theta=th, phi=phi, beta=beta.T.copy(), A=A, A_prev=Ap)
+
+
+def test_galaxy_images_match_oracle(clm):
+    N = 64
+    chi = np.array([100.0, 200.0, 300.0, 400.0])   # three planes and the target
+    k = 2                                            # rays at chi_2, shell [250, 350)
+    st = synthetic_rays(N, seed=41, shift=0.3 * PIXEL(N))
+    plan = clm.Plan(N, nside_sht=16, lmax=32, nside_bundle=4, patch_cells=64, mg_vcycles=1)
+    rays = plan.new_rays()
+    for key in ("theta", "phi", "beta", "A", "A_prev"):
+        rays[key].copy_(torch.from_numpy(np.ascontiguousarray(st[key])))
+    rng = np.random.default_rng(42)
+    ng = 60
+    gth, gph = inputs.uniform_sphere(ng, seed=43)
+    # a few galaxies near the poles (the cap triangles)
+    gth[:4] = [0.004, 0.02, np.pi - 0.006, np.pi - 0.03]
+    gch = rng.uniform(250.0, 350.0, ng)
+    gch[-5:] = rng.uniform(100.0, 240.0, 5)          # other shells: untouched
+    gal = dict(theta=torch.from_numpy(gth).cuda(), phi=torch.from_numpy(gph).cuda(),
+               chi=torch.from_numpy(gch).cuda(),
+               A=torch.full((4, ng), 7.0, dtype=torch.float32, device="cuda"))
+    th_i, ph_i, found = plan.galaxy_images(chi, k, rays, gal)
+    plan.sync_status()
+    th_i, ph_i, found = th_i.cpu().numpy(), ph_i.cpu().numpy(), found.cpu().numpy()
+    Ag = gal["A"].cpu().numpy()
+    ref = im.galaxy_images(N, st, chi, k, gth, gph, gch, radius=3 * PIXEL(N))
+    worst_pos = worst_A = 0.0
+    for i in range(ng):
+        if ref[i] is None:
+            assert found[i] == 0 and np.all(Ag[:, i] == 7.0), i
+            continue
+        ok, t, p, A = ref[i]
+        assert ok and found[i] == 1, i
+        v, w = hp.vec(np.cos(t), p), hp.vec(np.cos(th_i[i]), ph_i[i])
+        e = np.arctan2(np.linalg.norm(np.cross(v, w)), v @ w)
+        worst_pos = max(worst_pos, e)
+        worst_A = max(worst_A, np.abs(Ag[:, i] - A.ravel()).max())
+    print("PARITY images position %.3e rad, Jacobian %.3e" % (worst_pos, worst_A), flush=True)
+    assert worst_pos < 1e-12
+    assert worst_A < 2e-6
+    plan.close()
+
+
+def test_images_end_to_end(clm):
+    """Zero convergence: every image is the galaxy itself and its Jacobian
+    the identity.  Weak lensing through three planes: every galaxy of each
+    shell has an image within a pixel of its source position."""
+    N, lmax = 64, 32
+    chi = np.array([100.0, 200.0, 300.0, 400.0])
+    plan = clm.Plan(N, nside_sht=16, lmax=lmax, nside_bundle=4, patch_cells=64, mg_vcycles=2,
+                    mg_prec="fp64")
+    ng = 3000
+    gth, gph = inputs.uniform_sphere(ng, seed=51)
+    gch = np.random.default_rng(52).uniform(60.0, 390.0, ng)
+    gal = dict(theta=torch.from_numpy(gth).cuda(), phi=torch.from_numpy(gph).cuda(),
+               chi=torch.from_numpy(gch).cuda(),
+               A=torch.zeros(4, ng, dtype=torch.float32, device="cuda"))
+    edges = np.concatenate([[0.0], 0.5 * (chi[:-1] + chi[1:])])
+    for lensing in (False, True):
+        rays = plan.new_rays()
+        for k in range(len(chi)):
+            if k >= 1:
+                # a Gaussian field scaled to an 8 arcmin rms deflection (half
+                # a pixel of the Nside 64 grid): weak lensing
+                s = inputs.deflection_scale(lmax, 0.2, alpha_rms=8 * inputs.ARCMIN)
+                g = inputs.gaussian_alm(lmax, seed=60 + k, sigma=0.2)
+                kap = torch.from_numpy((s if lensing else 0.0) * hp_synth(N, lmax, g)).cuda()
+                plan.poisson_solve(kap)
+                plan.ray_update(chi, k - 1, rays)
+            th_i, ph_i, found = plan.galaxy_images(chi, k, rays, gal)
+            sel = (gch >= edges[k]) & (gch < (edges[k + 1] if k + 1 < len(edges) else np.inf))
+            f = found.cpu().numpy()[sel]
+            assert f.size > 0 and np.all(f == 1), (lensing, k)
+            ti, pi = th_i.cpu().numpy()[sel], ph_i.cpu().numpy()[sel]
+            v = hp.vec(np.cos(ti), pi)
+            w = hp.vec(np.cos(gth[sel]), gph[sel])
+            sep = np.arctan2(np.linalg.norm(np.cross(v, w), axis=1), np.einsum("ij,ij->i", v, w))
+            A = gal["A"].cpu().numpy()[:, sel]
+            if not lensing:
+                assert sep.max() < 1e-12, k
+                assert np.abs(A - np.array([[1], [0], [0], [1]])).max() < 1e-6
+            else:
+                assert sep.max() < PIXEL(N), k
+        plan.sync_status()
+    plan.close()
+
+
+def hp_synth(N, lmax, alm):
+    from oracle import sht as osht
+    return osht.alm2map(N, lmax, alm)
