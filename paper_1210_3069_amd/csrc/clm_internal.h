@@ -28,6 +28,17 @@ constexpr int kLdsLevelMax = 64;
 // Interior side of the multigrid tiles streamed through LDS on larger levels.
 constexpr int kTile = 64;
 
+// Logical block index for grids whose neighbouring blocks share data: the
+// hardware deals blocks round-robin over the 8 XCDs (each with its own L2),
+// so block b is given logical index (b mod 8) (nb / 8) + b / 8 and each XCD
+// runs one contiguous range of logical blocks.  Identity when the grid is
+// not a multiple of 8.
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  if (nb % 8 != 0) return b;
+  return (b % 8) * (nb / 8) + b / 8;
+}
+
 struct LevelGeom {
   int n;         // cells per side
   size_t crow;   // offset of this level's row coefficients (4 doubles per row)

@@ -28,7 +28,9 @@ struct EvalArgs {
 
 template <typename T, typename TO>
 __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  // consecutive points (a NESTED range: one region of one patch) stay on
+  // one XCD, so the L2 of one XCD holds their cell window
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= a.npts) return;
   double vx, vy, vz;
   int64_t b;

@@ -31,14 +31,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr double kPi = 3.14159265358979323846;
 
-// Logical block index: consecutive logical blocks (tiles of one patch) are
-// kept on one XCD (hardware dispatches blocks round-robin over 8 XCDs).
-__device__ __forceinline__ int64_t xcd_block() {
-  const int64_t b = blockIdx.x, nb = gridDim.x;
-  if (nb % 8 != 0) return b;
-  return (b % 8) * (nb / 8) + b / 8;
-}
-
 // ------------------------------------------------------------ patch setup
 // u0 = interp(psi_SHT) at the cell centres; ghost u0 = 2 b - u0(adjacent)
 // with b = interp(psi_SHT) at the face midpoint (corner: patch corner);

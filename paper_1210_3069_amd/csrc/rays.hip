@@ -88,7 +88,8 @@ struct RayArgs {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ray_update(RayArgs a) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  // the rays of one bundle (a NESTED range) stay on one XCD
+  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int64_t n = a.n;
   double st, ct, sp, cp;
