@@ -82,6 +82,11 @@ struct Plan {
   int* r2n_f = nullptr;         // RING -> NESTED at nside_fine
   double* rot = nullptr;        // [nbundle][9] patch rotations R_b
   double* coef = nullptr;       // level row coefficients
+  // per level row, in the multigrid precision (8 values of T, rows as in
+  // coef): s_m, s_p, 1 / s_c, area, the face term of the diagonal, the
+  // reciprocal diagonals off and on a side face, and (even rows) the
+  // quad-pair restriction weight 1 / (2 (A_i + A_i+1))
+  void* rowt = nullptr;
   double* cinv = nullptr;       // [16*16] inverse of the coarsest operator
   double* rcoef = nullptr;      // [nalm][2] Legendre recurrence a_l, b_l (matrix-core SHT)
 

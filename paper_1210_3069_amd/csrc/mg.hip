@@ -556,6 +556,7 @@ struct TileArgs {
   int n, ntile, nu;
   int nu2;              // fused post + pre: the pre-smoothing sweeps
   const double* coef;   // this level's rows
+  const T* rowt;        // this level's row table (8 values per row)
   const T* u_in;        // level iterate in (nullptr: zero), or ubar (level >= 1 pre)
   const T* f_in;        // source (level 0: f'; level >= 1 post: A f), or rbar (level >= 1 pre)
   T* u_out;
@@ -623,12 +624,18 @@ __device__ __forceinline__ void store2(T* p, T a, T b) {
 }
 
 // LDS of a tile: u of cell (li, lj) at (lj & 1) * PAR + (li + 1) * S + (lj >> 1) + 1;
-// per region row the coefficients, the interior diagonal and its reciprocal.
+// per region row the coefficients, the term er that a patch face above or
+// below the row adds to the diagonal (ghost = -u: the missing neighbour's
+// coefficient), and the reciprocal diagonals of the row's cells away from
+// the side faces (rD) and on a side face (rD1, one more isc); per region
+// column cf = 1 on a side face of the patch, else 0.  Tile levels have at
+// least 128 cells per side, so no column lies on both side faces.
 template <typename T, int HH>
 struct QLds {
   using G = QT<T, HH>;
   T u[2 * G::PAR];
-  T sm[G::RR], sp[G::RR], isc[G::RR], A[G::RR], D[G::RR], rD[G::RR];
+  T sm[G::RR], sp[G::RR], isc[G::RR], A[G::RR], er[G::RR], rD[G::RR], rD1[G::RR];
+  T cf[G::RR];
   T rden[G::Q];   // 1 / (2 (A_2k + A_2k+1)): area weight of a quad row pair
 };
 
@@ -650,32 +657,36 @@ struct Quad {
   bool live, edge;  // edge: a cell of the quad lies on the patch boundary
 };
 
+// Row table of the region (rows i0 .. i0 + RR - 1 of the level's table,
+// defaults outside the patch), the side-face flags of its columns and the
+// zero guard ring of both parity arrays.
+template <typename T>
+struct alignas(8 * sizeof(T)) Row8 {
+  T v[8];
+};
+
 template <typename T, int HH>
-__device__ __forceinline__ void qload_rows(QLds<T, HH>& t, const double* coef, int n, int i0) {
+__device__ __forceinline__ void qload_rows(QLds<T, HH>& t, const T* rowt, int n, int i0, int j0) {
   using G = QT<T, HH>;
-  for (int r = threadIdx.x; r < G::RR; r += G::NT) {
-    const int gi = i0 + r;
-    T sm = T(0), sp = T(0), isc = T(0), A = T(1), D = T(1), rD = T(1);
-    if (gi >= 0 && gi < n) {
-      const double* c = coef + 4 * gi;
-      const double d = c[0] + c[1] + 2.0 / c[2];
-      sm = T(c[0]);
-      sp = T(c[1]);
-      isc = T(1.0 / c[2]);
-      A = T(c[3]);
-      D = T(d);
-      rD = T(1.0 / d);
-    }
-    t.sm[r] = sm; t.sp[r] = sp; t.isc[r] = isc; t.A[r] = A; t.D[r] = D; t.rD[r] = rD;
-  }
-  for (int k = threadIdx.x; k < G::Q; k += G::NT) {
-    const int gi = i0 + 2 * k;
-    double a0 = 1.0, a1 = 1.0;
-    if (gi >= 0 && gi + 1 < n) {
-      a0 = coef[4 * gi + 3];
-      a1 = coef[4 * gi + 7];
-    }
-    t.rden[k] = T(1.0 / (2.0 * (a0 + a1)));
+  static_assert(G::RR <= G::NT, "one region row per thread");
+  const Row8<T>* rows = reinterpret_cast<const Row8<T>*>(rowt);
+  const int r = threadIdx.x;
+  if (r < G::RR) {
+    // both loads first (the quad-pair weight of quad row r: row 2 r)
+    const int gi = i0 + r, gp = i0 + 2 * r;  // i0 is even
+    const bool rin = gi >= 0 && gi < n, pin = r < G::Q && gp >= 0 && gp + 1 < n;
+    const Row8<T> w = rows[min(max(gi, 0), n - 1)];
+    const T rd = rowt[8 * min(max(gp, 0), n - 2) + 7];
+    const int gj = j0 + r;
+    t.sm[r] = rin ? w.v[0] : T(0);
+    t.sp[r] = rin ? w.v[1] : T(0);
+    t.isc[r] = rin ? w.v[2] : T(0);
+    t.A[r] = rin ? w.v[3] : T(1);
+    t.er[r] = rin ? w.v[4] : T(0);
+    t.rD[r] = rin ? w.v[5] : T(1);
+    t.rD1[r] = rin ? w.v[6] : T(1);
+    t.cf[r] = (gj == 0 || gj == n - 1) ? T(1) : T(0);
+    if (r < G::Q) t.rden[r] = pin ? rd : T(0.25);
   }
   // the guard ring of both parity arrays is zero (every region cell is
   // written by its quad)
@@ -693,32 +704,18 @@ __device__ __forceinline__ void qload_rows(QLds<T, HH>& t, const double* coef, i
   }
 }
 
-// Diagonal of the in-patch cell (gi, gj): the interior one plus, across a
-// patch face, the coefficient of the missing neighbour (ghost = -u).
-template <typename T>
-__device__ __forceinline__ T cell_diag(T D, T sm, T sp, T isc, int gi, int gj, int n) {
-  if (gi == 0) D += sm;
-  if (gi == n - 1) D += sp;
-  if (gj == 0) D += isc;
-  if (gj == n - 1) D += isc;
-  return D;
-}
-
-// Set up the thread's row pair and quads: coefficients, A f, reciprocal
-// diagonals, u (in registers; written to LDS by qput after the zero fill is
-// visible).  u_in and f_in point at this patch's level array.
+// The thread's row pair and quads, and the global loads of their u and
+// (unscaled) source, issued before anything waits: every lane loads, from
+// an address clamped into the patch, and qfinish zeroes the cells outside
+// it.  u_in and f_in point at this patch's level array (u_in nullptr: zero).
 template <typename T, int HH>
-__device__ __forceinline__ void qinit(QLds<T, HH>& t, QRow<T>& rw, Quad<T> (&qd)[QT<T, HH>::IT],
-                                      const T* u_in, const T* f_in, bool f_scaled, int n,
-                                      int i0, int j0) {
+__device__ __forceinline__ void qissue(QRow<T>& rw, Quad<T> (&qd)[QT<T, HH>::IT],
+                                       const T* u_in, const T* f_in, int n, int i0, int j0) {
   using G = QT<T, HH>;
   const int qi = threadIdx.x / G::TPR, tr = threadIdx.x - qi * G::TPR;
   rw.live = qi < G::Q;
   rw.qi = rw.live ? qi : 0;
-  const int li = 2 * rw.qi;
-  rw.sm0 = t.sm[li]; rw.sp0 = t.sp[li]; rw.is0 = t.isc[li];
-  rw.sm1 = t.sm[li + 1]; rw.sp1 = t.sp[li + 1]; rw.is1 = t.isc[li + 1];
-  const int gi0 = i0 + li;
+  const int gi0 = i0 + 2 * rw.qi;
 #pragma unroll
   for (int it = 0; it < G::IT; ++it) {
     Quad<T>& Qd = qd[it];
@@ -728,34 +725,50 @@ __device__ __forceinline__ void qinit(QLds<T, HH>& t, QRow<T>& rw, Quad<T> (&qd)
     Qd.b = 2 * rw.qi * G::S + Qd.qj + 1;
     const int gj = j0 + 2 * Qd.qj;
     Qd.edge = gi0 == 0 || gi0 + 1 == n - 1 || gj == 0 || gj + 1 == n - 1;
+    const int cj = min(max(gj, 0), n - 2);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int ci = min(max(gi0 + a, 0), n - 1);
+      const int g = ci * n + cj;
+      if (u_in)
+        load2(u_in + g, Qd.u[2 * a], Qd.u[2 * a + 1]);
+      else
+        Qd.u[2 * a] = Qd.u[2 * a + 1] = T(0);
+      load2(f_in + g, Qd.ft[2 * a], Qd.ft[2 * a + 1]);
+    }
+  }
+}
+
+// After the row table is visible: the row pair's coefficients, A f (unless
+// f_in held it), the reciprocal diagonals, and zero u, A f and 1 / D on the
+// cells outside the patch (u is written to LDS by qput).
+template <typename T, int HH>
+__device__ __forceinline__ void qfinish(const QLds<T, HH>& t, QRow<T>& rw,
+                                        Quad<T> (&qd)[QT<T, HH>::IT], bool f_scaled, int n,
+                                        int i0, int j0) {
+  using G = QT<T, HH>;
+  const int li = 2 * rw.qi;
+  rw.sm0 = t.sm[li]; rw.sp0 = t.sp[li]; rw.is0 = t.isc[li];
+  rw.sm1 = t.sm[li + 1]; rw.sp1 = t.sp[li + 1]; rw.is1 = t.isc[li + 1];
+  const int gi0 = i0 + li;
+#pragma unroll
+  for (int it = 0; it < G::IT; ++it) {
+    Quad<T>& Qd = qd[it];
+    const int gj = j0 + 2 * Qd.qj;
+    const bool cin = Qd.live && gj >= 0 && gj < n;
+    const bool side0 = t.cf[2 * Qd.qj] != T(0), side1 = t.cf[2 * Qd.qj + 1] != T(0);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int gi = gi0 + a;
-      const bool in = Qd.live && gi >= 0 && gi < n && gj >= 0 && gj < n;
-      T u0 = T(0), u1 = T(0), f0 = T(0), f1 = T(0), r0 = T(0), r1 = T(0);
-      if (in) {
-        const int g = gi * n + gj;
-        if (u_in) load2(u_in + g, u0, u1);
-        load2(f_in + g, f0, f1);
-        if (!f_scaled) {
-          const T A = t.A[li + a];
-          f0 *= A;
-          f1 *= A;
-        }
-        r0 = r1 = t.rD[li + a];
-        if (Qd.edge) {
-          const T D = t.D[li + a];
-          const T sm = a ? rw.sm1 : rw.sm0, sp = a ? rw.sp1 : rw.sp0;
-          const T isc = a ? rw.is1 : rw.is0;
-          const T d0 = cell_diag(D, sm, sp, isc, gi, gj, n);
-          const T d1 = cell_diag(D, sm, sp, isc, gi, gj + 1, n);
-          if (d0 != D) r0 = T(1) / d0;
-          if (d1 != D) r1 = T(1) / d1;
-        }
-      }
-      Qd.u[2 * a] = u0; Qd.u[2 * a + 1] = u1;
-      Qd.ft[2 * a] = f0; Qd.ft[2 * a + 1] = f1;
-      Qd.rD[2 * a] = r0; Qd.rD[2 * a + 1] = r1;
+      const bool in = cin && gi >= 0 && gi < n;
+      const T A = f_scaled ? T(1) : t.A[li + a];
+      const T rd = t.rD[li + a], rd1 = t.rD1[li + a];
+      Qd.u[2 * a] = in ? Qd.u[2 * a] : T(0);
+      Qd.u[2 * a + 1] = in ? Qd.u[2 * a + 1] : T(0);
+      Qd.ft[2 * a] = in ? Qd.ft[2 * a] * A : T(0);
+      Qd.ft[2 * a + 1] = in ? Qd.ft[2 * a + 1] * A : T(0);
+      Qd.rD[2 * a] = in ? (side0 ? rd1 : rd) : T(0);
+      Qd.rD[2 * a + 1] = in ? (side1 ? rd1 : rd) : T(0);
     }
   }
 }
@@ -813,30 +826,26 @@ __device__ __forceinline__ void qsweep(QLds<T, HH>& t, const QRow<T>& rw,
 // enters twice.
 template <typename T, int HH>
 __device__ __forceinline__ void qalap(const QLds<T, HH>& t, const QRow<T>& rw, const Quad<T>& Qd,
-                                      int gi, int gj, int n, T AL[4]) {
+                                      T AL[4]) {
   using G = QT<T, HH>;
   constexpr int S = G::S, P = G::PAR;
   const T* ub = t.u + Qd.b;
   const T* u = Qd.u;
+  const T er0 = t.er[2 * rw.qi], er1 = t.er[2 * rw.qi + 1];
+  const T cf0 = t.cf[2 * Qd.qj], cf1 = t.cf[2 * Qd.qj + 1];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const T nb0 = c == 0 ? ub[0] : c == 1 ? ub[P] : c == 2 ? u[0] : u[1];
     const T nb1 = c == 0 ? u[2] : c == 1 ? u[3] : c == 2 ? ub[3 * S] : ub[P + 3 * S];
     const T nb2 = c == 0 ? ub[P + S - 1] : c == 1 ? u[0] : c == 2 ? ub[P + 2 * S - 1] : u[2];
     const T nb3 = c == 0 ? u[1] : c == 1 ? ub[S + 1] : c == 2 ? u[3] : ub[2 * S + 1];
-    const T nb[1][4] = {{nb0, nb1, nb2, nb3}};
     const int aa = c >> 1, bb = c & 1;
     const T sm = aa ? rw.sm1 : rw.sm0, sp = aa ? rw.sp1 : rw.sp0, isc = aa ? rw.is1 : rw.is0;
     const T x = u[c];
-    const int ci = gi + aa, cj = gj + bb;
-    T v = sm * (nb[0][0] - x) + sp * (nb[0][1] - x) + isc * ((nb[0][2] - x) + (nb[0][3] - x));
-    if (Qd.edge) {
-      if (ci == 0) v -= sm * x;
-      if (ci == n - 1) v -= sp * x;
-      if (cj == 0) v -= isc * x;
-      if (cj == n - 1) v -= isc * x;
-    }
-    AL[c] = v;
+    const T v = sm * (nb0 - x) + sp * (nb1 - x) + isc * ((nb2 - x) + (nb3 - x));
+    // the face terms: er of the row, isc on a side-face column
+    const T e = (aa ? er1 : er0) + isc * (bb ? cf1 : cf0);
+    AL[c] = v - e * x;
   }
 }
 
@@ -878,7 +887,7 @@ __device__ __forceinline__ void pre_epilogue(const TileArgs<T>& a, const QLds<T,
     // in float32 the cells the last half sweep updated carry the rounding
     // of that update, which the coarse correction must see)
     T AL[4];
-    qalap<T, HH>(t, rw, Qd, gi, gj, n, AL);
+    qalap<T, HH>(t, rw, Qd, AL);
     const T ar = ((Qd.ft[0] - AL[0]) + (Qd.ft[1] - AL[1])) + ((Qd.ft[2] - AL[2]) + (Qd.ft[3] - AL[3]));
     const int gc = (gi / 2) * nc + gj / 2;
     ubo[gc] = (a0 * (Qd.u[0] + Qd.u[1]) + a1 * (Qd.u[2] + Qd.u[3])) * rden;
@@ -889,21 +898,42 @@ __device__ __forceinline__ void pre_epilogue(const TileArgs<T>& a, const QLds<T,
 // Coarse correction e = u_H - ubar on the coarse cells covering the region
 // (+- 1 cell), then added to the owned quads: bilinear (9, 3, 3, 1)/16 of
 // the parent and its neighbours toward the child, direct injection of the
-// parent on the outermost fine ring.
+// parent on the outermost fine ring.  corr_issue loads the thread's items
+// (clamped into the patch) without waiting; corr_store writes them to LDS,
+// zero outside the patch.
 template <typename T, int HH>
-__device__ __forceinline__ void load_correction(const TileArgs<T>& a, T* e, size_t cbase, int i0,
-                                                int j0) {
-  using G = QT<T, HH>;
-  constexpr int CR = G::Q + 2;
+struct CorrIn {
+  static constexpr int CR = QT<T, HH>::Q + 2;
+  static constexpr int NE = (CR * CR + QT<T, HH>::NT - 1) / QT<T, HH>::NT;
+  T uc[NE], ub[NE];
+};
+
+template <typename T, int HH>
+__device__ __forceinline__ void corr_issue(const TileArgs<T>& a, CorrIn<T, HH>& c, size_t cbase,
+                                           int i0, int j0) {
+  using C = CorrIn<T, HH>;
   const int nc = a.n / 2, ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // i0, j0 even
-  for (int item = threadIdx.x; item < CR * CR; item += G::NT) {
-    const int I = ci0 + item / CR, J = cj0 + item % CR;
-    T v = T(0);
-    if (I >= 0 && I < nc && J >= 0 && J < nc) {
-      const size_t g = cbase + size_t(I) * nc + J;
-      v = a.uc[g] - a.ubarc[g];
-    }
-    e[item] = v;
+#pragma unroll
+  for (int k = 0; k < C::NE; ++k) {
+    const int item = min(int(threadIdx.x) + k * QT<T, HH>::NT, C::CR * C::CR - 1);
+    const int I = min(max(ci0 + item / C::CR, 0), nc - 1);
+    const int J = min(max(cj0 + item % C::CR, 0), nc - 1);
+    const size_t g = cbase + size_t(I) * nc + J;
+    c.uc[k] = a.uc[g];
+    c.ub[k] = a.ubarc[g];
+  }
+}
+
+template <typename T, int HH>
+__device__ __forceinline__ void corr_store(T* e, const CorrIn<T, HH>& c, int n, int i0, int j0) {
+  using C = CorrIn<T, HH>;
+  const int nc = n / 2, ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;
+#pragma unroll
+  for (int k = 0; k < C::NE; ++k) {
+    const int item = int(threadIdx.x) + k * QT<T, HH>::NT;
+    if (item >= C::CR * C::CR) break;
+    const int I = ci0 + item / C::CR, J = cj0 + item % C::CR;
+    e[item] = (I >= 0 && I < nc && J >= 0 && J < nc) ? c.uc[k] - c.ub[k] : T(0);
   }
 }
 
@@ -955,9 +985,10 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_pre(TileArgs<T> a) {
   const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
   const int n = a.n, nc = n / 2;
   const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
-  qload_rows(t, a.coef, n, i0);
+  qissue<T, HH>(rw, qd, a.u_in ? a.u_in + pbase : nullptr, a.f_in + pbase, n, i0, j0);
+  qload_rows(t, a.rowt, n, i0, j0);
   __syncthreads();
-  qinit<T, HH>(t, rw, qd, a.u_in ? a.u_in + pbase : nullptr, a.f_in + pbase, false, n, i0, j0);
+  qfinish<T, HH>(t, rw, qd, false, n, i0, j0);
   qput<T, HH>(t, qd);
   __syncthreads();
   if (a.fas_source) {
@@ -967,7 +998,7 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_pre(TileArgs<T> a) {
       Quad<T>& Qd = qd[it];
       if (!Qd.live) continue;
       T AL[4];
-      qalap<T, HH>(t, rw, Qd, i0 + 2 * rw.qi, j0 + 2 * Qd.qj, n, AL);
+      qalap<T, HH>(t, rw, Qd, AL);
 #pragma unroll
       for (int c = 0; c < 4; ++c) Qd.ft[c] = Qd.rD[c] != T(0) ? Qd.ft[c] + AL[c] : T(0);
     }
@@ -998,10 +1029,13 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_post(TileArgs<T> a) {
   const int n = a.n, nc = n / 2;
   const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
   if (a.done && a.done[patch]) return;
-  qload_rows(t, a.coef, n, i0);
-  load_correction<T, HH>(a, e, cbase, i0, j0);
+  CorrIn<T, HH> ci;
+  qissue<T, HH>(rw, qd, a.u_in + pbase, a.f_in + pbase, n, i0, j0);
+  corr_issue<T, HH>(a, ci, cbase, i0, j0);
+  qload_rows(t, a.rowt, n, i0, j0);
+  corr_store<T, HH>(e, ci, n, i0, j0);
   __syncthreads();
-  qinit<T, HH>(t, rw, qd, a.u_in + pbase, a.f_in + pbase, a.f_scaled != 0, n, i0, j0);
+  qfinish<T, HH>(t, rw, qd, a.f_scaled != 0, n, i0, j0);
   apply_correction<T, HH>(e, rw, qd, i0, j0, n);
   qput<T, HH>(t, qd);
   __syncthreads();
@@ -1043,10 +1077,13 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_postpre(TileArgs<T> a) 
   const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
   const int n = a.n, nc = n / 2;
   const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
-  qload_rows(t, a.coef, n, i0);
-  load_correction<T, HH>(a, e, cbase, i0, j0);
+  CorrIn<T, HH> ci;
+  qissue<T, HH>(rw, qd, a.u_in + pbase, a.f_in + pbase, n, i0, j0);
+  corr_issue<T, HH>(a, ci, cbase, i0, j0);
+  qload_rows(t, a.rowt, n, i0, j0);
+  corr_store<T, HH>(e, ci, n, i0, j0);
   __syncthreads();
-  qinit<T, HH>(t, rw, qd, a.u_in + pbase, a.f_in + pbase, false, n, i0, j0);
+  qfinish<T, HH>(t, rw, qd, false, n, i0, j0);
   apply_correction<T, HH>(e, rw, qd, i0, j0, n);
   qput<T, HH>(t, qd);
   __syncthreads();
@@ -1618,6 +1655,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     a.ntile = a.n / kTile;
     a.nu = pre ? d.nu_pre : d.nu_post;
     a.coef = p->coef + p->lev[l].crow;
+    a.rowt = static_cast<const T*>(p->rowt) + 2 * p->lev[l].crow;
     a.done = done;
     return a;
   };

@@ -33,7 +33,7 @@ Plan::~Plan() {
   auto f = [](void* q) { if (q) (void)hipFree(q); };
   f(ring_s); f(ringi_s); f(ringx_s); f(ring_f); f(ringi_f); f(ringx_f); f(lam_mant);
   f(lam_scale); f(blu_off); f(blu);
-  f(r2n_s); f(r2n_f); f(rot); f(coef); f(cinv); f(kap_s); f(F); f(G); f(red);
+  f(r2n_s); f(r2n_f); f(rot); f(coef); f(rowt); f(cinv); f(kap_s); f(F); f(G); f(red);
   f(rcoef); f(Fb); f(Gb); f(apart); f(psib); f(mfma_ctr);
   f(deriv); f(fprime); f(dutmp); f(status_dev); f(iter_map); f(iter_alm);
   for (auto* q : ubar) f(q);
@@ -270,6 +270,37 @@ clm_status build_tables(Plan* p) {
   }
   CLM_TRY(alloc(p, &p->coef, cf.size()));
   CLM_HIP(hipMemcpy(p->coef, cf.data(), cf.size() * 8, hipMemcpyHostToDevice));
+
+  // the tile kernels' row table (same row order as cf, 8 values per row):
+  // a patch face above or below the row adds its missing neighbour's
+  // coefficient to the diagonal (ghost = -u); a side face adds 1 / s_c
+  {
+    std::vector<double> rt(2 * cf.size(), 0.0);
+    for (const LevelGeom& lg : p->lev)
+      for (int i = 0; i < lg.n; ++i) {
+        const double* c = cf.data() + lg.crow + 4 * i;
+        double* r = rt.data() + 2 * (lg.crow + 4 * i);
+        const double ic = 1.0 / c[2];
+        const double e = (i == 0 ? c[0] : 0.0) + (i == lg.n - 1 ? c[1] : 0.0);
+        const double dg = c[0] + c[1] + 2.0 * ic + e;
+        r[0] = c[0]; r[1] = c[1]; r[2] = ic; r[3] = c[3]; r[4] = e;
+        r[5] = 1.0 / dg;
+        r[6] = 1.0 / (dg + ic);
+        r[7] = (i % 2 == 0 && i + 1 < lg.n) ? 1.0 / (2.0 * (c[3] + c[7])) : 0.25;
+      }
+    if (p->fp64mg) {
+      double* q = nullptr;
+      CLM_TRY(alloc(p, &q, rt.size()));
+      p->rowt = q;
+      CLM_HIP(hipMemcpy(q, rt.data(), rt.size() * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> r32(rt.begin(), rt.end());
+      float* q = nullptr;
+      CLM_TRY(alloc(p, &q, r32.size()));
+      p->rowt = q;
+      CLM_HIP(hipMemcpy(q, r32.data(), r32.size() * 4, hipMemcpyHostToDevice));
+    }
+  }
 
   // coarsest level (4 x 4): dense operator with zero face values, inverted
   {
