@@ -462,21 +462,41 @@ def c3_run(clm, torch, inputs, cosmo, gal):
     plan.sync_status()
     npix = plan.npix_fine
     A = gal["A"].double()
+    # a second pass over all planes with every launch timed: the stage
+    # breakdown, and after each plane the grid search for the images of the
+    # galaxies of the shell the rays have just reached (Sec. 3.3)
     rays2 = plan.new_rays()
+    ng = gal["theta"].numel()
+    gimg = dict(theta=gal["theta"], phi=gal["phi"], chi=gal["chi"], A=torch.zeros_like(gal["A"]))
+    found = torch.zeros(ng, dtype=torch.int32, device="cuda")
     plan.set_timing(True)
     plan.get_timing()
-    for m in range(3):
+    found += plan.galaxy_images(chi, 0, rays2, gimg)[2]
+    for m in range(nplanes):
         plan.raytrace_planes(kap[m], chi, m, rays2)
-    stages = {k: (v[0] / 3.0, v[1] / 3.0) for k, v in plan.get_timing().items()}
+        found += plan.galaxy_images(chi, m + 1, rays2, gimg)[2]
+    tm = plan.get_timing()
+    stages = {k: (v[0] / nplanes, v[1] / nplanes) for k, v in tm.items() if k != "galaxy_images"}
+    img_ms = tm.get("galaxy_images", (0.0, 0))[0]
     plan.set_timing(False)
     plan.sync_status()
-    del rays2
+    # the Jacobian at the found image against the reduced step's (taken at
+    # the galaxy's own position): they differ by the image-source offset
+    Ai = gimg["A"].double()
+    ok = found > 0
+    dA = (Ai[:, ok] - A[:, ok]).abs().amax(0)
+    images = dict(galaxies=ng, found=int(ok.sum()), ms_all_shells=img_ms,
+                  galaxies_per_s=ng / max(img_ms * 1e-3, 1e-12),
+                  jacobian_vs_reduced=dict(median=float(dA.median()) if dA.numel() else None,
+                                           max=float(dA.max()) if dA.numel() else None))
+    del rays2, gimg
     out = dict(
         planes=nplanes, nside_sht=ns3, lmax=l3, ms_all_planes=ms, ms_per_plane=ms / nplanes,
         ray_plane_updates_per_s=dict(end_to_end=npix * nplanes / (ms * 1e-3),
                                      kernel_only=npix / (ru[0] / ru[1] * 1e-3)),
         stage_ms_per_plane={k: v[0] for k, v in stages.items()},
-        stage_note="per plane, from a separate 3-plane pass with every launch timed",
+        stage_note="per plane, from a second pass with every launch timed",
+        galaxy_images=images,
         galaxies=int(gal["theta"].numel()),
         galaxies_with_A=int((A.abs().sum(0) > 0).sum()),
         galaxy_A_finite=bool(torch.isfinite(A).all()))
