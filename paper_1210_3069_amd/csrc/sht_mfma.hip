@@ -104,10 +104,58 @@ __device__ __forceinline__ float rec_value(Rec& r, int m, int dl, double a, doub
   return r.s == 0 ? float(r.p1) : 0.0f;
 }
 
+// One step of the recurrence: the kStep values of l from dl0 of this lane's
+// ring, as float (0 while the scale exponent is negative or beyond l_max),
+// into rows 0 .. kStep - 1 of the wave's tile (row stride STRIDE floats).
+// The step's coefficients arrive as one vector (lane t holding element
+// 2 dl0 + t: a_l, b_l interleaved); the wave stages them in its LDS slot cs
+// and every lane then reads each (a_l, b_l) pair from one address.  The
+// scaled recurrence is rescaled once per step instead of at each value:
+// over 32 consecutive values it grows by less than 2^(16 log2(2m) - 58)
+// (the largest factors are the first ones, l near m, near a pole), so from
+// below 2^400 it stays far below the FP64 range for any m below 2^37, and
+// the rescale is by a power of two, so every value, and every float
+// written, equals that of a rescale at the threshold value.
+template <int STRIDE>
+__device__ __forceinline__ void rec_step(Rec& r, int m, int dl0, int nl, double rcv, double* cs,
+                                         float* tw, int lane) {
+  cs[lane] = rcv;
+  __builtin_amdgcn_wave_barrier();
+  const double2* ab = reinterpret_cast<const double2*>(cs);
+  if (dl0 == 0) {
+#pragma unroll
+    for (int d = 0; d < kStep; ++d) {
+      if (d == 1) {
+        r.p2 = r.p1;
+        r.p1 = sqrt(2.0 * m + 3.0) * r.z * r.p2;
+      } else if (d >= 2) {
+        const double2 c = ab[d];
+        const double p0 = c.x * (r.z * r.p1 - c.y * r.p2);
+        r.p2 = r.p1;
+        r.p1 = p0;
+      }
+      tw[d * STRIDE + lane] = (d < nl && r.s == 0) ? float(r.p1) : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < kStep; ++d) {
+      const double2 c = ab[d];
+      const double p0 = c.x * (r.z * r.p1 - c.y * r.p2);
+      r.p2 = r.p1;
+      r.p1 = p0;
+      tw[d * STRIDE + lane] = (dl0 + d < nl && r.s == 0) ? float(r.p1) : 0.0f;
+    }
+  }
+  if (r.s < 0 && fabs(r.p1) > kHugeB) {
+    r.p1 *= kSmallB;
+    r.p2 *= kSmallB;
+    r.s += 1;
+  }
+}
+
 // The recurrence coefficients of a step of kStep values of l are read with
 // one vector load a step ahead, lane t holding rc[2 dl0 + t] (a_l, b_l
-// interleaved); each value is then taken from its lane as a wave-uniform
-// scalar, so the recurrence never waits on memory.
+// interleaved), so the recurrence never waits on memory.
 __device__ __forceinline__ double rc_fetch(const double* rc, int dl0, int nl, int lane) {
   const int t = 2 * dl0 + lane;
   return t < 2 * nl ? rc[t] : 0.0;
@@ -187,7 +235,8 @@ __device__ __forceinline__ Rec rec_start(const MfmaArgs& a, int m, int q) {
 // workgroups fit per CU, so one's recurrence runs beside the other's matrix
 // products.
 template <int FORM, int NW>
-__device__ __forceinline__ void analysis_item(const MfmaArgs& a, int m, int rb, float* tiles) {
+__device__ __forceinline__ void analysis_item(const MfmaArgs& a, int m, int rb, float* tiles,
+                                              double* coefs) {
   constexpr int SA = AnaStride<FORM>::S;
   constexpr int NS = Split<FORM>::NS;
   constexpr int KB = FORM == kFP32 ? 16 : 2;   // k-blocks over the 64 rings
@@ -196,6 +245,7 @@ __device__ __forceinline__ void analysis_item(const MfmaArgs& a, int m, int rb, 
   const int nl = a.lmax - m + 1;
   const int qb = (rb * a.nwv + w) * 64;  // first ring of this wave
   float* tw = tiles + w * kStep * SA;
+  double* cs = coefs + w * 2 * kStep;
   const double* rc = a.rc + 2 * alm_base(m, a.lmax);
   Rec r = rec_start(a, m, qb + l);
 
@@ -233,12 +283,7 @@ __device__ __forceinline__ void analysis_item(const MfmaArgs& a, int m, int rb, 
   for (int dl0 = 0; dl0 < nl; dl0 += kStep) {
     const double rcn = rc_fetch(rc, dl0 + kStep, nl, l);  // next step's, in flight
     // lambda for dl0 .. dl0 + 31 of this lane's ring into the wave's tile
-#pragma unroll
-    for (int d = 0; d < kStep; ++d) {
-      const int dl = dl0 + d;
-      tw[d * SA + l] =
-          dl < nl ? rec_value(r, m, dl, lane_value(rcv, 2 * d), lane_value(rcv, 2 * d + 1)) : 0.0f;
-    }
+    rec_step<SA>(r, m, dl0, nl, rcv, cs, tw, l);
     rcv = rcn;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tile is written
@@ -320,11 +365,13 @@ __device__ __forceinline__ void load_groups(const MfmaMulti& mm, MfmaArgs* ga) {
 template <int FORM, int NW>
 __global__ __launch_bounds__(64 * NW, 32 / NW) void k_analysis_mfma(MfmaMulti mm) {
   __shared__ float tiles[NW * kStep * AnaStride<FORM>::S];
+  __shared__ __align__(16) double coefs[NW * 2 * kStep];
   __shared__ MfmaArgs ga[kMaxGroups];
   __shared__ int slot;
   load_groups(mm, ga);
   int g, m, rb;
-  while (next_item(mm, &slot, g, m, rb) >= 0) analysis_item<FORM, NW>(ga[g], m, rb, tiles);
+  while (next_item(mm, &slot, g, m, rb) >= 0)
+    analysis_item<FORM, NW>(ga[g], m, rb, tiles, coefs);
 }
 
 // Sum of the ring-block partials, weighted, into the planes' alm.
@@ -352,13 +399,15 @@ __global__ void k_pack_psi(MfmaArgs a, float* psi) {
 // One item: order m, block of 64 NW rings; each wave owns 64 rings and sums
 // over all l, even and odd l - m apart.
 template <int FORM, int NW>
-__device__ __forceinline__ void synthesis_item(const MfmaArgs& a, int m, int rb, float* tiles) {
+__device__ __forceinline__ void synthesis_item(const MfmaArgs& a, int m, int rb, float* tiles,
+                                               double* coefs) {
   constexpr int SS = kSynStride;
   constexpr int NS = Split<FORM>::NS;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int nl = a.lmax - m + 1;
   const int qb = (rb * a.nwv + w) * 64;
   float* tw = tiles + w * kStep * SS;
+  double* cs = coefs + w * 2 * kStep;
   const double* rc = a.rc + 2 * alm_base(m, a.lmax);
   const float* pm = a.psi + alm_base(m, a.lmax) * kCols;
   Rec r = rec_start(a, m, qb + l);
@@ -408,12 +457,7 @@ __device__ __forceinline__ void synthesis_item(const MfmaArgs& a, int m, int rb,
   for (int dl0 = 0; dl0 < nl; dl0 += kStep) {
     const double rcn = rc_fetch(rc, dl0 + kStep, nl, l);  // next step's, in flight
     psi_fetch(dl0, pv);
-#pragma unroll
-    for (int d = 0; d < kStep; ++d) {
-      const int dl = dl0 + d;
-      tw[d * SS + l] =
-          dl < nl ? rec_value(r, m, dl, lane_value(rcv, 2 * d), lane_value(rcv, 2 * d + 1)) : 0.0f;
-    }
+    rec_step<SS>(r, m, dl0, nl, rcv, cs, tw, l);
     rcv = rcn;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);
@@ -488,11 +532,13 @@ __device__ __forceinline__ void synthesis_item(const MfmaArgs& a, int m, int rb,
 template <int FORM, int NW>
 __global__ __launch_bounds__(64 * NW) void k_synthesis_mfma(MfmaMulti mm) {
   __shared__ float tiles[NW * kStep * kSynStride];
+  __shared__ __align__(16) double coefs[NW * 2 * kStep];
   __shared__ MfmaArgs ga[kMaxGroups];
   __shared__ int slot;
   load_groups(mm, ga);
   int g, m, rb;
-  while (next_item(mm, &slot, g, m, rb) >= 0) synthesis_item<FORM, NW>(ga[g], m, rb, tiles);
+  while (next_item(mm, &slot, g, m, rb) >= 0)
+    synthesis_item<FORM, NW>(ga[g], m, rb, tiles, coefs);
 }
 
 // Recurrence coefficients per (l, m) in alm order:
