@@ -84,28 +84,10 @@ struct Rec {
   int s;
 };
 
-// lambda_lm at dl = l - m as float (0 below range), advancing the state for
-// dl >= 1: lambda_{m+1,m} = sqrt(2m+3) z lambda_mm, then
-// lambda_l = a_l (z lambda_{l-1} - b_l lambda_{l-2}) with (a, b) = (a_l, b_l).
-__device__ __forceinline__ float rec_value(Rec& r, int m, int dl, double a, double b) {
-  if (dl == 1) {
-    r.p2 = r.p1;
-    r.p1 = sqrt(2.0 * m + 3.0) * r.z * r.p2;
-  } else if (dl >= 2) {
-    const double p0 = a * (r.z * r.p1 - b * r.p2);
-    r.p2 = r.p1;
-    r.p1 = p0;
-    if (r.s < 0 && fabs(p0) > kHugeB) {
-      r.p1 *= kSmallB;
-      r.p2 *= kSmallB;
-      r.s += 1;
-    }
-  }
-  return r.s == 0 ? float(r.p1) : 0.0f;
-}
-
-// One step of the recurrence: the kStep values of l from dl0 of this lane's
-// ring, as float (0 while the scale exponent is negative or beyond l_max),
+// One step of the recurrence (lambda_{m+1,m} = sqrt(2m+3) z lambda_mm, then
+// lambda_l = a_l (z lambda_{l-1} - b_l lambda_{l-2})): the kStep values of l
+// from dl0 of this lane's ring, as float (0 while the scale exponent is
+// negative or beyond l_max),
 // into rows 0 .. kStep - 1 of the wave's tile (row stride STRIDE floats).
 // The step's coefficients arrive as one vector (lane t holding element
 // 2 dl0 + t: a_l, b_l interleaved); the wave stages them in its LDS slot cs
@@ -161,12 +143,6 @@ __device__ __forceinline__ double rc_fetch(const double* rc, int dl0, int nl, in
   return t < 2 * nl ? rc[t] : 0.0;
 }
 
-__device__ __forceinline__ double lane_value(double v, int lane) {
-  const long long bits = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane(int(bits), lane);
-  const unsigned hi = __builtin_amdgcn_readlane(int(bits >> 32), lane);
-  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
-}
 
 struct MfmaArgs {
   const double* F;         // analysis in: [P][nring][lmax+1] complex
