@@ -492,7 +492,9 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
   const int i0 = st.i0, j0 = st.j0;
   const double* R = a.rot + 9 * patch;
   const double th0 = kPi / 2 - a.L / 2, ph0 = -a.L / 2;
-  const SetupMeta& m = a.meta[lb];
+  // a copy in registers: a reference to global memory would be reloaded
+  // after every global store of the cell loop (it may alias them)
+  const SetupMeta m = a.meta[lb];
   const PhiRef pr{m.phi, m.c, m.s};
   for (int r = threadIdx.x; r < RR; r += blockDim.x) {
     double s_t, c_t, s_p, c_p;
