@@ -723,7 +723,17 @@ __device__ __forceinline__ void recur_step(Recur& r, double z, double a, double 
   const double p0 = a * (z * r.p1 - b * r.p2);
   r.p2 = r.p1;
   r.p1 = p0;
-  if (r.s < 0 && fabs(p0) > kHuge) {
+}
+
+// The rescale of the scaled recurrence, applied after every kRecGroup
+// values of l instead of after each: across a group the values grow by less
+// than 2^(4 log2(2m)) (the largest factors, l near m near a pole), so from
+// below 2^400 they stay far inside the FP64 range.  A value that the
+// rescale at the threshold would already have counted (true size below
+// 2^-350) then enters as 0 until the group ends.
+constexpr int kRecGroup = 8;
+__device__ __forceinline__ void recur_rescale(Recur& r) {
+  if (r.s < 0 && fabs(r.p1) > kHuge) {
     r.p1 *= kSmall;
     r.p2 *= kSmall;
     r.s += 1;
@@ -801,6 +811,9 @@ __global__ __launch_bounds__(leg_threads_max(RPT)) void k_analysis(const double*
         acc[2 * cc] = sr;
         acc[2 * cc + 1] = si;
       }
+      static_assert(kRecGroup == 8, "one rescale per group of eight l");
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) recur_rescale(st[k]);
       const double tot = wave_sum16(acc);
       const int idx = lane >> 2;  // 2 cc + (0: real, 1: imaginary)
       const int c = c0 + (idx >> 1);
@@ -869,6 +882,7 @@ __global__ __launch_bounds__(1024) void k_synthesis(const double* alm, const dou
   double wer = 0, wei = 0, wor = 0, woi = 0;  // d2lambda sums
   const double M = m;
   for (int dl = 0; dl < nl; ++dl) {
+    if (dl % kRecGroup == 0) recur_rescale(r);
     const double lm1 = r.s == 0 ? r.p1 : 0.0;  // lambda_{l-1} (valid for dl >= 1)
     if (dl == 1) {
       r.p2 = r.p1;
