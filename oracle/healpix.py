@@ -152,6 +152,14 @@ def ring2nest(nside, p):
     return inv[np.asarray(p, dtype=np.int64)]
 
 
+def ring2nest_pix(nside, p):
+    """NESTED index of the RING pixels p, without the full permutation: the
+    NESTED pixel that holds each RING pixel's centre (a centre lies half a
+    pixel inside its own pixel)."""
+    z, phi, _ = pix2ang_ring(nside, np.asarray(p, dtype=np.int64))
+    return ang2pix_nest(nside, z, phi)
+
+
 def pix2ang_nest(nside, p):
     return pix2ang_ring(nside, nest2ring(nside, p))
 

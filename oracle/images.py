@@ -191,7 +191,9 @@ def galaxy_images(nside, rays, chi, k, gal_theta, gal_phi, gal_chi, radius, K=0.
     chi = np.asarray(chi, dtype=np.float64)
     edges = np.concatenate([[0.0], 0.5 * (chi[:-1] + chi[1:])])
     hi = edges[k + 1] if k + 1 < len(edges) else np.inf
-    r2n = hp.ring2nest(nside, np.arange(12 * nside * nside))
+
+    def r2n(p):
+        return int(hp.ring2nest_pix(nside, np.array([p]))[0])
 
     def nvec(i):
         return hp.vec(np.cos(rays["theta"][i]), rays["phi"][i])
@@ -209,7 +211,7 @@ def galaxy_images(nside, rays, chi, k, gal_theta, gal_phi, gal_chi, radius, K=0.
         def src_of(pix):
             res = []
             for p in pix:
-                i = r2n[p]
+                i = r2n(int(p))
                 b = np.array([rays["beta"][0][i], rays["beta"][1][i], rays["beta"][2][i]])
                 res.append(propagate(nvec(i), b, chi[k], cg))
             return np.array(res)
@@ -220,9 +222,9 @@ def galaxy_images(nside, rays, chi, k, gal_theta, gal_phi, gal_chi, radius, K=0.
             continue
         img = found[0]
         w = shell_weight(chi[k - 1], chi[k], cg, K)
-        Aq = lambda p: np.asarray(rays["A"][:, r2n[p]], dtype=np.float64).reshape(2, 2)
-        Apq = lambda p: np.asarray(rays["A_prev"][:, r2n[p]], dtype=np.float64).reshape(2, 2)
-        Ag = image_jacobian(nside, img, Aq, Apq, lambda p: nvec(r2n[p]), w)
+        Aq = lambda p: np.asarray(rays["A"][:, r2n(p)], dtype=np.float64).reshape(2, 2)
+        Apq = lambda p: np.asarray(rays["A_prev"][:, r2n(p)], dtype=np.float64).reshape(2, 2)
+        Ag = image_jacobian(nside, img, Aq, Apq, lambda p: nvec(r2n(p)), w)
         ti, pi = hp.vec2ang(img)
         out.append((True, ti, pi, Ag))
     return out

@@ -30,27 +30,67 @@ def clm():
     return c
 
 
-def synthetic_rays(N, seed, shift):
-    """NESTED-order ray state: positions = pixel centres turned by a smooth
-    rotation field of about `shift` rad, directions tilted by 1e-3 rad,
-    Jacobians I + 0.05 (smooth fields), rounded to float32."""
+def ray_field(seed, shift):
+    """The seeded smooth fields of the synthetic ray state: two rotation
+    axes (the second scaled by n . c), a tilt axis for the directions."""
     rng = np.random.default_rng(seed)
     a, b, c, d = (rng.standard_normal(3) for _ in range(4))
-    a *= shift / np.linalg.norm(a)
-    b *= shift / np.linalg.norm(b)
-    n_pix = 12 * N * N
-    z, ph, s = hp.pix2ang_nest(N, np.arange(n_pix))
+    return a * shift / np.linalg.norm(a), b * shift / np.linalg.norm(b), c, d / np.linalg.norm(d)
+
+
+def ray_state(N, idx, field):
+    """Synthetic state of the NESTED rays idx: positions = pixel centres
+    turned by the smooth rotation field (a fraction of a pixel), directions
+    tilted by 1e-3 rad, Jacobians I + 0.05 (smooth fields), float32."""
+    a, b, c, d = field
+    z, ph, s = hp.pix2ang_nest(N, idx)
     n = hp.vec(z, ph, s)
     pos = n + np.cross(a, n) + (n @ c)[:, None] * np.cross(b, n)
     pos /= np.linalg.norm(pos, axis=1)[:, None]
-    beta = pos + 1e-3 * np.cross(d / np.linalg.norm(d), pos)
+    beta = pos + 1e-3 * np.cross(d, pos)
     beta /= np.linalg.norm(beta, axis=1)[:, None]
     th, phi = hp.vec2ang(pos)
     A = np.stack([1 + 0.05 * np.sin(3 * th), 0.05 * np.cos(2 * phi),
                   0.03 * np.sin(phi + th), 1 - 0.04 * np.cos(th)]).astype(np.float32)
     Ap = np.stack([1 + 0.02 * np.cos(th), 0.01 * np.sin(phi),
                    -0.02 * np.sin(2 * th), 1 + 0.03 * np.sin(phi)]).astype(np.float32)
-    return dict(theta=th, phi=phi, beta=beta.T.copy(), A=A, A_prev=Ap)
+    return th, phi, beta.T, A, Ap
+
+
+def synthetic_rays(N, seed, shift):
+    """The synthetic state of every ray (NESTED order)."""
+    th, phi, beta, A, Ap = ray_state(N, np.arange(12 * N * N), ray_field(seed, shift))
+    return dict(theta=th, phi=phi, beta=beta.copy(), A=A, A_prev=Ap)
+
+
+def synthetic_rays_near(N, seed, shift, gth, gph, R):
+    """The synthetic state of the rays within R rad of each galaxy; every
+    other ray holds one fixed valid state (position and direction along x,
+    identity Jacobians).  A search that reads only rays near the galaxy
+    sees the same data as with the whole synthetic state."""
+    n = 12 * N * N
+    st = dict(theta=np.full(n, np.pi / 2), phi=np.zeros(n),
+              beta=np.zeros((3, n)), A=np.zeros((4, n), np.float32),
+              A_prev=np.zeros((4, n), np.float32))
+    st["beta"][0] = 1.0
+    st["A"][0] = st["A"][3] = st["A_prev"][0] = st["A_prev"][3] = 1.0
+    h = 0.25 * PIXEL(N)
+    x = np.arange(-R, R + h, h)
+    X, Y = np.meshgrid(x, x)
+    idx = []
+    for t, p in zip(gth, gph):
+        g = hp.vec(np.cos(t), p)
+        et = np.array([np.cos(t) * np.cos(p), np.cos(t) * np.sin(p), -np.sin(t)])
+        ep = np.array([-np.sin(p), np.cos(p), 0.0])
+        v = g + X.reshape(-1, 1) * et + Y.reshape(-1, 1) * ep
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        vt, vp = hp.vec2ang(v)
+        idx.append(hp.ang2pix_nest(N, np.cos(vt), vp))
+    idx = np.unique(np.concatenate(idx))
+    th, phi, beta, A, Ap = ray_state(N, idx, ray_field(seed, shift))
+    st["theta"][idx], st["phi"][idx] = th, phi
+    st["beta"][:, idx], st["A"][:, idx], st["A_prev"][:, idx] = beta, A, Ap
+    return st
 
 
 def test_galaxy_images_match_oracle(clm):
@@ -92,6 +132,48 @@ def test_galaxy_images_match_oracle(clm):
     assert worst_pos < 1e-12
     assert worst_A < 2e-6
     plan.close()
+
+
+def test_galaxy_images_fullsize(clm):
+    """The benchmark's grid (Nside 2048, 50.3M rays) and search settings:
+    28 galaxies of one shell, four of them within 0.01 rad of a pole,
+    against the oracle on the same synthetic ray state."""
+    N = 2048
+    chi = np.array([1000.0, 1100.0, 1200.0, 1300.0])
+    k = 2                                            # shell [1150, 1250)
+    ng = 28
+    gth, gph = inputs.uniform_sphere(ng, seed=72)
+    gth[:4] = [0.0007, 0.006, np.pi - 0.0009, np.pi - 0.008]
+    gch = np.random.default_rng(73).uniform(1150.0, 1250.0, ng)
+    print("fixture: synthetic ray state at Nside 2048 near the galaxies", flush=True)
+    st = synthetic_rays_near(N, 71, 0.3 * PIXEL(N), gth, gph, 16 * PIXEL(N))
+    # a pure-SHT plan carries the fine-grid tables the search reads
+    plan = clm.Plan(N, nside_sht=N, lmax=8, solver="sht")
+    rays = plan.new_rays()
+    for key in ("theta", "phi", "beta", "A", "A_prev"):
+        rays[key].copy_(torch.from_numpy(np.ascontiguousarray(st[key])))
+    gal = dict(theta=torch.from_numpy(gth).cuda(), phi=torch.from_numpy(gph).cuda(),
+               chi=torch.from_numpy(gch).cuda(),
+               A=torch.zeros((4, ng), dtype=torch.float32, device="cuda"))
+    th_i, ph_i, found = plan.galaxy_images(chi, k, rays, gal)
+    plan.sync_status()
+    th_i, ph_i, found = th_i.cpu().numpy(), ph_i.cpu().numpy(), found.cpu().numpy()
+    Ag = gal["A"].cpu().numpy()
+    plan.close()
+    del rays
+    print("oracle: %d galaxies" % ng, flush=True)
+    ref = im.galaxy_images(N, st, chi, k, gth, gph, gch, radius=3 * PIXEL(N))
+    worst_pos = worst_A = 0.0
+    for i in range(ng):
+        ok, t, p, A = ref[i]
+        assert ok and found[i] == 1, i
+        v, w = hp.vec(np.cos(t), p), hp.vec(np.cos(th_i[i]), ph_i[i])
+        worst_pos = max(worst_pos, np.arctan2(np.linalg.norm(np.cross(v, w)), v @ w))
+        worst_A = max(worst_A, np.abs(Ag[:, i] - A.ravel()).max())
+    print("PARITY images Nside 2048 position %.3e rad, Jacobian %.3e" % (worst_pos, worst_A),
+          flush=True)
+    assert worst_pos < 1e-12
+    assert worst_A < 2e-6
 
 
 def test_images_end_to_end(clm):

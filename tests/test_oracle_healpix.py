@@ -41,6 +41,8 @@ def test_nest_ring_bijection_and_ang2pix(N):
     assert np.array_equal(hp.ring2nest(N, r), p)
     z, phi, _ = hp.pix2ang_nest(N, p)
     assert np.array_equal(hp.ang2pix_nest(N, z, phi), p)
+    # the per-pixel RING -> NESTED map agrees with the full permutation
+    assert np.array_equal(hp.ring2nest_pix(N, p), hp.ring2nest(N, p))
 
 
 @pytest.mark.parametrize("N", [2, 4, 8])
