@@ -285,6 +285,16 @@ __device__ __forceinline__ void rec_weights(const SetupRing& A, const SetupRing&
   w[3] = wt * wb;
 }
 
+// Element p of a map whose base is the same for the whole wave: the index
+// enters as an unsigned 32-bit byte offset (pixel counts stay far below
+// 2^28), so the load takes the uniform base in scalar registers and one
+// offset register, with no 64-bit address arithmetic per lane.
+template <typename T>
+__device__ __forceinline__ T map_at(const T* base, int p) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                     unsigned(p) * unsigned(sizeof(T)));
+}
+
 // Pass 1 of the setup with record stores: the global direction of a cell
 // from per-row coefficients (z, and the cos/sin-weighted components along
 // the reference azimuth, each A + B cos phi' + C sin phi') and the column's
@@ -357,17 +367,18 @@ __device__ void setup_pass1_rec(const SetupArgs& a, const SetupRing* rf, const S
         if (inner) hpx::interp_weights_g(gfs, gf, z, rho, dphi, pf, wf);
         hpx::interp_weights_g(gss, min(max(gsr, -1), a.rs.nring - 1), z, rho, dphi, ps, ws);
       }
-      v = ws[0] * a.psi_s[ps[0]] + ws[1] * a.psi_s[ps[1]] + ws[2] * a.psi_s[ps[2]] +
-          ws[3] * a.psi_s[ps[3]];
+      v = ws[0] * map_at(a.psi_s, ps[0]) + ws[1] * map_at(a.psi_s, ps[1]) +
+          ws[2] * map_at(a.psi_s, ps[2]) + ws[3] * map_at(a.psi_s, ps[3]);
       if (inner) {
         double kv;
         if (a.kappa_fp64) {
           const double* km = static_cast<const double*>(a.kappa);
-          kv = wf[0] * km[pf[0]] + wf[1] * km[pf[1]] + wf[2] * km[pf[2]] + wf[3] * km[pf[3]];
+          kv = wf[0] * map_at(km, pf[0]) + wf[1] * map_at(km, pf[1]) +
+               wf[2] * map_at(km, pf[2]) + wf[3] * map_at(km, pf[3]);
         } else {
           const float* km = static_cast<const float*>(a.kappa);
-          kv = wf[0] * double(km[pf[0]]) + wf[1] * double(km[pf[1]]) +
-               wf[2] * double(km[pf[2]]) + wf[3] * double(km[pf[3]]);
+          kv = wf[0] * double(map_at(km, pf[0])) + wf[1] * double(map_at(km, pf[1])) +
+               wf[2] * double(map_at(km, pf[2])) + wf[3] * double(map_at(km, pf[3]));
         }
         if (fsh)
           fsh[(li - 1) * TILE + (lj - 1)] = T(2.0 * (kv - mean));
