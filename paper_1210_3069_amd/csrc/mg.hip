@@ -79,7 +79,7 @@ __device__ __forceinline__ void patch_dir(const double* R, double st, double ct,
 // Rings of the two grids a setup block may copy to LDS (the tile's z range
 // plus one cell of slack; blocks whose range is wider read the global
 // tables).
-constexpr int kRingCapF = 192, kRingCapS = 48;
+constexpr int kRingCapF = 192, kRingCapS = 96;
 constexpr int kSetupBlock = 512;
 constexpr int kLdsBlock = 512;
 
