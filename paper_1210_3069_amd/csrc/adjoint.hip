@@ -448,18 +448,31 @@ __global__ void k_prolong_T(int n, int64_t np, const double* xf, double* ec, dou
   const int64_t b = t / (int64_t(nc) * nc);
   const int c = int(t % (int64_t(nc) * nc)), I = c / nc, J = c % nc;
   const double* x = xf + size_t(b) * n * n;
+  // the 4 x 4 fine window, every load issued before any is used (indices
+  // clamped into the patch; cells outside it add nothing)
+  double xv[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+      const int r = min(max(2 * I - 1 + a, 0), n - 1), q = min(max(2 * J - 1 + c4, 0), n - 1);
+      xv[a][c4] = x[r * n + q];
+    }
   double v = 0.0;
-  for (int r = 2 * I - 1; r <= 2 * I + 2; ++r) {
-    if (r < 0 || r >= n) continue;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int r = 2 * I - 1 + a;
     const double wr = (r >> 1) == I ? 0.75 : 0.25;
-    for (int q = 2 * J - 1; q <= 2 * J + 2; ++q) {
-      if (q < 0 || q >= n) continue;
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+      const int q = 2 * J - 1 + c4;
+      if (r < 0 || r >= n || q < 0 || q >= n) continue;
       const bool ring = r == 0 || r == n - 1 || q == 0 || q == n - 1;
       const bool own = (r >> 1) == I && (q >> 1) == J;
       if (ring) {
-        if (own) v += x[r * n + q];
+        if (own) v += xv[a][c4];
       } else {
-        v += wr * ((q >> 1) == J ? 0.75 : 0.25) * x[r * n + q];
+        v += wr * ((q >> 1) == J ? 0.75 : 0.25) * xv[a][c4];
       }
     }
   }
