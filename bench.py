@@ -677,6 +677,90 @@ def c4_run(clm, torch, inputs):
     return out
 
 
+def next2_run(clm, torch, inputs):
+    """The pure-SHT solver as a production path at Nside 2048 (Sec. 3.2,
+    last paragraph): 8 planes of Gaussian kappa (lmax 4096, sigma 0.5,
+    C_l ~ l^-2, seeds 700 + i) solved as one GEMM batch on the matrix cores
+    (float32 form), then the gradient and covariant Hessian at all 50.3M
+    pixels of every plane by the matrix-core derivative synthesis (NESTED,
+    float32 outputs).  Timed end to end; a second pass with events around
+    the matrix-core launches gives their algorithmic rates (derivative
+    synthesis: 2 flops x 10 real columns x H x n_lm per plane).  One plane
+    of the FP64 form (vector Legendre sums) is timed beside it and its
+    fields compared with the float32 form's."""
+    N, lmax, P = 2048, 4096, 8
+    npix = 12 * N * N
+    kap = torch.stack([clm.alm2map(torch.from_numpy(
+        inputs.gaussian_alm(lmax, seed=700 + i, sigma=0.5)).cuda(), lmax, N) for i in range(P)])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plan = clm.Plan(N, nside_sht=N, lmax=lmax, solver="sht", max_planes=P, legendre_prec="fp32")
+    t_create = time.perf_counter() - t
+    g = torch.empty(P, 2, npix, dtype=torch.float32, device="cuda")
+    h = torch.empty(P, 3, npix, dtype=torch.float32, device="cuda")
+
+    def step():
+        plan.poisson_solve(kap)
+        plan.shear_at_pixels_batch(0, P, order="nested", fp64=False, out=(g, h))
+
+    step()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 2
+    t0.record()
+    for _ in range(reps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    plan.set_timing(True)
+    plan.get_timing()
+    step()
+    st = plan.get_timing()
+    plan.set_timing(False)
+    plan.sync_status()
+    H = 2 * N
+    nlm = (lmax + 1) * (lmax + 2) // 2
+    mfma = {}
+    for k, cols in (("sht_analysis_mfma", 2), ("sht_synthesis_mfma", 2), ("sht_deriv_mfma", 10)):
+        tot, cnt = st.get(k, (0.0, 0))
+        if cnt:
+            tf = P * 2.0 * cols * H * nlm / (tot * 1e-3) / 1e12
+            mfma[k] = dict(ms=tot, launches=int(cnt), alg_tflops=tf,
+                           mfma_frac=tf / MFMA_PEAK_TFLOPS["fp32"])
+    # one plane of the FP64 form beside it
+    p64 = clm.Plan(N, nside_sht=N, lmax=lmax, solver="sht", max_planes=1)
+    p64.poisson_solve(kap[:1])
+    torch.cuda.synchronize()
+    t0.record()
+    g64, h64 = p64.shear_at_pixels(0, order="nested", fp64=True)
+    t1.record()
+    torch.cuda.synchronize()
+    ms64 = t0.elapsed_time(t1)
+    p64.sync_status()
+    err = {}
+    for k, name in enumerate(("g_t", "g_p")):
+        d = g[0, k].double() - g64[k]
+        err[name] = float(d.norm() / g64[k].norm())
+    for k, name in enumerate(("U_tt", "U_pp", "U_tp")):
+        d = h[0, k].double() - h64[k]
+        err[name] = float(d.norm() / h64[k].norm())
+    p64.close()
+    plan.close()
+    del plan, p64, g, h, g64, h64, kap
+    torch.cuda.empty_cache()
+    return dict(
+        planes_per_s=P * 1000.0 / ms, ms_per_plane=ms / P, ms_all_planes=ms,
+        stage_ms_per_plane={k: v[0] / P for k, v in st.items() if v[1]},
+        matrix_core=mfma, plan_create_s=t_create,
+        fp64_form=dict(deriv_ms_one_plane=ms64,
+                       rel_l2_fp32_vs_fp64_form=err),
+        workload="8 planes at Nside 2048, lmax 4096, pure-SHT Poisson solve (float32 "
+                 "matrix-core analysis) + gradient and covariant Hessian at all 50.3M pixels "
+                 "(matrix-core derivative synthesis, 8 planes per launch, 5 ring inverses "
+                 "per plane)")
+
+
 def c5_run(clm, torch, inputs):
     """Differentiation workload: 8 planes at Nside_fine (256, 512, 1024, 2048)
     x 2 (Nside_sht = Nside / 8, lmax = 2 Nside_sht, bundles Nside / 64,
@@ -790,6 +874,8 @@ def parse_args(argv=None):
                     help="skip the batched-precision workload (32 uneven pure-SHT planes)")
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the differentiation workload (8 planes, chi^2 gradient)")
+    ap.add_argument("--no-pure-sht", action="store_true",
+                    help="skip the pure-SHT production path (8 planes at Nside 2048)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with a plain copy kernel of known size (counter calibration)")
     ap.add_argument("--summarize-stats", nargs="+", metavar="ARG",
@@ -971,6 +1057,9 @@ def main():
     if not args.no_c5:
         print("bench: differentiation", file=sys.stderr, flush=True)
         out["c5_gradient"] = c5_run(clm, torch, inputs)
+    if not args.no_pure_sht:
+        print("bench: pure-SHT solver", file=sys.stderr, flush=True)
+        out["pure_sht_nside2048"] = next2_run(clm, torch, inputs)
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

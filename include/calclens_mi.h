@@ -127,6 +127,10 @@ typedef struct {
                             form and batch); the choice is readable with
                             clm_plan_get_desc                             */
   int32_t mfma_syn_waves;
+  int32_t mfma_der_waves; /* pure-SHT plans of a matrix-core form: waves per
+                            workgroup of the derivative synthesis of
+                            clm_shear_at_pixels (4 or 8); 0 (default):
+                            chosen at plan creation like the two above    */
 } clm_plan_desc;
 
 /* Fill *d with the defaults for a fine grid: nside_sht = nside_fine / 8
@@ -280,7 +284,7 @@ clm_status clm_get_patch_potential(clm_plan plan, int32_t slot, int64_t first_pa
  * clm_shear_from_potential: points theta_dev/phi_dev [npts] float64 (SHT+MG
  * solver only).  clm_shear_at_pixels: all 12 nside_fine^2 pixel centres in
  * `order` (both solvers; the SHT solver synthesises the derivatives
- * directly from psi_lm).  grad_dev: [2][npts], hess_dev: [3][npts], float64
+ * directly from psi_lm, as clm_shear_at_pixels_batch below).  grad_dev: [2][npts], hess_dev: [3][npts], float64
  * if out_fp64 else float32.  Points whose interpolation footprint leaves
  * their patch get NaN and latch CLM_ERAY_LEFT_PATCH.
  */
@@ -289,6 +293,25 @@ clm_status clm_shear_from_potential(clm_plan plan, int32_t slot, const double* t
                                     void* grad_dev, void* hess_dev, hipStream_t stream);
 clm_status clm_shear_at_pixels(clm_plan plan, int32_t slot, int32_t order, int32_t out_fp64,
                                void* grad_dev, void* hess_dev, hipStream_t stream);
+
+/*
+ * The pure-SHT solver's derivative fields for several planes (Sec. 3.2,
+ * last paragraph): clm_shear_at_pixels for slots first_slot ..
+ * first_slot + nplanes - 1 of an SHT-only plan, into grad_dev
+ * [nplanes][2][npix] and hess_dev [nplanes][3][npix] (npix = 12
+ * nside_fine^2, `order` RING or NESTED, float64 if out_fp64 else float32).
+ * With a matrix-core legendre_prec the synthesis runs on the matrix cores,
+ * up to 8 planes per launch, in the float32 form for every matrix-core
+ * plan: per (ring, l) the FP64 recurrence generates lambda, d lambda / d
+ * theta and the two spin-2 functions (the gamma_1 and gamma_2 parts of the
+ * covariant Hessian), rounded to float32; then five ring inverses per
+ * plane.  An FP64 plan runs the FP64 synthesis plane by plane.  Errors:
+ * CLM_EINVAL for a bad slot range, order or pointer; CLM_EUNSUPPORTED on an
+ * SHT+MG plan.  Asynchronous on `stream`; no allocation.
+ */
+clm_status clm_shear_at_pixels_batch(clm_plan plan, int32_t first_slot, int32_t nplanes,
+                                     int32_t order, int32_t out_fp64, void* grad_dev,
+                                     void* hess_dev, hipStream_t stream);
 
 /*
  * Ray state (Sec. 2.2), one ray per HEALPix pixel of nside_fine in NESTED

@@ -27,7 +27,8 @@ class PlanDesc(ctypes.Structure):
                                                ("adjoint", ctypes.c_int32),
                                                ("analysis_iters", ctypes.c_int32),
                                                ("mfma_ana_waves", ctypes.c_int32),
-                                               ("mfma_syn_waves", ctypes.c_int32)]
+                                               ("mfma_syn_waves", ctypes.c_int32),
+                                               ("mfma_der_waves", ctypes.c_int32)]
 
 
 class Rays(ctypes.Structure):
@@ -69,6 +70,7 @@ _SIGS = {
     "clm_get_patch_potential": (_P, _I32, _I64, _I64, _P, _P),
     "clm_shear_from_potential": (_P, _I32, _P, _P, _I64, _I32, _P, _P, _P),
     "clm_shear_at_pixels": (_P, _I32, _I32, _I32, _P, _P, _P),
+    "clm_shear_at_pixels_batch": (_P, _I32, _I32, _I32, _I32, _P, _P, _P),
     "clm_rays_init": (_P, ctypes.POINTER(Rays), _P),
     "clm_raytrace_planes": (_P, _P, _I32, ctypes.POINTER(_D), _I32, _I32, _I32, _D,
                             ctypes.POINTER(Rays), ctypes.POINTER(Galaxies), _P),
@@ -191,8 +193,8 @@ def tune_cache_path():
 
 def _tune_key(dev, d):
     batch = min(d.max_planes, 16)
-    return "%s|nside %d|lmax %d|form %d|batch %d" % (torch.cuda.get_device_name(dev), d.nside_sht,
-                                                     d.lmax, d.legendre_prec, batch)
+    return "%s|nside %d|lmax %d|form %d|batch %d|solver %d" % (
+        torch.cuda.get_device_name(dev), d.nside_sht, d.lmax, d.legendre_prec, batch, d.solver)
 
 
 def _tune_load():
@@ -203,10 +205,10 @@ def _tune_load():
         return {}
 
 
-def _tune_store(key, ana, syn):
+def _tune_store(key, ana, syn, der):
     path = tune_cache_path()
     table = _tune_load()
-    table[key] = [int(ana), int(syn)]
+    table[key] = [int(ana), int(syn), int(der)]
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         tmp = path + ".tmp%d" % os.getpid()
@@ -235,12 +237,16 @@ class Plan:
             setattr(d, k, float(v) if k == "mg_eps" else int(v))
         dev = torch.cuda.current_device() if device is None else int(device)
         tune_key = None
-        if d.legendre_prec != FP64 and (d.mfma_ana_waves == 0 or d.mfma_syn_waves == 0):
+        sht_only = d.solver == SOLVER_SHT
+        if d.legendre_prec != FP64 and (d.mfma_ana_waves == 0 or d.mfma_syn_waves == 0 or
+                                        (sht_only and d.mfma_der_waves == 0)):
             tune_key = _tune_key(dev, d)
             hit = _tune_load().get(tune_key)
-            if hit and len(hit) == 2:
+            if hit and len(hit) == 3:
                 d.mfma_ana_waves = d.mfma_ana_waves or int(hit[0])
                 d.mfma_syn_waves = d.mfma_syn_waves or int(hit[1])
+                if sht_only:
+                    d.mfma_der_waves = d.mfma_der_waves or int(hit[2])
                 tune_key = None
         h = ctypes.c_void_p()
         st = L.clm_plan_create(ctypes.byref(d), dev, ctypes.byref(h))
@@ -256,7 +262,8 @@ class Plan:
         self.npix_sht = 12 * self.desc["nside_sht"] ** 2
         self.lmax = self.desc["lmax"]
         if tune_key is not None:
-            _tune_store(tune_key, self.desc["mfma_ana_waves"], self.desc["mfma_syn_waves"])
+            _tune_store(tune_key, self.desc["mfma_ana_waves"], self.desc["mfma_syn_waves"],
+                        self.desc["mfma_der_waves"])
 
     def _check(self, st, what, h="self"):
         if st == CLM_OK:
@@ -397,6 +404,22 @@ class Plan:
             g, h = out
         self._check(lib().clm_shear_at_pixels(self.h, slot, o, int(fp64), _ptr(g), _ptr(h),
                                               _stream()), "shear_at_pixels")
+        return g, h
+
+    def shear_at_pixels_batch(self, first_slot=0, nplanes=1, order="ring", fp64=True,
+                              out=None):
+        """Pure-SHT plans: gradient [nplanes][2][npix] and Hessian
+        [nplanes][3][npix] of slots first_slot .. first_slot + nplanes - 1."""
+        o = ORDER_RING if order == "ring" else ORDER_NESTED
+        dt = torch.float64 if fp64 else torch.float32
+        if out is None:
+            g = torch.empty(nplanes, 2, self.npix_fine, dtype=dt, device=self.device)
+            h = torch.empty(nplanes, 3, self.npix_fine, dtype=dt, device=self.device)
+        else:
+            g, h = out
+        self._check(lib().clm_shear_at_pixels_batch(self.h, first_slot, nplanes, o, int(fp64),
+                                                    _ptr(g), _ptr(h), _stream()),
+                    "shear_at_pixels_batch")
         return g, h
 
     # ---------------------------------------------------------------- rays

@@ -89,6 +89,7 @@ struct Plan {
   void* rowt = nullptr;
   double* cinv = nullptr;       // [16*16] inverse of the coarsest operator
   double* rcoef = nullptr;      // [nalm][2] Legendre recurrence a_l, b_l (matrix-core SHT)
+  double* dcoef = nullptr;      // [nalm] derivative coefficients k_l (pure-SHT matrix-core plans)
 
   // scratch
   double* kap_s = nullptr;      // [npix_s] degraded, demeaned kappa
@@ -99,10 +100,12 @@ struct Plan {
   int batch = 0;                // planes per GEMM batch (<= 16)
   int ncu = 0;                  // compute units of the device
   int ana_nw = 8, syn_nw = 16;  // waves per workgroup of the matrix-core kernels
+  int der_nw = 4;               // ... and of the derivative synthesis
   int* mfma_ctr = nullptr;      // work counter of their persistent launches
   std::vector<std::pair<std::string, float>> tune_ms;  // autotuner timings
   double* Fb = nullptr;         // [batch][nring_s][lmax+1] complex ring transforms
-  double* Gb = nullptr;         // [batch][nring_s][lmax+1] complex synthesis sums
+  double* Gb = nullptr;         // [batch][nring_s][lmax+1] complex synthesis sums; pure-SHT
+                                // plans: at least [8][5] such fields (derivative synthesis)
   float* apart = nullptr;       // [ring blocks][nalm][32] analysis partial sums
   float* psib = nullptr;        // [nalm][32] psi_lm as GEMM columns
   double* deriv = nullptr;      // [5][npix_s] pure-SHT raw derivative maps
@@ -268,6 +271,11 @@ clm_status sht_solve_multi(Plan* const* ps, int n, const void* const* kappa,
 clm_status mfma_tables(Plan* p, hipStream_t s);
 clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s);
 clm_status mfma_synthesis(Plan* p, int first_slot, int P, hipStream_t s);
+int mfma_deriv_planes();                                 // planes per derivative synthesis
+clm_status mfma_deriv_synthesis(Plan* p, int first_slot, int P, hipStream_t s);
+clm_status sht_pixel_derivs_batch(Plan* p, int first_slot, int nplanes, int order,
+                                  int out_fp64, void* grad, void* hess,
+                                  hipStream_t s);  // sht.hip
 clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64,
                             void* grad, void* hess, hipStream_t s);  // sht.hip
 clm_status mg_solve(Plan* p, const void* kappa, int kappa_fp64, int slot,

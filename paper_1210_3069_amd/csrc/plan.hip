@@ -34,7 +34,7 @@ Plan::~Plan() {
   f(ring_s); f(ringi_s); f(ringx_s); f(ring_f); f(ringi_f); f(ringx_f); f(lam_mant);
   f(lam_scale); f(blu_off); f(blu);
   f(r2n_s); f(r2n_f); f(rot); f(coef); f(rowt); f(cinv); f(kap_s); f(F); f(G); f(red);
-  f(rcoef); f(Fb); f(Gb); f(apart); f(psib); f(mfma_ctr);
+  f(rcoef); f(dcoef); f(Fb); f(Gb); f(apart); f(psib); f(mfma_ctr);
   f(deriv); f(fprime); f(dutmp); f(status_dev); f(iter_map); f(iter_alm);
   for (auto* q : ubar) f(q);
   f(ubar1b);
@@ -380,7 +380,8 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
       (d.analysis_iters > 0 && (d.legendre_prec != CLM_FP64 || d.adjoint)) ||
       (d.mfma_ana_waves != 0 && d.mfma_ana_waves != 8 && d.mfma_ana_waves != 16) ||
       (d.mfma_syn_waves != 0 && d.mfma_syn_waves != 8 && d.mfma_syn_waves != 12 &&
-       d.mfma_syn_waves != 16))
+       d.mfma_syn_waves != 16) ||
+      (d.mfma_der_waves != 0 && d.mfma_der_waves != 4 && d.mfma_der_waves != 8))
     return CLM_EINVAL;
   if (d.solver == CLM_SOLVER_SHT && d.nside_sht != d.nside_fine) return CLM_EINVAL;
   if (d.solver == CLM_SOLVER_SHT_MG) {
@@ -451,7 +452,11 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
     if ((s = alloc(p, &p->mfma_ctr, 4)) != CLM_OK) return bail(s);
     if ((s = alloc(p, &p->rcoef, size_t(p->nalm) * 2)) != CLM_OK) return bail(s);
     if ((s = alloc(p, &p->Fb, size_t(nF) * p->batch)) != CLM_OK) return bail(s);
-    if ((s = alloc(p, &p->Gb, size_t(nF) * p->batch)) != CLM_OK) return bail(s);
+    // pure-SHT plans: the derivative synthesis writes five fields per plane
+    const int gfields = p->mg ? p->batch
+                              : std::max(p->batch, 5 * std::min(p->batch, mfma_deriv_planes()));
+    if ((s = alloc(p, &p->Gb, size_t(nF) * gfields)) != CLM_OK) return bail(s);
+    if (!p->mg && (s = alloc(p, &p->dcoef, size_t(p->nalm))) != CLM_OK) return bail(s);
     if ((s = alloc(p, &p->psib, size_t(p->nalm) * 32)) != CLM_OK) return bail(s);
     const int R = mfma_ring_blocks(p->H);
     if (R > 1 && (s = alloc(p, &p->apart, size_t(R) * p->nalm * 32)) != CLM_OK) return bail(s);
@@ -760,9 +765,20 @@ clm_status clm_shear_at_pixels(clm_plan plan, int32_t slot, int32_t order, int32
   if (!plan || !grad || !hess || slot < 0 || slot >= plan->d.max_planes ||
       (order != CLM_ORDER_RING && order != CLM_ORDER_NESTED))
     return CLM_EINVAL;
-  if (!plan->mg) return sht_pixel_derivs(plan, slot, order, out_fp64, grad, hess, stream);
+  if (!plan->mg) return sht_pixel_derivs_batch(plan, slot, 1, order, out_fp64, grad, hess, stream);
   return eval_points(plan, slot, nullptr, nullptr, plan->npix_f, order, out_fp64, grad, hess,
                      stream);
+}
+
+clm_status clm_shear_at_pixels_batch(clm_plan plan, int32_t first_slot, int32_t nplanes,
+                                     int32_t order, int32_t out_fp64, void* grad, void* hess,
+                                     hipStream_t stream) {
+  if (!plan || !grad || !hess || first_slot < 0 || nplanes < 1 ||
+      nplanes > plan->d.max_planes - first_slot ||
+      (order != CLM_ORDER_RING && order != CLM_ORDER_NESTED))
+    return CLM_EINVAL;
+  if (plan->mg) return CLM_EUNSUPPORTED;
+  return sht_pixel_derivs_batch(plan, first_slot, nplanes, order, out_fp64, grad, hess, stream);
 }
 
 clm_status clm_rays_init(clm_plan plan, const clm_rays* rays, hipStream_t stream) {

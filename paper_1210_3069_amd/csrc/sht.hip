@@ -1356,6 +1356,66 @@ clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* gr
   return CLM_OK;
 }
 
+// The five derivative maps [5][npix] (g_t, g_p, U_tt, U_pp, U_tp, RING) to
+// the caller's gradient [2][npix] and Hessian [3][npix] in RING or NESTED
+// order.
+template <typename TO>
+__global__ void k_deriv_out(const double* D, int64_t npix, const int* r2n, int nested, TO* grad,
+                            TO* hess) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  const int64_t o = nested ? int64_t(r2n[p]) : p;
+  grad[o] = TO(D[p]);
+  grad[npix + o] = TO(D[npix + p]);
+  hess[o] = TO(D[2 * npix + p]);
+  hess[npix + o] = TO(D[3 * npix + p]);
+  hess[2 * npix + o] = TO(D[4 * npix + p]);
+}
+
+// Gradient and covariant Hessian at every pixel for planes first_slot ..
+// first_slot + nplanes - 1 of a pure-SHT plan: the matrix-core derivative
+// synthesis of up to 8 planes per launch, then per plane five ring inverses
+// and the reordering; FP64 plans run the FP64 synthesis plane by plane.
+clm_status sht_pixel_derivs_batch(Plan* p, int first_slot, int nplanes, int order, int out_fp64,
+                                  void* grad, void* hess, hipStream_t s) {
+  const size_t esz = out_fp64 ? 8 : 4;
+  const size_t npix = size_t(p->npix_s);
+  char* g = static_cast<char*>(grad);
+  char* h = static_cast<char*>(hess);
+  clm_status st;
+  if (p->batch == 0) {
+    for (int k = 0; k < nplanes; ++k)
+      if ((st = sht_pixel_derivs(p, first_slot + k, order, out_fp64, g + k * 2 * npix * esz,
+                                 h + k * 3 * npix * esz, s)) != CLM_OK)
+        return st;
+    return CLM_OK;
+  }
+  const int dp = std::min(p->batch, mfma_deriv_planes());
+  const size_t nF = size_t(p->nring_s) * (p->d.lmax + 1) * 2;
+  const dim3 grid(unsigned((npix + kBlock - 1) / kBlock));
+  for (int k0 = 0; k0 < nplanes; k0 += dp) {
+    const int nb = std::min(dp, nplanes - k0);
+    if ((st = mfma_deriv_synthesis(p, first_slot + k0, nb, s)) != CLM_OK) return st;
+    for (int k = 0; k < nb; ++k) {
+      if ((st = ring_inverse(p, p->Gb + 5 * k * nF, 5, p->deriv, s)) != CLM_OK) return st;
+      const size_t pk = size_t(k0 + k);
+      CLM_TIMED(p, s, "sht_deriv_out");
+      if (out_fp64)
+        hipLaunchKernelGGL(k_deriv_out<double>, grid, dim3(kBlock), 0, s, p->deriv,
+                           int64_t(npix), p->r2n_s, order == CLM_ORDER_NESTED,
+                           reinterpret_cast<double*>(g + pk * 2 * npix * esz),
+                           reinterpret_cast<double*>(h + pk * 3 * npix * esz));
+      else
+        hipLaunchKernelGGL(k_deriv_out<float>, grid, dim3(kBlock), 0, s, p->deriv,
+                           int64_t(npix), p->r2n_s, order == CLM_ORDER_NESTED,
+                           reinterpret_cast<float*>(g + pk * 2 * npix * esz),
+                           reinterpret_cast<float*>(h + pk * 3 * npix * esz));
+    }
+    CLM_LAUNCH_CHECK();
+  }
+  return CLM_OK;
+}
+
 }  // namespace clm
 
 extern "C" clm_status clm_alm2map(const double* alm, int32_t lmax, int32_t nside, double* map,

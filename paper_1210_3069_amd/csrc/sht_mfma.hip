@@ -151,6 +151,7 @@ struct MfmaArgs {
   const double* lam_mant;  // [lmax+1][H]
   const int* lam_scale;
   const double* rc;        // recurrence coefficients (a, b) per (l, m), alm order
+  const double* rk;        // derivative coefficients k_l per (l, m), alm order
   const float* psi;        // synthesis in: [nalm][32] (column c = 2 p + re/im)
   float* part;             // analysis out with several ring blocks: [R][nalm][32]
   double* alm[16];         // analysis out with one ring block: per plane
@@ -517,6 +518,245 @@ __global__ __launch_bounds__(64 * NW) void k_synthesis_mfma(MfmaMulti mm) {
     synthesis_item<FORM, NW>(ga[g], m, rb, tiles, coefs);
 }
 
+// ----------------------------------------------------- derivative synthesis
+// The pure-SHT solver's fields (Sec. 3.2, last paragraph; covariant
+// components as in App. A): on every ring the m-coefficients of
+//   g_t = psi_theta, g_p = psi_phi / sin, U_tt, U_pp, U_tp
+// from psi_lm.  Per (ring, l) the recurrence generates, in FP64, four
+// functions of theta (z = cos, s = sin):
+//   lambda;
+//   T = d lambda / d theta = (l z lambda_l - k_l lambda_{l-1}) / s,
+//       k_l = sqrt((2l+1)(l^2-m^2)/(2l-1))  (from the Legendre equation);
+//   X = (m^2/s^2 - l(l+1)/2) lambda - (z/s) T, so that
+//       gamma_1 = (U_tt - U_pp)/2 = sum X psi e^{i m phi};
+//   Y = (m/s) (T - (z/s) lambda), so that gamma_2 = U_tp = sum i Y psi e^{i m phi}.
+// X and Y are the spin-2 functions (and T with (m/s) lambda the spin-1
+// pair): their 1/s and 1/s^2 terms cancel inside the FP64 evaluation, so
+// the rounded values keep float32 relative precision on the polar rings.
+// They enter float32 matrix products with the GEMM columns psi_lm (8
+// planes x re/im) and, for lambda only, l(l+1) psi_lm (the Laplacian:
+// U_tt + U_pp = -sum l(l+1) psi_lm Y_lm):
+//   G = sum lambda psi, L = sum lambda l(l+1) psi, T, X, Y = sum (T|X|Y) psi.
+// Per ring then g_t = T, g_p = i (m/s) G, U_tt = X - L/2, U_pp = -X - L/2,
+// U_tp = i Y.  On the mirror ring lambda, L and X take the sign (-1)^(l+m)
+// of lambda, T and Y the opposite one.
+constexpr int kStepD = 16;   // values of l per step (8 per parity: 2 K blocks)
+constexpr int kPlanesD = 8;  // planes of one launch (32 columns: psi and l(l+1) psi)
+constexpr int kTileD = kStepD * kSynStride;  // floats of one function's tile
+
+// One step of kStepD values of l of this lane's ring: lambda, T, X, Y into
+// the four tiles of the wave (rows d, column = lane).  The step's
+// coefficients arrive as one vector: lanes 0..31 hold (a_l, b_l)
+// interleaved, lanes 32..47 hold k_l; the wave stages them in LDS.  The
+// rescale rule is that of rec_step over fewer values.
+__device__ __forceinline__ void deriv_value(const Rec& r, double L, double kl, double zs,
+                                            double is, double ms, double mms, bool ok,
+                                            float* tw, int off) {
+  const double t = L * zs * r.p1 - (kl * is) * r.p2;
+  const double x = (mms - 0.5 * L * (L + 1.0)) * r.p1 - zs * t;
+  const double y = ms * (t - zs * r.p1);
+  tw[off] = ok ? float(r.p1) : 0.0f;
+  tw[kTileD + off] = ok ? float(t) : 0.0f;
+  tw[2 * kTileD + off] = ok ? float(x) : 0.0f;
+  tw[3 * kTileD + off] = ok ? float(y) : 0.0f;
+}
+
+__device__ __forceinline__ void rec_step_deriv(Rec& r, int m, int dl0, int nl, double cv,
+                                               double* cs, float* tw, int lane, double zs,
+                                               double is, double ms, double mms) {
+  cs[lane] = cv;
+  __builtin_amdgcn_wave_barrier();
+  const double2* ab = reinterpret_cast<const double2*>(cs);
+  const double* kk = cs + 2 * kStepD;
+  const double L0 = double(m + dl0);
+  if (dl0 == 0) {
+#pragma unroll
+    for (int d = 0; d < kStepD; ++d) {
+      if (d == 1) {
+        r.p2 = r.p1;
+        r.p1 = sqrt(2.0 * m + 3.0) * r.z * r.p2;
+      } else if (d >= 2) {
+        const double2 c = ab[d];
+        const double p0 = c.x * (r.z * r.p1 - c.y * r.p2);
+        r.p2 = r.p1;
+        r.p1 = p0;
+      }
+      deriv_value(r, L0 + d, kk[d], zs, is, ms, mms, d < nl && r.s == 0, tw,
+                  d * kSynStride + lane);
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < kStepD; ++d) {
+      const double2 c = ab[d];
+      const double p0 = c.x * (r.z * r.p1 - c.y * r.p2);
+      r.p2 = r.p1;
+      r.p1 = p0;
+      deriv_value(r, L0 + d, kk[d], zs, is, ms, mms, dl0 + d < nl && r.s == 0, tw,
+                  d * kSynStride + lane);
+    }
+  }
+  if (r.s < 0 && fabs(r.p1) > kHugeB) {
+    r.p1 *= kSmallB;
+    r.p2 *= kSmallB;
+    r.s += 1;
+  }
+}
+
+// The coefficients of the step at dl0 (layout of rec_step_deriv), loaded a
+// step ahead.
+__device__ __forceinline__ double dcoef_fetch(const double* rc, const double* rk, int dl0,
+                                              int nl, int lane) {
+  if (lane < 2 * kStepD) {
+    const int t = 2 * dl0 + lane;
+    return t < 2 * nl ? rc[t] : 0.0;
+  }
+  const int t = dl0 + lane - 2 * kStepD;
+  return (lane < 3 * kStepD && t < nl) ? rk[t] : 0.0;
+}
+
+// psi_lm of up to kPlanesD planes as float GEMM columns [nalm][32]: column
+// 2 p + re/im holds psi_lm of plane p, column 16 + 2 p + re/im holds
+// l (l + 1) psi_lm.  One workgroup per m.
+__global__ void k_pack_psi_deriv(MfmaArgs a, float* psi) {
+  const int m = blockIdx.x;
+  const int nl = a.lmax - m + 1;
+  const size_t base = alm_base(m, a.lmax);
+  for (int t = threadIdx.x; t < nl * kCols; t += blockDim.x) {
+    const int dl = t >> 5, c = t & 31;
+    const int cc = c & 15, p = cc >> 1;
+    double v = 0.0;
+    if (p < a.P) {
+      v = a.alm[p][2 * (base + dl) + (cc & 1)];
+      if (c >= 16) {
+        const double L = double(m + dl);
+        v *= L * (L + 1.0);
+      }
+    }
+    psi[(base + dl) * kCols + c] = float(v);
+  }
+}
+
+// One item: order m, block of 64 NW rings; each wave owns 64 rings.  Output
+// G = [P][5 fields][nring][lmax+1] complex, fields g_t, g_p, U_tt, U_pp, U_tp.
+template <int NW>
+__device__ __forceinline__ void deriv_item(const MfmaArgs& a, int m, int rb, float* tiles,
+                                           double* coefs) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nl = a.lmax - m + 1;
+  const int qb = (rb * a.nwv + w) * 64;
+  float* tw = tiles + w * 4 * kTileD;
+  double* cs = coefs + w * 4 * kStepD;
+  const double* rc = a.rc + 2 * alm_base(m, a.lmax);
+  const double* rk = a.rk + alm_base(m, a.lmax);
+  const float* pm = a.psi + alm_base(m, a.lmax) * kCols;
+  Rec r = rec_start(a, m, qb + l);
+  double is = 0.0;
+  if (qb + l < a.H) is = 1.0 / a.rt[4 * (qb + l) + 1];
+  const double zs = r.z * is, ms = double(m) * is, mms = ms * ms;
+  // acc[par][mb][f]: rings 16 mb + .., f = lambda x psi, lambda x l(l+1) psi,
+  // T x psi, X x psi, Y x psi (columns lane % 16 of the psi block)
+  f4 acc[2][4][5];
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int f = 0; f < 5; ++f) acc[par][mb][f] = f4{0.f, 0.f, 0.f, 0.f};
+  const int i = l & 15, k = l >> 4;
+  // psi operands of a step, per parity: K block j (values 2 (4 j + k) + par)
+  // x column block nb (psi, l(l+1) psi), as element 2 j + nb
+  auto psi_fetch = [&](int dl0, float (&v)[2][4]) {
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int dl = dl0 + 2 * (4 * (e >> 1) + k) + par;
+        v[par][e] = dl < nl ? pm[size_t(dl) * kCols + i + 16 * (e & 1)] : 0.0f;
+      }
+  };
+  float pv[2][4];
+  double cv = dcoef_fetch(rc, rk, 0, nl, l);
+  for (int dl0 = 0; dl0 < nl; dl0 += kStepD) {
+    const double cn = dcoef_fetch(rc, rk, dl0 + kStepD, nl, l);  // next step's, in flight
+    psi_fetch(dl0, pv);
+    rec_step_deriv(r, m, dl0, nl, cv, cs, tw, l, zs, is, ms, mms);
+    cv = cn;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the tiles are written
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int row = 2 * (4 * j + k) + par;
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          const float* ap = tw + row * kSynStride + 16 * mb + i;
+          const float a0 = ap[0], a1 = ap[kTileD], a2 = ap[2 * kTileD], a3 = ap[3 * kTileD];
+          const float b0 = pv[par][2 * j], b1 = pv[par][2 * j + 1];
+          acc[par][mb][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[par][mb][0], 0, 0, 0);
+          acc[par][mb][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[par][mb][1], 0, 0, 0);
+          acc[par][mb][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[par][mb][2], 0, 0, 0);
+          acc[par][mb][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b0, acc[par][mb][3], 0, 0, 0);
+          acc[par][mb][4] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, b0, acc[par][mb][4], 0, 0, 0);
+        }
+      }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // tile reads done before the next step
+  }
+  // C fragment: ring 16 mb + 4 (lane / 16) + i4, column lane % 16 = 2 p + ri.
+  // Multiplying by i moves component ri to 1 - ri with sign (+ for ri = 0).
+  const size_t fs = size_t(a.nring) * (a.lmax + 1) * 2;  // one field, doubles
+  const int p = i >> 1, ri = i & 1;
+  const double sg = ri == 0 ? 1.0 : -1.0;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int i4 = 0; i4 < 4; ++i4) {
+      const int q = qb + 16 * mb + 4 * k + i4;
+      if (q >= a.H || p >= a.P) continue;
+      const double mos = double(m) / a.rt[4 * q + 1];
+      const int qm = a.nring - 1 - q;
+      double* Gp = a.G + size_t(p) * 5 * fs;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && qm == q) break;
+        const double sn = h == 0 ? 1.0 : -1.0;  // even + sn odd
+        const double G = double(acc[0][mb][0][i4]) + sn * double(acc[1][mb][0][i4]);
+        const double L = double(acc[0][mb][1][i4]) + sn * double(acc[1][mb][1][i4]);
+        const double T = sn * (double(acc[0][mb][2][i4]) + sn * double(acc[1][mb][2][i4]));
+        const double X = double(acc[0][mb][3][i4]) + sn * double(acc[1][mb][3][i4]);
+        const double Y = sn * (double(acc[0][mb][4][i4]) + sn * double(acc[1][mb][4][i4]));
+        double* g = Gp + (size_t(h == 0 ? q : qm) * (a.lmax + 1) + m) * 2;
+        g[ri] = T;
+        g[fs + 1 - ri] = sg * mos * G;
+        g[2 * fs + ri] = X - 0.5 * L;
+        g[3 * fs + ri] = -X - 0.5 * L;
+        g[4 * fs + 1 - ri] = sg * Y;
+      }
+    }
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 2) void k_deriv_mfma(MfmaMulti mm) {
+  __shared__ float tiles[NW * 4 * kTileD];
+  __shared__ __align__(16) double coefs[NW * 4 * kStepD];
+  __shared__ MfmaArgs ga[kMaxGroups];
+  __shared__ int slot;
+  load_groups(mm, ga);
+  int g, m, rb;
+  while (next_item(mm, &slot, g, m, rb) >= 0) deriv_item<NW>(ga[g], m, rb, tiles, coefs);
+}
+
+// k_l = sqrt((2l+1)(l^2-m^2)/(2l-1)) per (l, m) in alm order (0 at l = m).
+__global__ void k_deriv_table(int lmax, double* rk) {
+  const int m = blockIdx.x;
+  const size_t base = alm_base(m, lmax);
+  for (int l = m + threadIdx.x; l <= lmax; l += blockDim.x) {
+    const double L = l, M = m;
+    rk[base + l - m] = sqrt((2.0 * L + 1.0) * (L * L - M * M) / fmax(2.0 * L - 1.0, 1.0));
+  }
+}
+
 // Recurrence coefficients per (l, m) in alm order:
 // a_l = sqrt((4l^2-1)/(l^2-m^2)), b_l = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)).
 __global__ void k_recur_table(int lmax, double* rc) {
@@ -685,6 +925,52 @@ clm_status synthesis_groups(const MfmaGroup* gs, int ng, int nw, hipStream_t s) 
   return CLM_OK;
 }
 
+template <int NW>
+void launch_der(const MfmaMulti& mm, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_deriv_mfma<NW>), dim3(blocks), dim3(64 * NW), 0, s, mm);
+}
+
+constexpr int kDerNW[] = {4, 8};
+
+// psi_lm of planes first_slot .. first_slot + P - 1 packed as GEMM columns,
+// then one persistent derivative-synthesis launch; the five fields of plane
+// k land in Gb + 5 k nF.
+clm_status deriv_launch(Plan* p, int first_slot, int P, int nw, hipStream_t s) {
+  if (P < 1 || P > kPlanesD) return fail(p, CLM_EINVAL, "1 to 8 planes per derivative synthesis");
+  if (!p->dcoef) return fail(p, CLM_EINVAL, "derivative synthesis needs a pure-SHT plan");
+  MfmaMulti mm{};
+  mm.ng = 1;
+  mm.ctr = p->mfma_ctr;
+  MfmaArgs& a = mm.g[0];
+  a = base_args(p, first_slot, P);
+  a.G = p->Gb;
+  a.psi = p->psib;
+  a.rk = p->dcoef;
+  a.nwv = nw;
+  a.R = ring_blocks_nw(a.H, nw);
+  mm.R[0] = a.R;
+  mm.start[0] = 0;
+  mm.start[1] = (a.lmax + 1) * a.R;
+  {
+    CLM_TIMED(p, s, "sht_pack_psi");
+    hipLaunchKernelGGL(k_pack_psi_deriv, dim3(a.lmax + 1), dim3(kBlk), 0, s, a, p->psib);
+  }
+  CLM_LAUNCH_CHECK();
+  const size_t lds = size_t(nw) * 4 * (kTileD * 4 + kStepD * 8) + sizeof(mm.g);
+  const int blocks = persistent_blocks(p, lds, nw, mm.start[1]);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, p->mfma_ctr);
+  {
+    CLM_TIMED(p, s, "sht_deriv_mfma");
+    switch (nw) {
+      case 4: launch_der<4>(mm, blocks, s); break;
+      case 8: launch_der<8>(mm, blocks, s); break;
+      default: return fail(p, CLM_EINVAL, "no derivative-synthesis shape with that many waves");
+    }
+  }
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
 }  // namespace
 
 // Ring blocks of the analysis at the fewest waves the autotuner may pick
@@ -693,8 +979,17 @@ int mfma_ring_blocks(int H) { return ring_blocks_nw(H, kAnaNW[0]); }
 
 clm_status mfma_tables(Plan* p, hipStream_t s) {
   hipLaunchKernelGGL(k_recur_table, dim3(p->d.lmax + 1), dim3(kBlk), 0, s, p->d.lmax, p->rcoef);
+  if (p->dcoef)
+    hipLaunchKernelGGL(k_deriv_table, dim3(p->d.lmax + 1), dim3(kBlk), 0, s, p->d.lmax,
+                       p->dcoef);
   CLM_LAUNCH_CHECK();
   return CLM_OK;
+}
+
+int mfma_deriv_planes() { return kPlanesD; }
+
+clm_status mfma_deriv_synthesis(Plan* p, int first_slot, int P, hipStream_t s) {
+  return deriv_launch(p, first_slot, P, p->der_nw, s);
 }
 
 clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s) {
@@ -730,7 +1025,7 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mutex;
-std::map<TuneKey, std::pair<int, int>> g_tuned;
+std::map<TuneKey, std::tuple<int, int, int>> g_tuned;
 
 template <typename F>
 float time_launch(F f, clm_status& st) {
@@ -757,18 +1052,20 @@ float time_launch(F f, clm_status& st) {
 
 clm_status mfma_autotune(Plan* p) {
   const clm_plan_desc& d = p->d;
-  const TuneKey key{p->device, d.nside_sht, d.lmax, form_of(p), p->batch};
+  const TuneKey key{p->device, d.nside_sht, d.lmax, form_of(p) + (p->mg ? 0 : 8), p->batch};
   int ana = d.mfma_ana_waves, syn = d.mfma_syn_waves;
+  int der = p->mg ? p->der_nw : d.mfma_der_waves;
   {
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
-      if (ana == 0) ana = it->second.first;
-      if (syn == 0) syn = it->second.second;
+      if (ana == 0) ana = std::get<0>(it->second);
+      if (syn == 0) syn = std::get<1>(it->second);
+      if (der == 0) der = std::get<2>(it->second);
     }
   }
   const size_t nF = size_t(p->nring_s) * (d.lmax + 1) * 2;
-  if (ana == 0 || syn == 0) {
+  if (ana == 0 || syn == 0 || der == 0) {
     if (hipMemset(p->Fb, 0, nF * p->batch * 8) != hipSuccess ||
         hipMemset(p->psib, 0, size_t(p->nalm) * kCols * 4) != hipSuccess)
       return fail(p, CLM_EHIP, "autotune set-up failed");
@@ -793,12 +1090,28 @@ clm_status mfma_autotune(Plan* p) {
       if (t < best) { best = t; syn = nw; }
     }
   }
+  if (der == 0) {
+    // on psi_lm = 0 (the slots' coefficients are not yet written)
+    float best = 1e30f;
+    const int P = std::min(p->batch, kPlanesD);
+    for (int k = 0; k < P; ++k)
+      if (hipMemset(p->slots[k].alm, 0, size_t(p->nalm) * 16) != hipSuccess)
+        return fail(p, CLM_EHIP, "autotune set-up failed");
+    for (int nw : kDerNW) {
+      const float t = time_launch([&] { return deriv_launch(p, 0, P, nw, nullptr); }, st);
+      if (st != CLM_OK) return st;
+      p->tune_ms.push_back({std::string("derivative_waves_") + std::to_string(nw), t});
+      if (t < best) { best = t; der = nw; }
+    }
+  }
   p->ana_nw = ana;
   p->syn_nw = syn;
+  p->der_nw = der;
   p->d.mfma_ana_waves = ana;
   p->d.mfma_syn_waves = syn;
+  if (!p->mg) p->d.mfma_der_waves = der;
   std::lock_guard<std::mutex> lk(g_tune_mutex);
-  g_tuned[key] = {ana, syn};
+  g_tuned[key] = {ana, syn, der};
   return CLM_OK;
 }
 

@@ -106,18 +106,19 @@ def test_autotuner_choice(clm, tmp_path, monkeypatch):
     monkeypatch.setenv("CALCLENS_MI_TUNE_CACHE", str(cache))
     pl = clm.Plan(64, nside_sht=64, lmax=128, solver="sht", max_planes=4,
                   legendre_prec="bf16x6")
-    pick = (pl.desc["mfma_ana_waves"], pl.desc["mfma_syn_waves"])
-    assert pick[0] in (8, 16) and pick[1] in (8, 12, 16)
+    names = ("mfma_ana_waves", "mfma_syn_waves", "mfma_der_waves")
+    pick = tuple(pl.desc[n] for n in names)
+    assert pick[0] in (8, 16) and pick[1] in (8, 12, 16) and pick[2] in (4, 8)
     pl.close()
     table = json.loads(cache.read_text())
     assert list(table.values()) == [list(pick)]
     # a planted entry is what the next plan of the same key uses
     key = list(table)[0]
-    other = (16, 12) if pick != (16, 12) else (8, 8)
+    other = (16, 12, 8) if pick != (16, 12, 8) else (8, 8, 4)
     cache.write_text(json.dumps({key: list(other)}))
     pl = clm.Plan(64, nside_sht=64, lmax=128, solver="sht", max_planes=4,
                   legendre_prec="bf16x6")
-    assert (pl.desc["mfma_ana_waves"], pl.desc["mfma_syn_waves"]) == other
+    assert tuple(pl.desc[n] for n in names) == other
     pl.close()
     pl = clm.Plan(64, nside_sht=64, lmax=128, solver="sht", max_planes=4,
                   legendre_prec="fp32", mfma_ana_waves=16, mfma_syn_waves=12)

@@ -136,3 +136,32 @@ def test_sht_nside512_lmax1024_against_oracle(clm, sht512_case, form, tol_l2):
     if form == "fp64":
         assert rel(alm, c["palm"]) < 1e-10
         assert rel(psi, c["psi"]) < 1e-10
+
+
+# both polar caps (rings 0-3 and 2043-2046), the belt edges (511, 1535 and
+# their neighbours) and the equator (1023) of the Nside 512 grid
+SHT512_RINGS = [0, 1, 2, 3, 255, 510, 511, 512, 1022, 1023, 1024, 1534, 1535, 1536, 2043,
+                2044, 2045, 2046]
+
+
+@pytest.mark.parametrize("form,tol", [("fp64", 1e-10), ("fp32", 2e-6)])
+def test_pure_sht_derivatives_nside512(clm, sht512_case, form, tol):
+    """The pure-SHT solver's gradient and covariant Hessian at Nside 512 /
+    lmax 1024 (FP64 synthesis, and the matrix-core synthesis of the float32
+    form) against the oracle's derivative fields of its own solve, on every
+    pixel of 18 sampled rings.  Max-norm error per field relative to the
+    field's largest sampled magnitude."""
+    c = sht512_case
+    print("case: pure-SHT derivatives Nside 512 lmax 1024, %s" % form, flush=True)
+    ref = osht.derivative_maps(c["N"], c["lmax"], c["palm"], rings=SHT512_RINGS)
+    pix = osht.ring_pixels(c["N"], SHT512_RINGS)
+    plan = clm.Plan(c["N"], nside_sht=c["N"], lmax=c["lmax"], solver="sht", legendre_prec=form)
+    plan.poisson_solve(torch.from_numpy(c["kap"]).cuda())
+    g, h = plan.shear_at_pixels_batch(0, 1, order="ring")
+    g, h = g[0].cpu().numpy()[:, pix], h[0].cpu().numpy()[:, pix]
+    plan.sync_status()
+    plan.close()
+    for k, name in enumerate(("g_t", "g_p")):
+        assert report("sht512 %s %s" % (form, name), rel(g[k], ref[name])) < tol
+    for k, name in enumerate(("U_tt", "U_pp", "U_tp")):
+        assert report("sht512 %s %s" % (form, name), rel(h[k], ref[name])) < tol

@@ -39,15 +39,16 @@ def test_default_description(L):
     assert (d.mg_vcycles, d.nu_pre, d.nu_post, d.patch_factor) == (4, 2, 2, 4)
     assert (d.mg_max_vcycles, d.mg_eps, d.adjoint) == (20, 0.1, 0)
     assert d.analysis_iters == 0
-    assert (d.mfma_ana_waves, d.mfma_syn_waves) == (0, 0)
-    assert ctypes.sizeof(d) == 80  # 14 int32, padding, a double, four int32
+    assert (d.mfma_ana_waves, d.mfma_syn_waves, d.mfma_der_waves) == (0, 0, 0)
+    assert ctypes.sizeof(d) == 88  # 14 int32, a double, five int32, padding
 
 
 @pytest.mark.parametrize("fields", [
     dict(nside_fine=100), dict(nside_sht=4096), dict(patch_cells=96), dict(nu_pre=0),
     dict(mg_vcycles=-1), dict(max_planes=0), dict(solver=7), dict(mg_prec=9),
     dict(nside_bundle=1), dict(legendre_prec=4), dict(legendre_prec=-1),
-    dict(mfma_ana_waves=4), dict(mfma_syn_waves=10), dict(lmax=(1 << 20) + 1),
+    dict(mfma_ana_waves=4), dict(mfma_syn_waves=10), dict(mfma_der_waves=16),
+    dict(lmax=(1 << 20) + 1),
     # the epsilon rule needs a positive threshold and cycle limit, and the
     # adjoint a fixed cycle count
     dict(mg_vcycles=0, mg_eps=0.0), dict(mg_vcycles=0, mg_max_vcycles=0),
@@ -82,9 +83,9 @@ def test_tune_cache_roundtrip(tmp_path, monkeypatch):
     monkeypatch.setenv("CALCLENS_MI_TUNE_CACHE", str(path))
     assert clm.tune_cache_path() == str(path)
     assert clm._tune_load() == {}
-    clm._tune_store("gpu|nside 512|lmax 1024|form 1|batch 6", 8, 16)
-    clm._tune_store("gpu|nside 2048|lmax 4096|form 3|batch 15", 16, 12)
-    assert clm._tune_load() == {"gpu|nside 512|lmax 1024|form 1|batch 6": [8, 16],
-                                "gpu|nside 2048|lmax 4096|form 3|batch 15": [16, 12]}
+    clm._tune_store("gpu|nside 512|lmax 1024|form 1|batch 6|solver 1", 8, 16, 0)
+    clm._tune_store("gpu|nside 2048|lmax 4096|form 3|batch 15|solver 0", 16, 12, 4)
+    assert clm._tune_load() == {"gpu|nside 512|lmax 1024|form 1|batch 6|solver 1": [8, 16, 0],
+                                "gpu|nside 2048|lmax 4096|form 3|batch 15|solver 0": [16, 12, 4]}
     path.write_text("not json")
     assert clm._tune_load() == {}

@@ -206,3 +206,21 @@ def test_epanechnikov_pure_sht(lmax, tol_g, tol_s):
     assert np.abs(d["g_p"]).max() < 1e-12
     g1m = 0.5 * (d["U_tt"] - d["U_pp"])
     assert np.abs(g1m[sel] - g1[sel]).max() < tol_s * np.abs(g1[sel]).max()
+
+
+def test_derivative_maps_ring_subset():
+    """derivative_maps on a subset of rings is the full computation at those
+    rings' pixels (polar caps, belt edges, equator)."""
+    N, lmax = 16, 40
+    rng = np.random.default_rng(21)
+    a = rng.standard_normal(sht.nalm(lmax)) + 1j * rng.standard_normal(sht.nalm(lmax))
+    l, m = sht.lm_arrays(lmax)
+    a[m == 0] = a[m == 0].real
+    p = sht.poisson(lmax, a)
+    full = sht.derivative_maps(N, lmax, p)
+    rings = [0, 1, 14, 15, 16, 31, 47, 48, 61, 62]
+    sub = sht.derivative_maps(N, lmax, p, rings=rings)
+    pix = sht.ring_pixels(N, rings)
+    assert pix.size == sum(min(r + 1, 4 * N - r - 1, N) * 4 for r in rings)
+    for k in full:
+        np.testing.assert_allclose(sub[k], full[k][pix], rtol=1e-13, atol=1e-13 * np.abs(full[k]).max())
