@@ -440,6 +440,32 @@ clm_status clm_galaxies_reduced(clm_plan plan, const clm_rays* rays, const doubl
                                 float* A_g_dev, hipStream_t stream);
 
 /*
+ * Full-sky power spectra of a ray state (Sec. 5): the convergence, the E-
+ * and B-modes of the shear and the rotation of eq. invmagmat,
+ *   kappa = 1 - (A11 + A22)/2, gamma_1 = (A22 - A11)/2,
+ *   gamma_2 = -(A12 + A21)/2, omega = (A12 - A21)/2,
+ * as maps on the ray grid: ray p (NESTED pixel p) gives the value at its
+ * pixel centre, its Jacobian rays->A transported there first from the
+ * ray's position rays->theta/phi (App. B).  kappa and omega are analysed
+ * as scalars; the shear by the spin-2 functions of the covariant Hessian
+ * (X = (m^2/s^2 - l(l+1)/2) lambda - (z/s) d lambda/d theta,
+ * Y = (m/s)(d lambda/d theta - (z/s) lambda)), normalised so that the
+ * shear of a potential psi (half the trace-free part of its covariant
+ * Hessian) has E_lm = N_l psi_lm / 2, N_l^2 = (l-1) l (l+1) (l+2), and
+ * B = 0; E and B are 0 for l < 2.  All in FP64 with the HEALPix quadrature
+ * weight 4 pi / N_pix.
+ * plan: an SHT-only plan (any Legendre form) whose grid is the rays' grid
+ * (rays->n = 12 nside_sht^2, nside_sht <= 2048); lmax from the plan.
+ * alm_dev: [4][n_lm] complex float64 (kappa, E, B, omega), HEALPix order;
+ * cl_dev: [4][lmax+1] float64, C_l = (|a_l0|^2 + 2 sum_{m>0} |a_lm|^2)/(2l+1).
+ * Both caller-owned.  Errors: CLM_EINVAL (pointers, ray count),
+ * CLM_EUNSUPPORTED (SHT+MG plan, or nside_sht above 2048).  Uses the
+ * plan's derivative workspace; asynchronous on `stream`.
+ */
+clm_status clm_jacobian_spectra(clm_plan plan, const clm_rays* rays, double* alm_dev,
+                                double* cl_dev, hipStream_t stream);
+
+/*
  * Multigrid convergence of the latest SHT+MG solve: per patch (bundle index
  * order) the epsilon ratio after the patch's last V-cycle and the number of
  * V-cycles it ran (device buffers of nbundle FP64 / int32 values).  The

@@ -72,6 +72,7 @@ _SIGS = {
     "clm_shear_at_pixels": (_P, _I32, _I32, _I32, _P, _P, _P),
     "clm_shear_at_pixels_batch": (_P, _I32, _I32, _I32, _I32, _P, _P, _P),
     "clm_rays_init": (_P, ctypes.POINTER(Rays), _P),
+    "clm_jacobian_spectra": (_P, ctypes.POINTER(Rays), _P, _P, _P),
     "clm_raytrace_planes": (_P, _P, _I32, ctypes.POINTER(_D), _I32, _I32, _I32, _D,
                             ctypes.POINTER(Rays), ctypes.POINTER(Galaxies), _P),
     "clm_ray_update": (_P, _I32, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays), _P),
@@ -441,6 +442,17 @@ class Plan:
     def rays_init(self, r):
         s = self._rays_struct(r)
         self._check(lib().clm_rays_init(self.h, ctypes.byref(s), _stream()), "rays_init")
+
+    def jacobian_spectra(self, rays):
+        """SHT-only plans on the rays' grid: (alm [4][n_lm] complex128,
+        cl [4][lmax+1] float64) of kappa, E, B and omega of the rays' A."""
+        nlm = (self.lmax + 1) * (self.lmax + 2) // 2
+        alm = torch.empty(4, nlm, dtype=torch.complex128, device=self.device)
+        cl = torch.empty(4, self.lmax + 1, dtype=torch.float64, device=self.device)
+        s = self._rays_struct(rays)
+        self._check(lib().clm_jacobian_spectra(self.h, ctypes.byref(s), _ptr(alm), _ptr(cl),
+                                               _stream()), "jacobian_spectra")
+        return alm, cl
 
     def raytrace_planes(self, kappa, chi, first_plane, rays, K=0.0, galaxies=None):
         k = kappa if kappa.dim() == 2 else kappa.reshape(1, -1)

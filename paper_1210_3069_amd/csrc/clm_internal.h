@@ -273,6 +273,10 @@ clm_status mfma_analysis(Plan* p, int first_slot, int P, hipStream_t s);
 clm_status mfma_synthesis(Plan* p, int first_slot, int P, hipStream_t s);
 int mfma_deriv_planes();                                 // planes per derivative synthesis
 clm_status mfma_deriv_synthesis(Plan* p, int first_slot, int P, hipStream_t s);
+clm_status jacobian_fields(Plan* p, const clm_rays* r, double* out,
+                           hipStream_t s);  // rays.hip: [4][npix_s] RING maps
+clm_status sht_jacobian_spectra(Plan* p, const clm_rays* rays, double* alm, double* cl,
+                                hipStream_t s);  // sht.hip
 clm_status sht_pixel_derivs_batch(Plan* p, int first_slot, int nplanes, int order,
                                   int out_fp64, void* grad, void* hess,
                                   hipStream_t s);  // sht.hip

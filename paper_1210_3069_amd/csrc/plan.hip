@@ -781,6 +781,15 @@ clm_status clm_shear_at_pixels_batch(clm_plan plan, int32_t first_slot, int32_t 
   return sht_pixel_derivs_batch(plan, first_slot, nplanes, order, out_fp64, grad, hess, stream);
 }
 
+clm_status clm_jacobian_spectra(clm_plan plan, const clm_rays* rays, double* alm,
+                                double* cl, hipStream_t stream) {
+  if (!plan || !rays || !alm || !cl || !rays->theta || !rays->phi || !rays->A ||
+      rays->n != plan->npix_s)
+    return CLM_EINVAL;
+  if (plan->mg) return CLM_EUNSUPPORTED;
+  return sht_jacobian_spectra(plan, rays, alm, cl, stream);
+}
+
 clm_status clm_rays_init(clm_plan plan, const clm_rays* rays, hipStream_t stream) {
   if (!plan || !rays || rays->n != plan->npix_f || !rays->theta || !rays->phi || !rays->beta ||
       !rays->A || !rays->A_prev)

@@ -72,6 +72,46 @@ __device__ __forceinline__ void basis(const double v[3], double et[3], double ep
   ep[0] = -sp; ep[1] = cp; ep[2] = 0.0;
 }
 
+// App. B: the rotation that carries unit vector n0 to n1 about n0 x n1,
+// applied to the basis (et0, ep0) at n0 and projected on the basis at n1:
+// M_kl = e_k(n1) . R e_l(n0).  A tensor transports as M X M^T.
+__device__ __forceinline__ void transport_matrix(const double n0[3], const double et0[3],
+                                                 const double ep0[3], const double n1[3],
+                                                 double M[4]) {
+  double et1[3], ep1[3];
+  basis(n1, et1, ep1);
+  double ax[3] = {n0[1] * n1[2] - n0[2] * n1[1], n0[2] * n1[0] - n0[0] * n1[2],
+                  n0[0] * n1[1] - n0[1] * n1[0]};
+  const double sn = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+  double rt[3], rp[3];
+  if (sn > 0) {
+    ax[0] /= sn; ax[1] /= sn; ax[2] /= sn;
+    // the angle between the unit vectors: cosine n0.n1, sine |n0 x n1|;
+    // 1 - cos = sin^2 / (1 + cos) without cancellation
+    const double cw = n0[0] * n1[0] + n0[1] * n1[1] + n0[2] * n1[2];
+    const double omc = sn * sn / (1.0 + cw);
+    rotate_cs(ax, cw, sn, omc, et0, rt);
+    rotate_cs(ax, cw, sn, omc, ep0, rp);
+  } else {
+    for (int k = 0; k < 3; ++k) { rt[k] = et0[k]; rp[k] = ep0[k]; }
+  }
+  M[0] = et1[0] * rt[0] + et1[1] * rt[1] + et1[2] * rt[2];
+  M[1] = et1[0] * rp[0] + et1[1] * rp[1] + et1[2] * rp[2];
+  M[2] = ep1[0] * rt[0] + ep1[1] * rt[1] + ep1[2] * rt[2];
+  M[3] = ep1[0] * rp[0] + ep1[1] * rp[1] + ep1[2] * rp[2];
+}
+
+// M X M^T of a row-major 2 x 2 tensor
+__device__ __forceinline__ void transport_tensor(const double M[4], const double X[4],
+                                                 double out[4]) {
+  const double t00 = M[0] * X[0] + M[1] * X[2], t01 = M[0] * X[1] + M[1] * X[3];
+  const double t10 = M[2] * X[0] + M[3] * X[2], t11 = M[2] * X[1] + M[3] * X[3];
+  out[0] = t00 * M[0] + t01 * M[1];
+  out[1] = t00 * M[2] + t01 * M[3];
+  out[2] = t10 * M[0] + t11 * M[1];
+  out[3] = t10 * M[2] + t11 * M[3];
+}
+
 struct RayArgs {
   PatchField P;
   int shift;
@@ -141,35 +181,12 @@ __global__ __launch_bounds__(kBlock) void k_ray_update(RayArgs a) {
     }
   // App. B: rotate the old basis along the great circle n -> n', project on
   // the new basis, A <- M A M^T for both Jacobians
-  double et1[3], ep1[3];
-  basis(nn, et1, ep1);
-  double ax[3] = {nv[1] * nn[2] - nv[2] * nn[1], nv[2] * nn[0] - nv[0] * nn[2],
-                  nv[0] * nn[1] - nv[1] * nn[0]};
-  const double sn = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
-  double rt[3], rp[3];
-  if (sn > 0) {
-    ax[0] /= sn; ax[1] /= sn; ax[2] /= sn;
-    // the angle between the unit vectors: cosine n.n', sine |n x n'|;
-    // 1 - cos = sin^2 / (1 + cos) without cancellation
-    const double cw = nv[0] * nn[0] + nv[1] * nn[1] + nv[2] * nn[2];
-    const double omc = sn * sn / (1.0 + cw);
-    rotate_cs(ax, cw, sn, omc, et, rt);
-    rotate_cs(ax, cw, sn, omc, ep, rp);
-  } else {
-    for (int k = 0; k < 3; ++k) { rt[k] = et[k]; rp[k] = ep[k]; }
-  }
-  const double M[4] = {et1[0] * rt[0] + et1[1] * rt[1] + et1[2] * rt[2],
-                       et1[0] * rp[0] + et1[1] * rp[1] + et1[2] * rp[2],
-                       ep1[0] * rt[0] + ep1[1] * rt[1] + ep1[2] * rt[2],
-                       ep1[0] * rp[0] + ep1[1] * rp[1] + ep1[2] * rp[2]};
+  double M[4];
+  transport_matrix(nv, et, ep, nn, M);
   auto transport = [&](const double X[4], float* dst) {
-    // M X M^T
-    const double t00 = M[0] * X[0] + M[1] * X[2], t01 = M[0] * X[1] + M[1] * X[3];
-    const double t10 = M[2] * X[0] + M[3] * X[2], t11 = M[2] * X[1] + M[3] * X[3];
-    dst[0 * n + i] = float(t00 * M[0] + t01 * M[1]);
-    dst[1 * n + i] = float(t00 * M[2] + t01 * M[3]);
-    dst[2 * n + i] = float(t10 * M[0] + t11 * M[1]);
-    dst[3 * n + i] = float(t10 * M[2] + t11 * M[3]);
+    double Y[4];
+    transport_tensor(M, X, Y);
+    for (int k = 0; k < 4; ++k) dst[k * n + i] = float(Y[k]);
   };
   transport(A0, a.Ap);
   transport(An, a.A);
@@ -444,8 +461,6 @@ __device__ void image_jacobian(const ImgArgs& a, const double img[3], double w, 
   int pix[4];
   double wt[4];
   hpx::interp_weights(a.rf, img[2], rho, ph, pix, wt);
-  double et1[3], ep1[3];
-  basis(img, et1, ep1);
   double S[4] = {0, 0, 0, 0}, Sp[4] = {0, 0, 0, 0};
   for (int q = 0; q < 4; ++q) {
     const int64_t r = a.r2n_f[pix[q]];
@@ -453,34 +468,15 @@ __device__ void image_jacobian(const ImgArgs& a, const double img[3], double w, 
     sincos(a.rth[r], &st, &ct);
     sincos(a.rph[r], &sp, &cp);
     const double nv[3] = {st * cp, st * sp, ct};
-    double et[3], ep[3];
+    double et[3], ep[3], M[4];
     basis(nv, et, ep);
-    double ax[3] = {nv[1] * img[2] - nv[2] * img[1], nv[2] * img[0] - nv[0] * img[2],
-                    nv[0] * img[1] - nv[1] * img[0]};
-    const double sn = sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
-    double rt[3], rp[3];
-    if (sn > 0) {
-      ax[0] /= sn; ax[1] /= sn; ax[2] /= sn;
-      const double cw = nv[0] * img[0] + nv[1] * img[1] + nv[2] * img[2];
-      const double omc = sn * sn / (1.0 + cw);
-      rotate_cs(ax, cw, sn, omc, et, rt);
-      rotate_cs(ax, cw, sn, omc, ep, rp);
-    } else {
-      for (int c = 0; c < 3; ++c) { rt[c] = et[c]; rp[c] = ep[c]; }
-    }
-    const double M[4] = {et1[0] * rt[0] + et1[1] * rt[1] + et1[2] * rt[2],
-                         et1[0] * rp[0] + et1[1] * rp[1] + et1[2] * rp[2],
-                         ep1[0] * rt[0] + ep1[1] * rt[1] + ep1[2] * rt[2],
-                         ep1[0] * rp[0] + ep1[1] * rp[1] + ep1[2] * rp[2]};
+    transport_matrix(nv, et, ep, img, M);
     auto add = [&](const float* src, double acc[4]) {
       const double X[4] = {double(src[r]), double(src[a.nray + r]), double(src[2 * a.nray + r]),
                            double(src[3 * a.nray + r])};
-      const double t00 = M[0] * X[0] + M[1] * X[2], t01 = M[0] * X[1] + M[1] * X[3];
-      const double t10 = M[2] * X[0] + M[3] * X[2], t11 = M[2] * X[1] + M[3] * X[3];
-      acc[0] += wt[q] * (t00 * M[0] + t01 * M[1]);
-      acc[1] += wt[q] * (t00 * M[2] + t01 * M[3]);
-      acc[2] += wt[q] * (t10 * M[0] + t11 * M[1]);
-      acc[3] += wt[q] * (t10 * M[2] + t11 * M[3]);
+      double T[4];
+      transport_tensor(M, X, T);
+      for (int c = 0; c < 4; ++c) acc[c] += wt[q] * T[c];
     };
     add(a.A, S);
     add(a.Ap, Sp);
@@ -548,7 +544,46 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_images(ImgArgs a) {
   a.found[i] = 1;
 }
 
+// ------------------------------------------------------ final-plane fields
+// Sec. 5: kappa, gamma_1, gamma_2, omega of eq. invmagmat on the ray grid.
+// Ray p (NESTED pixel p of the image plane) gives the value at its pixel
+// centre; its Jacobian, held in the basis at the ray's position, is
+// transported there first (App. B).  Output: RING-order maps [4][n].
+__global__ __launch_bounds__(kBlock) void k_jacobian_fields(int64_t N, int64_t n,
+                                                            const double* th, const double* ph,
+                                                            const float* A, double* out) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t r = hpx::nest2ring(N, p);
+  double z, st1, phi;
+  hpx::pix2ang_ring(N, r, z, st1, phi);
+  const double n1[3] = {st1 * cos(phi), st1 * sin(phi), z};
+  double st, ct, sp, cp;
+  sincos(th[p], &st, &ct);
+  sincos(ph[p], &sp, &cp);
+  const double n0[3] = {st * cp, st * sp, ct};
+  double et[3], ep[3], M[4], T[4];
+  basis(n0, et, ep);
+  transport_matrix(n0, et, ep, n1, M);
+  const double X[4] = {double(A[p]), double(A[n + p]), double(A[2 * n + p]),
+                       double(A[3 * n + p])};
+  transport_tensor(M, X, T);
+  out[r] = 1.0 - 0.5 * (T[0] + T[3]);
+  out[n + r] = 0.5 * (T[3] - T[0]);
+  out[2 * n + r] = -0.5 * (T[1] + T[2]);
+  out[3 * n + r] = 0.5 * (T[1] - T[2]);
+}
+
 }  // namespace
+
+clm_status jacobian_fields(Plan* p, const clm_rays* r, double* out, hipStream_t s) {
+  const int64_t n = r->n;
+  CLM_TIMED(p, s, "jacobian_fields");
+  hipLaunchKernelGGL(k_jacobian_fields, dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, int64_t(p->d.nside_sht), n, r->theta, r->phi, r->A, out);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
 
 clm_status galaxy_images(Plan* p, const double* chi, int nchi, int k, double K,
                          const clm_rays* r, const clm_galaxies* gl, double radius,

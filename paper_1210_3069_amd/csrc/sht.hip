@@ -835,6 +835,155 @@ __global__ __launch_bounds__(leg_threads_max(RPT)) void k_analysis(const double*
   }
 }
 
+// E/B analysis of a shear field (Sec. 5: full-sky E/B decomposition of the
+// final plane's shear).  With the spin-2 functions of the covariant Hessian
+// (z = cos, s = sin theta, dlambda = d lambda / d theta)
+//   X = (m^2/s^2 - l(l+1)/2) lambda - (z/s) dlambda,  Y = (m/s)(dlambda - (z/s) lambda),
+// the shear of psi = Y_lm is gamma_1 = X e^{i m phi}, gamma_2 = i Y e^{i m phi};
+// both basis fields have squared norm N_l^2/4, N_l^2 = (l-1) l (l+1) (l+2):
+//   E_lm = (2/N_l) w sum_rings [X F1 - i Y F2],  B_lm = (2/N_l) w sum_rings [X F2 + i Y F1]
+// for l >= 2 (0 below), F1, F2 the ring transforms of gamma_1, gamma_2.  On
+// the mirror ring X keeps the sign (-1)^(l+m) of lambda and Y takes the
+// opposite one.  One workgroup per m; four l per wave reduction.
+template <int RPT>
+__global__ __launch_bounds__(leg_threads_max(RPT)) void k_analysis_spin2(
+    const double* F1, const double* F2, const double* rt, const double* lam_mant,
+    const int* lam_scale, int H, int nring, int lmax, double w, double* E, double* B) {
+  extern __shared__ double sm[];
+  const int m = blockIdx.x;
+  const int nl = lmax - m + 1;
+  double* a = sm;                 // [nl]
+  double* b = sm + nl;            // [nl]
+  double* kc = sm + 2 * nl;       // [nl] k_l = sqrt((2l+1)(l^2-m^2)/(2l-1))
+  double* part = sm + 3 * nl;     // [64][waves][4]
+  const int nw = blockDim.x >> 6;
+  recur_coeffs(m, lmax, a, b);
+  for (int dl = threadIdx.x; dl < nl; dl += blockDim.x) {
+    const double L = m + dl, M = m;
+    kc[dl] = sqrt((2.0 * L + 1.0) * (L * L - M * M) / fmax(2.0 * L - 1.0, 1.0));
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double M = m;
+  // per ring: z, 1/s, and F1, F2 folded with the mirror ring (+: sum, -: difference)
+  double z[RPT], is[RPT], f1p[RPT][2], f1m[RPT][2], f2p[RPT][2], f2m[RPT][2];
+  Recur st[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int q = threadIdx.x + k * blockDim.x;
+    if (q < H) {
+      z[k] = rt[4 * q];
+      is[k] = 1.0 / rt[4 * q + 1];
+      const int qm = nring - 1 - q;
+      const double* a1 = F1 + (size_t(q) * (lmax + 1) + m) * 2;
+      const double* b1 = F1 + (size_t(qm) * (lmax + 1) + m) * 2;
+      const double* a2 = F2 + (size_t(q) * (lmax + 1) + m) * 2;
+      const double* b2 = F2 + (size_t(qm) * (lmax + 1) + m) * 2;
+      for (int c = 0; c < 2; ++c) {
+        if (qm != q) {
+          f1p[k][c] = a1[c] + b1[c]; f1m[k][c] = a1[c] - b1[c];
+          f2p[k][c] = a2[c] + b2[c]; f2m[k][c] = a2[c] - b2[c];
+        } else {
+          f1p[k][c] = f1m[k][c] = a1[c];
+          f2p[k][c] = f2m[k][c] = a2[c];
+        }
+      }
+      st[k].p1 = lam_mant[size_t(m) * H + q];
+      st[k].p2 = 0.0;
+      st[k].s = lam_scale[size_t(m) * H + q];
+    } else {
+      z[k] = 0.0; is[k] = 0.0;
+      for (int c = 0; c < 2; ++c) f1p[k][c] = f1m[k][c] = f2p[k][c] = f2m[k][c] = 0.0;
+      st[k].p1 = st[k].p2 = 0.0; st[k].s = -1;
+    }
+  }
+  __syncthreads();
+  for (int l0 = 0; l0 < nl; l0 += 64) {
+    const int cnt = nl - l0 < 64 ? nl - l0 : 64;
+    for (int c0 = 0; c0 < cnt; c0 += 4) {
+      double acc[16];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int dl = l0 + c0 + cc;  // l - m
+        double er = 0.0, ei = 0.0, br = 0.0, bi = 0.0;
+        if (c0 + cc < cnt) {
+          const double L = M + dl, kl = kc[dl], hl = 0.5 * L * (L + 1.0);
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) {
+            const double prev = dl == 0 ? 0.0 : recur_value(st[k]);  // lambda_{l-1}
+            if (dl == 1) {
+              st[k].p2 = st[k].p1;
+              st[k].p1 = sqrt(2.0 * m + 3.0) * z[k] * st[k].p2;
+            } else if (dl >= 2) {
+              recur_step(st[k], z[k], a[dl], b[dl]);
+            }
+            const double v = recur_value(st[k]);
+            const double zs = z[k] * is[k], ms = M * is[k];
+            const double t = (L * z[k] * v - kl * prev) * is[k];
+            const double X = (ms * ms - hl) * v - zs * t;
+            const double Y = ms * (t - zs * v);
+            const double* fx1 = (dl & 1) ? f1m[k] : f1p[k];   // X: parity of lambda
+            const double* fx2 = (dl & 1) ? f2m[k] : f2p[k];
+            const double* fy1 = (dl & 1) ? f1p[k] : f1m[k];   // Y: the opposite
+            const double* fy2 = (dl & 1) ? f2p[k] : f2m[k];
+            er += X * fx1[0] + Y * fy2[1];
+            ei += X * fx1[1] - Y * fy2[0];
+            br += X * fx2[0] - Y * fy1[1];
+            bi += X * fx2[1] + Y * fy1[0];
+          }
+        }
+        acc[4 * cc] = er;
+        acc[4 * cc + 1] = ei;
+        acc[4 * cc + 2] = br;
+        acc[4 * cc + 3] = bi;
+      }
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) recur_rescale(st[k]);
+      const double tot = wave_sum16(acc);
+      const int idx = lane >> 2;  // 4 cc + (E re, E im, B re, B im)
+      const int c = c0 + (idx >> 2);
+      if ((lane & 3) == 0 && c < cnt) part[(c * nw + wv) * 4 + (idx & 3)] = tot;
+    }
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+      const int c = threadIdx.x;
+      double v4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int v = 0; v < nw; ++v)
+        for (int j = 0; j < 4; ++j) v4[j] += part[(c * nw + v) * 4 + j];
+      const double L = m + l0 + c;
+      const double n2 = (L - 1.0) * L * (L + 1.0) * (L + 2.0);
+      const double f = L >= 2.0 ? 2.0 * w / sqrt(n2) : 0.0;
+      const size_t idx = size_t(m) * (2 * lmax + 1 - m) / 2 + (m + l0 + c);
+      E[2 * idx] = f * v4[0];
+      E[2 * idx + 1] = f * v4[1];
+      B[2 * idx] = f * v4[2];
+      B[2 * idx + 1] = f * v4[3];
+    }
+    __syncthreads();
+  }
+}
+
+// C_l = (|a_l0|^2 + 2 sum_{m>0} |a_lm|^2) / (2l + 1) of nf coefficient sets
+// [nf][n_lm] complex into cl [nf][lmax+1]; one workgroup per (l, set), a
+// fixed-order tree sum.
+__global__ void k_spectrum(const double* alm, int64_t nalm, int lmax, double* cl) {
+  __shared__ double red[256];
+  const int l = blockIdx.x, f = blockIdx.y;
+  const double* a = alm + size_t(f) * nalm * 2;
+  double acc = 0.0;
+  for (int m = threadIdx.x; m <= l; m += blockDim.x) {
+    const size_t idx = size_t(m) * (2 * lmax + 1 - m) / 2 + l;
+    const double p = a[2 * idx] * a[2 * idx] + a[2 * idx + 1] * a[2 * idx + 1];
+    acc += m == 0 ? p : 2.0 * p;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cl[size_t(f) * (lmax + 1) + l] = red[0] / (2.0 * l + 1.0);
+}
+
 // psi_lm = -2 kappa_lm / (l (l+1)), psi_00 = 0
 __global__ void k_poisson(double* alm, int lmax) {
   const int m = blockIdx.x;
@@ -1413,6 +1562,63 @@ clm_status sht_pixel_derivs_batch(Plan* p, int first_slot, int nplanes, int orde
     }
     CLM_LAUNCH_CHECK();
   }
+  return CLM_OK;
+}
+
+// kappa, E, B, omega coefficients [4][n_lm] and spectra [4][lmax+1] of a
+// ray state's final Jacobians on the plan's grid (Sec. 5).
+clm_status sht_jacobian_spectra(Plan* p, const clm_rays* rays, double* alm, double* cl,
+                                hipStream_t s) {
+  if (p->H > 4 * leg_threads_max(4))
+    return fail(p, CLM_EUNSUPPORTED, "spectra: at most 4096 north rings (Nside 2048)");
+  const size_t npix = size_t(p->npix_s);
+  clm_status st = jacobian_fields(p, rays, p->deriv, s);
+  if (st != CLM_OK) return st;
+  const int lmax = p->d.lmax;
+  const size_t na = size_t(p->nalm) * 2;
+  const int rpt = rpt_for(p->H, lmax);
+  auto spin0 = [&](const double* map, double* out) -> clm_status {
+    clm_status e = ring_forward(p, map, p->F, s);
+    return e != CLM_OK ? e : analysis(p, out, s);
+  };
+  if ((st = spin0(p->deriv, alm)) != CLM_OK) return st;                       // kappa
+  if ((st = spin0(p->deriv + 3 * npix, alm + 3 * na)) != CLM_OK) return st;  // omega
+  if ((st = ring_forward(p, p->deriv + npix, p->F, s)) != CLM_OK) return st;
+  if ((st = ring_forward(p, p->deriv + 2 * npix, p->G, s)) != CLM_OK) return st;
+  {
+    const int r2 = rpt < 4 ? rpt : 4;
+    const int nt = std::min(leg_threads_max(r2), round64((p->H + r2 - 1) / r2));
+    const size_t shm = (3 * size_t(lmax + 1) + 64 * size_t(nt / 64) * 4) * sizeof(double);
+    const double w = 4.0 * kPi / double(p->npix_s);
+    CLM_TIMED(p, s, "spin2_analysis");
+    switch (r2) {
+      case 1:
+        if (allow_lds(p, k_analysis_spin2<1>, shm) != CLM_OK) return CLM_EHIP;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_spin2<1>), dim3(lmax + 1), dim3(nt), shm,
+                           s, p->F, p->G, p->ring_s, p->lam_mant, p->lam_scale, p->H,
+                           p->nring_s, lmax, w, alm + na, alm + 2 * na);
+        break;
+      case 2:
+        if (allow_lds(p, k_analysis_spin2<2>, shm) != CLM_OK) return CLM_EHIP;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_spin2<2>), dim3(lmax + 1), dim3(nt), shm,
+                           s, p->F, p->G, p->ring_s, p->lam_mant, p->lam_scale, p->H,
+                           p->nring_s, lmax, w, alm + na, alm + 2 * na);
+        break;
+      default:
+        if (allow_lds(p, k_analysis_spin2<4>, shm) != CLM_OK) return CLM_EHIP;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_analysis_spin2<4>), dim3(lmax + 1), dim3(nt), shm,
+                           s, p->F, p->G, p->ring_s, p->lam_mant, p->lam_scale, p->H,
+                           p->nring_s, lmax, w, alm + na, alm + 2 * na);
+        break;
+    }
+  }
+  CLM_LAUNCH_CHECK();
+  {
+    CLM_TIMED(p, s, "spectra");
+    hipLaunchKernelGGL(k_spectrum, dim3(lmax + 1, 4), dim3(256), 0, s, alm, int64_t(p->nalm),
+                       lmax, cl);
+  }
+  CLM_LAUNCH_CHECK();
   return CLM_OK;
 }
 
