@@ -16,7 +16,12 @@ Readings:
   mass, matching the sign of eq. disclighttraj in the small-angle limit);
 * the first plane lenses: beta^(-1) = n^(0), chi_{-1} = 0;
 * the K < 0 branch of r(chi) is the standard sinh((-K)^{1/2} chi)/(-K)^{1/2};
-* both indices of A are transported; U^(m) is evaluated at x^(m)/|x^(m)|.
+* both indices of A are transported; U^(m) is evaluated at x^(m)/|x^(m)|;
+* pure-SHT planes give their gradient and Hessian at the pixel centres of
+  the ray grid; at a ray they are the four-point HEALPix interpolation of
+  those values, each transported from its pixel centre to the ray (App. B),
+  as the Jacobians at galaxy images are (Sec. 3.3).  The paper does not say
+  how its pure-SHT solver reaches rays that have left the pixel centres.
 """
 import numpy as np
 
@@ -150,3 +155,24 @@ def galaxy_weight(chi, k, chi_g, K=0.0):
     w = D_k D_{k-1,g} / (D_g D_{k-1,k})."""
     D = lambda a, b: float(r_of_chi(b - a, K))
     return (D(0, chi[k]) * D(chi[k - 1], chi_g)) / (D(0, chi_g) * D(chi[k - 1], chi[k]))
+
+
+def pixel_field_at(nside, g_ring, U_ring, n):
+    """Gradient and covariant Hessian of a pure-SHT plane at unit vector n
+    from their values at the RING pixel centres (g_ring [2][npix]: g_t, g_p;
+    U_ring [3][npix]: U_tt, U_pp, U_tp): four-point HEALPix interpolation of
+    the values transported from each pixel centre to n (App. B).  Returns
+    (g [2], U [2][2]) in the basis at n."""
+    th, ph = hp.vec2ang(n)
+    pix, wt = hp.interp_weights(nside, np.array([th]), np.array([ph]))
+    zc, pc, sc = hp.pix2ang_ring(nside, pix[:, 0])
+    g = np.zeros(2)
+    U = np.zeros((2, 2))
+    for c in range(4):
+        p = pix[c, 0]
+        M = transport_matrix(hp.vec(zc[c], pc[c], sc[c]), n)
+        gq = np.array([g_ring[0, p], g_ring[1, p]])
+        Uq = np.array([[U_ring[0, p], U_ring[2, p]], [U_ring[2, p], U_ring[1, p]]])
+        g += wt[c, 0] * (M @ gq)
+        U += wt[c, 0] * (M @ Uq @ M.T)
+    return g, U

@@ -137,3 +137,64 @@ def test_ray_step_matches_recurrence_for_tiny_deflections():
     ref = rays.jacobian_recurrence(chi, Us)
     assert np.allclose(r.A, ref[-1], atol=1e-14)
     assert np.allclose(r.A_prev, ref[-2], atol=1e-14)
+
+
+def closed_form_fields(nside, which):
+    """Gradient and covariant Hessian of psi = z = cos(theta) or
+    psi = x = sin(theta) cos(phi) at the RING pixel centres, by hand: for
+    l = 1 the covariant Hessian is -psi times the metric."""
+    z, ph, s = hp.pix2ang_ring(nside, np.arange(12 * nside * nside))
+    if which == "z":
+        psi, g = z, np.stack([-s, 0.0 * s])
+    else:
+        psi, g = s * np.cos(ph), np.stack([z * np.cos(ph), -np.sin(ph)])
+    return g, np.stack([-psi, -psi, 0.0 * psi])
+
+
+def exact_at(which, n):
+    th, ph = hp.vec2ang(n)
+    z, s = np.cos(th), np.sin(th)
+    if which == "z":
+        psi, g = z, np.array([-s, 0.0])
+    else:
+        psi, g = s * np.cos(ph), np.array([z * np.cos(ph), -np.sin(ph)])
+    return g, -psi * np.eye(2)
+
+
+def test_pixel_field_at_pixel_centres_is_exact():
+    N = 8
+    g, U = closed_form_fields(N, "x")
+    for p in (0, 3, 100, 383, 767):
+        z, ph, s = hp.pix2ang_ring(N, np.array([p]))
+        gi, Ui = rays.pixel_field_at(N, g, U, hp.vec(z[0], ph[0], s[0]))
+        np.testing.assert_allclose(gi, g[:, p], atol=1e-14)
+        np.testing.assert_allclose(Ui, [[U[0, p], U[2, p]], [U[2, p], U[1, p]]], atol=1e-14)
+
+
+@pytest.mark.parametrize("which", ["z", "x"])
+def test_pixel_field_at_converges_with_transport(which):
+    """Off-centre points: the interpolation error of the closed-form fields
+    falls as Nside^-2 away from the poles (at least 3x per doubling) and at
+    least as Nside^-1 inside the polar caps above the first ring, where the
+    public package's scheme bilinearly joins four pixels 90 degrees apart
+    through a virtual pole (at least 1.8x per doubling).  psi = x has a
+    gradient whose (theta-hat, phi-hat) components turn with phi, at an
+    O(1) rate near the poles, so an interpolation of the components without
+    the transport would not converge there."""
+    rng = np.random.default_rng(3)
+    mid = hp.vec(rng.uniform(-0.9, 0.9, 40), rng.uniform(0, 2 * np.pi, 40))
+    zc = np.concatenate([rng.uniform(0.995, 0.99999, 20), -rng.uniform(0.995, 0.99999, 20)])
+    cap = hp.vec(zc, rng.uniform(0, 2 * np.pi, zc.size))
+    errs = {"mid": [], "cap": []}
+    for N in (16, 32, 64):
+        g, U = closed_form_fields(N, which)
+        for name, pts in (("mid", mid), ("cap", cap)):
+            e = 0.0
+            for n in pts:
+                gi, Ui = rays.pixel_field_at(N, g, U, n)
+                ge, Ue = exact_at(which, n)
+                e = max(e, np.abs(gi - ge).max(), np.abs(Ui - Ue).max())
+            errs[name].append(e)
+    m, c = errs["mid"], errs["cap"]
+    assert m[1] < m[0] / 3 and m[2] < m[1] / 3 and m[2] < 2e-4, errs
+    assert c[1] < c[0] / 1.8 and c[2] < c[1] / 1.8 and c[2] < 5e-3, errs
