@@ -348,12 +348,19 @@ clm_status clm_rays_init(clm_plan plan, const clm_rays* rays, hipStream_t stream
 
 /*
  * Propagate rays through lens planes first_plane .. first_plane+nplanes-1
- * (SHT+MG solver).  kappa_dev: [nplanes][12 nside_fine^2] (RING) of those
+ * (both solvers).  kappa_dev: [nplanes][12 nside_fine^2] (RING) of those
  * planes.  chi_host: [nchi] comoving distances of all planes of the run,
  * chi_0 .. chi_{N-1}, followed by the final target chi_N (nchi = N + 1);
  * curvature_K in the inverse square of the same unit.  For each plane m the
- * call solves the plane (slot 0), then for every ray:
- *   g, U at n^(m) from the ray's bundle patch; d = -(g_t theta-hat + g_p phi-hat);
+ * call solves the plane, then for every ray:
+ *   g, U at n^(m): SHT+MG, from the ray's bundle patch (slot 0 holds the
+ *   plane); pure SHT, the HEALPix four-point interpolation of the gradient
+ *   and covariant Hessian at the pixel centres (clm_shear_at_pixels_batch's
+ *   fields), each transported from its pixel centre to the ray (App. B).
+ *   A pure-SHT plan solves up to 8 planes at once into slots 0 .. 7 (one
+ *   matrix-core derivative synthesis; FP64 plans: one plane in slot 0) and
+ *   keeps psi_lm only (no psi maps);
+ *   d = -(g_t theta-hat + g_p phi-hat);
  *   beta <- R(n x d/|d|, |d|) beta (eq. betaprop, read so that rays bend
  *   toward mass, as eq. disclighttraj requires);
  *   x <- x + lambda beta with |x + lambda beta| = chi_{m+1} (eq. posprop);
@@ -373,7 +380,8 @@ clm_status clm_raytrace_planes(clm_plan plan, const void* kappa_dev, int32_t kap
 /*
  * One ray update through an already solved slot (the per-plane step of
  * clm_raytrace_planes without the solve and without galaxies): plane index
- * m, distances chi_host as above.
+ * m, distances chi_host as above.  A pure-SHT plan first synthesises the
+ * slot's derivative fields at the pixel centres (one plane).
  */
 clm_status clm_ray_update(clm_plan plan, int32_t slot, const double* chi_host, int32_t nchi,
                           int32_t m, double curvature_K, const clm_rays* rays,

@@ -241,13 +241,17 @@ __global__ void k_lambda_mm(const double* rt, int H, int lmax, double* mant, int
 
 // ---- stage launchers (each returns CLM_OK or an error recorded in p->err)
 clm_status build_tables(Plan* p);                       // plan.hip
+// psi_map = false: stop at psi_lm (the pure-SHT ray tracing, which needs
+// only the derivative fields)
 clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot,
-                     hipStream_t s);                    // sht.hip
+                     hipStream_t s, bool psi_map = true);  // sht.hip
 clm_status plane_mean(Plan* p, const void* kappa, int kappa_fp64,
                       hipStream_t s);                   // sht.hip: red[1023] = mean
 clm_status ring_plan(Plan* p);                          // sht.hip
 clm_status sht_solve_batch(Plan* p, const void* kappa, int kappa_fp64, int first_slot,
-                           int nplanes, hipStream_t s);  // sht.hip
+                           int nplanes, hipStream_t s, bool psi_map = true);  // sht.hip
+clm_status sht_plane_fields(Plan* p, int slot, hipStream_t s);  // sht.hip: into p->deriv
+clm_status sht_batch_fields(Plan* p, int k, hipStream_t s);     // sht.hip: into p->deriv
 clm_status sht_adjoint(Plan* p, const double* psibar, double* alm, double* ksbar,
                        hipStream_t s);                   // sht.hip
 clm_status shear_adjoint(Plan* p, const double* th, const double* ph, int64_t npts,

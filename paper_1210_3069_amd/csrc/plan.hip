@@ -803,8 +803,9 @@ clm_status clm_ray_update(clm_plan plan, int32_t slot, const double* chi, int32_
   if (!plan || !rays || !chi || rays->n != plan->npix_f || slot < 0 ||
       slot >= plan->d.max_planes || m < 0 || m + 1 >= nchi)
     return CLM_EINVAL;
-  if (!plan->mg) return CLM_EUNSUPPORTED;
-  const clm_status s = ray_update(plan, slot, chi, nchi, m, K, rays, stream);
+  clm_status s = CLM_OK;
+  if (!plan->mg && (s = sht_plane_fields(plan, slot, stream)) != CLM_OK) return s;
+  s = ray_update(plan, slot, chi, nchi, m, K, rays, stream);
   if (s == CLM_OK) {
     plan->ray_chi.assign(chi, chi + nchi);
     plan->ray_K = K;
@@ -868,7 +869,6 @@ clm_status clm_raytrace_planes(clm_plan plan, const void* kappa, int32_t kappa_i
   if (!plan || !kappa || !chi || !rays || rays->n != plan->npix_f || first_plane < 0 ||
       nplanes < 1 || first_plane + nplanes + 1 > nchi)
     return CLM_EINVAL;
-  if (!plan->mg) return CLM_EUNSUPPORTED;
   if (gal && (gal->n < 0 || (gal->n > 0 && (!gal->theta || !gal->phi || !gal->chi || !gal->A))))
     return CLM_EINVAL;
   for (int k = 1; k < nchi; ++k)
@@ -881,17 +881,45 @@ clm_status clm_raytrace_planes(clm_plan plan, const void* kappa, int32_t kappa_i
     s = galaxies_shell(p, chi, nchi, 0, K, rays, gal, stream);
     if (s != CLM_OK) return s;
   }
-  for (int k = 0; k < nplanes; ++k) {
-    const int m = first_plane + k;
-    const char* kp = static_cast<const char*>(kappa) + size_t(k) * p->npix_f * esz;
-    if ((s = sht_solve(p, kp, kappa_is_fp64, 0, stream)) != CLM_OK) return s;
-    if ((s = mg_solve(p, kp, kappa_is_fp64, 0, stream)) != CLM_OK) return s;
-    if ((s = ray_update(p, 0, chi, nchi, m, K, rays, stream)) != CLM_OK) return s;
+  // one plane after the other: its rays, then the galaxies of the shell
+  // the rays have just reached
+  auto advance = [&](int slot, int m) -> clm_status {
+    clm_status e = ray_update(p, slot, chi, nchi, m, K, rays, stream);
+    if (e != CLM_OK) return e;
     p->ray_chi.assign(chi, chi + nchi);
     p->ray_K = K;
     p->ray_plane = m;
-    if (gal && gal->n > 0) {
-      if ((s = galaxies_shell(p, chi, nchi, m + 1, K, rays, gal, stream)) != CLM_OK) return s;
+    if (gal && gal->n > 0) return galaxies_shell(p, chi, nchi, m + 1, K, rays, gal, stream);
+    return CLM_OK;
+  };
+  if (p->mg) {
+    for (int k = 0; k < nplanes; ++k) {
+      const char* kp = static_cast<const char*>(kappa) + size_t(k) * p->npix_f * esz;
+      if ((s = sht_solve(p, kp, kappa_is_fp64, 0, stream)) != CLM_OK) return s;
+      if ((s = mg_solve(p, kp, kappa_is_fp64, 0, stream)) != CLM_OK) return s;
+      if ((s = advance(0, first_plane + k)) != CLM_OK) return s;
+    }
+    return CLM_OK;
+  }
+  // pure-SHT planes: psi_lm of a batch of planes (slots 0 ..), no psi maps;
+  // the derivative fields of the batch in one matrix-core launch (FP64
+  // plans: plane by plane); per plane the fields at the pixel centres, then
+  // its rays
+  const int dp = p->batch > 0 ? std::min(p->batch, mfma_deriv_planes()) : 1;
+  for (int k0 = 0; k0 < nplanes; k0 += dp) {
+    const int nb = std::min(dp, nplanes - k0);
+    const char* kp = static_cast<const char*>(kappa) + size_t(k0) * p->npix_f * esz;
+    if (p->batch > 0) {
+      if ((s = sht_solve_batch(p, kp, kappa_is_fp64, 0, nb, stream, false)) != CLM_OK) return s;
+      if ((s = mfma_deriv_synthesis(p, 0, nb, stream)) != CLM_OK) return s;
+      for (int k = 0; k < nb; ++k) {
+        if ((s = sht_batch_fields(p, k, stream)) != CLM_OK) return s;
+        if ((s = advance(k, first_plane + k0 + k)) != CLM_OK) return s;
+      }
+    } else {
+      if ((s = sht_solve(p, kp, kappa_is_fp64, 0, stream, false)) != CLM_OK) return s;
+      if ((s = sht_plane_fields(p, 0, stream)) != CLM_OK) return s;
+      if ((s = advance(0, first_plane + k0)) != CLM_OK) return s;
     }
   }
   return CLM_OK;

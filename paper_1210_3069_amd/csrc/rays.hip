@@ -114,6 +114,9 @@ __device__ __forceinline__ void transport_tensor(const double M[4], const double
 
 struct RayArgs {
   PatchField P;
+  const double* D;   // pure-SHT planes: [5][n] g_t, g_p, U_tt, U_pp, U_tp at the RING
+                     // pixel centres of the ray grid
+  hpx::Rings rf;     // ... and that grid's ring tables
   int shift;
   int64_t n;
   double chi_m, chi_m1;  // chi_m, chi_{m+1}
@@ -126,7 +129,40 @@ struct RayArgs {
   int* status;
 };
 
-template <typename T>
+// Pure-SHT planes: g and U (U_tt, U_pp, U_tp) at the ray nv (cos theta ct,
+// sin theta st, phi in [0, 2 pi)) from the fields at the pixel centres: the
+// four-point HEALPix interpolation of the values transported from each
+// pixel centre to the ray (App. B), as for the Jacobians at galaxy images.
+__device__ __forceinline__ void pixel_field(const RayArgs& a, const double nv[3], double ct,
+                                            double st, double ph, double g[2], double U[3]) {
+  int pix[4];
+  double wt[4];
+  hpx::interp_weights(a.rf, ct, st, ph, pix, wt);
+  const int64_t n = a.n;
+  g[0] = g[1] = 0.0;
+  U[0] = U[1] = U[2] = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r = pix[q];
+    double zq, sq, pq;
+    hpx::pix2ang_ring(a.rf.N, r, zq, sq, pq);
+    const double nq[3] = {sq * cos(pq), sq * sin(pq), zq};
+    double et[3], ep[3], M[4], T[4];
+    basis(nq, et, ep);
+    transport_matrix(nq, et, ep, nv, M);
+    const double g0 = a.D[r], g1 = a.D[n + r];
+    const double X[4] = {a.D[2 * n + r], a.D[4 * n + r], a.D[4 * n + r], a.D[3 * n + r]};
+    transport_tensor(M, X, T);
+    g[0] += wt[q] * (M[0] * g0 + M[1] * g1);
+    g[1] += wt[q] * (M[2] * g0 + M[3] * g1);
+    U[0] += wt[q] * T[0];
+    U[1] += wt[q] * T[3];
+    U[2] += wt[q] * T[1];
+  }
+}
+
+// SHT: the plane is a pure-SHT plane (fields at the pixel centres, a.D);
+// else an SHT+MG plane (patches of multigrid precision T).
+template <typename T, bool SHT>
 __global__ __launch_bounds__(kBlock) void k_ray_update(RayArgs a) {
   // the rays of one bundle (a NESTED range) stay on one XCD
   const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
@@ -137,7 +173,9 @@ __global__ __launch_bounds__(kBlock) void k_ray_update(RayArgs a) {
   sincos(a.ph[i], &sp, &cp);
   const double nv[3] = {st * cp, st * sp, ct};
   double g[2], U[3];
-  if (!eval_patch<T>(a.P, i >> a.shift, nv[0], nv[1], nv[2], g, U)) {
+  if constexpr (SHT) {
+    pixel_field(a, nv, ct, st, a.ph[i], g, U);
+  } else if (!eval_patch<T>(a.P, i >> a.shift, nv[0], nv[1], nv[2], g, U)) {
     atomicOr(a.status, ST_LEFT_PATCH);
     for (int k = 0; k < 4; ++k) a.A[k * n + i] = NAN;
     return;
@@ -638,9 +676,15 @@ static double r_host(double x, double K) {
 clm_status ray_update(Plan* p, int slot, const double* chi, int nchi, int m, double K,
                       const clm_rays* r, hipStream_t s) {
   (void)nchi;
-  RayArgs a;
-  a.P = PatchField{p->rot, p->slots[slot].u0, p->slots[slot].du, p->n, p->L, p->delta};
-  a.shift = p->bundle_shift;
+  RayArgs a{};
+  if (p->mg) {
+    a.P = PatchField{p->rot, p->slots[slot].u0, p->slots[slot].du, p->n, p->L, p->delta};
+    a.shift = p->bundle_shift;
+  } else {
+    // the plane's fields at the pixel centres are in p->deriv
+    a.D = p->deriv;
+    a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->ringx_f, p->nring_f, p->d.nside_fine};
+  }
   a.n = r->n;
   a.chi_m = chi[m];
   a.chi_m1 = chi[m + 1];
@@ -658,10 +702,12 @@ clm_status ray_update(Plan* p, int slot, const double* chi, int nchi, int m, dou
   a.status = p->status_dev;
   const dim3 g((r->n + kBlock - 1) / kBlock);
   CLM_TIMED(p, s, "ray_update");
-  if (p->fp64mg)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ray_update<double>), g, dim3(kBlock), 0, s, a);
+  if (!p->mg)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ray_update<double, true>), g, dim3(kBlock), 0, s, a);
+  else if (p->fp64mg)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ray_update<double, false>), g, dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ray_update<float>), g, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ray_update<float, false>), g, dim3(kBlock), 0, s, a);
   CLM_LAUNCH_CHECK();
   return CLM_OK;
 }

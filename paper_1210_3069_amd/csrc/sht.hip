@@ -1334,7 +1334,8 @@ __global__ void k_add_to(int64_t n, const double* x, double* y) {
 
 }  // namespace
 
-clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
+clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s,
+                     bool psi_map) {
   clm_status st = sht_front(p, kappa, kappa_fp64, p->F, s);
   if (st != CLM_OK) return st;
   double* alm = p->slots[slot].alm;
@@ -1361,6 +1362,7 @@ clm_status sht_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipSt
     CLM_LAUNCH_CHECK();
   }
   if ((st = poisson(p, alm, s)) != CLM_OK) return st;
+  if (!psi_map) return CLM_OK;
   if ((st = synthesis(p, alm, s)) != CLM_OK) return st;
   return ring_inverse(p, p->G, 1, p->slots[slot].psi_s, s);
 }
@@ -1390,7 +1392,7 @@ clm_status sht_adjoint(Plan* p, const double* psibar, double* alm, double* ksbar
 }
 
 clm_status sht_solve_batch(Plan* p, const void* kappa, int kappa_fp64, int first_slot,
-                           int nplanes, hipStream_t s) {
+                           int nplanes, hipStream_t s, bool psi_map) {
   if (nplanes < 1 || nplanes > p->batch) return fail(p, CLM_EINVAL, "batch size");
   const size_t nF = size_t(p->nring_s) * (p->d.lmax + 1) * 2;
   const size_t esz = kappa_fp64 ? 8 : 4;
@@ -1402,6 +1404,7 @@ clm_status sht_solve_batch(Plan* p, const void* kappa, int kappa_fp64, int first
   if ((st = mfma_analysis(p, first_slot, nplanes, s)) != CLM_OK) return st;
   for (int k = 0; k < nplanes; ++k)
     if ((st = poisson(p, p->slots[first_slot + k].alm, s)) != CLM_OK) return st;
+  if (!psi_map) return CLM_OK;
   if ((st = mfma_synthesis(p, first_slot, nplanes, s)) != CLM_OK) return st;
   for (int k = 0; k < nplanes; ++k)
     if ((st = ring_inverse(p, p->Gb + k * nF, 1, p->slots[first_slot + k].psi_s, s)) != CLM_OK)
@@ -1462,8 +1465,9 @@ clm_status sht_solve_multi(Plan* const* ps, int n, const void* const* kappa,
   return CLM_OK;
 }
 
-clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* grad, void* hess,
-                            hipStream_t s) {
+// The raw partials psi_t, psi_p, psi_tt, psi_pp, psi_tp of slot `slot` at
+// the RING pixel centres into p->deriv (FP64 synthesis).
+clm_status fp64_raw_derivs(Plan* p, int slot, hipStream_t s) {
   // theta sums G, G_t, G_tt into fields 0..2 of G ([field][ring][m]); G is
   // sized for five fields in SHT-only plans
   const int lmax = p->d.lmax;
@@ -1489,7 +1493,12 @@ clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* gr
                        p->nring_s, lmax, p->G);
   }
   CLM_LAUNCH_CHECK();
-  clm_status st = ring_inverse(p, p->G, 5, p->deriv, s);
+  return ring_inverse(p, p->G, 5, p->deriv, s);
+}
+
+clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* grad, void* hess,
+                            hipStream_t s) {
+  clm_status st = fp64_raw_derivs(p, slot, s);
   if (st != CLM_OK) return st;
   const dim3 g((p->npix_s + kBlock - 1) / kBlock);
   CLM_TIMED(p, s, "sht_covariant");
@@ -1503,6 +1512,34 @@ clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64, void* gr
                        static_cast<float*>(grad), static_cast<float*>(hess));
   CLM_LAUNCH_CHECK();
   return CLM_OK;
+}
+
+// The gradient and covariant Hessian of slot `slot` at the RING pixel
+// centres, FP64, into p->deriv [5][npix] (g_t, g_p, U_tt, U_pp, U_tp): the
+// fields a ray update through a pure-SHT plane interpolates.  In matrix-core
+// plans the derivative synthesis of the slot (one plane); FP64 plans take the
+// raw partials and make them covariant in place (each thread reads its five
+// values before writing them).
+clm_status sht_plane_fields(Plan* p, int slot, hipStream_t s) {
+  clm_status st;
+  if (p->batch > 0) {
+    if ((st = mfma_deriv_synthesis(p, slot, 1, s)) != CLM_OK) return st;
+    return ring_inverse(p, p->Gb, 5, p->deriv, s);
+  }
+  if ((st = fp64_raw_derivs(p, slot, s)) != CLM_OK) return st;
+  const dim3 g((p->npix_s + kBlock - 1) / kBlock);
+  CLM_TIMED(p, s, "sht_covariant");
+  hipLaunchKernelGGL(k_covariant<double>, g, dim3(kBlock), 0, s, p->deriv, p->npix_s, p->ring_s,
+                     p->ringi_s, p->nring_s, p->r2n_s, 0, p->deriv, p->deriv + 2 * p->npix_s);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+// Fields of plane k of the latest derivative synthesis batch (Gb) into
+// p->deriv.
+clm_status sht_batch_fields(Plan* p, int k, hipStream_t s) {
+  const size_t nF = size_t(p->nring_s) * (p->d.lmax + 1) * 2;
+  return ring_inverse(p, p->Gb + 5 * k * nF, 5, p->deriv, s);
 }
 
 // The five derivative maps [5][npix] (g_t, g_p, U_tt, U_pp, U_tp, RING) to
