@@ -418,6 +418,40 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
 MFMA_PRODUCTS = {"fp32": 1, "bf16x3": 3, "bf16x6": 6}
 
 
+def jacobian_spectra_summary(clm, torch, rays, nside, lmax):
+    """Sec. 5 on the final plane of a ray tracing run: full-sky spectra of
+    kappa, the shear E- and B-modes and the rotation omega of the rays'
+    Jacobians (an FP64 SHT plan on the ray grid), the time of the call, and
+    band averages of C_EE / C_kk (divided by (l-1)(l+2)/(l(l+1)), 1 for a
+    Born-level shear), C_BB / C_EE, C_ww / C_EE and C_BB / C_ww."""
+    sp = clm.Plan(nside, nside_sht=nside, lmax=lmax, solver="sht")
+    sp.jacobian_spectra(rays)                      # first call: kernel set-up
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    _, cl = sp.jacobian_spectra(rays)
+    t1.record()
+    torch.cuda.synchronize()
+    sp.sync_status()
+    sp.close()
+    cl = cl.cpu().numpy()
+    l = np.arange(lmax + 1, dtype=np.float64)
+    ee_kk = np.zeros_like(l)
+    ok = l >= 2
+    ee_kk[ok] = cl[1, ok] / cl[0, ok] * l[ok] * (l[ok] + 1) / ((l[ok] - 1) * (l[ok] + 2))
+    bands = {}
+    for lo, hi in ((10, 100), (100, 300), (300, 1000), (1000, lmax + 1)):
+        b = slice(lo, min(hi, lmax + 1))
+        bands["%d-%d" % (lo, min(hi, lmax + 1) - 1)] = dict(
+            ee_over_kk_born=float(np.mean(ee_kk[b])),
+            bb_over_ee=float(np.mean(cl[2, b] / cl[1, b])),
+            ww_over_ee=float(np.mean(cl[3, b] / cl[1, b])),
+            bb_over_ww=float(np.mean(cl[2, b] / cl[3, b])))
+    return dict(ms=t0.elapsed_time(t1), lmax=lmax, bands=bands,
+                note="kappa, E, B, omega of eq. invmagmat on the Nside %d ray grid, Jacobians "
+                     "transported to the pixel centres, FP64 analyses" % nside)
+
+
 def c3_run(clm, torch, inputs, cosmo, gal):
     """Multiplane ray tracing: 20 lens planes at chi_m = (m + 1/2) dchi to
     z = 1.5, each an Nside 2048 lognormal kappa (sigma_g 0.1 -> 0.6 with the
@@ -462,6 +496,7 @@ def c3_run(clm, torch, inputs, cosmo, gal):
     plan.sync_status()
     npix = plan.npix_fine
     A = gal["A"].double()
+    spectra = jacobian_spectra_summary(clm, torch, rays, NF, 2048)
     # a second pass over all planes with every launch timed: the stage
     # breakdown, and after each plane the grid search for the images of the
     # galaxies of the shell the rays have just reached (Sec. 3.3)
@@ -490,6 +525,10 @@ def c3_run(clm, torch, inputs, cosmo, gal):
                   jacobian_vs_reduced=dict(median=float(dA.median()) if dA.numel() else None,
                                            max=float(dA.max()) if dA.numel() else None))
     del rays2, gimg
+    plan.close()
+    del plan, rays
+    torch.cuda.empty_cache()
+    pure = c3_pure_sht(clm, torch, kap, chi, gal)
     out = dict(
         planes=nplanes, nside_sht=ns3, lmax=l3, ms_all_planes=ms, ms_per_plane=ms / nplanes,
         ray_plane_updates_per_s=dict(end_to_end=npix * nplanes / (ms * 1e-3),
@@ -497,11 +536,60 @@ def c3_run(clm, torch, inputs, cosmo, gal):
         stage_ms_per_plane={k: v[0] for k, v in stages.items()},
         stage_note="per plane, from a second pass with every launch timed",
         galaxy_images=images,
+        final_plane_spectra=spectra,
+        pure_sht_solver=pure,
         galaxies=int(gal["theta"].numel()),
         galaxies_with_A=int((A.abs().sum(0) > 0).sum()),
         galaxy_A_finite=bool(torch.isfinite(A).all()))
+    del kap
+    torch.cuda.empty_cache()
+    return out
+
+
+def c3_pure_sht(clm, torch, kap, chi, gal):
+    """The same 20 planes and galaxies through the pure-SHT solver (Sec.
+    3.2, last paragraph) at the ray grid: Nside 2048, lmax 4096, float32
+    matrix-core form, 8 planes per derivative synthesis, g and U at the rays
+    by transported four-point interpolation; timed over all planes (solve,
+    fields, rays, galaxies), then the final-plane spectra as for SHT+MG."""
+    nplanes = kap.shape[0]
+    plan = clm.Plan(NF, nside_sht=NF, lmax=2 * NF, solver="sht", max_planes=8,
+                    legendre_prec="fp32")
+    rays = plan.new_rays()
+    g2 = dict(gal, A=torch.zeros_like(gal["A"]))
+    plan.raytrace_planes(kap[:1], chi, 0, rays, galaxies=g2)      # kernel set-up
+    plan.rays_init(rays)
+    g2["A"].zero_()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    plan.raytrace_planes(kap, chi, 0, rays, galaxies=g2)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    plan.sync_status()
+    # a second pass with every launch timed: the stage breakdown
+    rays2 = plan.new_rays()
+    plan.set_timing(True)
+    plan.get_timing()
+    plan.raytrace_planes(kap, chi, 0, rays2)
+    tm = plan.get_timing()
+    plan.set_timing(False)
+    plan.sync_status()
+    del rays2
     plan.close()
-    del plan, rays, kap
+    del plan
+    torch.cuda.empty_cache()
+    spectra = jacobian_spectra_summary(clm, torch, rays, NF, 2048)
+    A = g2["A"]
+    out = dict(ms_all_planes=ms, ms_per_plane=ms / nplanes,
+               ray_plane_updates_per_s=12 * NF * NF * nplanes / (ms * 1e-3),
+               stage_ms_per_plane={k: v[0] / nplanes for k, v in tm.items() if v[1]},
+               galaxies_with_A=int((A.abs().sum(0) > 0).sum()),
+               final_plane_spectra=spectra,
+               workload="the C3 planes, rays and galaxies; pure-SHT solver at Nside 2048, lmax "
+                        "4096 (float32 matrix-core form)")
+    del rays, g2
     torch.cuda.empty_cache()
     return out
 
