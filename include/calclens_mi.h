@@ -448,6 +448,33 @@ clm_status clm_galaxies_reduced(clm_plan plan, const clm_rays* rays, const doubl
                                 float* A_g_dev, hipStream_t stream);
 
 /*
+ * Partial sky (Sec. 3.4): run the SHT step over the whole sky but the
+ * multigrid step, the shear evaluation and the ray update only over a
+ * domain of bundles, so that matter outside the domain still acts on it
+ * through the SHT boundary values.  bundles_host: [nbundles] NESTED bundle
+ * indices at nside_bundle (any order, duplicates allowed); nbundles = 0
+ * restores the whole sky.  After the call, until the next one:
+ *   - clm_poisson_solve / clm_raytrace_planes set up and solve the patches
+ *     of the domain only; every patch still stops on its own under the
+ *     epsilon rule, and clm_get_mg_convergence reports 0 cycles and NaN for
+ *     patches outside the domain;
+ *   - clm_shear_at_pixels writes the pixels of the domain's bundles and
+ *     leaves the others untouched; clm_shear_from_potential gives NaN at
+ *     points outside the domain and latches CLM_ERAY_LEFT_PATCH;
+ *   - clm_ray_update / clm_raytrace_planes move the rays of the domain's
+ *     bundles and leave the others untouched; galaxies are served from the
+ *     rays around them, so they belong inside the domain, at least one
+ *     bundle from its edge;
+ *   - clm_get_patch_potential of a patch outside the domain returns that
+ *     patch's last solve;
+ *   - the adjoints return CLM_EUNSUPPORTED.
+ * SHT+MG plans only (CLM_EUNSUPPORTED otherwise); CLM_EINVAL for an index
+ * outside 0 .. 12 nside_bundle^2 - 1.  Synchronises the device (the domain
+ * tables are copied from the host); no allocation.
+ */
+clm_status clm_plan_set_domain(clm_plan plan, const int32_t* bundles_host, int64_t nbundles);
+
+/*
  * Full-sky power spectra of a ray state (Sec. 5): the convergence, the E-
  * and B-modes of the shear and the rotation of eq. invmagmat,
  *   kappa = 1 - (A11 + A22)/2, gamma_1 = (A22 - A11)/2,

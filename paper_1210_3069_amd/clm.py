@@ -73,6 +73,7 @@ _SIGS = {
     "clm_shear_at_pixels_batch": (_P, _I32, _I32, _I32, _I32, _P, _P, _P),
     "clm_rays_init": (_P, ctypes.POINTER(Rays), _P),
     "clm_jacobian_spectra": (_P, ctypes.POINTER(Rays), _P, _P, _P),
+    "clm_plan_set_domain": (_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64),
     "clm_raytrace_planes": (_P, _P, _I32, ctypes.POINTER(_D), _I32, _I32, _I32, _D,
                             ctypes.POINTER(Rays), ctypes.POINTER(Galaxies), _P),
     "clm_ray_update": (_P, _I32, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays), _P),
@@ -442,6 +443,13 @@ class Plan:
     def rays_init(self, r):
         s = self._rays_struct(r)
         self._check(lib().clm_rays_init(self.h, ctypes.byref(s), _stream()), "rays_init")
+
+    def set_domain(self, bundles=None):
+        """Partial sky: the multigrid step, shear and rays over these NESTED
+        bundles only (None or empty: the whole sky)."""
+        b = np.ascontiguousarray([] if bundles is None else bundles, dtype=np.int32)
+        ptr = b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if b.size else None
+        self._check(lib().clm_plan_set_domain(self.h, ptr, b.size), "set_domain")
 
     def jacobian_spectra(self, rays):
         """SHT-only plans on the rays' grid: (alm [4][n_lm] complex128,

@@ -33,6 +33,13 @@ constexpr int kTile = 64;
 // so block b is given logical index (b mod 8) (nb / 8) + b / 8 and each XCD
 // runs one contiguous range of logical blocks.  Identity when the grid is
 // not a multiple of 8.
+// The patch (bundle) of compact index c under a partial-sky domain: the
+// c-th entry of the sorted list of the domain's bundles, or c itself when
+// the plan covers the whole sky (pmap = nullptr).
+__device__ __forceinline__ int64_t patch_of(const int* pmap, int64_t c) {
+  return pmap ? int64_t(pmap[c]) : c;
+}
+
 __device__ __forceinline__ int64_t xcd_block() {
   const int64_t b = blockIdx.x, nb = gridDim.x;
   if (nb % 8 != 0) return b;
@@ -127,6 +134,12 @@ struct Plan {
   double* mg_eps_dev = nullptr;   // [nbundle] epsilon ratio of the latest solve
   int* mg_cycles_dev = nullptr;   // [nbundle] V-cycles run
   int* mg_done_dev = nullptr;     // [nbundle] epsilon rule met
+  // partial sky (clm_plan_set_domain): the multigrid, the evaluation and the
+  // rays run over the domain's bundles only
+  bool domain = false;            // false: the whole sky
+  int64_t nactive = 0;            // bundles of the domain (nbundle without one)
+  int* dom_map = nullptr;         // [nbundle] the domain's bundles, ascending
+  int* dom_flag = nullptr;        // [nbundle] 1 inside the domain
   double* mg_eps_part = nullptr;  // epsilon rule: [nbundle][tiles][4] partial sums
   int* mg_active_dev = nullptr;   // epsilon rule: patches still above mg_eps
   int* mg_active_host = nullptr;  // pinned copy of mg_active_dev

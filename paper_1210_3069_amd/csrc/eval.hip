@@ -24,25 +24,38 @@ struct EvalArgs {
   void* grad;
   void* hess;
   int* status;
+  const int* pmap;     // partial sky: the domain's bundles (pixel mode), or nullptr
+  const int* dflag;    // partial sky: 1 for a bundle of the domain (point mode), or nullptr
 };
 
 template <typename T, typename TO>
 __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
   // consecutive points (a NESTED range: one region of one patch) stay on
   // one XCD, so the L2 of one XCD holds their cell window
-  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i >= a.npts) return;
+  const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
+  int64_t i = c;  // output index
   double vx, vy, vz;
   int64_t b;
+  bool inside = true;
   if (a.th) {
+    if (c >= a.npts) return;
     double st, ct, sp, cp;
     sincos(a.th[i], &st, &ct);
     sincos(a.ph[i], &sp, &cp);
     vx = st * cp; vy = st * sp; vz = ct;
     b = hpx::ang2nest(a.Nb, ct, a.ph[i]);
+    inside = !a.dflag || a.dflag[b];
   } else {
     int64_t pring, pnest;
-    if (a.order == CLM_ORDER_NESTED) {
+    if (a.pmap) {
+      // the pixels of the domain's bundles, NESTED ranges one after the other
+      if ((c >> a.shift) >= a.npts) return;
+      pnest = (int64_t(a.pmap[c >> a.shift]) << a.shift) | (c & ((int64_t(1) << a.shift) - 1));
+      pring = hpx::nest2ring(a.Nf, pnest);
+      i = a.order == CLM_ORDER_NESTED ? pnest : pring;
+    } else if (c >= a.npts) {
+      return;
+    } else if (a.order == CLM_ORDER_NESTED) {
       pnest = i;
       pring = hpx::nest2ring(a.Nf, i);
     } else {
@@ -56,21 +69,22 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalArgs a) {
     vx = st * cp; vy = st * sp; vz = z;
     b = pnest >> a.shift;
   }
+  const int64_t nout = a.pmap ? a.Nf * a.Nf * 12 : a.npts;  // output stride
   double g[2], U[3];
   TO* gr = static_cast<TO*>(a.grad);
   TO* hs = static_cast<TO*>(a.hess);
-  if (!eval_patch<T>(a.P, b, vx, vy, vz, g, U)) {
+  if (!inside || !eval_patch<T>(a.P, b, vx, vy, vz, g, U)) {
     atomicOr(a.status, ST_LEFT_PATCH);
     const TO nan = TO(NAN);
-    gr[i] = nan; gr[a.npts + i] = nan;
-    hs[i] = nan; hs[a.npts + i] = nan; hs[2 * a.npts + i] = nan;
+    gr[i] = nan; gr[nout + i] = nan;
+    hs[i] = nan; hs[nout + i] = nan; hs[2 * nout + i] = nan;
     return;
   }
   gr[i] = TO(g[0]);
-  gr[a.npts + i] = TO(g[1]);
+  gr[nout + i] = TO(g[1]);
   hs[i] = TO(U[0]);
-  hs[a.npts + i] = TO(U[1]);
-  hs[2 * a.npts + i] = TO(U[2]);
+  hs[nout + i] = TO(U[1]);
+  hs[2 * nout + i] = TO(U[2]);
 }
 
 }  // namespace
@@ -90,7 +104,20 @@ clm_status eval_points(Plan* p, int slot, const double* th, const double* ph, in
   a.grad = grad;
   a.hess = hess;
   a.status = p->status_dev;
-  const dim3 g((npts + kBlock - 1) / kBlock);
+  a.pmap = nullptr;
+  a.dflag = nullptr;
+  int64_t nthreads = npts;
+  if (p->domain) {
+    if (th) {
+      a.dflag = p->dom_flag;
+    } else {
+      // pixel mode: threads over the domain's pixels; a.npts counts its bundles
+      a.pmap = p->dom_map;
+      a.npts = p->nactive;
+      nthreads = p->nactive << p->bundle_shift;
+    }
+  }
+  const dim3 g(unsigned((nthreads + kBlock - 1) / kBlock));
   CLM_TIMED(p, s, th ? "eval_points" : "eval_pixels");
   if (p->fp64mg) {
     if (out_fp64) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eval<double, double>), g, dim3(kBlock), 0, s, a);

@@ -59,6 +59,7 @@ struct SetupArgs {
   double* u0;          // [patch][(n+2)^2]
   void* fprime;        // [patch][n^2] of T
   SetupMeta* meta;     // [patch][tile]
+  const int* pmap;     // partial sky: the domain's patches (nullptr: all)
 };
 
 // Global direction of the patch point with sin/cos of theta' and phi':
@@ -497,7 +498,9 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
   __shared__ SetupRing recs[kRingCapS];
   __shared__ T fshm[sizeof(T) == 4 ? TILE * TILE : 1];
   T* fsh = sizeof(T) == 4 ? fshm : nullptr;
-  const int64_t lb = xcd_block();
+  const int64_t lc = xcd_block();
+  const int64_t tpp = int64_t(a.ntile) * a.ntile;
+  const int64_t lb = patch_of(a.pmap, lc / tpp) * tpp + lc % tpp;  // this tile's record
   const SetupTile st = setup_tile(lb, a.ntile, TILE);
   const int64_t patch = st.patch;
   const int i0 = st.i0, j0 = st.j0;
@@ -581,6 +584,7 @@ struct TileArgs {
   int fas_source;       // pre on level >= 1: A f = A L u_in + A f_in
   int f_scaled;         // f_in already holds A f
   const int* done;      // epsilon rule: patches that stopped (nullptr: none)
+  const int* pmap;      // partial sky: the domain's patches (nullptr: all)
 };
 
 // Quads per region side, threads per workgroup and threads per quad row.
@@ -992,7 +996,7 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_pre(TileArgs<T> a) {
   Quad<T> qd[G::IT];
   const int64_t lb = xcd_block();
   const int tpp = a.ntile * a.ntile;
-  const int64_t patch = lb / tpp;
+  const int64_t patch = patch_of(a.pmap, lb / tpp);
   const int tt = int(lb % tpp);
   if (a.done && a.done[patch]) return;
   const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
@@ -1036,7 +1040,7 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_post(TileArgs<T> a) {
   Quad<T> qd[G::IT];
   const int64_t lb = xcd_block();
   const int tpp = a.ntile * a.ntile;
-  const int64_t patch = lb / tpp;
+  const int64_t patch = patch_of(a.pmap, lb / tpp);
   const int tt = int(lb % tpp);
   const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
   const int n = a.n, nc = n / 2;
@@ -1085,7 +1089,7 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_postpre(TileArgs<T> a) 
   Quad<T> qd[G::IT];
   const int64_t lb = xcd_block();
   const int tpp = a.ntile * a.ntile;
-  const int64_t patch = lb / tpp;
+  const int64_t patch = patch_of(a.pmap, lb / tpp);
   const int tt = int(lb % tpp);
   const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
   const int n = a.n, nc = n / 2;
@@ -1144,6 +1148,7 @@ struct LdsArgs {
   T* u_out;
   int fas_source;
   const int* done;        // epsilon rule: patches that stopped (nullptr: none)
+  const int* pmap;        // partial sky: the domain's patches (nullptr: all)
 };
 
 template <typename T>
@@ -1228,7 +1233,7 @@ __device__ __forceinline__ LLevel<T> lds_level(unsigned char* smem, int K, int n
 template <typename T>
 __global__ __launch_bounds__(kLdsBlock) void k_mg_lds(LdsArgs<T> a) {
   extern __shared__ unsigned char smem[];
-  const int64_t patch = xcd_block();
+  const int64_t patch = patch_of(a.pmap, xcd_block());
   if (a.done && a.done[patch]) return;
   const int K = a.lv.K, nl = a.lv.nlev, n0 = a.lv.n0;
   for (int l = K; l < nl; ++l) {
@@ -1340,6 +1345,7 @@ struct EpsArgs {
   const T* fp;
   const int* done;      // patches that already stopped
   double* part;         // [patch][tile][4]: sum A r^2, sum A, sum A_H tau^2, sum A_H
+  const int* pmap;      // partial sky: the domain's patches (nullptr: all)
 };
 
 template <typename T, int TC>
@@ -1354,7 +1360,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_eps(EpsArgs<T> a) {
   __shared__ double RF[5][2 * TC], RC[5][TC], RW[2][CS];
   __shared__ double red[4][NW];
   const int tiles = a.ntile * a.ntile;
-  const int64_t patch = blockIdx.x / tiles;
+  const int64_t patch = patch_of(a.pmap, blockIdx.x / tiles);
   const int tile = blockIdx.x % tiles;
   if (a.done[patch]) return;
   const int n = a.n, nc = n / 2;
@@ -1477,11 +1483,12 @@ struct EpsFinal {
   double* eps_out;
   int* active;          // patches still above the threshold (added to)
   int* status;          // latched conditions (ST_NONFINITE)
+  const int* pmap;      // partial sky: the domain's patches (nullptr: all)
 };
 
 // one wave per patch: partial sums added in a fixed order
 __global__ __launch_bounds__(64) void k_mg_eps_final(EpsFinal a) {
-  const int64_t patch = blockIdx.x;
+  const int64_t patch = patch_of(a.pmap, blockIdx.x);
   if (a.done[patch]) return;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int t = threadIdx.x; t < a.tiles; t += 64)
@@ -1513,9 +1520,15 @@ __global__ void k_fill_f64(int64_t n, double v, double* y) {
   if (t < n) y[t] = v;
 }
 
-__global__ void k_notconv(int64_t n, const int* done, int* status) {
+__global__ void k_notconv(int64_t n, const int* pmap, const int* done, int* status) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < n && !done[t]) atomicOr(status, ST_NOTCONV);
+  if (t < n && !done[patch_of(pmap, t)]) atomicOr(status, ST_NOTCONV);
+}
+
+// y[patch] = v for the n patches of a domain (pmap) or the first n
+__global__ void k_fill_patches(int64_t n, const int* pmap, int v, int* y) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) y[patch_of(pmap, t)] = v;
 }
 
 // ------------------------------------------------------------ potential out
@@ -1613,16 +1626,21 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
   Slot& sl = p->slots[slot];
   const int n = p->n;
   const int64_t np = p->nbundle;
+  // the patches the grids cover: the domain's (pm maps compact indices to
+  // patches) or all of them
+  const int64_t na = p->domain ? p->nactive : np;
+  const int* pm = p->domain ? p->dom_map : nullptr;
   // patch setup
   {
     SetupArgs a = setup_geometry(p);
+    a.pmap = pm;
     a.psi_s = sl.psi_s;
     a.kappa = kappa;
     a.kappa_fp64 = kappa_fp64;
     a.red = p->red;
     a.u0 = sl.u0;
     a.fprime = p->fprime;
-    const dim3 grid(unsigned(np * a.ntile * a.ntile));
+    const dim3 grid(unsigned(na * a.ntile * a.ntile));
     {
       CLM_TIMED(p, s, "patch_setup");
       switch (a.tile) {
@@ -1648,6 +1666,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
   la.nu2 = d.nu_post;
   la.coef = p->coef;
   la.cinv = p->cinv;
+  la.pmap = pm;
   size_t lds_elems = 0;
   for (int l = K; l < p->nlev; ++l) {
     const size_t nn = size_t(n >> l);
@@ -1670,18 +1689,23 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     a.coef = p->coef + p->lev[l].crow;
     a.rowt = static_cast<const T*>(p->rowt) + 2 * p->lev[l].crow;
     a.done = done;
+    a.pmap = pm;
     return a;
   };
+  // per-patch convergence record: patches outside a domain report 0 cycles
+  // and NaN
   const dim3 gfill(unsigned((np + kBlock - 1) / kBlock));
+  const dim3 gfa(unsigned((na + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_fill_f64, gfill, dim3(kBlock), 0, s, np, double(NAN), p->mg_eps_dev);
   if (eps_mode) {
     hipLaunchKernelGGL(k_fill_int, gfill, dim3(kBlock), 0, s, np, 0, p->mg_done_dev);
-    CLM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_fill_int, gfill, dim3(kBlock), 0, s, np, 0, p->mg_cycles_dev);
   } else {
-    hipLaunchKernelGGL(k_fill_int, gfill, dim3(kBlock), 0, s, np, d.mg_vcycles,
+    if (pm) hipLaunchKernelGGL(k_fill_int, gfill, dim3(kBlock), 0, s, np, 0, p->mg_cycles_dev);
+    hipLaunchKernelGGL(k_fill_patches, gfa, dim3(kBlock), 0, s, na, pm, d.mg_vcycles,
                        p->mg_cycles_dev);
-    hipLaunchKernelGGL(k_fill_f64, gfill, dim3(kBlock), 0, s, np, double(NAN), p->mg_eps_dev);
-    CLM_LAUNCH_CHECK();
   }
+  CLM_LAUNCH_CHECK();
   la.done = done;
   const int eps_tc = std::min(kEpsTC, n / 2), eps_nt = (n / 2) / eps_tc;
   auto eps_eval = [&](int cycle) -> clm_status {
@@ -1695,6 +1719,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     e.fp = fp;
     e.done = p->mg_done_dev;
     e.part = p->mg_eps_part;
+    e.pmap = pm;
     EpsFinal g{};
     g.tiles = eps_nt * eps_nt;
     g.eps = d.mg_eps;
@@ -1705,17 +1730,18 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     g.eps_out = p->mg_eps_dev;
     g.active = p->mg_active_dev;
     g.status = p->status_dev;
+    g.pmap = pm;
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, int64_t(1), 0, p->mg_active_dev);
     {
       CLM_TIMED(p, s, "mg_eps");
-      const dim3 ge(unsigned(np * g.tiles));
+      const dim3 ge(unsigned(na * g.tiles));
       if (eps_tc == 16)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_eps<T, 16>), ge, dim3(kBlock), 0, s, e);
       else if (eps_tc == 8)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_eps<T, 8>), ge, dim3(kBlock), 0, s, e);
       else
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_eps<T, 4>), ge, dim3(kBlock), 0, s, e);
-      hipLaunchKernelGGL(k_mg_eps_final, dim3(unsigned(np)), dim3(64), 0, s, g);
+      hipLaunchKernelGGL(k_mg_eps_final, dim3(unsigned(na)), dim3(64), 0, s, g);
     }
     CLM_LAUNCH_CHECK();
     return CLM_OK;
@@ -1754,7 +1780,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       la.fas_source = 0;
       {
         CLM_TIMED(p, s, "mg_lds");
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(np), dim3(kLdsBlock), lds_bytes, s,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(na), dim3(kLdsBlock), lds_bytes, s,
                            la);
       }
       CLM_LAUNCH_CHECK();
@@ -1780,7 +1806,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       a.rbar_out = static_cast<T*>(p->rbar[l + 1]);
       {
         CLM_TIMED(p, s, l == 0 ? "mg_pre_l0" : "mg_pre_l1+");
-        const clm_status st = launch_tile<T, true>(p, a, np, s);
+        const clm_status st = launch_tile<T, true>(p, a, na, s);
         if (st != CLM_OK) return st;
       }
     }
@@ -1791,7 +1817,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     la.fas_source = 1;
     {
       CLM_TIMED(p, s, "mg_lds");
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(np), dim3(kLdsBlock), lds_bytes, s, la);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mg_lds<T>), dim3(na), dim3(kLdsBlock), lds_bytes, s, la);
     }
     CLM_LAUNCH_CHECK();
     // prolongation, correction and post-smoothing back up
@@ -1814,7 +1840,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
         a.rbar_out = static_cast<T*>(p->rbar[1]);
         {
           CLM_TIMED(p, s, "mg_postpre_l0");
-          const clm_status st = launch_postpre<T>(p, a, np, s);
+          const clm_status st = launch_postpre<T>(p, a, na, s);
           if (st != CLM_OK) return st;
         }
         ub1 = ub1n;
@@ -1836,7 +1862,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       }
       {
         CLM_TIMED(p, s, l == 0 ? "mg_post_l0" : "mg_post_l1+");
-        const clm_status st = launch_tile<T, false>(p, a, np, s);
+        const clm_status st = launch_tile<T, false>(p, a, na, s);
         if (st != CLM_OK) return st;
       }
     }
@@ -1844,7 +1870,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
   if (eps_mode && !all_done) {
     const clm_status st = eps_eval(ncyc);
     if (st != CLM_OK) return st;
-    hipLaunchKernelGGL(k_notconv, gfill, dim3(kBlock), 0, s, np,
+    hipLaunchKernelGGL(k_notconv, gfa, dim3(kBlock), 0, s, na, pm,
                        static_cast<const int*>(p->mg_done_dev), p->status_dev);
     CLM_LAUNCH_CHECK();
   }

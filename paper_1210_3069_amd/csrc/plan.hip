@@ -46,6 +46,7 @@ Plan::~Plan() {
   for (auto& s : slots) { f(s.alm); f(s.psi_s); f(s.u0); f(s.du); }
   f(adj_ubar); f(adj_psi); f(adj_ks); f(adj_alm); f(adj_psi_priv); f(adj_rrows);
   f(mg_eps_dev); f(mg_cycles_dev); f(mg_done_dev); f(mg_eps_part); f(mg_active_dev);
+  f(dom_map); f(dom_flag);
   if (mg_active_host) (void)hipHostFree(mg_active_host);
   for (auto* q : adj_u) f(q);
   for (auto* q : adj_v) f(q);
@@ -486,6 +487,9 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
     if ((s = alloc(p, &p->mg_eps_dev, size_t(p->nbundle))) != CLM_OK) return bail(s);
     if ((s = alloc(p, &p->mg_cycles_dev, size_t(p->nbundle))) != CLM_OK) return bail(s);
     if ((s = alloc(p, &p->mg_done_dev, size_t(p->nbundle))) != CLM_OK) return bail(s);
+    if ((s = alloc(p, &p->dom_map, size_t(p->nbundle))) != CLM_OK) return bail(s);
+    if ((s = alloc(p, &p->dom_flag, size_t(p->nbundle))) != CLM_OK) return bail(s);
+    p->nactive = p->nbundle;
     if (d.mg_vcycles == 0) {
       // epsilon rule: per-tile partial sums
       const size_t nc = size_t(p->n / 2), tc = std::min<size_t>(kEpsTile, nc);
@@ -770,6 +774,31 @@ clm_status clm_shear_at_pixels(clm_plan plan, int32_t slot, int32_t order, int32
                      stream);
 }
 
+clm_status clm_plan_set_domain(clm_plan plan, const int32_t* bundles, int64_t nb) {
+  if (!plan || nb < 0 || (nb > 0 && !bundles)) return CLM_EINVAL;
+  Plan* p = plan;
+  if (!p->mg) return fail(p, CLM_EUNSUPPORTED, "a domain restricts the multigrid step only");
+  std::vector<int> flag(size_t(p->nbundle), nb > 0 ? 0 : 1);
+  for (int64_t k = 0; k < nb; ++k) {
+    if (bundles[k] < 0 || bundles[k] >= p->nbundle)
+      return fail(p, CLM_EINVAL, "domain: bundle index outside 0 .. nbundle - 1");
+    flag[size_t(bundles[k])] = 1;
+  }
+  std::vector<int> list;
+  for (int64_t b = 0; b < p->nbundle; ++b)
+    if (flag[size_t(b)]) list.push_back(int(b));
+  CLM_HIP_P(p, hipSetDevice(p->device));
+  // the device may be running the plan's kernels: wait for them first
+  CLM_HIP_P(p, hipDeviceSynchronize());
+  CLM_HIP_P(p, hipMemcpy(p->dom_map, list.data(), list.size() * sizeof(int),
+                         hipMemcpyHostToDevice));
+  CLM_HIP_P(p, hipMemcpy(p->dom_flag, flag.data(), flag.size() * sizeof(int),
+                         hipMemcpyHostToDevice));
+  p->nactive = int64_t(list.size());
+  p->domain = p->nactive < p->nbundle;
+  return CLM_OK;
+}
+
 clm_status clm_shear_at_pixels_batch(clm_plan plan, int32_t first_slot, int32_t nplanes,
                                      int32_t order, int32_t out_fp64, void* grad, void* hess,
                                      hipStream_t stream) {
@@ -934,6 +963,7 @@ clm_status clm_shear_adjoint(clm_plan plan, int32_t slot, const double* theta, c
   Plan* p = plan;
   if (!p->mg || !p->d.adjoint)
     return fail(p, CLM_EUNSUPPORTED, "the adjoint needs an SHT+MG plan created with adjoint = 1");
+  if (p->domain) return fail(p, CLM_EUNSUPPORTED, "the adjoint covers the whole sky only");
   if (npts == 0) return CLM_OK;
   if (!theta || !phi || !dgrad || !dhess) return CLM_EINVAL;
   CLM_HIP(hipSetDevice(p->device));
@@ -945,6 +975,7 @@ clm_status clm_poisson_adjoint(clm_plan plan, int32_t slot, double* dkappa, hipS
   Plan* p = plan;
   if (!p->mg || !p->d.adjoint)
     return fail(p, CLM_EUNSUPPORTED, "the adjoint needs an SHT+MG plan created with adjoint = 1");
+  if (p->domain) return fail(p, CLM_EUNSUPPORTED, "the adjoint covers the whole sky only");
   CLM_HIP(hipSetDevice(p->device));
   return poisson_adjoint(p, dkappa, stream);
 }

@@ -117,6 +117,8 @@ struct RayArgs {
   const double* D;   // pure-SHT planes: [5][n] g_t, g_p, U_tt, U_pp, U_tp at the RING
                      // pixel centres of the ray grid
   hpx::Rings rf;     // ... and that grid's ring tables
+  const int* pmap;   // partial sky: the domain's bundles (their rays only), or nullptr
+  int64_t nlaunch;   // rays the grid covers (n, or the domain's)
   int shift;
   int64_t n;
   double chi_m, chi_m1;  // chi_m, chi_{m+1}
@@ -165,8 +167,11 @@ __device__ __forceinline__ void pixel_field(const RayArgs& a, const double nv[3]
 template <typename T, bool SHT>
 __global__ __launch_bounds__(kBlock) void k_ray_update(RayArgs a) {
   // the rays of one bundle (a NESTED range) stay on one XCD
-  const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+  const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
+  if (c >= a.nlaunch) return;
+  const int64_t i =
+      a.pmap ? (int64_t(a.pmap[c >> a.shift]) << a.shift) | (c & ((int64_t(1) << a.shift) - 1))
+             : c;
   const int64_t n = a.n;
   double st, ct, sp, cp;
   sincos(a.th[i], &st, &ct);
@@ -686,6 +691,11 @@ clm_status ray_update(Plan* p, int slot, const double* chi, int nchi, int m, dou
     a.rf = hpx::Rings{p->ring_f, p->ringi_f, p->ringx_f, p->nring_f, p->d.nside_fine};
   }
   a.n = r->n;
+  a.nlaunch = r->n;
+  if (p->mg && p->domain) {
+    a.pmap = p->dom_map;
+    a.nlaunch = p->nactive << p->bundle_shift;
+  }
   a.chi_m = chi[m];
   a.chi_m1 = chi[m + 1];
   // eq. Atraj with chi_{-1} = 0: c_m = D_m/D_{m+1} * D_{m-1,m+1}/D_{m-1,m},
@@ -700,7 +710,7 @@ clm_status ray_update(Plan* p, int slot, const double* chi, int nchi, int m, dou
   a.A = r->A;
   a.Ap = r->A_prev;
   a.status = p->status_dev;
-  const dim3 g((r->n + kBlock - 1) / kBlock);
+  const dim3 g(unsigned((a.nlaunch + kBlock - 1) / kBlock));
   CLM_TIMED(p, s, "ray_update");
   if (!p->mg)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ray_update<double, true>), g, dim3(kBlock), 0, s, a);
