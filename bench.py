@@ -250,7 +250,7 @@ def plane_distances(nplanes):
 
 
 def run_form(clm, torch, kappa, gal, prec, steps, warmup, vcycles=VCYC, eps=0.1,
-             stage_steps=0, timed_stages=None):
+             stage_steps=0, timed_stages=None, domain=None):
     """Times `steps` lens-plane steps (solve, shear at all pixels, ray update,
     galaxies of the shell) of one form on a fresh light cone.
 
@@ -264,6 +264,8 @@ def run_form(clm, torch, kappa, gal, prec, steps, warmup, vcycles=VCYC, eps=0.1,
     events of the stage pass)."""
     plan = clm.Plan(NF, nside_sht=NS, lmax=LMAX, nside_bundle=NB, patch_cells=NCELL,
                     mg_vcycles=vcycles, mg_eps=eps, mg_max_vcycles=20, mg_prec=prec)
+    if domain is not None:
+        plan.set_domain(domain)
     rays = plan.new_rays()
     chi = plane_distances(steps)
     last = len(chi) - 2                       # index of the last plane
@@ -450,6 +452,53 @@ def jacobian_spectra_summary(clm, torch, rays, nside, lmax):
     return dict(ms=t0.elapsed_time(t1), lmax=lmax, bands=bands,
                 note="kappa, E, B, omega of eq. invmagmat on the Nside %d ray grid, Jacobians "
                      "transported to the pixel centres, FP64 analyses" % nside)
+
+
+def cap_bundles(nside_bundle, theta0, phi0, radius):
+    """NESTED bundles whose centres lie within `radius` of (theta0, phi0)
+    (host geometry of the benchmark's domain, through the library's own
+    pixel centres)."""
+    import torch
+    from paper_1210_3069_amd import clm
+    pl = clm.Plan(nside_bundle, nside_sht=nside_bundle, lmax=2, solver="sht")
+    r = pl.new_rays()
+    torch.cuda.synchronize()
+    th, ph = r["theta"].cpu().numpy(), r["phi"].cpu().numpy()
+    pl.close()
+    v = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1)
+    c = np.array([np.sin(theta0) * np.cos(phi0), np.sin(theta0) * np.sin(phi0), np.cos(theta0)])
+    return np.nonzero(v @ c > np.cos(radius))[0]
+
+
+def partial_sky_run(clm, torch, kappa, gal, steps, warmup, full_ms):
+    """Sec. 3.4: the headline step with the multigrid, shear and rays
+    restricted to a domain of about 1/8 of the sky (the bundles whose
+    centres lie in a cap of half-angle 41.4 degrees about theta = 120 deg,
+    phi = 0), the SHT still over the whole sky; the galaxies are those whose
+    bundle lies in the cap shrunk by one bundle size.  Timed like the
+    headline (stage pass, then the timed steps)."""
+    theta0, radius = np.radians(120.0), np.arccos(0.75)
+    dom = cap_bundles(NB, theta0, 0.0, radius)
+    inner = cap_bundles(NB, theta0, 0.0, radius - 2.0 * np.sqrt(4 * np.pi / (12 * NB * NB)))
+    th, ph = gal["theta"].cpu().numpy(), gal["phi"].cpu().numpy()
+    v = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1)
+    c = np.array([np.sin(theta0), 0.0, np.cos(theta0)])
+    keep = np.nonzero(v @ c > np.cos(radius - 2.0 * np.sqrt(4 * np.pi / (12 * NB * NB))))[0]
+    keep_t = torch.from_numpy(keep).cuda()
+    g2 = {k: (gal[k][..., keep_t].contiguous()) for k in ("theta", "phi", "chi", "A")}
+    S = 2
+    plan, rays, ms, _, _, stages = run_form(clm, torch, kappa, g2, "fp32", steps, warmup,
+                                            stage_steps=S, domain=dom)
+    plan.close()
+    del plan, rays
+    torch.cuda.empty_cache()
+    return dict(bundles=int(dom.size), sky_fraction=dom.size / (12.0 * NB * NB),
+                inner_bundles=int(inner.size), galaxies=int(keep.size),
+                ms_per_step=ms, value=1000.0 / ms, speedup_vs_whole_sky=full_ms / ms,
+                stage_ms_per_step={k: v[0] / S for k, v in stages.items() if v[1]},
+                workload="the headline step (Nside 2048, SHT Nside 256 / lmax 512 over the "
+                         "whole sky) with multigrid, shear and rays over a cap of 1/8 of the "
+                         "sky (theta0 120 deg, half-angle 41.4 deg)")
 
 
 def c3_run(clm, torch, inputs, cosmo, gal):
@@ -964,6 +1013,8 @@ def parse_args(argv=None):
                     help="skip the differentiation workload (8 planes, chi^2 gradient)")
     ap.add_argument("--no-pure-sht", action="store_true",
                     help="skip the pure-SHT production path (8 planes at Nside 2048)")
+    ap.add_argument("--no-partial-sky", action="store_true",
+                    help="skip the partial-sky run (the headline step over 1/8 of the sky)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with a plain copy kernel of known size (counter calibration)")
     ap.add_argument("--summarize-stats", nargs="+", metavar="ARG",
@@ -1136,6 +1187,9 @@ def main():
         pe.close()
         del pe, re_
         torch.cuda.empty_cache()
+    if not args.no_partial_sky:
+        print("bench: partial sky", file=sys.stderr, flush=True)
+        out["partial_sky"] = partial_sky_run(clm, torch, kappa, gal, args.steps, args.warmup, ms)
     if not args.no_c3:
         print("bench: multiplane ray tracing", file=sys.stderr, flush=True)
         out["c3_multiplane"] = c3_run(clm, torch, inputs, cosmo, gal)
