@@ -1,0 +1,92 @@
+"""Pins of the oracle's Epanechnikov deposition (oracle/deposit.py) against
+App. E and the mathematics, not its own formulas retyped:
+
+* the kernel integrates to one over the sphere (numerical quadrature of
+  the printed normalisation N(sigma));
+* mass is conserved exactly, also for particles whose sigma reaches no
+  pixel centre (all their mass in the pixel that contains them);
+* a wide kernel sampled on the grid is the continuous kernel: the
+  deposited map equals w K(theta) to the grid's quadrature error;
+* the smoothed point mass of App. E: a particle at the pole, deposited,
+  then solved by the oracle's pure SHT, has the App. E deflection and
+  shear (the closed forms of App. E, restated in the test)."""
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+from oracle import deposit as dep
+from oracle import healpix as hp
+from oracle import sht
+
+
+def app_e(theta, sigma):
+    """App. E at the pole for lap Psi = K - 1/(4 pi): (dPsi/dtheta, gamma_1)."""
+    sinc = np.sinc
+    nrm = 2 * np.pi * (sinc(sigma / (2 * np.pi)) ** 2 - 2 * sinc(sigma / np.pi) + 1)
+    c = np.cos(theta)
+    K = np.where(theta < sigma, (1 - (theta / sigma) ** 2) / nrm, 0.0)
+    h = ((theta / sigma) ** 2 * (-2 * sinc(theta / np.pi) + c + sinc(theta / 2 / np.pi) ** 2)
+         + 1 - c) / (nrm * (1 - c)) - 1 / (4 * np.pi)
+    inside = theta < sigma
+    dpsi = np.where(inside, h * (1 - c) / np.sin(theta), np.sin(theta) / (4 * np.pi * (1 - c)))
+    g1 = np.where(inside, -0.5 * (2 * c / (1 + c) * h - K + 1 / (4 * np.pi)),
+                  -(1 + c) / (8 * np.pi * (1 - c)))
+    return dpsi, g1
+
+
+@pytest.mark.parametrize("sigma", [1e-3, 0.05, 0.4, 1.5])
+def test_kernel_integrates_to_one(sigma):
+    """The printed N(sigma) cancels to O(sigma^2) from terms of O(1), so in
+    float64 it keeps about 1e-16 / sigma^2 relative precision (the
+    deposition's normalised weights do not depend on it)."""
+    v, _ = quad(lambda t: 2 * np.pi * dep.kernel(t, sigma) * np.sin(t), 0, sigma,
+                epsabs=1e-14, epsrel=1e-13)
+    assert abs(v - 1) < max(1e-11, 1e-15 / sigma ** 2)
+
+
+def test_mass_conservation_and_small_kernels():
+    N = 16
+    rng = np.random.default_rng(2)
+    n = 60
+    th = np.arccos(rng.uniform(-1, 1, n))
+    ph = rng.uniform(0, 2 * np.pi, n)
+    th[:3] = [0.0, np.pi, 1e-4]                       # the poles
+    w = rng.uniform(0.5, 2.0, n)
+    pix = np.sqrt(4 * np.pi / hp.npix(N))
+    sg = pix * rng.uniform(0.05, 3.0, n)
+    m = dep.deposit(N, th, ph, w, sg)
+    assert abs(m.sum() * 4 * np.pi / hp.npix(N) - w.sum()) < 1e-13 * w.sum()
+    # a kernel narrower than any pixel-centre distance: all in its own pixel
+    t, p = 1.0, 0.3
+    own = int(hp.nest2ring(N, hp.ang2pix_nest(N, np.cos(t), p)))
+    one = dep.deposit(N, [t], [p], [1.0], [1e-6])
+    assert one[own] * 4 * np.pi / hp.npix(N) == pytest.approx(1.0, rel=1e-15)
+    assert np.count_nonzero(one) == 1
+
+
+def test_wide_kernel_is_the_continuous_kernel():
+    N, sigma = 64, 0.3
+    t0, p0 = 0.9, 2.0
+    m = dep.deposit(N, [t0], [p0], [1.0], [sigma])
+    z, ph, s = hp.pix2ang_ring(N, np.arange(hp.npix(N)))
+    n0 = hp.vec(np.cos(t0), p0)
+    ang = np.arctan2(np.linalg.norm(np.cross(hp.vec(z, ph, s), n0), axis=1),
+                     hp.vec(z, ph, s) @ n0)
+    K = dep.kernel(ang, sigma)
+    assert np.abs(m - K).max() < 1e-4 * K.max()
+
+
+def test_smoothed_point_mass_app_e():
+    """Deposit, solve (pure SHT, oracle), compare with App. E away from the
+    kernel's edge, where its kink slows the harmonic convergence."""
+    N, lmax, sigma = 64, 128, 0.6
+    kstd = dep.deposit(N, [0.0], [0.0], [0.5], [sigma])   # standard convergence
+    psi = sht.poisson(lmax, sht.map2alm(N, lmax, kstd - kstd.mean()))
+    d = sht.derivative_maps(N, lmax, psi)
+    z, ph, s = hp.pix2ang_ring(N, np.arange(hp.npix(N)))
+    th = np.arctan2(s, z)
+    dpsi, g1 = app_e(th, sigma)
+    sel = (th > 0.15) & (np.abs(th - sigma) > 0.15) & (th < 2.5)
+    assert np.abs(d["g_t"][sel] - dpsi[sel]).max() < 2e-3 * np.abs(dpsi[sel]).max()
+    g1m = 0.5 * (d["U_tt"] - d["U_pp"])
+    assert np.abs(g1m[sel] - g1[sel]).max() < 2e-2 * np.abs(g1[sel]).max()
