@@ -33,10 +33,13 @@ def kernel(theta, sigma):
     return np.where(theta < sigma, (1 - (theta / sigma) ** 2) / nrm, 0.0)
 
 
-def deposit(nside, theta, phi, weight, sigma):
-    """RING map of the particles' kappa (mass per steradian)."""
+def deposit(nside, theta, phi, weight, sigma, pixels=None):
+    """RING map of the particles' kappa (mass per steradian).  `pixels`
+    (RING indices) limits the pixel centres tried, for large grids: it must
+    hold every pixel centre within sigma of every particle."""
     npix = hp.npix(nside)
-    z, ph, s = hp.pix2ang_ring(nside, np.arange(npix))
+    cand = np.arange(npix) if pixels is None else np.asarray(pixels)
+    z, ph, s = hp.pix2ang_ring(nside, cand)
     V = hp.vec(z, ph, s)
     out = np.zeros(npix)
     for t, p, w, sg in zip(theta, phi, weight, sigma):
@@ -48,5 +51,5 @@ def deposit(nside, theta, phi, weight, sigma):
             own = hp.nest2ring(nside, hp.ang2pix_nest(nside, np.cos(t), p))
             out[own] += w
         else:
-            out[sel] += w * k / k.sum()
+            out[cand[sel]] += w * k / k.sum()
     return out / (4 * np.pi / npix)

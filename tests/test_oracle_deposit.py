@@ -90,3 +90,16 @@ def test_smoothed_point_mass_app_e():
     assert np.abs(d["g_t"][sel] - dpsi[sel]).max() < 2e-3 * np.abs(dpsi[sel]).max()
     g1m = 0.5 * (d["U_tt"] - d["U_pp"])
     assert np.abs(g1m[sel] - g1[sel]).max() < 2e-2 * np.abs(g1[sel]).max()
+
+
+def test_candidate_pixels_change_nothing():
+    """Limiting the pixel centres tried to whole rings around the particles
+    gives the same map."""
+    N = 32
+    th, ph = np.array([0.5, 0.52, 3.1]), np.array([1.0, 1.1, 2.0])
+    w, sg = np.array([1.0, 2.0, 0.5]), np.array([0.05, 0.08, 0.06])
+    full = dep.deposit(N, th, ph, w, sg)
+    rt = hp.ring_table(N)
+    rings = np.nonzero(np.any(np.abs(rt["theta"][:, None] - th[None, :]) < 0.15, axis=1))[0]
+    pix = np.concatenate([rt["first"][r] + np.arange(rt["n"][r]) for r in rings])
+    np.testing.assert_array_equal(dep.deposit(N, th, ph, w, sg, pixels=pix), full)
