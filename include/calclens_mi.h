@@ -187,6 +187,32 @@ clm_status clm_plan_timings(clm_plan plan, double* ms_per_stage_host, int32_t ns
 const char* clm_plan_stage_name(clm_plan plan, int32_t i);
 
 /*
+ * Epanechnikov deposition of particles onto a HEALPix map (Sec. 3.2): the
+ * kernel K(theta; sigma) proportional to 1 - (theta / sigma)^2 inside the
+ * particle's smoothing angle sigma (App. E's normalised kernel), sampled
+ * at the pixel centres within sigma of the particle and normalised over
+ * them, so that every particle deposits exactly its weight (exact mass
+ * conservation); a particle whose sigma reaches no pixel centre deposits
+ * all of it in the pixel that contains it.  Adds
+ * weight_i W_i(p) / Omega_pix (Omega_pix = 4 pi / (12 nside^2)) into map_dev
+ * [12 nside^2] float64, RING order, so that the map holds mass per unit
+ * area (convergence when the weights are convergence times steradian).
+ * theta_dev, phi_dev, weight_dev, sigma_dev: [npart] float64, angles in
+ * radians; sigma <= 0 or non-finite deposits into the own pixel, sigma
+ * above pi is taken as pi; particles with a non-finite position are
+ * skipped.  The cost grows as sigma^2 (pixels per disc): meant for kernels
+ * of a few pixels.  Float64 atomic additions: the last bits depend on the
+ * order in which particles land.  Independent of any plan; accumulates, so
+ * the caller zeroes the map first; asynchronous on `stream`, no
+ * allocation.  Errors: CLM_EINVAL (sizes, pointers, nside not a power of
+ * two up to 8192).
+ */
+clm_status clm_deposit_epanechnikov(const double* theta_dev, const double* phi_dev,
+                                    const double* weight_dev, const double* sigma_dev,
+                                    int64_t npart, int32_t nside, double* map_dev,
+                                    hipStream_t stream);
+
+/*
  * Synthesis of a real field from a_lm (Sec. 3.2, the SHT synthesis):
  *   f(r, j) = sum_l a_l0 lambda_l0(theta_r)
  *             + 2 Re sum_{m>=1} [sum_l a_lm lambda_lm(theta_r)] e^{i m phi_rj}

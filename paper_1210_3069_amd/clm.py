@@ -74,6 +74,7 @@ _SIGS = {
     "clm_rays_init": (_P, ctypes.POINTER(Rays), _P),
     "clm_jacobian_spectra": (_P, ctypes.POINTER(Rays), _P, _P, _P),
     "clm_plan_set_domain": (_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64),
+    "clm_deposit_epanechnikov": (_P, _P, _P, _P, ctypes.c_int64, _I32, _P, _P),
     "clm_raytrace_planes": (_P, _P, _I32, ctypes.POINTER(_D), _I32, _I32, _I32, _D,
                             ctypes.POINTER(Rays), ctypes.POINTER(Galaxies), _P),
     "clm_ray_update": (_P, _I32, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays), _P),
@@ -137,6 +138,27 @@ def alm2map(alm, lmax, nside):
     st = lib().clm_alm2map(_ptr(a), lmax, nside, _ptr(out), _stream())
     if st != CLM_OK:
         raise ClmError(st, "clm_alm2map failed: %s" % lib().clm_status_string(st).decode())
+    return out
+
+
+def deposit_epanechnikov(theta, phi, weight, sigma, nside, out=None):
+    """Epanechnikov deposition of particles (float64 tensors on the GPU) onto
+    a RING map of nside, added into `out` (zeros when None); returns the map."""
+    for t in (theta, phi, weight, sigma):
+        _dev(t, torch.float64)
+    n = theta.numel()
+    if not (phi.numel() == weight.numel() == sigma.numel() == n):
+        raise ValueError("theta, phi, weight and sigma must have one value per particle")
+    if out is None:
+        out = torch.zeros(12 * nside * nside, dtype=torch.float64, device=theta.device)
+    _dev(out, torch.float64)
+    if out.numel() != 12 * nside * nside:
+        raise ValueError("out has %d values, expected %d" % (out.numel(), 12 * nside * nside))
+    st = lib().clm_deposit_epanechnikov(_ptr(theta), _ptr(phi), _ptr(weight), _ptr(sigma), n,
+                                        nside, _ptr(out), _stream())
+    if st != CLM_OK:
+        raise ClmError(st, "clm_deposit_epanechnikov failed: %s"
+                       % lib().clm_status_string(st).decode())
     return out
 
 
