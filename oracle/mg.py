@@ -26,6 +26,11 @@ Readings (the paper is silent or refers to an absent reference):
 * nu1 = nu2 = 2 red-black sweeps (red = (i+j) even first), levels down to
   4 x 4 solved exactly; injection on the outermost ring of fine cells;
 * the MG source is 2 x the HEALPix interpolation of the demeaned fine map;
+  with particles (Sec. 3.2: "a similar procedure is employed for the MG
+  patches") it is 2 x (the Epanechnikov deposition onto the patch cells
+  minus the mean), the deposition normalised over the cells of the patch's
+  grid continued beyond its faces, so that a particle's mass splits
+  between the patch and the outside exactly (patch_deposit);
 * raw partials are interpolated, the metric is applied at the point.
 """
 import numpy as np
@@ -322,11 +327,53 @@ def sht_stage(spec, kappa_fine_ring):
     return mean, ks, palm, psi
 
 
-def patch_setup(spec, b, kappa_fine_ring, mean, psi_sht_ring):
+def patch_deposit(spec, b, theta, phi, weight, sigma):
+    """Mass per unit area on the n x n cells of patch b from particles
+    (Sec. 3.2): each particle's Epanechnikov kernel K(angle) times the cell
+    area, over the cell centres of the patch grid (continued beyond the
+    faces) closer than sigma, normalised to the particle's weight; the part
+    on cells of the patch is kept.  A particle whose sigma reaches no cell
+    centre puts its weight in the cell that contains it (if in the patch).
+    Cell areas: Delta (cos theta'_{i-1/2} - cos theta'_{i+1/2})."""
+    from .deposit import kernel
+    n, d = spec.n, spec.delta
+    th0, ph0 = np.pi / 2 - spec.L / 2, -spec.L / 2
+    R = patch_rotation(spec.nb, b)
+    rho = np.zeros((n, n))
+    for t, p, w, sg in zip(theta, phi, weight, sigma):
+        v = R @ hp.vec(np.cos(t), p, np.sin(t))
+        tp = np.arctan2(np.hypot(v[0], v[1]), v[2])
+        pp = np.arctan2(v[1], v[0])
+        smin = max(np.sin(min(np.pi / 2 + spec.L / 2 + sg, np.pi - 1e-3)), 1e-3)
+        di, dj = int(sg / d) + 2, int(sg / (d * smin)) + 2
+        ic, jc = int(np.floor((tp - th0) / d)), int(np.floor((pp - ph0) / d))
+        ii = np.arange(ic - di, ic + di + 1)
+        jj = np.arange(jc - dj, jc + dj + 1)
+        tc = th0 + (ii + 0.5) * d
+        pc = ph0 + (jj + 0.5) * d
+        T, P = np.meshgrid(tc, pc, indexing="ij")
+        C = np.stack([np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)], -1)
+        ang = np.arctan2(np.linalg.norm(np.cross(C, v), axis=-1), C @ v)
+        area = (d * (np.cos(tc - 0.5 * d) - np.cos(tc + 0.5 * d)))[:, None]
+        k = kernel(ang, sg) if sg > 0 else np.zeros_like(ang)
+        tot = np.sum(k * area)
+        inside_i = (ii >= 0) & (ii < n)
+        inside_j = (jj >= 0) & (jj < n)
+        if tot > 0:
+            dens = w * k / tot
+            rho[np.ix_(ii[inside_i], jj[inside_j])] += dens[np.ix_(inside_i, inside_j)]
+        elif 0 <= ic < n and 0 <= jc < n:
+            a = d * (np.cos(th0 + ic * d) - np.cos(th0 + (ic + 1) * d))
+            rho[ic, jc] += w / a
+    return rho
+
+
+def patch_setup(spec, b, kappa_fine_ring, mean, psi_sht_ring, source=None):
     """u0 = interp(psi_SHT) at the cell centres (the starting guess) and
     Dirichlet data b = interp(psi_SHT) at the midpoints of the boundary faces
     (corner ghosts: at the patch corners), ghost u0 = 2 b - u0(adjacent
-    interior cell); f = 2 interp(kappa - mean) at the cell centres;
+    interior cell); f = 2 interp(kappa - mean) at the cell centres, or
+    f = 2 (source - mean) for a source on the cells (particles);
     f' = f - L u0.  Returns (R, u0 [n+2, n+2], f' [n, n])."""
     n, L = spec.n, spec.L
     R = patch_rotation(spec.nb, b)
@@ -352,8 +399,11 @@ def patch_setup(spec, b, kappa_fine_ring, mean, psi_sht_ring):
     u0[0, -1] = 2 * corners[1] - u0[1, -2]
     u0[-1, 0] = 2 * corners[2] - u0[-2, 1]
     u0[-1, -1] = 2 * corners[3] - u0[-2, -2]
-    f = 2.0 * (hp.interp(spec.nf, kappa_fine_ring, th.ravel(), ph.ravel()) - mean)
-    f = f.reshape(n, n)
+    if source is None:
+        f = 2.0 * (hp.interp(spec.nf, kappa_fine_ring, th.ravel(), ph.ravel()) - mean)
+        f = f.reshape(n, n)
+    else:
+        f = 2.0 * (source - mean)
     fp = f - apply_L(u0, level_coeffs(spec, n))
     return R, u0, fp
 
@@ -367,12 +417,16 @@ def mg_solve(spec, fp, vcycles=None):
     return du
 
 
-def solve_plane(spec, kappa_fine_ring, bundles):
-    """The full SHT+MG solve for the listed bundles."""
+def solve_plane(spec, kappa_fine_ring, bundles, particles=None):
+    """The full SHT+MG solve for the listed bundles.  With particles
+    (theta, phi, weight, sigma), kappa_fine_ring is their deposition on the
+    fine grid (it feeds the SHT stage) and each patch's source is their
+    deposition on its cells."""
     mean, ks, palm, psi = sht_stage(spec, kappa_fine_ring)
     patches = {}
     for b in bundles:
-        R, u0, fp = patch_setup(spec, b, kappa_fine_ring, mean, psi)
+        src = None if particles is None else patch_deposit(spec, b, *particles)
+        R, u0, fp = patch_setup(spec, b, kappa_fine_ring, mean, psi, source=src)
         du = mg_solve(spec, fp)
         patches[int(b)] = dict(R=R, u0=u0, du=du, fp=fp)
     return dict(mean=mean, kappa_sht=ks, psi_alm=palm, psi_sht=psi,
