@@ -207,10 +207,44 @@ const char* clm_plan_stage_name(clm_plan plan, int32_t i);
  * allocation.  Errors: CLM_EINVAL (sizes, pointers, nside not a power of
  * two up to 8192).
  */
+/* Particles of one lens plane, caller-owned device arrays of n float64:
+ * sky position (theta, phi, radians), weight (convergence times steradian)
+ * and Epanechnikov smoothing angle sigma (radians). */
+typedef struct {
+  const double* theta;
+  const double* phi;
+  const double* weight;
+  const double* sigma;
+  int64_t n;
+} clm_particles;
+
 clm_status clm_deposit_epanechnikov(const double* theta_dev, const double* phi_dev,
                                     const double* weight_dev, const double* sigma_dev,
                                     int64_t npart, int32_t nside, double* map_dev,
                                     hipStream_t stream);
+
+/*
+ * The lens-plane solve from particles (Sec. 3.2): the particles are
+ * deposited with the Epanechnikov kernel on the fine grid (as
+ * clm_deposit_epanechnikov), which feeds the SHT step exactly as a kappa
+ * map given to clm_poisson_solve does (its mean removed, degraded to the
+ * SHT grid).  In SHT+MG plans the multigrid source is the particles'
+ * deposition on each patch's cells instead of the interpolated fine map:
+ * the kernel times the cell area over the cell centres within sigma of the
+ * patch grid continued past its faces, normalised to the particle's weight,
+ * so that a particle's mass splits exactly between a patch and its outside;
+ * f = 2 (mass per area - mean).  The solve's results go to `slot` as with
+ * clm_poisson_solve.  The fine map is formed in the plan's multigrid
+ * workspace (SHT+MG plans; CLM_EUNSUPPORTED when that holds fewer than
+ * 8 x 12 nside_fine^2 bytes) or in its derivative workspace (SHT-only
+ * plans).  A partial-sky domain limits the patch deposition to its patches.
+ * Cost per particle grows as sigma^2 and, on the patches, with the number
+ * of patches its disc reaches (patches overlap: about patch_factor^2).
+ * Asynchronous on `stream`; no allocation.  Errors: CLM_EINVAL (pointers,
+ * slot), CLM_EUNSUPPORTED as above.
+ */
+clm_status clm_poisson_solve_particles(clm_plan plan, const clm_particles* particles,
+                                       int32_t slot, hipStream_t stream);
 
 /*
  * Synthesis of a real field from a_lm (Sec. 3.2, the SHT synthesis):

@@ -36,6 +36,11 @@ class Rays(ctypes.Structure):
                 ("A", ctypes.c_void_p), ("A_prev", ctypes.c_void_p), ("n", ctypes.c_int64)]
 
 
+class Particles(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("weight", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
 class Galaxies(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("chi", ctypes.c_void_p),
                 ("A", ctypes.c_void_p), ("n", ctypes.c_int64)]
@@ -75,6 +80,7 @@ _SIGS = {
     "clm_jacobian_spectra": (_P, ctypes.POINTER(Rays), _P, _P, _P),
     "clm_plan_set_domain": (_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64),
     "clm_deposit_epanechnikov": (_P, _P, _P, _P, ctypes.c_int64, _I32, _P, _P),
+    "clm_poisson_solve_particles": (_P, ctypes.POINTER(Particles), _I32, _P),
     "clm_raytrace_planes": (_P, _P, _I32, ctypes.POINTER(_D), _I32, _I32, _I32, _D,
                             ctypes.POINTER(Rays), ctypes.POINTER(Galaxies), _P),
     "clm_ray_update": (_P, _I32, ctypes.POINTER(_D), _I32, _I32, _D, ctypes.POINTER(Rays), _P),
@@ -361,6 +367,19 @@ class Plan:
             raise ValueError("kappa has %d pixels, plan expects %d" % (k.shape[1], self.npix_fine))
         self._check(lib().clm_poisson_solve(self.h, _ptr(k), int(k.dtype == torch.float64),
                                             first_slot, k.shape[0], _stream()), "poisson_solve")
+
+    def poisson_solve_particles(self, theta, phi, weight, sigma, slot=0):
+        """The plane solve from particles (float64 tensors on the GPU):
+        Epanechnikov deposition on the fine grid for the SHT step and, in
+        SHT+MG plans, on the patch cells for the multigrid source."""
+        for t in (theta, phi, weight, sigma):
+            _dev(t, torch.float64)
+        n = theta.numel()
+        if not (phi.numel() == weight.numel() == sigma.numel() == n):
+            raise ValueError("theta, phi, weight and sigma must have one value per particle")
+        pr = Particles(theta.data_ptr(), phi.data_ptr(), weight.data_ptr(), sigma.data_ptr(), n)
+        self._check(lib().clm_poisson_solve_particles(self.h, ctypes.byref(pr), slot, _stream()),
+                    "poisson_solve_particles")
 
     def mg_convergence(self):
         """(epsilon [nbundle] float64, V-cycles [nbundle] int32) of the latest

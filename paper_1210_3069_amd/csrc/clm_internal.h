@@ -299,8 +299,13 @@ clm_status sht_pixel_derivs_batch(Plan* p, int first_slot, int nplanes, int orde
                                   hipStream_t s);  // sht.hip
 clm_status sht_pixel_derivs(Plan* p, int slot, int order, int out_fp64,
                             void* grad, void* hess, hipStream_t s);  // sht.hip
+// kappa = nullptr with particles: the source is the particles' deposition
+// on the patch cells
 clm_status mg_solve(Plan* p, const void* kappa, int kappa_fp64, int slot,
-                    hipStream_t s);                     // mg.hip
+                    hipStream_t s, const clm_particles* parts = nullptr);  // mg.hip
+clm_status patch_deposit(Plan* p, const clm_particles* parts, hipStream_t s);  // deposit.hip
+clm_status deposit_map(const clm_particles* parts, int64_t nside, double* map,
+                       hipStream_t s);                  // deposit.hip: adds into a RING map
 int64_t setup_tiles(const Plan* p);                     // mg.hip: patch-setup tiles
 clm_status setup_tables(Plan* p, hipStream_t s);        // mg.hip: fills setup_meta
 clm_status mg_patch_potential(Plan* p, int slot, int64_t first, int64_t np,

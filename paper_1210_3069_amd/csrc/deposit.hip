@@ -137,7 +137,131 @@ __global__ __launch_bounds__(kBlock) void k_deposit(int64_t N, int64_t npart, co
   }
 }
 
+// ------------------------------------------------------------- patches
+// Sec. 3.2: the same smoothing binned over the multigrid patches' cells.
+// A particle's kernel times the cell area is taken over the cell centres of
+// the patch grid, continued past its faces, within sigma, and normalised
+// to its weight there; the cells of the patch get their share, so a
+// particle's mass splits exactly between a patch and its outside.  A
+// particle whose sigma reaches no cell centre puts its weight in the cell
+// that holds it.  The result enters the source as 2 x mass per area, added
+// into f' (the setup wrote -2 mean - L u0).
+struct PatchDep {
+  const double* th;
+  const double* ph;
+  const double* w;
+  const double* sg;
+  int64_t npart;
+  const double* rot;   // [nbundle][9] patch rotations
+  int64_t Nb;          // bundle grid
+  int n;               // cells per side
+  double L, delta;
+  const int* dflag;    // partial sky: 1 for a patch of the domain, or nullptr
+  void* fp;            // f' [patch][n][n] of T
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_patch_deposit(PatchDep a) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= a.npart) return;
+  if (!isfinite(a.th[t]) || !isfinite(a.ph[t])) return;
+  double st, ct, sp, cp;
+  sincos(a.th[t], &st, &ct);
+  sincos(a.ph[t], &sp, &cp);
+  const double p[3] = {st * cp, st * sp, ct};
+  const double theta = atan2(sqrt(p[0] * p[0] + p[1] * p[1]), p[2]);
+  double phi = atan2(p[1], p[0]);
+  if (phi < 0.0) phi += 2.0 * kPiD;
+  if (phi >= 2.0 * kPiD) phi = 0.0;
+  const double sigma = isfinite(a.sg[t]) && a.sg[t] > 0.0 ? fmin(a.sg[t], kPiD) : 0.0;
+  const double w2 = 2.0 * a.w[t];
+  const int n = a.n;
+  const double d = a.delta, th0 = 0.5 * kPiD - 0.5 * a.L, ph0 = -0.5 * a.L;
+  const double is2 = sigma > 0.0 ? 1.0 / (sigma * sigma) : 0.0;
+  const double smin = fmax(sin(fmin(0.5 * kPiD + 0.5 * a.L + sigma, kPiD - 1e-3)), 1e-3);
+  const int di = int(sigma / d) + 2, dj = int(sigma / (d * smin)) + 2;
+  T* fp = static_cast<T*>(a.fp);
+  // the patches whose square the disc can reach: bundle centres within
+  // 0.75 L + sigma (a patch's corners are L / sqrt 2 from its centre)
+  disc_pixels(a.Nb, p, theta, phi, 0.75 * a.L + sigma + 2.0 * d, [&](int64_t rb, double) {
+    double zb, sb, pb;
+    hpx::pix2ang_ring(a.Nb, rb, zb, sb, pb);
+    const int64_t b = hpx::ang2nest(a.Nb, zb, pb);
+    if (a.dflag && !a.dflag[b]) return;
+    const double* R = a.rot + 9 * b;
+    const double v0 = R[0] * p[0] + R[1] * p[1] + R[2] * p[2];
+    const double v1 = R[3] * p[0] + R[4] * p[1] + R[5] * p[2];
+    const double v2 = R[6] * p[0] + R[7] * p[1] + R[8] * p[2];
+    const double tp = atan2(sqrt(v0 * v0 + v1 * v1), v2), pp = atan2(v1, v0);
+    const int ic = int(floor((tp - th0) / d)), jc = int(floor((pp - ph0) / d));
+    if (ic + di < 0 || ic - di >= n || jc + dj < 0 || jc - dj >= n) return;
+    const double stp = sin(tp);
+    T* fb = fp + size_t(b) * n * n;
+    // angle to a cell centre by the haversine (accurate at small angles);
+    // the cell area 2 d sin(theta'_i) sin(d / 2)
+    auto visit = [&](auto&& f) {
+      for (int i = ic - di; i <= ic + di; ++i) {
+        const double ti = th0 + (i + 0.5) * d;
+        const double sti = sin(ti), hti = sin(0.5 * (ti - tp));
+        const double area = 2.0 * d * sti * sin(0.5 * d);
+        for (int j = jc - dj; j <= jc + dj; ++j) {
+          const double hpj = sin(0.5 * (ph0 + (j + 0.5) * d - pp));
+          const double hv = fmin(hti * hti + sti * stp * hpj * hpj, 1.0);
+          const double ang = 2.0 * asin(sqrt(hv));
+          if (ang < sigma) f(i, j, 1.0 - ang * ang * is2, area);
+        }
+      }
+    };
+    double tot = 0.0;
+    if (sigma > 0.0) visit([&](int, int, double k, double area) { tot += k * area; });
+    if (tot > 0.0) {
+      const double f = w2 / tot;
+      visit([&](int i, int j, double k, double) {
+        if (i >= 0 && i < n && j >= 0 && j < n)
+          unsafeAtomicAdd(fb + size_t(i) * n + j, T(f * k));
+      });
+    } else if (ic >= 0 && ic < n && jc >= 0 && jc < n) {
+      const double ti = th0 + (ic + 0.5) * d;
+      unsafeAtomicAdd(fb + size_t(ic) * n + jc, T(w2 / (2.0 * d * sin(ti) * sin(0.5 * d))));
+    }
+  });
+}
+
 }  // namespace
+
+clm_status patch_deposit(Plan* p, const clm_particles* parts, hipStream_t s) {
+  if (parts->n == 0) return CLM_OK;
+  PatchDep a;
+  a.th = parts->theta;
+  a.ph = parts->phi;
+  a.w = parts->weight;
+  a.sg = parts->sigma;
+  a.npart = parts->n;
+  a.rot = p->rot;
+  a.Nb = p->d.nside_bundle;
+  a.n = p->n;
+  a.L = p->L;
+  a.delta = p->delta;
+  a.dflag = p->domain ? p->dom_flag : nullptr;
+  a.fp = p->fprime;
+  const dim3 g(unsigned((parts->n + kBlock - 1) / kBlock));
+  CLM_TIMED(p, s, "patch_deposit");
+  if (p->fp64mg)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_patch_deposit<double>), g, dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_patch_deposit<float>), g, dim3(kBlock), 0, s, a);
+  CLM_LAUNCH_CHECK();
+  return CLM_OK;
+}
+
+clm_status deposit_map(const clm_particles* parts, int64_t nside, double* map, hipStream_t s) {
+  if (parts->n == 0) return CLM_OK;
+  const dim3 g(unsigned((parts->n + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_deposit, g, dim3(kBlock), 0, s, nside, parts->n, parts->theta,
+                     parts->phi, parts->weight, parts->sigma, map);
+  return hipGetLastError() == hipSuccess ? CLM_OK : CLM_EHIP;
+}
+
 }  // namespace clm
 
 extern "C" clm_status clm_deposit_epanechnikov(const double* theta, const double* phi,

@@ -53,7 +53,7 @@ struct SetupArgs {
   const double* coef;  // level-0 rows
   hpx::Rings rs, rf;
   const double* psi_s;
-  const void* kappa;
+  const void* kappa;   // fine map, or nullptr: f = -2 mean (particles add the rest)
   int kappa_fp64;
   const double* red;   // red[1023] = mean of kappa
   double* u0;          // [patch][(n+2)^2]
@@ -122,8 +122,9 @@ __device__ void setup_pass1(const SetupArgs& a, const TS& rs, const TF& rf, doub
         int pf[4];
         double wf[4];
         hpx::interp_weights_g(rf, gf, z, rho, dph, pf, wf);
-        double k4[4];
-        if (a.kappa_fp64) {
+        double k4[4] = {0.0, 0.0, 0.0, 0.0};  // no map: the source comes from particles
+        if (!a.kappa) {
+        } else if (a.kappa_fp64) {
           const double* km = static_cast<const double*>(a.kappa);
           for (int c = 0; c < 4; ++c) k4[c] = km[pf[c]];
         } else {
@@ -372,7 +373,9 @@ __device__ void setup_pass1_rec(const SetupArgs& a, const SetupRing* rf, const S
           ws[2] * map_at(a.psi_s, ps[2]) + ws[3] * map_at(a.psi_s, ps[3]);
       if (inner) {
         double kv;
-        if (a.kappa_fp64) {
+        if (!a.kappa) {
+          kv = 0.0;  // no map: the source comes from particles
+        } else if (a.kappa_fp64) {
           const double* km = static_cast<const double*>(a.kappa);
           kv = wf[0] * map_at(km, pf[0]) + wf[1] * map_at(km, pf[1]) +
                wf[2] * map_at(km, pf[2]) + wf[3] * map_at(km, pf[3]);
@@ -1621,7 +1624,8 @@ SetupArgs setup_geometry(const Plan* p) {
 }
 
 template <typename T>
-clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
+clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s,
+                  const clm_particles* parts) {
   const clm_plan_desc& d = p->d;
   Slot& sl = p->slots[slot];
   const int n = p->n;
@@ -1651,6 +1655,11 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
       }
     }
     CLM_LAUNCH_CHECK();
+  }
+  // particles: their deposition on the patch cells completes the source
+  if (parts) {
+    const clm_status st = patch_deposit(p, parts, s);
+    if (st != CLM_OK) return st;
   }
   T* du = static_cast<T*>(sl.du);
   T* dt = static_cast<T*>(p->dutmp);
@@ -1893,10 +1902,11 @@ clm_status setup_tables(Plan* p, hipStream_t s) {
   return CLM_OK;
 }
 
-clm_status mg_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s) {
+clm_status mg_solve(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStream_t s,
+                    const clm_particles* parts) {
   if (p->nlev > 16) return fail(p, CLM_EUNSUPPORTED, "too many multigrid levels");
-  return p->fp64mg ? run_mg<double>(p, kappa, kappa_fp64, slot, s)
-                   : run_mg<float>(p, kappa, kappa_fp64, slot, s);
+  return p->fp64mg ? run_mg<double>(p, kappa, kappa_fp64, slot, s, parts)
+                   : run_mg<float>(p, kappa, kappa_fp64, slot, s, parts);
 }
 
 clm_status mg_patch_potential(Plan* p, int slot, int64_t first, int64_t np, double* out,

@@ -330,6 +330,13 @@ clm_status build_tables(Plan* p) {
 
 using namespace clm;
 
+namespace clm {
+__global__ void k_zero_f64(int64_t n, double* y) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = 0.0;
+}
+}  // namespace clm
+
 extern "C" {
 
 const char* clm_status_string(clm_status s) {
@@ -707,6 +714,36 @@ clm_status clm_poisson_solve(clm_plan plan, const void* kappa, int32_t kappa_is_
     }
   }
   return CLM_OK;
+}
+
+clm_status clm_poisson_solve_particles(clm_plan plan, const clm_particles* parts, int32_t slot,
+                                       hipStream_t stream) {
+  if (!plan || !parts || parts->n < 0 || slot < 0 || slot >= plan->d.max_planes ||
+      (parts->n > 0 && (!parts->theta || !parts->phi || !parts->weight || !parts->sigma)))
+    return CLM_EINVAL;
+  Plan* p = plan;
+  CLM_HIP(hipSetDevice(p->device));
+  double* map = nullptr;
+  if (p->mg) {
+    const size_t ws = size_t(p->nbundle) * p->n * p->n * (p->fp64mg ? 8 : 4);
+    if (ws < size_t(p->npix_f) * 8)
+      return fail(p, CLM_EUNSUPPORTED, "particles: patches too coarse to hold the fine map");
+    map = static_cast<double*>(p->dutmp);
+  } else {
+    map = p->deriv;
+  }
+  hipLaunchKernelGGL(clm::k_zero_f64, dim3(unsigned((p->npix_f + 255) / 256)), dim3(256), 0,
+                     stream, p->npix_f, map);
+  CLM_LAUNCH_CHECK();
+  clm_status s = deposit_map(parts, p->d.nside_fine, map, stream);
+  if (s != CLM_OK) return s;
+  if (p->batch > 0)
+    s = sht_solve_batch(p, map, 1, slot, 1, stream);
+  else
+    s = sht_solve(p, map, 1, slot, stream);
+  if (s != CLM_OK || !p->mg) return s;
+  if (p->batch > 0 && (s = plane_mean(p, map, 1, stream)) != CLM_OK) return s;
+  return mg_solve(p, nullptr, 1, slot, stream, parts);
 }
 
 clm_status clm_poisson_solve_multi(const clm_plan* plans, int32_t nplans,

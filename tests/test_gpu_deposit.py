@@ -86,3 +86,91 @@ def test_deposit_errors(clm):
                                           n, ns, clm._ptr(m), None) == clm.CLM_EINVAL
     assert L.clm_deposit_epanechnikov(None, None, None, None, 0, 4, clm._ptr(m),
                                       None) == clm.CLM_OK
+
+
+# ------------------------------------------------------- the plane solve
+from oracle import mg as omg  # noqa: E402
+from oracle import sht as osht  # noqa: E402
+
+NF, NS, LMAX, NB = 64, 16, 32, 4
+
+
+@pytest.fixture(scope="module")
+def plane_particles():
+    th, ph, w, sg = inputs.particle_cone(1500, seed=21, nside=NF)
+    kfine = odep.deposit(NF, th, ph, w, sg)
+    return th, ph, w, sg, kfine
+
+
+@pytest.mark.parametrize("n,prec", [(64, "fp64"), (256, "fp64"), (64, "fp32")])
+def test_particle_solve_matches_oracle(clm, plane_particles, n, prec):
+    """SHT+MG from particles: the fine-grid deposition feeds the SHT, the
+    patch-cell deposition the multigrid; u = u0 + du of three patches (one
+    polar) against the oracle's solve from the same particles."""
+    th, ph, w, sg, kfine = plane_particles
+    bundles = [15, 77, 130]
+    spec = omg.PatchSpec(NF, NS, LMAX, NB, ncell=n, vcycles=3)
+    sol = omg.solve_plane(spec, kfine, bundles, particles=(th, ph, w, sg))
+    plan = clm.Plan(NF, nside_sht=NS, lmax=LMAX, nside_bundle=NB, patch_cells=n, mg_vcycles=3,
+                    mg_prec=prec)
+    plan.poisson_solve_particles(*cuda(th, ph, w, sg))
+    plan.sync_status()
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    assert np.abs(plan.psi_alm().cpu().numpy() - sol["psi_alm"]).max() < \
+        1e-10 * np.abs(sol["psi_alm"]).max()
+    for b in bundles:
+        pt = sol["patches"][b]
+        ref = (pt["u0"] + pt["du"])[1:-1, 1:-1]
+        got = plan.patch_potential(b, 1)[0].cpu().numpy()
+        e = np.abs(got - ref).max() / np.abs(ref).max()
+        print("PARITY particle solve n=%d %s b=%d %.2e" % (n, prec, b, e), flush=True)
+        assert e < tol, (b, e)
+    plan.close()
+
+
+def test_particle_solve_sht_only(clm, plane_particles):
+    th, ph, w, sg, kfine = plane_particles
+    plan = clm.Plan(NF, nside_sht=NF, lmax=2 * NF, solver="sht")
+    plan.poisson_solve_particles(*cuda(th, ph, w, sg))
+    ref = osht.poisson(2 * NF, osht.map2alm(NF, 2 * NF, kfine - kfine.mean()))
+    got = plan.psi_alm().cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max()
+    plan.sync_status()
+    plan.close()
+
+
+def test_particle_point_mass_app_e(clm):
+    """The paper's point-mass test (Sec. 4) on the GPU: one particle at the
+    centre of bundle 77 (Nside 64 rays, SHT at Nside 32, 64^2 patches),
+    deflection around it against App. E: within the paper's bounds (max
+    error 5 %, rms 1-2 %)."""
+    spec = omg.PatchSpec(64, 32, 64, 4, ncell=64)
+    b = 77
+    R = omg.patch_rotation(4, b)
+    sg = 3 * np.sqrt(4 * np.pi / (12 * 64 * 64))
+    t0, p0 = (float(x[0]) for x in omg.patch_dirs(spec, R, np.array([np.pi / 2]),
+                                                     np.array([0.0])))
+    plan = clm.Plan(64, nside_sht=32, lmax=64, nside_bundle=4, patch_cells=64, mg_vcycles=4,
+                    mg_prec="fp64")
+    plan.poisson_solve_particles(*cuda([t0], [p0], [0.5], [sg]))
+    k = np.arange(40)
+    r = sg * (1.3 + 2.5 * k / 40)
+    a = 2 * np.pi * k / 7.3
+    tt, pp = omg.patch_dirs(spec, R, np.pi / 2 + r * np.cos(a), r * np.sin(a))
+    g, _ = plan.shear_from_potential(*cuda(tt, pp))
+    g = g.cpu().numpy()
+    n0 = hp.vec(np.cos(t0), p0)
+    v = hp.vec(np.cos(tt), pp)
+    ang = np.arctan2(np.linalg.norm(np.cross(v, n0), axis=1), v @ n0)
+    sinc = np.sinc
+    nrm = 2 * np.pi * (sinc(sg / (2 * np.pi)) ** 2 - 2 * sinc(sg / np.pi) + 1)
+    c = np.cos(ang)
+    h = ((ang / sg) ** 2 * (-2 * sinc(ang / np.pi) + c + sinc(ang / 2 / np.pi) ** 2)
+         + 1 - c) / (nrm * (1 - c)) - 1 / (4 * np.pi)
+    dpsi = np.where(ang < sg, h * (1 - c) / np.sin(ang), np.sin(ang) / (4 * np.pi * (1 - c)))
+    err = np.abs(np.hypot(g[0], g[1]) - np.abs(dpsi)) / np.abs(dpsi)
+    print("PARITY point mass max %.3f rms %.3f" % (err.max(), np.sqrt(np.mean(err ** 2))),
+          flush=True)
+    assert err.max() < 0.05 and np.sqrt(np.mean(err ** 2)) < 0.02
+    plan.sync_status()
+    plan.close()
