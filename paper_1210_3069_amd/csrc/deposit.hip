@@ -178,8 +178,14 @@ __global__ __launch_bounds__(kBlock) void k_patch_deposit(PatchDep a) {
   const int n = a.n;
   const double d = a.delta, th0 = 0.5 * kPiD - 0.5 * a.L, ph0 = -0.5 * a.L;
   const double is2 = sigma > 0.0 ? 1.0 / (sigma * sigma) : 0.0;
+  const double hs = sin(0.5 * sigma), hs2 = hs * hs;  // hav(sigma)
+  double sh, ch;                                     // sin, cos of half a cell
+  sincos(0.5 * a.delta, &sh, &ch);
   const double smin = fmax(sin(fmin(0.5 * kPiD + 0.5 * a.L + sigma, kPiD - 1e-3)), 1e-3);
-  const int di = int(sigma / d) + 2, dj = int(sigma / (d * smin)) + 2;
+  // cells within sigma lie within sigma / d + 1/2 cells of the particle's
+  // fractional cell coordinate, so this window (from the cell holding it)
+  // contains them all
+  const int di = int(sigma / d + 0.5) + 1, dj = int(sigma / (d * smin) + 0.5) + 1;
   T* fp = static_cast<T*>(a.fp);
   // the patches whose square the disc can reach: bundle centres within
   // 0.75 L + sigma (a patch's corners are L / sqrt 2 from its centre)
@@ -197,18 +203,36 @@ __global__ __launch_bounds__(kBlock) void k_patch_deposit(PatchDep a) {
     if (ic + di < 0 || ic - di >= n || jc + dj < 0 || jc - dj >= n) return;
     const double stp = sin(tp);
     T* fb = fp + size_t(b) * n * n;
-    // angle to a cell centre by the haversine (accurate at small angles);
-    // the cell area 2 d sin(theta'_i) sin(d / 2)
+    // angle to a cell centre by the haversine (accurate at small angles):
+    // hav = sin^2(dtheta / 2) + sin theta'_i sin theta'_p sin^2(dphi / 2),
+    // inside sigma when hav < sin^2(sigma / 2); the sines of the half azimuth
+    // offsets by the angle-addition recurrence along the row.  The cell area
+    // is 2 d sin(theta'_i) sin(d / 2).
+    // Row i holds cells of the disc only where sin^2(dphi / 2) <
+    // (hav(sigma) - sin^2(dtheta / 2)) / (sin theta'_i sin theta'_p): its
+    // window is cut to that azimuth range, widened by a cell.
     auto visit = [&](auto&& f) {
       for (int i = ic - di; i <= ic + di; ++i) {
         const double ti = th0 + (i + 0.5) * d;
         const double sti = sin(ti), hti = sin(0.5 * (ti - tp));
-        const double area = 2.0 * d * sti * sin(0.5 * d);
-        for (int j = jc - dj; j <= jc + dj; ++j) {
-          const double hpj = sin(0.5 * (ph0 + (j + 0.5) * d - pp));
-          const double hv = fmin(hti * hti + sti * stp * hpj * hpj, 1.0);
-          const double ang = 2.0 * asin(sqrt(hv));
-          if (ang < sigma) f(i, j, 1.0 - ang * ang * is2, area);
+        const double area = 2.0 * d * sti * sh;
+        const double h2 = hti * hti, ss = sti * stp;
+        if (h2 >= hs2) continue;
+        const double q = ss > 0.0 ? (hs2 - h2) / ss : 2.0;
+        const double dph = q >= 1.0 ? 2.0 * kPiD : 2.0 * asin(sqrt(q));
+        const int jlo = max(jc - dj, int(floor((pp - dph - ph0) / d - 0.5)) - 1);
+        const int jhi = min(jc + dj, int(ceil((pp + dph - ph0) / d - 0.5)) + 1);
+        double sa, ca;
+        sincos(0.5 * (ph0 + (jlo + 0.5) * d - pp), &sa, &ca);
+        for (int j = jlo; j <= jhi; ++j) {
+          const double hv = fmin(fma(ss * sa, sa, h2), 1.0);
+          if (hv < hs2) {
+            const double ang = 2.0 * hpx::asin_small(sqrt(hv));
+            f(i, j, 1.0 - ang * ang * is2, area);
+          }
+          const double sn = fma(sa, ch, ca * sh);
+          ca = fma(ca, ch, -sa * sh);
+          sa = sn;
         }
       }
     };
