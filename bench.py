@@ -501,6 +501,60 @@ def partial_sky_run(clm, torch, kappa, gal, steps, warmup, full_ms):
                          "sky (theta0 120 deg, half-angle 41.4 deg)")
 
 
+def particles_run(clm, torch, inputs, npart=4_000_000):
+    """Sec. 3.2's input path: one lens plane from particles at the headline
+    geometry (fine grid Nside 2048, SHT Nside 256 / lmax 512, 12,288
+    patches of 256^2, 4 V-cycles, float32 multigrid).  A synthetic particle
+    light cone (half field, half in halos; smoothing angles of 2-3 fine
+    pixels), ordered by latitude-longitude tile of about 0.7 degrees (part
+    of the input recipe) so that neighbouring threads deposit into
+    neighbouring cells.  Timed: the Epanechnikov deposition on the fine
+    grid, the SHT, the patch setup, the deposition on the patch cells and
+    the V-cycles."""
+    th, ph, w, sg = inputs.particle_cone(npart, seed=5, nside=NF)
+    key = inputs.sky_order(th, ph, 256)
+    args = [torch.from_numpy(np.ascontiguousarray(x[key])).cuda() for x in (th, ph, w, sg)]
+    plan = clm.Plan(NF, nside_sht=NS, lmax=LMAX, nside_bundle=NB, patch_cells=NCELL,
+                    mg_vcycles=VCYC, mg_prec="fp32")
+    plan.poisson_solve_particles(*args)                 # kernel set-up
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    t0.record()
+    for _ in range(reps):
+        plan.poisson_solve_particles(*args)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    plan.set_timing(True)
+    plan.get_timing()
+    plan.poisson_solve_particles(*args)
+    st = plan.get_timing()
+    plan.set_timing(False)
+    plan.sync_status()
+    plan.close()
+    m = torch.zeros(12 * NF * NF, dtype=torch.float64, device="cuda")
+    clm.deposit_epanechnikov(*args, NF, out=m)
+    torch.cuda.synchronize()
+    t0.record()
+    clm.deposit_epanechnikov(*args, NF, out=m)
+    t1.record()
+    torch.cuda.synchronize()
+    map_ms = t0.elapsed_time(t1)
+    mass = float(m.sum()) * 4 * np.pi / (12 * NF * NF) / 2.0   # two depositions
+    pd = st.get("patch_deposit", (0.0, 1))[0]
+    del m, args
+    torch.cuda.empty_cache()
+    return dict(particles=npart, ms_per_plane=ms, planes_per_s=1000.0 / ms,
+                stage_ms={k: v[0] for k, v in st.items() if v[1]},
+                fine_map_deposit_ms=map_ms, fine_map_particles_per_s=npart / (map_ms * 1e-3),
+                patch_deposit_particles_per_s=npart / (pd * 1e-3) if pd else None,
+                mass_conservation_rel=abs(mass - float(w.sum())) / float(w.sum()),
+                workload="one plane from %d particles at the headline geometry (Nside 2048 "
+                         "fine grid, SHT Nside 256 / lmax 512, 12,288 patches of 256^2, "
+                         "4 V-cycles)" % npart)
+
+
 def c3_run(clm, torch, inputs, cosmo, gal):
     """Multiplane ray tracing: 20 lens planes at chi_m = (m + 1/2) dchi to
     z = 1.5, each an Nside 2048 lognormal kappa (sigma_g 0.1 -> 0.6 with the
@@ -1013,6 +1067,8 @@ def parse_args(argv=None):
                     help="skip the differentiation workload (8 planes, chi^2 gradient)")
     ap.add_argument("--no-pure-sht", action="store_true",
                     help="skip the pure-SHT production path (8 planes at Nside 2048)")
+    ap.add_argument("--no-particles", action="store_true",
+                    help="skip the plane from particles (Epanechnikov deposition)")
     ap.add_argument("--no-partial-sky", action="store_true",
                     help="skip the partial-sky run (the headline step over 1/8 of the sky)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -1190,6 +1246,9 @@ def main():
     if not args.no_partial_sky:
         print("bench: partial sky", file=sys.stderr, flush=True)
         out["partial_sky"] = partial_sky_run(clm, torch, kappa, gal, args.steps, args.warmup, ms)
+    if not args.no_particles:
+        print("bench: plane from particles", file=sys.stderr, flush=True)
+        out["particles_plane"] = particles_run(clm, torch, inputs)
     if not args.no_c3:
         print("bench: multiplane ray tracing", file=sys.stderr, flush=True)
         out["c3_multiplane"] = c3_run(clm, torch, inputs, cosmo, gal)

@@ -122,3 +122,15 @@ def particle_cone(n, seed, nside, halo_fraction=0.5, halo_radius=2e-3):
     pix = np.sqrt(4.0 * np.pi / (12.0 * nside * nside))
     sigma = pix * rng.uniform(2.0, 3.0, n)
     return th, phi, w, sigma
+
+
+def sky_order(theta, phi, ntheta):
+    """Indices that order points by latitude-longitude tile (ntheta bands in
+    theta, tiles of about equal width in each band, band after band): the
+    input order of the deposition benchmarks, so that neighbouring threads
+    handle neighbouring particles."""
+    band = np.minimum((theta / np.pi * ntheta).astype(np.int64), ntheta - 1)
+    width = np.maximum(1, np.round(2 * ntheta * np.sin((band + 0.5) * np.pi / ntheta)))
+    tile = np.minimum((np.mod(phi, 2 * np.pi) / (2 * np.pi) * width).astype(np.int64),
+                      width.astype(np.int64) - 1)
+    return np.lexsort((tile, band))
