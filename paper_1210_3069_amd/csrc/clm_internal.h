@@ -130,6 +130,13 @@ struct Plan {
   // grids that bracket the tile's region and its reference azimuth, which
   // depend on the plan's geometry only (kSetupMetaBytes each)
   char* setup_meta = nullptr;
+  // the SHT potential and the fine map as the patch setup reads them in its
+  // common case: every ring followed and preceded by pad_s (pad_f) copies of
+  // its pixels from the other end, ring q starting at first_q + 2 q pad, so
+  // that the two pixels around an azimuth sit side by side without a wrap
+  double* spad = nullptr;       // [npix_s + 2 pad_s nring_s]
+  void* kpad = nullptr;         // [npix_f + 2 pad_f nring_f], the fine map's type
+  int pad_s = 0, pad_f = 0;
   int* status_dev = nullptr;
   double* mg_eps_dev = nullptr;   // [nbundle] epsilon ratio of the latest solve
   int* mg_cycles_dev = nullptr;   // [nbundle] V-cycles run
@@ -307,6 +314,7 @@ clm_status patch_deposit(Plan* p, const clm_particles* parts, hipStream_t s);  /
 clm_status deposit_map(const clm_particles* parts, int64_t nside, double* map,
                        hipStream_t s);                  // deposit.hip: adds into a RING map
 int64_t setup_tiles(const Plan* p);                     // mg.hip: patch-setup tiles
+int setup_ring_pad(int nside);                          // mg.hip: pad_s / pad_f of a grid
 clm_status setup_tables(Plan* p, hipStream_t s);        // mg.hip: fills setup_meta
 clm_status mg_patch_potential(Plan* p, int slot, int64_t first, int64_t np,
                               double* out, hipStream_t s);  // mg.hip

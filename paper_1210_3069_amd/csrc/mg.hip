@@ -31,6 +31,19 @@ namespace {
 constexpr int kBlock = 256;
 constexpr double kPi = 3.14159265358979323846;
 
+// Element i of an array whose base is the same for the whole workgroup, as
+// an unsigned 32-bit byte offset (level arrays of a patch stay far below
+// 2^30 elements): the access takes the base in scalar registers and one
+// offset register, with no 64-bit address arithmetic per lane.
+template <typename T>
+__device__ __forceinline__ T* at(T* base, unsigned i) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * unsigned(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const T* at(const T* base, unsigned i) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * unsigned(sizeof(T)));
+}
+
 // ------------------------------------------------------------ patch setup
 // u0 = interp(psi_SHT) at the cell centres; ghost u0 = 2 b - u0(adjacent)
 // with b = interp(psi_SHT) at the face midpoint (corner: patch corner);
@@ -56,6 +69,9 @@ struct SetupArgs {
   const void* kappa;   // fine map, or nullptr: f = -2 mean (particles add the rest)
   int kappa_fp64;
   const double* red;   // red[1023] = mean of kappa
+  const double* spad;  // psi_s with padded rings (pad_s), read in the common case
+  const void* kpad;    // kappa with padded rings (pad_f), its type
+  int pad_s, pad_f;
   double* u0;          // [patch][(n+2)^2]
   void* fprime;        // [patch][n^2] of T
   SetupMeta* meta;     // [patch][tile]
@@ -83,6 +99,12 @@ __device__ __forceinline__ void patch_dir(const double* R, double st, double ct,
 constexpr int kRingCapF = 192, kRingCapS = 96;
 constexpr int kSetupBlock = 512;
 constexpr int kLdsBlock = 512;
+
+// The setup's common case: azimuth offsets from the tile's reference
+// azimuth below asin(kSetupSeries) (the series asin), so that a ring of n
+// pixels is read at most asin(kSetupSeries) n / (2 pi) < 0.0319 nside pixels
+// beyond either end (n <= 4 nside); setup_ring_pad covers that.
+constexpr double kSetupSeries = 0.05;
 
 // Reference azimuth of a setup block (the region centre's).
 struct PhiRef {
@@ -195,13 +217,13 @@ __device__ void setup_passes23(const SetupArgs& a, double* shu, const T* fsh,
     // write u0: the tile's cells, plus the patch ghosts beside this tile
     const bool own_i = (li >= 1 && li <= TILE) || (gi == -1) || (gi == n);
     const bool own_j = (lj >= 1 && lj <= TILE) || (gj == -1) || (gj == n);
-    if (own_i && own_j) u0[size_t(gi + 1) * G + (gj + 1)] = shu[idx];
+    if (own_i && own_j) *at(u0, unsigned((gi + 1) * (n + 2) + gj + 1)) = shu[idx];
     if (!(li >= 1 && li <= TILE && lj >= 1 && lj <= TILE)) continue;
     const double* q = prow + 4 * (li - 1);  // c_minus, c_plus, 1 / s_c, 1 / A of the row
     const double u = shu[idx];
     const double Lu = (q[0] * (shu[idx - RR] - u) + q[1] * (shu[idx + RR] - u) +
                        (shu[idx - 1] - 2.0 * u + shu[idx + 1]) * q[2]) * q[3];
-    T* fo = fp + size_t(gi) * n + gj;
+    T* fo = at(fp, unsigned(gi * n + gj));
     const double f = fsh ? double(fsh[(li - 1) * TILE + (lj - 1)]) : double(*fo);
     *fo = T(f - Lu);
   }
@@ -216,7 +238,7 @@ struct alignas(16) SetupRing {
   double gbelow;   // 1 / (theta_{q+1} - theta_q) (last ring: 1 / (pi - theta_q))
   double off;      // fine rings: theta_q - theta of the SHT ring above them
                    // (0 above the first SHT ring); 0 for SHT rings
-  int n, first;
+  int n, first;    // pixels; the ring's pixel 0 in the padded map
 };
 static_assert(sizeof(SetupRing) == 64, "ring record size");
 
@@ -232,11 +254,11 @@ struct RecTab {
   __device__ __forceinline__ int hi() const { return top == nr - 1 ? top : top - 1; }
 };
 
-// All threads of the block: rings b .. t of grid R into the record store;
-// fine rings (shift >= 0) also get their offset to the SHT ring above,
-// from the SHT grid's theta column rt_s.
+// All threads of the block: rings b .. t of grid R (padded by pad pixels per
+// side) into the record store; fine rings (shift >= 0) also get their offset
+// to the SHT ring above, from the SHT grid's theta column rt_s.
 __device__ void fill_records(SetupRing* st, const hpx::Rings& R, int b, int t, double phi_ref,
-                             int shift, const double* rt_s) {
+                             int shift, const double* rt_s, int pad) {
   for (int k = threadIdx.x; k <= t - b; k += blockDim.x) {
     const int q = b + k;
     SetupRing r;
@@ -251,40 +273,9 @@ __device__ void fill_records(SetupRing* st, const hpx::Rings& R, int b, int t, d
       r.off = R.rt[4 * q + 2] - (gs >= 0 ? rt_s[4 * gs + 2] : 0.0);
     }
     r.n = R.ri[2 * q];
-    r.first = R.ri[2 * q + 1];
+    r.first = R.ri[2 * q + 1] + (2 * q + 1) * pad;
     st[k] = r;
   }
-}
-
-// The two pixels of ring r around azimuth offset dphi and the weight of the
-// second.
-__device__ __forceinline__ void rec_pair(const SetupRing& r, double dphi, int& a, int& b,
-                                         double& wp) {
-  const double t = fma(dphi, r.k, r.t0);
-  const double fl = floor(t);
-  wp = t - fl;
-  int i1 = int(fl);
-  i1 += i1 < 0 ? r.n : 0;
-  i1 -= i1 >= r.n ? r.n : 0;
-  i1 = min(max(i1, 0), r.n - 1);  // azimuths outside (-pi, 3 pi) only
-  a = r.first + i1;
-  b = i1 + 1 == r.n ? r.first : a + 1;
-}
-
-// Bilinear weights between rings A (above) and B (below) for a point at
-// theta - theta_A = dth.
-__device__ __forceinline__ void rec_weights(const SetupRing& A, const SetupRing& B, double dth,
-                                            double dphi, int pix[4], double w[4]) {
-  int a1, a2, b1, b2;
-  double wa, wb;
-  rec_pair(A, dphi, a1, a2, wa);
-  rec_pair(B, dphi, b1, b2, wb);
-  const double wt = dth * A.gbelow;
-  pix[0] = a1; pix[1] = a2; pix[2] = b1; pix[3] = b2;
-  w[0] = (1 - wt) * (1 - wa);
-  w[1] = (1 - wt) * wa;
-  w[2] = wt * (1 - wb);
-  w[3] = wt * wb;
 }
 
 // Element p of a map whose base is the same for the whole wave: the index
@@ -297,15 +288,46 @@ __device__ __forceinline__ T map_at(const T* base, int p) {
                                      unsigned(p) * unsigned(sizeof(T)));
 }
 
+// Pixels p and p + 1 of a map in one load (element alignment only).
+template <typename T>
+struct alignas(sizeof(T)) Pair {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ Pair<T> pair_at(const T* base, int p) {
+  return *reinterpret_cast<const Pair<T>*>(reinterpret_cast<const char*>(base) +
+                                           unsigned(p) * unsigned(sizeof(T)));
+}
+
+// HEALPix bilinear interpolation of a ring-padded map between rings A
+// (above) and B (below) at theta - theta_A = dth and azimuth offset dphi
+// (|dphi| < asin kSetupSeries, which the padding covers): in each ring the
+// pixels i = floor(t), i + 1 around t = (phi - phi_0) n / (2 pi), weight
+// t - i on the second; along theta weight dth / (theta_B - theta_A) on ring
+// B.  The same weights as the general path, in linear-interpolation form.
+template <typename M>
+__device__ __forceinline__ double pair_interp(const M* map, const SetupRing& A,
+                                              const SetupRing& B, double dth, double dphi) {
+  const double ta = fma(dphi, A.k, A.t0), tb = fma(dphi, B.k, B.t0);
+  const double fa = floor(ta), fb = floor(tb);
+  const Pair<M> pa = pair_at(map, A.first + int(fa));
+  const Pair<M> pb = pair_at(map, B.first + int(fb));
+  const double va = fma(ta - fa, double(pa.y) - double(pa.x), double(pa.x));
+  const double vb = fma(tb - fb, double(pb.y) - double(pb.x), double(pb.x));
+  return fma(dth * A.gbelow, vb - va, va);
+}
+
 // Pass 1 of the setup with record stores: the global direction of a cell
 // from per-row coefficients (z, and the cos/sin-weighted components along
 // the reference azimuth, each A + B cos phi' + C sin phi') and the column's
 // cos/sin phi'; rho and 1 / rho from the hardware reciprocal square root
 // refined by two Newton steps; the azimuth offset as asin(sn / rho).  The
 // fine-grid theta offset comes from its upper ring, the SHT grid's from it
-// plus the tabulated difference of the two rings' colatitudes.  Cells whose
-// rings are not both in the stores (poles, wide regions) and azimuth
-// offsets beyond the series take the general path on the global tables.
+// plus the tabulated difference of the two rings' colatitudes.  Cells with
+// an azimuth offset below asin kSetupSeries and rings in the stores (the
+// common case) interpolate the ring-padded maps; the others (poles, wide
+// regions) take the general path on the global tables and the plain maps.
 template <typename T, int TILE>
 __device__ void setup_pass1_rec(const SetupArgs& a, const SetupRing* rf, const SetupMeta& m,
                                 const SetupRing* rs, double* shu, T* fsh, const double* rowc,
@@ -346,44 +368,56 @@ __device__ void setup_pass1_rec(const SetupArgs& a, const SetupRing* rf, const S
         rho = sqrt(r2);
       }
       const double sd = sn * irho;
-      if (fast && cs > 0.0 && fabs(sd) < 0.05) {
-        dphi = hpx::asin_small(sd);
+      const bool series = fast && cs > 0.0 && fabs(sd) < kSetupSeries;
+      if (series) {
+        dphi = hpx::asin_series(sd);
       } else {
         dphi = hpx::atan2_r(sn, cs);
         if (!fast) rho = sqrt(r2);
       }
       const int gf = hpx::ring_above(tf, z);
-      int ps[4], pf[4];
-      double ws[4], wf[4];
       const bool inner = li >= 1 && li <= TILE && lj >= 1 && lj <= TILE;
       const int gsr = ((gf + 1) >> a.ring_shift) - 1;
-      if (fast && gf >= m.bf && gf < m.tf) {
+      double kv = 0.0;  // no map: the source comes from particles
+      if (series && gf >= m.bf && gf < m.tf) {
         const SetupRing& A = rf[gf - m.bf];
         const double dthf = hpx::asin_small(fma(rho, A.z, -z * A.s));
-        if (inner) rec_weights(A, rf[gf - m.bf + 1], dthf, dphi, pf, wf);
-        if (gsr >= m.bs && gsr < m.ts)
-          rec_weights(rs[gsr - m.bs], rs[gsr - m.bs + 1], dthf + A.off, dphi, ps, ws);
-        else
-          hpx::interp_weights_g(gss, min(max(gsr, -1), a.rs.nring - 1), z, rho, dphi, ps, ws);
-      } else {
-        if (inner) hpx::interp_weights_g(gfs, gf, z, rho, dphi, pf, wf);
-        hpx::interp_weights_g(gss, min(max(gsr, -1), a.rs.nring - 1), z, rho, dphi, ps, ws);
-      }
-      v = ws[0] * map_at(a.psi_s, ps[0]) + ws[1] * map_at(a.psi_s, ps[1]) +
-          ws[2] * map_at(a.psi_s, ps[2]) + ws[3] * map_at(a.psi_s, ps[3]);
-      if (inner) {
-        double kv;
-        if (!a.kappa) {
-          kv = 0.0;  // no map: the source comes from particles
-        } else if (a.kappa_fp64) {
-          const double* km = static_cast<const double*>(a.kappa);
-          kv = wf[0] * map_at(km, pf[0]) + wf[1] * map_at(km, pf[1]) +
-               wf[2] * map_at(km, pf[2]) + wf[3] * map_at(km, pf[3]);
-        } else {
-          const float* km = static_cast<const float*>(a.kappa);
-          kv = wf[0] * double(map_at(km, pf[0])) + wf[1] * double(map_at(km, pf[1])) +
-               wf[2] * double(map_at(km, pf[2])) + wf[3] * double(map_at(km, pf[3]));
+        if (inner && a.kappa) {
+          const SetupRing& B = rf[gf - m.bf + 1];
+          kv = a.kappa_fp64 ? pair_interp(static_cast<const double*>(a.kpad), A, B, dthf, dphi)
+                            : pair_interp(static_cast<const float*>(a.kpad), A, B, dthf, dphi);
         }
+        if (gsr >= m.bs && gsr < m.ts) {
+          v = pair_interp(a.spad, rs[gsr - m.bs], rs[gsr - m.bs + 1], dthf + A.off, dphi);
+        } else {
+          int ps[4];
+          double ws[4];
+          hpx::interp_weights_g(gss, min(max(gsr, -1), a.rs.nring - 1), z, rho, dphi, ps, ws);
+          v = ws[0] * map_at(a.psi_s, ps[0]) + ws[1] * map_at(a.psi_s, ps[1]) +
+              ws[2] * map_at(a.psi_s, ps[2]) + ws[3] * map_at(a.psi_s, ps[3]);
+        }
+      } else {
+        int ps[4];
+        double ws[4];
+        if (inner && a.kappa) {
+          int pf[4];
+          double wf[4];
+          hpx::interp_weights_g(gfs, gf, z, rho, dphi, pf, wf);
+          if (a.kappa_fp64) {
+            const double* km = static_cast<const double*>(a.kappa);
+            kv = wf[0] * map_at(km, pf[0]) + wf[1] * map_at(km, pf[1]) +
+                 wf[2] * map_at(km, pf[2]) + wf[3] * map_at(km, pf[3]);
+          } else {
+            const float* km = static_cast<const float*>(a.kappa);
+            kv = wf[0] * double(map_at(km, pf[0])) + wf[1] * double(map_at(km, pf[1])) +
+                 wf[2] * double(map_at(km, pf[2])) + wf[3] * double(map_at(km, pf[3]));
+          }
+        }
+        hpx::interp_weights_g(gss, min(max(gsr, -1), a.rs.nring - 1), z, rho, dphi, ps, ws);
+        v = ws[0] * map_at(a.psi_s, ps[0]) + ws[1] * map_at(a.psi_s, ps[1]) +
+            ws[2] * map_at(a.psi_s, ps[2]) + ws[3] * map_at(a.psi_s, ps[3]);
+      }
+      if (inner) {
         if (fsh)
           fsh[(li - 1) * TILE + (lj - 1)] = T(2.0 * (kv - mean));
         else
@@ -543,8 +577,8 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
     prow[4 * r + 3] = 1.0 / c[3];
   }
   if (m.lds) {
-    fill_records(recs, a.rs, m.bs, m.ts, pr.phi, -1, nullptr);
-    fill_records(recf, a.rf, m.bf, m.tf, pr.phi, a.ring_shift, a.rs.rt);
+    fill_records(recs, a.rs, m.bs, m.ts, pr.phi, -1, nullptr, a.pad_s);
+    fill_records(recf, a.rf, m.bf, m.tf, pr.phi, a.ring_shift, a.rs.rt, a.pad_f);
     __syncthreads();
     setup_pass1_rec<T, TILE>(a, recf, m, recs, shu, fsh, rowc, colc, pr, patch, i0, j0);
   } else {
@@ -553,6 +587,31 @@ __global__ __launch_bounds__(kSetupBlock) void k_patch_setup(SetupArgs a) {
                          shu, fsh, rowc, colc, R, pr, patch, i0, j0);
   }
   setup_passes23<T, TILE>(a, shu, fsh, prow, R, pr, patch, i0, j0);
+}
+
+// Ring padding of a RING-ordered map for the setup's common case: ring q
+// (n pixels from first) becomes pixels -pad .. n + pad - 1 at first + 2 q pad
+// onward, pixel i holding pixel i mod n.  One block row per ring.
+template <typename M>
+__global__ __launch_bounds__(kBlock) void k_pad_rings(const M* src, M* dst, const int* ri,
+                                                      int pad) {
+  const int q = blockIdx.y;
+  const int n = ri[2 * q], first = ri[2 * q + 1];
+  const int w = n + 2 * pad;
+  const int64_t base = int64_t(first) + 2 * int64_t(q) * pad;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < w; i += gridDim.x * kBlock) {
+    int k = (i - pad) % n;
+    k += k < 0 ? n : 0;
+    dst[base + i] = src[first + k];
+  }
+}
+
+template <typename M>
+void pad_rings(const M* src, M* dst, const int* ri, int nring, int nside, int pad,
+               hipStream_t s) {
+  const int wmax = 4 * nside + 2 * pad;
+  const dim3 grid(unsigned(std::min((wmax + kBlock - 1) / kBlock, 64)), unsigned(nring));
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pad_rings<M>), grid, dim3(kBlock), 0, s, src, dst, ri, pad);
 }
 
 // ------------------------------------------------------------ tile kernels
@@ -669,13 +728,17 @@ struct QRow {
 
 // Per owned quad (qi, qj): cells c = 2a + b at (2 qi + a, 2 qj + b).  b is
 // the LDS index of cell (2 qi - 1, 2 qj); every neighbour outside the quad
-// is at a fixed offset from it.
+// is at a fixed offset from it.  Regions start at even cells and levels have
+// an even size, so a quad lies wholly inside or wholly outside the patch:
+// the quads outside (in false) hold u = 0 in LDS and are never updated, and
+// their registers are never read.
 template <typename T>
 struct Quad {
   T u[4], ft[4], rD[4];
   int b, qj;
-  bool live, edge;  // edge: a cell of the quad lies on the patch boundary
+  bool live, in, edge;  // edge: a cell of the quad lies on the patch boundary
 };
+
 
 // Row table of the region (rows i0 .. i0 + RR - 1 of the level's table,
 // defaults outside the patch), the side-face flags of its columns and the
@@ -724,10 +787,10 @@ __device__ __forceinline__ void qload_rows(QLds<T, HH>& t, const T* rowt, int n,
   }
 }
 
-// The thread's row pair and quads, and the global loads of their u and
-// (unscaled) source, issued before anything waits: every lane loads, from
-// an address clamped into the patch, and qfinish zeroes the cells outside
-// it.  u_in and f_in point at this patch's level array (u_in nullptr: zero).
+// The thread's row pair and quads, and the global loads of the u and
+// (unscaled) source of its quads inside the patch, issued before anything
+// waits.  u_in and f_in point at this patch's level array (u_in nullptr:
+// zero).
 template <typename T, int HH>
 __device__ __forceinline__ void qissue(QRow<T>& rw, Quad<T> (&qd)[QT<T, HH>::IT],
                                        const T* u_in, const T* f_in, int n, int i0, int j0) {
@@ -736,6 +799,7 @@ __device__ __forceinline__ void qissue(QRow<T>& rw, Quad<T> (&qd)[QT<T, HH>::IT]
   rw.live = qi < G::Q;
   rw.qi = rw.live ? qi : 0;
   const int gi0 = i0 + 2 * rw.qi;
+  const bool rin = rw.live && gi0 >= 0 && gi0 < n;
 #pragma unroll
   for (int it = 0; it < G::IT; ++it) {
     Quad<T>& Qd = qd[it];
@@ -744,24 +808,27 @@ __device__ __forceinline__ void qissue(QRow<T>& rw, Quad<T> (&qd)[QT<T, HH>::IT]
     Qd.qj = Qd.live ? qj : 0;
     Qd.b = 2 * rw.qi * G::S + Qd.qj + 1;
     const int gj = j0 + 2 * Qd.qj;
+    Qd.in = rin && Qd.live && gj >= 0 && gj < n;
     Qd.edge = gi0 == 0 || gi0 + 1 == n - 1 || gj == 0 || gj + 1 == n - 1;
-    const int cj = min(max(gj, 0), n - 2);
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int ci = min(max(gi0 + a, 0), n - 1);
-      const int g = ci * n + cj;
-      if (u_in)
-        load2(u_in + g, Qd.u[2 * a], Qd.u[2 * a + 1]);
-      else
-        Qd.u[2 * a] = Qd.u[2 * a + 1] = T(0);
-      load2(f_in + g, Qd.ft[2 * a], Qd.ft[2 * a + 1]);
+    if (Qd.in) {
+      // the second row through its own (uniform) base: one offset register
+      const unsigned g = unsigned(gi0 * n + gj);
+      load2(at(f_in, g), Qd.ft[0], Qd.ft[1]);
+      load2(at(f_in + n, g), Qd.ft[2], Qd.ft[3]);
+      if (u_in) {
+        load2(at(u_in, g), Qd.u[0], Qd.u[1]);
+        load2(at(u_in + n, g), Qd.u[2], Qd.u[3]);
+      } else {
+        Qd.u[0] = Qd.u[1] = Qd.u[2] = Qd.u[3] = T(0);
+      }
     }
   }
 }
 
-// After the row table is visible: the row pair's coefficients, A f (unless
-// f_in held it), the reciprocal diagonals, and zero u, A f and 1 / D on the
-// cells outside the patch (u is written to LDS by qput).
+// After the row table is visible: the row pair's coefficients, and per
+// quad inside the patch A f (unless f_in held it) and the reciprocal
+// diagonals (one more isc on a side face: column 0 is the even cell of its
+// quad, column n - 1 the odd one).
 template <typename T, int HH>
 __device__ __forceinline__ void qfinish(const QLds<T, HH>& t, QRow<T>& rw,
                                         Quad<T> (&qd)[QT<T, HH>::IT], bool f_scaled, int n,
@@ -770,26 +837,24 @@ __device__ __forceinline__ void qfinish(const QLds<T, HH>& t, QRow<T>& rw,
   const int li = 2 * rw.qi;
   rw.sm0 = t.sm[li]; rw.sp0 = t.sp[li]; rw.is0 = t.isc[li];
   rw.sm1 = t.sm[li + 1]; rw.sp1 = t.sp[li + 1]; rw.is1 = t.isc[li + 1];
-  const int gi0 = i0 + li;
+  const T A0 = f_scaled ? T(1) : t.A[li], A1 = f_scaled ? T(1) : t.A[li + 1];
+  const T rd0 = t.rD[li], rd1 = t.rD[li + 1], re0 = t.rD1[li], re1 = t.rD1[li + 1];
 #pragma unroll
   for (int it = 0; it < G::IT; ++it) {
     Quad<T>& Qd = qd[it];
+    if (!Qd.in) continue;
     const int gj = j0 + 2 * Qd.qj;
-    const bool cin = Qd.live && gj >= 0 && gj < n;
-    const bool side0 = t.cf[2 * Qd.qj] != T(0), side1 = t.cf[2 * Qd.qj + 1] != T(0);
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int gi = gi0 + a;
-      const bool in = cin && gi >= 0 && gi < n;
-      const T A = f_scaled ? T(1) : t.A[li + a];
-      const T rd = t.rD[li + a], rd1 = t.rD1[li + a];
-      Qd.u[2 * a] = in ? Qd.u[2 * a] : T(0);
-      Qd.u[2 * a + 1] = in ? Qd.u[2 * a + 1] : T(0);
-      Qd.ft[2 * a] = in ? Qd.ft[2 * a] * A : T(0);
-      Qd.ft[2 * a + 1] = in ? Qd.ft[2 * a + 1] * A : T(0);
-      Qd.rD[2 * a] = in ? (side0 ? rd1 : rd) : T(0);
-      Qd.rD[2 * a + 1] = in ? (side1 ? rd1 : rd) : T(0);
+    const bool side0 = gj == 0, side1 = gj + 1 == n - 1;
+    if (!f_scaled) {
+      Qd.ft[0] *= A0;
+      Qd.ft[1] *= A0;
+      Qd.ft[2] *= A1;
+      Qd.ft[3] *= A1;
     }
+    Qd.rD[0] = side0 ? re0 : rd0;
+    Qd.rD[1] = side1 ? re0 : rd0;
+    Qd.rD[2] = side0 ? re1 : rd1;
+    Qd.rD[3] = side1 ? re1 : rd1;
   }
 }
 
@@ -802,10 +867,17 @@ __device__ __forceinline__ void qput(QLds<T, HH>& t, const Quad<T> (&qd)[QT<T, H
     const Quad<T>& Qd = qd[it];
     if (!Qd.live) continue;
     T* ub = t.u + Qd.b;
-    ub[G::S] = Qd.u[0];
-    ub[G::PAR + G::S] = Qd.u[1];
-    ub[2 * G::S] = Qd.u[2];
-    ub[G::PAR + 2 * G::S] = Qd.u[3];
+    if (Qd.in) {
+      ub[G::S] = Qd.u[0];
+      ub[G::PAR + G::S] = Qd.u[1];
+      ub[2 * G::S] = Qd.u[2];
+      ub[G::PAR + 2 * G::S] = Qd.u[3];
+    } else {
+      ub[G::S] = T(0);
+      ub[G::PAR + G::S] = T(0);
+      ub[2 * G::S] = T(0);
+      ub[G::PAR + 2 * G::S] = T(0);
+    }
   }
 }
 
@@ -818,7 +890,7 @@ __device__ __forceinline__ void qsweep(QLds<T, HH>& t, const QRow<T>& rw,
 #pragma unroll
   for (int it = 0; it < G::IT; ++it) {
     Quad<T>& Qd = qd[it];
-    if (!Qd.live) continue;
+    if (!Qd.in) continue;
     T* ub = t.u + Qd.b;
     if (color == 0) {
       const T up = ub[0], lf = ub[P + S - 1], dn = ub[P + 3 * S], rt = ub[2 * S + 1];
@@ -872,7 +944,7 @@ __device__ __forceinline__ void qalap(const QLds<T, HH>& t, const QRow<T>& rw, c
 template <typename T, int HH>
 __device__ __forceinline__ bool interior_quad(const QRow<T>& rw, const Quad<T>& Qd) {
   using G = QT<T, HH>;
-  return Qd.live && rw.qi >= G::QH && rw.qi < G::QH + kTile / 2 && Qd.qj >= G::QH &&
+  return Qd.in && rw.qi >= G::QH && rw.qi < G::QH + kTile / 2 && Qd.qj >= G::QH &&
          Qd.qj < G::QH + kTile / 2;
 }
 
@@ -895,13 +967,13 @@ __device__ __forceinline__ void pre_epilogue(const TileArgs<T>& a, const QLds<T,
     const Quad<T>& Qd = qd[it];
     if (!interior_quad<T, HH>(rw, Qd)) continue;
     const int gi = i0 + li, gj = j0 + 2 * Qd.qj;
-    const int g = gi * n + gj;
-    store2(uo + g, Qd.u[0], Qd.u[1]);
-    store2(uo + g + n, Qd.u[2], Qd.u[3]);
+    const unsigned g = unsigned(gi * n + gj);
+    store2(at(uo, g), Qd.u[0], Qd.u[1]);
+    store2(at(uo + n, g), Qd.u[2], Qd.u[3]);
     if (a.fas_source) {
       T* fo = a.f_out + pbase;
-      store2(fo + g, Qd.ft[0], Qd.ft[1]);
-      store2(fo + g + n, Qd.ft[2], Qd.ft[3]);
+      store2(at(fo, g), Qd.ft[0], Qd.ft[1]);
+      store2(at(fo + n, g), Qd.ft[2], Qd.ft[3]);
     }
     // A r = A f - A L u, summed over the quad (formed at all four cells:
     // in float32 the cells the last half sweep updated carry the rounding
@@ -909,9 +981,9 @@ __device__ __forceinline__ void pre_epilogue(const TileArgs<T>& a, const QLds<T,
     T AL[4];
     qalap<T, HH>(t, rw, Qd, AL);
     const T ar = ((Qd.ft[0] - AL[0]) + (Qd.ft[1] - AL[1])) + ((Qd.ft[2] - AL[2]) + (Qd.ft[3] - AL[3]));
-    const int gc = (gi / 2) * nc + gj / 2;
-    ubo[gc] = (a0 * (Qd.u[0] + Qd.u[1]) + a1 * (Qd.u[2] + Qd.u[3])) * rden;
-    rbo[gc] = ar * rden;
+    const unsigned gc = unsigned((gi / 2) * nc + gj / 2);
+    *at(ubo, gc) = (a0 * (Qd.u[0] + Qd.u[1]) + a1 * (Qd.u[2] + Qd.u[3])) * rden;
+    *at(rbo, gc) = ar * rden;
   }
 }
 
@@ -938,9 +1010,9 @@ __device__ __forceinline__ void corr_issue(const TileArgs<T>& a, CorrIn<T, HH>& 
     const int item = min(int(threadIdx.x) + k * QT<T, HH>::NT, C::CR * C::CR - 1);
     const int I = min(max(ci0 + item / C::CR, 0), nc - 1);
     const int J = min(max(cj0 + item % C::CR, 0), nc - 1);
-    const size_t g = cbase + size_t(I) * nc + J;
-    c.uc[k] = a.uc[g];
-    c.ub[k] = a.ubarc[g];
+    const unsigned g = unsigned(I * nc + J);
+    c.uc[k] = *at(a.uc + cbase, g);
+    c.ub[k] = *at(a.ubarc + cbase, g);
   }
 }
 
@@ -966,7 +1038,7 @@ __device__ __forceinline__ void apply_correction(const T* e, const QRow<T>& rw,
 #pragma unroll
   for (int it = 0; it < G::IT; ++it) {
     Quad<T>& Qd = qd[it];
-    if (!Qd.live) continue;
+    if (!Qd.in) continue;
     const T* ec = e + (rw.qi + 1) * CR + (Qd.qj + 1);
     const T c = ec[0];
     const T nu = ec[-CR], nd = ec[CR], nl = ec[-1], nr = ec[1];
@@ -981,12 +1053,11 @@ __device__ __forceinline__ void apply_correction(const T* e, const QRow<T>& rw,
       for (int k = 0; k < 4; ++k) {
         const int ci = gi + (k >> 1), cj = gj + (k & 1);
         const bool ring = ci == 0 || ci == n - 1 || cj == 0 || cj == n - 1;
-        const T corr = ring ? c : p[k];
-        Qd.u[k] += Qd.rD[k] != T(0) ? corr : T(0);
+        Qd.u[k] += ring ? c : p[k];
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) Qd.u[k] += Qd.rD[k] != T(0) ? p[k] : T(0);
+      for (int k = 0; k < 4; ++k) Qd.u[k] += p[k];
     }
   }
 }
@@ -1016,11 +1087,11 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_pre(TileArgs<T> a) {
 #pragma unroll
     for (int it = 0; it < G::IT; ++it) {
       Quad<T>& Qd = qd[it];
-      if (!Qd.live) continue;
+      if (!Qd.in) continue;
       T AL[4];
       qalap<T, HH>(t, rw, Qd, AL);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Qd.ft[c] = Qd.rD[c] != T(0) ? Qd.ft[c] + AL[c] : T(0);
+      for (int c = 0; c < 4; ++c) Qd.ft[c] += AL[c];
     }
     __syncthreads();
   }
@@ -1070,9 +1141,9 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_post(TileArgs<T> a) {
   for (int it = 0; it < G::IT; ++it) {
     const Quad<T>& Qd = qd[it];
     if (!interior_quad<T, HH>(rw, Qd)) continue;
-    const int g = (i0 + 2 * rw.qi) * n + (j0 + 2 * Qd.qj);
-    store2(uo + g, Qd.u[0], Qd.u[1]);
-    store2(uo + g + n, Qd.u[2], Qd.u[3]);
+    const unsigned g = unsigned((i0 + 2 * rw.qi) * n + (j0 + 2 * Qd.qj));
+    store2(at(uo, g), Qd.u[0], Qd.u[1]);
+    store2(at(uo + n, g), Qd.u[2], Qd.u[3]);
   }
 }
 
@@ -1641,6 +1712,18 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     a.psi_s = sl.psi_s;
     a.kappa = kappa;
     a.kappa_fp64 = kappa_fp64;
+    a.spad = p->spad;
+    a.kpad = p->kpad;
+    a.pad_s = p->pad_s;
+    a.pad_f = p->pad_f;
+    pad_rings(sl.psi_s, p->spad, p->ringi_s, p->nring_s, p->d.nside_sht, p->pad_s, s);
+    if (kappa && kappa_fp64)
+      pad_rings(static_cast<const double*>(kappa), static_cast<double*>(p->kpad), p->ringi_f,
+                p->nring_f, p->d.nside_fine, p->pad_f, s);
+    else if (kappa)
+      pad_rings(static_cast<const float*>(kappa), static_cast<float*>(p->kpad), p->ringi_f,
+                p->nring_f, p->d.nside_fine, p->pad_f, s);
+    CLM_LAUNCH_CHECK();
     a.red = p->red;
     a.u0 = sl.u0;
     a.fprime = p->fprime;
@@ -1887,6 +1970,12 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
 }
 
 }  // namespace
+
+int setup_ring_pad(int nside) {
+  // asin(kSetupSeries) 4 nside / (2 pi) = 0.03185 nside pixels beyond the
+  // ring ends, one more for the pair, one for t0 in (-1, n)
+  return int(std::ceil(0.032 * nside)) + 3;
+}
 
 int64_t setup_tiles(const Plan* p) {
   const int tile = p->n < kTile ? p->n : kTile;

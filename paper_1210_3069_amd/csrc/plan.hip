@@ -38,7 +38,7 @@ Plan::~Plan() {
   f(deriv); f(fprime); f(dutmp); f(status_dev); f(iter_map); f(iter_alm);
   for (auto* q : ubar) f(q);
   f(ubar1b);
-  f(setup_meta);
+  f(setup_meta); f(spad); f(kpad);
   for (auto* q : rbar) f(q);
   for (auto* q : flev) f(q);
   for (auto* q : ulev) f(q);
@@ -544,6 +544,15 @@ clm_status clm_plan_create(const clm_plan_desc* desc, int device, clm_plan* out)
     }
     if ((s = alloc(p, &p->setup_meta, size_t(setup_tiles(p)) * kSetupMetaBytes)) != CLM_OK)
       return bail(s);
+    p->pad_s = setup_ring_pad(d.nside_sht);
+    p->pad_f = setup_ring_pad(d.nside_fine);
+    if ((s = alloc(p, &p->spad, size_t(p->npix_s) + 2 * size_t(p->pad_s) * p->nring_s)) !=
+        CLM_OK)
+      return bail(s);
+    double* kp = nullptr;  // sized for float64 maps; float32 maps use half of it
+    if ((s = alloc(p, &kp, size_t(p->npix_f) + 2 * size_t(p->pad_f) * p->nring_f)) != CLM_OK)
+      return bail(s);
+    p->kpad = kp;
     if ((s = setup_tables(p, nullptr)) != CLM_OK) return bail(s);
   } else {
     if ((s = alloc(p, &p->deriv, size_t(p->npix_s) * 5)) != CLM_OK) return bail(s);

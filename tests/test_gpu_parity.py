@@ -279,6 +279,31 @@ def test_mg_wide_patch_global_ring_tables(clm, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("kdtype", [np.float64, np.float32])
+def test_mg_setup_azimuth_wrap(clm, mg_case, kdtype):
+    """Patches across the azimuth phi = 0 of the RING order (bundles 64 to
+    67): the setup's interpolation reads both maps across the end of every
+    ring, in both map precisions."""
+    c = mg_case
+    n, bl = 64, [64, 65, 66, 67]
+    kap = c["kap"].astype(kdtype)
+    spec = omg.PatchSpec(c["Nf"], c["Ns"], c["lmax"], c["Nb"], ncell=n, vcycles=3)
+    sol = omg.solve_plane(spec, kap.astype(np.float64), bl)
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=n, mg_vcycles=3, mg_prec="fp64")
+    plan.poisson_solve(torch.from_numpy(kap).cuda())
+    for b in bl:
+        pt = sol["patches"][b]
+        _, ph = omg.patch_cell_dirs(spec, pt["R"])
+        assert ph.min() < 0.05 and ph.max() > 2 * np.pi - 0.05, b
+        ref = (pt["u0"] + pt["du"])[1:-1, 1:-1]
+        got = plan.patch_potential(b, 1)[0].cpu().numpy()
+        assert report("azimuth wrap %s b=%d" % (np.dtype(kdtype).name, b), rel(got, ref)) < \
+            1e-10, b
+    plan.sync_status()
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_mg_float32_kappa_input(clm, mg_case, prec):
     """A float32 convergence map (the input type of the Nside 2048 workload):
