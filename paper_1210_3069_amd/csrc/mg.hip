@@ -1205,7 +1205,9 @@ __device__ __forceinline__ T prolong_cell(int gi, int gj, int n, EF e) {
 // (fewer threads sit idle on the coarser levels, and in float32 three such
 // workgroups share a CU's LDS, against two of 1024 threads).  Per level l:
 // u, f (and ubar for l > K) as row-major n_l x n_l arrays, and the level's
-// row coefficients (s_m, s_p, 1/s_c, area, interior 1/diag).
+// row coefficients (s_m, s_p, 1/s_c, area, and the reciprocal diagonals of
+// the row's cells off and on a side face, with the face terms of rows 0
+// and n - 1 included).
 struct LdsLevels {
   int K, nlev, n0;        // first level handled here, number of levels, its size
   size_t crow[16];        // coefficient row offsets per level (absolute level index)
@@ -1232,6 +1234,7 @@ struct LRows {
   const T* isc;
   const T* A;
   const T* rD;
+  const T* rDs;
 };
 
 // (L u)_ij, zero face value across the patch boundary.
@@ -1245,6 +1248,8 @@ __device__ __forceinline__ T lap_g(const T* u, int n, int i, int j, const LRows<
   return (r.sm[i] * (up - uc) + r.sp[i] * (dn - uc) + (lf - T(2) * uc + rt) * r.isc[i]) / r.A[i];
 }
 
+// Red-black sweeps: a neighbour across the patch face is zero (the ghost
+// -u enters through the diagonal, which the row's reciprocals include).
 template <typename T>
 __device__ void lds_smooth(T* u, const T* f, int n, int lg, const LRows<T>& r, int sweeps) {
   const int half = n >> 1;
@@ -1253,25 +1258,13 @@ __device__ void lds_smooth(T* u, const T* f, int n, int lg, const LRows<T>& r, i
       for (int idx = threadIdx.x; idx < n * half; idx += kLdsBlock) {
         const int i = idx >> (lg - 1);
         const int j = 2 * (idx & (half - 1)) + ((color + i) & 1);
-        const T sm = r.sm[i], sp = r.sp[i], isc = r.isc[i];
-        T num = -r.A[i] * f[i * n + j];
-        T lr = T(0);
-        bool edge = false;
-        if (i > 0) num += sm * u[(i - 1) * n + j]; else edge = true;
-        if (i < n - 1) num += sp * u[(i + 1) * n + j]; else edge = true;
-        if (j > 0) lr += u[i * n + j - 1]; else edge = true;
-        if (j < n - 1) lr += u[i * n + j + 1]; else edge = true;
-        num += lr * isc;
-        if (edge) {
-          T diag = sm + sp + T(2) * isc;
-          if (i == 0) diag += sm;
-          if (i == n - 1) diag += sp;
-          if (j == 0) diag += isc;
-          if (j == n - 1) diag += isc;
-          u[i * n + j] = num / diag;
-        } else {
-          u[i * n + j] = num * r.rD[i];
-        }
+        const int c = i * n + j;
+        const T up = i > 0 ? u[c - n] : T(0);
+        const T dn = i < n - 1 ? u[c + n] : T(0);
+        const T lf = j > 0 ? u[c - 1] : T(0);
+        const T rt = j < n - 1 ? u[c + 1] : T(0);
+        const T num = r.sm[i] * up + r.sp[i] * dn + r.isc[i] * (lf + rt) - r.A[i] * f[c];
+        u[c] = num * (j == 0 || j == n - 1 ? r.rDs[i] : r.rD[i]);
       }
       __syncthreads();
     }
@@ -1292,7 +1285,7 @@ __device__ __forceinline__ LLevel<T> lds_level(unsigned char* smem, int K, int n
   T* q = reinterpret_cast<T*>(smem);
   for (int k = K; k < l; ++k) {
     const int nn = n0 >> (k - K);
-    q += nn * nn * (k > K ? 3 : 2) + 5 * nn;
+    q += nn * nn * (k > K ? 3 : 2) + 6 * nn;
   }
   const int nn = n0 >> (l - K);
   LLevel<T> v;
@@ -1300,7 +1293,7 @@ __device__ __forceinline__ LLevel<T> lds_level(unsigned char* smem, int K, int n
   v.f = q + nn * nn;
   v.b = l > K ? q + 2 * nn * nn : nullptr;
   T* rows = q + nn * nn * (l > K ? 3 : 2);
-  v.r = LRows<T>{rows, rows + nn, rows + 2 * nn, rows + 3 * nn, rows + 4 * nn};
+  v.r = LRows<T>{rows, rows + nn, rows + 2 * nn, rows + 3 * nn, rows + 4 * nn, rows + 5 * nn};
   return v;
 }
 
@@ -1316,11 +1309,14 @@ __global__ __launch_bounds__(kLdsBlock) void k_mg_lds(LdsArgs<T> a) {
     T* rows = const_cast<T*>(L.r.sm);
     for (int i = threadIdx.x; i < nn; i += kLdsBlock) {
       const double* c = a.coef + a.lv.crow[l] + 4 * i;
+      const double is = 1.0 / c[2];
+      const double d = c[0] + c[1] + 2.0 * is + (i == 0 ? c[0] : 0.0) + (i == nn - 1 ? c[1] : 0.0);
       rows[i] = T(c[0]);
       rows[nn + i] = T(c[1]);
-      rows[2 * nn + i] = T(1.0 / c[2]);
+      rows[2 * nn + i] = T(is);
       rows[3 * nn + i] = T(c[3]);
-      rows[4 * nn + i] = T(1.0 / (c[0] + c[1] + 2.0 / c[2]));
+      rows[4 * nn + i] = T(1.0 / d);
+      rows[5 * nn + i] = T(1.0 / (d + is));
     }
   }
   int lg0 = 0;
@@ -1762,7 +1758,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
   size_t lds_elems = 0;
   for (int l = K; l < p->nlev; ++l) {
     const size_t nn = size_t(n >> l);
-    lds_elems += nn * nn * (l > K ? 3 : 2) + 5 * nn;
+    lds_elems += nn * nn * (l > K ? 3 : 2) + 6 * nn;
   }
   const size_t lds_bytes = lds_elems * sizeof(T);
   if (allow_lds(p, k_mg_lds<T>, lds_bytes) != CLM_OK) return CLM_EHIP;
