@@ -881,6 +881,13 @@ __device__ __forceinline__ void qput(QLds<T, HH>& t, const Quad<T> (&qd)[QT<T, H
   }
 }
 
+// Gauss-Seidel value of one cell: (s_m u_up + s_p u_down + isc (u_left +
+// u_right) - A f) / D, accumulated from -A f so that each product fuses.
+template <typename T>
+__device__ __forceinline__ T gs_update(T sm, T up, T sp, T dn, T isc, T lr, T af, T rd) {
+  return fma(isc, lr, fma(sp, dn, fma(sm, up, -af))) * rd;
+}
+
 // Red-black half sweep over the owned quads.
 template <typename T, int HH>
 __device__ __forceinline__ void qsweep(QLds<T, HH>& t, const QRow<T>& rw,
@@ -894,16 +901,16 @@ __device__ __forceinline__ void qsweep(QLds<T, HH>& t, const QRow<T>& rw,
     T* ub = t.u + Qd.b;
     if (color == 0) {
       const T up = ub[0], lf = ub[P + S - 1], dn = ub[P + 3 * S], rt = ub[2 * S + 1];
-      const T v0 = (rw.sm0 * up + rw.sp0 * Qd.u[2] + rw.is0 * (lf + Qd.u[1]) - Qd.ft[0]) * Qd.rD[0];
-      const T v3 = (rw.sm1 * Qd.u[1] + rw.sp1 * dn + rw.is1 * (Qd.u[2] + rt) - Qd.ft[3]) * Qd.rD[3];
+      const T v0 = gs_update(rw.sm0, up, rw.sp0, Qd.u[2], rw.is0, lf + Qd.u[1], Qd.ft[0], Qd.rD[0]);
+      const T v3 = gs_update(rw.sm1, Qd.u[1], rw.sp1, dn, rw.is1, Qd.u[2] + rt, Qd.ft[3], Qd.rD[3]);
       Qd.u[0] = v0;
       Qd.u[3] = v3;
       ub[S] = v0;
       ub[P + 2 * S] = v3;
     } else {
       const T up = ub[P], rt = ub[S + 1], dn = ub[3 * S], lf = ub[P + 2 * S - 1];
-      const T v1 = (rw.sm0 * up + rw.sp0 * Qd.u[3] + rw.is0 * (Qd.u[0] + rt) - Qd.ft[1]) * Qd.rD[1];
-      const T v2 = (rw.sm1 * Qd.u[0] + rw.sp1 * dn + rw.is1 * (lf + Qd.u[3]) - Qd.ft[2]) * Qd.rD[2];
+      const T v1 = gs_update(rw.sm0, up, rw.sp0, Qd.u[3], rw.is0, Qd.u[0] + rt, Qd.ft[1], Qd.rD[1]);
+      const T v2 = gs_update(rw.sm1, Qd.u[0], rw.sp1, dn, rw.is1, lf + Qd.u[3], Qd.ft[2], Qd.rD[2]);
       Qd.u[1] = v1;
       Qd.u[2] = v2;
       ub[P + S] = v1;
