@@ -1106,6 +1106,24 @@ def dominant_stage(stage_pass, nsteps, nbundle, npix):
     return best
 
 
+def copy_rate(torch, nbytes=2 << 30, reps=5):
+    """GB/s (bytes read + written) of a plain device-to-device copy."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def main():
     args = parse_args()
     if args.summarize_stats:
@@ -1168,8 +1186,12 @@ def main():
     ms_launch = tot / cnt
     achieved = b_dom / (ms_launch * 1e-3) / 1e9
     traffic = read_traffic(dom)
+    copy_gbs = copy_rate(torch)
     roofline = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS,
+                    copy_GBps=copy_gbs, frac_of_copy=achieved / copy_gbs,
+                    copy_note="a plain device-to-device copy of 2 GiB (read + write bytes), "
+                              "timed in this run: the streaming rate the HBM reaches in practice",
                     traffic=None if traffic is None else traffic / 1e9,
                     traffic_unit="GB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                     alg_bytes_per_launch=b_dom, ms_per_launch=ms_launch,

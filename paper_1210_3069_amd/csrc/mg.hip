@@ -632,6 +632,7 @@ constexpr int kTileBlock = 512;
 template <typename T>
 struct TileArgs {
   int n, ntile, nu;
+  int lgt;              // log2(ntile): tile levels have a power-of-two size
   int nu2;              // fused post + pre: the pre-smoothing sweeps
   const double* coef;   // this level's rows
   const T* rowt;        // this level's row table (8 values per row)
@@ -941,10 +942,10 @@ __device__ __forceinline__ void qalap(const QLds<T, HH>& t, const QRow<T>& rw, c
     const int aa = c >> 1, bb = c & 1;
     const T sm = aa ? rw.sm1 : rw.sm0, sp = aa ? rw.sp1 : rw.sp0, isc = aa ? rw.is1 : rw.is0;
     const T x = u[c];
-    const T v = sm * (nb0 - x) + sp * (nb1 - x) + isc * ((nb2 - x) + (nb3 - x));
-    // the face terms: er of the row, isc on a side-face column
-    const T e = (aa ? er1 : er0) + isc * (bb ? cf1 : cf0);
-    AL[c] = v - e * x;
+    AL[c] = sm * (nb0 - x) + sp * (nb1 - x) + isc * ((nb2 - x) + (nb3 - x));
+    // the face terms (quads on the patch boundary only): er of the row,
+    // isc on a side-face column
+    if (Qd.edge) AL[c] -= ((aa ? er1 : er0) + isc * (bb ? cf1 : cf0)) * x;
   }
 }
 
@@ -1076,11 +1077,10 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_pre(TileArgs<T> a) {
   QRow<T> rw;
   Quad<T> qd[G::IT];
   const int64_t lb = xcd_block();
-  const int tpp = a.ntile * a.ntile;
-  const int64_t patch = patch_of(a.pmap, lb / tpp);
-  const int tt = int(lb % tpp);
+  const int64_t patch = patch_of(a.pmap, lb >> (2 * a.lgt));
+  const int tt = int(lb & ((int64_t(1) << (2 * a.lgt)) - 1));
   if (a.done && a.done[patch]) return;
-  const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
+  const int i0 = (tt >> a.lgt) * kTile - HH, j0 = (tt & (a.ntile - 1)) * kTile - HH;
   const int n = a.n, nc = n / 2;
   const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
   qissue<T, HH>(rw, qd, a.u_in ? a.u_in + pbase : nullptr, a.f_in + pbase, n, i0, j0);
@@ -1120,10 +1120,9 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_post(TileArgs<T> a) {
   QRow<T> rw;
   Quad<T> qd[G::IT];
   const int64_t lb = xcd_block();
-  const int tpp = a.ntile * a.ntile;
-  const int64_t patch = patch_of(a.pmap, lb / tpp);
-  const int tt = int(lb % tpp);
-  const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
+  const int64_t patch = patch_of(a.pmap, lb >> (2 * a.lgt));
+  const int tt = int(lb & ((int64_t(1) << (2 * a.lgt)) - 1));
+  const int i0 = (tt >> a.lgt) * kTile - HH, j0 = (tt & (a.ntile - 1)) * kTile - HH;
   const int n = a.n, nc = n / 2;
   const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
   if (a.done && a.done[patch]) return;
@@ -1169,10 +1168,9 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_postpre(TileArgs<T> a) 
   QRow<T> rw;
   Quad<T> qd[G::IT];
   const int64_t lb = xcd_block();
-  const int tpp = a.ntile * a.ntile;
-  const int64_t patch = patch_of(a.pmap, lb / tpp);
-  const int tt = int(lb % tpp);
-  const int i0 = (tt / a.ntile) * kTile - HH, j0 = (tt % a.ntile) * kTile - HH;
+  const int64_t patch = patch_of(a.pmap, lb >> (2 * a.lgt));
+  const int tt = int(lb & ((int64_t(1) << (2 * a.lgt)) - 1));
+  const int i0 = (tt >> a.lgt) * kTile - HH, j0 = (tt & (a.ntile - 1)) * kTile - HH;
   const int n = a.n, nc = n / 2;
   const size_t pbase = size_t(patch) * n * n, cbase = size_t(patch) * nc * nc;
   CorrIn<T, HH> ci;
@@ -1780,6 +1778,8 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
     TileArgs<T> a{};
     a.n = n >> l;
     a.ntile = a.n / kTile;
+    a.lgt = 0;
+    while ((1 << a.lgt) < a.ntile) ++a.lgt;
     a.nu = pre ? d.nu_pre : d.nu_post;
     a.coef = p->coef + p->lev[l].crow;
     a.rowt = static_cast<const T*>(p->rowt) + 2 * p->lev[l].crow;
