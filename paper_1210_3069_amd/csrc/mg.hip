@@ -1210,9 +1210,9 @@ __device__ __forceinline__ T prolong_cell(int gi, int gj, int n, EF e) {
 // (fewer threads sit idle on the coarser levels, and in float32 three such
 // workgroups share a CU's LDS, against two of 1024 threads).  Per level l:
 // u, f (and ubar for l > K) as row-major n_l x n_l arrays, and the level's
-// row coefficients (s_m, s_p, 1/s_c, area, and the reciprocal diagonals of
-// the row's cells off and on a side face, with the face terms of rows 0
-// and n - 1 included).
+// row coefficients (s_m, s_p, 1/s_c, area, the reciprocal diagonals of the
+// row's cells off and on a side face, with the face terms of rows 0 and
+// n - 1 included, and 1/area).
 struct LdsLevels {
   int K, nlev, n0;        // first level handled here, number of levels, its size
   size_t crow[16];        // coefficient row offsets per level (absolute level index)
@@ -1240,6 +1240,7 @@ struct LRows {
   const T* A;
   const T* rD;
   const T* rDs;
+  const T* iA;
 };
 
 // (L u)_ij, zero face value across the patch boundary.
@@ -1250,26 +1251,39 @@ __device__ __forceinline__ T lap_g(const T* u, int n, int i, int j, const LRows<
   const T dn = i < n - 1 ? u[(i + 1) * n + j] : -uc;
   const T lf = j > 0 ? u[i * n + j - 1] : -uc;
   const T rt = j < n - 1 ? u[i * n + j + 1] : -uc;
-  return (r.sm[i] * (up - uc) + r.sp[i] * (dn - uc) + (lf - T(2) * uc + rt) * r.isc[i]) / r.A[i];
+  return (r.sm[i] * (up - uc) + r.sp[i] * (dn - uc) + (lf - T(2) * uc + rt) * r.isc[i]) * r.iA[i];
 }
 
 // Red-black sweeps: a neighbour across the patch face is zero (the ghost
 // -u enters through the diagonal, which the row's reciprocals include).
+// Each thread keeps one row (its coefficients and face flags in registers)
+// and cpt cells of the colour in it, columns q, q + tpr, ... of the colour;
+// a missing neighbour is read at the cell itself and weighted by zero, so no
+// load is predicated.
 template <typename T>
 __device__ void lds_smooth(T* u, const T* f, int n, int lg, const LRows<T>& r, int sweeps) {
   const int half = n >> 1;
+  const int cpt = max(1, (n * half) / kLdsBlock);  // powers of two
+  const int tpr = half / cpt;
+  const int i = threadIdx.x / tpr, q = threadIdx.x - i * tpr;
+  const bool live = i < n;
+  const int ii = live ? i : 0;
+  const T sm = i > 0 ? r.sm[ii] : T(0), sp = i < n - 1 ? r.sp[ii] : T(0);
+  const T isc = r.isc[ii], A = r.A[ii], rd = r.rD[ii], rds = r.rDs[ii];
+  const int om = i > 0 ? -n : 0, op = i < n - 1 ? n : 0;
   for (int s = 0; s < sweeps; ++s) {
     for (int color = 0; color < 2; ++color) {
-      for (int idx = threadIdx.x; idx < n * half; idx += kLdsBlock) {
-        const int i = idx >> (lg - 1);
-        const int j = 2 * (idx & (half - 1)) + ((color + i) & 1);
-        const int c = i * n + j;
-        const T up = i > 0 ? u[c - n] : T(0);
-        const T dn = i < n - 1 ? u[c + n] : T(0);
-        const T lf = j > 0 ? u[c - 1] : T(0);
-        const T rt = j < n - 1 ? u[c + 1] : T(0);
-        const T num = r.sm[i] * up + r.sp[i] * dn + r.isc[i] * (lf + rt) - r.A[i] * f[c];
-        u[c] = num * (j == 0 || j == n - 1 ? r.rDs[i] : r.rD[i]);
+      if (live) {
+        const int par = (color + i) & 1;
+        for (int k = 0; k < cpt; ++k) {
+          const int j = 2 * (q + tpr * k) + par;
+          const int c = ii * n + j;
+          const bool lfin = j > 0, rtin = j < n - 1;
+          const T lf = u[lfin ? c - 1 : c], rt = u[rtin ? c + 1 : c];
+          const T lr = (lfin ? lf : T(0)) + (rtin ? rt : T(0));
+          const T num = fma(isc, lr, fma(sp, u[c + op], fma(sm, u[c + om], -A * f[c])));
+          u[c] = num * (lfin && rtin ? rd : rds);
+        }
       }
       __syncthreads();
     }
@@ -1290,7 +1304,7 @@ __device__ __forceinline__ LLevel<T> lds_level(unsigned char* smem, int K, int n
   T* q = reinterpret_cast<T*>(smem);
   for (int k = K; k < l; ++k) {
     const int nn = n0 >> (k - K);
-    q += nn * nn * (k > K ? 3 : 2) + 6 * nn;
+    q += nn * nn * (k > K ? 3 : 2) + 7 * nn;
   }
   const int nn = n0 >> (l - K);
   LLevel<T> v;
@@ -1298,7 +1312,8 @@ __device__ __forceinline__ LLevel<T> lds_level(unsigned char* smem, int K, int n
   v.f = q + nn * nn;
   v.b = l > K ? q + 2 * nn * nn : nullptr;
   T* rows = q + nn * nn * (l > K ? 3 : 2);
-  v.r = LRows<T>{rows, rows + nn, rows + 2 * nn, rows + 3 * nn, rows + 4 * nn, rows + 5 * nn};
+  v.r = LRows<T>{rows,          rows + nn,     rows + 2 * nn, rows + 3 * nn,
+                 rows + 4 * nn, rows + 5 * nn, rows + 6 * nn};
   return v;
 }
 
@@ -1322,6 +1337,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_mg_lds(LdsArgs<T> a) {
       rows[3 * nn + i] = T(c[3]);
       rows[4 * nn + i] = T(1.0 / d);
       rows[5 * nn + i] = T(1.0 / (d + is));
+      rows[6 * nn + i] = T(1.0 / c[3]);
     }
   }
   int lg0 = 0;
@@ -1763,7 +1779,7 @@ clm_status run_mg(Plan* p, const void* kappa, int kappa_fp64, int slot, hipStrea
   size_t lds_elems = 0;
   for (int l = K; l < p->nlev; ++l) {
     const size_t nn = size_t(n >> l);
-    lds_elems += nn * nn * (l > K ? 3 : 2) + 6 * nn;
+    lds_elems += nn * nn * (l > K ? 3 : 2) + 7 * nn;
   }
   const size_t lds_bytes = lds_elems * sizeof(T);
   if (allow_lds(p, k_mg_lds<T>, lds_bytes) != CLM_OK) return CLM_EHIP;
