@@ -1243,14 +1243,16 @@ struct LRows {
   const T* iA;
 };
 
-// (L u)_ij, zero face value across the patch boundary.
+// (L u)_ij, zero face value across the patch boundary (the ghost -u); a
+// missing neighbour is read at the cell itself, so no load is predicated.
 template <typename T>
 __device__ __forceinline__ T lap_g(const T* u, int n, int i, int j, const LRows<T>& r) {
-  const T uc = u[i * n + j];
-  const T up = i > 0 ? u[(i - 1) * n + j] : -uc;
-  const T dn = i < n - 1 ? u[(i + 1) * n + j] : -uc;
-  const T lf = j > 0 ? u[i * n + j - 1] : -uc;
-  const T rt = j < n - 1 ? u[i * n + j + 1] : -uc;
+  const int c = i * n + j;
+  const T uc = u[c];
+  const bool ui = i > 0, di = i < n - 1, lj = j > 0, rj = j < n - 1;
+  const T upv = u[ui ? c - n : c], dnv = u[di ? c + n : c];
+  const T lfv = u[lj ? c - 1 : c], rtv = u[rj ? c + 1 : c];
+  const T up = ui ? upv : -uc, dn = di ? dnv : -uc, lf = lj ? lfv : -uc, rt = rj ? rtv : -uc;
   return (r.sm[i] * (up - uc) + r.sp[i] * (dn - uc) + (lf - T(2) * uc + rt) * r.isc[i]) * r.iA[i];
 }
 
@@ -1345,9 +1347,11 @@ __global__ __launch_bounds__(kLdsBlock) void k_mg_lds(LdsArgs<T> a) {
   const size_t g0 = size_t(patch) * n0 * n0;
   {
     const LLevel<T> L = lds_level<T>(smem, K, n0, K);
+    const T* ui = a.u_in ? a.u_in + g0 : nullptr;
+    const T* fi = a.f_in + g0;
     for (int idx = threadIdx.x; idx < n0 * n0; idx += kLdsBlock) {
-      L.u[idx] = a.u_in ? a.u_in[g0 + idx] : T(0);
-      L.f[idx] = a.f_in[g0 + idx];
+      L.u[idx] = ui ? *at(ui, unsigned(idx)) : T(0);
+      L.f[idx] = *at(fi, unsigned(idx));
     }
     __syncthreads();
     if (a.fas_source) {
@@ -1403,7 +1407,11 @@ __global__ __launch_bounds__(kLdsBlock) void k_mg_lds(LdsArgs<T> a) {
     const int nn = 1 << lg, nc = nn >> 1;
     const LLevel<T> L = lds_level<T>(smem, K, n0, l);
     const LLevel<T> C = lds_level<T>(smem, K, n0, l + 1);
-    auto ef = [&](int I, int J) { return C.u[I * nc + J] - C.b[I * nc + J]; };
+    // the coarse correction e = u_H - ubar once per coarse cell (ubar is not
+    // needed again in this cycle)
+    for (int idx = threadIdx.x; idx < nc * nc; idx += kLdsBlock) C.b[idx] = C.u[idx] - C.b[idx];
+    __syncthreads();
+    auto ef = [&](int I, int J) { return C.b[I * nc + J]; };
     for (int idx = threadIdx.x; idx < nn * nn; idx += kLdsBlock)
       L.u[idx] += prolong_cell<T>(idx >> lg, idx & (nn - 1), nn, ef);
     __syncthreads();
@@ -1411,7 +1419,8 @@ __global__ __launch_bounds__(kLdsBlock) void k_mg_lds(LdsArgs<T> a) {
   }
   {
     const LLevel<T> L = lds_level<T>(smem, K, n0, K);
-    for (int idx = threadIdx.x; idx < n0 * n0; idx += kLdsBlock) a.u_out[g0 + idx] = L.u[idx];
+    T* uo = a.u_out + g0;
+    for (int idx = threadIdx.x; idx < n0 * n0; idx += kLdsBlock) *at(uo, unsigned(idx)) = L.u[idx];
   }
 }
 
