@@ -409,8 +409,8 @@ __device__ __forceinline__ void synthesis_item(const MfmaArgs& a, int m, int rb,
         for (int v = 0; v < 16; ++v) accb[par][mt][v] = 0.f;
   }
   const int i = l & 15, k = l >> 4;
-  // psi operands of a step, loaded before the step's recurrence so that it
-  // hides their latency.  float32: per parity, 4 values of l (k-blocks) x 2
+  // psi operands of a step (bf16 forms: loaded before the step's recurrence
+  // so that it hides their latency).  float32: per parity, 4 values of l (k-blocks) x 2
   // column blocks; bf16: per parity the 8 values of l 2 (8 (lane / 32) + e)
   // + parity at column lane % 32.
   auto psi_fetch = [&](int dl0, float (&v)[2][8]) {
@@ -433,8 +433,12 @@ __device__ __forceinline__ void synthesis_item(const MfmaArgs& a, int m, int rb,
   double rcv = rc_fetch(rc, 0, nl, l);
   for (int dl0 = 0; dl0 < nl; dl0 += kStep) {
     const double rcn = rc_fetch(rc, dl0 + kStep, nl, l);  // next step's, in flight
-    psi_fetch(dl0, pv);
+    // float32: the operands are fetched after the recurrence, which keeps
+    // them out of its register peak (fewer spills at 16 waves per
+    // workgroup; the other waves of the CU hide their latency)
+    if constexpr (FORM != kFP32) psi_fetch(dl0, pv);
     rec_step<SS>(r, m, dl0, nl, rcv, cs, tw, l);
+    if constexpr (FORM == kFP32) psi_fetch(dl0, pv);
     rcv = rcn;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);
