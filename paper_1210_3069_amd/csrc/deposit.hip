@@ -179,76 +179,142 @@ __global__ __launch_bounds__(kBlock) void k_patch_deposit(PatchDep a) {
   const double d = a.delta, th0 = 0.5 * kPiD - 0.5 * a.L, ph0 = -0.5 * a.L;
   const double is2 = sigma > 0.0 ? 1.0 / (sigma * sigma) : 0.0;
   const double hs = sin(0.5 * sigma), hs2 = hs * hs;  // hav(sigma)
-  double sh, ch;                                     // sin, cos of half a cell
+  double sh, ch, sd, cd;                             // sin, cos of half a cell, a cell
   sincos(0.5 * a.delta, &sh, &ch);
+  sincos(a.delta, &sd, &cd);
   const double smin = fmax(sin(fmin(0.5 * kPiD + 0.5 * a.L + sigma, kPiD - 1e-3)), 1e-3);
   // cells within sigma lie within sigma / d + 1/2 cells of the particle's
   // fractional cell coordinate, so this window (from the cell holding it)
   // contains them all
   const int di = int(sigma / d + 0.5) + 1, dj = int(sigma / (d * smin) + 0.5) + 1;
   T* fp = static_cast<T*>(a.fp);
+  const int64_t Nb = a.Nb;
+  const double reach = 0.75 * a.L + sigma + 2.0 * d;
   // the patches whose square the disc can reach: bundle centres within
-  // 0.75 L + sigma (a patch's corners are L / sqrt 2 from its centre)
-  disc_pixels(a.Nb, p, theta, phi, 0.75 * a.L + sigma + 2.0 * d, [&](int64_t rb, double) {
-    double zb, sb, pb;
-    hpx::pix2ang_ring(a.Nb, rb, zb, sb, pb);
-    const int64_t b = hpx::ang2nest(a.Nb, zb, pb);
-    if (a.dflag && !a.dflag[b]) return;
-    const double* R = a.rot + 9 * b;
-    const double v0 = R[0] * p[0] + R[1] * p[1] + R[2] * p[2];
-    const double v1 = R[3] * p[0] + R[4] * p[1] + R[5] * p[2];
-    const double v2 = R[6] * p[0] + R[7] * p[1] + R[8] * p[2];
-    const double tp = atan2(sqrt(v0 * v0 + v1 * v1), v2), pp = atan2(v1, v0);
-    const int ic = int(floor((tp - th0) / d)), jc = int(floor((pp - ph0) / d));
-    if (ic + di < 0 || ic - di >= n || jc + dj < 0 || jc - dj >= n) return;
-    const double stp = sin(tp);
-    T* fb = fp + size_t(b) * n * n;
-    // angle to a cell centre by the haversine (accurate at small angles):
-    // hav = sin^2(dtheta / 2) + sin theta'_i sin theta'_p sin^2(dphi / 2),
-    // inside sigma when hav < sin^2(sigma / 2); the sines of the half azimuth
-    // offsets by the angle-addition recurrence along the row.  The cell area
-    // is 2 d sin(theta'_i) sin(d / 2).
-    // Row i holds cells of the disc only where sin^2(dphi / 2) <
-    // (hav(sigma) - sin^2(dtheta / 2)) / (sin theta'_i sin theta'_p): its
-    // window is cut to that azimuth range, widened by a cell.
-    auto visit = [&](auto&& f) {
-      for (int i = ic - di; i <= ic + di; ++i) {
-        const double ti = th0 + (i + 0.5) * d;
-        const double sti = sin(ti), hti = sin(0.5 * (ti - tp));
-        const double area = 2.0 * d * sti * sh;
-        const double h2 = hti * hti, ss = sti * stp;
-        if (h2 >= hs2) continue;
-        const double q = ss > 0.0 ? (hs2 - h2) / ss : 2.0;
-        const double dph = q >= 1.0 ? 2.0 * kPiD : 2.0 * asin(sqrt(q));
-        const int jlo = max(jc - dj, int(floor((pp - dph - ph0) / d - 0.5)) - 1);
-        const int jhi = min(jc + dj, int(ceil((pp + dph - ph0) / d - 0.5)) + 1);
-        double sa, ca;
-        sincos(0.5 * (ph0 + (jlo + 0.5) * d - pp), &sa, &ca);
-        for (int j = jlo; j <= jhi; ++j) {
-          const double hv = fmin(fma(ss * sa, sa, h2), 1.0);
-          if (hv < hs2) {
-            const double ang = 2.0 * hpx::asin_small(sqrt(hv));
-            f(i, j, 1.0 - ang * ang * is2, area);
-          }
-          const double sn = fma(sa, ch, ca * sh);
-          ca = fma(ca, ch, -sa * sh);
-          sa = sn;
+  // 0.75 L + sigma (a patch's corners are L / sqrt 2 from its centre).
+  // Candidates: the bundle pixels of the rings within reach in colatitude,
+  // in each ring those within the azimuth range of the reach (a superset of
+  // the disc; the window test below drops the patches it misses).
+  const double rlo = fmax(0.0, theta - reach), rhi = fmin(kPiD, theta + reach);
+  const int64_t q_lo = max(int64_t(1), int64_t(floor(ring_of(Nb, rlo))) - 1);
+  const int64_t q_hi = min(4 * Nb - 1, int64_t(ceil(ring_of(Nb, rhi))) + 1);
+  const double creach = cos(fmin(reach, kPiD)), sp0 = sqrt(p[0] * p[0] + p[1] * p[1]);
+  for (int64_t q = q_lo; q <= q_hi; ++q) {
+    const RingG g = ring_geom(Nb, q);
+    int64_t c0 = 0, c1 = g.n - 1;
+    const double den = sp0 * g.s;
+    if (den > 1e-300) {
+      // azimuths within reach: cos dphi >= (cos reach - z_p z_r) / (s_p s_r)
+      const double c = (creach - p[2] * g.z) / den;
+      if (c >= 1.0) continue;
+      if (c > -1.0) {
+        const double dmax = acos(c);
+        const int64_t ca = int64_t(floor((phi - dmax - g.phi0) / g.dphi)) - 1;
+        const int64_t cb = int64_t(ceil((phi + dmax - g.phi0) / g.dphi)) + 1;
+        if (cb - ca + 1 < g.n) {
+          c0 = ca;
+          c1 = cb;
         }
       }
-    };
-    double tot = 0.0;
-    if (sigma > 0.0) visit([&](int, int, double k, double area) { tot += k * area; });
-    if (tot > 0.0) {
-      const double f = w2 / tot;
-      visit([&](int i, int j, double k, double) {
-        if (i >= 0 && i < n && j >= 0 && j < n)
-          unsafeAtomicAdd(fb + size_t(i) * n + j, T(f * k));
-      });
-    } else if (ic >= 0 && ic < n && jc >= 0 && jc < n) {
-      const double ti = th0 + (ic + 0.5) * d;
-      unsafeAtomicAdd(fb + size_t(ic) * n + jc, T(w2 / (2.0 * d * sin(ti) * sin(0.5 * d))));
     }
-  });
+    for (int64_t cj = c0; cj <= c1; ++cj) {
+      const int64_t rb = g.first + ((cj % g.n) + g.n) % g.n;
+      double zb, sb, pb;
+      hpx::pix2ang_ring(a.Nb, rb, zb, sb, pb);
+      const int64_t b = hpx::ang2nest(a.Nb, zb, pb);
+      if (a.dflag && !a.dflag[b]) continue;
+      const double* R = a.rot + 9 * b;
+      const double v0 = R[0] * p[0] + R[1] * p[1] + R[2] * p[2];
+      const double v1 = R[3] * p[0] + R[4] * p[1] + R[5] * p[2];
+      const double v2 = R[6] * p[0] + R[7] * p[1] + R[8] * p[2];
+      const double rho = sqrt(v0 * v0 + v1 * v1);  // sin theta'_p (|v| = 1)
+      const double tp = hpx::atan2_r(rho, v2), pp = hpx::atan2_r(v1, v0);
+      const int ic = int(floor((tp - th0) / d)), jc = int(floor((pp - ph0) / d));
+      if (ic + di < 0 || ic - di >= n || jc + dj < 0 || jc - dj >= n) continue;
+      const double stp = rho;
+      T* fb = fp + size_t(b) * n * n;
+      // angle to a cell centre by the haversine (accurate at small angles):
+      // hav = sin^2(dtheta / 2) + sin theta'_i sin theta'_p sin^2(dphi / 2),
+      // inside sigma when hav < sin^2(sigma / 2).  The cell area is
+      // 2 d sin(theta'_i) sin(d / 2).  Row i holds cells of the disc only
+      // where sin^2(dphi / 2) < (hav(sigma) - sin^2(dtheta / 2)) /
+      // (sin theta'_i sin theta'_p): its window is cut to that azimuth
+      // range, widened by a cell (the float32 bound is far inside it).  The
+      // sines along the rows (steps d and d / 2) and along a row (steps
+      // d / 2) come from angle-addition recurrences, the start of each
+      // row's azimuth run from the window's first column by a short sine
+      // series of the offset; the squared angle from a series in hav.
+      const int i0 = ic - di, j0 = jc - dj;
+      double st0, ct0, hs0, hc0, sj0, cj0;
+      sincos(th0 + (i0 + 0.5) * d, &st0, &ct0);
+      sincos(0.5 * (th0 + (i0 + 0.5) * d - tp), &hs0, &hc0);
+      sincos(0.5 * (ph0 + (j0 + 0.5) * d - pp), &sj0, &cj0);
+      auto visit = [&](auto&& f) {
+        double sti = st0, cti = ct0, hti = hs0, hci = hc0;
+        for (int i = i0; i <= ic + di; ++i) {
+          const double h2 = hti * hti, ss = sti * stp;
+          if (h2 < hs2) {
+            const double area = 2.0 * d * sti * sh;
+            const double q = ss > 0.0 ? (hs2 - h2) / ss : 2.0;
+            const double dph = q >= 1.0 ? 2.0 * kPiD : 2.0 * double(asinf(sqrtf(float(q))));
+            const int jlo = max(jc - dj, int(floor((pp - dph - ph0) / d - 0.5)) - 1);
+            const int jhi = min(jc + dj, int(ceil((pp + dph - ph0) / d - 0.5)) + 1);
+            // sin, cos of half the azimuth offset of column jlo from j0
+            const double x = 0.5 * d * double(jlo - j0);
+            double sx, cx;
+            if (x < 0.05) {
+              const double x2 = x * x;
+              sx = x * fma(x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+              cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+            } else {
+              sincos(x, &sx, &cx);
+            }
+            double sa = fma(sj0, cx, cj0 * sx), ca = fma(cj0, cx, -sj0 * sx);
+            for (int j = jlo; j <= jhi; ++j) {
+              const double hv = fmin(fma(ss * sa, sa, h2), 1.0);
+              if (hv < hs2) {
+                // (2 asin sqrt(hv))^2 = 4 (hv + hv^2 / 3 + 8 hv^3 / 45 + ...)
+                double a2;
+                if (hv < 1e-3) {
+                  a2 = 4.0 * hv *
+                       fma(hv,
+                           fma(hv, fma(hv, fma(hv, 128.0 / 1575.0, 4.0 / 35.0), 8.0 / 45.0),
+                               1.0 / 3.0),
+                           1.0);
+                } else {
+                  const double ang = 2.0 * hpx::asin_small(sqrt(hv));
+                  a2 = ang * ang;
+                }
+                f(i, j, 1.0 - a2 * is2, area);
+              }
+              const double sn = fma(sa, ch, ca * sh);
+              ca = fma(ca, ch, -sa * sh);
+              sa = sn;
+            }
+          }
+          // next row: theta'_i by d, the half offset by d / 2
+          const double s1 = fma(sti, cd, cti * sd);
+          cti = fma(cti, cd, -sti * sd);
+          sti = s1;
+          const double h1 = fma(hti, ch, hci * sh);
+          hci = fma(hci, ch, -hti * sh);
+          hti = h1;
+        }
+      };
+      double tot = 0.0;
+      if (sigma > 0.0) visit([&](int, int, double k, double area) { tot += k * area; });
+      if (tot > 0.0) {
+        const double f = w2 / tot;
+        visit([&](int i, int j, double k, double) {
+          if (i >= 0 && i < n && j >= 0 && j < n)
+            unsafeAtomicAdd(fb + size_t(i) * n + j, T(f * k));
+        });
+      } else if (ic >= 0 && ic < n && jc >= 0 && jc < n) {
+        const double ti = th0 + (ic + 0.5) * d;
+        unsafeAtomicAdd(fb + size_t(ic) * n + jc, T(w2 / (2.0 * d * sin(ti) * sin(0.5 * d))));
+      }
+    }
+  }
 }
 
 }  // namespace
