@@ -11,7 +11,9 @@
 * The pure-SHT Poisson solve at Nside 512 / lmax 1024 (the smallest plane of
   the batched-precision workload): psi_lm and the psi map of the FP64 form
   element by element, and the matrix-core FP32, BF16x3 and BF16x6 forms
-  with their error stated as the relative L2 norm of the psi map."""
+  with their error stated as the relative L2 norm of the psi map.
+* The plane from particles at the headline geometry: deposition on the fine
+  grid and on the patch cells, SHT and multigrid, at the three patches."""
 import numpy as np
 import pytest
 import torch
@@ -100,6 +102,65 @@ def test_c2_geometry_patches_and_shear(clm, c2_case, prec):
             assert eg < tol and eu < tol, (b, pix[k], eg, eu)
     report("c2 grad %s" % prec, worst_g)
     report("c2 hess %s" % prec, worst_u)
+    plan.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def c2_particles_case():
+    """Particles at the headline geometry: a uniform field over the sky
+    and particles within 0.04 rad of each compared bundle's centre (so
+    their patches' sources come from many particles, across their faces),
+    smoothing angles of 2-3 fine pixels.  The oracle deposits them on the
+    fine grid (local pixels per particle) and on the patch cells."""
+    from oracle import deposit as odep
+    Nf, Ns, lmax, Nb, n = 2048, 256, 512, 32, 256
+    print("fixture: oracle particle plane at the C2 geometry", flush=True)
+    th, ph, w, sg = inputs.particle_cone(1200, seed=31, nside=Nf, halo_fraction=0.0)
+    rng = np.random.default_rng(32)
+    pix = np.sqrt(4 * np.pi / (12 * Nf * Nf))
+    ths, phs = [th], [ph]
+    for b in C2_BUNDLES:
+        zc, pc, sc = hp.pix2ang_nest(Nb, np.array([b]))
+        c = hp.vec(zc, pc, sc)[0]
+        # uniform in a cap of 0.04 rad around the bundle centre
+        r = np.arccos(1 - rng.uniform(0, 1 - np.cos(0.04), 500))
+        a = rng.standard_normal((500, 3))
+        a -= (a @ c)[:, None] * c
+        a /= np.linalg.norm(a, axis=1)[:, None]
+        v = np.cos(r)[:, None] * c + np.sin(r)[:, None] * a
+        ths.append(np.arctan2(np.hypot(v[:, 0], v[:, 1]), v[:, 2]))
+        phs.append(np.mod(np.arctan2(v[:, 1], v[:, 0]), 2 * np.pi))
+    th, ph = np.concatenate(ths), np.concatenate(phs)
+    w = np.full(th.size, 4 * np.pi * 0.05 / th.size)
+    sg = pix * rng.uniform(2.0, 3.0, th.size)
+    kfine = odep.deposit_sparse(Nf, th, ph, w, sg)
+    spec = omg.PatchSpec(Nf, Ns, lmax, Nb, ncell=n, vcycles=4)
+    sol = omg.solve_plane(spec, kfine, C2_BUNDLES, particles=(th, ph, w, sg))
+    return dict(Nf=Nf, Ns=Ns, lmax=lmax, Nb=Nb, n=n, parts=(th, ph, w, sg), sol=sol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c2_geometry_particle_plane(clm, c2_particles_case, prec):
+    """clm_poisson_solve_particles at the headline geometry against the
+    oracle: psi_lm (fine-grid deposition and SHT) and u at the three
+    patches (deposition on the patch cells and the multigrid)."""
+    c = c2_particles_case
+    print("case: particle plane at the C2 geometry, %s multigrid" % prec, flush=True)
+    plan = clm.Plan(c["Nf"], nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"],
+                    patch_cells=c["n"], mg_vcycles=4, mg_prec=prec)
+    plan.poisson_solve_particles(*[torch.from_numpy(np.ascontiguousarray(x)).cuda()
+                                   for x in c["parts"]])
+    plan.sync_status()
+    sol = c["sol"]
+    assert report("c2 particles psi_lm %s" % prec,
+                  rel(plan.psi_alm().cpu().numpy(), sol["psi_alm"])) < 1e-10
+    tol_u = 1e-10 if prec == "fp64" else 1e-6
+    for b in C2_BUNDLES:
+        pt = sol["patches"][b]
+        ref = (pt["u0"] + pt["du"])[1:-1, 1:-1]
+        got = plan.patch_potential(b, 1)[0].cpu().numpy()
+        assert report("c2 particles u %s b=%d" % (prec, b), rel(got, ref)) < tol_u, b
     plan.close()
     torch.cuda.empty_cache()
 

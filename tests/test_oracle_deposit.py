@@ -92,6 +92,21 @@ def test_smoothed_point_mass_app_e():
     assert np.abs(g1m[sel] - g1[sel]).max() < 2e-2 * np.abs(g1[sel]).max()
 
 
+@pytest.mark.parametrize("N", [16, 64])
+def test_sparse_deposit_is_the_full_deposit(N):
+    """deposit_sparse (each particle over its local pixels) gives the map of
+    deposit() over all pixel centres bit for bit: particles at both poles,
+    across the azimuth wrap, wide and vanishing kernels."""
+    from paper_1210_3069_amd import inputs
+    th, ph, w, sg = inputs.particle_cone(200, seed=3, nside=N)
+    th = np.concatenate([th, [0.0, np.pi, 1e-3, 0.02, 1.5]])
+    ph = np.concatenate([ph, [0.0, 1.0, 6.2, 6.28, 0.001]])
+    w = np.concatenate([w, np.ones(5)])
+    sg = np.concatenate([sg, [0.3, 0.05, 1e-6, 0.2, 0.1]])
+    np.testing.assert_array_equal(dep.deposit_sparse(N, th, ph, w, sg),
+                                  dep.deposit(N, th, ph, w, sg))
+
+
 def test_candidate_pixels_change_nothing():
     """Limiting the pixel centres tried to whole rings around the particles
     gives the same map."""
