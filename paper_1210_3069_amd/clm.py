@@ -133,6 +133,15 @@ def _dev(t, dtype):
     return t
 
 
+def _out(t, dtype, numel, name):
+    """A caller's output tensor: contiguous, of the dtype the call writes and
+    with room for the values it writes (the library checks the rest)."""
+    _dev(t, dtype)
+    if t.numel() < numel:
+        raise ValueError("%s has %d values, the call writes %d" % (name, t.numel(), numel))
+    return t
+
+
 def nalm(lmax):
     return (lmax + 1) * (lmax + 2) // 2
 
@@ -444,7 +453,8 @@ class Plan:
             g = torch.empty(2, self.npix_fine, dtype=dt, device=self.device)
             h = torch.empty(3, self.npix_fine, dtype=dt, device=self.device)
         else:
-            g, h = out
+            g = _out(out[0], dt, 2 * self.npix_fine, "the gradient output")
+            h = _out(out[1], dt, 3 * self.npix_fine, "the Hessian output")
         self._check(lib().clm_shear_at_pixels(self.h, slot, o, int(fp64), _ptr(g), _ptr(h),
                                               _stream()), "shear_at_pixels")
         return g, h
@@ -459,7 +469,8 @@ class Plan:
             g = torch.empty(nplanes, 2, self.npix_fine, dtype=dt, device=self.device)
             h = torch.empty(nplanes, 3, self.npix_fine, dtype=dt, device=self.device)
         else:
-            g, h = out
+            g = _out(out[0], dt, nplanes * 2 * self.npix_fine, "the gradient output")
+            h = _out(out[1], dt, nplanes * 3 * self.npix_fine, "the Hessian output")
         self._check(lib().clm_shear_at_pixels_batch(self.h, first_slot, nplanes, o, int(fp64),
                                                     _ptr(g), _ptr(h), _stream()),
                     "shear_at_pixels_batch")

@@ -106,6 +106,50 @@ def test_c2_geometry_patches_and_shear(clm, c2_case, prec):
     torch.cuda.empty_cache()
 
 
+def test_c2_geometry_partial_sky(clm, c2_case):
+    """Partial sky at the headline geometry (clm_plan_set_domain): a domain
+    of the bundles within 0.1 rad of the north pole and within 0.06 rad of
+    bundle 5000's centre.  Every patch is its own solve with boundary values
+    from the full-sky SHT, so the domain's patches and shear equal those of
+    the whole-sky run (itself compared with the oracle above) bit for bit,
+    and the pixels outside the domain are left as they were."""
+    c = c2_case
+    print("case: partial sky at the C2 geometry", flush=True)
+    z, ph, s = hp.pix2ang_nest(c["Nb"], np.arange(12 * c["Nb"] ** 2))
+    v = hp.vec(z, ph, s)
+    cb = v[5000]
+    dom = np.nonzero((z > np.cos(0.1)) | (v @ cb > np.cos(0.06)))[0]
+    assert 1023 in dom and 5000 in dom and 8192 not in dom
+    kw = dict(nside_sht=c["Ns"], lmax=c["lmax"], nside_bundle=c["Nb"], patch_cells=c["n"],
+              mg_vcycles=4, mg_prec="fp32")
+    k = torch.from_numpy(c["k32"]).cuda()
+    full = clm.Plan(c["Nf"], **kw)
+    full.poisson_solve(k)
+    gf, hf = full.shear_at_pixels(order="nested", fp64=True)
+    full_u = {b: full.patch_potential(b, 1) for b in (1023, 5000)}
+    full.sync_status()
+    full.close()
+    part = clm.Plan(c["Nf"], **kw)
+    part.set_domain(dom)
+    part.poisson_solve(k)
+    for b in (1023, 5000):
+        assert torch.equal(part.patch_potential(b, 1), full_u[b]), b
+    npix = 12 * c["Nf"] ** 2
+    g = torch.full((2, npix), 7.0, dtype=torch.float64, device="cuda")
+    h = torch.full((3, npix), 7.0, dtype=torch.float64, device="cuda")
+    part.shear_at_pixels(order="nested", fp64=True, out=(g, h))
+    part.sync_status()
+    part.close()
+    per = (c["Nf"] // c["Nb"]) ** 2
+    inside = torch.zeros(npix, dtype=torch.bool, device="cuda")
+    for b in dom:
+        inside[int(b) * per:(int(b) + 1) * per] = True
+    assert torch.equal(g[:, inside], gf[:, inside]) and torch.equal(h[:, inside], hf[:, inside])
+    assert bool((g[:, ~inside] == 7.0).all()) and bool((h[:, ~inside] == 7.0).all())
+    report("c2 partial sky bundles", float(dom.size))
+    torch.cuda.empty_cache()
+
+
 @pytest.fixture(scope="module")
 def c2_particles_case():
     """Particles at the headline geometry: a uniform field over the sky
