@@ -1004,8 +1004,14 @@ __device__ __forceinline__ void pre_epilogue(const TileArgs<T>& a, const QLds<T,
 template <typename T, int HH>
 struct CorrIn {
   static constexpr int CR = QT<T, HH>::Q + 2;
-  static constexpr int NE = (CR * CR + QT<T, HH>::NT - 1) / QT<T, HH>::NT;
-  T uc[NE], ub[NE];
+  // the region's first coarse column, (tile) 32 - HH / 2 - 1, is even when
+  // HH / 2 is odd: then coarse columns pair up (an even one and the next,
+  // both inside or both outside the patch) and each item is a pair
+  static constexpr bool PAIR = (HH / 2) % 2 == 1;
+  static constexpr int CW = PAIR ? CR / 2 : CR;  // items per row
+  static constexpr int NE = (CR * CW + QT<T, HH>::NT - 1) / QT<T, HH>::NT;
+  static constexpr int EV = PAIR ? 2 : 1;        // values per item
+  T uc[NE * EV], ub[NE * EV];
 };
 
 template <typename T, int HH>
@@ -1015,12 +1021,20 @@ __device__ __forceinline__ void corr_issue(const TileArgs<T>& a, CorrIn<T, HH>& 
   const int nc = a.n / 2, ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // i0, j0 even
 #pragma unroll
   for (int k = 0; k < C::NE; ++k) {
-    const int item = min(int(threadIdx.x) + k * QT<T, HH>::NT, C::CR * C::CR - 1);
-    const int I = min(max(ci0 + item / C::CR, 0), nc - 1);
-    const int J = min(max(cj0 + item % C::CR, 0), nc - 1);
-    const unsigned g = unsigned(I * nc + J);
-    c.uc[k] = *at(a.uc + cbase, g);
-    c.ub[k] = *at(a.ubarc + cbase, g);
+    const int item = min(int(threadIdx.x) + k * QT<T, HH>::NT, C::CR * C::CW - 1);
+    const int r = item / C::CW, q = item - r * C::CW;
+    const int I = min(max(ci0 + r, 0), nc - 1);
+    if constexpr (C::PAIR) {
+      const int J = min(max(cj0 + 2 * q, 0), nc - 2);
+      const unsigned g = unsigned(I * nc + J);
+      load2(at(a.uc + cbase, g), c.uc[2 * k], c.uc[2 * k + 1]);
+      load2(at(a.ubarc + cbase, g), c.ub[2 * k], c.ub[2 * k + 1]);
+    } else {
+      const int J = min(max(cj0 + q, 0), nc - 1);
+      const unsigned g = unsigned(I * nc + J);
+      c.uc[k] = *at(a.uc + cbase, g);
+      c.ub[k] = *at(a.ubarc + cbase, g);
+    }
   }
 }
 
@@ -1031,9 +1045,18 @@ __device__ __forceinline__ void corr_store(T* e, const CorrIn<T, HH>& c, int n, 
 #pragma unroll
   for (int k = 0; k < C::NE; ++k) {
     const int item = int(threadIdx.x) + k * QT<T, HH>::NT;
-    if (item >= C::CR * C::CR) break;
-    const int I = ci0 + item / C::CR, J = cj0 + item % C::CR;
-    e[item] = (I >= 0 && I < nc && J >= 0 && J < nc) ? c.uc[k] - c.ub[k] : T(0);
+    if (item >= C::CR * C::CW) break;
+    const int r = item / C::CW, q = item - r * C::CW;
+    const int I = ci0 + r;
+    if constexpr (C::PAIR) {
+      const int J = cj0 + 2 * q;
+      const bool in = I >= 0 && I < nc && J >= 0 && J < nc;
+      e[r * C::CR + 2 * q] = in ? c.uc[2 * k] - c.ub[2 * k] : T(0);
+      e[r * C::CR + 2 * q + 1] = in ? c.uc[2 * k + 1] - c.ub[2 * k + 1] : T(0);
+    } else {
+      const int J = cj0 + q;
+      e[item] = (I >= 0 && I < nc && J >= 0 && J < nc) ? c.uc[k] - c.ub[k] : T(0);
+    }
   }
 }
 
