@@ -1004,6 +1004,10 @@ __device__ __forceinline__ void pre_epilogue(const TileArgs<T>& a, const QLds<T,
 template <typename T, int HH>
 struct CorrIn {
   static constexpr int CR = QT<T, HH>::Q + 2;
+  // LDS row stride of the staged correction: on the conflict-free quad
+  // mapping (TPR threads per quad row) a stride congruent to TPR modulo 64
+  // puts a wave's rows on successive banks, as in the sweeps
+  static constexpr int ES = HH >= 10 ? CR + ((QT<T, HH>::TPR - CR) % 64 + 64) % 64 : CR;
   // the region's first coarse column, (tile) 32 - HH / 2 - 1, is even when
   // HH / 2 is odd: then coarse columns pair up (an even one and the next,
   // both inside or both outside the patch) and each item is a pair
@@ -1051,11 +1055,11 @@ __device__ __forceinline__ void corr_store(T* e, const CorrIn<T, HH>& c, int n, 
     if constexpr (C::PAIR) {
       const int J = cj0 + 2 * q;
       const bool in = I >= 0 && I < nc && J >= 0 && J < nc;
-      e[r * C::CR + 2 * q] = in ? c.uc[2 * k] - c.ub[2 * k] : T(0);
-      e[r * C::CR + 2 * q + 1] = in ? c.uc[2 * k + 1] - c.ub[2 * k + 1] : T(0);
+      e[r * C::ES + 2 * q] = in ? c.uc[2 * k] - c.ub[2 * k] : T(0);
+      e[r * C::ES + 2 * q + 1] = in ? c.uc[2 * k + 1] - c.ub[2 * k + 1] : T(0);
     } else {
       const int J = cj0 + q;
-      e[item] = (I >= 0 && I < nc && J >= 0 && J < nc) ? c.uc[k] - c.ub[k] : T(0);
+      e[r * C::ES + q] = (I >= 0 && I < nc && J >= 0 && J < nc) ? c.uc[k] - c.ub[k] : T(0);
     }
   }
 }
@@ -1065,7 +1069,7 @@ __device__ __forceinline__ void apply_correction(const T* e, const QRow<T>& rw,
                                                  Quad<T> (&qd)[QT<T, HH>::IT], int i0, int j0,
                                                  int n) {
   using G = QT<T, HH>;
-  constexpr int CR = G::Q + 2;
+  constexpr int CR = CorrIn<T, HH>::ES;
 #pragma unroll
   for (int it = 0; it < G::IT; ++it) {
     Quad<T>& Qd = qd[it];
@@ -1139,7 +1143,7 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_post(TileArgs<T> a) {
   using G = QT<T, HH>;
   constexpr int CR = G::Q + 2;  // coarse cells covering the region quads +- 1
   __shared__ QLds<T, HH> t;
-  __shared__ T e[CR * CR];
+  __shared__ T e[CR * CorrIn<T, HH>::ES];
   QRow<T> rw;
   Quad<T> qd[G::IT];
   const int64_t lb = xcd_block();
@@ -1187,7 +1191,7 @@ __global__ __launch_bounds__(tile_threads(HH)) void k_mg_postpre(TileArgs<T> a) 
   using G = QT<T, HH>;
   constexpr int CR = G::Q + 2;
   __shared__ QLds<T, HH> t;
-  __shared__ T e[CR * CR];
+  __shared__ T e[CR * CorrIn<T, HH>::ES];
   QRow<T> rw;
   Quad<T> qd[G::IT];
   const int64_t lb = xcd_block();
