@@ -16,7 +16,7 @@ import bench  # noqa: E402
 def test_entry_points_present():
     for name in ("bytes_model", "make_inputs", "run_form", "cpu_baseline", "main",
                  "summarize_stats", "summarize_pmc", "read_traffic", "stage_kernels",
-                 "parse_args", "check_args", "plane_distances", "dominant_stage"):
+                 "parse_args", "check_args", "plane_distances", "ranked_stages"):
         assert callable(getattr(bench, name)), name
 
 
@@ -109,11 +109,16 @@ def test_plane_distances():
     assert (np.diff(chi) > 0).all()
 
 
-def test_dominant_stage():
+def test_ranked_stages():
     st = {"mg_postpre_l0": (12.9, 3), "patch_setup": (11.3, 1), "mean": (50.0, 2),
           "ray_update": (2.6, 1)}
-    # "mean" has no byte model and is never the roofline kernel
-    assert bench.dominant_stage(st, 1, 12288, 12 * 2048 ** 2) == "mg_postpre_l0"
+    # "mean" has no byte model and is never a roofline kernel; the first two
+    # get the roofline and the runner-up roofline
+    assert bench.ranked_stages(st, 1, 12288, 12 * 2048 ** 2) == [
+        "mg_postpre_l0", "patch_setup", "ray_update"]
+    st["patch_setup"] = (13.0, 1)
+    assert bench.ranked_stages(st, 1, 12288, 12 * 2048 ** 2)[:2] == [
+        "patch_setup", "mg_postpre_l0"]
 
 
 def test_host_cpu():
